@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms
+(Lemma 3.1), textbook eigenpairs of the 5-point stencil, manufactured solutions
+built from those closed forms, the linear-quadratic case solved by a library
+direct solve, RASPEN versus a monolithic Newton solve (F_eps(x) = 0 iff the RASPEN
+residual vanishes, Section 4.2), central differences for every Jacobian, and the
+algebraic identities of the restriction/prolongation operators.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import pointwise as pw
+from oracle.krylov import gmres
+from oracle.newton import newton_continuation, CONVERGED, LINESEARCH_FAIL
+from oracle.schwarz import (Raspen, global_newton, partition, prolong, prolong_core,
+                            restrict, split_1d)
+from oracle.system import System, laplacian
+
+EPS_LIST = [1e-10, 1e-6, 1e-3, 0.5, 3.0, 10.0]
+T = np.concatenate([np.linspace(-5, 5, 2001), [-1.0, 0.0, 1.0, 1e-9, -1e-9]])
+
+
+# ---------------------------------------------------------------- P1: P_eps, P'_eps
+def test_P0_is_projection():
+    # eq. (smoothProj) at eps = 0 is (|x+1| - |x-1|)/2 = proj_[-1,1] (Section 3.1)
+    err = np.abs(pw.P_eps(T, 0.0) - np.clip(T, -1, 1))
+    assert np.all(err <= 2.3e-16 * np.maximum(np.abs(T), 1e-300) + 1e-300)   # one rounding
+
+
+@pytest.mark.parametrize("eps", EPS_LIST)
+def test_P_eps_lemma_3_1(eps):
+    P, dP = pw.P_eps(T, eps), pw.dP_eps(T, eps)
+    # point (iv): |proj - P_eps| <= sqrt(eps)
+    assert np.all(np.abs(np.clip(T, -1, 1) - P) <= math.sqrt(eps) + 1e-15)
+    # point (i): range [-1, 1], odd, strictly increasing, limits +-1
+    assert np.all(np.abs(P) <= 1.0)
+    assert np.allclose(pw.P_eps(-T, eps), -P, rtol=0, atol=1e-16)
+    assert np.all(np.diff(pw.P_eps(np.sort(T), eps)) >= 0)
+    big = pw.P_eps(np.array([-1e9, 1e9]), eps)
+    assert abs(big[0] + 1) < 1e-8 and abs(big[1] - 1) < 1e-8
+    # point (ii): 0 < P' <= 1/sqrt(1+eps), maximum at 0
+    assert np.all(dP > 0) and np.all(dP <= 1 / math.sqrt(1 + eps) * (1 + 1e-15))
+    assert abs(pw.dP_eps(0.0, eps) - 1 / math.sqrt(1 + eps)) < 1e-15
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-3, 0.5, 3.0])
+def test_dP_is_derivative_of_P(eps):
+    h = 1e-5
+    t = np.linspace(-3, 3, 601)
+    fd = (pw.P_eps(t + h, eps) - pw.P_eps(t - h, eps)) / (2 * h)
+    scale = max(1.0, 1.0 / eps) ** 1.5          # third derivative grows like eps^-3/2
+    assert np.max(np.abs(fd - pw.dP_eps(t, eps))) < 10 * h * h * scale + 1e-9
+
+
+@pytest.mark.parametrize("eps", [0.5, 3.0, 10.0])
+def test_rationalised_equals_printed_form(eps):
+    # Figure 1 plots eq. (smoothProj) on [-4, 4] for eps in {0.5, 3, 10}
+    t = np.linspace(-4, 4, 101)
+    assert np.max(np.abs(pw.P_eps(t, eps) - pw.P_eps_direct(t, eps))) < 1e-15
+    # closed-form values at t = 1: (sqrt(4+eps) - sqrt(eps))/2; eps = 0.5 gives 1/sqrt(2)
+    assert abs(pw.P_eps(1.0, eps) - 0.5 * (math.sqrt(4 + eps) - math.sqrt(eps))) < 1e-15
+    assert abs(pw.P_eps(1.0, 0.5) - 1 / math.sqrt(2)) < 1e-15
+
+
+def test_dP_pointwise_limits():
+    # Lemma 3.1 (ii): P'_eps -> 1 on |x|<1, 1/2 at |x|=1, 0 on |x|>1 as eps -> 0
+    e = 1e-14
+    assert abs(pw.dP_eps(0.5, e) - 1) < 1e-12
+    assert abs(pw.dP_eps(1.0, e) - 0.5) < 1e-6
+    assert abs(pw.dP_eps(1.5, e)) < 1e-12
+
+
+# ---------------------------------------------------------------- P2: soft threshold
+def test_control_is_soft_threshold_at_eps0():
+    p = np.linspace(-0.3, 0.3, 1201)
+    mu, nu = 0.05, 1e-3
+    S = np.where(p > mu, p - mu, np.where(p < -mu, p + mu, 0.0))   # written out, no oracle
+    assert np.max(np.abs(pw.control(p, nu, mu, 0.0) + S / nu)) <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-8, 1e-4, 1e-2, 1.0])
+def test_control_soft_threshold_bound(eps):
+    p = np.linspace(-0.3, 0.3, 1201)
+    mu, nu = 0.05, 1e-3
+    S = np.sign(p) * np.maximum(np.abs(p) - mu, 0)
+    assert np.all(np.abs(pw.control(p, nu, mu, eps) + S / nu) <= mu * math.sqrt(eps) / nu * (1 + 1e-12))
+
+
+def test_mu_zero_and_dg():
+    p = np.linspace(-1, 1, 11)
+    assert np.array_equal(pw.control(p, 0.1, 0.0, 1e-3), -p / 0.1)
+    assert np.array_equal(pw.dg(p, 0.0, 1e-3), np.ones_like(p))
+    mu, eps, h = 0.05, 1e-3, 1e-7
+    q = np.linspace(-0.2, 0.2, 401)
+    fd = (pw.g(q + h, mu, eps) - pw.g(q - h, mu, eps)) / (2 * h)
+    assert np.max(np.abs(fd - pw.dg(q, mu, eps))) < 1e-6
+
+
+@pytest.mark.parametrize("kind", [synth.PHI_ZERO, synth.PHI_CUBIC, synth.PHI_EXP, synth.PHI_PAPER])
+def test_phi_family(kind):
+    y = np.linspace(-2, 2, 81)
+    h = 1e-5
+    d1 = (pw.phi(y + h, kind) - pw.phi(y - h, kind)) / (2 * h)
+    d2 = (pw.dphi(y + h, kind) - pw.dphi(y - h, kind)) / (2 * h)
+    assert np.allclose(d1, pw.dphi(y, kind), rtol=1e-8, atol=1e-8)
+    assert np.allclose(d2, pw.ddphi(y, kind), rtol=1e-8, atol=1e-8)
+    assert np.all(pw.dphi(y, kind) >= 0)            # Assumption 1: phi monotone
+    ref = {synth.PHI_ZERO: 0.0, synth.PHI_CUBIC: 8.0, synth.PHI_EXP: math.exp(2) - 1,
+           synth.PHI_PAPER: 0.1 * (8 + math.exp(0.2))}[kind]
+    assert abs(pw.phi(2.0, kind) - ref) < 1e-14
+
+
+# ---------------------------------------------------------------- P3: the stencil
+def eig(nx, ny, k, l):
+    hx, hy = 1 / (nx + 1), 1 / (ny + 1)
+    X, Y = synth.node_coords(nx, ny)
+    v = np.sin(k * math.pi * X) * np.sin(l * math.pi * Y)
+    lam = 4 / hx ** 2 * math.sin(k * math.pi * hx / 2) ** 2 + 4 / hy ** 2 * math.sin(l * math.pi * hy / 2) ** 2
+    return v.reshape(-1), lam
+
+
+@pytest.mark.parametrize("nx,ny", [(7, 5), (12, 9), (1, 4)])
+def test_laplacian_eigenpairs(nx, ny):
+    A = laplacian(nx, ny)
+    assert abs(A - A.T).max() == 0
+    for k in range(1, nx + 1, max(1, nx // 3)):
+        for l in range(1, ny + 1, max(1, ny // 3)):
+            v, lam = eig(nx, ny, k, l)
+            assert np.max(np.abs(A @ v - lam * v)) < 1e-9 * lam
+
+
+# ---------------------------------------------------------------- P4: F_eps by closed-form MMS
+@pytest.mark.parametrize("kind", [synth.PHI_CUBIC, synth.PHI_EXP, synth.PHI_PAPER])
+def test_residual_vanishes_at_closed_form_mms(kind):
+    nx, ny, nu, mu = 11, 8, 1e-2, 0.05
+    vy, ly = eig(nx, ny, 1, 2)
+    vp, lp = eig(nx, ny, 2, 1)
+    ys, ps = 0.7 * vy, 0.12 * vp              # p* crosses +-mu
+    # phi written out independently of the oracle
+    ph = {synth.PHI_CUBIC: (ys ** 3, 3 * ys ** 2), synth.PHI_EXP: (np.exp(ys) - 1, np.exp(ys)),
+          synth.PHI_PAPER: (0.1 * (ys ** 3 + np.exp(0.1 * ys)), 0.1 * (3 * ys ** 2 + 0.1 * np.exp(0.1 * ys)))}[kind]
+    S = np.sign(ps) * np.maximum(np.abs(ps) - mu, 0)
+    f = ly * ys + ph[0] + S / nu                       # state line with g_0 = soft threshold
+    yd = ys - lp * ps - ph[1] * ps                     # adjoint line
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=nu, mu=mu)
+    s = System(prob, yd.reshape(ny, nx), f.reshape(ny, nx))
+    x = np.concatenate([ys, ps])
+    r0 = s.residual(x, 0.0)
+    assert np.max(np.abs(r0)) < 1e-10 * max(ly, lp)
+    # eps > 0 only changes the state line, by at most mu sqrt(eps)/nu (Lemma 3.1 (iv))
+    for eps in [1e-6, 1e-2]:
+        r = s.residual(x, eps)
+        assert np.max(np.abs(r[s.n:] - r0[s.n:])) == 0
+        assert np.max(np.abs(r[:s.n])) <= mu * math.sqrt(eps) / nu + 1e-9 * ly
+
+
+@pytest.mark.parametrize("kind", [synth.PHI_CUBIC, synth.PHI_EXP, synth.PHI_PAPER])
+def test_jacobian_central_difference(kind):
+    prob = synth.Problem(nx=9, ny=7, phi=kind, nu=1e-2, mu=0.02)
+    rng = np.random.default_rng(0)
+    s = System(prob, rng.standard_normal((7, 9)), rng.standard_normal((7, 9)))
+    x = np.concatenate([0.5 * rng.standard_normal(s.n), 0.05 * rng.standard_normal(s.n)])
+    d = rng.standard_normal(2 * s.n)
+    for eps in [1e-3, 0.3]:
+        t = 1e-6
+        fd = (s.residual(x + t * d, eps) - s.residual(x - t * d, eps)) / (2 * t)
+        Jd = s.jacobian(x, eps) @ d
+        assert np.linalg.norm(fd - Jd) < 1e-6 * np.linalg.norm(Jd)
+
+
+# ---------------------------------------------------------------- Algorithm 1 and GMRES
+def test_newton_scalar_and_schedule():
+    res = lambda x, e: np.array([x[0] ** 3 - 2.0 + e * 0.0])
+    jac = lambda x, e: sp.csc_matrix([[3 * x[0] ** 2]])
+    x, info = newton_continuation(res, jac, np.array([1.0]), 1.0, 1e-6, 0.5, 1.1, 1e-12, 200, 2 ** -30)
+    assert abs(x[0] - 2 ** (1 / 3)) < 1e-12 and info.status == CONVERGED
+    # the continuation must run until eps reaches eps_min: 2^-20 < 1e-6 <= 2^-19
+    assert info.iterations == 20 and info.eps == 1e-6
+    x, info = newton_continuation(res, jac, np.array([1.0]), 1e-6, 1e-6, 0.5, 1.1, 1e-12, 200, 2 ** -30)
+    assert info.iterations < 8
+
+
+def test_newton_backtracking():
+    # undamped Newton on atan diverges from x0 = 1.5; backtracking with sigma = 1 converges
+    res = lambda x, e: np.arctan(x)
+    jac = lambda x, e: sp.csc_matrix([[1 / (1 + x[0] ** 2)]])
+    x, info = newton_continuation(res, jac, np.array([1.5]), 1.0, 1.0, 1.0, 1.0, 1e-12, 100, 2 ** -30)
+    assert info.status == CONVERGED and abs(x[0]) < 1e-12 and info.backtracks > 0
+    # a residual that is NaN for every trial point is a line-search failure
+    res2 = lambda x, e: np.array([1.0]) if x[0] == 0 else np.array([np.nan])
+    x, info = newton_continuation(res2, lambda x, e: sp.csc_matrix([[1.0]]), np.array([0.0]),
+                                  1.0, 1.0, 1.0, 1.1, 1e-12, 10, 2 ** -30)
+    assert info.status == LINESEARCH_FAIL and x[0] == 0.0
+
+
+@pytest.mark.parametrize("restart", [60, 7])
+def test_gmres_against_direct_solve(restart):
+    rng = np.random.default_rng(3)
+    n = 60
+    M = np.eye(n) * 4 + rng.standard_normal((n, n)) / math.sqrt(n)
+    b = rng.standard_normal(n)
+    x, used, rel = gmres(lambda v: M @ v, b, restart=restart, rtol=1e-12, maxiter=400)
+    assert np.linalg.norm(M @ x - b) <= 2e-12 * np.linalg.norm(b)
+    assert abs(np.linalg.norm(M @ x - b) / np.linalg.norm(b) - rel) < 1e-13
+    assert np.allclose(x, np.linalg.solve(M, b), rtol=0, atol=1e-10)
+    if restart >= n:
+        assert used <= n
+    x, used, rel = gmres(lambda v: M @ v, b, restart=restart, rtol=1e-30, maxiter=5)
+    assert used == 5
+
+
+# ---------------------------------------------------------------- P8: partition and operators
+def test_partition_sizes_of_the_workloads():
+    assert split_1d(63, 2) == [(0, 32), (32, 63)]
+    subs = partition(63, 63, 2, 2, 2)
+    assert sorted({s.box[1] - s.box[0] for s in subs}) == [33, 34]
+    subs = partition(255, 255, 8, 8, 4)
+    assert sorted({s.box[1] - s.box[0] for s in subs}) == [35, 36, 40]
+    subs = partition(511, 511, 16, 16, 4)
+    assert max(s.rows.size for s in subs) == 1600          # ~2 x 1600 local unknowns
+    with pytest.raises(ValueError):
+        split_1d(9, 4)                                       # ceil(9/4) = 3 leaves box 4 empty
+
+
+@pytest.mark.parametrize("nx,ny,sx,sy,ov", [(15, 15, 2, 2, 1), (23, 17, 3, 2, 2), (20, 9, 4, 1, 3)])
+def test_restriction_prolongation_identities(nx, ny, sx, sy, ov):
+    n = nx * ny
+    subs = partition(nx, ny, sx, sy, ov)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(2 * n)
+    total = np.zeros(2 * n)
+    cover = np.zeros(n, dtype=int)
+    for s in subs:
+        c = rng.standard_normal(2 * s.rows.size)
+        assert np.array_equal(restrict(s, prolong(s, c, n), n), c)      # R_i P_i = I
+        total += prolong_core(s, restrict(s, v, n), n)
+        cover[s.core_rows] += 1
+        bx0, bx1, by0, by1 = s.box
+        assert s.rows.size == (bx1 - bx0) * (by1 - by0)
+    assert np.array_equal(total, v)                                       # sum P~_i R_i = I
+    assert np.all(cover == 1)                                             # disjoint cores
+
+
+# ---------------------------------------------------------------- P5, P11: linear-quadratic case
+def lq_direct(nx, ny, nu, yd, f):
+    """[[A, I/nu], [-I, A]] x = [f; -y_d], the eps-independent linear system for
+    phi = 0, mu = 0, assembled here from kron and solved by SuperLU."""
+    hx, hy = 1 / (nx + 1), 1 / (ny + 1)
+    Tx = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(nx, nx)) / hx ** 2
+    Ty = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(ny, ny)) / hy ** 2
+    A = sp.kron(sp.eye(ny), Tx) + sp.kron(Ty, sp.eye(nx))
+    n = nx * ny
+    K = sp.bmat([[A, sp.eye(n) / nu], [-sp.eye(n), A]]).tocsc()
+    return spla.spsolve(K, np.concatenate([f.reshape(-1), -yd.reshape(-1)]))
+
+
+def test_linear_quadratic_case():
+    prob = synth.Problem(nx=21, ny=17, phi=synth.PHI_ZERO, nu=1e-3, mu=0.0, eps0=1e-6,
+                         eps_min=1e-6, sx=2, sy=2, overlap=2, seed=7)
+    yd, f = prob.inputs()
+    f = f + 0.3
+    xs = lq_direct(prob.nx, prob.ny, prob.nu, yd, f)
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-14, max_gmres=500)
+    x, info, _ = global_newton(prob, opts, yd, f)
+    assert info.iterations == 1
+    assert np.max(np.abs(x - xs)) <= 1e-12 * np.max(np.abs(xs))
+    out = Raspen(prob, opts, yd, f).solve()
+    assert out["outer"] == 1                              # affine F: one outer step (P11)
+    assert np.max(np.abs(out["x"] - xs)) <= 1e-11 * np.max(np.abs(xs))
+    assert np.max(np.abs(out["u"] + out["p"] / prob.nu)) <= 1e-12 * np.max(np.abs(out["u"]))
+
+
+# ---------------------------------------------------------------- P4 (solvers), P6: RASPEN = global
+def mms_problem(kind, nx, ny, sx, sy, ov, eps_min=1e-6):
+    """Manufactured solution in the spirit of Section 4 (pick p crossing +-mu and y,
+    derive f and y_d so that F_eps(y, p) = 0): f and y_d come from the oracle's own F."""
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=0.02, eps0=1.0,
+                         eps_min=eps_min, gamma=0.5, sx=sx, sy=sy, overlap=ov)
+    X, Y = synth.node_coords(nx, ny)
+    ys = 0.6 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    ps = 0.05 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    s0 = System(prob, np.zeros((ny, nx)), np.zeros((ny, nx)))
+    x = np.concatenate([ys.reshape(-1), ps.reshape(-1)])
+    r = s0.residual(x, eps_min)
+    f = r[:s0.n].reshape(ny, nx)              # F_1(x*) - f = r_1 with f = 0  =>  f := r_1
+    yd = -r[s0.n:].reshape(ny, nx)            # F_2 = ... + y_d              =>  y_d := -r_2
+    return prob, yd, f, x
+
+
+@pytest.mark.parametrize("kind", [synth.PHI_CUBIC, synth.PHI_EXP])
+def test_solvers_recover_manufactured_solution(kind):
+    prob, yd, f, xs = mms_problem(kind, 19, 15, 2, 2, 2)
+    opts = synth.Options(tol_outer=1e-12, tol_inner=1e-12, gmres_rtol=1e-13)
+    x, info, _ = global_newton(prob, opts, yd, f)
+    assert info.status == CONVERGED
+    assert np.max(np.abs(x - xs)) <= 1e-11 * np.max(np.abs(xs))
+    out = Raspen(prob, opts, yd, f).solve()
+    assert out["status"] == CONVERGED
+    assert np.max(np.abs(out["x"] - xs)) <= 1e-11 * np.max(np.abs(xs))
+
+
+@pytest.mark.parametrize("nx,ny,sx,sy,ov,kind", [(15, 15, 2, 2, 1, synth.PHI_CUBIC),
+                                                 (31, 31, 3, 3, 2, synth.PHI_CUBIC),
+                                                 (23, 17, 3, 2, 2, synth.PHI_EXP)])
+def test_raspen_equals_global_newton(nx, ny, sx, sy, ov, kind):
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=sx, sy=sy, overlap=ov, seed=11)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-13)
+    xg, info, s = global_newton(prob, opts, yd, f)
+    assert info.status == CONVERGED
+    out = Raspen(prob, opts, yd, f).solve()
+    assert out["status"] == CONVERGED
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-11 * np.max(np.abs(xg))
+    # the zero of the RASPEN residual is a zero of F_eps (Section 4.2)
+    assert np.linalg.norm(s.residual(out["x"], prob.eps_min)) < 1e-9
+
+
+# ---------------------------------------------------------------- P7, P12: RASPEN Jacobian
+def test_raspen_jacobian_central_difference_and_halo_form():
+    prob = synth.Problem(nx=17, ny=13, phi=synth.PHI_CUBIC, nu=1e-2, mu=1e-2, eps0=1e-4,
+                         eps_min=1e-4, sx=2, sy=2, overlap=2, seed=5)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_inner=1e-14, max_inner=60)
+    R = Raspen(prob, opts, yd, f)
+    n = R.n
+    rng = np.random.default_rng(2)
+    x = np.concatenate([0.3 * rng.standard_normal(n), 0.02 * rng.standard_normal(n)])
+    d = rng.standard_normal(2 * n)
+    F0, _ = R.eval_F(x, continuation=False)
+    Jd = R.jac_apply(d)
+    # halo form: F'(x) d = -d - sum_i P~_i J_i^{-1} B_i d with B_i d = R_i diag(A, A)(I - P_i R_i) d
+    halo = -d.copy()
+    for i, sub in enumerate(R.subs):
+        dout = d.copy()
+        dout[sub.rows] = 0.0
+        dout[n + sub.rows] = 0.0
+        Bd = np.concatenate([R.A_rows[i] @ dout[:n], R.A_rows[i] @ dout[n:]])
+        halo -= prolong_core(sub, R.lu[i].solve(Bd), n)
+    assert np.max(np.abs(halo - Jd)) <= 1e-12 * np.max(np.abs(Jd))
+    t = 1e-6
+    Fp, _ = R.eval_F(x + t * d, continuation=False)
+    Fm, _ = R.eval_F(x - t * d, continuation=False)
+    fd = (Fp - Fm) / (2 * t)
+    assert np.linalg.norm(fd - Jd) < 1e-6 * np.linalg.norm(Jd)
+
+
+# ---------------------------------------------------------------- P9: eps -> 0 (weak)
+def test_smoothing_error_decays_at_least_like_sqrt_eps():
+    prob = synth.Problem(nx=15, ny=15, phi=synth.PHI_CUBIC, nu=1e-3, mu=0.05, seed=4)
+    yd, f = prob.inputs()
+    yd = 20 * yd
+    opts = synth.Options(tol_outer=1e-12)
+    ref = None
+    errs = []
+    epss = [1e-2, 1e-3, 1e-4]
+    for e in [1e-12] + epss:
+        p2 = synth.Problem(**{**prob.__dict__, "eps0": 1.0, "eps_min": e, "gamma": 0.2})
+        x, info, _ = global_newton(p2, opts, yd, f)
+        assert info.status == CONVERGED
+        if ref is None:
+            ref = x
+        else:
+            errs.append(np.linalg.norm(x - ref))
+    slopes = np.diff(np.log(errs)) / np.diff(np.log(epss))
+    assert errs[0] > 0 and np.all(slopes >= 0.45)
