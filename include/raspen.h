@@ -1,0 +1,204 @@
+/*
+ * raspen.h -- C ABI of the MI355X (gfx950) RASPEN library.
+ *
+ * Solves the smoothed first-order optimality system of the L2/L1-regularised
+ * semilinear elliptic optimal control problem
+ *
+ *     min 1/2 |y - y_d|^2 + nu/2 |u|^2 + mu |u|_1   s.t.  A y + phi(y) = f + u
+ *
+ * (paper: eq. (P); reduced smoothed system eq. (reg_OS_red), Section 3.2) with u
+ * eliminated through the smoothed soft-threshold u = -(1/nu)(p + mu P_eps(-p/mu))
+ * (eq. (smoothProj)), by one-level RASPEN (Section 4.2, Algorithms 2-4) whose
+ * local problems are solved by damped Newton with eps-continuation (Algorithm 1).
+ *
+ * Discretisation: unit square, A = 5-point finite-difference -Laplacian with
+ * homogeneous Dirichlet data, nx x ny interior nodes, hx = 1/(nx+1),
+ * hy = 1/(ny+1).  Every grid array is float64, row-major [ny][nx] (x fastest).
+ * A state vector x = (y, p) is stored as [2][ny][nx] (y first).
+ *
+ * Memory: unless stated otherwise, array arguments are DEVICE pointers on the
+ * context's device, owned by the caller, and must stay valid until the work
+ * enqueued on `stream` has completed.  Calls that return results to the host
+ * (norms, histories) synchronise `stream` before they return.
+ *
+ * Errors: every call returns an int status.  0 = success / converged; > 0 =
+ * completed with the last iterate written (RSP_NOT_CONVERGED, RSP_LINESEARCH_FAIL,
+ * RSP_GMRES_STAGNATION, RSP_REFINE_FALLBACK); < 0 = hard error with outputs
+ * undefined (RSP_EINVAL, RSP_ENOMEM, RSP_EHIP, RSP_ENUMERIC).  rsp_last_error()
+ * returns a thread-local message for the last failing call.  No C++ exception
+ * crosses this interface.  A context is not thread-safe: use one per host thread.
+ */
+#ifndef RASPEN_H
+#define RASPEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSP_VERSION 100
+
+/* status codes */
+#define RSP_OK 0
+#define RSP_NOT_CONVERGED 1     /* iteration limit reached (Algorithms 1 and 2 k_max) */
+#define RSP_LINESEARCH_FAIL 2   /* backtracking went below alpha_min (Algorithm 1) */
+#define RSP_GMRES_STAGNATION 3  /* GMRES hit max_gmres above its tolerance */
+#define RSP_REFINE_FALLBACK 4   /* FP32 factors + refinement did not converge */
+#define RSP_EINVAL (-1)
+#define RSP_ENOMEM (-2)
+#define RSP_EHIP (-3)
+#define RSP_ENUMERIC (-4)
+
+/* phi(y), Assumption 1 (phi in C^2, monotone increasing) */
+#define RSP_PHI_ZERO 0          /* phi = 0 (linear state equation)            */
+#define RSP_PHI_CUBIC 1         /* phi = y^3                                   */
+#define RSP_PHI_EXP 2           /* phi = exp(y) - 1                            */
+#define RSP_PHI_PAPER 3         /* phi = kappa (y^3 + exp(kappa y)), Section 4 */
+
+/* where eps-continuation is applied (Algorithm 2 and Section 5: "only in the
+   first inner Newton iterations") */
+#define RSP_CONT_FIRST 0        /* local solves of the first evaluation only */
+#define RSP_CONT_NONE 1         /* never: every local solve at eps_min        */
+#define RSP_CONT_EVERY 2        /* every evaluation                           */
+
+#define RSP_FP64 0              /* local factors in FP64                        */
+#define RSP_FP32_REFINED 1      /* local factors in FP32 + FP64 refinement       */
+
+/* Problem data (eq. (P), eq. (reg_OS_red), Algorithm 1 eps schedule, Section 4.2
+   partition).  The domain is the unit square.  sx x sy non-overlapping boxes of
+   width ceil(n/s) per direction; each is extended by `overlap` nodes per side and
+   clipped to the grid (the overlapping subdomain Omega_i). */
+typedef struct rsp_problem {
+  int32_t nx, ny;         /* interior nodes per direction, >= 1                     */
+  int32_t phi_kind;       /* RSP_PHI_*                                             */
+  double kappa;           /* parameter of RSP_PHI_PAPER                            */
+  double nu;              /* > 0, L2 weight                                        */
+  double mu;              /* >= 0, L1 weight (mu = 0: u = -p/nu exactly)           */
+  double eps0, eps_min;   /* 0 < eps_min <= eps0: continuation start and target    */
+  double gamma;           /* eps_{k+1} = max(gamma eps_k, eps_min), 0 < gamma < 1   */
+  int32_t sx, sy;         /* boxes per direction, 1 <= s <= n, no box may be empty */
+  int32_t overlap;        /* >= 0, nodes added on each side                        */
+} rsp_problem;
+
+/* Solver options (paper Section 5 gives tol 1e-10, inner tol 1e-8, sigma 1.1). */
+typedef struct rsp_options {
+  double tol_outer;       /* Algorithm 2: stop when |F(x^k)| <= max(tol, tol |F(x^0)|)  */
+  double tol_inner;       /* Algorithm 1 tolerance of the local solves                 */
+  double gmres_rtol;      /* GMRES: stop when |r| <= rtol |b|                          */
+  double sigma;           /* >= 1, relaxed backtracking, eq. (line_search)             */
+  double alpha_min;       /* > 0, backtracking floor (then RSP_LINESEARCH_FAIL)        */
+  int32_t gmres_restart;  /* 1 .. 64                                                    */
+  int32_t max_outer;      /* Algorithm 2 k_max                                          */
+  int32_t max_inner;      /* Algorithm 1 k_max                                          */
+  int32_t max_gmres;      /* matrix-vector products per outer iteration                 */
+  int32_t precision;      /* RSP_FP64 or RSP_FP32_REFINED                               */
+  int32_t max_refine;     /* refinement steps per FP32 local solve                      */
+  int32_t continuation;   /* RSP_CONT_*                                                 */
+} rsp_options;
+
+#define RSP_HIST_MAX 64
+
+/* Convergence history of one solve (host memory, filled by rsp_solve). */
+typedef struct rsp_history {
+  int32_t status;                       /* final status code                           */
+  int32_t outer;                        /* outer iterations done                       */
+  double norm[RSP_HIST_MAX + 1];        /* |F(x^k)|_2 for k = 0..outer (RASPEN residual) */
+  int32_t gmres_its[RSP_HIST_MAX + 1];  /* GMRES products in outer step k (k >= 1)     */
+  double gmres_rel[RSP_HIST_MAX + 1];   /* GMRES final relative residual estimate      */
+  int32_t inner_min[RSP_HIST_MAX + 1];  /* local Newton iterations of evaluation k     */
+  int32_t inner_max[RSP_HIST_MAX + 1];
+  double inner_avg[RSP_HIST_MAX + 1];
+  int32_t backtracks[RSP_HIST_MAX + 1]; /* step halvings, summed over subdomains       */
+  int32_t subdomains;                   /* S                                            */
+  int64_t factorizations;               /* local Jacobian factorisations (x subdomains)  */
+  int64_t local_solves;                 /* local block solves                           */
+  int64_t gmres_total;                  /* matrix-vector products                       */
+  double residual_final;                /* |F_{eps_min}(y, p)|_2 on the global grid      */
+  double flops;                         /* algorithmic flops of the solve               */
+  double ms_eval, ms_gmres, ms_total;   /* wall time of Algorithm 3 calls, GMRES, total  */
+} rsp_history;
+
+typedef struct rsp_context rsp_context;
+
+/* Library version (RSP_VERSION). */
+int rsp_version(void);
+
+/* Thread-local message describing the last error ("" if none). */
+const char* rsp_last_error(void);
+
+/* Partition of Section 4.2 (host only, no GPU needed).  Writes S (sx*sy), the
+   largest overlapping-tile width txm and height tym; if `boxes` is not NULL it
+   must hold 8*S int32 and receives per subdomain (row-major over boxes, x fastest):
+   x0, x1, y0, y1 of the overlapping box Omega_i and x0, x1, y0, y1 of the
+   non-overlapping box Omega~_i, all half-open node ranges.  RSP_EINVAL on a
+   problem that leaves a box empty or a tile wider than the library supports. */
+int rsp_partition(const rsp_problem* prob, int32_t* S, int32_t* txm, int32_t* tym,
+                  int32_t* boxes);
+
+/* Exact device-memory footprint (bytes) of rsp_setup for this problem/options:
+   factors, tiles, Krylov basis and state.  The admission key for serving. */
+size_t rsp_workspace_bytes(const rsp_problem* prob, const rsp_options* opts);
+
+/* Create / destroy a context on HIP device `device`.  `hbm_budget` (bytes, 0 =
+   unlimited) bounds what rsp_setup may allocate (RSP_ENOMEM beyond it). */
+int rsp_context_create(rsp_context** ctx, int device, size_t hbm_budget);
+int rsp_context_destroy(rsp_context* ctx);
+
+/* Bind a problem to the context: partition, allocate the workspace, copy y_d and
+   f (device, [ny][nx]; f may be NULL for f = 0).  Enqueued on `stream`. */
+int rsp_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
+              const double* yd, const double* f, hipStream_t stream);
+
+/* ---- steps of the hot path (after rsp_setup); tile arrays are [S][2][tym][txm],
+   float64, local node (a, b) of subdomain s at [s][field][b][a], entries outside
+   the subdomain's own tile zero on output and ignored on input ---- */
+
+/* F_eps(x) on the whole grid (Section 4: the map F(x, eps)): x, out are [2][ny][nx]. */
+int rsp_residual(rsp_context* ctx, const double* x, double eps, double* out,
+                 hipStream_t stream);
+
+/* u = -(1/nu)(p + mu P_eps(-p/mu)) (stationarity line of eq. (reg_OS)); p, u [ny][nx]. */
+int rsp_control(rsp_context* ctx, const double* p, double eps, double* u,
+                hipStream_t stream);
+
+/* R_i x for every subdomain (Section 4.2, R_i): x [2][ny][nx] -> tiles. */
+int rsp_restrict(rsp_context* ctx, const double* x, double* tiles, hipStream_t stream);
+
+/* out = sum_i P~_i c_i (Section 4.2, P~_i; eq. (RASPEN def)): tiles -> [2][ny][nx]. */
+int rsp_prolong(rsp_context* ctx, const double* tiles, double* out, hipStream_t stream);
+
+/* Local residuals K_i(c_i) = R_i F_eps(x + P_i c_i) (eq. (c_i)) -> tiles `out`,
+   and |K_i(c_i)|_2 per subdomain -> `norms` (device, S doubles). */
+int rsp_local_residual(rsp_context* ctx, const double* x, const double* c, double eps,
+                       double* out, double* norms, hipStream_t stream);
+
+/* Local linear solves z_i = J_i^{-1} r_i with J_i = R_i F'_eps(x + P_i c_i) P_i
+   (eq. (DerC) and the local Newton systems of Algorithm 1), by block-tridiagonal
+   LU over grid lines.  c, rhs, z: tiles. */
+int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double eps,
+                    const double* rhs, double* z, hipStream_t stream);
+
+/* Algorithm 3: F_eps(x) = sum_i P~_i C_i(x) -> out ([2][ny][nx]); stores the
+   corrections C_i(x) and the factors of R_i F'_eps(x^(i)) P_i for rsp_jac_apply.
+   continuation != 0 runs the local solves from eps0, else from eps_min.
+   Returns the worst local status; `norm` (host, nullable) gets |out|_2. */
+int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out,
+             double* norm, hipStream_t stream);
+
+/* Algorithm 4: out = F'_eps(x) d for the x of the last rsp_eval ([2][ny][nx]). */
+int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream);
+
+/* Algorithm 2 (RASPEN with eps-continuation in the local solves): from x^0 =
+   (y0, p0) (both NULL for x^0 = 0) to y, p and u = D_eps_min(p), all [ny][nx].
+   yd, f as in rsp_setup; `hist` (host, nullable) receives the history. */
+int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
+              const double* yd, const double* f, const double* y0, const double* p0,
+              double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RASPEN_H */

@@ -7,7 +7,8 @@ Readings taken where the paper leaves room (each listed in the design doc):
   * backtracking halves alpha while NOT (||F(x + alpha d)|| <= sigma ||F(x)||), so
     a NaN trial is rejected like a too-large one; below alpha_min the solve stops
     with status LINESEARCH_FAIL and keeps the last accepted iterate;
-  * norms are Euclidean norms of the discrete vectors.
+  * norms are Euclidean norms of the discrete vectors; a NaN residual never
+    counts as converged (the loop test is written as NOT (||F|| <= threshold)).
 """
 import dataclasses
 
@@ -48,7 +49,7 @@ def newton_continuation(residual, jacobian, x0, eps0, eps_min, gamma, sigma,
     k = 0
     backtracks = 0
     status = CONVERGED
-    while (r > thresh or eps > eps_min) and k <= kmax:
+    while (not (r <= thresh) or eps > eps_min) and k <= kmax:
         d = solve(jacobian(x, eps), -Fx)
         alpha = 1.0
         while True:
@@ -69,6 +70,6 @@ def newton_continuation(residual, jacobian, x0, eps0, eps_min, gamma, sigma,
         r = float(np.linalg.norm(Fx))
         if on_step is not None:
             on_step(k, x, eps)
-    if status == CONVERGED and (r > thresh or eps > eps_min):
+    if status == CONVERGED and (not (r <= thresh) or eps > eps_min):
         status = NOT_CONVERGED
     return x, NewtonInfo(status, k, backtracks, r, r0, eps)

@@ -195,7 +195,7 @@ class Raspen:
         status = info.status
         F0 = hist[0]["norm"]
         k = 0
-        while hist[-1]["norm"] > max(o.tol_outer, o.tol_outer * F0) and k < o.max_outer:
+        while not (hist[-1]["norm"] <= max(o.tol_outer, o.tol_outer * F0)) and k < o.max_outer:
             d, used, rel = gmres(self.jac_apply, -Fx, o.gmres_restart, o.gmres_rtol, o.max_gmres)
             x = x + d
             k += 1
@@ -203,7 +203,7 @@ class Raspen:
             status = max(status, info.status)
             hist.append(dict(norm=float(np.linalg.norm(Fx)), gmres=used, gmres_rel=rel,
                              inner=info.inner_iterations, backtracks=info.backtracks))
-        if hist[-1]["norm"] > max(o.tol_outer, o.tol_outer * F0) and status == CONVERGED:
+        if not (hist[-1]["norm"] <= max(o.tol_outer, o.tol_outer * F0)) and status == CONVERGED:
             status = NOT_CONVERGED
         y, pp = x[:n].copy(), x[n:].copy()
         res = dict(x=x, y=y, p=pp, u=self.sys.control(x, p.eps_min), status=status,

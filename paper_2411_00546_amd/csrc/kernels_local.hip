@@ -1,0 +1,306 @@
+// Per-subdomain kernels of the RASPEN hot path (one workgroup per subdomain):
+// restriction R_i with halo, local residual K_i (5-point stencil + phi + the
+// smoothed soft-threshold), Algorithm 1 line search / eps update, prolongation
+// P~_i, and the ring right-hand side of the RASPEN Jacobian (Algorithm 4).
+#include "rsp_kernels.h"
+
+namespace rsp {
+
+namespace {
+
+constexpr int kHalo = kMaxTile + 2;   // LDS stride of a staged tile with halo
+
+__device__ __forceinline__ int4 tile_box(const int4* box, int s, int& tx, int& ty) {
+  const int4 b = box[s];
+  tx = b.y - b.x;
+  ty = b.w - b.z;
+  return b;
+}
+
+// Stage z = R_i x (+ c + alpha dir on the tile interior) into LDS, halo included.
+__device__ void stage(const DevProblem& P, int s, int tx, int ty, const double* __restrict__ tilex,
+                      const double* __restrict__ c, const double* __restrict__ dir, double alpha,
+                      double* z) {
+  const int W = tx + 2, H = ty + 2;
+  for (int e = threadIdx.x; e < 2 * W * H; e += kBlock) {
+    const int f = e / (W * H);
+    const int r = e - f * W * H;
+    const int b = r / W, a = r - b * W;
+    double v = tilex[halo_idx(P, s, f, b, a)];
+    if (c && a >= 1 && a <= tx && b >= 1 && b <= ty) {
+      double cv = c[tile_idx(P, s, f, b - 1, a - 1)];
+      if (dir) cv = cv + alpha * dir[tile_idx(P, s, f, b - 1, a - 1)];
+      v = v + cv;
+    }
+    z[(f * kHalo + b) * kHalo + a] = v;
+  }
+}
+
+// K_i at local node (a, b) from the staged tile: the two rows of F_eps (Section 4).
+__device__ __forceinline__ void node_residual(const DevProblem& P, const double* z, int a, int b,
+                                              double ydv, double fv, double eps, double& ky,
+                                              double& kp) {
+  const double* zy = z;
+  const double* zp = z + kHalo * kHalo;
+  const int c0 = (b + 1) * kHalo + (a + 1);
+  const double y = zy[c0], p = zp[c0];
+  const double lap_y = P.diag0 * y - P.hx2i * (zy[c0 - 1] + zy[c0 + 1])
+                       - P.hy2i * (zy[c0 - kHalo] + zy[c0 + kHalo]);
+  const double lap_p = P.diag0 * p - P.hx2i * (zp[c0 - 1] + zp[c0 + 1])
+                       - P.hy2i * (zp[c0 - kHalo] + zp[c0 + kHalo]);
+  ky = lap_y + phi_of(P.phi, y, P.kappa) - fv + g_of(p, P.mu, eps) * P.inv_nu;
+  kp = lap_p + dphi_of(P.phi, y, P.kappa) * p - y + ydv;
+}
+
+// Sum of squares of K_i over the tile; optionally writes K_i to `out`.
+__device__ double tile_residual(const DevProblem& P, int s, int4 bx, int tx, int ty,
+                                const double* z, const double* __restrict__ yd,
+                                const double* __restrict__ f, double eps, double* out,
+                                double* red) {
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < tx * ty; e += kBlock) {
+    const int b = e / tx, a = e - b * tx;
+    const size_t gi = (size_t)(bx.z + b) * P.nx + (bx.x + a);
+    double ky, kp;
+    node_residual(P, z, a, b, yd[gi], f ? f[gi] : 0.0, eps, ky, kp);
+    if (out) {
+      out[tile_idx(P, s, 0, b, a)] = ky;
+      out[tile_idx(P, s, 1, b, a)] = kp;
+    }
+    acc += ky * ky + kp * kp;
+  }
+  return block_sum(acc, red);
+}
+
+__global__ __launch_bounds__(kBlock) void k_restrict_halo(DevProblem P, const int4* __restrict__ box,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ tilex) {
+  const int s = blockIdx.x;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  const int W = P.txm + 2, H = P.tym + 2;
+  const size_t n = (size_t)P.nx * P.ny;
+  for (int e = threadIdx.x; e < 2 * W * H; e += kBlock) {
+    const int f = e / (W * H);
+    const int r = e - f * W * H;
+    const int b = r / W, a = r - b * W;
+    const int gi = bx.x - 1 + a, gj = bx.z - 1 + b;
+    double v = 0.0;
+    if (a <= tx + 1 && b <= ty + 1 && gi >= 0 && gi < P.nx && gj >= 0 && gj < P.ny)
+      v = x[f * n + (size_t)gj * P.nx + gi];
+    tilex[halo_idx(P, s, f, b, a)] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_restrict(DevProblem P, const int4* __restrict__ box,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ tiles) {
+  const int s = blockIdx.x;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  const size_t n = (size_t)P.nx * P.ny;
+  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
+    const int f = e / (P.txm * P.tym);
+    const int r = e - f * P.txm * P.tym;
+    const int b = r / P.txm, a = r - b * P.txm;
+    double v = 0.0;
+    if (a < tx && b < ty) v = x[f * n + (size_t)(bx.z + b) * P.nx + (bx.x + a)];
+    tiles[tile_idx(P, s, f, b, a)] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prolong(DevProblem P, const int4* __restrict__ box,
+                                                    const int4* __restrict__ core,
+                                                    const double* __restrict__ tiles,
+                                                    const double* __restrict__ d,
+                                                    double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int4 bx = box[s], co = core[s];
+  const int cw = co.y - co.x, ch = co.w - co.z;
+  const size_t n = (size_t)P.nx * P.ny;
+  for (int e = threadIdx.x; e < 2 * cw * ch; e += kBlock) {
+    const int f = e / (cw * ch);
+    const int r = e - f * cw * ch;
+    const int b = r / cw, a = r - b * cw;
+    const int gi = co.x + a, gj = co.z + b;
+    const size_t g = f * n + (size_t)gj * P.nx + gi;
+    const double v = tiles[tile_idx(P, s, f, gj - bx.z, gi - bx.x)];
+    out[g] = d ? v - d[g] : v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_local_residual(DevProblem P, const int4* __restrict__ box,
+                                                           const double* __restrict__ tilex,
+                                                           const double* __restrict__ yd,
+                                                           const double* __restrict__ f,
+                                                           const double* __restrict__ c, double eps,
+                                                           double* __restrict__ out,
+                                                           double* __restrict__ norms) {
+  __shared__ double z[2 * kHalo * kHalo];
+  __shared__ double red[kBlock];
+  const int s = blockIdx.x;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  // zero the padding of the output tile
+  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
+    const int fl = e / (P.txm * P.tym);
+    const int r = e - fl * P.txm * P.tym;
+    const int b = r / P.txm, a = r - b * P.txm;
+    if (a >= tx || b >= ty) out[tile_idx(P, s, fl, b, a)] = 0.0;
+  }
+  stage(P, s, tx, ty, tilex, c, nullptr, 0.0, z);
+  __syncthreads();
+  const double ss = tile_residual(P, s, bx, tx, ty, z, yd, f, eps, out, red);
+  if (threadIdx.x == 0) norms[s] = sqrt(ss);
+}
+
+__global__ __launch_bounds__(kBlock) void k_newton_init(DevProblem P, const int4* __restrict__ box,
+                                                        const double* __restrict__ tilex,
+                                                        const double* __restrict__ yd,
+                                                        const double* __restrict__ f,
+                                                        double* __restrict__ c, double* __restrict__ res,
+                                                        SubState* __restrict__ state, double eps0,
+                                                        double tol, int kmax) {
+  __shared__ double z[2 * kHalo * kHalo];
+  __shared__ double red[kBlock];
+  const int s = blockIdx.x;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
+    c[(size_t)s * 2 * P.txm * P.tym + e] = 0.0;
+    res[(size_t)s * 2 * P.txm * P.tym + e] = 0.0;
+  }
+  stage(P, s, tx, ty, tilex, nullptr, nullptr, 0.0, z);
+  __syncthreads();
+  const double r = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, eps0, res, red));
+  if (threadIdx.x == 0) {
+    SubState S;
+    S.eps = eps0;
+    S.rnorm = r;
+    S.thresh = fmax(tol, tol * r);
+    S.alpha = 0.0;
+    S.k = 0;
+    S.backtracks = 0;
+    const bool done = (r <= S.thresh) && !(eps0 > P.eps_min);
+    S.active = (!done && kmax >= 0) ? 1 : 0;
+    S.status = (!done && !S.active) ? 1 : 0;
+    state[s] = S;
+  }
+}
+
+// One Algorithm 1 step after the Newton direction `dir` is known: alpha = 1, 1/2, ...
+// until |K_{eps_k}(c + alpha dir)| <= sigma |K_{eps_k}(c)| (a NaN trial is rejected),
+// then c += alpha dir, eps_{k+1} = max(gamma eps_k, eps_min), k += 1, new residual,
+// and the loop test of Algorithm 1 (with the eps_k = eps_min requirement).
+__global__ __launch_bounds__(kBlock) void k_linesearch(DevProblem P, const int4* __restrict__ box,
+                                                       const double* __restrict__ tilex,
+                                                       const double* __restrict__ yd,
+                                                       const double* __restrict__ f,
+                                                       double* __restrict__ c,
+                                                       const double* __restrict__ dir,
+                                                       double* __restrict__ res,
+                                                       SubState* __restrict__ state, double sigma,
+                                                       double alpha_min, int kmax) {
+  __shared__ double z[2 * kHalo * kHalo];
+  __shared__ double red[kBlock];
+  const int s = blockIdx.x;
+  SubState S = state[s];
+  if (!S.active) return;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  double alpha = 1.0;
+  for (;;) {
+    stage(P, s, tx, ty, tilex, c, dir, alpha, z);
+    __syncthreads();
+    const double rt = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, S.eps, nullptr, red));
+    if (rt <= sigma * S.rnorm) break;
+    alpha *= 0.5;
+    S.backtracks += 1;
+    if (alpha < alpha_min) {
+      if (threadIdx.x == 0) {
+        S.status = 2;
+        S.active = 0;
+        state[s] = S;
+      }
+      return;
+    }
+  }
+  // accept: c <- c + alpha dir (the staged tile already holds R_i x + c_new)
+  for (int e = threadIdx.x; e < tx * ty; e += kBlock) {
+    const int b = e / tx, a = e - b * tx;
+    for (int fl = 0; fl < 2; ++fl) {
+      const size_t i = tile_idx(P, s, fl, b, a);
+      c[i] = c[i] + alpha * dir[i];
+    }
+  }
+  S.eps = fmax(P.gamma * S.eps, P.eps_min);
+  S.k += 1;
+  S.alpha = alpha;
+  S.rnorm = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, S.eps, res, red));
+  const bool done = (S.rnorm <= S.thresh) && !(S.eps > P.eps_min);
+  S.active = (!done && S.k <= kmax) ? 1 : 0;
+  S.status = (!done && !S.active) ? 1 : 0;
+  if (threadIdx.x == 0) state[s] = S;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ring_rhs(DevProblem P, const int4* __restrict__ box,
+                                                     const double* __restrict__ d,
+                                                     double* __restrict__ rhs) {
+  const int s = blockIdx.x;
+  int tx, ty;
+  const int4 bx = tile_box(box, s, tx, ty);
+  const size_t n = (size_t)P.nx * P.ny;
+  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
+    const int f = e / (P.txm * P.tym);
+    const int r = e - f * P.txm * P.tym;
+    const int b = r / P.txm, a = r - b * P.txm;
+    double v = 0.0;
+    if (a < tx && b < ty) {
+      const int gi = bx.x + a, gj = bx.z + b;
+      const double* df = d + f * n;
+      if (a == 0 && gi > 0) v += P.hx2i * df[(size_t)gj * P.nx + gi - 1];
+      if (a == tx - 1 && gi + 1 < P.nx) v += P.hx2i * df[(size_t)gj * P.nx + gi + 1];
+      if (b == 0 && gj > 0) v += P.hy2i * df[(size_t)(gj - 1) * P.nx + gi];
+      if (b == ty - 1 && gj + 1 < P.ny) v += P.hy2i * df[(size_t)(gj + 1) * P.nx + gi];
+    }
+    rhs[tile_idx(P, s, f, b, a)] = v;
+  }
+}
+
+}  // namespace
+
+void launch_restrict_halo(const DevProblem& P, const int4* box, const double* x, double* tilex,
+                          hipStream_t st) {
+  k_restrict_halo<<<P.S, kBlock, 0, st>>>(P, box, x, tilex);
+}
+void launch_restrict(const DevProblem& P, const int4* box, const double* x, double* tiles,
+                     hipStream_t st) {
+  k_restrict<<<P.S, kBlock, 0, st>>>(P, box, x, tiles);
+}
+void launch_prolong(const DevProblem& P, const int4* box, const int4* core, const double* tiles,
+                    const double* d, double* out, hipStream_t st) {
+  k_prolong<<<P.S, kBlock, 0, st>>>(P, box, core, tiles, d, out);
+}
+void launch_local_residual(const DevProblem& P, const int4* box, const double* tilex,
+                           const double* yd, const double* f, const double* c, double eps,
+                           double* out, double* norms, hipStream_t st) {
+  k_local_residual<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, eps, out, norms);
+}
+void launch_newton_init(const DevProblem& P, const int4* box, const double* tilex,
+                        const double* yd, const double* f, double* c, double* res,
+                        SubState* state, double eps0, double tol, int kmax, hipStream_t st) {
+  k_newton_init<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, res, state, eps0, tol, kmax);
+}
+void launch_linesearch(const DevProblem& P, const int4* box, const double* tilex,
+                       const double* yd, const double* f, double* c, const double* dir,
+                       double* res, SubState* state, double sigma, double alpha_min, int kmax,
+                       hipStream_t st) {
+  k_linesearch<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, dir, res, state, sigma,
+                                       alpha_min, kmax);
+}
+void launch_ring_rhs(const DevProblem& P, const int4* box, const double* d, double* rhs,
+                     hipStream_t st) {
+  k_ring_rhs<<<P.S, kBlock, 0, st>>>(P, box, d, rhs);
+}
+
+}  // namespace rsp

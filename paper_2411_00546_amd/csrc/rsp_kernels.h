@@ -1,0 +1,64 @@
+// Host-side launchers of the RASPEN HIP kernels (one declaration per kernel).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "rsp_device.h"
+
+namespace rsp {
+
+// a2: halo tiles of R_i x ([S][2][tym+2][txm+2]; nodes outside the grid are 0).
+void launch_restrict_halo(const DevProblem& P, const int4* box, const double* x,
+                          double* tilex, hipStream_t st);
+// R_i x without halo ([S][2][tym][txm]).
+void launch_restrict(const DevProblem& P, const int4* box, const double* x, double* tiles,
+                     hipStream_t st);
+// a7: out[core of s] = tiles[s] (every node written once: the cores tile the grid).
+// If d != nullptr: out = -d + (that), the assembly of Algorithm 4.
+void launch_prolong(const DevProblem& P, const int4* box, const int4* core, const double* tiles,
+                    const double* d, double* out, hipStream_t st);
+// a3: K_i(c) at `eps` (per subdomain from state if eps < 0), tiles -> out, norms[s].
+void launch_local_residual(const DevProblem& P, const int4* box, const double* tilex,
+                           const double* yd, const double* f, const double* c, double eps,
+                           double* out, double* norms, hipStream_t st);
+// Algorithm 1 start: c = 0, residual at eps0, threshold, active flags.
+void launch_newton_init(const DevProblem& P, const int4* box, const double* tilex,
+                        const double* yd, const double* f, double* c, double* res,
+                        SubState* state, double eps0, double tol, int kmax, hipStream_t st);
+// a6: backtracking on |K|, update c and eps, new residual, stopping test.
+void launch_linesearch(const DevProblem& P, const int4* box, const double* tilex,
+                       const double* yd, const double* f, double* c, const double* dir,
+                       double* res, SubState* state, double sigma, double alpha_min, int kmax,
+                       hipStream_t st);
+// a9: ring right-hand side h^-2 (outside neighbours of d) per tile.
+void launch_ring_rhs(const DevProblem& P, const int4* box, const double* d, double* rhs,
+                     hipStream_t st);
+// a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1}.
+void launch_factor(const DevProblem& P, const int4* box, const double* tilex, const double* c,
+                   const SubState* state, double eps_fixed, const double* rhs, double rhs_scale,
+                   double* facT, double* g, hipStream_t st);
+// a5: backward sweep after a fused forward sweep.
+void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state,
+                      const double* facT, const double* g, double* out, hipStream_t st);
+// a5/a9: forward + backward sweeps with stored factors.
+void launch_block_solve(const DevProblem& P, const int4* box, const double* facT,
+                        const double* rhs, double* out, hipStream_t st);
+// Section 4 F(x, eps) on the whole grid and the control u(p).
+void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
+                            const double* x, double eps, double* out, hipStream_t st);
+void launch_control(const DevProblem& P, const double* p, double eps, double* u, hipStream_t st);
+
+// GMRES vector kernels (length L), deterministic two-stage reductions.
+int multidot_blocks(size_t L);
+void launch_multidot(const double* V, size_t ldv, int nvec, const double* w, size_t L,
+                     double* partial, hipStream_t st);
+void launch_reduce_partials(const double* partial, int nblk, int nvec, double* out,
+                            int accumulate, hipStream_t st);
+void launch_axpy_multi(const double* V, size_t ldv, int nvec, const double* h, double* w,
+                       size_t L, hipStream_t st);
+void launch_scale_by_inv_sqrt(const double* w, const double* sumsq, double* out, size_t L,
+                              hipStream_t st);
+void launch_axpy(double a, const double* x, double* y, size_t L, hipStream_t st);
+void launch_scale(double a, const double* x, double* y, size_t L, hipStream_t st);
+void launch_combine(const double* V, size_t ldv, int k, const double* y, double* x, size_t L,
+                    hipStream_t st);
+
+}  // namespace rsp

@@ -1,0 +1,236 @@
+"""Thin Python binding of the C ABI in include/raspen.h (argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Device arrays are
+torch tensors (float64, contiguous, on the context's CUDA/HIP device); torch
+provides memory and streams, every step of the method runs in libraspen.so.
+Importing this module fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libraspen.so")
+
+RSP_OK, RSP_NOT_CONVERGED, RSP_LINESEARCH_FAIL, RSP_GMRES_STAGNATION, RSP_REFINE_FALLBACK = 0, 1, 2, 3, 4
+RSP_EINVAL, RSP_ENOMEM, RSP_EHIP, RSP_ENUMERIC = -1, -2, -3, -4
+RSP_FP64, RSP_FP32_REFINED = 0, 1
+RSP_CONT_FIRST, RSP_CONT_NONE, RSP_CONT_EVERY = 0, 1, 2
+RSP_HIST_MAX = 64
+
+
+class RaspenError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("raspen error %d: %s" % (code, msg))
+        self.code = code
+
+
+class rsp_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("phi_kind", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("nu", ctypes.c_double), ("mu", ctypes.c_double),
+                ("eps0", ctypes.c_double), ("eps_min", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+
+
+class rsp_options(ctypes.Structure):
+    _fields_ = [("tol_outer", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("gmres_rtol", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("alpha_min", ctypes.c_double), ("gmres_restart", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+                ("max_gmres", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("continuation", ctypes.c_int32)]
+
+
+_H = RSP_HIST_MAX + 1
+
+
+class rsp_history(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("norm", ctypes.c_double * _H), ("gmres_its", ctypes.c_int32 * _H),
+                ("gmres_rel", ctypes.c_double * _H), ("inner_min", ctypes.c_int32 * _H),
+                ("inner_max", ctypes.c_int32 * _H), ("inner_avg", ctypes.c_double * _H),
+                ("backtracks", ctypes.c_int32 * _H), ("subdomains", ctypes.c_int32),
+                ("factorizations", ctypes.c_int64), ("local_solves", ctypes.c_int64),
+                ("gmres_total", ctypes.c_int64), ("residual_final", ctypes.c_double),
+                ("flops", ctypes.c_double), ("ms_eval", ctypes.c_double),
+                ("ms_gmres", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        k = min(self.outer, RSP_HIST_MAX)
+        return dict(status=self.status, outer=self.outer, norm=list(self.norm[:k + 1]),
+                    gmres_its=list(self.gmres_its[1:k + 1]), gmres_rel=list(self.gmres_rel[1:k + 1]),
+                    inner_min=list(self.inner_min[:k + 1]), inner_max=list(self.inner_max[:k + 1]),
+                    inner_avg=list(self.inner_avg[:k + 1]), backtracks=list(self.backtracks[:k + 1]),
+                    subdomains=self.subdomains, factorizations=self.factorizations,
+                    local_solves=self.local_solves, gmres_total=self.gmres_total,
+                    residual_final=self.residual_final, flops=self.flops, ms_eval=self.ms_eval,
+                    ms_gmres=self.ms_gmres, ms_total=self.ms_total)
+
+
+# (name, restype, argtypes) of every exported entry point, in header order
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_PROB = ctypes.POINTER(rsp_problem)
+_OPTS = ctypes.POINTER(rsp_options)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = [
+    ("rsp_version", _I, []),
+    ("rsp_last_error", ctypes.c_char_p, []),
+    ("rsp_partition", _I, [_PROB, _I32P, _I32P, _I32P, _I32P]),
+    ("rsp_workspace_bytes", ctypes.c_size_t, [_PROB, _OPTS]),
+    ("rsp_context_create", _I, [ctypes.POINTER(_P), _I, ctypes.c_size_t]),
+    ("rsp_context_destroy", _I, [_P]),
+    ("rsp_setup", _I, [_P, _PROB, _OPTS, _P, _P, _P]),
+    ("rsp_residual", _I, [_P, _P, _D, _P, _P]),
+    ("rsp_control", _I, [_P, _P, _D, _P, _P]),
+    ("rsp_restrict", _I, [_P, _P, _P, _P]),
+    ("rsp_prolong", _I, [_P, _P, _P, _P]),
+    ("rsp_local_residual", _I, [_P, _P, _P, _D, _P, _P, _P]),
+    ("rsp_local_solve", _I, [_P, _P, _P, _D, _P, _P, _P]),
+    ("rsp_eval", _I, [_P, _P, _I, _P, ctypes.POINTER(_D), _P]),
+    ("rsp_jac_apply", _I, [_P, _P, _P, _P]),
+    ("rsp_solve", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
+                       ctypes.POINTER(rsp_history), _P]),
+]
+
+_lib = None
+
+
+def load():
+    """Load libraspen.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libraspen.so is not built; run paper_2411_00546_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code, allow_positive=True):
+    if code < 0 or (code > 0 and not allow_positive):
+        raise RaspenError(code, load().rsp_last_error().decode())
+    return code
+
+
+def _ptr(t, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError("array argument is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("device arrays must be torch tensors")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("arrays must be contiguous float64 device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_problem(p):
+    """rsp_problem from a synth.Problem-like object."""
+    return rsp_problem(p.nx, p.ny, p.phi, p.kappa, p.nu, p.mu, p.eps0, p.eps_min, p.gamma,
+                       p.sx, p.sy, p.overlap)
+
+
+def make_options(o):
+    """rsp_options from a synth.Options-like object."""
+    return rsp_options(o.tol_outer, o.tol_inner, o.gmres_rtol, o.sigma, o.alpha_min,
+                       o.gmres_restart, o.max_outer, o.max_inner, o.max_gmres, o.precision,
+                       o.max_refine, o.continuation)
+
+
+# ---------------------------------------------------------------- entry points
+def rsp_version():
+    return load().rsp_version()
+
+
+def rsp_last_error():
+    return load().rsp_last_error().decode()
+
+
+def rsp_partition(prob):
+    """Returns (S, txm, tym, boxes[S][8]) (host)."""
+    lib = load()
+    S, tx, ty = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.rsp_partition(ctypes.byref(prob), ctypes.byref(S), ctypes.byref(tx),
+                             ctypes.byref(ty), None))
+    boxes = (ctypes.c_int32 * (8 * S.value))()
+    _check(lib.rsp_partition(ctypes.byref(prob), None, None, None, boxes))
+    b = [list(boxes[8 * i:8 * i + 8]) for i in range(S.value)]
+    return S.value, tx.value, ty.value, b
+
+
+def rsp_workspace_bytes(prob, opts):
+    return load().rsp_workspace_bytes(ctypes.byref(prob), ctypes.byref(opts))
+
+
+def rsp_context_create(device=0, hbm_budget=0):
+    h = ctypes.c_void_p()
+    _check(load().rsp_context_create(ctypes.byref(h), device, hbm_budget))
+    return h
+
+
+def rsp_context_destroy(ctx):
+    return _check(load().rsp_context_destroy(ctx))
+
+
+def rsp_setup(ctx, prob, opts, yd, f=None, stream=None):
+    return _check(load().rsp_setup(ctx, ctypes.byref(prob), ctypes.byref(opts), _ptr(yd),
+                                   _ptr(f, True), _stream(stream)))
+
+
+def rsp_residual(ctx, x, eps, out, stream=None):
+    return _check(load().rsp_residual(ctx, _ptr(x), eps, _ptr(out), _stream(stream)))
+
+
+def rsp_control(ctx, p, eps, u, stream=None):
+    return _check(load().rsp_control(ctx, _ptr(p), eps, _ptr(u), _stream(stream)))
+
+
+def rsp_restrict(ctx, x, tiles, stream=None):
+    return _check(load().rsp_restrict(ctx, _ptr(x), _ptr(tiles), _stream(stream)))
+
+
+def rsp_prolong(ctx, tiles, out, stream=None):
+    return _check(load().rsp_prolong(ctx, _ptr(tiles), _ptr(out), _stream(stream)))
+
+
+def rsp_local_residual(ctx, x, c, eps, out, norms, stream=None):
+    return _check(load().rsp_local_residual(ctx, _ptr(x), _ptr(c), eps, _ptr(out), _ptr(norms),
+                                            _stream(stream)))
+
+
+def rsp_local_solve(ctx, x, c, eps, rhs, z, stream=None):
+    return _check(load().rsp_local_solve(ctx, _ptr(x), _ptr(c), eps, _ptr(rhs), _ptr(z),
+                                         _stream(stream)))
+
+
+def rsp_eval(ctx, x, continuation, out, stream=None):
+    """Algorithm 3.  Returns (status, |out|_2)."""
+    nrm = ctypes.c_double()
+    st = _check(load().rsp_eval(ctx, _ptr(x), int(continuation), _ptr(out), ctypes.byref(nrm),
+                                _stream(stream)))
+    return st, nrm.value
+
+
+def rsp_jac_apply(ctx, d, out, stream=None):
+    return _check(load().rsp_jac_apply(ctx, _ptr(d), _ptr(out), _stream(stream)))
+
+
+def rsp_solve(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):
+    """Algorithm 2.  Returns (status, history dict)."""
+    h = rsp_history()
+    st = _check(load().rsp_solve(ctx, ctypes.byref(prob), ctypes.byref(opts), _ptr(yd),
+                                 _ptr(f, True), _ptr(y0, True), _ptr(p0, True), _ptr(y), _ptr(p),
+                                 _ptr(u), ctypes.byref(h), _stream(stream)))
+    return st, h.as_dict()

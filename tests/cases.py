@@ -1,0 +1,37 @@
+"""Shared test problems built on the CPU (closed forms and the oracle only)."""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle.system import System
+
+
+def lq_direct(nx, ny, nu, yd, f):
+    """[[A, I/nu], [-I, A]] x = [f; -y_d], the eps-independent linear system for
+    phi = 0, mu = 0, assembled here from kron and solved by SuperLU."""
+    hx, hy = 1 / (nx + 1), 1 / (ny + 1)
+    Tx = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(nx, nx)) / hx ** 2
+    Ty = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(ny, ny)) / hy ** 2
+    A = sp.kron(sp.eye(ny), Tx) + sp.kron(Ty, sp.eye(nx))
+    n = nx * ny
+    K = sp.bmat([[A, sp.eye(n) / nu], [-sp.eye(n), A]]).tocsc()
+    return spla.spsolve(K, np.concatenate([f.reshape(-1), -yd.reshape(-1)]))
+
+
+def mms_problem(kind, nx, ny, sx, sy, ov, eps_min=1e-6):
+    """Manufactured solution in the spirit of Section 4 (pick p crossing +-mu and y,
+    derive f and y_d so that F_eps(y, p) = 0): f and y_d come from the oracle's own F."""
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=0.02, eps0=1.0,
+                         eps_min=eps_min, gamma=0.5, sx=sx, sy=sy, overlap=ov)
+    X, Y = synth.node_coords(nx, ny)
+    ys = 0.6 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    ps = 0.05 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    s0 = System(prob, np.zeros((ny, nx)), np.zeros((ny, nx)))
+    x = np.concatenate([ys.reshape(-1), ps.reshape(-1)])
+    r = s0.residual(x, eps_min)
+    f = r[:s0.n].reshape(ny, nx)              # F_1(x*) - f = r_1 with f = 0  =>  f := r_1
+    yd = -r[s0.n:].reshape(ny, nx)            # F_2 = ... + y_d              =>  y_d := -r_2
+    return prob, yd, f, x

@@ -1,0 +1,88 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point that
+include/raspen.h declares, and its host-only partition / validation logic agrees
+with the oracle's partition of Section 4.2."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+from oracle.schwarz import partition as oracle_partition
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "raspen.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(rsp_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2411_00546_amd import raspen
+    raspen.load()
+    return raspen
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ["rsp_solve", "rsp_eval", "rsp_jac_apply", "rsp_local_solve", "rsp_local_residual",
+                 "rsp_restrict", "rsp_prolong", "rsp_residual", "rsp_control", "rsp_partition",
+                 "rsp_workspace_bytes", "rsp_context_create", "rsp_context_destroy", "rsp_setup",
+                 "rsp_version", "rsp_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(R):
+    lib = ctypes.CDLL(R.LIB_PATH)
+    bound = {name for name, _, _ in R.SIGNATURES}
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in bound, name           # the binding covers every declaration
+        assert hasattr(R, name), name        # and exposes it under the same name
+
+
+def test_version(R):
+    assert R.rsp_version() == 100
+
+
+@pytest.mark.parametrize("nx,ny,sx,sy,ov", [(63, 63, 2, 2, 2), (255, 255, 8, 8, 4),
+                                             (511, 511, 16, 16, 4), (23, 17, 3, 2, 2),
+                                             (20, 9, 4, 1, 3), (127, 63, 4, 2, 4), (5, 5, 1, 1, 0)])
+def test_partition_matches_oracle(R, nx, ny, sx, sy, ov):
+    prob = synth.Problem(nx=nx, ny=ny, sx=sx, sy=sy, overlap=ov)
+    S, txm, tym, boxes = R.rsp_partition(R.make_problem(prob))
+    subs = oracle_partition(nx, ny, sx, sy, ov)
+    assert S == len(subs)
+    for b, s in zip(boxes, subs):
+        assert tuple(b[:4]) == s.box and tuple(b[4:]) == s.core
+    assert txm == max(s.box[1] - s.box[0] for s in subs)
+    assert tym == max(s.box[3] - s.box[2] for s in subs)
+
+
+@pytest.mark.parametrize("change", [dict(sx=4, nx=9), dict(nu=0.0), dict(mu=-1.0), dict(eps_min=0.0),
+                                    dict(eps0=1e-9, eps_min=1e-8), dict(gamma=1.0), dict(overlap=-1),
+                                    dict(nx=200, sx=2, overlap=4), dict(phi=7)])
+def test_invalid_problems_are_rejected(R, change):
+    prob = synth.Problem(nx=31, ny=31, sx=2, sy=2, overlap=2)
+    for k, v in change.items():
+        setattr(prob, k, v)
+    with pytest.raises(R.RaspenError) as e:
+        R.rsp_partition(R.make_problem(prob))
+    assert e.value.code == R.RSP_EINVAL
+    assert R.rsp_last_error() != ""
+
+
+def test_workspace_bytes(R):
+    o = R.make_options(synth.Options())
+    small = R.rsp_workspace_bytes(R.make_problem(synth.config_small()), o)
+    plain = R.rsp_workspace_bytes(R.make_problem(synth.config_plain()), o)
+    prec = R.rsp_workspace_bytes(R.make_problem(synth.config_precision()), o)
+    assert 0 < small < plain < prec
+    # factors dominate: S * tym * M^2 doubles for the 255x255 workload (64 * 40 * 80^2 * 8 B)
+    assert plain > 64 * 40 * 80 * 80 * 8
+    bad = synth.Problem(nx=9, ny=9, sx=4, sy=1)
+    assert R.rsp_workspace_bytes(R.make_problem(bad), o) == 0

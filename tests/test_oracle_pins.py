@@ -22,6 +22,8 @@ from oracle.schwarz import (Raspen, global_newton, partition, prolong, prolong_c
                             restrict, split_1d)
 from oracle.system import System, laplacian
 
+from cases import lq_direct, mms_problem
+
 EPS_LIST = [1e-10, 1e-6, 1e-3, 0.5, 3.0, 10.0]
 T = np.concatenate([np.linspace(-5, 5, 2001), [-1.0, 0.0, 1.0, 1e-9, -1e-9]])
 
@@ -248,18 +250,6 @@ def test_restriction_prolongation_identities(nx, ny, sx, sy, ov):
 
 
 # ---------------------------------------------------------------- P5, P11: linear-quadratic case
-def lq_direct(nx, ny, nu, yd, f):
-    """[[A, I/nu], [-I, A]] x = [f; -y_d], the eps-independent linear system for
-    phi = 0, mu = 0, assembled here from kron and solved by SuperLU."""
-    hx, hy = 1 / (nx + 1), 1 / (ny + 1)
-    Tx = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(nx, nx)) / hx ** 2
-    Ty = sp.diags([-1, 2, -1], [-1, 0, 1], shape=(ny, ny)) / hy ** 2
-    A = sp.kron(sp.eye(ny), Tx) + sp.kron(Ty, sp.eye(nx))
-    n = nx * ny
-    K = sp.bmat([[A, sp.eye(n) / nu], [-sp.eye(n), A]]).tocsc()
-    return spla.spsolve(K, np.concatenate([f.reshape(-1), -yd.reshape(-1)]))
-
-
 def test_linear_quadratic_case():
     prob = synth.Problem(nx=21, ny=17, phi=synth.PHI_ZERO, nu=1e-3, mu=0.0, eps0=1e-6,
                          eps_min=1e-6, sx=2, sy=2, overlap=2, seed=7)
@@ -277,22 +267,6 @@ def test_linear_quadratic_case():
 
 
 # ---------------------------------------------------------------- P4 (solvers), P6: RASPEN = global
-def mms_problem(kind, nx, ny, sx, sy, ov, eps_min=1e-6):
-    """Manufactured solution in the spirit of Section 4 (pick p crossing +-mu and y,
-    derive f and y_d so that F_eps(y, p) = 0): f and y_d come from the oracle's own F."""
-    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=0.02, eps0=1.0,
-                         eps_min=eps_min, gamma=0.5, sx=sx, sy=sy, overlap=ov)
-    X, Y = synth.node_coords(nx, ny)
-    ys = 0.6 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
-    ps = 0.05 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
-    s0 = System(prob, np.zeros((ny, nx)), np.zeros((ny, nx)))
-    x = np.concatenate([ys.reshape(-1), ps.reshape(-1)])
-    r = s0.residual(x, eps_min)
-    f = r[:s0.n].reshape(ny, nx)              # F_1(x*) - f = r_1 with f = 0  =>  f := r_1
-    yd = -r[s0.n:].reshape(ny, nx)            # F_2 = ... + y_d              =>  y_d := -r_2
-    return prob, yd, f, x
-
-
 @pytest.mark.parametrize("kind", [synth.PHI_CUBIC, synth.PHI_EXP])
 def test_solvers_recover_manufactured_solution(kind):
     prob, yd, f, xs = mms_problem(kind, 19, 15, 2, 2, 2)
