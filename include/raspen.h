@@ -116,6 +116,8 @@ typedef struct rsp_history {
   int64_t factorizations;               /* local Jacobian factorisations (x subdomains)  */
   int64_t local_solves;                 /* local block solves                           */
   int64_t gmres_total;                  /* matrix-vector products                       */
+  int64_t newton_iterations;            /* local Newton iterations, summed over subdomains */
+  int64_t jac_applies;                  /* Algorithm 4 applications (GMRES + restarts)   */
   double residual_final;                /* |F_{eps_min}(y, p)|_2 on the global grid      */
   double flops;                         /* algorithmic flops of the solve               */
   double ms_eval, ms_gmres, ms_total;   /* wall time of Algorithm 3 calls, GMRES, total  */
@@ -197,6 +199,26 @@ int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st
 int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
               const double* yd, const double* f, const double* y0, const double* p0,
               double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
+
+/* ---- kernel timing (HIP events around every launch of the hot-path kernels) ---- */
+
+typedef struct rsp_kernel_stat {
+  char name[32];      /* kernel (or GMRES phase) name                               */
+  int64_t launches;   /* timed launches since the last reset                        */
+  double ms;          /* summed device time between the launch's start/end events    */
+  double flops;       /* summed algorithmic flops of those launches                 */
+  double bytes;       /* summed algorithmic HBM bytes of those launches             */
+} rsp_kernel_stat;
+
+/* Turn event timing on (1) or off (0) for the calls that follow on this context. */
+int rsp_set_profiling(rsp_context* ctx, int on);
+
+/* Zero the accumulated kernel statistics. */
+int rsp_reset_kernel_stats(rsp_context* ctx);
+
+/* Copy up to `max` kernel statistics into `out` (host) and their number into `count`.
+   Synchronises with the recorded events. */
+int rsp_kernel_stats(rsp_context* ctx, rsp_kernel_stat* out, int max, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libraspen.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RSP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels_local.hip", "kernels_global.hip", "kernels_factor.hip", "raspen.cpp"]
+SOURCES = ["kernels_local.hip", "kernels_global.hip", "kernels_factor.hip", "kernels_solve.hip",
+           "kernels_gmres.hip", "raspen.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", "--offload-arch=" + ARCH,

@@ -10,6 +10,9 @@
 // forward g_j = S_j^{-1}(r_j + hy^-2 g_{j-1}); backward z_j = g_j + hy^-2 S_j^{-1} z_{j+1}.
 // Each S_j^{-1} comes from in-place Gauss-Jordan with partial pivoting (rows are
 // not moved: step k pivots on row pr[k]; afterwards S^{-1}[a][b] = A[pr[a]][pinv[b]]).
+// The line block lives in registers (256 threads, an R x R slice each); per step the
+// pivot is found inside the wave that holds the column, the column goes through LDS
+// (one barrier per step) and the pivot row is broadcast with in-wave shuffles.
 // The inverses are stored transposed, facT[s][j][b][a] = S_j^{-1}[a][b], so that
 // the solves read them coalesced.  Lines are padded to M (multiple of 16) with
 // an identity block.
@@ -19,25 +22,55 @@ namespace rsp {
 
 namespace {
 
+// DPP lane exchange inside 16-lane rows (quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror): four steps give every lane of a row the row-wide
+// result of a symmetric combine.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v));
+  const int hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+// Keep the larger |value|, ties to the smaller row index (a total order, so every
+// lane of the row ends with the same winner).
+template <int CTRL>
+__device__ __forceinline__ void pivot_step(double& best, int& bi, double& bv) {
+  const double ob = dpp_d<CTRL>(best);
+  const int oi = dpp_i<CTRL>(bi);
+  const double ov = dpp_d<CTRL>(bv);
+  const bool take = (ob > best) | ((ob == best) & (oi < bi));
+  best = take ? ob : best;
+  bi = take ? oi : bi;
+  bv = take ? ov : bv;
+}
+
+constexpr int kFacThreads = 256;   // 16 x 16 threads; thread (ti, tj) owns rows ti + 16 rr, cols tj + 16 cc
+
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_factor(DevProblem P, const int4* __restrict__ box,
-                                                   const double* __restrict__ tilex,
-                                                   const double* __restrict__ c,
-                                                   const SubState* __restrict__ state,
-                                                   double eps_fixed, const double* __restrict__ rhs,
-                                                   double rhs_scale, double* __restrict__ facT,
-                                                   double* __restrict__ gout) {
+__global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4* __restrict__ box,
+                                                        const double* __restrict__ tilex,
+                                                        const double* __restrict__ c,
+                                                        const SubState* __restrict__ state,
+                                                        double eps_fixed, const double* __restrict__ rhs,
+                                                        double rhs_scale, double* __restrict__ facT,
+                                                        double* __restrict__ gout) {
+  constexpr int R = M / 16;          // rows (and columns) of the line block per thread
   constexpr int LD = M + 1;
-  constexpr int NE = (M * M + kBlock - 1) / kBlock;
-  __shared__ double A[M * LD];
-  __shared__ double colk[M], rowr[M], vin[M], gprev[M];
+  __shared__ double Mx[M * LD];      // finished in-place Gauss-Jordan result of the line
+  __shared__ double colb[2][M];      // pivot column of the current step (double buffered)
+  __shared__ int pivb[2];
+  __shared__ double pivv[2][2];      // pivot value and its reciprocal
+  __shared__ int pr[2][M], pinv[2][M];
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
-  __shared__ double redv[kBlock];
-  __shared__ int redi[kBlock];
-  __shared__ int pr[M], pinv[M], used[M];
+  __shared__ double vin[M], gprev[M];
 
   const int s = blockIdx.x;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
+  const int lane = t & 63;
   double eps = eps_fixed;
   if (state) {
     if (!state[s].active) return;
@@ -47,12 +80,14 @@ __global__ __launch_bounds__(kBlock) void k_factor(DevProblem P, const int4* __r
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const int m = 2 * tx;
   const double hy4i = P.hy2i * P.hy2i;
+  double A[R][R];
 
-  for (int i = t; i < M; i += kBlock) gprev[i] = 0.0;
+  for (int i = t; i < M; i += kFacThreads) gprev[i] = 0.0;
 
   for (int j = 0; j < ty; ++j) {
+    const int pj = j & 1, pp = pj ^ 1;
     // coefficients of line j at z = R_i x + c
-    for (int a = t; a < tx; a += kBlock) {
+    for (int a = t; a < tx; a += kFacThreads) {
       const double y = tilex[halo_idx(P, s, 0, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 0, j, a)] : 0.0);
       const double p = tilex[halo_idx(P, s, 1, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 1, j, a)] : 0.0);
       la[a] = dphi_of(P.phi, y, P.kappa);
@@ -60,209 +95,160 @@ __global__ __launch_bounds__(kBlock) void k_factor(DevProblem P, const int4* __r
       lc[a] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
     }
     __syncthreads();
-    // S_j = D_j - hy^-4 S_{j-1}^{-1} (active m x m block), identity padding
-    double nv[NE];
+    // S_j = D_j - hy^-4 S_{j-1}^{-1} on the active m x m block, identity padding;
+    // S_{j-1}^{-1}[a][b] = Mx[pr[a]][pinv[b]] of the previous line
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = t + q * kBlock;
-      double d = 0.0;
-      if (e < M * M) {
-        const int r = e / M, col = e - r * M;
-        if (r >= m || col >= m) {
-          d = (r == col) ? 1.0 : 0.0;
+    for (int rr = 0; rr < R; ++rr) {
+      const int a = ti + 16 * rr;
+#pragma unroll
+      for (int cc = 0; cc < R; ++cc) {
+        const int b = tj + 16 * cc;
+        double d;
+        if (a >= m || b >= m) {
+          d = (a == b) ? 1.0 : 0.0;
         } else {
-          const int fr = r >= tx, fc = col >= tx;
-          const int ar = r - fr * tx, ac = col - fc * tx;
+          const int fr = a >= tx, fc = b >= tx;
+          const int ar = a - fr * tx, ac = b - fc * tx;
+          d = 0.0;
           if (fr == fc) {
             if (ar == ac) d = P.diag0 + la[ar];
             else if (ar == ac + 1 || ac == ar + 1) d = -P.hx2i;
           } else if (ar == ac) {
             d = fr == 0 ? lb[ar] : lc[ar];
           }
-          if (j > 0) d -= hy4i * A[pr[r] * LD + pinv[col]];
+          if (j > 0) d -= hy4i * Mx[pr[pp][a] * LD + pinv[pp][b]];
         }
+        A[rr][cc] = d;
       }
-      nv[q] = d;
     }
-    __syncthreads();
+    unsigned used = 0;                 // bit rr: row ti + 16 rr already pivoted
+    // in-place Gauss-Jordan with partial pivoting over the m active columns
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = t + q * kBlock;
-      if (e < M * M) {
-        const int r = e / M, col = e - r * M;
-        A[r * LD + col] = nv[q];
-      }
-    }
-    for (int i = t; i < M; i += kBlock) used[i] = 0;
-    __syncthreads();
-
-    // in-place Gauss-Jordan with partial pivoting
-    for (int k = 0; k < M; ++k) {
-      double v = -1.0;
-      if (t < M && !used[t]) v = fabs(A[t * LD + k]);
-      redv[t] = v;
-      redi[t] = t;
-      __syncthreads();
-      for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (t < w) {
-          const double o = redv[t + w];
-          if (o > redv[t]) {          // ties keep the smaller row index
-            redv[t] = o;
-            redi[t] = redi[t + w];
+    for (int ck = 0; ck < R; ++ck) {
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = 16 * ck + kk;
+        if (k >= m) break;
+        const int pb = k & 1;
+        // pivot search by the 16 lanes that hold column k (DPP reduction inside the
+        // row), only in the wave that holds them; the winner's value and reciprocal
+        // are published with its row index
+        if ((t >> 6) == (kk >> 2)) {
+          double best = -1.0, bv = 0.0;
+          int bi = 1 << 30;
+          if (tj == kk) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              const double v = fabs(A[rr][ck]);
+              const bool take = !((used >> rr) & 1u) & (v > best);
+              best = take ? v : best;
+              bi = take ? ti + 16 * rr : bi;
+              bv = take ? A[rr][ck] : bv;
+            }
+          }
+          pivot_step<0xB1>(best, bi, bv);
+          pivot_step<0x4E>(best, bi, bv);
+          pivot_step<0x141>(best, bi, bv);
+          pivot_step<0x140>(best, bi, bv);
+          if (tj == kk) {
+            if (ti == 0) {
+              const bool ok = bi < M;                     // a NaN column has no candidate
+              const double pv = ok ? bv : __builtin_nan("");
+              pivb[pb] = ok ? bi : k;
+              pivv[pb][0] = pv;
+              pivv[pb][1] = 1.0 / pv;
+            }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
           }
         }
         __syncthreads();
-      }
-      const int r = redi[0];
-      if (t < M) {
-        colk[t] = A[t * LD + k];
-        rowr[t] = A[r * LD + t];
-      }
-      if (t == 0) {
-        used[r] = 1;
-        pr[k] = r;
-        pinv[r] = k;
-      }
-      __syncthreads();
-      const double ipiv = 1.0 / rowr[k];
+        const int r = __builtin_amdgcn_readfirstlane(pivb[pb]);
+        const int rq = r >> 4, rl = r & 15;
+        const double piv = pivv[pb][0];
+        const double ipiv = pivv[pb][1];
+        // pivot row: held by lane (rl) of this 16-lane group, register row rq (wave-uniform)
+        double rs[R], mult[R], src[R];
+        // rq is wave-uniform: one scalar branch picks the register row (the empty asm
+        // keeps the compiler from turning the cases into per-element selects)
 #pragma unroll
-      for (int q = 0; q < NE; ++q) {
-        const int e = t + q * kBlock;
-        if (e < M * M) {
-          const int i = e / M, jj = e - i * M;
-          double a;
-          if (i == r) a = (jj == k) ? ipiv : rowr[jj] * ipiv;
-          else a = (jj == k) ? -colk[i] * ipiv : A[i * LD + jj] - colk[i] * (rowr[jj] * ipiv);
-          A[i * LD + jj] = a;
+        for (int q = 0; q < R; ++q)
+          if (q == rq) {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int cc = 0; cc < R; ++cc) src[cc] = A[q][cc];
+          }
+#pragma unroll
+        for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(src[cc], (lane & 48) | rl, 64) * ipiv;
+        // multipliers; the pivot row takes piv - 1 so that the update below turns it
+        // into row / piv
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+          const double cv = colb[pb][ti + 16 * rr];
+          mult[rr] = (ti + 16 * rr == r) ? piv - 1.0 : cv;
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
+        // column k becomes -column k / piv, and (r, k) = 1 / piv
+        if (tj == kk) {
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            const double cv = colb[pb][ti + 16 * rr];
+            A[rr][ck] = (ti + 16 * rr == r) ? ipiv : -cv * ipiv;
+          }
+        }
+        if (ti == rl) used |= 1u << rq;
+        if (t == 0) {
+          pr[pj][k] = r;
+          pinv[pj][r] = k;
         }
       }
-      __syncthreads();
     }
+    // padded steps are identities: pivot row k for k >= m
+    for (int k = m + t; k < M; k += kFacThreads) {
+      pr[pj][k] = k;
+      pinv[pj][k] = k;
+    }
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int cc = 0; cc < R; ++cc) Mx[(ti + 16 * rr) * LD + tj + 16 * cc] = A[rr][cc];
+    __syncthreads();
 
     // fused forward sweep: g_j = S_j^{-1}(rhs_scale r_j + hy^-2 g_{j-1})
     if (rhs) {
-      for (int i = t; i < M; i += kBlock) {
-        double r = 0.0;
+      for (int i = t; i < M; i += kFacThreads) {
+        double rv = 0.0;
         if (i < m) {
           const int f = i >= tx;
-          r = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
+          rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
         }
-        vin[i] = r + P.hy2i * gprev[i];
-      }
-      __syncthreads();
-      double acc = 0.0;
-      if (t < M) {
-        const double* row = A + pr[t] * LD;
-        for (int k = 0; k < M; ++k) acc += row[k] * vin[pr[k]];
+        vin[i] = rv + P.hy2i * gprev[i];
       }
       __syncthreads();
       if (t < M) {
+        const double* row = Mx + pr[pj][t] * LD;
+        double acc = 0.0;
+        for (int k = 0; k < M; ++k) acc += row[k] * vin[pr[pj][k]];
         gprev[t] = acc;
         gout[((size_t)s * P.tym + j) * M + t] = acc;
       }
     }
-    // store S_j^{-1} transposed
+    // store S_j^{-1} transposed: facT[b][a] = Mx[pr[a]][pinv[b]]
     double* F = facT + ((size_t)s * P.tym + j) * M * M;
 #pragma unroll
-    for (int q = 0; q < NE; ++q) {
-      const int e = t + q * kBlock;
-      if (e < M * M) {
-        const int b = e / M, a = e - b * M;
-        F[e] = A[pr[a] * LD + pinv[b]];
+    for (int cc = 0; cc < R; ++cc) {
+      const int b = tj + 16 * cc;
+      const int cb = pinv[pj][b];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) {
+        const int a = ti + 16 * rr;
+        F[(size_t)b * M + a] = Mx[pr[pj][a] * LD + cb];
       }
     }
     __syncthreads();
   }
-}
-
-// z_{ty-1} = g_{ty-1}; z_j = g_j + hy^-2 S_j^{-1} z_{j+1}; written to the tile `out`.
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_solve_bwd(DevProblem P, const int4* __restrict__ box,
-                                                      const SubState* __restrict__ state,
-                                                      const double* __restrict__ facT,
-                                                      const double* __restrict__ g,
-                                                      double* __restrict__ out) {
-  __shared__ double z[M];
-  const int s = blockIdx.x, t = threadIdx.x;
-  if (state && !state[s].active) return;
-  const int4 bx = box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
-  const int m = 2 * tx;
-  for (int j = ty - 1; j >= 0; --j) {
-    double v = 0.0;
-    if (t < M) {
-      v = g[((size_t)s * P.tym + j) * M + t];
-      if (j < ty - 1) {
-        const double* F = facT + ((size_t)s * P.tym + j) * M * M;
-        double acc = 0.0;
-        for (int b = 0; b < M; ++b) acc += F[(size_t)b * M + t] * z[b];
-        v += P.hy2i * acc;
-      }
-    }
-    __syncthreads();
-    if (t < M) {
-      z[t] = v;
-      if (t < m) {
-        const int f = t >= tx;
-        out[tile_idx(P, s, f, j, t - f * tx)] = v;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Forward and backward sweeps with stored factors: out = J_i^{-1} rhs.
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_block_solve(DevProblem P, const int4* __restrict__ box,
-                                                        const double* __restrict__ facT,
-                                                        const double* __restrict__ rhs,
-                                                        double* __restrict__ out) {
-  __shared__ double gl[kMaxTile * M];
-  __shared__ double v[M];
-  const int s = blockIdx.x, t = threadIdx.x;
-  const int4 bx = box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
-  const int m = 2 * tx;
-  for (int e = t; e < 2 * P.txm * P.tym; e += kBlock) {       // zero padding of the output
-    const int f = e / (P.txm * P.tym);
-    const int r = e - f * P.txm * P.tym;
-    const int b = r / P.txm, a = r - b * P.txm;
-    if (a >= tx || b >= ty) out[tile_idx(P, s, f, b, a)] = 0.0;
-  }
-  for (int j = 0; j < ty; ++j) {
-    if (t < M) {
-      double r = 0.0;
-      if (t < m) {
-        const int f = t >= tx;
-        r = rhs[tile_idx(P, s, f, j, t - f * tx)];
-      }
-      v[t] = r + (j > 0 ? P.hy2i * gl[(j - 1) * M + t] : 0.0);
-    }
-    __syncthreads();
-    if (t < M) {
-      const double* F = facT + ((size_t)s * P.tym + j) * M * M;
-      double acc = 0.0;
-      for (int b = 0; b < M; ++b) acc += F[(size_t)b * M + t] * v[b];
-      gl[j * M + t] = acc;
-    }
-    __syncthreads();
-  }
-  for (int j = ty - 2; j >= 0; --j) {
-    if (t < M) {
-      const double* F = facT + ((size_t)s * P.tym + j) * M * M;
-      double acc = 0.0;
-      for (int b = 0; b < M; ++b) acc += F[(size_t)b * M + t] * gl[(j + 1) * M + b];
-      v[t] = gl[j * M + t] + P.hy2i * acc;
-    }
-    __syncthreads();
-    if (t < M) gl[j * M + t] = v[t];
-    __syncthreads();
-  }
-  for (int j = 0; j < ty; ++j)
-    for (int i = t; i < m; i += kBlock) {
-      const int f = i >= tx;
-      out[tile_idx(P, s, f, j, i - f * tx)] = gl[j * M + i];
-    }
 }
 
 #define RSP_DISPATCH_M(M_, CALL) \
@@ -282,21 +268,7 @@ void launch_factor(const DevProblem& P, const int4* box, const double* tilex, co
                    const SubState* state, double eps_fixed, const double* rhs, double rhs_scale,
                    double* facT, double* g, hipStream_t st) {
 #define RSP_CALL(MM) \
-  k_factor<MM><<<P.S, kBlock, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
-#undef RSP_CALL
-}
-
-void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state,
-                      const double* facT, const double* g, double* out, hipStream_t st) {
-#define RSP_CALL(MM) k_solve_bwd<MM><<<P.S, kBlock, 0, st>>>(P, box, state, facT, g, out)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
-#undef RSP_CALL
-}
-
-void launch_block_solve(const DevProblem& P, const int4* box, const double* facT,
-                        const double* rhs, double* out, hipStream_t st) {
-#define RSP_CALL(MM) k_block_solve<MM><<<P.S, kBlock, 0, st>>>(P, box, facT, rhs, out)
+  k_factor<MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g)
   RSP_DISPATCH_M(P.M, RSP_CALL)
 #undef RSP_CALL
 }

@@ -7,6 +7,7 @@
 #include "raspen.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -141,10 +142,11 @@ DevProblem make_dev(const rsp_problem* p, const Partition& part) {
 
 // Sizes (in doubles unless noted) of every workspace buffer.
 struct Layout {
-  size_t n, L, tile, halo, fac, g, V, partial;
+  size_t n, L, tile, halo, fac, g, V, partial, gpart;
   size_t bytes() const {
     return 8 * (2 * n /*yd,f*/ + 2 * L /*x,F*/ + halo + 5 * tile /*c,dir,res,t1,t2*/ + fac + g +
-                V + 3 * L /*w, b, dx*/ + partial + 4 * 80 /*h bufs*/);
+                V + 4 * L /*w, b, dx, r*/ + partial + 4 * 80 /*h bufs*/ + 2 * gpart) +
+           sizeof(rsp::GmState);
   }
 };
 
@@ -158,14 +160,30 @@ Layout make_layout(const DevProblem& P, const rsp_options* o) {
   l.g = (size_t)P.S * P.tym * P.M;
   l.V = (size_t)(o->gmres_restart + 1) * l.L;
   l.partial = (size_t)rsp::multidot_blocks(l.L) * 72;
+  l.gpart = (size_t)rsp::kGmBlocks * rsp::kGmMaxVec;
   return l;
 }
 
-constexpr size_t kBuffers = 24;   // buffers carved from the workspace, each 256-byte aligned
+constexpr size_t kBuffers = 28;   // buffers carved from the workspace, each 256-byte aligned
 
 size_t layout_bytes(const Layout& l, int S) {
   return l.bytes() + S * (sizeof(int4) * 2 + sizeof(SubState)) + kBuffers * 256;
 }
+
+// Kernel timing: HIP events around launches, resolved at synchronisation points.
+enum Kid {
+  KID_RESTRICT, KID_INIT, KID_FACTOR, KID_SOLVE_BWD, KID_LINESEARCH, KID_PROLONG, KID_RING,
+  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_N
+};
+const char* const kKidName[KID_N] = {"restrict_halo", "newton_init", "factor", "solve_bwd",
+                                     "linesearch", "prolong", "ring_rhs", "block_solve",
+                                     "gmres_ortho", "global_residual"};
+
+struct Pending {
+  int kid;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
 
 }  // namespace
 
@@ -186,10 +204,16 @@ struct rsp_context {
   double *yd = nullptr, *f = nullptr, *x = nullptr, *F = nullptr, *tilex = nullptr;
   double *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
   double *fac = nullptr, *g = nullptr, *V = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr;
-  double *partial = nullptr, *hbuf = nullptr;
+  double *partial = nullptr, *hbuf = nullptr, *r = nullptr, *gp1 = nullptr, *gp2 = nullptr;
+  rsp::GmState* gst = nullptr;
   std::vector<SubState> hstate;
+  // kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  rsp_kernel_stat kstat[KID_N]{};
   // counters of the current solve
-  int64_t n_factor = 0, n_solve = 0, n_gmres = 0;
+  int64_t n_factor = 0, n_solve = 0, n_gmres = 0, n_newton = 0, n_apply = 0;
   double flops = 0;
   int64_t eval_inner_sum = 0;
 };
@@ -200,6 +224,78 @@ struct EvalStats {
   int status = 0, inner_min = 0, inner_max = 0, backtracks = 0;
   double inner_avg = 0;
 };
+
+int resolve_events(rsp_context* ctx) {
+  for (auto& p : ctx->pending) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    rsp_kernel_stat& k = ctx->kstat[p.kid];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+  return 0;
+}
+
+hipEvent_t event_get(rsp_context* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches issued during its lifetime with events (when timing is on),
+// attributing the given algorithmic flops and bytes to kernel `kid`.
+struct Timed {
+  rsp_context* c;
+  int kid;
+  hipStream_t st;
+  double fl, by;
+  hipEvent_t a = nullptr;
+  Timed(rsp_context* c_, int kid_, hipStream_t st_, double fl_, double by_)
+      : c(c_), kid(kid_), st(st_), fl(fl_), by(by_) {
+    if (c->prof && (a = event_get(c)) != nullptr && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = event_get(c);
+    if (!b || hipEventRecord(b, st) != hipSuccess) return;
+    c->pending.push_back({kid, a, b, fl, by});
+    if (c->pending.size() > 16384) (void)resolve_events(c);
+  }
+};
+
+// Algorithmic work of the per-subdomain kernels (m = 2 tx line unknowns, ty lines).
+struct SubWork {
+  double factor_fl = 0, factor_by = 0, bwd_fl = 0, bwd_by = 0, solve_fl = 0, solve_by = 0;
+  double tile_by = 0, halo_by = 0;
+};
+
+SubWork sub_work(const std::vector<int4>& boxes, const std::vector<SubState>* state) {
+  SubWork w;
+  for (size_t s = 0; s < boxes.size(); ++s) {
+    if (state && !(*state)[s].active) continue;
+    const double tx = boxes[s].y - boxes[s].x, ty = boxes[s].w - boxes[s].z, m = 2 * tx;
+    w.factor_fl += 16.0 * ty * tx * tx * tx;           // ty Gauss-Jordan inversions of m x m
+    w.factor_by += 8.0 * ty * m * m;                   // the inverses written once
+    w.bwd_fl += 2.0 * (ty - 1) * m * m;
+    w.bwd_by += 8.0 * (ty - 1) * m * m;
+    w.solve_fl += 2.0 * (2 * ty - 1) * m * m;          // forward + backward sweeps
+    w.solve_by += 8.0 * (2 * ty - 1) * m * m + 8.0 * 2 * m * ty;
+    w.tile_by += 8.0 * m * ty;
+    w.halo_by += 8.0 * 2 * (tx + 2) * (ty + 2);
+  }
+  return w;
+}
 
 // Number of Algorithm 1 steps until eps reaches eps_min (evaluated like the device).
 int continuation_steps(double eps0, double eps_min, double gamma) {
@@ -212,24 +308,6 @@ int continuation_steps(double eps0, double eps_min, double gamma) {
   return k;
 }
 
-double factor_flops(rsp_context* ctx) {       // 16 ty tx^3 per subdomain (2 m^3 per line)
-  double s = 0;
-  for (auto& b : ctx->part.box) {
-    const double tx = b.y - b.x, ty = b.w - b.z;
-    s += 16.0 * ty * tx * tx * tx;
-  }
-  return s;
-}
-
-double solve_flops(rsp_context* ctx) {        // 2 sweeps of dense m x m products per line
-  double s = 0;
-  for (auto& b : ctx->part.box) {
-    const double tx = b.y - b.x, ty = b.w - b.z;
-    s += 16.0 * ty * tx * tx;
-  }
-  return s;
-}
-
 // Algorithm 3 on the device: local Newton solves (Algorithm 1) for every subdomain,
 // factorisation at x^(i), and the assembly F(x) = sum_i P~_i C_i(x) into `out`.
 int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, EvalStats* es,
@@ -238,68 +316,100 @@ int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, 
   const rsp_problem& pr = ctx->prob;
   const rsp_options& o = ctx->opts;
   const double eps0 = continuation ? pr.eps0 : pr.eps_min;
-  rsp::launch_restrict_halo(P, ctx->box, x, ctx->tilex, st);
-  rsp::launch_newton_init(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->res, ctx->state,
-                          eps0, o.tol_inner, o.max_inner, st);
+  const SubWork all = sub_work(ctx->part.box, nullptr);
+  {
+    Timed t(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
+    rsp::launch_restrict_halo(P, ctx->box, x, ctx->tilex, st);
+  }
+  {
+    Timed t(ctx, KID_INIT, st, 40.0 * all.tile_by / 8, all.halo_by + 3 * all.tile_by);
+    rsp::launch_newton_init(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->res, ctx->state,
+                            eps0, o.tol_inner, o.max_inner, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->hstate.data(), ctx->state, sizeof(SubState) * P.S,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   const int ncont = continuation_steps(eps0, pr.eps_min, pr.gamma);
   int it = 0;
-  const double ff = factor_flops(ctx), sf = solve_flops(ctx);
-  for (;;) {
-    // run the continuation steps without looking (every subdomain needs them), then check
-    // after every step
+  int active = 0;
+  for (auto& s : ctx->hstate) active += s.active;
+  while (active && it < o.max_inner + 1) {
+    // every subdomain needs the continuation steps: run them without looking, then
+    // check after every step
     const int batch = std::max(1, std::min(ncont - it, o.max_inner + 1 - it));
-    if (it >= o.max_inner + 1) break;
+    const SubWork w = sub_work(ctx->part.box, &ctx->hstate);
     for (int b = 0; b < batch; ++b) {
-      rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, ctx->state, 0.0, ctx->res, -1.0,
-                         ctx->fac, ctx->g, st);
-      rsp::launch_solve_bwd(P, ctx->box, ctx->state, ctx->fac, ctx->g, ctx->dir, st);
-      rsp::launch_linesearch(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->dir, ctx->res,
-                             ctx->state, o.sigma, o.alpha_min, o.max_inner, st);
+      {
+        Timed t(ctx, KID_FACTOR, st, w.factor_fl + w.bwd_fl / 2, w.factor_by);
+        rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, ctx->state, 0.0, ctx->res, -1.0,
+                           ctx->fac, ctx->g, st);
+      }
+      {
+        Timed t(ctx, KID_SOLVE_BWD, st, w.bwd_fl, w.bwd_by);
+        rsp::launch_solve_bwd(P, ctx->box, ctx->state, ctx->fac, ctx->g, ctx->dir, st);
+      }
+      {
+        Timed t(ctx, KID_LINESEARCH, st, 40.0 * w.tile_by / 8, 6 * w.tile_by);
+        rsp::launch_linesearch(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->dir, ctx->res,
+                               ctx->state, o.sigma, o.alpha_min, o.max_inner, st);
+      }
     }
     HIPCHK(hipGetLastError());
-    const int before = it;
     it += batch;
     HIPCHK(hipMemcpyAsync(ctx->hstate.data(), ctx->state, sizeof(SubState) * P.S,
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int active = 0;
+    active = 0;
     for (auto& s : ctx->hstate) active += s.active;
-    (void)before;
-    if (!active) break;
   }
-  // counters: every subdomain did hstate.k Newton steps (one factor + solve each)
   int64_t ksum = 0;
   es->inner_min = 1 << 30;
   es->inner_max = 0;
   es->backtracks = 0;
   es->status = 0;
-  for (auto& s : ctx->hstate) {
-    ksum += s.k;
-    es->inner_min = std::min(es->inner_min, s.k);
-    es->inner_max = std::max(es->inner_max, s.k);
-    es->backtracks += s.backtracks;
-    es->status = std::max(es->status, s.status);
+  double fl = 0;
+  for (int s = 0; s < P.S; ++s) {
+    const SubState& S = ctx->hstate[s];
+    ksum += S.k;
+    es->inner_min = std::min(es->inner_min, S.k);
+    es->inner_max = std::max(es->inner_max, S.k);
+    es->backtracks += S.backtracks;
+    es->status = std::max(es->status, S.status);
+    const double tx = ctx->part.box[s].y - ctx->part.box[s].x, ty = ctx->part.box[s].w - ctx->part.box[s].z;
+    fl += S.k * (16.0 * ty * tx * tx * tx + 2.0 * (2 * ty - 1) * 4 * tx * tx);
   }
   es->inner_avg = (double)ksum / P.S;
   ctx->n_factor += ksum + P.S;
   ctx->n_solve += ksum;
-  ctx->flops += (double)ksum / P.S * (ff + sf) + ff;
+  ctx->n_newton += ksum;
+  ctx->flops += fl + all.factor_fl;
   // factor at x^(i) = x + P_i C_i(x) for Algorithm 4
-  rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, nullptr, pr.eps_min, nullptr, 0.0, ctx->fac,
-                     ctx->g, st);
-  rsp::launch_prolong(P, ctx->box, ctx->core, ctx->c, nullptr, out, st);
+  {
+    Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
+    rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, nullptr, pr.eps_min, nullptr, 0.0, ctx->fac,
+                       ctx->g, st);
+  }
+  {
+    Timed t(ctx, KID_PROLONG, st, 0, 8.0 * 2 * ctx->lay.L);
+    rsp::launch_prolong(P, ctx->box, ctx->core, ctx->c, nullptr, out, st);
+  }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-// Algorithm 4: out = -d + sum_i P~_i J_i^{-1} (hy^-2/hx^-2 weighted outside neighbours of d).
-int run_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st) {
+// Algorithm 4: out = -d + sum_i P~_i J_i^{-1} (hx^-2/hy^-2 weighted outside neighbours of d).
+int run_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st,
+                  const int* skip = nullptr) {
   const DevProblem& P = ctx->P;
-  rsp::launch_ring_rhs(P, ctx->box, d, ctx->t1, st);
-  rsp::launch_block_solve(P, ctx->box, ctx->fac, ctx->t1, ctx->t2, st);
-  rsp::launch_prolong(P, ctx->box, ctx->core, ctx->t2, d, out, st);
+  const SubWork w = sub_work(ctx->part.box, nullptr);
+  {
+    Timed t(ctx, KID_BLOCK_SOLVE, st, w.solve_fl, w.solve_by + 8.0 * 2 * ctx->lay.L);
+    rsp::launch_jac_apply(P, ctx->box, ctx->core, ctx->fac, d, out, skip, st);
+  }
   ctx->n_solve += P.S;
-  ctx->flops += solve_flops(ctx);
+  ctx->n_apply += 1;
+  ctx->flops += w.solve_fl;
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -316,98 +426,53 @@ int dev_norm(rsp_context* ctx, const double* v, size_t L, double* out, hipStream
   return 0;
 }
 
-// Restarted GMRES(m) with classical Gram-Schmidt applied twice, x_0 = 0:
-// solves F'(x) dx = b.  Returns the status (RSP_GMRES_STAGNATION if max_gmres is hit).
+// Restarted GMRES(m), x_0 = 0, on the device (kernels_gmres.hip): solves F'(x) dx = b.
+// The host enqueues Arnoldi steps in chunks and reads the small state header back
+// once per chunk; a stop flag set on the device turns the rest of a chunk into
+// no-ops.  Returns RSP_GMRES_STAGNATION if max_gmres products did not reach rtol.
 int run_gmres(rsp_context* ctx, const double* b, double* xs, int* used_out, double* rel_out,
               hipStream_t st) {
+  constexpr int kChunk = 8;
   const size_t L = ctx->lay.L;
   const int m = ctx->opts.gmres_restart;
-  const int maxit = ctx->opts.max_gmres;
   const double rtol = ctx->opts.gmres_rtol;
-  const int nb = rsp::multidot_blocks(L);
   double* V = ctx->V;
-  double bnorm = 0;
-  RSPCHK(dev_norm(ctx, b, L, &bnorm, st));
+  rsp::GmState hs{};
+  const size_t hdr = offsetof(rsp::GmState, H);
+  rsp::gm_init_state(ctx->gst, m, ctx->opts.max_gmres, rtol, st);
   HIPCHK(hipMemsetAsync(xs, 0, L * sizeof(double), st));
-  *used_out = 0;
-  *rel_out = 0;
-  if (bnorm == 0) return 0;
-  int used = 0;
-  double rel = 1;
-  bool first = true;
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hh(2 * 80 + 1);
-  while (used < maxit) {
-    if (first) {
-      HIPCHK(hipMemcpyAsync(V, b, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-    } else {
-      RSPCHK(run_jac_apply(ctx, xs, ctx->w, st));
-      HIPCHK(hipMemcpyAsync(V, b, L * sizeof(double), hipMemcpyDeviceToDevice, st));
-      rsp::launch_axpy(-1.0, ctx->w, V, L, st);
-    }
-    first = false;
-    double beta = 0;
-    RSPCHK(dev_norm(ctx, V, L, &beta, st));
-    rel = beta / bnorm;
-    if (beta <= rtol * bnorm) break;
-    rsp::launch_scale(1.0 / beta, V, V, L, st);
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
-    int jlast = -1;
-    for (int j = 0; j < m; ++j) {
-      double* vj = V + (size_t)j * L;
-      double* vn = V + (size_t)(j + 1) * L;
-      RSPCHK(run_jac_apply(ctx, vj, ctx->w, st));
-      ++used;
-      // CGS2: h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2
-      rsp::launch_multidot(V, L, j + 1, ctx->w, L, ctx->partial, st);
-      rsp::launch_reduce_partials(ctx->partial, nb, j + 1, ctx->hbuf, 0, st);
-      rsp::launch_axpy_multi(V, L, j + 1, ctx->hbuf, ctx->w, L, st);
-      rsp::launch_multidot(V, L, j + 1, ctx->w, L, ctx->partial, st);
-      rsp::launch_reduce_partials(ctx->partial, nb, j + 1, ctx->hbuf + 80, 0, st);
-      rsp::launch_axpy_multi(V, L, j + 1, ctx->hbuf + 80, ctx->w, L, st);
-      rsp::launch_multidot(ctx->w, 0, 1, ctx->w, L, ctx->partial, st);
-      rsp::launch_reduce_partials(ctx->partial, nb, 1, ctx->hbuf + 160, 0, st);
-      rsp::launch_scale_by_inv_sqrt(ctx->w, ctx->hbuf + 160, vn, L, st);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(hh.data(), ctx->hbuf, (2 * 80 + 1) * sizeof(double),
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      double* Hc = H.data();
-      for (int i = 0; i <= j; ++i) Hc[i * m + j] = hh[i] + hh[80 + i];
-      Hc[(j + 1) * m + j] = std::sqrt(hh[160]);
-      const bool breakdown = !(hh[160] > 0);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hc[i * m + j] + sn[i] * Hc[(i + 1) * m + j];
-        Hc[(i + 1) * m + j] = -sn[i] * Hc[i * m + j] + cs[i] * Hc[(i + 1) * m + j];
-        Hc[i * m + j] = t;
+  rsp::launch_gm_sumsq(b, L, ctx->gp1, st);
+  rsp::launch_gm_start(V, L, b, ctx->gst, ctx->gp1, 1, st);
+  for (;;) {
+    for (int j = 0; j < m;) {
+      const int chunk = std::min(kChunk, m - j);
+      for (int c = 0; c < chunk; ++c, ++j) {
+        RSPCHK(run_jac_apply(ctx, V + (size_t)j * L, ctx->w, st, &ctx->gst->done));
+        Timed tm(ctx, KID_GMRES_ORTHO, st, (double)L * (8.0 * (j + 1) + 3), 8.0 * L * (4.0 * j + 13));
+        rsp::launch_gm_arnoldi(V, L, j, ctx->w, ctx->gst, ctx->gp1, ctx->gp2, st);
       }
-      const double den = std::hypot(Hc[j * m + j], Hc[(j + 1) * m + j]);
-      cs[j] = Hc[j * m + j] / den;
-      sn[j] = Hc[(j + 1) * m + j] / den;
-      Hc[j * m + j] = den;
-      Hc[(j + 1) * m + j] = 0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      rel = std::fabs(gv[j + 1]) / bnorm;
-      jlast = j;
-      if (rel <= rtol || used >= maxit || breakdown) break;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&hs, ctx->gst, hdr, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hs.done) break;
     }
-    const int k = jlast + 1;
-    for (int i = k - 1; i >= 0; --i) {
-      double s = gv[i];
-      for (int l = i + 1; l < k; ++l) s -= H[i * m + l] * y[l];
-      y[i] = s / H[i * m + i];
-    }
-    HIPCHK(hipMemcpyAsync(ctx->hbuf + 2 * 80, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-    rsp::launch_combine(V, L, k, ctx->hbuf + 2 * 80, xs, L, st);
-    HIPCHK(hipStreamSynchronize(st));   // y lives on the host stack frame
-    if (rel <= rtol) break;
+    rsp::launch_gm_update_x(V, L, ctx->gst, xs, st);
+    if (!(hs.rel > rtol) || hs.used >= ctx->opts.max_gmres || hs.steps == 0) break;
+    // restart from r = b - F'(x) x
+    RSPCHK(run_jac_apply(ctx, xs, ctx->w, st));
+    rsp::launch_gm_residual(b, ctx->w, ctx->r, L, st);
+    rsp::launch_gm_sumsq(ctx->r, L, ctx->gp1, st);
+    rsp::launch_gm_start(V, L, ctx->r, ctx->gst, ctx->gp1, 0, st);
+    HIPCHK(hipMemcpyAsync(&hs, ctx->gst, hdr, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hs.done) break;
   }
-  ctx->n_gmres += used;
-  *used_out = used;
-  *rel_out = rel;
-  return rel <= rtol ? 0 : RSP_GMRES_STAGNATION;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  ctx->n_gmres += hs.used;
+  *used_out = hs.used;
+  *rel_out = hs.rel;
+  return hs.rel <= rtol ? 0 : RSP_GMRES_STAGNATION;
 }
 
 int ensure_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts) {
@@ -455,6 +520,10 @@ int ensure_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* o
   ctx->dx = (double*)take(8 * lay.L);
   ctx->partial = (double*)take(8 * lay.partial);
   ctx->hbuf = (double*)take(8 * 4 * 80);
+  ctx->r = (double*)take(8 * lay.L);
+  ctx->gp1 = (double*)take(8 * lay.gpart);
+  ctx->gp2 = (double*)take(8 * lay.gpart);
+  ctx->gst = (rsp::GmState*)take(sizeof(rsp::GmState));
   if ((size_t)(p - (char*)ctx->mem) > ctx->mem_bytes)
     return fail(RSP_ENOMEM, "internal: workspace layout overflow");
   ctx->prob = *prob;
@@ -514,10 +583,10 @@ int rsp_context_create(rsp_context** ctx, int device, size_t hbm_budget) {
 
 int rsp_context_destroy(rsp_context* ctx) {
   if (!ctx) return 0;
-  if (ctx->mem) {
-    (void)hipSetDevice(ctx->device);
-    (void)hipFree(ctx->mem);
-  }
+  (void)hipSetDevice(ctx->device);
+  (void)resolve_events(ctx);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->mem) (void)hipFree(ctx->mem);
   delete ctx;
   return 0;
 }
@@ -615,7 +684,7 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
   if ((y0 == nullptr) != (p0 == nullptr)) return fail(RSP_EINVAL, "give both y0 and p0 or neither");
   RSPCHK(rsp_setup(ctx, prob, opts, yd, f, stream));
   const size_t n = ctx->lay.n, L = ctx->lay.L;
-  ctx->n_factor = ctx->n_solve = ctx->n_gmres = 0;
+  ctx->n_factor = ctx->n_solve = ctx->n_gmres = ctx->n_newton = ctx->n_apply = 0;
   ctx->flops = 0;
   rsp_history hloc;
   rsp_history* h = hist ? hist : &hloc;
@@ -684,12 +753,42 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
   h->factorizations = ctx->n_factor;
   h->local_solves = ctx->n_solve;
   h->gmres_total = ctx->n_gmres;
+  h->newton_iterations = ctx->n_newton;
+  h->jac_applies = ctx->n_apply;
   h->residual_final = rfin;
   h->flops = ctx->flops;
   h->ms_eval = ms_eval;
   h->ms_gmres = ms_gmres;
   h->ms_total = ms(t0, clk::now());
+  RSPCHK(resolve_events(ctx));
   return status;
+}
+
+int rsp_set_profiling(rsp_context* ctx, int on) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  ctx->prof = on != 0;
+  return 0;
+}
+
+int rsp_reset_kernel_stats(rsp_context* ctx) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  RSPCHK(resolve_events(ctx));
+  for (auto& k : ctx->kstat) k = rsp_kernel_stat{};
+  return 0;
+}
+
+int rsp_kernel_stats(rsp_context* ctx, rsp_kernel_stat* out, int max, int32_t* count) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  RSPCHK(resolve_events(ctx));
+  int n = 0;
+  for (int k = 0; k < KID_N && n < max; ++k) {
+    if (!out) break;
+    out[n] = ctx->kstat[k];
+    std::snprintf(out[n].name, sizeof out[n].name, "%s", kKidName[k]);
+    ++n;
+  }
+  if (count) *count = out ? n : KID_N;
+  return 0;
 }
 
 }  // extern "C"

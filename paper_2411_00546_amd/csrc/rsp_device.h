@@ -35,6 +35,17 @@ struct SubState {
   int backtracks;    // step halvings so far
 };
 
+// Device-resident GMRES state (restart m <= kGmMaxRestart).
+constexpr int kGmMaxRestart = 64;
+constexpr int kGmMaxVec = kGmMaxRestart + 1;
+constexpr int kGmBlocks = 128;        // fixed reduction blocks of the GMRES vector kernels
+struct GmState {
+  int m, maxit, steps, used, done, pad;
+  double rtol, bnorm, beta, rel;
+  double H[(kGmMaxRestart + 1) * kGmMaxRestart];   // H[i * m + j]
+  double cs[kGmMaxRestart], sn[kGmMaxRestart], g[kGmMaxRestart + 1];
+};
+
 // ---------------------------------------------------------------- pointwise
 // P_eps in the cancellation-free form 2t / (sqrt((t+1)^2+eps) + sqrt((t-1)^2+eps))
 // (Lemma 3.1, proof of point (i)).

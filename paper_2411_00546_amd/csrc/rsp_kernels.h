@@ -38,9 +38,13 @@ void launch_factor(const DevProblem& P, const int4* box, const double* tilex, co
 // a5: backward sweep after a fused forward sweep.
 void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state,
                       const double* facT, const double* g, double* out, hipStream_t st);
-// a5/a9: forward + backward sweeps with stored factors.
+// a5: forward + backward sweeps with stored factors (tile rhs -> tile out).
 void launch_block_solve(const DevProblem& P, const int4* box, const double* facT,
                         const double* rhs, double* out, hipStream_t st);
+// a9 (Algorithm 4), fused: ring rhs of d, both sweeps, out = -d + sum_i P~_i z_i.
+// `skip` (nullable, device): the launch does nothing when *skip != 0.
+void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const double* facT,
+                      const double* d, double* out, const int* skip, hipStream_t st);
 // Section 4 F(x, eps) on the whole grid and the control u(p).
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
                             const double* x, double eps, double* out, hipStream_t st);
@@ -60,5 +64,15 @@ void launch_axpy(double a, const double* x, double* y, size_t L, hipStream_t st)
 void launch_scale(double a, const double* x, double* y, size_t L, hipStream_t st);
 void launch_combine(const double* V, size_t ldv, int k, const double* y, double* x, size_t L,
                     hipStream_t st);
+
+// Device-resident GMRES (kernels_gmres.hip).
+void gm_init_state(GmState* st_dev, int m, int maxit, double rtol, hipStream_t s);
+void launch_gm_sumsq(const double* v, size_t L, double* partial, hipStream_t s);
+void launch_gm_residual(const double* b, const double* w, double* r, size_t L, hipStream_t s);
+void launch_gm_start(double* V0, size_t L, const double* r, GmState* st, const double* partial,
+                     int first_cycle, hipStream_t s);
+void launch_gm_arnoldi(const double* V, size_t L, int j, double* w, GmState* st, double* p1,
+                       double* p2, hipStream_t s);
+void launch_gm_update_x(const double* V, size_t L, GmState* st, double* x, hipStream_t s);
 
 }  // namespace rsp

@@ -50,7 +50,8 @@ class rsp_history(ctypes.Structure):
                 ("inner_max", ctypes.c_int32 * _H), ("inner_avg", ctypes.c_double * _H),
                 ("backtracks", ctypes.c_int32 * _H), ("subdomains", ctypes.c_int32),
                 ("factorizations", ctypes.c_int64), ("local_solves", ctypes.c_int64),
-                ("gmres_total", ctypes.c_int64), ("residual_final", ctypes.c_double),
+                ("gmres_total", ctypes.c_int64), ("newton_iterations", ctypes.c_int64),
+                ("jac_applies", ctypes.c_int64), ("residual_final", ctypes.c_double),
                 ("flops", ctypes.c_double), ("ms_eval", ctypes.c_double),
                 ("ms_gmres", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
@@ -62,8 +63,14 @@ class rsp_history(ctypes.Structure):
                     inner_avg=list(self.inner_avg[:k + 1]), backtracks=list(self.backtracks[:k + 1]),
                     subdomains=self.subdomains, factorizations=self.factorizations,
                     local_solves=self.local_solves, gmres_total=self.gmres_total,
+                    newton_iterations=self.newton_iterations, jac_applies=self.jac_applies,
                     residual_final=self.residual_final, flops=self.flops, ms_eval=self.ms_eval,
                     ms_gmres=self.ms_gmres, ms_total=self.ms_total)
+
+
+class rsp_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every exported entry point, in header order
@@ -91,6 +98,9 @@ SIGNATURES = [
     ("rsp_jac_apply", _I, [_P, _P, _P, _P]),
     ("rsp_solve", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                        ctypes.POINTER(rsp_history), _P]),
+    ("rsp_set_profiling", _I, [_P, _I]),
+    ("rsp_reset_kernel_stats", _I, [_P]),
+    ("rsp_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
 ]
 
 _lib = None
@@ -234,3 +244,22 @@ def rsp_solve(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):
                                  _ptr(f, True), _ptr(y0, True), _ptr(p0, True), _ptr(y), _ptr(p),
                                  _ptr(u), ctypes.byref(h), _stream(stream)))
     return st, h.as_dict()
+
+
+def rsp_set_profiling(ctx, on=True):
+    return _check(load().rsp_set_profiling(ctx, int(on)))
+
+
+def rsp_reset_kernel_stats(ctx):
+    return _check(load().rsp_reset_kernel_stats(ctx))
+
+
+def rsp_kernel_stats(ctx):
+    """Returns {name: dict(launches, ms, flops, bytes)}."""
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.rsp_kernel_stats(ctx, None, 0, ctypes.byref(n)))
+    arr = (rsp_kernel_stat * n.value)()
+    _check(lib.rsp_kernel_stats(ctx, arr, n.value, ctypes.byref(n)))
+    return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
+            for a in arr[:n.value]}
