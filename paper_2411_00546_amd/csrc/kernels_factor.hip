@@ -48,6 +48,15 @@ __device__ __forceinline__ void pivot_step(double& best, int& bi, double& bv) {
   bv = take ? ov : bv;
 }
 
+// Sum over the 16 lanes of a DPP row (every lane gets the sum, same order in all).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
 constexpr int kFacThreads = 256;   // 16 x 16 threads; thread (ti, tj) owns rows ti + 16 rr, cols tj + 16 cc
 
 template <int M>
@@ -67,6 +76,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
   __shared__ int pr[2][M], pinv[2][M];
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
   __shared__ double vin[M], gprev[M];
+  __shared__ int nondom;
 
   const int s = blockIdx.x;
   const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
@@ -86,6 +96,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
 
   for (int j = 0; j < ty; ++j) {
     const int pj = j & 1, pp = pj ^ 1;
+    if (t == 0) nondom = 0;
     // coefficients of line j at z = R_i x + c
     for (int a = t; a < tx; a += kFacThreads) {
       const double y = tilex[halo_idx(P, s, 0, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 0, j, a)] : 0.0);
@@ -121,87 +132,157 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
         A[rr][cc] = d;
       }
     }
-    unsigned used = 0;                 // bit rr: row ti + 16 rr already pivoted
-    // in-place Gauss-Jordan with partial pivoting over the m active columns
+    // Column diagonal dominance |S_kk| >= sum_{i != k} |S_ik| of the active block:
+    // then Gauss-Jordan with partial pivoting keeps every diagonal pivot (the
+    // property is inherited by the Schur complements), so the static-pivot steps
+    // below compute exactly what the pivoted ones would.
+    {
+      bool bad = false;
 #pragma unroll
-    for (int ck = 0; ck < R; ++ck) {
-      for (int kk = 0; kk < 16; ++kk) {
-        const int k = 16 * ck + kk;
-        if (k >= m) break;
-        const int pb = k & 1;
-        // pivot search by the 16 lanes that hold column k (DPP reduction inside the
-        // row), only in the wave that holds them; the winner's value and reciprocal
-        // are published with its row index
-        if ((t >> 6) == (kk >> 2)) {
-          double best = -1.0, bv = 0.0;
-          int bi = 1 << 30;
-          if (tj == kk) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-              const double v = fabs(A[rr][ck]);
-              const bool take = !((used >> rr) & 1u) & (v > best);
-              best = take ? v : best;
-              bi = take ? ti + 16 * rr : bi;
-              bv = take ? A[rr][ck] : bv;
-            }
-          }
-          pivot_step<0xB1>(best, bi, bv);
-          pivot_step<0x4E>(best, bi, bv);
-          pivot_step<0x141>(best, bi, bv);
-          pivot_step<0x140>(best, bi, bv);
-          if (tj == kk) {
-            if (ti == 0) {
-              const bool ok = bi < M;                     // a NaN column has no candidate
-              const double pv = ok ? bv : __builtin_nan("");
-              pivb[pb] = ok ? bi : k;
-              pivv[pb][0] = pv;
-              pivv[pb][1] = 1.0 / pv;
-            }
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
-          }
-        }
-        __syncthreads();
-        const int r = __builtin_amdgcn_readfirstlane(pivb[pb]);
-        const int rq = r >> 4, rl = r & 15;
-        const double piv = pivv[pb][0];
-        const double ipiv = pivv[pb][1];
-        // pivot row: held by lane (rl) of this 16-lane group, register row rq (wave-uniform)
-        double rs[R], mult[R], src[R];
-        // rq is wave-uniform: one scalar branch picks the register row (the empty asm
-        // keeps the compiler from turning the cases into per-element selects)
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (q == rq) {
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int cc = 0; cc < R; ++cc) src[cc] = A[q][cc];
-          }
-#pragma unroll
-        for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(src[cc], (lane & 48) | rl, 64) * ipiv;
-        // multipliers; the pivot row takes piv - 1 so that the update below turns it
-        // into row / piv
+      for (int cc = 0; cc < R; ++cc) {
+        const int b = tj + 16 * cc;
+        double off = 0.0, dia = 0.0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
-          const double cv = colb[pb][ti + 16 * rr];
-          mult[rr] = (ti + 16 * rr == r) ? piv - 1.0 : cv;
+          const double v = fabs(A[rr][cc]);
+          const bool d = (ti + 16 * rr) == b;
+          dia += d ? v : 0.0;
+          off += d ? 0.0 : v;
         }
+        off = row_sum16(off);
+        dia = row_sum16(dia);
+        bad |= (b < m) & !(dia >= off);
+      }
+      if (bad) nondom = 1;
+    }
+    __syncthreads();
+    if (!nondom) {
+      // static pivots: step k eliminates with row k
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr)
+      for (int ck = 0; ck < R; ++ck) {
+        for (int kk = 0; kk < 16; ++kk) {
+          const int k = 16 * ck + kk;
+          if (k >= m) break;
+          const int pb = k & 1;
+          if (tj == kk) {
 #pragma unroll
-          for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
-        // column k becomes -column k / piv, and (r, k) = 1 / piv
-        if (tj == kk) {
+            for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
+            if (ti == kk) {
+              pivv[pb][0] = A[ck][ck];
+              pivv[pb][1] = 1.0 / A[ck][ck];
+            }
+          }
+          __syncthreads();
+          const double piv = pivv[pb][0];
+          const double ipiv = pivv[pb][1];
+          double rs[R], mult[R];
+#pragma unroll
+          for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(A[ck][cc], (lane & 48) | kk, 64) * ipiv;
 #pragma unroll
           for (int rr = 0; rr < R; ++rr) {
             const double cv = colb[pb][ti + 16 * rr];
-            A[rr][ck] = (ti + 16 * rr == r) ? ipiv : -cv * ipiv;
+            mult[rr] = (rr == ck && ti == kk) ? piv - 1.0 : cv;
+          }
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
+          if (tj == kk) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              const double cv = colb[pb][ti + 16 * rr];
+              A[rr][ck] = (rr == ck && ti == kk) ? ipiv : -cv * ipiv;
+            }
           }
         }
-        if (ti == rl) used |= 1u << rq;
-        if (t == 0) {
-          pr[pj][k] = r;
-          pinv[pj][r] = k;
+      }
+      for (int k = t; k < m; k += kFacThreads) {
+        pr[pj][k] = k;
+        pinv[pj][k] = k;
+      }
+    } else {
+      unsigned used = 0;                 // bit rr: row ti + 16 rr already pivoted
+      // in-place Gauss-Jordan with partial pivoting over the m active columns
+  #pragma unroll
+      for (int ck = 0; ck < R; ++ck) {
+        for (int kk = 0; kk < 16; ++kk) {
+          const int k = 16 * ck + kk;
+          if (k >= m) break;
+          const int pb = k & 1;
+          // pivot search by the 16 lanes that hold column k (DPP reduction inside the
+          // row), only in the wave that holds them; the winner's value and reciprocal
+          // are published with its row index
+          if ((t >> 6) == (kk >> 2)) {
+            double best = -1.0, bv = 0.0;
+            int bi = 1 << 30;
+            if (tj == kk) {
+  #pragma unroll
+              for (int rr = 0; rr < R; ++rr) {
+                const double v = fabs(A[rr][ck]);
+                const bool take = !((used >> rr) & 1u) & (v > best);
+                best = take ? v : best;
+                bi = take ? ti + 16 * rr : bi;
+                bv = take ? A[rr][ck] : bv;
+              }
+            }
+            pivot_step<0xB1>(best, bi, bv);
+            pivot_step<0x4E>(best, bi, bv);
+            pivot_step<0x141>(best, bi, bv);
+            pivot_step<0x140>(best, bi, bv);
+            if (tj == kk) {
+              if (ti == 0) {
+                const bool ok = bi < M;                     // a NaN column has no candidate
+                const double pv = ok ? bv : __builtin_nan("");
+                pivb[pb] = ok ? bi : k;
+                pivv[pb][0] = pv;
+                pivv[pb][1] = 1.0 / pv;
+              }
+  #pragma unroll
+              for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
+            }
+          }
+          __syncthreads();
+          const int r = __builtin_amdgcn_readfirstlane(pivb[pb]);
+          const int rq = r >> 4, rl = r & 15;
+          const double piv = pivv[pb][0];
+          const double ipiv = pivv[pb][1];
+          // pivot row: held by lane (rl) of this 16-lane group, register row rq (wave-uniform)
+          double rs[R], mult[R], src[R];
+          // rq is wave-uniform: one scalar branch picks the register row (the empty asm
+          // keeps the compiler from turning the cases into per-element selects)
+  #pragma unroll
+          for (int q = 0; q < R; ++q)
+            if (q == rq) {
+              asm volatile("" ::: "memory");
+  #pragma unroll
+              for (int cc = 0; cc < R; ++cc) src[cc] = A[q][cc];
+            }
+  #pragma unroll
+          for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(src[cc], (lane & 48) | rl, 64) * ipiv;
+          // multipliers; the pivot row takes piv - 1 so that the update below turns it
+          // into row / piv
+  #pragma unroll
+          for (int rr = 0; rr < R; ++rr) {
+            const double cv = colb[pb][ti + 16 * rr];
+            mult[rr] = (ti + 16 * rr == r) ? piv - 1.0 : cv;
+          }
+  #pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+  #pragma unroll
+            for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
+          // column k becomes -column k / piv, and (r, k) = 1 / piv
+          if (tj == kk) {
+  #pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              const double cv = colb[pb][ti + 16 * rr];
+              A[rr][ck] = (ti + 16 * rr == r) ? ipiv : -cv * ipiv;
+            }
+          }
+          if (ti == rl) used |= 1u << rq;
+          if (t == 0) {
+            pr[pj][k] = r;
+            pinv[pj][r] = k;
+          }
         }
       }
     }

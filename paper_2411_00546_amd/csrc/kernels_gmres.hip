@@ -25,10 +25,11 @@ __device__ __forceinline__ void chunk_of(size_t L, size_t& lo, size_t& hi) {
 
 // Block sums of acc[i] for i < nv (wave shuffles, then the 4 wave results in order);
 // thread i < nv of the block returns sum i.  Fixed order: deterministic.
-__device__ __forceinline__ double block_sums(const double (&acc)[kGmMaxVec], int nv, double* red) {
+template <int NB>
+__device__ __forceinline__ double block_sums(const double (&acc)[NB], int nv, double* red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < kGmMaxVec; ++i) {
+  for (int i = 0; i < NB; ++i) {
     if (i < nv) {
       double v = acc[i];
 #pragma unroll
@@ -67,7 +68,12 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
   __syncthreads();
 }
 
-// partial sums of V_i . w for i <= j over this block's chunk
+// NB: compile-time bound on the number of basis vectors (bucket >= nv).  Loads of all
+// NB vectors are issued unconditionally (index clamped to nv - 1, the extra ones hit
+// the cache) and the unused products are masked, so the loads are not serialised.
+
+// partial sums of V_i . w for i < nv over this block's chunk
+template <int NB>
 __global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, size_t L, int nv,
                                                 const double* __restrict__ w,
                                                 const GmState* __restrict__ st,
@@ -76,22 +82,25 @@ __global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, si
   if (st->done) return;
   size_t lo, hi;
   chunk_of(L, lo, hi);
-  double acc[kGmMaxVec];
+  double acc[NB];
 #pragma unroll
-  for (int i = 0; i < kGmMaxVec; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
     const double we = w[e];
 #pragma unroll
-    for (int i = 0; i < kGmMaxVec; ++i)
-      if (i < nv) acc[i] = fma(V[(size_t)i * L + e], we, acc[i]);
+    for (int i = 0; i < NB; ++i) {
+      const double v = V[(size_t)min(i, nv - 1) * L + e];
+      acc[i] = fma(v, i < nv ? we : 0.0, acc[i]);
+    }
   }
-  const double r = block_sums(acc, nv, red);
+  const double r = block_sums<NB>(acc, nv, red);
   if ((int)threadIdx.x < nv) partial[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
 }
 
 // h = sum of the previous partials; w -= V h; then either the partial dots of the new
 // w with V (next = 0) or its partial squared norm (next = 1).  Block 0 adds h into
 // the Hessenberg column j.
+template <int NB>
 __global__ __launch_bounds__(kT) void k_gm_update(const double* __restrict__ V, size_t L, int nv,
                                                   double* __restrict__ w, GmState* __restrict__ st,
                                                   const double* __restrict__ pin, int first,
@@ -105,27 +114,31 @@ __global__ __launch_bounds__(kT) void k_gm_update(const double* __restrict__ V, 
     double* Hc = st->H + threadIdx.x * m + j;
     *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
   }
+  double h[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) h[i] = i < nv ? hs[i] : 0.0;
   size_t lo, hi;
   chunk_of(L, lo, hi);
-  const int nout = next == 0 ? nv : 1;
-  double acc[kGmMaxVec];
+  double acc[NB];
 #pragma unroll
-  for (int i = 0; i < kGmMaxVec; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
+    double v[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * L + e];
     double we = w[e];
 #pragma unroll
-    for (int i = 0; i < kGmMaxVec; ++i)
-      if (i < nv) we = fma(-hs[i], V[(size_t)i * L + e], we);
+    for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
     w[e] = we;
     if (next == 0) {
 #pragma unroll
-      for (int i = 0; i < kGmMaxVec; ++i)
-        if (i < nv) acc[i] = fma(V[(size_t)i * L + e], we, acc[i]);
+      for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
     } else {
       acc[0] = fma(we, we, acc[0]);
     }
   }
-  const double r = block_sums(acc, nout, red);
+  const int nout = next == 0 ? nv : 1;
+  const double r = block_sums<NB>(acc, nout, red);
   if ((int)threadIdx.x < nout) pout[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
 }
 
@@ -145,25 +158,37 @@ __global__ __launch_bounds__(kT) void k_gm_normalize(double* __restrict__ Vn, si
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) Vn[e] = w[e] * inv;
 }
 
-// Givens rotations on Hessenberg column j, residual estimate and stopping test.
-__global__ void k_gm_givens(GmState* __restrict__ st, int j) {
-  if (threadIdx.x != 0 || st->done) return;
+// Givens rotations on Hessenberg column j, residual estimate and stopping test.  The
+// column and the rotations are staged in LDS so the sequential part runs from LDS.
+__global__ __launch_bounds__(kT) void k_gm_givens(GmState* __restrict__ st, int j) {
+  __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
+  if (st->done) return;
   const int m = st->m;
-  double* H = st->H;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[i * m + j], b = H[(i + 1) * m + j];
-    H[i * m + j] = st->cs[i] * a + st->sn[i] * b;
-    H[(i + 1) * m + j] = -st->sn[i] * a + st->cs[i] * b;
+  const int t = threadIdx.x;
+  if (t <= j + 1) col[t] = st->H[t * m + j];
+  if (t < j) {
+    cs[t] = st->cs[t];
+    sn[t] = st->sn[t];
   }
-  const double a = H[j * m + j], b = H[(j + 1) * m + j];
+  __syncthreads();
+  if (t != 0) return;
+  for (int i = 0; i < j; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[j], b = col[j + 1];
   const double den = hypot(a, b);
-  st->cs[j] = a / den;
-  st->sn[j] = b / den;
-  H[j * m + j] = den;
+  const double c = a / den, s = b / den;
+  st->cs[j] = c;
+  st->sn[j] = s;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  for (int i = 0; i <= j + 1; ++i) st->H[i * m + j] = col[i];
   const bool breakdown = !(b > 0.0);
-  H[(j + 1) * m + j] = 0.0;
-  st->g[j + 1] = -st->sn[j] * st->g[j];
-  st->g[j] = st->cs[j] * st->g[j];
+  const double gj = st->g[j];
+  st->g[j + 1] = -s * gj;
+  st->g[j] = c * gj;
   st->rel = fabs(st->g[j + 1]) / st->bnorm;
   st->steps = j + 1;
   st->used += 1;
@@ -261,14 +286,24 @@ void launch_gm_start(double* V0, size_t L, const double* r, GmState* st, const d
                      int first_cycle, hipStream_t s) {
   k_gm_start<<<kGmBlocks, kT, 0, s>>>(V0, L, r, st, partial, first_cycle);
 }
+template <int NB>
+void arnoldi_nb(const double* V, size_t L, int j, double* w, GmState* st, double* p1, double* p2,
+                hipStream_t s) {
+  const int nv = j + 1;
+  k_gm_dots<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1);
+  k_gm_update<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1, 1, 0, p2, j);
+  k_gm_update<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p2, 0, 1, p1, j);
+  k_gm_normalize<<<kGmBlocks, kT, 0, s>>>(const_cast<double*>(V) + (size_t)(j + 1) * L, L, w, st, p1, j);
+  k_gm_givens<<<1, kT, 0, s>>>(st, j);
+}
+
 void launch_gm_arnoldi(const double* V, size_t L, int j, double* w, GmState* st, double* p1,
                        double* p2, hipStream_t s) {
   const int nv = j + 1;
-  k_gm_dots<<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1);
-  k_gm_update<<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1, 1, 0, p2, j);
-  k_gm_update<<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p2, 0, 1, p1, j);
-  k_gm_normalize<<<kGmBlocks, kT, 0, s>>>(const_cast<double*>(V) + (size_t)(j + 1) * L, L, w, st, p1, j);
-  k_gm_givens<<<1, 64, 0, s>>>(st, j);
+  if (nv <= 8) arnoldi_nb<8>(V, L, j, w, st, p1, p2, s);
+  else if (nv <= 16) arnoldi_nb<16>(V, L, j, w, st, p1, p2, s);
+  else if (nv <= 32) arnoldi_nb<32>(V, L, j, w, st, p1, p2, s);
+  else arnoldi_nb<64>(V, L, j, w, st, p1, p2, s);
 }
 void launch_gm_update_x(const double* V, size_t L, GmState* st, double* x, hipStream_t s) {
   k_gm_update_x<<<kGmBlocks, kT, 0, s>>>(V, L, st, x);
