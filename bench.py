@@ -24,7 +24,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (and FP64 matrix) peak
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (and FP32 matrix) peak
 BOUND = {"factor": ("alu", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm", HBM_PEAK_GBS, "GB/s"),
+         "newton_refine": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "solve_bwd": ("hbm", HBM_PEAK_GBS, "GB/s"), "gmres_ortho": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "linesearch": ("hbm", HBM_PEAK_GBS, "GB/s"), "prolong": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "ring_rhs": ("hbm", HBM_PEAK_GBS, "GB/s"), "restrict_halo": ("hbm", HBM_PEAK_GBS, "GB/s"),
@@ -33,10 +35,10 @@ KERNEL_SOURCES = {"factor": "kernels_factor.hip", "block_solve": "kernels_factor
                   "solve_bwd": "kernels_factor.hip"}
 
 
-def workload(name):
+def workload(name, precision="fp64", max_refine=0):
     import synth
     prob = synth.config_by_name(name)
-    opts = synth.Options()
+    opts = synth.Options(precision=1 if precision == "mixed" else 0, max_refine=max_refine)
     return prob, opts
 
 
@@ -46,7 +48,9 @@ def describe(prob, opts):
             "grid": [prob.nx, prob.ny], "phi": ["0", "y^3", "exp(y)-1", "kappa(y^3+exp(kappa y))"][prob.phi],
             "nu": prob.nu, "mu": prob.mu, "eps": [prob.eps0, prob.eps_min], "gamma": prob.gamma,
             "subdomains": [prob.sx, prob.sy], "overlap": prob.overlap, "gmres": [opts.gmres_restart, opts.gmres_rtol],
-            "tol_outer": opts.tol_outer, "tol_inner": opts.tol_inner, "precision": "fp64",
+            "tol_outer": opts.tol_outer, "tol_inner": opts.tol_inner,
+            "precision": ("fp32 line factors, fp64 residuals / Newton / GMRES, %d extra refinement step(s) "
+                          "per local solve" % opts.max_refine) if opts.precision == 1 else "fp64",
             "seed": prob.seed, "unknowns": 2 * prob.nx * prob.ny}
 
 
@@ -135,6 +139,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
+                    help="mixed: FP32 line factors + FP64 refinement (the FP64 path is timed beside it)")
+    ap.add_argument("--max-refine", type=int, default=0,
+                    help="FP64 refinement steps per FP32 local solve (the local Newton iteration "
+                         "refines against its FP64 residual in any case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0 "
@@ -150,13 +159,14 @@ def main():
     import torch
     from paper_2411_00546_amd import raspen as R
     R.load()
-    prob, opts = workload(args.workload)
+    prob, opts = workload(args.workload, args.precision, args.max_refine)
+    _, opts64 = workload(args.workload, "fp64")
     yd, f = prob.inputs()
     dev = torch.device("cuda:0")
     ydt = torch.as_tensor(yd, dtype=torch.float64, device=dev).contiguous()
     ft = torch.as_tensor(f, dtype=torch.float64, device=dev).contiguous()
     y, p, u = (torch.empty_like(ydt) for _ in range(3))
-    P, O = R.make_problem(prob), R.make_options(opts)
+    P, O, O64 = R.make_problem(prob), R.make_options(opts), R.make_options(opts64)
     ctx = R.rsp_context_create(0)
     if args.phases:
         try:
@@ -177,24 +187,41 @@ def main():
         finally:
             R.rsp_context_destroy(ctx)
         return
-    try:
-        for _ in range(args.warmup):
-            R.rsp_solve(ctx, P, O, ydt, ft, None, None, y, p, u)
-        R.rsp_set_profiling(ctx, True)
-        R.rsp_reset_kernel_stats(ctx)
+
+    def solves(opt, steps, warmup, profile):
+        for _ in range(warmup):
+            R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+        if profile:
+            R.rsp_set_profiling(ctx, True)
+            R.rsp_reset_kernel_stats(ctx)
         torch.cuda.synchronize()
-        lat = []
-        hist = None
+        lat, hist = [], None
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             ts = time.perf_counter()
-            st, hist = R.rsp_solve(ctx, P, O, ydt, ft, None, None, y, p, u)
+            st, hist = R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
             lat.append(time.perf_counter() - ts)
             if st != 0:
                 raise RuntimeError("solve ended with status %d" % st)
         torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        stats = R.rsp_kernel_stats(ctx)
+        el = time.perf_counter() - t0
+        stats = R.rsp_kernel_stats(ctx) if profile else None
+        R.rsp_set_profiling(ctx, False)
+        x = torch.cat([y.reshape(-1), p.reshape(-1)]).cpu().numpy()
+        return el, lat, hist, stats, x
+
+    try:
+        elapsed, lat, hist, stats, x = solves(O, args.steps, args.warmup, True)
+        cmp64 = None
+        if opts.precision == 1:
+            el64, lat64, hist64, _, x64 = solves(O64, args.steps, 1, False)
+            err = float(np.abs(x - x64).max() / np.abs(x64).max())
+            cmp64 = {"value": args.steps / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / args.steps,
+                     "latency_ms": {"p50": float(np.percentile(np.array(lat64) * 1e3, 50)),
+                                    "p99": float(np.percentile(np.array(lat64) * 1e3, 99))},
+                     "rel_err_mixed_vs_fp64": err, "outer": hist64["outer"]}
+            if not err <= 1e-8:
+                raise RuntimeError("mixed-precision solution differs from FP64 by %.3e > 1e-8" % err)
     finally:
         R.rsp_context_destroy(ctx)
 
@@ -204,6 +231,8 @@ def main():
     dom = max(single, key=lambda k: single[k]["ms"])
     d = kern[dom]
     bound, peak, unit = BOUND[dom]
+    if dom == "factor" and opts.precision == 1:
+        peak = FP32_PEAK_TFLOPS
     avg_s = d["ms"] / d["launches"] / 1e3
     if bound == "hbm":
         achieved = d["bytes"] / d["launches"] / avg_s / 1e9
@@ -224,13 +253,14 @@ def main():
     out = {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",
            "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded Gaussian-bump y_d)",
+           "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
+           "data": "synthetic (seeded Gaussian-bump y_d)",
            "config": describe(prob, opts),
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
                      "residual_final": hist["residual_final"], "norm": hist["norm"][-1]},
-           "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+           "fp64": cmp64, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
     print(json.dumps(out))
 
 

@@ -35,13 +35,17 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = dpp_i<CTRL>(__double2hiint(v));
   return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_d(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
 // Keep the larger |value|, ties to the smaller row index (a total order, so every
 // lane of the row ends with the same winner).
-template <int CTRL>
-__device__ __forceinline__ void pivot_step(double& best, int& bi, double& bv) {
-  const double ob = dpp_d<CTRL>(best);
+template <int CTRL, typename T>
+__device__ __forceinline__ void pivot_step(T& best, int& bi, T& bv) {
+  const T ob = dpp_d<CTRL>(best);
   const int oi = dpp_i<CTRL>(bi);
-  const double ov = dpp_d<CTRL>(bv);
+  const T ov = dpp_d<CTRL>(bv);
   const bool take = (ob > best) | ((ob == best) & (oi < bi));
   best = take ? ob : best;
   bi = take ? oi : bi;
@@ -49,7 +53,8 @@ __device__ __forceinline__ void pivot_step(double& best, int& bi, double& bv) {
 }
 
 // Sum over the 16 lanes of a DPP row (every lane gets the sum, same order in all).
-__device__ __forceinline__ double row_sum16(double v) {
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
   v += dpp_d<0x141>(v);
@@ -59,20 +64,23 @@ __device__ __forceinline__ double row_sum16(double v) {
 
 constexpr int kFacThreads = 256;   // 16 x 16 threads; thread (ti, tj) owns rows ti + 16 rr, cols tj + 16 cc
 
-template <int M>
+// T: arithmetic and storage type of the line inverses (double, or float for the
+// FP32 factors of the mixed-precision form); coefficients and the fused forward
+// sweep stay in double.
+template <typename T, int M>
 __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4* __restrict__ box,
                                                         const double* __restrict__ tilex,
                                                         const double* __restrict__ c,
                                                         const SubState* __restrict__ state,
                                                         double eps_fixed, const double* __restrict__ rhs,
-                                                        double rhs_scale, double* __restrict__ facT,
+                                                        double rhs_scale, T* __restrict__ facT,
                                                         double* __restrict__ gout) {
   constexpr int R = M / 16;          // rows (and columns) of the line block per thread
   constexpr int LD = M + 1;
-  __shared__ double Mx[M * LD];      // finished in-place Gauss-Jordan result of the line
-  __shared__ double colb[2][M];      // pivot column of the current step (double buffered)
+  __shared__ T Mx[M * LD];      // finished in-place Gauss-Jordan result of the line
+  __shared__ T colb[2][M];      // pivot column of the current step (double buffered)
   __shared__ int pivb[2];
-  __shared__ double pivv[2][2];      // pivot value and its reciprocal
+  __shared__ T pivv[2][2];      // pivot value and its reciprocal
   __shared__ int pr[2][M], pinv[2][M];
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
   __shared__ double vin[M], gprev[M];
@@ -90,7 +98,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const int m = 2 * tx;
   const double hy4i = P.hy2i * P.hy2i;
-  double A[R][R];
+  T A[R][R];
 
   for (int i = t; i < M; i += kFacThreads) gprev[i] = 0.0;
 
@@ -127,9 +135,9 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
           } else if (ar == ac) {
             d = fr == 0 ? lb[ar] : lc[ar];
           }
-          if (j > 0) d -= hy4i * Mx[pr[pp][a] * LD + pinv[pp][b]];
+          if (j > 0) d -= hy4i * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
         }
-        A[rr][cc] = d;
+        A[rr][cc] = (T)d;
       }
     }
     // Column diagonal dominance |S_kk| >= sum_{i != k} |S_ik| of the active block:
@@ -141,13 +149,13 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
 #pragma unroll
       for (int cc = 0; cc < R; ++cc) {
         const int b = tj + 16 * cc;
-        double off = 0.0, dia = 0.0;
+        T off = 0, dia = 0;
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
-          const double v = fabs(A[rr][cc]);
+          const T v = fabs(A[rr][cc]);
           const bool d = (ti + 16 * rr) == b;
-          dia += d ? v : 0.0;
-          off += d ? 0.0 : v;
+          dia += d ? v : (T)0;
+          off += d ? (T)0 : v;
         }
         off = row_sum16(off);
         dia = row_sum16(dia);
@@ -169,28 +177,30 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
             for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
             if (ti == kk) {
               pivv[pb][0] = A[ck][ck];
-              pivv[pb][1] = 1.0 / A[ck][ck];
+              pivv[pb][1] = (T)1 / A[ck][ck];
             }
           }
           __syncthreads();
-          const double piv = pivv[pb][0];
-          const double ipiv = pivv[pb][1];
-          double rs[R], mult[R];
+          const T ipiv = pivv[pb][1];
+          T rs[R], mult[R];
 #pragma unroll
           for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(A[ck][cc], (lane & 48) | kk, 64) * ipiv;
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr) {
-            const double cv = colb[pb][ti + 16 * rr];
-            mult[rr] = (rr == ck && ti == kk) ? piv - 1.0 : cv;
-          }
+          for (int rr = 0; rr < R; ++rr) mult[rr] = colb[pb][ti + 16 * rr];
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
+          // the pivot row becomes row / piv (assigned, not updated: the update would
+          // cancel catastrophically for |piv| >> 1)
+          if (ti == kk) {
+#pragma unroll
+            for (int cc = 0; cc < R; ++cc) A[ck][cc] = rs[cc];
+          }
           if (tj == kk) {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
-              const double cv = colb[pb][ti + 16 * rr];
+              const T cv = colb[pb][ti + 16 * rr];
               A[rr][ck] = (rr == ck && ti == kk) ? ipiv : -cv * ipiv;
             }
           }
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
     } else {
       unsigned used = 0;                 // bit rr: row ti + 16 rr already pivoted
       // in-place Gauss-Jordan with partial pivoting over the m active columns
-  #pragma unroll
+#pragma unroll
       for (int ck = 0; ck < R; ++ck) {
         for (int kk = 0; kk < 16; ++kk) {
           const int k = 16 * ck + kk;
@@ -213,12 +223,12 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
           // row), only in the wave that holds them; the winner's value and reciprocal
           // are published with its row index
           if ((t >> 6) == (kk >> 2)) {
-            double best = -1.0, bv = 0.0;
+            T best = -1, bv = 0;
             int bi = 1 << 30;
             if (tj == kk) {
-  #pragma unroll
+#pragma unroll
               for (int rr = 0; rr < R; ++rr) {
-                const double v = fabs(A[rr][ck]);
+                const T v = fabs(A[rr][ck]);
                 const bool take = !((used >> rr) & 1u) & (v > best);
                 best = take ? v : best;
                 bi = take ? ti + 16 * rr : bi;
@@ -232,49 +242,53 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
             if (tj == kk) {
               if (ti == 0) {
                 const bool ok = bi < M;                     // a NaN column has no candidate
-                const double pv = ok ? bv : __builtin_nan("");
+                const T pv = ok ? bv : (T)__builtin_nan("");
                 pivb[pb] = ok ? bi : k;
                 pivv[pb][0] = pv;
-                pivv[pb][1] = 1.0 / pv;
+                pivv[pb][1] = (T)1 / pv;
               }
-  #pragma unroll
+#pragma unroll
               for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
             }
           }
           __syncthreads();
           const int r = __builtin_amdgcn_readfirstlane(pivb[pb]);
           const int rq = r >> 4, rl = r & 15;
-          const double piv = pivv[pb][0];
-          const double ipiv = pivv[pb][1];
+          const T ipiv = pivv[pb][1];
           // pivot row: held by lane (rl) of this 16-lane group, register row rq (wave-uniform)
-          double rs[R], mult[R], src[R];
+          T rs[R], mult[R], src[R];
           // rq is wave-uniform: one scalar branch picks the register row (the empty asm
           // keeps the compiler from turning the cases into per-element selects)
-  #pragma unroll
+#pragma unroll
           for (int q = 0; q < R; ++q)
             if (q == rq) {
               asm volatile("" ::: "memory");
-  #pragma unroll
+#pragma unroll
               for (int cc = 0; cc < R; ++cc) src[cc] = A[q][cc];
             }
-  #pragma unroll
+#pragma unroll
           for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(src[cc], (lane & 48) | rl, 64) * ipiv;
-          // multipliers; the pivot row takes piv - 1 so that the update below turns it
-          // into row / piv
-  #pragma unroll
-          for (int rr = 0; rr < R; ++rr) {
-            const double cv = colb[pb][ti + 16 * rr];
-            mult[rr] = (ti + 16 * rr == r) ? piv - 1.0 : cv;
-          }
-  #pragma unroll
+          // rank-1 update, then the pivot row is assigned row / piv (see the static steps)
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) mult[rr] = colb[pb][ti + 16 * rr];
+#pragma unroll
           for (int rr = 0; rr < R; ++rr)
-  #pragma unroll
+#pragma unroll
             for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
+          if (ti == rl) {
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+              if (q == rq) {
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int cc = 0; cc < R; ++cc) A[q][cc] = rs[cc];
+              }
+          }
           // column k becomes -column k / piv, and (r, k) = 1 / piv
           if (tj == kk) {
-  #pragma unroll
+#pragma unroll
             for (int rr = 0; rr < R; ++rr) {
-              const double cv = colb[pb][ti + 16 * rr];
+              const T cv = colb[pb][ti + 16 * rr];
               A[rr][ck] = (ti + 16 * rr == r) ? ipiv : -cv * ipiv;
             }
           }
@@ -309,15 +323,15 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
       }
       __syncthreads();
       if (t < M) {
-        const double* row = Mx + pr[pj][t] * LD;
+        const T* row = Mx + pr[pj][t] * LD;
         double acc = 0.0;
-        for (int k = 0; k < M; ++k) acc += row[k] * vin[pr[pj][k]];
+        for (int k = 0; k < M; ++k) acc += (double)row[k] * vin[pr[pj][k]];
         gprev[t] = acc;
         gout[((size_t)s * P.tym + j) * M + t] = acc;
       }
     }
     // store S_j^{-1} transposed: facT[b][a] = Mx[pr[a]][pinv[b]]
-    double* F = facT + ((size_t)s * P.tym + j) * M * M;
+    T* F = facT + ((size_t)s * P.tym + j) * M * M;
 #pragma unroll
     for (int cc = 0; cc < R; ++cc) {
       const int b = tj + 16 * cc;
@@ -347,11 +361,20 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
 
 void launch_factor(const DevProblem& P, const int4* box, const double* tilex, const double* c,
                    const SubState* state, double eps_fixed, const double* rhs, double rhs_scale,
-                   double* facT, double* g, hipStream_t st) {
-#define RSP_CALL(MM) \
-  k_factor<MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
+                   void* facT, int fp32, double* g, hipStream_t st) {
+  if (fp32) {
+#define RSP_CALL(MM)                                                                                  \
+  k_factor<float, MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                   (float*)facT, g)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
 #undef RSP_CALL
+  } else {
+#define RSP_CALL(MM)                                                                                   \
+  k_factor<double, MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                    (double*)facT, g)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  }
 }
 
 }  // namespace rsp

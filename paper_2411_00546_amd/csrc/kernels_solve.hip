@@ -7,68 +7,91 @@
 //
 // Each line is an M x M matrix-vector product that only depends on the previous
 // line through the (small) vector, so the matrices are streamed from HBM with
-// loads issued two lines ahead of the product that consumes them.  4M threads:
-// thread (a2, bg) owns output columns 2a2, 2a2+1 and rows bg*M/8 .. of the line
-// matrix (double2 loads, coalesced along a), partial sums are combined in LDS in
-// a fixed order.
+// loads issued two lines ahead of the product that consumes them.  4M threads;
+// 16-byte loads of W factor entries (double2 or float4), coalesced along the
+// output index; partial sums are combined in LDS in a fixed order.  Vectors and
+// accumulation are FP64 for both factor types.
+//
+// Mixed precision (FP32 factors): a local solve is refined in FP64,
+//   z <- F^{-1} b;  repeat: r = b - J_i z (J_i applied matrix-free on the tile in
+//   FP64, zero outside the tile), z <- z + F^{-1} r.
 #include "rsp_kernels.h"
 
 namespace rsp {
 
 namespace {
 
-template <int M>
-struct Sweep {
-  static constexpr int NT = 4 * M;   // threads
-  static constexpr int P2 = M / 2;   // column pairs
-  static constexpr int K = M / 8;    // rows per thread per line
+template <typename TF>
+struct Vec;
+template <>
+struct Vec<double> {
+  using type = double2;
+  static constexpr int W = 2;
+};
+template <>
+struct Vec<float> {
+  using type = float4;
+  static constexpr int W = 4;
 };
 
-template <int M>
-__device__ __forceinline__ void load_line(const double* __restrict__ F, int a2, int bg,
-                                          double2 (&buf)[Sweep<M>::K]) {
-  constexpr int K = Sweep<M>::K;
-  const double2* p = reinterpret_cast<const double2*>(F) + (size_t)(bg * K) * (M / 2) + a2;
+template <typename TF, int M>
+struct Sweep {
+  using VT = typename Vec<TF>::type;
+  static constexpr int W = Vec<TF>::W;
+  static constexpr int NT = 4 * M;   // threads
+  static constexpr int NC = M / W;   // column groups (one 16-byte load each)
+  static constexpr int G = NT / NC;  // row groups
+  static constexpr int K = M / G;    // rows per thread per line
+};
+
+template <typename TF, int M>
+__device__ __forceinline__ void load_line(const TF* __restrict__ F, int ac, int bg,
+                                          typename Sweep<TF, M>::VT (&buf)[Sweep<TF, M>::K]) {
+  using S = Sweep<TF, M>;
+  const typename S::VT* p = reinterpret_cast<const typename S::VT*>(F) + (size_t)(bg * S::K) * S::NC + ac;
 #pragma unroll
-  for (int i = 0; i < K; ++i) buf[i] = p[(size_t)i * (M / 2)];
+  for (int i = 0; i < S::K; ++i) buf[i] = p[(size_t)i * S::NC];
 }
 
 // y = F v for one line: partial sums of this thread's rows, then a fixed-order
-// reduction over the 8 row groups by threads t < M.  Returns y[t] (t < M).
-template <int M>
-__device__ __forceinline__ double line_product(const double2 (&buf)[Sweep<M>::K], const double* v,
-                                               int a2, int bg, double* red) {
-  constexpr int K = Sweep<M>::K;
-  double s0 = 0.0, s1 = 0.0;
+// reduction over the row groups by threads t < M.  Returns y[t] (t < M).
+template <typename TF, int M>
+__device__ __forceinline__ double line_product(const typename Sweep<TF, M>::VT (&buf)[Sweep<TF, M>::K],
+                                               const double* v, int ac, int bg, double* red) {
+  using S = Sweep<TF, M>;
+  double sum[S::W];
 #pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const double vb = v[bg * K + i];
-    s0 = fma(buf[i].x, vb, s0);
-    s1 = fma(buf[i].y, vb, s1);
+  for (int w = 0; w < S::W; ++w) sum[w] = 0.0;
+#pragma unroll
+  for (int i = 0; i < S::K; ++i) {
+    const double vb = v[bg * S::K + i];
+    const TF* e = reinterpret_cast<const TF*>(&buf[i]);
+#pragma unroll
+    for (int w = 0; w < S::W; ++w) sum[w] = fma((double)e[w], vb, sum[w]);
   }
-  red[bg * M + 2 * a2] = s0;
-  red[bg * M + 2 * a2 + 1] = s1;
+#pragma unroll
+  for (int w = 0; w < S::W; ++w) red[bg * M + S::W * ac + w] = sum[w];
   __syncthreads();
   double y = 0.0;
   const int t = threadIdx.x;
   if (t < M) {
 #pragma unroll
-    for (int g = 0; g < 8; ++g) y += red[g * M + t];
+    for (int g = 0; g < S::G; ++g) y += red[g * M + t];
   }
   return y;
 }
 
 // Forward sweep in place on gl[ty][M] (rhs -> g).
-template <int M>
-__device__ void forward_sweep(const double* __restrict__ Fs, int ty, double c, double* gl,
-                              double* red) {
-  const int t = threadIdx.x, a2 = t % (M / 2), bg = t / (M / 2);
+template <typename TF, int M>
+__device__ void forward_sweep(const TF* __restrict__ Fs, int ty, double c, double* gl, double* red) {
+  using S = Sweep<TF, M>;
+  const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
   const size_t MM = (size_t)M * M;
-  double2 b0[Sweep<M>::K], b1[Sweep<M>::K], b2[Sweep<M>::K];
-  load_line<M>(Fs, a2, bg, b0);
-  load_line<M>(Fs + MM * min(1, ty - 1), a2, bg, b1);
-  auto step = [&](const double2(&buf)[Sweep<M>::K], int j) {
-    const double y = line_product<M>(buf, gl + (size_t)j * M, a2, bg, red);
+  typename S::VT b0[S::K], b1[S::K], b2[S::K];
+  load_line<TF, M>(Fs, ac, bg, b0);
+  load_line<TF, M>(Fs + MM * min(1, ty - 1), ac, bg, b1);
+  auto step = [&](const typename S::VT(&buf)[S::K], int j) {
+    const double y = line_product<TF, M>(buf, gl + (size_t)j * M, ac, bg, red);
     if (t < M) {
       gl[(size_t)j * M + t] = y;
       if (j + 1 < ty) gl[(size_t)(j + 1) * M + t] += c * y;
@@ -76,55 +99,56 @@ __device__ void forward_sweep(const double* __restrict__ Fs, int ty, double c, d
     __syncthreads();
   };
   for (int j = 0; j < ty; j += 3) {
-    load_line<M>(Fs + MM * min(j + 2, ty - 1), a2, bg, b2);
+    load_line<TF, M>(Fs + MM * min(j + 2, ty - 1), ac, bg, b2);
     step(b0, j);
     if (j + 1 >= ty) break;
-    load_line<M>(Fs + MM * min(j + 3, ty - 1), a2, bg, b0);
+    load_line<TF, M>(Fs + MM * min(j + 3, ty - 1), ac, bg, b0);
     step(b1, j + 1);
     if (j + 2 >= ty) break;
-    load_line<M>(Fs + MM * min(j + 4, ty - 1), a2, bg, b1);
+    load_line<TF, M>(Fs + MM * min(j + 4, ty - 1), ac, bg, b1);
     step(b2, j + 2);
   }
 }
 
 // Backward sweep in place on gl (g -> z) for lines ty-2 down to jstop.
-template <int M>
-__device__ void backward_sweep(const double* __restrict__ Fs, int ty, int jstop, double c,
-                               double* gl, double* red) {
-  const int t = threadIdx.x, a2 = t % (M / 2), bg = t / (M / 2);
+template <typename TF, int M>
+__device__ void backward_sweep(const TF* __restrict__ Fs, int ty, int jstop, double c, double* gl,
+                               double* red) {
+  using S = Sweep<TF, M>;
+  const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
   const size_t MM = (size_t)M * M;
   const int j0 = ty - 2;
   if (j0 < jstop) return;
-  double2 b0[Sweep<M>::K], b1[Sweep<M>::K], b2[Sweep<M>::K];
-  load_line<M>(Fs + MM * j0, a2, bg, b0);
-  load_line<M>(Fs + MM * max(j0 - 1, jstop), a2, bg, b1);
-  auto step = [&](const double2(&buf)[Sweep<M>::K], int j) {
-    const double y = line_product<M>(buf, gl + (size_t)(j + 1) * M, a2, bg, red);
+  typename S::VT b0[S::K], b1[S::K], b2[S::K];
+  load_line<TF, M>(Fs + MM * j0, ac, bg, b0);
+  load_line<TF, M>(Fs + MM * max(j0 - 1, jstop), ac, bg, b1);
+  auto step = [&](const typename S::VT(&buf)[S::K], int j) {
+    const double y = line_product<TF, M>(buf, gl + (size_t)(j + 1) * M, ac, bg, red);
     if (t < M) gl[(size_t)j * M + t] += c * y;
     __syncthreads();
   };
   for (int j = j0; j >= jstop; j -= 3) {
-    load_line<M>(Fs + MM * max(j - 2, jstop), a2, bg, b2);
+    load_line<TF, M>(Fs + MM * max(j - 2, jstop), ac, bg, b2);
     step(b0, j);
     if (j - 1 < jstop) break;
-    load_line<M>(Fs + MM * max(j - 3, jstop), a2, bg, b0);
+    load_line<TF, M>(Fs + MM * max(j - 3, jstop), ac, bg, b0);
     step(b1, j - 1);
     if (j - 2 < jstop) break;
-    load_line<M>(Fs + MM * max(j - 4, jstop), a2, bg, b1);
+    load_line<TF, M>(Fs + MM * max(j - 4, jstop), ac, bg, b1);
     step(b2, j - 2);
   }
 }
 
 template <int M>
 __device__ __forceinline__ void tile_to_lines(const DevProblem& P, int s, int tx, int ty,
-                                              const double* __restrict__ tile, double* gl) {
+                                              const double* __restrict__ tile, double scale, double* gl) {
   const int m = 2 * tx;
-  for (int e = threadIdx.x; e < ty * M; e += Sweep<M>::NT) {
+  for (int e = threadIdx.x; e < ty * M; e += 4 * M) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
     if (i < m) {
       const int f = i >= tx;
-      v = tile[tile_idx(P, s, f, j, i - f * tx)];
+      v = scale * tile[tile_idx(P, s, f, j, i - f * tx)];
     }
     gl[e] = v;
   }
@@ -133,7 +157,7 @@ __device__ __forceinline__ void tile_to_lines(const DevProblem& P, int s, int tx
 template <int M>
 __device__ __forceinline__ void lines_to_tile(const DevProblem& P, int s, int tx, int ty,
                                               const double* gl, double* __restrict__ out) {
-  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += Sweep<M>::NT) {
+  for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += 4 * M) {
     const int f = e / (P.txm * P.tym);
     const int r = e - f * P.txm * P.tym;
     const int b = r / P.txm, a = r - b * P.txm;
@@ -141,62 +165,43 @@ __device__ __forceinline__ void lines_to_tile(const DevProblem& P, int s, int tx
   }
 }
 
+// rb -= J_i z on the tile (z in line layout, zero outside the tile), J_i the local
+// Jacobian at R_i x + c with smoothing eps (FP64, matrix-free 5-point stencil).
 template <int M>
-__global__ __launch_bounds__(4 * M) void k_block_solve(DevProblem P, const int4* __restrict__ box,
-                                                       const double* __restrict__ facT,
-                                                       const double* __restrict__ rhs,
-                                                       double* __restrict__ out) {
-  __shared__ double gl[kMaxTile * M];
-  __shared__ double red[8 * M];
-  const int s = blockIdx.x;
-  const int4 bx = box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
-  const double* Fs = facT + (size_t)s * P.tym * M * M;
-  tile_to_lines<M>(P, s, tx, ty, rhs, gl);
-  __syncthreads();
-  forward_sweep<M>(Fs, ty, P.hy2i, gl, red);
-  backward_sweep<M>(Fs, ty, 0, P.hy2i, gl, red);
-  lines_to_tile<M>(P, s, tx, ty, gl, out);
+__device__ void sub_local_jacobian(const DevProblem& P, int s, int tx, int ty,
+                                   const double* __restrict__ tilex, const double* __restrict__ c,
+                                   double eps, const double* gl, double* rb) {
+  for (int e = threadIdx.x; e < ty * tx; e += 4 * M) {
+    const int j = e / tx, a = e - j * tx;
+    const double y = tilex[halo_idx(P, s, 0, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 0, j, a)] : 0.0);
+    const double p = tilex[halo_idx(P, s, 1, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 1, j, a)] : 0.0);
+    // neighbours inside the tile (indices clamped, weights zero outside)
+    const double* zl = gl + (size_t)j * M;
+    const int al = a > 0 ? a - 1 : a, ar = a + 1 < tx ? a + 1 : a;
+    const int jd = j > 0 ? j - 1 : j, ju = j + 1 < ty ? j + 1 : j;
+    const double wl = a > 0 ? 1.0 : 0.0, wr = a + 1 < tx ? 1.0 : 0.0;
+    const double wd = j > 0 ? 1.0 : 0.0, wu = j + 1 < ty ? 1.0 : 0.0;
+    const double* zd = gl + (size_t)jd * M;
+    const double* zu = gl + (size_t)ju * M;
+    const double zy = zl[a], zp = zl[tx + a];
+    const double lap_y = P.diag0 * zy - P.hx2i * (wl * zl[al] + wr * zl[ar]) - P.hy2i * (wd * zd[a] + wu * zu[a]);
+    const double lap_p = P.diag0 * zp - P.hx2i * (wl * zl[tx + al] + wr * zl[tx + ar])
+                         - P.hy2i * (wd * zd[tx + a] + wu * zu[tx + a]);
+    const double dphi = dphi_of(P.phi, y, P.kappa);
+    const double jy = lap_y + dphi * zy + dg_of(p, P.mu, eps) * P.inv_nu * zp;
+    const double jp = (ddphi_of(P.phi, y, P.kappa) * p - 1.0) * zy + lap_p + dphi * zp;
+    rb[(size_t)j * M + a] -= jy;
+    rb[(size_t)j * M + tx + a] -= jp;
+  }
 }
 
-// Backward sweep after the factorisation kernel's fused forward sweep (g in gout).
+// Right-hand side of Algorithm 4 on the tile: hx^-2 / hy^-2 times the values of d
+// just outside the tile (the ring), in line layout.
 template <int M>
-__global__ __launch_bounds__(4 * M) void k_solve_bwd(DevProblem P, const int4* __restrict__ box,
-                                                     const SubState* __restrict__ state,
-                                                     const double* __restrict__ facT,
-                                                     const double* __restrict__ g,
-                                                     double* __restrict__ out) {
-  __shared__ double gl[kMaxTile * M];
-  __shared__ double red[8 * M];
-  const int s = blockIdx.x;
-  if (state && !state[s].active) return;
-  const int4 bx = box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
-  const double* Fs = facT + (size_t)s * P.tym * M * M;
-  for (int e = threadIdx.x; e < ty * M; e += Sweep<M>::NT) gl[e] = g[(size_t)s * P.tym * M + e];
-  __syncthreads();
-  backward_sweep<M>(Fs, ty, 0, P.hy2i, gl, red);
-  lines_to_tile<M>(P, s, tx, ty, gl, out);
-}
-
-// Algorithm 4 for one subdomain, fused: right-hand side from the values of d just
-// outside the tile (hx^-2 / hy^-2 weights), both sweeps, and out = -d + z on the
-// non-overlapping box (every global node is written by exactly one subdomain).
-template <int M>
-__global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* __restrict__ box,
-                                                     const int4* __restrict__ core,
-                                                     const double* __restrict__ facT,
-                                                     const double* __restrict__ d,
-                                                     double* __restrict__ out,
-                                                     const int* __restrict__ skip) {
-  __shared__ double gl[kMaxTile * M];
-  __shared__ double red[8 * M];
-  if (skip && *skip) return;
-  const int s = blockIdx.x;
-  const int4 bx = box[s], co = core[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+__device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty,
+                                         const double* __restrict__ d, double* gl) {
   const size_t n = (size_t)P.nx * P.ny;
-  for (int e = threadIdx.x; e < ty * M; e += Sweep<M>::NT) {
+  for (int e = threadIdx.x; e < ty * M; e += 4 * M) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
     if (i < 2 * tx) {
@@ -210,12 +215,120 @@ __global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* _
     }
     gl[e] = v;
   }
+}
+
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_block_solve(DevProblem P, const int4* __restrict__ box,
+                                                       const TF* __restrict__ facT,
+                                                       const double* __restrict__ rhs,
+                                                       double* __restrict__ out) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  const int s = blockIdx.x;
+  const int4 bx = box[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  tile_to_lines<M>(P, s, tx, ty, rhs, 1.0, gl);
   __syncthreads();
-  const double* Fs = facT + (size_t)s * P.tym * M * M;
-  forward_sweep<M>(Fs, ty, P.hy2i, gl, red);
-  backward_sweep<M>(Fs, ty, co.z - bx.z, P.hy2i, gl, red);
+  forward_sweep<TF, M>(Fs, ty, P.hy2i, gl, red);
+  backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, gl, red);
+  lines_to_tile<M>(P, s, tx, ty, gl, out);
+}
+
+// Backward sweep after the factorisation kernel's fused forward sweep (g in gout).
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_solve_bwd(DevProblem P, const int4* __restrict__ box,
+                                                     const SubState* __restrict__ state,
+                                                     const TF* __restrict__ facT,
+                                                     const double* __restrict__ g,
+                                                     double* __restrict__ out) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  const int s = blockIdx.x;
+  if (state && !state[s].active) return;
+  const int4 bx = box[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] = g[(size_t)s * P.tym * M + e];
+  __syncthreads();
+  backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, gl, red);
+  lines_to_tile<M>(P, s, tx, ty, gl, out);
+}
+
+// nref refinement steps of the Newton direction of Algorithm 1:
+// dir <- dir + F^{-1}(-K - J dir) with J at the subdomain's current c and eps_k.
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_newton_refine(DevProblem P, const int4* __restrict__ box,
+                                                         const double* __restrict__ tilex,
+                                                         const double* __restrict__ c,
+                                                         const SubState* __restrict__ state,
+                                                         const TF* __restrict__ facT,
+                                                         const double* __restrict__ res,
+                                                         double* __restrict__ dir, int nref) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double rb[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  const int s = blockIdx.x;
+  if (!state[s].active) return;
+  const double eps = state[s].eps;
+  const int4 bx = box[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  tile_to_lines<M>(P, s, tx, ty, dir, 1.0, gl);
+  for (int it = 0; it < nref; ++it) {
+    tile_to_lines<M>(P, s, tx, ty, res, -1.0, rb);
+    __syncthreads();
+    sub_local_jacobian<M>(P, s, tx, ty, tilex, c, eps, gl, rb);
+    __syncthreads();
+    forward_sweep<TF, M>(Fs, ty, P.hy2i, rb, red);
+    backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, rb, red);
+    for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
+    __syncthreads();
+  }
+  lines_to_tile<M>(P, s, tx, ty, gl, dir);
+}
+
+// Algorithm 4 for one subdomain, fused: right-hand side from the values of d just
+// outside the tile, both sweeps (plus nref FP64 refinement steps with J_i at
+// x^(i) = R_i x + c, eps_min), and out = -d + z on the non-overlapping box (every
+// global node is written by exactly one subdomain).  skip (nullable): do nothing
+// when *skip != 0.
+template <typename TF, int M, bool REF>
+__global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* __restrict__ box,
+                                                     const int4* __restrict__ core,
+                                                     const TF* __restrict__ facT,
+                                                     const double* __restrict__ tilex,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ d,
+                                                     double* __restrict__ out,
+                                                     const int* __restrict__ skip, int nref) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double rb[REF ? kMaxTile * M : 1];
+  if (skip && *skip) return;
+  if (!REF) nref = 0;
+  const int s = blockIdx.x;
+  const int4 bx = box[s], co = core[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const int jcore = co.z - bx.z;
+  ring_rhs<M>(P, bx, tx, ty, d, gl);
+  __syncthreads();
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  forward_sweep<TF, M>(Fs, ty, P.hy2i, gl, red);
+  backward_sweep<TF, M>(Fs, ty, nref > 0 ? 0 : jcore, P.hy2i, gl, red);
+  for (int it = 0; it < nref; ++it) {
+    ring_rhs<M>(P, bx, tx, ty, d, rb);
+    __syncthreads();
+    sub_local_jacobian<M>(P, s, tx, ty, tilex, c, P.eps_min, gl, rb);
+    __syncthreads();
+    forward_sweep<TF, M>(Fs, ty, P.hy2i, rb, red);
+    backward_sweep<TF, M>(Fs, ty, it + 1 == nref ? jcore : 0, P.hy2i, rb, red);
+    for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
+    __syncthreads();
+  }
+  const size_t n = (size_t)P.nx * P.ny;
   const int cw = co.y - co.x, ch = co.w - co.z;
-  for (int e = threadIdx.x; e < 2 * cw * ch; e += Sweep<M>::NT) {
+  for (int e = threadIdx.x; e < 2 * cw * ch; e += 4 * M) {
     const int f = e / (cw * ch);
     const int r = e - f * cw * ch;
     const int b = r / cw, a = r - b * cw;
@@ -238,25 +351,73 @@ __global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* _
 
 }  // namespace
 
-void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state,
-                      const double* facT, const double* g, double* out, hipStream_t st) {
-#define RSP_CALL(MM) k_solve_bwd<MM><<<P.S, 4 * MM, 0, st>>>(P, box, state, facT, g, out)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
+void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state, const void* facT,
+                      int fp32, const double* g, double* out, hipStream_t st) {
+  if (fp32) {
+#define RSP_CALL(MM) k_solve_bwd<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, state, (const float*)facT, g, out)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
 #undef RSP_CALL
+  } else {
+#define RSP_CALL(MM) k_solve_bwd<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, state, (const double*)facT, g, out)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  }
 }
 
-void launch_block_solve(const DevProblem& P, const int4* box, const double* facT,
+void launch_newton_refine(const DevProblem& P, const int4* box, const double* tilex, const double* c,
+                          const SubState* state, const void* facT, int fp32, const double* res,
+                          double* dir, int nref, hipStream_t st) {
+  if (nref <= 0) return;
+  if (fp32) {
+#define RSP_CALL(MM) \
+  k_newton_refine<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, tilex, c, state, (const float*)facT, res, dir, nref)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  } else {
+#define RSP_CALL(MM) \
+  k_newton_refine<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, tilex, c, state, (const double*)facT, res, dir, nref)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  }
+}
+
+void launch_block_solve(const DevProblem& P, const int4* box, const void* facT, int fp32,
                         const double* rhs, double* out, hipStream_t st) {
-#define RSP_CALL(MM) k_block_solve<MM><<<P.S, 4 * MM, 0, st>>>(P, box, facT, rhs, out)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
+  if (fp32) {
+#define RSP_CALL(MM) k_block_solve<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, (const float*)facT, rhs, out)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
 #undef RSP_CALL
+  } else {
+#define RSP_CALL(MM) k_block_solve<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, (const double*)facT, rhs, out)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  }
 }
 
-void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const double* facT,
-                      const double* d, double* out, const int* skip, hipStream_t st) {
-#define RSP_CALL(MM) k_jac_apply<MM><<<P.S, 4 * MM, 0, st>>>(P, box, core, facT, d, out, skip)
-  RSP_DISPATCH_M(P.M, RSP_CALL)
+void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const void* facT, int fp32,
+                      const double* tilex, const double* c, const double* d, double* out,
+                      const int* skip, int nref, hipStream_t st) {
+#define RSP_APPLY(TT, REFB, MM)                                                                      \
+  k_jac_apply<TT, MM, REFB><<<P.S, 4 * MM, 0, st>>>(P, box, core, (const TT*)facT, tilex, c, d, out, skip, \
+                                                    nref)
+  if (fp32 && nref > 0) {
+#define RSP_CALL(MM) RSP_APPLY(float, true, MM)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
 #undef RSP_CALL
+  } else if (fp32) {
+#define RSP_CALL(MM) RSP_APPLY(float, false, MM)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  } else if (nref > 0) {
+#define RSP_CALL(MM) RSP_APPLY(double, true, MM)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  } else {
+#define RSP_CALL(MM) RSP_APPLY(double, false, MM)
+    RSP_DISPATCH_M(P.M, RSP_CALL)
+#undef RSP_CALL
+  }
+#undef RSP_APPLY
 }
 
 }  // namespace rsp

@@ -84,7 +84,9 @@ int validate_options(const rsp_options* o) {
   if (!(o->alpha_min > 0 && o->alpha_min <= 1)) return fail(RSP_EINVAL, "need 0 < alpha_min <= 1");
   if (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart) return fail(RSP_EINVAL, "gmres_restart must be in 1..%d", kMaxRestart);
   if (o->max_outer < 0 || o->max_inner < 0 || o->max_gmres < 1) return fail(RSP_EINVAL, "negative iteration limit");
-  if (o->precision != RSP_FP64) return fail(RSP_EINVAL, "precision %d not supported", o->precision);
+  if (o->precision != RSP_FP64 && o->precision != RSP_FP32_REFINED)
+    return fail(RSP_EINVAL, "unknown precision %d", o->precision);
+  if (o->max_refine < 0 || o->max_refine > 8) return fail(RSP_EINVAL, "max_refine must be in 0..8");
   if (o->continuation < RSP_CONT_FIRST || o->continuation > RSP_CONT_EVERY) return fail(RSP_EINVAL, "unknown continuation mode");
   if (!(o->tol_outer >= 0) || !(o->tol_inner >= 0) || !(o->gmres_rtol >= 0)) return fail(RSP_EINVAL, "negative tolerance");
   return 0;
@@ -143,10 +145,11 @@ DevProblem make_dev(const rsp_problem* p, const Partition& part) {
 // Sizes (in doubles unless noted) of every workspace buffer.
 struct Layout {
   size_t n, L, tile, halo, fac, g, V, partial, gpart;
+  size_t fac_elem;   // bytes per stored factor entry (8 FP64, 4 FP32)
   size_t bytes() const {
-    return 8 * (2 * n /*yd,f*/ + 2 * L /*x,F*/ + halo + 5 * tile /*c,dir,res,t1,t2*/ + fac + g +
+    return 8 * (2 * n /*yd,f*/ + 2 * L /*x,F*/ + halo + 5 * tile /*c,dir,res,t1,t2*/ + g +
                 V + 4 * L /*w, b, dx, r*/ + partial + 4 * 80 /*h bufs*/ + 2 * gpart) +
-           sizeof(rsp::GmState);
+           fac_elem * fac + sizeof(rsp::GmState);
   }
 };
 
@@ -161,6 +164,7 @@ Layout make_layout(const DevProblem& P, const rsp_options* o) {
   l.V = (size_t)(o->gmres_restart + 1) * l.L;
   l.partial = (size_t)rsp::multidot_blocks(l.L) * 72;
   l.gpart = (size_t)rsp::kGmBlocks * rsp::kGmMaxVec;
+  l.fac_elem = o->precision == RSP_FP32_REFINED ? 4 : 8;
   return l;
 }
 
@@ -173,11 +177,11 @@ size_t layout_bytes(const Layout& l, int S) {
 // Kernel timing: HIP events around launches, resolved at synchronisation points.
 enum Kid {
   KID_RESTRICT, KID_INIT, KID_FACTOR, KID_SOLVE_BWD, KID_LINESEARCH, KID_PROLONG, KID_RING,
-  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_N
+  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_N
 };
 const char* const kKidName[KID_N] = {"restrict_halo", "newton_init", "factor", "solve_bwd",
                                      "linesearch", "prolong", "ring_rhs", "block_solve",
-                                     "gmres_ortho", "global_residual"};
+                                     "gmres_ortho", "global_residual", "newton_refine"};
 
 struct Pending {
   int kid;
@@ -203,9 +207,12 @@ struct rsp_context {
   SubState* state = nullptr;
   double *yd = nullptr, *f = nullptr, *x = nullptr, *F = nullptr, *tilex = nullptr;
   double *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
-  double *fac = nullptr, *g = nullptr, *V = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr;
+  void* fac = nullptr;
+  double *g = nullptr, *V = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr;
   double *partial = nullptr, *hbuf = nullptr, *r = nullptr, *gp1 = nullptr, *gp2 = nullptr;
   rsp::GmState* gst = nullptr;
+  int fp32 = 0;       // FP32 line factors (mixed precision)
+  int nref = 0;       // FP64 refinement steps per local solve with FP32 factors
   std::vector<SubState> hstate;
   // kernel timing
   bool prof = false;
@@ -280,17 +287,17 @@ struct SubWork {
   double tile_by = 0, halo_by = 0;
 };
 
-SubWork sub_work(const std::vector<int4>& boxes, const std::vector<SubState>* state) {
+SubWork sub_work(const std::vector<int4>& boxes, const std::vector<SubState>* state, double fe = 8.0) {
   SubWork w;
   for (size_t s = 0; s < boxes.size(); ++s) {
     if (state && !(*state)[s].active) continue;
     const double tx = boxes[s].y - boxes[s].x, ty = boxes[s].w - boxes[s].z, m = 2 * tx;
     w.factor_fl += 16.0 * ty * tx * tx * tx;           // ty Gauss-Jordan inversions of m x m
-    w.factor_by += 8.0 * ty * m * m;                   // the inverses written once
+    w.factor_by += fe * ty * m * m;                    // the inverses written once
     w.bwd_fl += 2.0 * (ty - 1) * m * m;
-    w.bwd_by += 8.0 * (ty - 1) * m * m;
+    w.bwd_by += fe * (ty - 1) * m * m;
     w.solve_fl += 2.0 * (2 * ty - 1) * m * m;          // forward + backward sweeps
-    w.solve_by += 8.0 * (2 * ty - 1) * m * m + 8.0 * 2 * m * ty;
+    w.solve_by += fe * (2 * ty - 1) * m * m + 8.0 * 2 * m * ty;
     w.tile_by += 8.0 * m * ty;
     w.halo_by += 8.0 * 2 * (tx + 2) * (ty + 2);
   }
@@ -316,7 +323,8 @@ int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, 
   const rsp_problem& pr = ctx->prob;
   const rsp_options& o = ctx->opts;
   const double eps0 = continuation ? pr.eps0 : pr.eps_min;
-  const SubWork all = sub_work(ctx->part.box, nullptr);
+  const double fe = (double)ctx->lay.fac_elem;
+  const SubWork all = sub_work(ctx->part.box, nullptr, fe);
   {
     Timed t(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
     rsp::launch_restrict_halo(P, ctx->box, x, ctx->tilex, st);
@@ -338,16 +346,22 @@ int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, 
     // every subdomain needs the continuation steps: run them without looking, then
     // check after every step
     const int batch = std::max(1, std::min(ncont - it, o.max_inner + 1 - it));
-    const SubWork w = sub_work(ctx->part.box, &ctx->hstate);
+    const SubWork w = sub_work(ctx->part.box, &ctx->hstate, fe);
     for (int b = 0; b < batch; ++b) {
       {
         Timed t(ctx, KID_FACTOR, st, w.factor_fl + w.bwd_fl / 2, w.factor_by);
         rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, ctx->state, 0.0, ctx->res, -1.0,
-                           ctx->fac, ctx->g, st);
+                           ctx->fac, ctx->fp32, ctx->g, st);
       }
       {
         Timed t(ctx, KID_SOLVE_BWD, st, w.bwd_fl, w.bwd_by);
-        rsp::launch_solve_bwd(P, ctx->box, ctx->state, ctx->fac, ctx->g, ctx->dir, st);
+        rsp::launch_solve_bwd(P, ctx->box, ctx->state, ctx->fac, ctx->fp32, ctx->g, ctx->dir, st);
+      }
+      if (ctx->nref > 0) {
+        Timed t(ctx, KID_REFINE, st, ctx->nref * (w.solve_fl + 20.0 * w.tile_by / 8),
+                ctx->nref * (w.solve_by + 2 * w.tile_by));
+        rsp::launch_newton_refine(P, ctx->box, ctx->tilex, ctx->c, ctx->state, ctx->fac, ctx->fp32,
+                                  ctx->res, ctx->dir, ctx->nref, st);
       }
       {
         Timed t(ctx, KID_LINESEARCH, st, 40.0 * w.tile_by / 8, 6 * w.tile_by);
@@ -388,7 +402,7 @@ int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, 
   {
     Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
     rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, nullptr, pr.eps_min, nullptr, 0.0, ctx->fac,
-                       ctx->g, st);
+                       ctx->fp32, ctx->g, st);
   }
   {
     Timed t(ctx, KID_PROLONG, st, 0, 8.0 * 2 * ctx->lay.L);
@@ -402,10 +416,12 @@ int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, 
 int run_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st,
                   const int* skip = nullptr) {
   const DevProblem& P = ctx->P;
-  const SubWork w = sub_work(ctx->part.box, nullptr);
+  const SubWork w = sub_work(ctx->part.box, nullptr, (double)ctx->lay.fac_elem);
   {
-    Timed t(ctx, KID_BLOCK_SOLVE, st, w.solve_fl, w.solve_by + 8.0 * 2 * ctx->lay.L);
-    rsp::launch_jac_apply(P, ctx->box, ctx->core, ctx->fac, d, out, skip, st);
+    Timed t(ctx, KID_BLOCK_SOLVE, st, (1 + ctx->nref) * w.solve_fl,
+            (1 + ctx->nref) * w.solve_by + 8.0 * 2 * ctx->lay.L);
+    rsp::launch_jac_apply(P, ctx->box, ctx->core, ctx->fac, ctx->fp32, ctx->tilex, ctx->c, d, out, skip,
+                          ctx->nref, st);
   }
   ctx->n_solve += P.S;
   ctx->n_apply += 1;
@@ -512,7 +528,7 @@ int ensure_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* o
   ctx->res = (double*)take(8 * lay.tile);
   ctx->t1 = (double*)take(8 * lay.tile);
   ctx->t2 = (double*)take(8 * lay.tile);
-  ctx->fac = (double*)take(8 * lay.fac);
+  ctx->fac = (void*)take(lay.fac_elem * lay.fac);
   ctx->g = (double*)take(8 * lay.g);
   ctx->V = (double*)take(8 * lay.V);
   ctx->w = (double*)take(8 * lay.L);
@@ -532,6 +548,8 @@ int ensure_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* o
   ctx->P = P;
   ctx->lay = lay;
   ctx->hstate.assign(P.S, SubState{});
+  ctx->fp32 = opts->precision == RSP_FP32_REFINED;
+  ctx->nref = ctx->fp32 ? opts->max_refine : 0;
   ctx->ready = true;
   return 0;
 }
@@ -654,8 +672,9 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
   NEED_READY(ctx);
   if (!(eps > 0)) return fail(RSP_EINVAL, "eps must be > 0");
   rsp::launch_restrict_halo(ctx->P, ctx->box, x, ctx->tilex, stream);
-  rsp::launch_factor(ctx->P, ctx->box, ctx->tilex, c, nullptr, eps, nullptr, 0.0, ctx->fac, ctx->g, stream);
-  rsp::launch_block_solve(ctx->P, ctx->box, ctx->fac, rhs, z, stream);
+  rsp::launch_factor(ctx->P, ctx->box, ctx->tilex, c, nullptr, eps, nullptr, 0.0, ctx->fac, ctx->fp32,
+                     ctx->g, stream);
+  rsp::launch_block_solve(ctx->P, ctx->box, ctx->fac, ctx->fp32, rhs, z, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }

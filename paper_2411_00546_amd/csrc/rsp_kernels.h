@@ -31,20 +31,27 @@ void launch_linesearch(const DevProblem& P, const int4* box, const double* tilex
 // a9: ring right-hand side h^-2 (outside neighbours of d) per tile.
 void launch_ring_rhs(const DevProblem& P, const int4* box, const double* d, double* rhs,
                      hipStream_t st);
-// a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1}.
+// a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1},
+// stored as double, or as float when fp32 != 0 (facT points to that type).
 void launch_factor(const DevProblem& P, const int4* box, const double* tilex, const double* c,
                    const SubState* state, double eps_fixed, const double* rhs, double rhs_scale,
-                   double* facT, double* g, hipStream_t st);
+                   void* facT, int fp32, double* g, hipStream_t st);
 // a5: backward sweep after a fused forward sweep.
-void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state,
-                      const double* facT, const double* g, double* out, hipStream_t st);
+void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state, const void* facT,
+                      int fp32, const double* g, double* out, hipStream_t st);
+// Refinement of the Newton direction: nref steps dir += F^{-1}(-res - J dir) (FP64 J).
+void launch_newton_refine(const DevProblem& P, const int4* box, const double* tilex, const double* c,
+                          const SubState* state, const void* facT, int fp32, const double* res,
+                          double* dir, int nref, hipStream_t st);
 // a5: forward + backward sweeps with stored factors (tile rhs -> tile out).
-void launch_block_solve(const DevProblem& P, const int4* box, const double* facT,
+void launch_block_solve(const DevProblem& P, const int4* box, const void* facT, int fp32,
                         const double* rhs, double* out, hipStream_t st);
-// a9 (Algorithm 4), fused: ring rhs of d, both sweeps, out = -d + sum_i P~_i z_i.
-// `skip` (nullable, device): the launch does nothing when *skip != 0.
-void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const double* facT,
-                      const double* d, double* out, const int* skip, hipStream_t st);
+// a9 (Algorithm 4), fused: ring rhs of d, both sweeps (+ nref FP64 refinement steps with
+// the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  `skip` (nullable,
+// device): the launch does nothing when *skip != 0.
+void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const void* facT, int fp32,
+                      const double* tilex, const double* c, const double* d, double* out,
+                      const int* skip, int nref, hipStream_t st);
 // Section 4 F(x, eps) on the whole grid and the control u(p).
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
                             const double* x, double eps, double* out, hipStream_t st);

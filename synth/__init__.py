@@ -98,7 +98,7 @@ class Options:
     max_inner: int = 200
     max_gmres: int = 300
     precision: int = 0          # 0 FP64, 1 FP32 factors + FP64 refinement
-    max_refine: int = 10
+    max_refine: int = 1
     continuation: int = 0       # 0 first evaluation, 1 none, 2 every evaluation
 
 

@@ -86,3 +86,6 @@ def test_workspace_bytes(R):
     assert plain > 64 * 40 * 80 * 80 * 8
     bad = synth.Problem(nx=9, ny=9, sx=4, sy=1)
     assert R.rsp_workspace_bytes(R.make_problem(bad), o) == 0
+    # FP32 line factors take half the factor bytes
+    mixed = R.rsp_workspace_bytes(R.make_problem(synth.config_plain()), R.make_options(synth.Options(precision=1)))
+    assert plain - mixed == 64 * 40 * 80 * 80 * 4

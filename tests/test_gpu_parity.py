@@ -386,3 +386,81 @@ def test_plain_workload_sampled(R):
             assert np.abs(mine - ref).max() <= 1e-8 * np.abs(ref).max()
     finally:
         c.close()
+
+
+# ------------------------------------------------------------------ mixed precision (FP32 factors)
+MIXED = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12, precision=1, max_refine=1)
+
+
+@pytest.mark.parametrize("name,phi,nu", [("small63", synth.PHI_CUBIC, 1e-2), ("rect23x17", synth.PHI_EXP, 1e-4),
+                                         ("tile40", synth.PHI_CUBIC, 1e-3)])
+def test_local_solve_fp32_factors(R, name, phi, nu):
+    """FP32 line inverses (no refinement in this entry point): the error is that of
+    an FP32 block LU, bounded here by 1e-4 relative."""
+    prob = make_problem(name, phi=phi, nu=nu)
+    c = Case(R, prob, synth.Options(precision=1))
+    try:
+        x = rand_state(c.n, 11)
+        rng = np.random.default_rng(12)
+        locs = [np.zeros(2 * s.rows.size) for s in c.ora.subs]
+        rhs = [rng.standard_normal(2 * s.rows.size) for s in c.ora.subs]
+        z = dev(np.zeros((c.S, 2, c.tym, c.txm)))
+        R.rsp_local_solve(c.ctx, dev(x), dev(to_tiles(c.ora.subs, c.txm, c.tym, locs)), 1e-4,
+                          dev(to_tiles(c.ora.subs, c.txm, c.tym, rhs)), z)
+        got = from_tiles(c.ora.subs, host(z))
+        import scipy.sparse.linalg as spla
+        for i in range(c.S):
+            ref = spla.spsolve(c.ora.local_jacobian(i, x, locs[i], 1e-4), rhs[i])
+            assert np.abs(got[i] - ref).max() <= 1e-4 * np.abs(ref).max()
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("nref,tol", [(1, 1e-9), (2, 1e-11)])
+def test_eval_and_jacobian_action_fp32_refined(R, nref, tol):
+    prob = make_problem("ragged37x29", phi=synth.PHI_CUBIC)
+    opts = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12, precision=1, max_refine=nref)
+    c = Case(R, prob, opts)
+    try:
+        n = c.n
+        x = rand_state(n, 13, 0.05, 0.005)
+        out = dev(np.zeros(2 * n))
+        st, nrm = R.rsp_eval(c.ctx, dev(x), 1, out)
+        ref, info = c.ora.eval_F(x, continuation=True)
+        assert st == 0
+        # the local Newton solves stop on FP64 residuals: same accuracy as FP64
+        assert np.abs(host(out) - ref).max() <= 1e-10 * np.abs(ref).max()
+        d = np.random.default_rng(14).standard_normal(2 * n)
+        jd = dev(np.zeros(2 * n))
+        R.rsp_jac_apply(c.ctx, dev(d), jd)
+        jref = c.ora.jac_apply(d)
+        assert np.abs(host(jd) - jref).max() <= tol * np.abs(jref).max()
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("name,phi,mu", [("small63", synth.PHI_CUBIC, 1e-2), ("rect23x17", synth.PHI_EXP, 1e-2),
+                                         ("ragged37x29", synth.PHI_CUBIC, 0.0)])
+def test_solve_mixed_precision(R, name, phi, mu):
+    """FP32 factors + FP64 refinement: within 1e-8 of the FP64 oracle and of the
+    GPU FP64 path."""
+    prob = make_problem(name, phi=phi, mu=mu)
+    yd, f = prob.inputs()
+    st, hist, x, u = gpu_solve(R, prob, MIXED, yd, f)
+    st64, hist64, x64, u64 = gpu_solve(R, prob, TIGHT, yd, f)
+    ref = Raspen(prob, TIGHT, yd, f).solve()
+    assert st == 0 and st64 == 0
+    assert rel(x, ref["x"]) <= 1e-8
+    assert rel(x, x64) <= 1e-8
+
+
+def test_plain_workload_mixed_vs_fp64(R):
+    """255x255 / 8x8 at the benchmark tolerances: mixed precision within 1e-8 of FP64."""
+    prob = synth.config_plain()
+    yd, f = prob.inputs()
+    st64, h64, x64, u64 = gpu_solve(R, prob, synth.Options(), yd, f)
+    st, h, x, u = gpu_solve(R, prob, synth.Options(precision=1, max_refine=1), yd, f)
+    assert st == 0 and st64 == 0
+    assert rel(x, x64) <= 1e-8
+    sysm = System(prob, yd, f)
+    assert np.linalg.norm(sysm.residual(x, prob.eps_min)) <= 1e-6
