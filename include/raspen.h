@@ -200,6 +200,26 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
               const double* yd, const double* f, const double* y0, const double* p0,
               double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
 
+/* Algorithm 2 for `count` independent instances at once (a batch).  Every launch of
+   the hot path covers the subdomains of all instances still iterating, and each
+   instance runs its own outer iteration: stopping test, GMRES (in lockstep, a
+   converged instance drops out through its own stop flag) and update.  Instance q
+   reads probs[q], yd[q], f[q] (f, y0, p0 may be NULL arrays, or hold NULL entries:
+   f = 0, x^0 = 0) and writes y[q], p[q], u[q] (device pointers) and hist[q] (host,
+   nullable array).  `opts` applies to every instance.  Per-instance reductions
+   have a fixed order that depends only on the instance, so an instance's result
+   does not depend on the other members of the batch when the batch's padded
+   line-block size (16-multiple above twice the widest tile) equals its own.
+   Returns the largest per-instance status (hist[q].status holds each), or a hard
+   error (< 0).  The single-problem calls above need rsp_setup again afterwards. */
+int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const rsp_options* opts,
+                    const double* const* yd, const double* const* f, const double* const* y0,
+                    const double* const* p0, double* const* y, double* const* p, double* const* u,
+                    rsp_history* hist, hipStream_t stream);
+
+/* Device bytes rsp_solve_batch needs for these problems (0 if one is invalid). */
+size_t rsp_batch_workspace_bytes(int count, const rsp_problem* probs, const rsp_options* opts);
+
 /* ---- kernel timing (HIP events around every launch of the hot-path kernels) ---- */
 
 typedef struct rsp_kernel_stat {

@@ -68,8 +68,7 @@ constexpr int kFacThreads = 256;   // 16 x 16 threads; thread (ti, tj) owns rows
 // FP32 factors of the mixed-precision form); coefficients and the fused forward
 // sweep stay in double.
 template <typename T, int M>
-__global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4* __restrict__ box,
-                                                        const double* __restrict__ tilex,
+__global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* __restrict__ tilex,
                                                         const double* __restrict__ c,
                                                         const SubState* __restrict__ state,
                                                         double eps_fixed, const double* __restrict__ rhs,
@@ -86,15 +85,17 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
   __shared__ double vin[M], gprev[M];
   __shared__ int nondom;
 
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
   const int lane = t & 63;
-  double eps = eps_fixed;
+  double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
   if (state) {
     if (!state[s].active) return;
     eps = state[s].eps;
   }
-  const int4 bx = box[s];
+  const int4 bx = I.box[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const int m = 2 * tx;
   const double hy4i = P.hy2i * P.hy2i;
@@ -359,20 +360,21 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(DevProblem P, const int4
 
 }  // namespace
 
-void launch_factor(const DevProblem& P, const int4* box, const double* tilex, const double* c,
-                   const SubState* state, double eps_fixed, const double* rhs, double rhs_scale,
-                   void* facT, int fp32, double* g, hipStream_t st) {
+void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
+                   double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
+                   hipStream_t st) {
+  if (I.count <= 0) return;
   if (fp32) {
 #define RSP_CALL(MM)                                                                                  \
-  k_factor<float, MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                   (float*)facT, g)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+  k_factor<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                       (float*)facT, g)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor<double, MM><<<P.S, kFacThreads, 0, st>>>(P, box, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                    (double*)facT, g)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+  k_factor<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                        (double*)facT, g)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
 }

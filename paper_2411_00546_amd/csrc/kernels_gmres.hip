@@ -1,13 +1,16 @@
-// Device-resident restarted GMRES (x_0 = 0) for the RASPEN Newton system of
-// Algorithm 2: Arnoldi with classical Gram-Schmidt applied twice, Givens rotations
-// on the Hessenberg column, the stopping test |g_{j+1}| <= rtol |b| and the
-// triangular solve, all on the device.  A stop flag written by the Givens kernel
-// lets the host enqueue a whole restart cycle without reading anything back:
-// every kernel of a later step returns at once when the flag is set.
+// Device-resident restarted GMRES (x_0 = 0) for the RASPEN Newton systems of
+// Algorithm 2, for every instance of a batch at once: Arnoldi with classical
+// Gram-Schmidt applied twice, Givens rotations on the Hessenberg column, the
+// stopping test |g_{j+1}| <= rtol |b| and the triangular solve, all on the device.
+// Launch grid: (kGmBlocks, instances); blockIdx.y selects the instance, whose
+// vectors are its segment of the batch's concatenated vectors (basis vector k of
+// every instance: V + k ldv).  A per-instance stop
+// flag written by the Givens kernel lets the host enqueue a whole restart cycle
+// without reading anything back: the kernels of a stopped instance return at once.
 //
-// Reductions are deterministic: kGmBlocks fixed blocks each own a contiguous
-// chunk, write their partial sums, and every consumer adds the partials in block
-// order.
+// Reductions are deterministic and depend only on the instance's own length:
+// kGmBlocks fixed blocks each own a contiguous chunk, write their partial sums, and
+// every consumer adds the partials in block order.
 #include "rsp_kernels.h"
 
 namespace rsp {
@@ -15,6 +18,21 @@ namespace rsp {
 namespace {
 
 constexpr int kT = 256;
+constexpr size_t kPart = (size_t)kGmBlocks * kGmMaxVec;   // partial sums per instance
+
+struct Seg {
+  int i;          // instance
+  size_t off, L;  // its vector segment
+};
+
+__device__ __forceinline__ Seg seg_of(const GmBatch& B) {
+  Seg g;
+  g.i = B.list ? B.list[blockIdx.y] : (int)blockIdx.y;
+  const GmSeg sg = B.seg[g.i];
+  g.off = (size_t)sg.off;
+  g.L = (size_t)sg.L;
+  return g;
+}
 
 __device__ __forceinline__ void chunk_of(size_t L, size_t& lo, size_t& hi) {
   const size_t ch = (L + kGmBlocks - 1) / kGmBlocks;
@@ -74,12 +92,16 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
 
 // partial sums of V_i . w for i < nv over this block's chunk
 template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, size_t L, int nv,
+__global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, const double* __restrict__ V, int nv,
                                                 const double* __restrict__ w,
-                                                const GmState* __restrict__ st,
                                                 double* __restrict__ partial) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
-  if (st->done) return;
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  const size_t L = g.L;
+  V += g.off;
+  w += g.off;
+  partial += g.i * kPart;
   size_t lo, hi;
   chunk_of(L, lo, hi);
   double acc[NB];
@@ -89,7 +111,7 @@ __global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, si
     const double we = w[e];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const double v = V[(size_t)min(i, nv - 1) * L + e];
+      const double v = V[(size_t)min(i, nv - 1) * B.ldv + e];
       acc[i] = fma(v, i < nv ? we : 0.0, acc[i]);
     }
   }
@@ -101,17 +123,22 @@ __global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, si
 // w with V (next = 0) or its partial squared norm (next = 1).  Block 0 adds h into
 // the Hessenberg column j.
 template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_update(const double* __restrict__ V, size_t L, int nv,
-                                                  double* __restrict__ w, GmState* __restrict__ st,
+__global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __restrict__ V, int nv,
+                                                  double* __restrict__ w,
                                                   const double* __restrict__ pin, int first,
                                                   int next, double* __restrict__ pout, int j) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
   __shared__ double hs[kGmMaxVec];
-  if (st->done) return;
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  const size_t L = g.L;
+  V += g.off;
+  w += g.off;
+  pin += g.i * kPart;
+  pout += g.i * kPart;
   gather_partials(pin, nv, hs);
   if (blockIdx.x == 0 && (int)threadIdx.x < nv) {
-    const int m = st->m;
-    double* Hc = st->H + threadIdx.x * m + j;
+    double* Hc = B.hs[g.i].H + threadIdx.x * B.m + j;
     *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
   }
   double h[NB];
@@ -125,7 +152,7 @@ __global__ __launch_bounds__(kT) void k_gm_update(const double* __restrict__ V, 
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
     double v[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * L + e];
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
     double we = w[e];
 #pragma unroll
     for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
@@ -143,32 +170,39 @@ __global__ __launch_bounds__(kT) void k_gm_update(const double* __restrict__ V, 
 }
 
 // |w| from the partials; V_{j+1} = w / |w|; block 0 stores H[j+1][j].
-__global__ __launch_bounds__(kT) void k_gm_normalize(double* __restrict__ Vn, size_t L,
+__global__ __launch_bounds__(kT) void k_gm_normalize(GmBatch B, double* __restrict__ V,
                                                      const double* __restrict__ w,
-                                                     GmState* __restrict__ st,
                                                      const double* __restrict__ pin, int j) {
   __shared__ double hs[1];
-  if (st->done) return;
-  gather_partials(pin, 1, hs);
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  const size_t L = g.L;
+  double* Vn = V + (size_t)(j + 1) * B.ldv + g.off;
+  w += g.off;
+  gather_partials(pin + g.i * kPart, 1, hs);
   const double nrm = sqrt(hs[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->H[(j + 1) * st->m + j] = nrm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) B.hs[g.i].H[(j + 1) * B.m + j] = nrm;
   const double inv = 1.0 / nrm;
   size_t lo, hi;
   chunk_of(L, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) Vn[e] = w[e] * inv;
 }
 
-// Givens rotations on Hessenberg column j, residual estimate and stopping test.  The
-// column and the rotations are staged in LDS so the sequential part runs from LDS.
-__global__ __launch_bounds__(kT) void k_gm_givens(GmState* __restrict__ st, int j) {
+// Givens rotations on Hessenberg column j, residual estimate and stopping test (one
+// block per instance).  The column and the rotations are staged in LDS so the
+// sequential part runs from LDS.
+__global__ __launch_bounds__(kT) void k_gm_givens(GmBatch B, int j) {
   __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
+  const Seg g = seg_of(B);
+  GmState* st = B.st + g.i;
+  GmHess* hz = B.hs + g.i;
   if (st->done) return;
-  const int m = st->m;
+  const int m = B.m;
   const int t = threadIdx.x;
-  if (t <= j + 1) col[t] = st->H[t * m + j];
+  if (t <= j + 1) col[t] = hz->H[t * m + j];
   if (t < j) {
-    cs[t] = st->cs[t];
-    sn[t] = st->sn[t];
+    cs[t] = hz->cs[t];
+    sn[t] = hz->sn[t];
   }
   __syncthreads();
   if (t != 0) return;
@@ -180,34 +214,57 @@ __global__ __launch_bounds__(kT) void k_gm_givens(GmState* __restrict__ st, int 
   const double a = col[j], b = col[j + 1];
   const double den = hypot(a, b);
   const double c = a / den, s = b / den;
-  st->cs[j] = c;
-  st->sn[j] = s;
+  hz->cs[j] = c;
+  hz->sn[j] = s;
   col[j] = den;
   col[j + 1] = 0.0;
-  for (int i = 0; i <= j + 1; ++i) st->H[i * m + j] = col[i];
+  for (int i = 0; i <= j + 1; ++i) hz->H[i * m + j] = col[i];
   const bool breakdown = !(b > 0.0);
-  const double gj = st->g[j];
-  st->g[j + 1] = -s * gj;
-  st->g[j] = c * gj;
-  st->rel = fabs(st->g[j + 1]) / st->bnorm;
+  const double gj = hz->g[j];
+  hz->g[j + 1] = -s * gj;
+  hz->g[j] = c * gj;
+  st->rel = fabs(hz->g[j + 1]) / st->bnorm;
   st->steps = j + 1;
   st->used += 1;
   if (!(st->rel > st->rtol) || st->used >= st->maxit || breakdown || j + 1 >= m) st->done = 1;
 }
 
+// Fresh solve: header of every instance of the launch (one block per instance).
+__global__ void k_gm_init(GmBatch B, int maxit, double rtol) {
+  const Seg g = seg_of(B);
+  if (threadIdx.x != 0) return;
+  GmState s;
+  s.m = B.m;
+  s.maxit = maxit;
+  s.steps = 0;
+  s.used = 0;
+  s.done = 0;
+  s.pad = 0;
+  s.rtol = rtol;
+  s.bnorm = 0.0;
+  s.beta = 0.0;
+  s.rel = 0.0;
+  B.st[g.i] = s;
+}
+
 // Cycle start: beta = |r| from partials, V_0 = r / beta, g = (beta, 0, ...).
-__global__ __launch_bounds__(kT) void k_gm_start(double* __restrict__ V0, size_t L,
+__global__ __launch_bounds__(kT) void k_gm_start(GmBatch B, double* __restrict__ V,
                                                  const double* __restrict__ r,
-                                                 GmState* __restrict__ st,
                                                  const double* __restrict__ pin, int first_cycle) {
   __shared__ double hs[1];
-  gather_partials(pin, 1, hs);
+  const Seg g = seg_of(B);
+  const size_t L = g.L;
+  double* V0 = V + g.off;
+  r += g.off;
+  gather_partials(pin + g.i * kPart, 1, hs);
   const double beta = sqrt(hs[0]);
+  GmState* st = B.st + g.i;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    GmHess* hz = B.hs + g.i;
     if (first_cycle) st->bnorm = beta;
     st->beta = beta;
-    for (int i = 0; i <= st->m; ++i) st->g[i] = 0.0;
-    st->g[0] = beta;
+    for (int i = 0; i <= B.m; ++i) hz->g[i] = 0.0;
+    hz->g[0] = beta;
     st->steps = 0;
     st->rel = st->bnorm > 0.0 ? beta / st->bnorm : 0.0;
     st->done = (!(beta > st->rtol * st->bnorm) || st->used >= st->maxit) ? 1 : 0;
@@ -220,17 +277,21 @@ __global__ __launch_bounds__(kT) void k_gm_start(double* __restrict__ V0, size_t
 }
 
 // y = R^{-1} g (back substitution over the steps done), x += V y.
-__global__ __launch_bounds__(kT) void k_gm_update_x(const double* __restrict__ V, size_t L,
-                                                    GmState* __restrict__ st,
+__global__ __launch_bounds__(kT) void k_gm_update_x(GmBatch B, const double* __restrict__ V,
                                                     double* __restrict__ x) {
   __shared__ double ys[kGmMaxVec];
-  const int k = st->steps;
+  const Seg g = seg_of(B);
+  const size_t L = g.L;
+  V += g.off;
+  x += g.off;
+  const GmHess* hz = B.hs + g.i;
+  const int k = B.st[g.i].steps;
   if (threadIdx.x == 0) {
-    const int m = st->m;
+    const int m = B.m;
     for (int i = k - 1; i >= 0; --i) {
-      double s = st->g[i];
-      for (int l = i + 1; l < k; ++l) s -= st->H[i * m + l] * ys[l];
-      ys[i] = s / st->H[i * m + i];
+      double s = hz->g[i];
+      for (int l = i + 1; l < k; ++l) s -= hz->H[i * m + l] * ys[l];
+      ys[i] = s / hz->H[i * m + i];
     }
   }
   __syncthreads();
@@ -238,75 +299,111 @@ __global__ __launch_bounds__(kT) void k_gm_update_x(const double* __restrict__ V
   chunk_of(L, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
     double acc = x[e];
-    for (int i = 0; i < k; ++i) acc += ys[i] * V[(size_t)i * L + e];
+    for (int i = 0; i < k; ++i) acc += ys[i] * V[(size_t)i * B.ldv + e];
     x[e] = acc;
   }
 }
 
-// partial squared norms of v (for k_gm_start)
-__global__ __launch_bounds__(kT) void k_gm_sumsq(const double* __restrict__ v, size_t L,
+// partial squared norms of v (for k_gm_start and the norms)
+__global__ __launch_bounds__(kT) void k_gm_sumsq(GmBatch B, const double* __restrict__ v,
                                                  double* __restrict__ partial) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
+  const Seg g = seg_of(B);
+  v += g.off;
   size_t lo, hi;
-  chunk_of(L, lo, hi);
-  double acc[kGmMaxVec];
-#pragma unroll
-  for (int i = 0; i < kGmMaxVec; ++i) acc[i] = 0.0;
+  chunk_of(g.L, lo, hi);
+  double acc[1] = {0.0};
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) acc[0] = fma(v[e], v[e], acc[0]);
-  const double r = block_sums(acc, 1, red);
-  if (threadIdx.x == 0) partial[blockIdx.x * kGmMaxVec] = r;
+  const double r = block_sums<1>(acc, 1, red);
+  if (threadIdx.x == 0) partial[g.i * kPart + blockIdx.x * kGmMaxVec] = r;
+}
+
+// out[instance] = sqrt(sum of its partials) (one block per instance)
+__global__ __launch_bounds__(kT) void k_gm_norms(GmBatch B, const double* __restrict__ partial,
+                                                 double* __restrict__ out) {
+  __shared__ double hs[1];
+  const Seg g = seg_of(B);
+  gather_partials(partial + g.i * kPart, 1, hs);
+  if (threadIdx.x == 0) out[g.i] = sqrt(hs[0]);
 }
 
 // r = b - w
-__global__ __launch_bounds__(kT) void k_gm_residual(const double* __restrict__ b,
+__global__ __launch_bounds__(kT) void k_gm_residual(GmBatch B, const double* __restrict__ b,
                                                     const double* __restrict__ w,
-                                                    double* __restrict__ r, size_t L) {
+                                                    double* __restrict__ r) {
+  const Seg g = seg_of(B);
   size_t lo, hi;
-  chunk_of(L, lo, hi);
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) r[e] = b[e] - w[e];
+  chunk_of(g.L, lo, hi);
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT) r[g.off + e] = b[g.off + e] - w[g.off + e];
 }
+
+// y = a x (+ y when accumulate)
+__global__ __launch_bounds__(kT) void k_gm_axpy(GmBatch B, double a, const double* __restrict__ x,
+                                                double* __restrict__ y, int accumulate) {
+  const Seg g = seg_of(B);
+  size_t lo, hi;
+  chunk_of(g.L, lo, hi);
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT)
+    y[g.off + e] = accumulate ? fma(a, x[g.off + e], y[g.off + e]) : a * x[g.off + e];
+}
+
+// x = 0
+__global__ __launch_bounds__(kT) void k_gm_zero(GmBatch B, double* __restrict__ x) {
+  const Seg g = seg_of(B);
+  size_t lo, hi;
+  chunk_of(g.L, lo, hi);
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT) x[g.off + e] = 0.0;
+}
+
+dim3 grid_of(const GmBatch& B) { return dim3(kGmBlocks, B.count); }
 
 }  // namespace
 
-void gm_init_state(GmState* st_dev, int m, int maxit, double rtol, hipStream_t s) {
-  GmState h{};
-  h.m = m;
-  h.maxit = maxit;
-  h.rtol = rtol;
-  (void)hipMemcpyAsync(st_dev, &h, sizeof(GmState), hipMemcpyHostToDevice, s);
+void launch_gm_init(const GmBatch& B, int maxit, double rtol, hipStream_t s) {
+  if (B.count > 0) k_gm_init<<<dim3(1, B.count), 64, 0, s>>>(B, maxit, rtol);
 }
-
-void launch_gm_sumsq(const double* v, size_t L, double* partial, hipStream_t s) {
-  k_gm_sumsq<<<kGmBlocks, kT, 0, s>>>(v, L, partial);
+void launch_gm_sumsq(const GmBatch& B, const double* v, double* partial, hipStream_t s) {
+  if (B.count > 0) k_gm_sumsq<<<grid_of(B), kT, 0, s>>>(B, v, partial);
 }
-void launch_gm_residual(const double* b, const double* w, double* r, size_t L, hipStream_t s) {
-  k_gm_residual<<<kGmBlocks, kT, 0, s>>>(b, w, r, L);
+void launch_gm_norms(const GmBatch& B, const double* v, double* partial, double* out, hipStream_t s) {
+  if (B.count <= 0) return;
+  k_gm_sumsq<<<grid_of(B), kT, 0, s>>>(B, v, partial);
+  k_gm_norms<<<dim3(1, B.count), kT, 0, s>>>(B, partial, out);
 }
-void launch_gm_start(double* V0, size_t L, const double* r, GmState* st, const double* partial,
-                     int first_cycle, hipStream_t s) {
-  k_gm_start<<<kGmBlocks, kT, 0, s>>>(V0, L, r, st, partial, first_cycle);
+void launch_gm_residual(const GmBatch& B, const double* b, const double* w, double* r, hipStream_t s) {
+  if (B.count > 0) k_gm_residual<<<grid_of(B), kT, 0, s>>>(B, b, w, r);
+}
+void launch_gm_axpy(const GmBatch& B, double a, const double* x, double* y, int accumulate, hipStream_t s) {
+  if (B.count > 0) k_gm_axpy<<<grid_of(B), kT, 0, s>>>(B, a, x, y, accumulate);
+}
+void launch_gm_zero(const GmBatch& B, double* x, hipStream_t s) {
+  if (B.count > 0) k_gm_zero<<<grid_of(B), kT, 0, s>>>(B, x);
+}
+void launch_gm_start(const GmBatch& B, double* V, const double* r, const double* partial, int first_cycle,
+                     hipStream_t s) {
+  if (B.count > 0) k_gm_start<<<grid_of(B), kT, 0, s>>>(B, V, r, partial, first_cycle);
 }
 template <int NB>
-void arnoldi_nb(const double* V, size_t L, int j, double* w, GmState* st, double* p1, double* p2,
-                hipStream_t s) {
+void arnoldi_nb(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, hipStream_t s) {
   const int nv = j + 1;
-  k_gm_dots<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1);
-  k_gm_update<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p1, 1, 0, p2, j);
-  k_gm_update<NB><<<kGmBlocks, kT, 0, s>>>(V, L, nv, w, st, p2, 0, 1, p1, j);
-  k_gm_normalize<<<kGmBlocks, kT, 0, s>>>(const_cast<double*>(V) + (size_t)(j + 1) * L, L, w, st, p1, j);
-  k_gm_givens<<<1, kT, 0, s>>>(st, j);
+  const dim3 gr = grid_of(B);
+  k_gm_dots<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1);
+  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1, 1, 0, p2, j);
+  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p2, 0, 1, p1, j);
+  k_gm_normalize<<<gr, kT, 0, s>>>(B, V, w, p1, j);
+  k_gm_givens<<<dim3(1, B.count), kT, 0, s>>>(B, j);
 }
-
-void launch_gm_arnoldi(const double* V, size_t L, int j, double* w, GmState* st, double* p1,
-                       double* p2, hipStream_t s) {
+void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2,
+                       hipStream_t s) {
+  if (B.count <= 0) return;
   const int nv = j + 1;
-  if (nv <= 8) arnoldi_nb<8>(V, L, j, w, st, p1, p2, s);
-  else if (nv <= 16) arnoldi_nb<16>(V, L, j, w, st, p1, p2, s);
-  else if (nv <= 32) arnoldi_nb<32>(V, L, j, w, st, p1, p2, s);
-  else arnoldi_nb<64>(V, L, j, w, st, p1, p2, s);
+  if (nv <= 8) arnoldi_nb<8>(B, V, j, w, p1, p2, s);
+  else if (nv <= 16) arnoldi_nb<16>(B, V, j, w, p1, p2, s);
+  else if (nv <= 32) arnoldi_nb<32>(B, V, j, w, p1, p2, s);
+  else arnoldi_nb<64>(B, V, j, w, p1, p2, s);
 }
-void launch_gm_update_x(const double* V, size_t L, GmState* st, double* x, hipStream_t s) {
-  k_gm_update_x<<<kGmBlocks, kT, 0, s>>>(V, L, st, x);
+void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s) {
+  if (B.count > 0) k_gm_update_x<<<grid_of(B), kT, 0, s>>>(B, V, x);
 }
 
 }  // namespace rsp

@@ -72,14 +72,16 @@ __device__ double tile_residual(const DevProblem& P, int s, int4 bx, int tx, int
   return block_sum(acc, red);
 }
 
-__global__ __launch_bounds__(kBlock) void k_restrict_halo(DevProblem P, const int4* __restrict__ box,
-                                                          const double* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_restrict_halo(Items I, const double* __restrict__ x,
                                                           double* __restrict__ tilex) {
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
   const int W = P.txm + 2, H = P.tym + 2;
   const size_t n = (size_t)P.nx * P.ny;
+  x += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * W * H; e += kBlock) {
     const int f = e / (W * H);
     const int r = e - f * W * H;
@@ -92,13 +94,15 @@ __global__ __launch_bounds__(kBlock) void k_restrict_halo(DevProblem P, const in
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_restrict(DevProblem P, const int4* __restrict__ box,
-                                                     const double* __restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_restrict(Items I, const double* __restrict__ x,
                                                      double* __restrict__ tiles) {
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
   const size_t n = (size_t)P.nx * P.ny;
+  x += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
     const int f = e / (P.txm * P.tym);
     const int r = e - f * P.txm * P.tym;
@@ -109,15 +113,17 @@ __global__ __launch_bounds__(kBlock) void k_restrict(DevProblem P, const int4* _
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_prolong(DevProblem P, const int4* __restrict__ box,
-                                                    const int4* __restrict__ core,
-                                                    const double* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_prolong(Items I, const double* __restrict__ tiles,
                                                     const double* __restrict__ d,
                                                     double* __restrict__ out) {
-  const int s = blockIdx.x;
-  const int4 bx = box[s], co = core[s];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 bx = I.box[s], co = I.core[s];
   const int cw = co.y - co.x, ch = co.w - co.z;
   const size_t n = (size_t)P.nx * P.ny;
+  out += 2 * P.noff;
+  if (d) d += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * cw * ch; e += kBlock) {
     const int f = e / (cw * ch);
     const int r = e - f * cw * ch;
@@ -129,8 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(DevProblem P, const int4* __
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_local_residual(DevProblem P, const int4* __restrict__ box,
-                                                           const double* __restrict__ tilex,
+__global__ __launch_bounds__(kBlock) void k_local_residual(Items I, const double* __restrict__ tilex,
                                                            const double* __restrict__ yd,
                                                            const double* __restrict__ f,
                                                            const double* __restrict__ c, double eps,
@@ -138,9 +143,11 @@ __global__ __launch_bounds__(kBlock) void k_local_residual(DevProblem P, const i
                                                            double* __restrict__ norms) {
   __shared__ double z[2 * kHalo * kHalo];
   __shared__ double red[kBlock];
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
   // zero the padding of the output tile
   for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
     const int fl = e / (P.txm * P.tym);
@@ -150,29 +157,33 @@ __global__ __launch_bounds__(kBlock) void k_local_residual(DevProblem P, const i
   }
   stage(P, s, tx, ty, tilex, c, nullptr, 0.0, z);
   __syncthreads();
-  const double ss = tile_residual(P, s, bx, tx, ty, z, yd, f, eps, out, red);
+  const double ss = tile_residual(P, s, bx, tx, ty, z, yd + P.noff, f ? f + P.noff : nullptr, eps,
+                                  out, red);
   if (threadIdx.x == 0) norms[s] = sqrt(ss);
 }
 
-__global__ __launch_bounds__(kBlock) void k_newton_init(DevProblem P, const int4* __restrict__ box,
-                                                        const double* __restrict__ tilex,
+// Algorithm 1 start at eps_0 = the instance's eps_start: c = 0, residual, threshold.
+__global__ __launch_bounds__(kBlock) void k_newton_init(Items I, const double* __restrict__ tilex,
                                                         const double* __restrict__ yd,
                                                         const double* __restrict__ f,
                                                         double* __restrict__ c, double* __restrict__ res,
-                                                        SubState* __restrict__ state, double eps0,
-                                                        double tol, int kmax) {
+                                                        SubState* __restrict__ state, double tol,
+                                                        int kmax) {
   __shared__ double z[2 * kHalo * kHalo];
   __shared__ double red[kBlock];
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
   for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
     c[(size_t)s * 2 * P.txm * P.tym + e] = 0.0;
     res[(size_t)s * 2 * P.txm * P.tym + e] = 0.0;
   }
   stage(P, s, tx, ty, tilex, nullptr, nullptr, 0.0, z);
   __syncthreads();
-  const double r = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, eps0, res, red));
+  const double eps0 = P.eps_start;
+  const double r = sqrt(tile_residual(P, s, bx, tx, ty, z, yd + P.noff, f + P.noff, eps0, res, red));
   if (threadIdx.x == 0) {
     SubState S;
     S.eps = eps0;
@@ -192,8 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_newton_init(DevProblem P, const int4
 // until |K_{eps_k}(c + alpha dir)| <= sigma |K_{eps_k}(c)| (a NaN trial is rejected),
 // then c += alpha dir, eps_{k+1} = max(gamma eps_k, eps_min), k += 1, new residual,
 // and the loop test of Algorithm 1 (with the eps_k = eps_min requirement).
-__global__ __launch_bounds__(kBlock) void k_linesearch(DevProblem P, const int4* __restrict__ box,
-                                                       const double* __restrict__ tilex,
+__global__ __launch_bounds__(kBlock) void k_linesearch(Items I, const double* __restrict__ tilex,
                                                        const double* __restrict__ yd,
                                                        const double* __restrict__ f,
                                                        double* __restrict__ c,
@@ -203,11 +213,15 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(DevProblem P, const int4*
                                                        double alpha_min, int kmax) {
   __shared__ double z[2 * kHalo * kHalo];
   __shared__ double red[kBlock];
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   SubState S = state[s];
   if (!S.active) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
+  yd += P.noff;
+  f += P.noff;
   double alpha = 1.0;
   for (;;) {
     stage(P, s, tx, ty, tilex, c, dir, alpha, z);
@@ -243,13 +257,15 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(DevProblem P, const int4*
   if (threadIdx.x == 0) state[s] = S;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ring_rhs(DevProblem P, const int4* __restrict__ box,
-                                                     const double* __restrict__ d,
+__global__ __launch_bounds__(kBlock) void k_ring_rhs(Items I, const double* __restrict__ d,
                                                      double* __restrict__ rhs) {
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   int tx, ty;
-  const int4 bx = tile_box(box, s, tx, ty);
+  const int4 bx = tile_box(I.box, s, tx, ty);
   const size_t n = (size_t)P.nx * P.ny;
+  d += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * P.txm * P.tym; e += kBlock) {
     const int f = e / (P.txm * P.tym);
     const int r = e - f * P.txm * P.tym;
@@ -269,38 +285,31 @@ __global__ __launch_bounds__(kBlock) void k_ring_rhs(DevProblem P, const int4* _
 
 }  // namespace
 
-void launch_restrict_halo(const DevProblem& P, const int4* box, const double* x, double* tilex,
-                          hipStream_t st) {
-  k_restrict_halo<<<P.S, kBlock, 0, st>>>(P, box, x, tilex);
+void launch_restrict_halo(const Items& I, const double* x, double* tilex, hipStream_t st) {
+  if (I.count > 0) k_restrict_halo<<<I.count, kBlock, 0, st>>>(I, x, tilex);
 }
-void launch_restrict(const DevProblem& P, const int4* box, const double* x, double* tiles,
-                     hipStream_t st) {
-  k_restrict<<<P.S, kBlock, 0, st>>>(P, box, x, tiles);
+void launch_restrict(const Items& I, const double* x, double* tiles, hipStream_t st) {
+  if (I.count > 0) k_restrict<<<I.count, kBlock, 0, st>>>(I, x, tiles);
 }
-void launch_prolong(const DevProblem& P, const int4* box, const int4* core, const double* tiles,
-                    const double* d, double* out, hipStream_t st) {
-  k_prolong<<<P.S, kBlock, 0, st>>>(P, box, core, tiles, d, out);
+void launch_prolong(const Items& I, const double* tiles, const double* d, double* out, hipStream_t st) {
+  if (I.count > 0) k_prolong<<<I.count, kBlock, 0, st>>>(I, tiles, d, out);
 }
-void launch_local_residual(const DevProblem& P, const int4* box, const double* tilex,
-                           const double* yd, const double* f, const double* c, double eps,
-                           double* out, double* norms, hipStream_t st) {
-  k_local_residual<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, eps, out, norms);
+void launch_local_residual(const Items& I, const double* tilex, const double* yd, const double* f,
+                           const double* c, double eps, double* out, double* norms, hipStream_t st) {
+  if (I.count > 0) k_local_residual<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, eps, out, norms);
 }
-void launch_newton_init(const DevProblem& P, const int4* box, const double* tilex,
-                        const double* yd, const double* f, double* c, double* res,
-                        SubState* state, double eps0, double tol, int kmax, hipStream_t st) {
-  k_newton_init<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, res, state, eps0, tol, kmax);
+void launch_newton_init(const Items& I, const double* tilex, const double* yd, const double* f,
+                        double* c, double* res, SubState* state, double tol, int kmax, hipStream_t st) {
+  if (I.count > 0) k_newton_init<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, res, state, tol, kmax);
 }
-void launch_linesearch(const DevProblem& P, const int4* box, const double* tilex,
-                       const double* yd, const double* f, double* c, const double* dir,
-                       double* res, SubState* state, double sigma, double alpha_min, int kmax,
-                       hipStream_t st) {
-  k_linesearch<<<P.S, kBlock, 0, st>>>(P, box, tilex, yd, f, c, dir, res, state, sigma,
-                                       alpha_min, kmax);
+void launch_linesearch(const Items& I, const double* tilex, const double* yd, const double* f,
+                       double* c, const double* dir, double* res, SubState* state, double sigma,
+                       double alpha_min, int kmax, hipStream_t st) {
+  if (I.count > 0)
+    k_linesearch<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, dir, res, state, sigma, alpha_min, kmax);
 }
-void launch_ring_rhs(const DevProblem& P, const int4* box, const double* d, double* rhs,
-                     hipStream_t st) {
-  k_ring_rhs<<<P.S, kBlock, 0, st>>>(P, box, d, rhs);
+void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t st) {
+  if (I.count > 0) k_ring_rhs<<<I.count, kBlock, 0, st>>>(I, d, rhs);
 }
 
 }  // namespace rsp

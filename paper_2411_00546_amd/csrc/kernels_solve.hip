@@ -201,6 +201,7 @@ template <int M>
 __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty,
                                          const double* __restrict__ d, double* gl) {
   const size_t n = (size_t)P.nx * P.ny;
+  d += 2 * P.noff;
   for (int e = threadIdx.x; e < ty * M; e += 4 * M) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
@@ -218,14 +219,15 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
 }
 
 template <typename TF, int M>
-__global__ __launch_bounds__(4 * M) void k_block_solve(DevProblem P, const int4* __restrict__ box,
-                                                       const TF* __restrict__ facT,
+__global__ __launch_bounds__(4 * M) void k_block_solve(Items I, const TF* __restrict__ facT,
                                                        const double* __restrict__ rhs,
                                                        double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
-  const int s = blockIdx.x;
-  const int4 bx = box[s];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 bx = I.box[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   tile_to_lines<M>(P, s, tx, ty, rhs, 1.0, gl);
@@ -237,16 +239,17 @@ __global__ __launch_bounds__(4 * M) void k_block_solve(DevProblem P, const int4*
 
 // Backward sweep after the factorisation kernel's fused forward sweep (g in gout).
 template <typename TF, int M>
-__global__ __launch_bounds__(4 * M) void k_solve_bwd(DevProblem P, const int4* __restrict__ box,
-                                                     const SubState* __restrict__ state,
+__global__ __launch_bounds__(4 * M) void k_solve_bwd(Items I, const SubState* __restrict__ state,
                                                      const TF* __restrict__ facT,
                                                      const double* __restrict__ g,
                                                      double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   if (state && !state[s].active) return;
-  const int4 bx = box[s];
+  const int4 bx = I.box[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] = g[(size_t)s * P.tym * M + e];
@@ -258,8 +261,7 @@ __global__ __launch_bounds__(4 * M) void k_solve_bwd(DevProblem P, const int4* _
 // nref refinement steps of the Newton direction of Algorithm 1:
 // dir <- dir + F^{-1}(-K - J dir) with J at the subdomain's current c and eps_k.
 template <typename TF, int M>
-__global__ __launch_bounds__(4 * M) void k_newton_refine(DevProblem P, const int4* __restrict__ box,
-                                                         const double* __restrict__ tilex,
+__global__ __launch_bounds__(4 * M) void k_newton_refine(Items I, const double* __restrict__ tilex,
                                                          const double* __restrict__ c,
                                                          const SubState* __restrict__ state,
                                                          const TF* __restrict__ facT,
@@ -268,10 +270,12 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(DevProblem P, const int
   __shared__ double gl[kMaxTile * M];
   __shared__ double rb[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
-  const int s = blockIdx.x;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   if (!state[s].active) return;
   const double eps = state[s].eps;
-  const int4 bx = box[s];
+  const int4 bx = I.box[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   tile_to_lines<M>(P, s, tx, ty, dir, 1.0, gl);
@@ -291,24 +295,21 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(DevProblem P, const int
 // Algorithm 4 for one subdomain, fused: right-hand side from the values of d just
 // outside the tile, both sweeps (plus nref FP64 refinement steps with J_i at
 // x^(i) = R_i x + c, eps_min), and out = -d + z on the non-overlapping box (every
-// global node is written by exactly one subdomain).  skip (nullable): do nothing
-// when *skip != 0.
+// global node is written by exactly one subdomain).
 template <typename TF, int M, bool REF>
-__global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* __restrict__ box,
-                                                     const int4* __restrict__ core,
-                                                     const TF* __restrict__ facT,
+__global__ __launch_bounds__(4 * M) void k_jac_apply(Items I, const TF* __restrict__ facT,
                                                      const double* __restrict__ tilex,
                                                      const double* __restrict__ c,
                                                      const double* __restrict__ d,
-                                                     double* __restrict__ out,
-                                                     const int* __restrict__ skip, int nref) {
+                                                     double* __restrict__ out, int nref) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
   __shared__ double rb[REF ? kMaxTile * M : 1];
-  if (skip && *skip) return;
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   if (!REF) nref = 0;
-  const int s = blockIdx.x;
-  const int4 bx = box[s], co = core[s];
+  const int4 bx = I.box[s], co = I.core[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const int jcore = co.z - bx.z;
   ring_rhs<M>(P, bx, tx, ty, d, gl);
@@ -328,6 +329,8 @@ __global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* _
   }
   const size_t n = (size_t)P.nx * P.ny;
   const int cw = co.y - co.x, ch = co.w - co.z;
+  d += 2 * P.noff;
+  out += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * cw * ch; e += 4 * M) {
     const int f = e / (cw * ch);
     const int r = e - f * cw * ch;
@@ -351,70 +354,71 @@ __global__ __launch_bounds__(4 * M) void k_jac_apply(DevProblem P, const int4* _
 
 }  // namespace
 
-void launch_solve_bwd(const DevProblem& P, const int4* box, const SubState* state, const void* facT,
-                      int fp32, const double* g, double* out, hipStream_t st) {
+void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
+                      const double* g, double* out, hipStream_t st) {
+  if (I.count <= 0) return;
   if (fp32) {
-#define RSP_CALL(MM) k_solve_bwd<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, state, (const float*)facT, g, out)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+#define RSP_CALL(MM) k_solve_bwd<float, MM><<<I.count, 4 * MM, 0, st>>>(I, state, (const float*)facT, g, out)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
-#define RSP_CALL(MM) k_solve_bwd<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, state, (const double*)facT, g, out)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+#define RSP_CALL(MM) k_solve_bwd<double, MM><<<I.count, 4 * MM, 0, st>>>(I, state, (const double*)facT, g, out)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
 }
 
-void launch_newton_refine(const DevProblem& P, const int4* box, const double* tilex, const double* c,
+void launch_newton_refine(const Items& I, int M, const double* tilex, const double* c,
                           const SubState* state, const void* facT, int fp32, const double* res,
                           double* dir, int nref, hipStream_t st) {
-  if (nref <= 0) return;
+  if (nref <= 0 || I.count <= 0) return;
   if (fp32) {
 #define RSP_CALL(MM) \
-  k_newton_refine<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, tilex, c, state, (const float*)facT, res, dir, nref)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+  k_newton_refine<float, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, (const float*)facT, res, dir, nref)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM) \
-  k_newton_refine<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, tilex, c, state, (const double*)facT, res, dir, nref)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+  k_newton_refine<double, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, (const double*)facT, res, dir, nref)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
 }
 
-void launch_block_solve(const DevProblem& P, const int4* box, const void* facT, int fp32,
-                        const double* rhs, double* out, hipStream_t st) {
+void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const double* rhs, double* out,
+                        hipStream_t st) {
+  if (I.count <= 0) return;
   if (fp32) {
-#define RSP_CALL(MM) k_block_solve<float, MM><<<P.S, 4 * MM, 0, st>>>(P, box, (const float*)facT, rhs, out)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+#define RSP_CALL(MM) k_block_solve<float, MM><<<I.count, 4 * MM, 0, st>>>(I, (const float*)facT, rhs, out)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
-#define RSP_CALL(MM) k_block_solve<double, MM><<<P.S, 4 * MM, 0, st>>>(P, box, (const double*)facT, rhs, out)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+#define RSP_CALL(MM) k_block_solve<double, MM><<<I.count, 4 * MM, 0, st>>>(I, (const double*)facT, rhs, out)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
 }
 
-void launch_jac_apply(const DevProblem& P, const int4* box, const int4* core, const void* facT, int fp32,
-                      const double* tilex, const double* c, const double* d, double* out,
-                      const int* skip, int nref, hipStream_t st) {
-#define RSP_APPLY(TT, REFB, MM)                                                                      \
-  k_jac_apply<TT, MM, REFB><<<P.S, 4 * MM, 0, st>>>(P, box, core, (const TT*)facT, tilex, c, d, out, skip, \
-                                                    nref)
+void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
+                      const double* c, const double* d, double* out, int nref, hipStream_t st) {
+  if (I.count <= 0) return;
+#define RSP_APPLY(TT, REFB, MM) \
+  k_jac_apply<TT, MM, REFB><<<I.count, 4 * MM, 0, st>>>(I, (const TT*)facT, tilex, c, d, out, nref)
   if (fp32 && nref > 0) {
 #define RSP_CALL(MM) RSP_APPLY(float, true, MM)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else if (fp32) {
 #define RSP_CALL(MM) RSP_APPLY(float, false, MM)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else if (nref > 0) {
 #define RSP_CALL(MM) RSP_APPLY(double, true, MM)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM) RSP_APPLY(double, false, MM)
-    RSP_DISPATCH_M(P.M, RSP_CALL)
+    RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
 #undef RSP_APPLY

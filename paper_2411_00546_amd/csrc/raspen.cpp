@@ -1,29 +1,41 @@
-// Host side of the RASPEN library: C ABI, context and workspace, the partition of
-// Section 4.2, and the drivers of Algorithms 1-4 (local Newton loop, evaluation
-// of the RASPEN residual, Jacobian action, outer Newton-GMRES).  All arithmetic
-// of the method runs in the HIP kernels; the host only sequences launches,
-// reads back per-subdomain / per-iteration scalars and does the Givens updates
-// of GMRES on the (restart+1) x restart Hessenberg matrix.
-#include "raspen.h"
+// Host side of the RASPEN library: C ABI, the batch engine and its memory layout,
+// the partition of Section 4.2, and the drivers of Algorithms 1-4 (local Newton
+// loop, evaluation of the RASPEN residual, Jacobian action, outer Newton-GMRES).
+// All arithmetic of the method runs in the HIP kernels; the host sequences the
+// launches and reads back per-subdomain and per-instance scalars.
+//
+// Memory of a context: a global arena with the instances' persistent arrays
+// (y_d, f, x; two of them, so that a new layout can take over the state of the
+// instances of the old one) and a work arena with everything an outer iteration
+// rebuilds (tiles, line factors, Krylov bases, per-item and per-instance tables).
+#include "engine.h"
 
 #include <algorithm>
-#include <cstddef>
-#include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "rsp_kernels.h"
-
 using rsp::DevProblem;
+using rsp::GmBatch;
+using rsp::GmHess;
+using rsp::GmSeg;
+using rsp::GmState;
+using rsp::Inst;
+using rsp::Items;
+using rsp::Partition;
 using rsp::SubState;
+using rsp::fail;
+using rsp::Clock;
+
+namespace rsp {
 
 namespace {
-
 thread_local std::string g_err;
+}
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -34,6 +46,10 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
+
+const char* last_error() { return g_err.c_str(); }
+
+}  // namespace rsp
 
 #define HIPCHK(expr)                                                              \
   do {                                                                            \
@@ -47,12 +63,10 @@ int fail(int code, const char* fmt, ...) {
     if (r_ < 0) return r_;  \
   } while (0)
 
-constexpr int kMaxRestart = 64;
+namespace {
 
-struct Partition {
-  int S = 0, txm = 0, tym = 0;
-  std::vector<int4> box, core;   // (x0, x1, y0, y1) half-open
-};
+constexpr int kMaxRestart = rsp::kGmMaxRestart;
+constexpr long long kAlignN = 32;   // instance offsets in the batch arrays: multiples of 32 nodes
 
 int split_1d(int n, int s, std::vector<std::pair<int, int>>* out) {
   if (s < 1 || s > n) return fail(RSP_EINVAL, "need 1 <= subdomains (%d) <= nodes (%d)", s, n);
@@ -77,6 +91,12 @@ int validate_problem(const rsp_problem* p) {
   if (p->overlap < 0) return fail(RSP_EINVAL, "overlap must be >= 0");
   return 0;
 }
+
+int line_block(int txm) { return ((2 * txm + 15) / 16) * 16; }
+
+}  // namespace
+
+namespace rsp {
 
 int validate_options(const rsp_options* o) {
   if (!o) return fail(RSP_EINVAL, "options are NULL");
@@ -111,67 +131,127 @@ int make_partition(const rsp_problem* p, Partition* out) {
       out->tym = std::max(out->tym, b.w - b.z);
     }
   out->S = (int)out->box.size();
-  if (out->txm > rsp::kMaxTile)
-    return fail(RSP_EINVAL, "tile width %d exceeds the supported %d nodes", out->txm, rsp::kMaxTile);
-  if (out->tym > rsp::kMaxTile)
-    return fail(RSP_EINVAL, "tile height %d exceeds the supported %d nodes", out->tym, rsp::kMaxTile);
+  if (out->txm > kMaxTile)
+    return fail(RSP_EINVAL, "tile width %d exceeds the supported %d nodes", out->txm, kMaxTile);
+  if (out->tym > kMaxTile)
+    return fail(RSP_EINVAL, "tile height %d exceeds the supported %d nodes", out->tym, kMaxTile);
   return 0;
 }
 
-int line_block(int txm) { return ((2 * txm + 15) / 16) * 16; }
-
-DevProblem make_dev(const rsp_problem* p, const Partition& part) {
-  DevProblem P;
-  P.nx = p->nx;
-  P.ny = p->ny;
-  P.phi = p->phi_kind;
-  P.kappa = p->kappa;
-  P.nu = p->nu;
-  P.inv_nu = 1.0 / p->nu;
-  P.mu = p->mu;
-  const double hx = 1.0 / (p->nx + 1), hy = 1.0 / (p->ny + 1);
-  P.hx2i = 1.0 / (hx * hx);
-  P.hy2i = 1.0 / (hy * hy);
-  P.diag0 = 2.0 * P.hx2i + 2.0 * P.hy2i;
-  P.eps_min = p->eps_min;
-  P.gamma = p->gamma;
-  P.S = part.S;
-  P.txm = part.txm;
-  P.tym = part.tym;
-  P.M = line_block(part.txm);
-  return P;
+int inst_init(Inst* in, const rsp_problem* prob) {
+  Partition part;
+  RSPCHK(make_partition(prob, &part));
+  *in = Inst{};
+  in->prob = *prob;
+  in->part = std::move(part);
+  in->n = (size_t)prob->nx * prob->ny;
+  in->t0 = Clock::now();
+  return 0;
 }
 
-// Sizes (in doubles unless noted) of every workspace buffer.
-struct Layout {
-  size_t n, L, tile, halo, fac, g, V, partial, gpart;
-  size_t fac_elem;   // bytes per stored factor entry (8 FP64, 4 FP32)
-  size_t bytes() const {
-    return 8 * (2 * n /*yd,f*/ + 2 * L /*x,F*/ + halo + 5 * tile /*c,dir,res,t1,t2*/ + g +
-                V + 4 * L /*w, b, dx, r*/ + partial + 4 * 80 /*h bufs*/ + 2 * gpart) +
-           fac_elem * fac + sizeof(rsp::GmState);
+}  // namespace rsp
+
+namespace {
+
+// Tile geometry and sizes of a layout.
+struct Geometry {
+  int ninst = 0, S = 0, txm = 0, tym = 0, M = 0;
+  long long ntot = 0;   // nodes of the concatenated [ny][nx] arrays (instances 32-aligned)
+};
+
+// Carves 256-byte aligned buffers; with base == nullptr it only counts the bytes,
+// so sizing and carving can never disagree.
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    const size_t o = off;
+    off += (count * sizeof(T) + 255) / 256 * 256;
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
   }
 };
 
-Layout make_layout(const DevProblem& P, const rsp_options* o) {
-  Layout l;
-  l.n = (size_t)P.nx * P.ny;
-  l.L = 2 * l.n;
-  l.tile = (size_t)P.S * 2 * P.txm * P.tym;
-  l.halo = (size_t)P.S * 2 * (P.txm + 2) * (P.tym + 2);
-  l.fac = (size_t)P.S * P.tym * P.M * P.M;
-  l.g = (size_t)P.S * P.tym * P.M;
-  l.V = (size_t)(o->gmres_restart + 1) * l.L;
-  l.partial = (size_t)rsp::multidot_blocks(l.L) * 72;
-  l.gpart = (size_t)rsp::kGmBlocks * rsp::kGmMaxVec;
-  l.fac_elem = o->precision == RSP_FP32_REFINED ? 4 : 8;
-  return l;
+enum { kLEval, kLGo, kLCyc, kLFin, kLists };
+
+// Buffers of the work arena.
+struct Work {
+  DevProblem* prob = nullptr;   // [ninst]
+  GmSeg* seg = nullptr;         // [ninst]
+  GmState* gst = nullptr;       // [ninst]
+  GmHess* ghs = nullptr;        // [ninst]
+  double* norms = nullptr;      // [ninst]
+  int* ilist[kLists] = {};      // [ninst] instance lists
+  int4 *box = nullptr, *core = nullptr;   // [S]
+  int* inst = nullptr;                    // [S]
+  SubState* state = nullptr;              // [S]
+  int* list[kLists] = {};                 // [S] item lists
+  double *F = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr, *r = nullptr;   // [2 ntot]
+  double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
+  void* fac = nullptr;
+  double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr;
+};
+
+void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x) {
+  *yd = cv.take<double>(g.ntot);
+  *f = cv.take<double>(g.ntot);
+  *x = cv.take<double>(2 * g.ntot);
 }
 
-constexpr size_t kBuffers = 28;   // buffers carved from the workspace, each 256-byte aligned
+void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
+  const size_t S = g.S, ni = g.ninst, L = 2 * (size_t)g.ntot;
+  const size_t tile = S * 2 * g.txm * g.tym, halo = S * 2 * (g.txm + 2) * (g.tym + 2);
+  const size_t fe = o.precision == RSP_FP32_REFINED ? 4 : 8;
+  const size_t part = ni * rsp::kGmBlocks * rsp::kGmMaxVec;
+  w->prob = cv.take<DevProblem>(ni);
+  w->seg = cv.take<GmSeg>(ni);
+  w->gst = cv.take<GmState>(ni);
+  w->ghs = cv.take<GmHess>(ni);
+  w->norms = cv.take<double>(ni);
+  for (auto& l : w->ilist) l = cv.take<int>(ni);
+  w->box = cv.take<int4>(S);
+  w->core = cv.take<int4>(S);
+  w->inst = cv.take<int>(S);
+  w->state = cv.take<SubState>(S);
+  for (auto& l : w->list) l = cv.take<int>(S);
+  w->F = cv.take<double>(L);
+  w->w = cv.take<double>(L);
+  w->b = cv.take<double>(L);
+  w->dx = cv.take<double>(L);
+  w->r = cv.take<double>(L);
+  w->tilex = cv.take<double>(halo);
+  w->c = cv.take<double>(tile);
+  w->dir = cv.take<double>(tile);
+  w->res = cv.take<double>(tile);
+  w->t1 = cv.take<double>(tile);
+  w->t2 = cv.take<double>(tile);
+  w->fac = cv.take<char>(fe * S * g.tym * g.M * g.M);
+  w->g = cv.take<double>(S * g.tym * g.M);
+  w->V = cv.take<double>((size_t)(o.gmres_restart + 1) * L);
+  w->p1 = cv.take<double>(part);
+  w->p2 = cv.take<double>(part);
+}
 
-size_t layout_bytes(const Layout& l, int S) {
-  return l.bytes() + S * (sizeof(int4) * 2 + sizeof(SubState)) + kBuffers * 256;
+Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns) {
+  Geometry g;
+  g.ninst = (int)parts.size();
+  for (size_t q = 0; q < parts.size(); ++q) {
+    g.S += parts[q]->S;
+    g.txm = std::max(g.txm, parts[q]->txm);
+    g.tym = std::max(g.tym, parts[q]->tym);
+    g.ntot += ((long long)ns[q] + kAlignN - 1) / kAlignN * kAlignN;
+  }
+  g.M = line_block(g.txm);
+  return g;
+}
+
+size_t layout_bytes(const Geometry& g, const rsp_options& o) {
+  Carve a, b;
+  double *yd, *f, *x;
+  Work w;
+  carve_global(a, g, &yd, &f, &x);
+  carve_work(b, g, o, &w);
+  return a.off + b.off;
 }
 
 // Kernel timing: HIP events around launches, resolved at synchronisation points.
@@ -194,43 +274,37 @@ struct Pending {
 struct rsp_context {
   int device = 0;
   size_t budget = 0;
-  bool ready = false;
-  rsp_problem prob{};
   rsp_options opts{};
-  Partition part;
-  DevProblem P{};
-  Layout lay{};
-  void* mem = nullptr;
-  size_t mem_bytes = 0;
-  int4* box = nullptr;
-  int4* core = nullptr;
-  SubState* state = nullptr;
-  double *yd = nullptr, *f = nullptr, *x = nullptr, *F = nullptr, *tilex = nullptr;
-  double *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
-  void* fac = nullptr;
-  double *g = nullptr, *V = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr;
-  double *partial = nullptr, *hbuf = nullptr, *r = nullptr, *gp1 = nullptr, *gp2 = nullptr;
-  rsp::GmState* gst = nullptr;
+  Geometry geo;
+  // global arenas (the current one holds the placed instances' y_d, f, x)
+  void* gmem[2] = {nullptr, nullptr};
+  size_t gcap[2] = {0, 0};
+  int gcur = 0;
+  double *yd = nullptr, *f = nullptr, *x = nullptr;
+  // work arena (capacity grows)
+  void* wmem = nullptr;
+  size_t wcap = 0;
+  Work w;
   int fp32 = 0;       // FP32 line factors (mixed precision)
   int nref = 0;       // FP64 refinement steps per local solve with FP32 factors
+  // host mirrors
+  std::vector<DevProblem> hprob;
+  std::vector<GmSeg> hseg;
   std::vector<SubState> hstate;
+  std::vector<GmState> hgm;
+  std::vector<double> hnorm;
+  std::vector<int> hlist[kLists], hilist[kLists];
+  // the instance bound by rsp_setup / rsp_solve for the single-problem calls
+  Inst single;
+  bool ready = false;
   // kernel timing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   rsp_kernel_stat kstat[KID_N]{};
-  // counters of the current solve
-  int64_t n_factor = 0, n_solve = 0, n_gmres = 0, n_newton = 0, n_apply = 0;
-  double flops = 0;
-  int64_t eval_inner_sum = 0;
 };
 
 namespace {
-
-struct EvalStats {
-  int status = 0, inner_min = 0, inner_max = 0, backtracks = 0;
-  double inner_avg = 0;
-};
 
 int resolve_events(rsp_context* ctx) {
   for (auto& p : ctx->pending) {
@@ -285,22 +359,28 @@ struct Timed {
 struct SubWork {
   double factor_fl = 0, factor_by = 0, bwd_fl = 0, bwd_by = 0, solve_fl = 0, solve_by = 0;
   double tile_by = 0, halo_by = 0;
+  void add(int4 b, double fe) {
+    const double tx = b.y - b.x, ty = b.w - b.z, m = 2 * tx;
+    factor_fl += 16.0 * ty * tx * tx * tx;           // ty Gauss-Jordan inversions of m x m
+    factor_by += fe * ty * m * m;                    // the inverses written once
+    bwd_fl += 2.0 * (ty - 1) * m * m;
+    bwd_by += fe * (ty - 1) * m * m;
+    solve_fl += 2.0 * (2 * ty - 1) * m * m;          // forward + backward sweeps
+    solve_by += fe * (2 * ty - 1) * m * m + 8.0 * 2 * m * ty;
+    tile_by += 8.0 * m * ty;
+    halo_by += 8.0 * 2 * (tx + 2) * (ty + 2);
+  }
 };
 
-SubWork sub_work(const std::vector<int4>& boxes, const std::vector<SubState>* state, double fe = 8.0) {
+// Work of the items in `items` (optionally only the active ones).
+SubWork sub_work(const rsp_context* ctx, const std::vector<Inst*>& set, bool active_only) {
   SubWork w;
-  for (size_t s = 0; s < boxes.size(); ++s) {
-    if (state && !(*state)[s].active) continue;
-    const double tx = boxes[s].y - boxes[s].x, ty = boxes[s].w - boxes[s].z, m = 2 * tx;
-    w.factor_fl += 16.0 * ty * tx * tx * tx;           // ty Gauss-Jordan inversions of m x m
-    w.factor_by += fe * ty * m * m;                    // the inverses written once
-    w.bwd_fl += 2.0 * (ty - 1) * m * m;
-    w.bwd_by += fe * (ty - 1) * m * m;
-    w.solve_fl += 2.0 * (2 * ty - 1) * m * m;          // forward + backward sweeps
-    w.solve_by += fe * (2 * ty - 1) * m * m + 8.0 * 2 * m * ty;
-    w.tile_by += 8.0 * m * ty;
-    w.halo_by += 8.0 * 2 * (tx + 2) * (ty + 2);
-  }
+  const double fe = ctx->fp32 ? 4.0 : 8.0;
+  for (const Inst* in : set)
+    for (int q = 0; q < in->part.S; ++q) {
+      if (active_only && !ctx->hstate[in->sub0 + q].active) continue;
+      w.add(in->part.box[q], fe);
+    }
   return w;
 }
 
@@ -315,243 +395,584 @@ int continuation_steps(double eps0, double eps_min, double gamma) {
   return k;
 }
 
-// Algorithm 3 on the device: local Newton solves (Algorithm 1) for every subdomain,
-// factorisation at x^(i), and the assembly F(x) = sum_i P~_i C_i(x) into `out`.
-int run_eval(rsp_context* ctx, const double* x, bool continuation, double* out, EvalStats* es,
-             hipStream_t st) {
-  const DevProblem& P = ctx->P;
-  const rsp_problem& pr = ctx->prob;
+Items items_of(const rsp_context* ctx, const int* list, int count) {
+  Items I;
+  I.prob = ctx->w.prob;
+  I.inst = ctx->w.inst;
+  I.box = ctx->w.box;
+  I.core = ctx->w.core;
+  I.list = list;
+  I.skip = nullptr;
+  I.skip_stride = 0;
+  I.count = count;
+  return I;
+}
+
+Items all_items(const rsp_context* ctx) { return items_of(ctx, nullptr, ctx->geo.S); }
+
+GmBatch gm_of(const rsp_context* ctx, const int* list, int count) {
+  GmBatch B;
+  B.seg = ctx->w.seg;
+  B.st = ctx->w.gst;
+  B.hs = ctx->w.ghs;
+  B.list = list;
+  B.ldv = 2 * ctx->geo.ntot;
+  B.count = count;
+  B.m = ctx->opts.gmres_restart;
+  return B;
+}
+
+// Uploads the item list and the instance list of `set` into list slot `l`.
+int upload_lists(rsp_context* ctx, int l, const std::vector<Inst*>& set, hipStream_t st) {
+  auto& it = ctx->hlist[l];
+  auto& il = ctx->hilist[l];
+  it.clear();
+  il.clear();
+  for (const Inst* in : set) {
+    il.push_back(in->slot);
+    for (int q = 0; q < in->part.S; ++q) it.push_back(in->sub0 + q);
+  }
+  if (!it.empty())
+    HIPCHK(hipMemcpyAsync(ctx->w.list[l], it.data(), sizeof(int) * it.size(), hipMemcpyHostToDevice, st));
+  if (!il.empty())
+    HIPCHK(hipMemcpyAsync(ctx->w.ilist[l], il.data(), sizeof(int) * il.size(), hipMemcpyHostToDevice, st));
+  return 0;
+}
+
+struct EvalStats {
+  int status = 0, inner_min = 0, inner_max = 0, backtracks = 0;
+  double inner_avg = 0;
+};
+
+// Algorithm 3 for the instances of `set` on the device: local Newton solves
+// (Algorithm 1) for their subdomains, factorisation at x^(i), and the assembly
+// F(x) = sum_i P~_i C_i(x) into `out`.  cont[q]: instance q starts its local
+// solves at eps0 (continuation), else at eps_min.  x, out: batch arrays.
+int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<char>& cont,
+             const double* x, double* out, std::vector<EvalStats>* es, hipStream_t st) {
   const rsp_options& o = ctx->opts;
-  const double eps0 = continuation ? pr.eps0 : pr.eps_min;
-  const double fe = (double)ctx->lay.fac_elem;
-  const SubWork all = sub_work(ctx->part.box, nullptr, fe);
+  const int M = ctx->geo.M;
+  int ncont = 0;
+  for (size_t q = 0; q < set.size(); ++q) {
+    const Inst* in = set[q];
+    DevProblem& P = ctx->hprob[in->slot];
+    P.eps_start = cont[q] ? in->prob.eps0 : in->prob.eps_min;
+    ncont = std::max(ncont, continuation_steps(P.eps_start, in->prob.eps_min, in->prob.gamma));
+  }
+  HIPCHK(hipMemcpyAsync(ctx->w.prob, ctx->hprob.data(), sizeof(DevProblem) * ctx->hprob.size(),
+                        hipMemcpyHostToDevice, st));
+  RSPCHK(upload_lists(ctx, kLEval, set, st));
+  const int count = (int)ctx->hlist[kLEval].size();
+  const Items I = items_of(ctx, ctx->w.list[kLEval], count);
+  const SubWork all = sub_work(ctx, set, false);
+  Work& w = ctx->w;
   {
     Timed t(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
-    rsp::launch_restrict_halo(P, ctx->box, x, ctx->tilex, st);
+    rsp::launch_restrict_halo(I, x, w.tilex, st);
   }
   {
     Timed t(ctx, KID_INIT, st, 40.0 * all.tile_by / 8, all.halo_by + 3 * all.tile_by);
-    rsp::launch_newton_init(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->res, ctx->state,
-                            eps0, o.tol_inner, o.max_inner, st);
+    rsp::launch_newton_init(I, w.tilex, ctx->yd, ctx->f, w.c, w.res, w.state, o.tol_inner, o.max_inner, st);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(ctx->hstate.data(), ctx->state, sizeof(SubState) * P.S,
-                        hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  const int ncont = continuation_steps(eps0, pr.eps_min, pr.gamma);
+  auto read_state = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(ctx->hstate.data(), w.state, sizeof(SubState) * ctx->hstate.size(),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+  };
+  auto count_active = [&]() {
+    int a = 0;
+    for (int s : ctx->hlist[kLEval]) a += ctx->hstate[s].active;
+    return a;
+  };
+  RSPCHK(read_state());
   int it = 0;
-  int active = 0;
-  for (auto& s : ctx->hstate) active += s.active;
+  int active = count_active();
   while (active && it < o.max_inner + 1) {
-    // every subdomain needs the continuation steps: run them without looking, then
-    // check after every step
+    // the continuation steps are needed by every subdomain that continues: run them
+    // without looking, then check after every step
     const int batch = std::max(1, std::min(ncont - it, o.max_inner + 1 - it));
-    const SubWork w = sub_work(ctx->part.box, &ctx->hstate, fe);
+    const SubWork sw = sub_work(ctx, set, true);
     for (int b = 0; b < batch; ++b) {
       {
-        Timed t(ctx, KID_FACTOR, st, w.factor_fl + w.bwd_fl / 2, w.factor_by);
-        rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, ctx->state, 0.0, ctx->res, -1.0,
-                           ctx->fac, ctx->fp32, ctx->g, st);
+        Timed t(ctx, KID_FACTOR, st, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
+        rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g, st);
       }
       {
-        Timed t(ctx, KID_SOLVE_BWD, st, w.bwd_fl, w.bwd_by);
-        rsp::launch_solve_bwd(P, ctx->box, ctx->state, ctx->fac, ctx->fp32, ctx->g, ctx->dir, st);
+        Timed t(ctx, KID_SOLVE_BWD, st, sw.bwd_fl, sw.bwd_by);
+        rsp::launch_solve_bwd(I, M, w.state, w.fac, ctx->fp32, w.g, w.dir, st);
       }
       if (ctx->nref > 0) {
-        Timed t(ctx, KID_REFINE, st, ctx->nref * (w.solve_fl + 20.0 * w.tile_by / 8),
-                ctx->nref * (w.solve_by + 2 * w.tile_by));
-        rsp::launch_newton_refine(P, ctx->box, ctx->tilex, ctx->c, ctx->state, ctx->fac, ctx->fp32,
-                                  ctx->res, ctx->dir, ctx->nref, st);
+        Timed t(ctx, KID_REFINE, st, ctx->nref * (sw.solve_fl + 20.0 * sw.tile_by / 8),
+                ctx->nref * (sw.solve_by + 2 * sw.tile_by));
+        rsp::launch_newton_refine(I, M, w.tilex, w.c, w.state, w.fac, ctx->fp32, w.res, w.dir, ctx->nref, st);
       }
       {
-        Timed t(ctx, KID_LINESEARCH, st, 40.0 * w.tile_by / 8, 6 * w.tile_by);
-        rsp::launch_linesearch(P, ctx->box, ctx->tilex, ctx->yd, ctx->f, ctx->c, ctx->dir, ctx->res,
-                               ctx->state, o.sigma, o.alpha_min, o.max_inner, st);
+        Timed t(ctx, KID_LINESEARCH, st, 40.0 * sw.tile_by / 8, 6 * sw.tile_by);
+        rsp::launch_linesearch(I, w.tilex, ctx->yd, ctx->f, w.c, w.dir, w.res, w.state, o.sigma,
+                               o.alpha_min, o.max_inner, st);
       }
     }
     HIPCHK(hipGetLastError());
     it += batch;
-    HIPCHK(hipMemcpyAsync(ctx->hstate.data(), ctx->state, sizeof(SubState) * P.S,
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    active = 0;
-    for (auto& s : ctx->hstate) active += s.active;
+    RSPCHK(read_state());
+    active = count_active();
   }
-  int64_t ksum = 0;
-  es->inner_min = 1 << 30;
-  es->inner_max = 0;
-  es->backtracks = 0;
-  es->status = 0;
-  double fl = 0;
-  for (int s = 0; s < P.S; ++s) {
-    const SubState& S = ctx->hstate[s];
-    ksum += S.k;
-    es->inner_min = std::min(es->inner_min, S.k);
-    es->inner_max = std::max(es->inner_max, S.k);
-    es->backtracks += S.backtracks;
-    es->status = std::max(es->status, S.status);
-    const double tx = ctx->part.box[s].y - ctx->part.box[s].x, ty = ctx->part.box[s].w - ctx->part.box[s].z;
-    fl += S.k * (16.0 * ty * tx * tx * tx + 2.0 * (2 * ty - 1) * 4 * tx * tx);
+  es->assign(set.size(), EvalStats{});
+  for (size_t q = 0; q < set.size(); ++q) {
+    Inst* in = set[q];
+    EvalStats& e = (*es)[q];
+    int64_t ksum = 0;
+    e.inner_min = 1 << 30;
+    double fl = 0, ffl = 0;
+    for (int j = 0; j < in->part.S; ++j) {
+      const SubState& S = ctx->hstate[in->sub0 + j];
+      ksum += S.k;
+      e.inner_min = std::min(e.inner_min, S.k);
+      e.inner_max = std::max(e.inner_max, S.k);
+      e.backtracks += S.backtracks;
+      e.status = std::max(e.status, S.status);
+      const int4 b = in->part.box[j];
+      const double tx = b.y - b.x, ty = b.w - b.z;
+      fl += S.k * (16.0 * ty * tx * tx * tx + 2.0 * (2 * ty - 1) * 4 * tx * tx);
+      ffl += 16.0 * ty * tx * tx * tx;
+    }
+    e.inner_avg = (double)ksum / in->part.S;
+    in->n_factor += ksum + in->part.S;
+    in->n_solve += ksum;
+    in->n_newton += ksum;
+    in->flops += fl + ffl;
   }
-  es->inner_avg = (double)ksum / P.S;
-  ctx->n_factor += ksum + P.S;
-  ctx->n_solve += ksum;
-  ctx->n_newton += ksum;
-  ctx->flops += fl + all.factor_fl;
   // factor at x^(i) = x + P_i C_i(x) for Algorithm 4
   {
     Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
-    rsp::launch_factor(P, ctx->box, ctx->tilex, ctx->c, nullptr, pr.eps_min, nullptr, 0.0, ctx->fac,
-                       ctx->fp32, ctx->g, st);
+    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, st);
   }
   {
-    Timed t(ctx, KID_PROLONG, st, 0, 8.0 * 2 * ctx->lay.L);
-    rsp::launch_prolong(P, ctx->box, ctx->core, ctx->c, nullptr, out, st);
+    Timed t(ctx, KID_PROLONG, st, 0, all.tile_by * 2);
+    rsp::launch_prolong(I, w.c, nullptr, out, st);
   }
   HIPCHK(hipGetLastError());
   return 0;
 }
 
-// Algorithm 4: out = -d + sum_i P~_i J_i^{-1} (hx^-2/hy^-2 weighted outside neighbours of d).
-int run_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st,
-                  const int* skip = nullptr) {
-  const DevProblem& P = ctx->P;
-  const SubWork w = sub_work(ctx->part.box, nullptr, (double)ctx->lay.fac_elem);
-  {
-    Timed t(ctx, KID_BLOCK_SOLVE, st, (1 + ctx->nref) * w.solve_fl,
-            (1 + ctx->nref) * w.solve_by + 8.0 * 2 * ctx->lay.L);
-    rsp::launch_jac_apply(P, ctx->box, ctx->core, ctx->fac, ctx->fp32, ctx->tilex, ctx->c, d, out, skip,
-                          ctx->nref, st);
-  }
-  ctx->n_solve += P.S;
-  ctx->n_apply += 1;
-  ctx->flops += w.solve_fl;
-  HIPCHK(hipGetLastError());
-  return 0;
+// Algorithm 4 for the items I: out = -d + sum_i P~_i J_i^{-1}(h^-2 weighted outside
+// neighbours of d) on their instances' segments.
+void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
+               hipStream_t st) {
+  Timed t(ctx, KID_BLOCK_SOLVE, st, (1 + ctx->nref) * sw.solve_fl,
+          (1 + ctx->nref) * sw.solve_by + 2 * sw.tile_by);
+  rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, out, ctx->nref, st);
 }
 
-// |v|_2 on the device, read back (synchronises).
-int dev_norm(rsp_context* ctx, const double* v, size_t L, double* out, hipStream_t st) {
-  const int nb = rsp::multidot_blocks(L);
-  rsp::launch_multidot(v, 0, 1, v, L, ctx->partial, st);
-  rsp::launch_reduce_partials(ctx->partial, nb, 1, ctx->hbuf + 3 * 80, 0, st);
-  double ss = 0;
-  HIPCHK(hipMemcpyAsync(&ss, ctx->hbuf + 3 * 80, sizeof(double), hipMemcpyDeviceToHost, st));
+// |v|_2 of every instance of `set` (list slot l must hold set), read back into hnorm.
+int read_norms(rsp_context* ctx, int l, int count, const double* v, hipStream_t st) {
+  const GmBatch B = gm_of(ctx, ctx->w.ilist[l], count);
+  rsp::launch_gm_norms(B, v, ctx->w.p1, ctx->w.norms, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->hnorm.data(), ctx->w.norms, sizeof(double) * ctx->hnorm.size(),
+                        hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  *out = std::sqrt(ss);
   return 0;
 }
 
-// Restarted GMRES(m), x_0 = 0, on the device (kernels_gmres.hip): solves F'(x) dx = b.
-// The host enqueues Arnoldi steps in chunks and reads the small state header back
-// once per chunk; a stop flag set on the device turns the rest of a chunk into
-// no-ops.  Returns RSP_GMRES_STAGNATION if max_gmres products did not reach rtol.
-int run_gmres(rsp_context* ctx, const double* b, double* xs, int* used_out, double* rel_out,
-              hipStream_t st) {
+int read_gm_headers(rsp_context* ctx, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(ctx->hgm.data(), ctx->w.gst, sizeof(GmState) * ctx->hgm.size(),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return 0;
+}
+
+// Restarted GMRES(m), x_0 = 0, on the device for every instance of `go` (list slot
+// kLGo must hold go): dx = F'(x)^{-1} b with b = -F.  All instances run their cycles
+// in lockstep (a finished one is skipped through its stop flag); the host enqueues
+// Arnoldi steps in chunks and reads the headers back once per chunk.
+int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
   constexpr int kChunk = 8;
-  const size_t L = ctx->lay.L;
-  const int m = ctx->opts.gmres_restart;
-  const double rtol = ctx->opts.gmres_rtol;
-  double* V = ctx->V;
-  rsp::GmState hs{};
-  const size_t hdr = offsetof(rsp::GmState, H);
-  rsp::gm_init_state(ctx->gst, m, ctx->opts.max_gmres, rtol, st);
-  HIPCHK(hipMemsetAsync(xs, 0, L * sizeof(double), st));
-  rsp::launch_gm_sumsq(b, L, ctx->gp1, st);
-  rsp::launch_gm_start(V, L, b, ctx->gst, ctx->gp1, 1, st);
+  const rsp_options& o = ctx->opts;
+  const int m = o.gmres_restart;
+  Work& w = ctx->w;
+  const size_t ldv = 2 * (size_t)ctx->geo.ntot;
+  const GmBatch Bgo = gm_of(ctx, w.ilist[kLGo], (int)go.size());
+  rsp::launch_gm_axpy(Bgo, -1.0, w.F, w.b, 0, st);
+  rsp::launch_gm_init(Bgo, o.max_gmres, o.gmres_rtol, st);
+  rsp::launch_gm_zero(Bgo, w.dx, st);
+  rsp::launch_gm_sumsq(Bgo, w.b, w.p1, st);
+  rsp::launch_gm_start(Bgo, w.V, w.b, w.p1, 1, st);
+  for (Inst* in : go) in->restarts = 0;
+  std::vector<Inst*> cyc = go;
+  int lslot = kLGo;
   for (;;) {
+    GmBatch B = gm_of(ctx, w.ilist[lslot], (int)cyc.size());
+    Items I = items_of(ctx, w.list[lslot], (int)ctx->hlist[lslot].size());
+    I.skip = &w.gst[0].done;
+    I.skip_stride = rsp::kGmDoneStride;
+    const SubWork sw = sub_work(ctx, cyc, false);
     for (int j = 0; j < m;) {
       const int chunk = std::min(kChunk, m - j);
       for (int c = 0; c < chunk; ++c, ++j) {
-        RSPCHK(run_jac_apply(ctx, V + (size_t)j * L, ctx->w, st, &ctx->gst->done));
-        Timed tm(ctx, KID_GMRES_ORTHO, st, (double)L * (8.0 * (j + 1) + 3), 8.0 * L * (4.0 * j + 13));
-        rsp::launch_gm_arnoldi(V, L, j, ctx->w, ctx->gst, ctx->gp1, ctx->gp2, st);
+        jac_apply(ctx, I, sw, w.V + (size_t)j * ldv, w.w, st);
+        double L = 0;
+        for (const Inst* in : cyc) L += 2.0 * in->n;
+        Timed tm(ctx, KID_GMRES_ORTHO, st, L * (8.0 * (j + 1) + 3), 8.0 * L * (4.0 * j + 13));
+        rsp::launch_gm_arnoldi(B, w.V, j, w.w, w.p1, w.p2, st);
       }
       HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(&hs, ctx->gst, hdr, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hs.done) break;
+      RSPCHK(read_gm_headers(ctx, st));
+      bool all = true;
+      for (const Inst* in : cyc) all = all && ctx->hgm[in->slot].done;
+      if (all) break;
     }
-    rsp::launch_gm_update_x(V, L, ctx->gst, xs, st);
-    if (!(hs.rel > rtol) || hs.used >= ctx->opts.max_gmres || hs.steps == 0) break;
-    // restart from r = b - F'(x) x
-    RSPCHK(run_jac_apply(ctx, xs, ctx->w, st));
-    rsp::launch_gm_residual(b, ctx->w, ctx->r, L, st);
-    rsp::launch_gm_sumsq(ctx->r, L, ctx->gp1, st);
-    rsp::launch_gm_start(V, L, ctx->r, ctx->gst, ctx->gp1, 0, st);
-    HIPCHK(hipMemcpyAsync(&hs, ctx->gst, hdr, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (hs.done) break;
+    rsp::launch_gm_update_x(B, w.V, w.dx, st);
+    // instances that restart from r = b - F'(x) x
+    std::vector<Inst*> next;
+    for (Inst* in : cyc) {
+      const GmState& h = ctx->hgm[in->slot];
+      if (h.rel > h.rtol && h.used < o.max_gmres && h.steps > 0) next.push_back(in);
+    }
+    if (next.empty()) break;
+    RSPCHK(upload_lists(ctx, kLCyc, next, st));
+    lslot = kLCyc;
+    const GmBatch Br = gm_of(ctx, w.ilist[kLCyc], (int)next.size());
+    const Items Ir = items_of(ctx, w.list[kLCyc], (int)ctx->hlist[kLCyc].size());
+    jac_apply(ctx, Ir, sub_work(ctx, next, false), w.dx, w.w, st);
+    rsp::launch_gm_residual(Br, w.b, w.w, w.r, st);
+    rsp::launch_gm_sumsq(Br, w.r, w.p1, st);
+    rsp::launch_gm_start(Br, w.V, w.r, w.p1, 0, st);
+    HIPCHK(hipGetLastError());
+    RSPCHK(read_gm_headers(ctx, st));
+    cyc.clear();
+    for (Inst* in : next) {
+      in->restarts += 1;
+      if (!ctx->hgm[in->slot].done) cyc.push_back(in);
+    }
+    if (cyc.empty()) break;
+    if (cyc.size() != next.size()) RSPCHK(upload_lists(ctx, kLCyc, cyc, st));
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
-  ctx->n_gmres += hs.used;
-  *used_out = hs.used;
-  *rel_out = hs.rel;
-  return hs.rel <= rtol ? 0 : RSP_GMRES_STAGNATION;
+  for (Inst* in : go) {
+    const GmState& h = ctx->hgm[in->slot];
+    in->gm_used = h.used;
+    in->gm_rel = h.rel;
+    in->n_gmres += h.used;
+    in->n_apply += h.used + in->restarts;
+    double sfl = 0;
+    for (int q = 0; q < in->part.S; ++q) {
+      const int4 b = in->part.box[q];
+      const double tx = b.y - b.x, ty = b.w - b.z;
+      sfl += 2.0 * (2 * ty - 1) * 4 * tx * tx;
+    }
+    in->n_solve += (int64_t)in->part.S * (h.used + in->restarts);
+    in->flops += sfl * (h.used + in->restarts);
+    if (!(h.rel <= h.rtol)) in->status = std::max(in->status, (int)RSP_GMRES_STAGNATION);
+  }
+  return 0;
 }
 
-int ensure_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts) {
-  RSPCHK(validate_options(opts));
-  Partition part;
-  RSPCHK(make_partition(prob, &part));
-  DevProblem P = make_dev(prob, part);
-  Layout lay = make_layout(P, opts);
-  const size_t bytes = layout_bytes(lay, P.S);
-  if (ctx->budget && bytes > ctx->budget)
-    return fail(RSP_ENOMEM, "workspace needs %zu bytes, budget is %zu", bytes, ctx->budget);
-  HIPCHK(hipSetDevice(ctx->device));
-  if (bytes > ctx->mem_bytes) {
-    if (ctx->mem) HIPCHK(hipFree(ctx->mem));
-    ctx->mem = nullptr;
-    ctx->mem_bytes = 0;
-    hipError_t e = hipMalloc(&ctx->mem, bytes);
-    if (e != hipSuccess) return fail(RSP_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-    ctx->mem_bytes = bytes;
+// Outputs of the instances that stopped: y, p, u = D_eps_min(p), the final global
+// residual norm and the history.
+int finish(rsp_context* ctx, const std::vector<Inst*>& fin, hipStream_t st) {
+  Work& w = ctx->w;
+  for (const Inst* in : fin) {
+    const DevProblem& P = ctx->hprob[in->slot];
+    const size_t n = in->n;
+    const double* xi = ctx->x + 2 * in->noff;
+    HIPCHK(hipMemcpyAsync(in->y, xi, 8 * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(in->p, xi + n, 8 * n, hipMemcpyDeviceToDevice, st));
+    rsp::launch_control(P, xi + n, in->prob.eps_min, in->u, st);
+    rsp::launch_global_residual(P, ctx->yd + in->noff, ctx->f + in->noff, xi, in->prob.eps_min,
+                                w.w + 2 * in->noff, st);
   }
-  char* p = (char*)ctx->mem;
-  auto take = [&](size_t nbytes) {
-    char* r = p;
-    p += (nbytes + 255) / 256 * 256;
-    return r;
-  };
-  ctx->box = (int4*)take(sizeof(int4) * P.S);
-  ctx->core = (int4*)take(sizeof(int4) * P.S);
-  ctx->state = (SubState*)take(sizeof(SubState) * P.S);
-  ctx->yd = (double*)take(8 * lay.n);
-  ctx->f = (double*)take(8 * lay.n);
-  ctx->x = (double*)take(8 * lay.L);
-  ctx->F = (double*)take(8 * lay.L);
-  ctx->tilex = (double*)take(8 * lay.halo);
-  ctx->c = (double*)take(8 * lay.tile);
-  ctx->dir = (double*)take(8 * lay.tile);
-  ctx->res = (double*)take(8 * lay.tile);
-  ctx->t1 = (double*)take(8 * lay.tile);
-  ctx->t2 = (double*)take(8 * lay.tile);
-  ctx->fac = (void*)take(lay.fac_elem * lay.fac);
-  ctx->g = (double*)take(8 * lay.g);
-  ctx->V = (double*)take(8 * lay.V);
-  ctx->w = (double*)take(8 * lay.L);
-  ctx->b = (double*)take(8 * lay.L);
-  ctx->dx = (double*)take(8 * lay.L);
-  ctx->partial = (double*)take(8 * lay.partial);
-  ctx->hbuf = (double*)take(8 * 4 * 80);
-  ctx->r = (double*)take(8 * lay.L);
-  ctx->gp1 = (double*)take(8 * lay.gpart);
-  ctx->gp2 = (double*)take(8 * lay.gpart);
-  ctx->gst = (rsp::GmState*)take(sizeof(rsp::GmState));
-  if ((size_t)(p - (char*)ctx->mem) > ctx->mem_bytes)
-    return fail(RSP_ENOMEM, "internal: workspace layout overflow");
-  ctx->prob = *prob;
-  ctx->opts = *opts;
-  ctx->part = part;
-  ctx->P = P;
-  ctx->lay = lay;
-  ctx->hstate.assign(P.S, SubState{});
-  ctx->fp32 = opts->precision == RSP_FP32_REFINED;
-  ctx->nref = ctx->fp32 ? opts->max_refine : 0;
-  ctx->ready = true;
+  HIPCHK(hipGetLastError());
+  RSPCHK(upload_lists(ctx, kLFin, fin, st));
+  RSPCHK(read_norms(ctx, kLFin, (int)fin.size(), w.w, st));
+  const auto now = Clock::now();
+  for (Inst* in : fin) {
+    rsp_history* h = &in->hist;
+    if (!(in->Fn <= in->thr) && in->status == 0) in->status = RSP_NOT_CONVERGED;
+    h->status = in->status;
+    h->outer = in->k;
+    h->subdomains = in->part.S;
+    h->factorizations = in->n_factor;
+    h->local_solves = in->n_solve;
+    h->gmres_total = in->n_gmres;
+    h->newton_iterations = in->n_newton;
+    h->jac_applies = in->n_apply;
+    h->residual_final = ctx->hnorm[in->slot];
+    h->flops = in->flops;
+    h->ms_eval = in->ms_eval;
+    h->ms_gmres = in->ms_gmres;
+    h->ms_total = std::chrono::duration<double, std::milli>(now - in->t0).count();
+    in->finished = true;
+  }
   return 0;
+}
+
+double ms_since(Clock::time_point a) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - a).count();
+}
+
+}  // namespace
+
+namespace rsp {
+
+size_t batch_bytes(const rsp_problem* const* probs, int count, const rsp_options& o) {
+  if (validate_options(&o) < 0 || count < 1) return 0;
+  std::vector<Partition> parts(count);
+  std::vector<const Partition*> pp;
+  std::vector<size_t> ns;
+  for (int q = 0; q < count; ++q) {
+    if (make_partition(probs[q], &parts[q]) < 0) return 0;
+    pp.push_back(&parts[q]);
+    ns.push_back((size_t)probs[q]->nx * probs[q]->ny);
+  }
+  return layout_bytes(geometry_of(pp, ns), o);
+}
+
+int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*>& live, hipStream_t st) {
+  RSPCHK(validate_options(&o));
+  if (live.empty()) return fail(RSP_EINVAL, "no instance to place");
+  std::vector<const Partition*> pp;
+  std::vector<size_t> ns;
+  for (const Inst* in : live) {
+    pp.push_back(&in->part);
+    ns.push_back(in->n);
+  }
+  const Geometry g = geometry_of(pp, ns);
+  Carve cg, cw;
+  double *yd, *f, *x;
+  Work w;
+  carve_global(cg, g, &yd, &f, &x);
+  carve_work(cw, g, o, &w);
+  if (ctx->budget && cg.off + cw.off > ctx->budget)
+    return fail(RSP_ENOMEM, "workspace needs %zu bytes, budget is %zu", cg.off + cw.off, ctx->budget);
+  HIPCHK(hipSetDevice(ctx->device));
+  bool migrate = false;
+  for (const Inst* in : live) migrate = migrate || in->placed;
+  const int tgt = migrate ? 1 - ctx->gcur : ctx->gcur;
+  if (ctx->gcap[tgt] < cg.off) {
+    if (ctx->gmem[tgt]) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipFree(ctx->gmem[tgt]));
+    }
+    ctx->gmem[tgt] = nullptr;
+    ctx->gcap[tgt] = 0;
+    hipError_t e = hipMalloc(&ctx->gmem[tgt], cg.off);
+    if (e != hipSuccess) return fail(RSP_ENOMEM, "hipMalloc(%zu): %s", cg.off, hipGetErrorString(e));
+    ctx->gcap[tgt] = cg.off;
+  }
+  Carve cg2;
+  cg2.base = (char*)ctx->gmem[tgt];
+  carve_global(cg2, g, &yd, &f, &x);
+  // place the instances: move the state of those already placed, load new ones
+  long long noff = 0;
+  int sub0 = 0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    Inst* in = live[q];
+    const size_t n = in->n;
+    if (in->placed) {
+      HIPCHK(hipMemcpyAsync(yd + noff, ctx->yd + in->noff, 8 * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(f + noff, ctx->f + in->noff, 8 * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(x + 2 * noff, ctx->x + 2 * in->noff, 16 * n, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIPCHK(hipMemcpyAsync(yd + noff, in->yd, 8 * n, hipMemcpyDeviceToDevice, st));
+      if (in->f) HIPCHK(hipMemcpyAsync(f + noff, in->f, 8 * n, hipMemcpyDeviceToDevice, st));
+      else HIPCHK(hipMemsetAsync(f + noff, 0, 8 * n, st));
+      if (in->y0) {
+        HIPCHK(hipMemcpyAsync(x + 2 * noff, in->y0, 8 * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(x + 2 * noff + n, in->p0, 8 * n, hipMemcpyDeviceToDevice, st));
+      } else {
+        HIPCHK(hipMemsetAsync(x + 2 * noff, 0, 16 * n, st));
+      }
+    }
+    in->slot = (int)q;
+    in->noff = noff;
+    in->sub0 = sub0;
+    noff += ((long long)n + kAlignN - 1) / kAlignN * kAlignN;
+    sub0 += in->part.S;
+  }
+  ctx->gcur = tgt;
+  ctx->yd = yd;
+  ctx->f = f;
+  ctx->x = x;
+  // work arena (contents are rebuilt by every outer iteration)
+  if (ctx->wcap < cw.off) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->wmem) HIPCHK(hipFree(ctx->wmem));
+    ctx->wmem = nullptr;
+    ctx->wcap = 0;
+    hipError_t e = hipMalloc(&ctx->wmem, cw.off);
+    if (e != hipSuccess) return fail(RSP_ENOMEM, "hipMalloc(%zu): %s", cw.off, hipGetErrorString(e));
+    ctx->wcap = cw.off;
+  }
+  Carve cw2;
+  cw2.base = (char*)ctx->wmem;
+  carve_work(cw2, g, o, &ctx->w);
+  ctx->geo = g;
+  ctx->opts = o;
+  ctx->fp32 = o.precision == RSP_FP32_REFINED;
+  ctx->nref = ctx->fp32 ? o.max_refine : 0;
+  // tables
+  ctx->hprob.assign(g.ninst, DevProblem{});
+  ctx->hseg.assign(g.ninst, GmSeg{});
+  std::vector<int4> hbox, hcore;
+  std::vector<int> hinst;
+  for (const Inst* in : live) {
+    const rsp_problem* p = &in->prob;
+    DevProblem& P = ctx->hprob[in->slot];
+    P.nx = p->nx;
+    P.ny = p->ny;
+    P.phi = p->phi_kind;
+    P.kappa = p->kappa;
+    P.nu = p->nu;
+    P.inv_nu = 1.0 / p->nu;
+    P.mu = p->mu;
+    const double hx = 1.0 / (p->nx + 1), hy = 1.0 / (p->ny + 1);
+    P.hx2i = 1.0 / (hx * hx);
+    P.hy2i = 1.0 / (hy * hy);
+    P.diag0 = 2.0 * P.hx2i + 2.0 * P.hy2i;
+    P.eps_min = p->eps_min;
+    P.gamma = p->gamma;
+    P.eps_start = p->eps_min;
+    P.noff = in->noff;
+    P.S = g.S;
+    P.txm = g.txm;
+    P.tym = g.tym;
+    P.M = g.M;
+    ctx->hseg[in->slot].off = 2 * in->noff;
+    ctx->hseg[in->slot].L = 2 * (long long)in->n;
+    for (int q = 0; q < in->part.S; ++q) {
+      hbox.push_back(in->part.box[q]);
+      hcore.push_back(in->part.core[q]);
+      hinst.push_back(in->slot);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ctx->w.prob, ctx->hprob.data(), sizeof(DevProblem) * g.ninst, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->w.seg, ctx->hseg.data(), sizeof(GmSeg) * g.ninst, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->w.box, hbox.data(), sizeof(int4) * g.S, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->w.core, hcore.data(), sizeof(int4) * g.S, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->w.inst, hinst.data(), sizeof(int) * g.S, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));   // host tables are temporaries; old arena no longer read
+  for (Inst* in : live) in->placed = true;
+  ctx->hstate.assign(g.S, SubState{});
+  ctx->hgm.assign(g.ninst, GmState{});
+  ctx->hnorm.assign(g.ninst, 0.0);
+  return 0;
+}
+
+int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st) {
+  const rsp_options& o = ctx->opts;
+  std::vector<Inst*> ev;
+  std::vector<char> cont;
+  for (Inst* in : live) {
+    if (in->finished) continue;
+    ev.push_back(in);
+    cont.push_back(!in->started ? o.continuation != RSP_CONT_NONE : o.continuation == RSP_CONT_EVERY);
+  }
+  if (ev.empty()) return 0;
+  auto t = Clock::now();
+  std::vector<EvalStats> es;
+  RSPCHK(run_eval(ctx, ev, cont, ctx->x, ctx->w.F, &es, st));
+  RSPCHK(read_norms(ctx, kLEval, (int)ev.size(), ctx->w.F, st));
+  double dt = ms_since(t);
+  std::vector<Inst*> go, fin;
+  for (size_t q = 0; q < ev.size(); ++q) {
+    Inst* in = ev[q];
+    in->ms_eval += dt;
+    in->Fn = ctx->hnorm[in->slot];
+    if (!in->started) {
+      in->thr = std::max(o.tol_outer, o.tol_outer * in->Fn);
+      in->started = true;
+    }
+    in->status = std::max(in->status, es[q].status);
+    const int k = in->k;
+    if (k <= RSP_HIST_MAX) {
+      rsp_history* h = &in->hist;
+      h->norm[k] = in->Fn;
+      h->inner_min[k] = es[q].inner_min;
+      h->inner_max[k] = es[q].inner_max;
+      h->inner_avg[k] = es[q].inner_avg;
+      h->backtracks[k] = es[q].backtracks;
+      if (k > 0) {
+        h->gmres_its[k] = in->gm_used;
+        h->gmres_rel[k] = in->gm_rel;
+      }
+    }
+    if (!(in->Fn <= in->thr) && in->k < o.max_outer) go.push_back(in);
+    else fin.push_back(in);
+  }
+  if (!fin.empty()) RSPCHK(finish(ctx, fin, st));
+  if (!go.empty()) {
+    // Newton systems F'(x^k) d = -F(x^k) by GMRES, then x^{k+1} = x^k + d (undamped)
+    t = Clock::now();
+    RSPCHK(upload_lists(ctx, kLGo, go, st));
+    RSPCHK(run_gmres(ctx, go, st));
+    const GmBatch B = gm_of(ctx, ctx->w.ilist[kLGo], (int)go.size());
+    rsp::launch_gm_axpy(B, 1.0, ctx->w.dx, ctx->x, 1, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    dt = ms_since(t);
+    for (Inst* in : go) {
+      in->ms_gmres += dt;
+      in->k += 1;
+    }
+  }
+  return 0;
+}
+
+}  // namespace rsp
+
+namespace {
+
+using rsp::engine_place;
+using rsp::engine_step;
+
+// Validates the arrays of a solve and builds its instances.
+int make_instances(int count, const rsp_problem* probs, const double* const* yd, const double* const* f,
+                   const double* const* y0, const double* const* p0, double* const* y, double* const* p,
+                   double* const* u, std::vector<Inst>* out) {
+  out->assign(count, Inst{});
+  for (int q = 0; q < count; ++q) {
+    if (!yd || !yd[q]) return fail(RSP_EINVAL, "instance %d: yd is NULL", q);
+    if (!y || !p || !u || !y[q] || !p[q] || !u[q]) return fail(RSP_EINVAL, "instance %d: outputs y, p, u are required", q);
+    const double* a = y0 ? y0[q] : nullptr;
+    const double* b = p0 ? p0[q] : nullptr;
+    if ((a == nullptr) != (b == nullptr)) return fail(RSP_EINVAL, "instance %d: give both y0 and p0 or neither", q);
+    Inst& in = (*out)[q];
+    int r = rsp::inst_init(&in, &probs[q]);
+    if (r < 0) return r;
+    in.yd = yd[q];
+    in.f = f ? f[q] : nullptr;
+    in.y0 = a;
+    in.p0 = b;
+    in.y = y[q];
+    in.p = p[q];
+    in.u = u[q];
+  }
+  return 0;
+}
+
+int solve_instances(rsp_context* ctx, const rsp_options* opts, std::vector<Inst>& insts, rsp_history* hist,
+                    hipStream_t stream) {
+  std::vector<Inst*> live;
+  for (auto& in : insts) live.push_back(&in);
+  RSPCHK(engine_place(ctx, *opts, live, stream));
+  for (auto& in : insts) in.t0 = rsp::Clock::now();
+  bool more = true;
+  while (more) {
+    RSPCHK(engine_step(ctx, live, stream));
+    more = false;
+    for (const Inst* in : live) more = more || !in->finished;
+  }
+  int worst = 0;
+  for (size_t q = 0; q < insts.size(); ++q) {
+    if (hist) hist[q] = insts[q].hist;
+    worst = std::max(worst, insts[q].status);
+  }
+  RSPCHK(resolve_events(ctx));
+  return worst;
 }
 
 }  // namespace
@@ -560,11 +981,11 @@ extern "C" {
 
 int rsp_version(void) { return RSP_VERSION; }
 
-const char* rsp_last_error(void) { return g_err.c_str(); }
+const char* rsp_last_error(void) { return rsp::last_error(); }
 
 int rsp_partition(const rsp_problem* prob, int32_t* S, int32_t* txm, int32_t* tym, int32_t* boxes) {
   Partition part;
-  RSPCHK(make_partition(prob, &part));
+  RSPCHK(rsp::make_partition(prob, &part));
   if (S) *S = part.S;
   if (txm) *txm = part.txm;
   if (tym) *tym = part.tym;
@@ -579,11 +1000,15 @@ int rsp_partition(const rsp_problem* prob, int32_t* S, int32_t* txm, int32_t* ty
 }
 
 size_t rsp_workspace_bytes(const rsp_problem* prob, const rsp_options* opts) {
-  Partition part;
-  if (make_partition(prob, &part) < 0 || validate_options(opts) < 0) return 0;
-  DevProblem P = make_dev(prob, part);
-  Layout lay = make_layout(P, opts);
-  return layout_bytes(lay, P.S);
+  if (!prob || !opts) return 0;
+  return rsp::batch_bytes(&prob, 1, *opts);
+}
+
+size_t rsp_batch_workspace_bytes(int count, const rsp_problem* probs, const rsp_options* opts) {
+  if (count < 1 || !probs || !opts) return 0;
+  std::vector<const rsp_problem*> pp;
+  for (int q = 0; q < count; ++q) pp.push_back(&probs[q]);
+  return rsp::batch_bytes(pp.data(), count, *opts);
 }
 
 int rsp_context_create(rsp_context** ctx, int device, size_t hbm_budget) {
@@ -604,7 +1029,9 @@ int rsp_context_destroy(rsp_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)resolve_events(ctx);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->mem) (void)hipFree(ctx->mem);
+  for (void* m : ctx->gmem)
+    if (m) (void)hipFree(m);
+  if (ctx->wmem) (void)hipFree(ctx->wmem);
   delete ctx;
   return 0;
 }
@@ -613,14 +1040,14 @@ int rsp_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
               const double* f, hipStream_t stream) {
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   if (!yd) return fail(RSP_EINVAL, "yd is NULL");
-  RSPCHK(ensure_setup(ctx, prob, opts));
-  const size_t n = ctx->lay.n;
-  HIPCHK(hipMemcpyAsync(ctx->box, ctx->part.box.data(), sizeof(int4) * ctx->P.S, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(ctx->core, ctx->part.core.data(), sizeof(int4) * ctx->P.S, hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(ctx->yd, yd, 8 * n, hipMemcpyDeviceToDevice, stream));
-  if (f) HIPCHK(hipMemcpyAsync(ctx->f, f, 8 * n, hipMemcpyDeviceToDevice, stream));
-  else HIPCHK(hipMemsetAsync(ctx->f, 0, 8 * n, stream));
-  HIPCHK(hipStreamSynchronize(stream));   // the partition vectors are host temporaries
+  ctx->ready = false;
+  RSPCHK(rsp::validate_options(opts));
+  RSPCHK(rsp::inst_init(&ctx->single, prob));
+  ctx->single.yd = yd;
+  ctx->single.f = f;
+  std::vector<Inst*> live{&ctx->single};
+  RSPCHK(engine_place(ctx, *opts, live, stream));
+  ctx->ready = true;
   return 0;
 }
 
@@ -630,7 +1057,7 @@ int rsp_setup(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
 int rsp_residual(rsp_context* ctx, const double* x, double eps, double* out, hipStream_t stream) {
   NEED_READY(ctx);
   if (!(eps >= 0)) return fail(RSP_EINVAL, "eps must be >= 0");
-  rsp::launch_global_residual(ctx->P, ctx->yd, ctx->f, x, eps, out, stream);
+  rsp::launch_global_residual(ctx->hprob[0], ctx->yd, ctx->f, x, eps, out, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -638,21 +1065,21 @@ int rsp_residual(rsp_context* ctx, const double* x, double eps, double* out, hip
 int rsp_control(rsp_context* ctx, const double* p, double eps, double* u, hipStream_t stream) {
   NEED_READY(ctx);
   if (!(eps >= 0)) return fail(RSP_EINVAL, "eps must be >= 0");
-  rsp::launch_control(ctx->P, p, eps, u, stream);
+  rsp::launch_control(ctx->hprob[0], p, eps, u, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
 
 int rsp_restrict(rsp_context* ctx, const double* x, double* tiles, hipStream_t stream) {
   NEED_READY(ctx);
-  rsp::launch_restrict(ctx->P, ctx->box, x, tiles, stream);
+  rsp::launch_restrict(all_items(ctx), x, tiles, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
 
 int rsp_prolong(rsp_context* ctx, const double* tiles, double* out, hipStream_t stream) {
   NEED_READY(ctx);
-  rsp::launch_prolong(ctx->P, ctx->box, ctx->core, tiles, nullptr, out, stream);
+  rsp::launch_prolong(all_items(ctx), tiles, nullptr, out, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -661,8 +1088,9 @@ int rsp_local_residual(rsp_context* ctx, const double* x, const double* c, doubl
                        double* norms, hipStream_t stream) {
   NEED_READY(ctx);
   if (!(eps >= 0)) return fail(RSP_EINVAL, "eps must be >= 0");
-  rsp::launch_restrict_halo(ctx->P, ctx->box, x, ctx->tilex, stream);
-  rsp::launch_local_residual(ctx->P, ctx->box, ctx->tilex, ctx->yd, ctx->f, c, eps, out, norms, stream);
+  const Items I = all_items(ctx);
+  rsp::launch_restrict_halo(I, x, ctx->w.tilex, stream);
+  rsp::launch_local_residual(I, ctx->w.tilex, ctx->yd, ctx->f, c, eps, out, norms, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -671,10 +1099,11 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
                     double* z, hipStream_t stream) {
   NEED_READY(ctx);
   if (!(eps > 0)) return fail(RSP_EINVAL, "eps must be > 0");
-  rsp::launch_restrict_halo(ctx->P, ctx->box, x, ctx->tilex, stream);
-  rsp::launch_factor(ctx->P, ctx->box, ctx->tilex, c, nullptr, eps, nullptr, 0.0, ctx->fac, ctx->fp32,
-                     ctx->g, stream);
-  rsp::launch_block_solve(ctx->P, ctx->box, ctx->fac, ctx->fp32, rhs, z, stream);
+  const Items I = all_items(ctx);
+  rsp::launch_restrict_halo(I, x, ctx->w.tilex, stream);
+  rsp::launch_factor(I, ctx->geo.M, ctx->w.tilex, c, nullptr, eps, nullptr, 0.0, ctx->w.fac, ctx->fp32,
+                     ctx->w.g, stream);
+  rsp::launch_block_solve(I, ctx->geo.M, ctx->w.fac, ctx->fp32, rhs, z, stream);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -682,105 +1111,54 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
 int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out, double* norm,
              hipStream_t stream) {
   NEED_READY(ctx);
-  EvalStats es;
-  RSPCHK(run_eval(ctx, x, continuation != 0, out, &es, stream));
-  if (norm) RSPCHK(dev_norm(ctx, out, ctx->lay.L, norm, stream));
-  return es.status;
+  std::vector<Inst*> set{&ctx->single};
+  std::vector<char> cont{(char)(continuation != 0)};
+  std::vector<EvalStats> es;
+  RSPCHK(run_eval(ctx, set, cont, x, out, &es, stream));
+  if (norm) {
+    RSPCHK(read_norms(ctx, kLEval, 1, out, stream));
+    *norm = ctx->hnorm[0];
+  }
+  return es[0].status;
 }
 
 int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream) {
   NEED_READY(ctx);
-  return run_jac_apply(ctx, d, out, stream);
+  std::vector<Inst*> set{&ctx->single};
+  jac_apply(ctx, all_items(ctx), sub_work(ctx, set, false), d, out, stream);
+  HIPCHK(hipGetLastError());
+  return 0;
 }
 
 int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts, const double* yd,
               const double* f, const double* y0, const double* p0, double* y, double* p, double* u,
               rsp_history* hist, hipStream_t stream) {
-  using clk = std::chrono::steady_clock;
-  const auto t0 = clk::now();
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
-  if (!y || !p || !u) return fail(RSP_EINVAL, "outputs y, p, u are required");
-  if ((y0 == nullptr) != (p0 == nullptr)) return fail(RSP_EINVAL, "give both y0 and p0 or neither");
-  RSPCHK(rsp_setup(ctx, prob, opts, yd, f, stream));
-  const size_t n = ctx->lay.n, L = ctx->lay.L;
-  ctx->n_factor = ctx->n_solve = ctx->n_gmres = ctx->n_newton = ctx->n_apply = 0;
-  ctx->flops = 0;
-  rsp_history hloc;
-  rsp_history* h = hist ? hist : &hloc;
-  std::memset(h, 0, sizeof(*h));
-  h->subdomains = ctx->P.S;
-  if (y0) {
-    HIPCHK(hipMemcpyAsync(ctx->x, y0, 8 * n, hipMemcpyDeviceToDevice, stream));
-    HIPCHK(hipMemcpyAsync(ctx->x + n, p0, 8 * n, hipMemcpyDeviceToDevice, stream));
-  } else {
-    HIPCHK(hipMemsetAsync(ctx->x, 0, 8 * L, stream));
+  RSPCHK(rsp::validate_options(opts));
+  if (!prob) return fail(RSP_EINVAL, "problem is NULL");
+  ctx->ready = false;
+  std::vector<Inst> insts;
+  RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
+  const int r = solve_instances(ctx, opts, insts, hist, stream);
+  if (r >= 0) {
+    // keep the problem bound for the single-problem calls, as after rsp_setup
+    ctx->single = insts[0];
+    ctx->ready = true;
   }
-  double ms_eval = 0, ms_gmres = 0;
-  auto ms = [](clk::time_point a, clk::time_point b) {
-    return std::chrono::duration<double, std::milli>(b - a).count();
-  };
-  EvalStats es;
-  auto te = clk::now();
-  RSPCHK(run_eval(ctx, ctx->x, opts->continuation != RSP_CONT_NONE, ctx->F, &es, stream));
-  double Fn = 0;
-  RSPCHK(dev_norm(ctx, ctx->F, L, &Fn, stream));
-  ms_eval += ms(te, clk::now());
-  int status = es.status;
-  h->norm[0] = Fn;
-  h->inner_min[0] = es.inner_min;
-  h->inner_max[0] = es.inner_max;
-  h->inner_avg[0] = es.inner_avg;
-  h->backtracks[0] = es.backtracks;
-  const double thr = std::max(opts->tol_outer, opts->tol_outer * Fn);
-  int k = 0;
-  while (!(Fn <= thr) && k < opts->max_outer) {
-    // Newton system F'(x^k) d = -F(x^k) by GMRES, then x^{k+1} = x^k + d (undamped)
-    const auto tg = clk::now();
-    rsp::launch_scale(-1.0, ctx->F, ctx->b, L, stream);
-    int used = 0;
-    double rel = 0;
-    int gs = run_gmres(ctx, ctx->b, ctx->dx, &used, &rel, stream);
-    if (gs < 0) return gs;
-    if (gs > 0) status = std::max(status, gs);
-    rsp::launch_axpy(1.0, ctx->dx, ctx->x, L, stream);
-    ms_gmres += ms(tg, clk::now());
-    ++k;
-    te = clk::now();
-    RSPCHK(run_eval(ctx, ctx->x, opts->continuation == RSP_CONT_EVERY, ctx->F, &es, stream));
-    RSPCHK(dev_norm(ctx, ctx->F, L, &Fn, stream));
-    ms_eval += ms(te, clk::now());
-    status = std::max(status, es.status);
-    if (k <= RSP_HIST_MAX) {
-      h->norm[k] = Fn;
-      h->gmres_its[k] = used;
-      h->gmres_rel[k] = rel;
-      h->inner_min[k] = es.inner_min;
-      h->inner_max[k] = es.inner_max;
-      h->inner_avg[k] = es.inner_avg;
-      h->backtracks[k] = es.backtracks;
-    }
-  }
-  if (!(Fn <= thr) && status == 0) status = RSP_NOT_CONVERGED;
-  HIPCHK(hipMemcpyAsync(y, ctx->x, 8 * n, hipMemcpyDeviceToDevice, stream));
-  HIPCHK(hipMemcpyAsync(p, ctx->x + n, 8 * n, hipMemcpyDeviceToDevice, stream));
-  rsp::launch_control(ctx->P, ctx->x + n, prob->eps_min, u, stream);
-  rsp::launch_global_residual(ctx->P, ctx->yd, ctx->f, ctx->x, prob->eps_min, ctx->w, stream);
-  double rfin = 0;
-  RSPCHK(dev_norm(ctx, ctx->w, L, &rfin, stream));
-  h->status = status;
-  h->outer = k;
-  h->factorizations = ctx->n_factor;
-  h->local_solves = ctx->n_solve;
-  h->gmres_total = ctx->n_gmres;
-  h->newton_iterations = ctx->n_newton;
-  h->jac_applies = ctx->n_apply;
-  h->residual_final = rfin;
-  h->flops = ctx->flops;
-  h->ms_eval = ms_eval;
-  h->ms_gmres = ms_gmres;
-  h->ms_total = ms(t0, clk::now());
-  RSPCHK(resolve_events(ctx));
-  return status;
+  return r;
+}
+
+int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const rsp_options* opts,
+                    const double* const* yd, const double* const* f, const double* const* y0,
+                    const double* const* p0, double* const* y, double* const* p, double* const* u,
+                    rsp_history* hist, hipStream_t stream) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  if (count < 1 || !probs) return fail(RSP_EINVAL, "need count >= 1 problems");
+  RSPCHK(rsp::validate_options(opts));
+  ctx->ready = false;
+  std::vector<Inst> insts;
+  RSPCHK(make_instances(count, probs, yd, f, y0, p0, y, p, u, &insts));
+  return solve_instances(ctx, opts, insts, hist, stream);
 }
 
 int rsp_set_profiling(rsp_context* ctx, int on) {

@@ -9,7 +9,11 @@ constexpr int kBlock = 256;            // threads of the per-subdomain kernels
 constexpr int kMaxTile = 48;           // widest overlapping tile (2*48 line unknowns)
 constexpr int kMaxM = 2 * kMaxTile;    // largest line block
 
-// Problem constants in the form the kernels use them (passed by value).
+// Constants of one problem instance in the form the kernels use them.  A batch
+// holds several instances; its global arrays are the instances' arrays one after
+// the other ([ny][nx] fields at offset noff, [2][ny][nx] states at 2 noff) and
+// the tile and factor arrays are laid out per subdomain with one tile geometry
+// for the whole batch (txm, tym, M: the same in every instance's record).
 struct DevProblem {
   int nx, ny;
   int phi;            // RSP_PHI_*
@@ -18,10 +22,36 @@ struct DevProblem {
   double hx2i, hy2i;  // 1/hx^2, 1/hy^2
   double diag0;       // 2/hx^2 + 2/hy^2
   double eps_min, gamma;
-  int S;              // subdomains
-  int txm, tym;       // largest tile width / height
+  double eps_start;   // eps_0 of the local solves of the next evaluation
+  long long noff;     // offset of this instance's [ny][nx] arrays
+  int S;              // subdomains of the batch
+  int txm, tym;       // largest tile width / height of the batch
   int M;              // padded line-block size (multiple of 16, >= 2*txm)
 };
+
+// Work list of a per-subdomain launch.  Items are the (instance, subdomain) pairs
+// of the batch, numbered consecutively; workgroup b handles item list[b] (or b).
+// An item is skipped when skip != nullptr and skip[instance * skip_stride] != 0
+// (the GMRES stop flags of the instances, for instance).
+struct Items {
+  const DevProblem* prob;   // [instances]
+  const int* inst;          // [items] instance of the item
+  const int4* box;          // [items] overlapping box (x0, x1, y0, y1), half-open
+  const int4* core;         // [items] non-overlapping box
+  const int* list;          // [count] or nullptr
+  const int* skip;
+  int skip_stride;
+  int count;                // workgroups of the launch
+};
+
+// Item of this workgroup and its instance's constants; false when it is skipped.
+__device__ __forceinline__ bool item_of(const Items& I, int& s, DevProblem& P) {
+  s = I.list ? I.list[blockIdx.x] : (int)blockIdx.x;
+  const int i = I.inst[s];
+  if (I.skip && I.skip[(size_t)i * I.skip_stride]) return false;
+  P = I.prob[i];
+  return true;
+}
 
 // Per-subdomain state of the local Newton solve (Algorithm 1).
 struct SubState {
@@ -35,15 +65,36 @@ struct SubState {
   int backtracks;    // step halvings so far
 };
 
-// Device-resident GMRES state (restart m <= kGmMaxRestart).
+// Device-resident GMRES (restart m <= kGmMaxRestart), one per instance: a small
+// header the host reads back for the whole batch in one copy, and the Hessenberg
+// matrix with the Givens rotations and the rotated right-hand side.
 constexpr int kGmMaxRestart = 64;
 constexpr int kGmMaxVec = kGmMaxRestart + 1;
-constexpr int kGmBlocks = 128;        // fixed reduction blocks of the GMRES vector kernels
+constexpr int kGmBlocks = 128;        // fixed reduction blocks per instance of the GMRES vector kernels
 struct GmState {
   int m, maxit, steps, used, done, pad;
   double rtol, bnorm, beta, rel;
+};
+constexpr int kGmDoneStride = sizeof(GmState) / sizeof(int);   // ints between two instances' done flags
+struct GmHess {
   double H[(kGmMaxRestart + 1) * kGmMaxRestart];   // H[i * m + j]
   double cs[kGmMaxRestart], sn[kGmMaxRestart], g[kGmMaxRestart + 1];
+};
+// Segment of one instance in the batch's concatenated global vectors (length L =
+// 2 nx ny at offset off).  The Krylov bases are [m+1][ldv]: basis vector k of all
+// instances is one concatenated vector.
+struct GmSeg {
+  long long off, L;
+};
+// Instances of a GMRES launch: blockIdx.y -> instance list[blockIdx.y] (or blockIdx.y).
+struct GmBatch {
+  const GmSeg* seg;
+  GmState* st;
+  GmHess* hs;
+  const int* list;
+  long long ldv;            // length of the concatenated vectors
+  int count;
+  int m;
 };
 
 // ---------------------------------------------------------------- pointwise

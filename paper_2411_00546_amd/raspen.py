@@ -98,6 +98,9 @@ SIGNATURES = [
     ("rsp_jac_apply", _I, [_P, _P, _P, _P]),
     ("rsp_solve", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                        ctypes.POINTER(rsp_history), _P]),
+    ("rsp_solve_batch", _I, [_P, _I, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
+                             ctypes.POINTER(rsp_history), _P]),
+    ("rsp_batch_workspace_bytes", ctypes.c_size_t, [_I, _PROB, _OPTS]),
     ("rsp_set_profiling", _I, [_P, _I]),
     ("rsp_reset_kernel_stats", _I, [_P]),
     ("rsp_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
@@ -244,6 +247,41 @@ def rsp_solve(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):
                                  _ptr(f, True), _ptr(y0, True), _ptr(p0, True), _ptr(y), _ptr(p),
                                  _ptr(u), ctypes.byref(h), _stream(stream)))
     return st, h.as_dict()
+
+
+def _ptr_array(ts, allow_none=False):
+    """Host array of device pointers (NULL array when every entry is None and allowed)."""
+    if ts is None or (allow_none and all(t is None for t in ts)):
+        if allow_none:
+            return None
+        raise ValueError("array argument is required")
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        p = _ptr(t, allow_none)
+        arr[i] = p.value if p is not None else None
+    return arr
+
+
+def rsp_solve_batch(ctx, probs, opts, yd, f, y0, p0, y, p, u, stream=None):
+    """Algorithm 2 for a batch.  probs: list of rsp_problem; yd .. u: lists of tensors
+    (f, y0, p0 may be None or hold None).  Returns (worst status, [history dicts])."""
+    n = len(probs)
+    parr = (rsp_problem * n)(*probs)
+    hist = (rsp_history * n)()
+    none = [None] * n
+    st = _check(load().rsp_solve_batch(ctx, n, parr, ctypes.byref(opts), _ptr_array(yd),
+                                       _ptr_array(f if f is not None else none, True),
+                                       _ptr_array(y0 if y0 is not None else none, True),
+                                       _ptr_array(p0 if p0 is not None else none, True),
+                                       _ptr_array(y), _ptr_array(p), _ptr_array(u), hist,
+                                       _stream(stream)))
+    return st, [h.as_dict() for h in hist]
+
+
+def rsp_batch_workspace_bytes(probs, opts):
+    n = len(probs)
+    parr = (rsp_problem * n)(*probs)
+    return load().rsp_batch_workspace_bytes(n, parr, ctypes.byref(opts))
 
 
 def rsp_set_profiling(ctx, on=True):
