@@ -51,6 +51,7 @@ extern "C" {
 #define RSP_ENOMEM (-2)
 #define RSP_EHIP (-3)
 #define RSP_ENUMERIC (-4)
+#define RSP_EAGAIN (-5)         /* rsp_server_wait: not done within the timeout */
 
 /* phi(y), Assumption 1 (phi in C^2, monotone increasing) */
 #define RSP_PHI_ZERO 0          /* phi = 0 (linear state equation)            */
@@ -219,6 +220,63 @@ int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const
 
 /* Device bytes rsp_solve_batch needs for these problems (0 if one is invalid). */
 size_t rsp_batch_workspace_bytes(int count, const rsp_problem* probs, const rsp_options* opts);
+
+/* ---- serving: continuous batching of solves on one device ----
+   A server owns a context, a stream and a worker thread.  Requests are admitted
+   first come first served between two outer iterations of the running batch
+   (Algorithm 2 steps), while the grown batch fits `hbm_budget` (by
+   rsp_batch_workspace_bytes) and `max_batch`; an instance leaves the batch at the
+   end of the iteration in which it meets its stopping test.  A request's result
+   does not depend on the other requests sharing its batch (see rsp_solve_batch).
+   All server calls are thread-safe. */
+
+typedef struct rsp_server rsp_server;
+
+typedef struct rsp_server_options {
+  int32_t device;       /* HIP device of the server's context and stream              */
+  int32_t max_batch;    /* most instances solved together (0: no limit)               */
+  size_t hbm_budget;    /* device bytes for the batch layout (0: no limit)            */
+  rsp_options opts;     /* solver options of every request                            */
+} rsp_server_options;
+
+#define RSP_TICKET_QUEUED 0
+#define RSP_TICKET_RUNNING 1
+#define RSP_TICKET_DONE 2
+
+typedef struct rsp_server_report {
+  int64_t submitted, completed, failed;   /* requests so far (failed: hard errors)       */
+  int64_t queued, running;                /* requests waiting / in the running batch      */
+  int64_t steps;                          /* outer iterations run by the worker           */
+  double mean_batch;                      /* average instances per outer iteration        */
+  double p50_ms, p99_ms, mean_ms;         /* submit-to-done latency of completed requests  */
+  double solves_per_s;                    /* completed / (last completion - first submit)  */
+} rsp_server_report;
+
+/* Start a server (worker thread, stream, context on opts->device). */
+int rsp_server_create(rsp_server** srv, const rsp_server_options* opts);
+
+/* Queue one solve (Algorithm 2 from x^0 = 0).  yd, f (nullable: 0) are device
+   arrays [ny][nx] whose data must be ready when this is called; y, p, u receive
+   the solution.  All five must stay valid and untouched until the ticket is done.
+   Returns at once with `ticket` (host); RSP_EINVAL for a problem that cannot be
+   partitioned or laid out. */
+int rsp_server_submit(rsp_server* srv, const rsp_problem* prob, const double* yd, const double* f,
+                      double* y, double* p, double* u, uint64_t* ticket);
+
+/* Current state of a ticket (RSP_TICKET_*). */
+int rsp_server_poll(rsp_server* srv, uint64_t ticket, int32_t* state);
+
+/* Block until the ticket is done (timeout_ms < 0: no limit; RSP_EAGAIN when it
+   expires), copy its history into `hist` (host, nullable) and release the ticket.
+   Returns the solve status, or the hard error that ended the request (RSP_ENOMEM
+   when the problem alone exceeds the budget). */
+int rsp_server_wait(rsp_server* srv, uint64_t ticket, double timeout_ms, rsp_history* hist);
+
+/* Counters and latency percentiles (nearest rank) since the server started. */
+int rsp_server_stats(rsp_server* srv, rsp_server_report* out);
+
+/* Finish every submitted request, then stop the worker and free the server. */
+int rsp_server_destroy(rsp_server* srv);
 
 /* ---- kernel timing (HIP events around every launch of the hot-path kernels) ---- */
 

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libraspen.so")
 
 RSP_OK, RSP_NOT_CONVERGED, RSP_LINESEARCH_FAIL, RSP_GMRES_STAGNATION, RSP_REFINE_FALLBACK = 0, 1, 2, 3, 4
-RSP_EINVAL, RSP_ENOMEM, RSP_EHIP, RSP_ENUMERIC = -1, -2, -3, -4
+RSP_EINVAL, RSP_ENOMEM, RSP_EHIP, RSP_ENUMERIC, RSP_EAGAIN = -1, -2, -3, -4, -5
+RSP_TICKET_QUEUED, RSP_TICKET_RUNNING, RSP_TICKET_DONE = 0, 1, 2
 RSP_FP64, RSP_FP32_REFINED = 0, 1
 RSP_CONT_FIRST, RSP_CONT_NONE, RSP_CONT_EVERY = 0, 1, 2
 RSP_HIST_MAX = 64
@@ -73,6 +74,19 @@ class rsp_kernel_stat(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class rsp_server_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("opts", rsp_options)]
+
+
+class rsp_server_report(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("mean_batch", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every exported entry point, in header order
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -101,6 +115,12 @@ SIGNATURES = [
     ("rsp_solve_batch", _I, [_P, _I, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(rsp_history), _P]),
     ("rsp_batch_workspace_bytes", ctypes.c_size_t, [_I, _PROB, _OPTS]),
+    ("rsp_server_create", _I, [ctypes.POINTER(_P), ctypes.POINTER(rsp_server_options)]),
+    ("rsp_server_submit", _I, [_P, _PROB, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("rsp_server_poll", _I, [_P, ctypes.c_uint64, _I32P]),
+    ("rsp_server_wait", _I, [_P, ctypes.c_uint64, _D, ctypes.POINTER(rsp_history)]),
+    ("rsp_server_stats", _I, [_P, ctypes.POINTER(rsp_server_report)]),
+    ("rsp_server_destroy", _I, [_P]),
     ("rsp_set_profiling", _I, [_P, _I]),
     ("rsp_reset_kernel_stats", _I, [_P]),
     ("rsp_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
@@ -282,6 +302,45 @@ def rsp_batch_workspace_bytes(probs, opts):
     n = len(probs)
     parr = (rsp_problem * n)(*probs)
     return load().rsp_batch_workspace_bytes(n, parr, ctypes.byref(opts))
+
+
+def rsp_server_create(opts, device=0, max_batch=0, hbm_budget=0):
+    """Start a server; opts: rsp_options of every request."""
+    h = ctypes.c_void_p()
+    so = rsp_server_options(device, max_batch, hbm_budget, opts)
+    _check(load().rsp_server_create(ctypes.byref(h), ctypes.byref(so)))
+    return h
+
+
+def rsp_server_submit(srv, prob, yd, f, y, p, u):
+    """Queue a solve; the tensors must stay alive until the ticket is done.  Returns the ticket."""
+    t = ctypes.c_uint64()
+    _check(load().rsp_server_submit(srv, ctypes.byref(prob), _ptr(yd), _ptr(f, True), _ptr(y), _ptr(p),
+                                    _ptr(u), ctypes.byref(t)))
+    return t.value
+
+
+def rsp_server_poll(srv, ticket):
+    st = ctypes.c_int32()
+    _check(load().rsp_server_poll(srv, ticket, ctypes.byref(st)))
+    return st.value
+
+
+def rsp_server_wait(srv, ticket, timeout_ms=-1.0):
+    """Returns (status, history dict); raises RaspenError on a hard error or RSP_EAGAIN."""
+    h = rsp_history()
+    st = _check(load().rsp_server_wait(srv, ticket, float(timeout_ms), ctypes.byref(h)))
+    return st, h.as_dict()
+
+
+def rsp_server_stats(srv):
+    r = rsp_server_report()
+    _check(load().rsp_server_stats(srv, ctypes.byref(r)))
+    return {k: getattr(r, k) for k, _ in rsp_server_report._fields_}
+
+
+def rsp_server_destroy(srv):
+    return _check(load().rsp_server_destroy(srv))
 
 
 def rsp_set_profiling(ctx, on=True):

@@ -89,3 +89,23 @@ def test_workspace_bytes(R):
     # FP32 line factors take half the factor bytes
     mixed = R.rsp_workspace_bytes(R.make_problem(synth.config_plain()), R.make_options(synth.Options(precision=1)))
     assert plain - mixed == 64 * 40 * 80 * 80 * 4
+
+
+def test_batch_workspace_bytes(R):
+    o = R.make_options(synth.Options())
+    a = R.make_problem(synth.config_small())
+    b = R.make_problem(synth.config_plain())
+    one = R.rsp_batch_workspace_bytes([a], o)
+    assert one == R.rsp_workspace_bytes(a, o)
+    both = R.rsp_batch_workspace_bytes([a, b], o)
+    assert both > R.rsp_workspace_bytes(b, o) > one
+    bad = R.make_problem(synth.Problem(nx=9, ny=9, sx=4, sy=1))
+    assert R.rsp_batch_workspace_bytes([a, bad], o) == 0
+    assert R.rsp_batch_workspace_bytes([], o) == 0
+
+
+def test_server_and_batch_entry_points_are_declared():
+    names = declared_functions()
+    for must in ["rsp_solve_batch", "rsp_batch_workspace_bytes", "rsp_server_create", "rsp_server_submit",
+                 "rsp_server_poll", "rsp_server_wait", "rsp_server_stats", "rsp_server_destroy"]:
+        assert must in names
