@@ -123,6 +123,7 @@ def cpu_baseline(prob, opts, hist):
                  + hist["gmres_total"] * t_mgs)
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "seconds_per_solve": per_solve,
+            "units": {"t_iter": t_iter, "t_factor": t_factor, "t_apply_sub": t_apply_sub, "t_mgs": t_mgs},
             "sample": ("NumPy/SciPy oracle, 1 thread: first-evaluation local Newton solves of %d of the %d "
                        "subdomains (%d iterations, %.2f ms each), %d sparse LU factorisations (%.1f ms), "
                        "%d local Jacobian solves (%.2f ms), %d Gram-Schmidt sweeps of 16 vectors (%.1f ms); "
@@ -133,12 +134,249 @@ def cpu_baseline(prob, opts, hist):
                           sample_s))}
 
 
+def kernel_roofline(stats, fp32):
+    """Roofline object of the dominant single-pass kernel from rsp_kernel_stats output."""
+    kern = {k: v for k, v in stats.items() if v["launches"] > 0}
+    single = {k: v for k, v in kern.items() if k != "gmres_ortho"}
+    dom = max(single, key=lambda k: single[k]["ms"])
+    d = kern[dom]
+    bound, peak, unit = BOUND[dom]
+    if dom == "factor" and fp32:
+        peak = FP32_PEAK_TFLOPS
+    avg_s = d["ms"] / d["launches"] / 1e3
+    if bound == "hbm":
+        achieved = d["bytes"] / d["launches"] / avg_s / 1e9
+    else:
+        achieved = d["flops"] / d["launches"] / avg_s / 1e12
+    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic_for(dom, d["launches"]),
+            "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+            "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
+    kernels = {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
+                   "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                   "GFLOPps": round(v["flops"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
+               for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+    return roof, kernels
+
+
+def pct(lat_s):
+    import numpy as np
+    a = np.array(lat_s) * 1e3
+    return {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99))}
+
+
+class Instances:
+    """Device inputs and outputs of a list of problems (allocated once, before timing)."""
+
+    def __init__(self, probs):
+        import torch
+        self.probs = probs
+        self.yd, self.f, self.y, self.p, self.u = [], [], [], [], []
+        for pr in probs:
+            yd, f = pr.inputs()
+            self.yd.append(torch.as_tensor(yd, dtype=torch.float64, device="cuda:0").contiguous())
+            self.f.append(torch.as_tensor(f, dtype=torch.float64, device="cuda:0").contiguous())
+            for lst in (self.y, self.p, self.u):
+                lst.append(torch.empty((pr.ny, pr.nx), dtype=torch.float64, device="cuda:0"))
+        torch.cuda.synchronize()
+
+    def x(self, q):
+        import torch
+        return torch.cat([self.y[q].reshape(-1), self.p[q].reshape(-1)]).cpu().numpy()
+
+
+def rel_errs(xs, refs):
+    """Max-norm relative error of each solution against its FP64 reference."""
+    import numpy as np
+    return [float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(xs, refs)]
+
+
+def err_report(errs):
+    """A solve counts toward solves/s when it is within 1e-8 of the FP64 solution."""
+    import numpy as np
+    e = np.array(errs)
+    return {"max": float(e.max()), "median": float(np.median(e)), "within_1e-8": int((e <= 1e-8).sum()),
+            "count": len(errs)}
+
+
+def batch_cpu_baseline(probs, opts, hists):
+    """Oracle cost of the batch: unit costs measured (bounded sample) on the largest
+    instance, scaled by every instance's own counts; Gram-Schmidt cost scaled by size."""
+    big = max(range(len(probs)), key=lambda q: probs[q].nx * probs[q].ny)
+    one = cpu_baseline(probs[big], opts, hists[big])
+    n_big = probs[big].nx * probs[big].ny
+    u = one["units"]
+    total = 0.0
+    for pr, h in zip(probs, hists):
+        S = h["subdomains"]
+        inner = h["newton_iterations"]
+        total += (inner * u["t_iter"] + (h["factorizations"] - inner) * u["t_factor"]
+                  + h["jac_applies"] * S * u["t_apply_sub"]
+                  + h["gmres_total"] * u["t_mgs"] * (pr.nx * pr.ny) / n_big)
+    return {"value": len(probs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "seconds_per_batch": total,
+            "sample": "unit costs from the bounded oracle sample of the %dx%d instance (%s), scaled by the "
+                      "counts of all %d instances" % (probs[big].nx, probs[big].ny, one["sample"], len(probs))}
+
+
+def run_batch_workload(args, R):
+    """64 uneven instances per step through rsp_solve_batch (FP32 line factors), checked
+    against the FP64 batch, with plain FP64 one-at-a-time solves timed beside it."""
+    import numpy as np
+    import synth
+    import torch
+    probs = synth.batch_instances(args.count)
+    opts = synth.Options(precision=1 if args.precision == "mixed" else 0, max_refine=args.max_refine)
+    opts64 = synth.Options()
+    inst = Instances(probs)
+    P = [R.make_problem(pr) for pr in probs]
+    O, O64 = R.make_options(opts), R.make_options(opts64)
+    ctx = R.rsp_context_create(0)
+    try:
+        def batch(o, steps, warm, profile):
+            for _ in range(warm):
+                R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
+            if profile:
+                R.rsp_set_profiling(ctx, True)
+                R.rsp_reset_kernel_stats(ctx)
+            torch.cuda.synchronize()
+            lat = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ts = time.perf_counter()
+                st, hists = R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
+                lat.append(time.perf_counter() - ts)
+                if st != 0:
+                    raise RuntimeError("batch ended with status %d" % st)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            stats = R.rsp_kernel_stats(ctx) if profile else None
+            R.rsp_set_profiling(ctx, False)
+            return el, lat, hists, stats, [inst.x(q) for q in range(len(probs))]
+
+        el, lat, hists, stats, xs = batch(O, args.steps, args.warmup, True)
+        el64b, _, hists64, _, x64 = batch(O64, 1, 0, False)
+        errs = err_report(rel_errs(xs, x64))
+        # plain FP64, one instance at a time
+        t0 = time.perf_counter()
+        lat1 = []
+        for q in range(len(probs)):
+            ts = time.perf_counter()
+            st, _ = R.rsp_solve(ctx, P[q], O64, inst.yd[q], inst.f[q], None, None, inst.y[q], inst.p[q],
+                                inst.u[q])
+            lat1.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t0
+    finally:
+        R.rsp_context_destroy(ctx)
+    roof, kernels = kernel_roofline(stats, opts.precision == 1)
+    flops = sum(h["flops"] for h in hists)
+    sizes = sorted({(pr.nx, pr.ny) for pr in probs})
+    cpu = None if args.no_cpu_baseline else batch_cpu_baseline(probs, opts, hists)
+    return {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",
+            "value": errs["within_1e-8"] * args.steps / el, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
+            "data": "synthetic (seeded Gaussian-bump y_d)",
+            "config": {"workload": "raspen_batch%d_grids63-255_32x32subdomains_ov4" % len(probs),
+                       "instances": len(probs), "grids": sizes, "step": "one rsp_solve_batch of every instance",
+                       "precision": "fp32 line factors" if opts.precision == 1 else "fp64"},
+            "latency_ms": pct([l / 1.0 for l in lat]),
+            "per_instance_latency_ms": {"p50": float(np.percentile([h["ms_total"] for h in hists], 50)),
+                                        "p99": float(np.percentile([h["ms_total"] for h in hists], 99))},
+            "gflops": flops / (el / args.steps) / 1e9,
+            "rel_err_mixed_vs_fp64": errs, "all_solves_per_s": len(probs) * args.steps / el,
+            "fp64_batch": {"value": len(probs) / el64b, "unit": "solves/s"},
+            "fp64_one_at_a_time": {"value": len(probs) / el1, "unit": "solves/s", "latency_ms": pct(lat1)},
+            "outer": [h["outer"] for h in hists], "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+
+
+def run_serve_workload(args, R):
+    """Poisson request stream through rsp_server_*: closed-loop capacity first, then an
+    open-loop stream at 0.8 of it; every result checked against plain FP64 solves."""
+    import numpy as np
+    import synth
+    import torch
+    # grids up to 511x511 (256 subdomains): the GMRES iterations of an outer step grow with the
+    # subdomain count, so the cap on products per outer step is raised for this stream
+    opts = synth.Options(precision=1 if args.precision == "mixed" else 0, max_refine=args.max_refine,
+                         max_gmres=1500)
+    _, probs = synth.request_stream(args.count, 1.0)
+    inst = Instances(probs)
+    P = [R.make_problem(pr) for pr in probs]
+    O, O64 = R.make_options(opts), R.make_options(synth.Options(max_gmres=1500))
+
+    def serve(arrivals):
+        srv = R.rsp_server_create(O)
+        try:
+            t0 = time.perf_counter()
+            tickets = []
+            for q in range(len(probs)):
+                if arrivals is not None:
+                    dt = t0 + arrivals[q] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets.append(R.rsp_server_submit(srv, P[q], inst.yd[q], inst.f[q], inst.y[q], inst.p[q],
+                                                   inst.u[q]))
+            hists = []
+            for t in tickets:
+                st, h = R.rsp_server_wait(srv, t)
+                if st != 0:
+                    raise RuntimeError("request ended with status %d" % st)
+                hists.append(h)
+            el = time.perf_counter() - t0
+            stats = R.rsp_server_stats(srv)
+        finally:
+            R.rsp_server_destroy(srv)
+        return el, hists, stats
+
+    serve(None)                                     # warm-up (code objects, allocations)
+    el_c, _, st_c = serve(None)
+    capacity = len(probs) / el_c
+    rate = 0.8 * capacity
+    arrivals, _ = synth.request_stream(args.count, rate)
+    el_o, hists, st_o = serve(arrivals)
+    xs = [inst.x(q) for q in range(len(probs))]
+    ctx = R.rsp_context_create(0)
+    try:
+        lat1 = []
+        t0 = time.perf_counter()
+        for q in range(len(probs)):
+            ts = time.perf_counter()
+            R.rsp_solve(ctx, P[q], O64, inst.yd[q], inst.f[q], None, None, inst.y[q], inst.p[q], inst.u[q])
+            lat1.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t0
+    finally:
+        R.rsp_context_destroy(ctx)
+    errs = err_report(rel_errs(xs, [inst.x(q) for q in range(len(probs))]))
+    return {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",
+            "value": st_o["solves_per_s"] * errs["within_1e-8"] / len(probs), "unit": "solves/s", "n_gpus": 1,
+            "steps": len(probs), "warmup": 1,
+            "ms_per_step": 1e3 * el_o / len(probs), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
+            "data": "synthetic (seeded Gaussian-bump y_d, Poisson arrivals)",
+            "config": {"workload": "raspen_serve%d_grids127-511_poisson" % len(probs), "requests": len(probs),
+                       "rate_per_s": rate, "load": 0.8, "grids": sorted({(pr.nx, pr.ny) for pr in probs})},
+            "latency_ms": {"p50": st_o["p50_ms"], "p99": st_o["p99_ms"], "mean": st_o["mean_ms"]},
+            "mean_batch": st_o["mean_batch"],
+            "closed_loop": {"solves_per_s": capacity, "p50_ms": st_c["p50_ms"], "p99_ms": st_c["p99_ms"],
+                            "mean_batch": st_c["mean_batch"]},
+            "rel_err_mixed_vs_fp64": errs, "all_solves_per_s": st_o["solves_per_s"],
+            "fp64_one_at_a_time": {"value": len(probs) / el1, "unit": "solves/s", "latency_ms": pct(lat1)},
+            "roofline": None, "cpu_baseline": None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision", "batch", "serve"],
+                    help="plain: 255x255 (default); small: 63x63; precision: 511x511 exp; batch: 64 uneven "
+                         "instances per step; serve: Poisson request stream through the server")
+    ap.add_argument("--count", type=int, default=64, help="instances (batch) or requests (serve)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
                     help="mixed: FP32 line factors + FP64 refinement (the FP64 path is timed beside it)")
     ap.add_argument("--max-refine", type=int, default=0,
@@ -159,6 +397,10 @@ def main():
     import torch
     from paper_2411_00546_amd import raspen as R
     R.load()
+    if args.workload in ("batch", "serve"):
+        run = run_batch_workload if args.workload == "batch" else run_serve_workload
+        print(json.dumps(run(args, R)))
+        return
     prob, opts = workload(args.workload, args.precision, args.max_refine)
     _, opts64 = workload(args.workload, "fp64")
     yd, f = prob.inputs()
@@ -226,28 +468,7 @@ def main():
         R.rsp_context_destroy(ctx)
 
     value = args.steps / elapsed
-    kern = {k: v for k, v in stats.items() if v["launches"] > 0}
-    single = {k: v for k, v in kern.items() if k != "gmres_ortho"}
-    dom = max(single, key=lambda k: single[k]["ms"])
-    d = kern[dom]
-    bound, peak, unit = BOUND[dom]
-    if dom == "factor" and opts.precision == 1:
-        peak = FP32_PEAK_TFLOPS
-    avg_s = d["ms"] / d["launches"] / 1e3
-    if bound == "hbm":
-        achieved = d["bytes"] / d["launches"] / avg_s / 1e9
-    else:
-        achieved = d["flops"] / d["launches"] / avg_s / 1e12
-    tb = traffic_for(dom, d["launches"])
-    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": tb,
-            "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
-            "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
-    kernels = {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
-                   "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
-                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
-                   "GFLOPps": round(v["flops"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
-               for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+    roof, kernels = kernel_roofline(stats, opts.precision == 1)
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob, opts, hist)
     lat_ms = np.array(lat) * 1e3
     out = {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",

@@ -45,7 +45,7 @@ extern "C" {
 #define RSP_OK 0
 #define RSP_NOT_CONVERGED 1     /* iteration limit reached (Algorithms 1 and 2 k_max) */
 #define RSP_LINESEARCH_FAIL 2   /* backtracking went below alpha_min (Algorithm 1) */
-#define RSP_GMRES_STAGNATION 3  /* GMRES hit max_gmres above its tolerance */
+#define RSP_GMRES_STAGNATION 3  /* not converged, and a GMRES solve hit max_gmres above its tolerance */
 #define RSP_REFINE_FALLBACK 4   /* FP32 factors + refinement did not converge */
 #define RSP_EINVAL (-1)
 #define RSP_ENOMEM (-2)

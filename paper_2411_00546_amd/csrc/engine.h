@@ -40,6 +40,7 @@ struct Inst {
   bool started = false;   // first evaluation done
   bool finished = false;  // outputs written, history complete
   int k = 0, status = 0, gm_used = 0, restarts = 0;
+  bool gm_stagnated = false;   // some GMRES solve stopped at max_gmres above its tolerance
   double Fn = 0, thr = 0, gm_rel = 0;
   rsp_history hist{};
   int64_t n_factor = 0, n_solve = 0, n_gmres = 0, n_newton = 0, n_apply = 0;

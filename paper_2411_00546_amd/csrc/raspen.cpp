@@ -666,7 +666,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     }
     in->n_solve += (int64_t)in->part.S * (h.used + in->restarts);
     in->flops += sfl * (h.used + in->restarts);
-    if (!(h.rel <= h.rtol)) in->status = std::max(in->status, (int)RSP_GMRES_STAGNATION);
+    if (!(h.rel <= h.rtol)) in->gm_stagnated = true;
   }
   return 0;
 }
@@ -691,7 +691,9 @@ int finish(rsp_context* ctx, const std::vector<Inst*>& fin, hipStream_t st) {
   const auto now = Clock::now();
   for (Inst* in : fin) {
     rsp_history* h = &in->hist;
-    if (!(in->Fn <= in->thr) && in->status == 0) in->status = RSP_NOT_CONVERGED;
+    // an inexact GMRES solve only matters if the outer iteration then fails to converge
+    if (!(in->Fn <= in->thr) && in->status == 0)
+      in->status = in->gm_stagnated ? RSP_GMRES_STAGNATION : RSP_NOT_CONVERGED;
     h->status = in->status;
     h->outer = in->k;
     h->subdomains = in->part.S;
