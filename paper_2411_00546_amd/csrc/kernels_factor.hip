@@ -8,11 +8,15 @@
 // with T = tridiag(-1/hx^2, 2/hx^2 + 2/hy^2, -1/hx^2), and both off-diagonal
 // blocks are -(1/hy^2) I.  Block LU: S_0 = D_0, S_j = D_j - hy^-4 S_{j-1}^{-1};
 // forward g_j = S_j^{-1}(r_j + hy^-2 g_{j-1}); backward z_j = g_j + hy^-2 S_j^{-1} z_{j+1}.
-// Each S_j^{-1} comes from in-place Gauss-Jordan with partial pivoting (rows are
-// not moved: step k pivots on row pr[k]; afterwards S^{-1}[a][b] = A[pr[a]][pinv[b]]).
-// The line block lives in registers (256 threads, an R x R slice each); per step the
-// pivot is found inside the wave that holds the column, the column goes through LDS
-// (one barrier per step) and the pivot row is broadcast with in-wave shuffles.
+// Each S_j is assembled in LDS and tested for column diagonal dominance.  A dominant
+// S_j (the usual case) is inverted by Gauss-Jordan with 16 x 16 pivot blocks whose
+// block products run on the matrix cores; partial pivoting would keep its diagonal,
+// so this is the same elimination.  A subdomain with a line that is not dominant is
+// redone by a second kernel with in-place Gauss-Jordan with partial pivoting in
+// registers (rows are not moved: step k pivots on row pr[k]; afterwards
+// S^{-1}[a][b] = A[pr[a]][pinv[b]]): per step the pivot is found inside the wave
+// that holds the column, the column goes through LDS (one barrier per step) and the
+// pivot row is broadcast with in-wave shuffles.
 // The inverses are stored transposed, facT[s][j][b][a] = S_j^{-1}[a][b], so that
 // the solves read them coalesced.  Lines are padded to M (multiple of 16) with
 // an identity block.
@@ -63,17 +67,353 @@ __device__ __forceinline__ T row_sum16(T v) {
 }
 
 constexpr int kFacThreads = 256;   // 16 x 16 threads; thread (ti, tj) owns rows ti + 16 rr, cols tj + 16 cc
+static_assert(kMaxTile < kFacThreads, "one thread per node of a line");
 
-// T: arithmetic and storage type of the line inverses (double, or float for the
-// FP32 factors of the mixed-precision form); coefficients and the fused forward
-// sweep stay in double.
+// ---------------------------------------------------------------- MFMA tiles
+// 16 x 16 x 4 matrix-core products (one wave).  Operand A[i][k] sits in lane i + 16 k,
+// operand B[k][j] in lane j + 16 k; the accumulator D[i][j] sits in lane j + 16 g,
+// register r, with i = 4 g + r for float and i = 4 r + g for double.  A product over
+// 16 values of k takes four instructions; instruction q of lane group k0 uses
+// k = kappa(q, k0), with kappa = 4 k0 + q for float and 4 q + k0 for double, so that
+// register q of an accumulator tile is exactly the B operand of instruction q: a
+// result tile feeds the next product from registers.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using V = f32x4;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ int kap(int q, int k0) { return 4 * k0 + q; }
+};
+template <>
+struct Mfma<double> {
+  using V = f64x4;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static __device__ __forceinline__ int kap(int q, int k0) { return 4 * q + k0; }
+};
+
+// Row stride (in elements) that keeps the rows of an LDS matrix 16-byte aligned.
+template <typename T>
+constexpr int padded(int n) { return n + 16 / (int)sizeof(T); }
+
+template <typename T>
+__device__ __forceinline__ void load4(const T* p, T (&v)[4]);
+template <>
+__device__ __forceinline__ void load4<float>(const float* p, float (&v)[4]) {
+  const f32x4 x = *reinterpret_cast<const f32x4*>(p);
+  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+}
+template <>
+__device__ __forceinline__ void load4<double>(const double* p, double (&v)[4]) {
+  const double2 x = reinterpret_cast<const double2*>(p)[0];
+  const double2 y = reinterpret_cast<const double2*>(p)[1];
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+template <typename T>
+__device__ __forceinline__ void store4(T* p, const T (&v)[4]);
+template <>
+__device__ __forceinline__ void store4<float>(float* p, const float (&v)[4]) {
+  f32x4 x;
+  x[0] = v[0]; x[1] = v[1]; x[2] = v[2]; x[3] = v[3];
+  *reinterpret_cast<f32x4*>(p) = x;
+}
+template <>
+__device__ __forceinline__ void store4<double>(double* p, const double (&v)[4]) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// Pivot reciprocal: the hardware reciprocal (1 ulp) for the FP32 factors; for FP64 the
+// hardware estimate refined by two Newton steps r <- r + r (1 - x r) (each squares the
+// relative error).
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// A operand (row-major 16 x 16 tile X, stride ldx) of instruction q.
+template <typename T>
+__device__ __forceinline__ void a_operand(const T* X, int ldx, int lane, T (&a)[4]) {
+  const int i = lane & 15, k0 = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a[q] = X[i * ldx + Mfma<T>::kap(q, k0)];
+}
+// B operand (row-major 16 x 16 tile Y, stride ldy) of instruction q.
+template <typename T>
+__device__ __forceinline__ void b_operand(const T* Y, int ldy, int lane, T (&b)[4]) {
+  const int j = lane & 15, k0 = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b[q] = Y[Mfma<T>::kap(q, k0) * ldy + j];
+}
+// c += sgn a b over the 16 values of k
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::V mma16(const T (&a)[4], const T (&b)[4], T sgn,
+                                                     typename Mfma<T>::V c) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c = Mfma<T>::mma(sgn * a[q], b[q], c);
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::V tile_load(const T* X, int ldx, int lane) {
+  typename Mfma<T>::V c;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c[r] = X[Mfma<T>::row(lane, r) * ldx + (lane & 15)];
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c, int lane) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[Mfma<T>::row(lane, r) * ldx + (lane & 15)] = c[r];
+}
+
+// In-place inverse of the M x M matrix A (LDS, row stride LD, rows 16-byte aligned)
+// by Gauss-Jordan with 16 x 16 pivot blocks taken in order (no pivot search): for
+// pivot block K,
+//   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
+//   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K).
+// This is the partial-pivoting Gauss-Jordan result whenever partial pivoting would
+// keep the diagonal, which holds for column diagonally dominant A (the Schur
+// complements inherit the property).  M / 16 waves; wave J owns column block J:
+// wave K inverts A_KK in place (one wave, LDS), then every other wave forms its
+// row-panel tile A_KK^{-1} A_KJ in registers and updates its column, while wave K
+// forms its new column and writes it once the others have read the old one.
 template <typename T, int M>
-__global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* __restrict__ tilex,
-                                                        const double* __restrict__ c,
-                                                        const SubState* __restrict__ state,
-                                                        double eps_fixed, const double* __restrict__ rhs,
-                                                        double rhs_scale, T* __restrict__ facT,
-                                                        double* __restrict__ gout) {
+__device__ void block_gauss_jordan(T* A, int LD) {
+  constexpr int NB = M / 16;
+  using V = typename Mfma<T>::V;
+  const int t = threadIdx.x, lane = t & 63, J = t >> 6;
+#pragma unroll 1
+  for (int K = 0; K < NB; ++K) {
+    T* AKK = A + 16 * K * LD + 16 * K;
+    if (J == K) {
+      // lane (i, q4) owns row i, columns 4 q4 .. 4 q4 + 3 of the pivot block and keeps
+      // them in registers; each step reads the pivot row and column written by the
+      // step before (one wave's LDS accesses complete in order)
+      const int i = lane & 15, q4 = lane >> 4;
+      T own[4];
+      load4<T>(AKK + i * LD + 4 * q4, own);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        T prow[4];
+        load4<T>(AKK + k * LD + 4 * q4, prow);
+        const T pcol = AKK[i * LD + k];
+        const T inv = recip(AKK[k * LD + k]);
+        const bool on_row = i == k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool on_col = 4 * q4 + q == k;
+          const T tr = prow[q] * inv;
+          own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
+        }
+        store4<T>(AKK + i * LD + 4 * q4, own);
+      }
+    }
+    __syncthreads();
+    V acc[NB];
+    if (J != K) {
+      // row-panel tile R = A_KK^{-1} A_KJ, then column J: A_IJ -= A_IK R, A_KJ = R
+      T a[4], b[4];
+      a_operand<T>(AKK, LD, lane, a);
+      b_operand<T>(A + 16 * K * LD + 16 * J, LD, lane, b);
+      V r = {0, 0, 0, 0};
+      r = mma16<T>(a, b, (T)1, r);
+      T rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rb[q] = r[q];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        T* AIJ = A + 16 * I * LD + 16 * J;
+        if (I == K) {
+          tile_store<T>(AIJ, LD, r, lane);
+        } else {
+          T ai[4];
+          a_operand<T>(A + 16 * I * LD + 16 * K, LD, lane, ai);
+          V c = tile_load<T>(AIJ, LD, lane);
+          c = mma16<T>(ai, rb, (T)-1, c);
+          tile_store<T>(AIJ, LD, c, lane);
+        }
+      }
+    } else {
+      // new column K: A_IK <- -A_IK A_KK^{-1} (I != K); A_KK already holds the inverse
+      T b[4];
+      b_operand<T>(AKK, LD, lane, b);
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        if (I == K) continue;
+        T ai[4];
+        a_operand<T>(A + 16 * I * LD + 16 * K, LD, lane, ai);
+        V c = {0, 0, 0, 0};
+        acc[I] = mma16<T>(ai, b, (T)-1, c);
+      }
+    }
+    __syncthreads();
+    if (J == K) {
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+        if (I != K) tile_store<T>(A + 16 * I * LD + 16 * K, LD, acc[I], lane);
+    }
+  }
+  __syncthreads();
+}
+
+// The usual path: S_j is assembled in LDS (S_j = D_j - hy^-4 S_{j-1}^{-1}, in place over
+// the previous inverse) together with its column sums, checked for column diagonal
+// dominance and inverted by the blocked Gauss-Jordan on the matrix cores.  A
+// subdomain with a line that is not dominant stops at that line and is marked in
+// fallback[s] for k_factor_pivot.  M / 16 waves.
+template <typename T, int M>
+__global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __restrict__ tilex,
+                                                       const double* __restrict__ c,
+                                                       const SubState* __restrict__ state,
+                                                       double eps_fixed, const double* __restrict__ rhs,
+                                                       double rhs_scale, T* __restrict__ facT,
+                                                       double* __restrict__ gout, int* __restrict__ fallback) {
+  constexpr int NT = 4 * M;             // 64 threads per column block
+  constexpr int LD = padded<T>(M);
+  constexpr int KC = M / 4;             // the forward sweep adds each row in 4 parts
+  __shared__ __attribute__((aligned(16))) T Mx[M * LD];   // S_j, then S_j^{-1}
+  __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
+  __shared__ double vin[M], gprev[M];
+  __shared__ double part[4 * M];
+
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) fallback[s] = 0;
+  double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
+  if (state) {
+    if (!state[s].active) return;
+    eps = state[s].eps;
+  }
+  const int4 bx = I.box[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const int m = 2 * tx;
+  const T nh4 = (T)(-P.hy2i * P.hy2i);
+  for (int i = t; i < M; i += NT) gprev[i] = 0.0;
+  // thread a < tx keeps (y, p) of node a of the next line in registers, so that the
+  // HBM loads overlap the work of the current line
+  auto state_at = [&](int jj, double& y, double& p) {
+    y = tilex[halo_idx(P, s, 0, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 0, jj, t)] : 0.0);
+    p = tilex[halo_idx(P, s, 1, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 1, jj, t)] : 0.0);
+  };
+  double ynext = 0.0, pnext = 0.0;
+  if (t < tx) state_at(0, ynext, pnext);
+
+  for (int j = 0; j < ty; ++j) {
+    // coefficients of line j at z = R_i x + c
+    if (t < tx) {
+      const double y = ynext, p = pnext;
+      if (j + 1 < ty) state_at(j + 1, ynext, pnext);
+      la[t] = dphi_of(P.phi, y, P.kappa);
+      lb[t] = dg_of(p, P.mu, eps) * P.inv_nu;
+      lc[t] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
+    }
+    __syncthreads();
+    // S_j = D_j - hy^-4 S_{j-1}^{-1} (identity padding), column b = 16 wave + (lane & 15),
+    // rows (lane >> 4) + 4 r; column sums of |S_ab| (a != b) reduced inside the wave
+    bool bad;
+    {
+      const int b = 16 * wave + (lane & 15), rg = lane >> 4;
+      const int fc = b >= tx, bc = b - fc * tx;
+      T off = 0, dia = 0;
+#pragma unroll 4
+      for (int r = 0; r < M / 4; ++r) {
+        const int a = rg + 4 * r;
+        T v;
+        if (a < m && b < m) {
+          const int fr = a >= tx, ar = a - fr * tx;
+          double d = 0.0;
+          if (fr == fc) {
+            if (ar == bc) d = P.diag0 + la[ar];
+            else if (ar == bc + 1 || bc == ar + 1) d = -P.hx2i;
+          } else if (ar == bc) {
+            d = fr == 0 ? lb[ar] : lc[ar];
+          }
+          v = (j > 0 ? nh4 * Mx[a * LD + b] : (T)0) + (T)d;
+        } else {
+          v = (T)(a == b ? 1 : 0);
+        }
+        Mx[a * LD + b] = v;
+        if (a == b) dia = fabs(v);
+        else off += fabs(v);
+      }
+      off += __shfl_xor(off, 16, 64);
+      off += __shfl_xor(off, 32, 64);
+      dia += __shfl_xor(dia, 16, 64);
+      dia += __shfl_xor(dia, 32, 64);
+      bad = b < m && !(dia >= off);
+    }
+    if (__syncthreads_or(bad)) {
+      if (t == 0) fallback[s] = 1;
+      return;
+    }
+    block_gauss_jordan<T, M>(Mx, LD);
+    // fused forward sweep: g_j = S_j^{-1}(rhs_scale r_j + hy^-2 g_{j-1})
+    if (rhs) {
+      for (int i = t; i < M; i += NT) {
+        double rv = 0.0;
+        if (i < m) {
+          const int f = i >= tx;
+          rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
+        }
+        vin[i] = rv + P.hy2i * gprev[i];
+      }
+      __syncthreads();
+      {
+        const int row_i = t % M, g = t / M;
+        const T* row = Mx + row_i * LD + g * KC;
+        double acc = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < KC; ++k) acc += (double)row[k] * vin[g * KC + k];
+        part[g * M + row_i] = acc;
+      }
+      __syncthreads();
+      if (t < M) {
+        const double acc = part[t] + part[M + t] + part[2 * M + t] + part[3 * M + t];
+        gprev[t] = acc;
+        gout[((size_t)s * P.tym + j) * M + t] = acc;
+      }
+    }
+    // store S_j^{-1} transposed: facT[b][a] = S_j^{-1}[a][b]
+    T* F = facT + ((size_t)s * P.tym + j) * M * M;
+    for (int e = t; e < M * M / 4; e += NT) {
+      const int b = e / (M / 4), a0 = 4 * (e - b * (M / 4));
+      T v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = Mx[(a0 + q) * LD + b];
+      store4<T>(F + (size_t)b * M + a0, v);
+    }
+    __syncthreads();
+  }
+}
+
+// Fallback for subdomains with a line block that is not column diagonally dominant
+// (only the items with only[s] != 0): in-place Gauss-Jordan with partial pivoting in
+// registers.  T: arithmetic and storage type of the line inverses (double, or float
+// for the FP32 factors of the mixed-precision form); coefficients and the fused
+// forward sweep stay in double.
+template <typename T, int M>
+__global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const double* __restrict__ tilex,
+                                                              const double* __restrict__ c,
+                                                              const SubState* __restrict__ state,
+                                                              double eps_fixed, const double* __restrict__ rhs,
+                                                              double rhs_scale, T* __restrict__ facT,
+                                                              double* __restrict__ gout,
+                                                              const int* __restrict__ only) {
   constexpr int R = M / 16;          // rows (and columns) of the line block per thread
   constexpr int LD = M + 1;
   __shared__ T Mx[M * LD];      // finished in-place Gauss-Jordan result of the line
@@ -83,11 +423,11 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* _
   __shared__ int pr[2][M], pinv[2][M];
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
   __shared__ double vin[M], gprev[M];
-  __shared__ int nondom;
 
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
+  if (!only[s]) return;
   const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
   const int lane = t & 63;
   double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
@@ -105,7 +445,6 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* _
 
   for (int j = 0; j < ty; ++j) {
     const int pj = j & 1, pp = pj ^ 1;
-    if (t == 0) nondom = 0;
     // coefficients of line j at z = R_i x + c
     for (int a = t; a < tx; a += kFacThreads) {
       const double y = tilex[halo_idx(P, s, 0, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 0, j, a)] : 0.0);
@@ -141,77 +480,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* _
         A[rr][cc] = (T)d;
       }
     }
-    // Column diagonal dominance |S_kk| >= sum_{i != k} |S_ik| of the active block:
-    // then Gauss-Jordan with partial pivoting keeps every diagonal pivot (the
-    // property is inherited by the Schur complements), so the static-pivot steps
-    // below compute exactly what the pivoted ones would.
     {
-      bool bad = false;
-#pragma unroll
-      for (int cc = 0; cc < R; ++cc) {
-        const int b = tj + 16 * cc;
-        T off = 0, dia = 0;
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-          const T v = fabs(A[rr][cc]);
-          const bool d = (ti + 16 * rr) == b;
-          dia += d ? v : (T)0;
-          off += d ? (T)0 : v;
-        }
-        off = row_sum16(off);
-        dia = row_sum16(dia);
-        bad |= (b < m) & !(dia >= off);
-      }
-      if (bad) nondom = 1;
-    }
-    __syncthreads();
-    if (!nondom) {
-      // static pivots: step k eliminates with row k
-#pragma unroll
-      for (int ck = 0; ck < R; ++ck) {
-        for (int kk = 0; kk < 16; ++kk) {
-          const int k = 16 * ck + kk;
-          if (k >= m) break;
-          const int pb = k & 1;
-          if (tj == kk) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) colb[pb][ti + 16 * rr] = A[rr][ck];
-            if (ti == kk) {
-              pivv[pb][0] = A[ck][ck];
-              pivv[pb][1] = (T)1 / A[ck][ck];
-            }
-          }
-          __syncthreads();
-          const T ipiv = pivv[pb][1];
-          T rs[R], mult[R];
-#pragma unroll
-          for (int cc = 0; cc < R; ++cc) rs[cc] = __shfl(A[ck][cc], (lane & 48) | kk, 64) * ipiv;
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr) mult[rr] = colb[pb][ti + 16 * rr];
-#pragma unroll
-          for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-            for (int cc = 0; cc < R; ++cc) A[rr][cc] = fma(-mult[rr], rs[cc], A[rr][cc]);
-          // the pivot row becomes row / piv (assigned, not updated: the update would
-          // cancel catastrophically for |piv| >> 1)
-          if (ti == kk) {
-#pragma unroll
-            for (int cc = 0; cc < R; ++cc) A[ck][cc] = rs[cc];
-          }
-          if (tj == kk) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-              const T cv = colb[pb][ti + 16 * rr];
-              A[rr][ck] = (rr == ck && ti == kk) ? ipiv : -cv * ipiv;
-            }
-          }
-        }
-      }
-      for (int k = t; k < m; k += kFacThreads) {
-        pr[pj][k] = k;
-        pinv[pj][k] = k;
-      }
-    } else {
       unsigned used = 0;                 // bit rr: row ti + 16 rr already pivoted
       // in-place Gauss-Jordan with partial pivoting over the m active columns
 #pragma unroll
@@ -362,18 +631,22 @@ __global__ __launch_bounds__(kFacThreads) void k_factor(Items I, const double* _
 
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   hipStream_t st) {
+                   int* fallback, hipStream_t st) {
   if (I.count <= 0) return;
   if (fp32) {
-#define RSP_CALL(MM)                                                                                  \
-  k_factor<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                       (float*)facT, g)
+#define RSP_CALL(MM)                                                                                   \
+  k_factor_mfma<float, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,        \
+                                                            rhs_scale, (float*)facT, g, fallback);     \
+  k_factor_pivot<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
+                                                             rhs_scale, (float*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                        (double*)facT, g)
+  k_factor_mfma<double, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
+                                                             rhs_scale, (double*)facT, g, fallback);   \
+  k_factor_pivot<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,      \
+                                                              rhs_scale, (double*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }

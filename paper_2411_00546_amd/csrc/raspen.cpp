@@ -185,6 +185,7 @@ struct Work {
   int4 *box = nullptr, *core = nullptr;   // [S]
   int* inst = nullptr;                    // [S]
   SubState* state = nullptr;              // [S]
+  int* fallback = nullptr;                // [S] factor fallback flags
   int* list[kLists] = {};                 // [S] item lists
   double *F = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr, *r = nullptr;   // [2 ntot]
   double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
@@ -213,6 +214,7 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->core = cv.take<int4>(S);
   w->inst = cv.take<int>(S);
   w->state = cv.take<SubState>(S);
+  w->fallback = cv.take<int>(S);
   for (auto& l : w->list) l = cv.take<int>(S);
   w->F = cv.take<double>(L);
   w->w = cv.take<double>(L);
@@ -497,7 +499,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
     for (int b = 0; b < batch; ++b) {
       {
         Timed t(ctx, KID_FACTOR, st, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
-        rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g, st);
+        rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g, w.fallback, st);
       }
       {
         Timed t(ctx, KID_SOLVE_BWD, st, sw.bwd_fl, sw.bwd_by);
@@ -547,7 +549,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
   // factor at x^(i) = x + P_i C_i(x) for Algorithm 4
   {
     Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
-    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, st);
+    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, w.fallback, st);
   }
   {
     Timed t(ctx, KID_PROLONG, st, 0, all.tile_by * 2);
@@ -1104,7 +1106,7 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
   const Items I = all_items(ctx);
   rsp::launch_restrict_halo(I, x, ctx->w.tilex, stream);
   rsp::launch_factor(I, ctx->geo.M, ctx->w.tilex, c, nullptr, eps, nullptr, 0.0, ctx->w.fac, ctx->fp32,
-                     ctx->w.g, stream);
+                     ctx->w.g, ctx->w.fallback, stream);
   rsp::launch_block_solve(I, ctx->geo.M, ctx->w.fac, ctx->fp32, rhs, z, stream);
   HIPCHK(hipGetLastError());
   return 0;

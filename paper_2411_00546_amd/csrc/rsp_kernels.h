@@ -29,10 +29,11 @@ void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t s
 // a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1},
 // stored as double, or as float when fp32 != 0 (facT points to that type).  The
 // smoothing is state[s].eps (state != nullptr; inactive items are skipped), else
-// eps_fixed when > 0, else the instance's eps_min.
+// eps_fixed when > 0, else the instance's eps_min.  fallback: [items] scratch flags
+// (subdomains redone with partial pivoting).
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   hipStream_t st);
+                   int* fallback, hipStream_t st);
 // a5: backward sweep after a fused forward sweep.
 void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
                       const double* g, double* out, hipStream_t st);

@@ -126,8 +126,11 @@ def test_batch_bitwise_equals_single_solves(R, precision, restart):
     assert len({tuple(h["gmres_its"]) for h in hists}) > 1
 
 
+# nu = 1e-4 on a 23 x 17 grid: 1/nu exceeds the 2/hy^2 margin, so line blocks of the
+# local Jacobians lose column diagonal dominance and those subdomains take the
+# partial-pivoting factorisation, in the same launches as the others
 MIXED = [
-    prob(23, 17, 3, 2, 2, seed=21),
+    prob(23, 17, 3, 2, 2, nu=1e-4, seed=21),
     prob(31, 31, 2, 2, 2, phi=synth.PHI_EXP, mu=0.0, seed=22),
     prob(12, 9, 1, 1, 2, phi=synth.PHI_PAPER, seed=23),
     prob(37, 29, 3, 4, 3, nu=3e-3, mu=2e-2, seed=24),
