@@ -31,10 +31,6 @@ BOUND = {"factor": ("alu", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm", 
          "linesearch": ("hbm", HBM_PEAK_GBS, "GB/s"), "prolong": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "ring_rhs": ("hbm", HBM_PEAK_GBS, "GB/s"), "restrict_halo": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "newton_init": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_residual": ("hbm", HBM_PEAK_GBS, "GB/s")}
-KERNEL_SOURCES = {"factor": "kernels_factor.hip", "block_solve": "kernels_factor.hip",
-                  "solve_bwd": "kernels_factor.hip"}
-
-
 def workload(name, precision="fp64", max_refine=0):
     import synth
     prob = synth.config_by_name(name)
@@ -54,19 +50,19 @@ def describe(prob, opts):
             "seed": prob.seed, "unknowns": 2 * prob.nx * prob.ny}
 
 
-def traffic_for(kernel, launches):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were taken on
-    the current source of the kernel (else None)."""
+def traffic_for(kernel, fp32):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size)
+    from the committed rocprofv3 counters, when they were taken on the current source
+    of the kernel and for the same factor precision (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = KERNEL_SOURCES.get(kernel)
-    if not os.path.exists(path) or src is None:
+    if not os.path.exists(path):
         return None
     data = json.load(open(path))
-    ent = data.get(kernel)
+    ent = data.get(kernel + ("/fp32" if fp32 else "/fp64")) or data.get(kernel)
     if not ent:
         return None
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2411_00546_amd", "csrc", src), "rb").read()).hexdigest()
-    if ent.get("source_sha256") != sha:
+    src = os.path.join(ROOT, "paper_2411_00546_amd", "csrc", ent["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != ent.get("source_sha256"):
         return None
     return ent.get("bytes_per_launch")
 
@@ -149,7 +145,7 @@ def kernel_roofline(stats, fp32):
     else:
         achieved = d["flops"] / d["launches"] / avg_s / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic_for(dom, d["launches"]),
+            "frac": achieved / peak, "traffic": traffic_for(dom, fp32),
             "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
             "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
     kernels = {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
@@ -384,8 +380,9 @@ def main():
                          "refines against its FP64 residual in any case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
-                    help="profiling mode: run N residual evaluations with continuation at x = 0 "
-                         "and 20 Jacobian actions of the workload instead of whole solves")
+                    help="profiling mode: run N residual evaluations with continuation at x = 0, "
+                         "20 Jacobian actions of the workload and 3 plain 64 MiB device copies "
+                         "(traffic-counter calibration) instead of whole solves")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -426,6 +423,13 @@ def main():
                 R.rsp_jac_apply(ctx, d, out)
             torch.cuda.synchronize()
             print("20 Jacobian actions done", flush=True)
+            # a plain device copy of 64 MiB, the calibration of the HBM traffic counters
+            src = torch.ones(8 << 20, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            print("3 copies of %d bytes done" % (src.numel() * 8), flush=True)
         finally:
             R.rsp_context_destroy(ctx)
         return
