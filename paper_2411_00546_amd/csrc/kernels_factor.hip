@@ -185,48 +185,101 @@ __device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c,
 //   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
 //   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K).
 // This is the partial-pivoting Gauss-Jordan result whenever partial pivoting would
-// keep the diagonal, which holds for column diagonally dominant A (the Schur
-// complements inherit the property).  M / 16 waves; wave J owns column block J:
-// wave K inverts A_KK in place (one wave, LDS), then every other wave forms its
-// row-panel tile A_KK^{-1} A_KJ in registers and updates its column, while wave K
-// forms its new column and writes it once the others have read the old one.
-template <typename T, int M>
-__device__ void block_gauss_jordan(T* A, int LD) {
+// keep the diagonal: for column diagonally dominant A always (the Schur complements
+// inherit the property).  M / 16 waves; wave J owns column block J.
+//
+// PANEL = false: wave K inverts A_KK in place (one wave, LDS), then every other wave
+// forms its row-panel tile A_KK^{-1} A_KJ in registers and updates its column, while
+// wave K forms its new column and writes it once the others have read the old one.
+//
+// PANEL = true: wave K eliminates the whole column panel A[:, K] (a copy in Pn), which
+// gives A_KK^{-1} and the new column K at once and every multiplier a_ik / a_kk of the
+// elimination in natural order; if one exceeds 1 in magnitude for an unpivoted row,
+// partial pivoting would have swapped rows, and the function returns true (A is then
+// left partly eliminated).  Returns false otherwise.
+template <typename T, int M, bool PANEL>
+__device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
   constexpr int NB = M / 16;
+  constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
   const int t = threadIdx.x, lane = t & 63, J = t >> 6;
+  if (PANEL && t == 0) *flag = 0;
 #pragma unroll 1
   for (int K = 0; K < NB; ++K) {
     T* AKK = A + 16 * K * LD + 16 * K;
+    const T* Pinv = AKK;          // where the other waves find A_KK^{-1}
+    int ldp = LD;
+    if (PANEL) {
+      Pinv = Pn + 16 * K * PLD;
+      ldp = PLD;
+    }
     if (J == K) {
-      // lane (i, q4) owns row i, columns 4 q4 .. 4 q4 + 3 of the pivot block and keeps
-      // them in registers; each step reads the pivot row and column written by the
-      // step before (one wave's LDS accesses complete in order)
-      const int i = lane & 15, q4 = lane >> 4;
-      T own[4];
-      load4<T>(AKK + i * LD + 4 * q4, own);
+      const int li = lane & 15, q4 = lane >> 4;
+      if (!PANEL) {
+        // lane (li, q4) owns row li, columns 4 q4 .. 4 q4 + 3 of the pivot block and
+        // keeps them in registers; each step reads the pivot row and column written by
+        // the step before (one wave's LDS accesses complete in order)
+        T own[4];
+        load4<T>(AKK + li * LD + 4 * q4, own);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        T prow[4];
-        load4<T>(AKK + k * LD + 4 * q4, prow);
-        const T pcol = AKK[i * LD + k];
-        const T inv = recip(AKK[k * LD + k]);
-        const bool on_row = i == k;
+        for (int k = 0; k < 16; ++k) {
+          T prow[4];
+          load4<T>(AKK + k * LD + 4 * q4, prow);
+          const T pcol = AKK[li * LD + k];
+          const T inv = recip(AKK[k * LD + k]);
+          const bool on_row = li == k;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const bool on_col = 4 * q4 + q == k;
-          const T tr = prow[q] * inv;
-          own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
+          for (int q = 0; q < 4; ++q) {
+            const bool on_col = 4 * q4 + q == k;
+            const T tr = prow[q] * inv;
+            own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
+          }
+          store4<T>(AKK + li * LD + 4 * q4, own);
         }
-        store4<T>(AKK + i * LD + 4 * q4, own);
+      } else {
+        // lane (li, q4) owns rows li + 16 r (r < NB), columns 4 q4 .. 4 q4 + 3 of the panel
+        T own[NB][4];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          load4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, own[r]);
+          store4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, own[r]);
+        }
+        bool swap = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int kk = 16 * K + k;               // pivot row
+          T prow[4];
+          load4<T>(Pn + kk * PLD + 4 * q4, prow);
+          T pcol[NB];
+#pragma unroll
+          for (int r = 0; r < NB; ++r) pcol[r] = Pn[(li + 16 * r) * PLD + k];
+          const T piv = Pn[kk * PLD + k];
+          const T inv = recip(piv);
+#pragma unroll
+          for (int r = 0; r < NB; ++r) {
+            const int i = li + 16 * r;
+            swap |= i > kk && fabs(pcol[r]) > fabs(piv);
+            const bool on_row = i == kk;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const bool on_col = 4 * q4 + q == k;
+              const T tr = prow[q] * inv;
+              own[r][q] = on_col ? (on_row ? inv : -pcol[r] * inv)
+                                 : (on_row ? tr : fma(-pcol[r], tr, own[r][q]));
+            }
+            store4<T>(Pn + i * PLD + 4 * q4, own[r]);
+          }
+        }
+        if (__any(swap) && lane == 0) *flag = 1;
       }
     }
     __syncthreads();
+    if (PANEL && *flag) return true;
     V acc[NB];
     if (J != K) {
       // row-panel tile R = A_KK^{-1} A_KJ, then column J: A_IJ -= A_IK R, A_KJ = R
       T a[4], b[4];
-      a_operand<T>(AKK, LD, lane, a);
+      a_operand<T>(Pinv, ldp, lane, a);
       b_operand<T>(A + 16 * K * LD + 16 * J, LD, lane, b);
       V r = {0, 0, 0, 0};
       r = mma16<T>(a, b, (T)1, r);
@@ -246,7 +299,7 @@ __device__ void block_gauss_jordan(T* A, int LD) {
           tile_store<T>(AIJ, LD, c, lane);
         }
       }
-    } else {
+    } else if (!PANEL) {
       // new column K: A_IK <- -A_IK A_KK^{-1} (I != K); A_KK already holds the inverse
       T b[4];
       b_operand<T>(AKK, LD, lane, b);
@@ -261,26 +314,44 @@ __device__ void block_gauss_jordan(T* A, int LD) {
     }
     __syncthreads();
     if (J == K) {
+      if (!PANEL) {
 #pragma unroll
-      for (int I = 0; I < NB; ++I)
-        if (I != K) tile_store<T>(A + 16 * I * LD + 16 * K, LD, acc[I], lane);
+        for (int I = 0; I < NB; ++I)
+          if (I != K) tile_store<T>(A + 16 * I * LD + 16 * K, LD, acc[I], lane);
+      } else {
+        // the eliminated panel is the new column K (A_KK^{-1} in rows K)
+        const int li = lane & 15, q4 = lane >> 4;
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          T v[4];
+          load4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, v);
+          store4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, v);
+        }
+      }
     }
   }
   __syncthreads();
+  return false;
 }
 
-// The usual path: S_j is assembled in LDS (S_j = D_j - hy^-4 S_{j-1}^{-1}, in place over
-// the previous inverse) together with its column sums, checked for column diagonal
-// dominance and inverted by the blocked Gauss-Jordan on the matrix cores.  A
-// subdomain with a line that is not dominant stops at that line and is marked in
-// fallback[s] for k_factor_pivot.  M / 16 waves.
+// The usual path, two-ended (twisted) block LU over the lines of the tile, t = ty / 2:
+// workgroup blockIdx.y = 0 factors lines 0 .. t-1 from the top (S_j = D_j - hy^-4
+// S_{j-1}^{-1}), workgroup 1 lines ty-1 .. t+1 from the bottom (T_j = D_j - hy^-4
+// T_{j+1}^{-1}); the second of them to finish factors the twist line Z_t = D_t -
+// hy^-4 (S_{t-1}^{-1} + T_{t+1}^{-1}).  Each line block is assembled in LDS with its
+// column sums, checked for column diagonal dominance and inverted by the blocked
+// Gauss-Jordan on the matrix cores.  The fused sweep gives g_j (top), h_j (bottom) and
+// z_t = Z_t^{-1}(r_t + hy^-2 (g_{t-1} + h_{t+1})) for the Newton right-hand side.  A
+// subdomain with a line that is not dominant is marked in fallback[s] and redone by
+// k_factor_pivot.  M / 16 waves per workgroup.
 template <typename T, int M>
 __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __restrict__ tilex,
                                                        const double* __restrict__ c,
                                                        const SubState* __restrict__ state,
                                                        double eps_fixed, const double* __restrict__ rhs,
                                                        double rhs_scale, T* __restrict__ facT,
-                                                       double* __restrict__ gout, int* __restrict__ fallback) {
+                                                       double* __restrict__ gout, int* __restrict__ fallback,
+                                                       int* __restrict__ counter) {
   constexpr int NT = 4 * M;             // 64 threads per column block
   constexpr int LD = padded<T>(M);
   constexpr int KC = M / 4;             // the forward sweep adds each row in 4 parts
@@ -288,108 +359,103 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
   __shared__ double vin[M], gprev[M];
   __shared__ double part[4 * M];
+  __shared__ int flag;
+  __shared__ __attribute__((aligned(16))) T Pn[M * padded<T>(16)];   // column panel of the twist line
 
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  if (t == 0) fallback[s] = 0;
   double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
   if (state) {
     if (!state[s].active) return;
     eps = state[s].eps;
   }
   const int4 bx = I.box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z, tw = ty / 2;
   const int m = 2 * tx;
-  const T nh4 = (T)(-P.hy2i * P.hy2i);
+  const double hy4i = P.hy2i * P.hy2i;
+  const T nh4 = (T)(-hy4i);
+  const int half = blockIdx.y;
+  const int j0 = half == 0 ? 0 : ty - 1, dir = half == 0 ? 1 : -1;
+  const int nlines = half == 0 ? tw : ty - 1 - tw;
+  T* Fs = facT + (size_t)s * P.tym * M * M;
+  double* gs = gout + (size_t)s * P.tym * M;
   for (int i = t; i < M; i += NT) gprev[i] = 0.0;
-  // thread a < tx keeps (y, p) of node a of the next line in registers, so that the
-  // HBM loads overlap the work of the current line
+
   auto state_at = [&](int jj, double& y, double& p) {
     y = tilex[halo_idx(P, s, 0, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 0, jj, t)] : 0.0);
     p = tilex[halo_idx(P, s, 1, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 1, jj, t)] : 0.0);
   };
-  double ynext = 0.0, pnext = 0.0;
-  if (t < tx) state_at(0, ynext, pnext);
-
-  for (int j = 0; j < ty; ++j) {
-    // coefficients of line j at z = R_i x + c
-    if (t < tx) {
-      const double y = ynext, p = pnext;
-      if (j + 1 < ty) state_at(j + 1, ynext, pnext);
-      la[t] = dphi_of(P.phi, y, P.kappa);
-      lb[t] = dg_of(p, P.mu, eps) * P.inv_nu;
-      lc[t] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
+  auto coefficients = [&](double y, double p) {
+    la[t] = dphi_of(P.phi, y, P.kappa);
+    lb[t] = dg_of(p, P.mu, eps) * P.inv_nu;
+    lc[t] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
+  };
+  // Line block of line j: D_j + (mode 0: nothing; 1: hy^-4 times -(the previous inverse
+  // in Mx); 2: Mx as it stands), identity padding, column sums; returns true when some
+  // active column is not dominant.  Column b = 16 wave + (lane & 15), rows (lane >> 4) + 4 r.
+  auto build = [&](int mode) -> bool {
+    const int b = 16 * wave + (lane & 15), rg = lane >> 4;
+    const int fc = b >= tx, bc = b - fc * tx;
+    T off = 0, dia = 0;
+#pragma unroll 4
+    for (int r = 0; r < M / 4; ++r) {
+      const int a = rg + 4 * r;
+      T v;
+      if (a < m && b < m) {
+        const int fr = a >= tx, ar = a - fr * tx;
+        double d = 0.0;
+        if (fr == fc) {
+          if (ar == bc) d = P.diag0 + la[ar];
+          else if (ar == bc + 1 || bc == ar + 1) d = -P.hx2i;
+        } else if (ar == bc) {
+          d = fr == 0 ? lb[ar] : lc[ar];
+        }
+        const T prev = Mx[a * LD + b];
+        v = (mode == 0 ? (T)0 : (mode == 1 ? nh4 * prev : prev)) + (T)d;
+      } else {
+        v = (T)(a == b ? 1 : 0);
+      }
+      Mx[a * LD + b] = v;
+      if (a == b) dia = fabs(v);
+      else off += fabs(v);
+    }
+    off += __shfl_xor(off, 16, 64);
+    off += __shfl_xor(off, 32, 64);
+    dia += __shfl_xor(dia, 16, 64);
+    dia += __shfl_xor(dia, 32, 64);
+    return __syncthreads_or(b < m && !(dia >= off)) != 0;
+  };
+  // fused sweep: y = S^{-1}(rhs_scale r_j + extra), extra in vin on entry; y -> gprev, gout
+  auto solve_line = [&](int j) {
+    for (int i = t; i < M; i += NT) {
+      double rv = 0.0;
+      if (i < m) {
+        const int f = i >= tx;
+        rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
+      }
+      vin[i] += rv;
     }
     __syncthreads();
-    // S_j = D_j - hy^-4 S_{j-1}^{-1} (identity padding), column b = 16 wave + (lane & 15),
-    // rows (lane >> 4) + 4 r; column sums of |S_ab| (a != b) reduced inside the wave
-    bool bad;
     {
-      const int b = 16 * wave + (lane & 15), rg = lane >> 4;
-      const int fc = b >= tx, bc = b - fc * tx;
-      T off = 0, dia = 0;
+      const int row_i = t % M, g = t / M;
+      const T* row = Mx + row_i * LD + g * KC;
+      double acc = 0.0;
 #pragma unroll 4
-      for (int r = 0; r < M / 4; ++r) {
-        const int a = rg + 4 * r;
-        T v;
-        if (a < m && b < m) {
-          const int fr = a >= tx, ar = a - fr * tx;
-          double d = 0.0;
-          if (fr == fc) {
-            if (ar == bc) d = P.diag0 + la[ar];
-            else if (ar == bc + 1 || bc == ar + 1) d = -P.hx2i;
-          } else if (ar == bc) {
-            d = fr == 0 ? lb[ar] : lc[ar];
-          }
-          v = (j > 0 ? nh4 * Mx[a * LD + b] : (T)0) + (T)d;
-        } else {
-          v = (T)(a == b ? 1 : 0);
-        }
-        Mx[a * LD + b] = v;
-        if (a == b) dia = fabs(v);
-        else off += fabs(v);
-      }
-      off += __shfl_xor(off, 16, 64);
-      off += __shfl_xor(off, 32, 64);
-      dia += __shfl_xor(dia, 16, 64);
-      dia += __shfl_xor(dia, 32, 64);
-      bad = b < m && !(dia >= off);
+      for (int k = 0; k < KC; ++k) acc += (double)row[k] * vin[g * KC + k];
+      part[g * M + row_i] = acc;
     }
-    if (__syncthreads_or(bad)) {
-      if (t == 0) fallback[s] = 1;
-      return;
+    __syncthreads();
+    if (t < M) {
+      const double acc = part[t] + part[M + t] + part[2 * M + t] + part[3 * M + t];
+      gprev[t] = acc;
+      gs[(size_t)j * M + t] = acc;
     }
-    block_gauss_jordan<T, M>(Mx, LD);
-    // fused forward sweep: g_j = S_j^{-1}(rhs_scale r_j + hy^-2 g_{j-1})
-    if (rhs) {
-      for (int i = t; i < M; i += NT) {
-        double rv = 0.0;
-        if (i < m) {
-          const int f = i >= tx;
-          rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
-        }
-        vin[i] = rv + P.hy2i * gprev[i];
-      }
-      __syncthreads();
-      {
-        const int row_i = t % M, g = t / M;
-        const T* row = Mx + row_i * LD + g * KC;
-        double acc = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < KC; ++k) acc += (double)row[k] * vin[g * KC + k];
-        part[g * M + row_i] = acc;
-      }
-      __syncthreads();
-      if (t < M) {
-        const double acc = part[t] + part[M + t] + part[2 * M + t] + part[3 * M + t];
-        gprev[t] = acc;
-        gout[((size_t)s * P.tym + j) * M + t] = acc;
-      }
-    }
-    // store S_j^{-1} transposed: facT[b][a] = S_j^{-1}[a][b]
-    T* F = facT + ((size_t)s * P.tym + j) * M * M;
+  };
+  // S^{-1} of line j, transposed: facT[j][b][a] = S^{-1}[a][b]
+  auto store = [&](int j) {
+    T* F = Fs + (size_t)j * M * M;
     for (int e = t; e < M * M / 4; e += NT) {
       const int b = e / (M / 4), a0 = 4 * (e - b * (M / 4));
       T v[4];
@@ -398,7 +464,66 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       store4<T>(F + (size_t)b * M + a0, v);
     }
     __syncthreads();
+  };
+
+  // this workgroup's half; thread a < tx keeps (y, p) of node a of the next line in
+  // registers, so that the HBM loads overlap the work of the current line
+  bool bad = false;
+  double ynext = 0.0, pnext = 0.0;
+  if (nlines > 0 && t < tx) state_at(j0, ynext, pnext);
+  for (int k = 0; k < nlines; ++k) {
+    const int j = j0 + dir * k;
+    if (t < tx) {
+      const double y = ynext, p = pnext;
+      if (k + 1 < nlines) state_at(j + dir, ynext, pnext);
+      coefficients(y, p);
+    }
+    __syncthreads();
+    if (build(k == 0 ? 0 : 1)) {
+      bad = true;
+      break;
+    }
+    block_gauss_jordan<T, M, false>(Mx, LD, nullptr, nullptr);
+    if (rhs) {
+      for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
+      solve_line(j);
+    }
+    store(j);
   }
+  if (bad && t == 0) atomicExch(fallback + s, 1);
+  if (!second_to_arrive(counter, s, &flag)) return;
+  if (t == 0) flag = atomicAdd(fallback + s, 0);
+  __syncthreads();
+  if (flag) return;
+
+  // the twist line: Mx = -hy^-4 (F_{t-1} + F_{t+1}) from the stored inverses, then + D_t
+  if (t < tx) {
+    double y, p;
+    state_at(tw, y, p);
+    coefficients(y, p);
+  }
+  const T* Fm = tw > 0 ? Fs + (size_t)(tw - 1) * M * M : nullptr;
+  const T* Fp = tw + 1 < ty ? Fs + (size_t)(tw + 1) * M * M : nullptr;
+  for (int e = t; e < M * M; e += NT) {
+    const int b = e / M, a = e - b * M;   // stored transposed: F[b][a] = inverse[a][b]
+    const double v = (Fm ? (double)Fm[e] : 0.0) + (Fp ? (double)Fp[e] : 0.0);
+    Mx[a * LD + b] = (T)(-hy4i * v);
+  }
+  __syncthreads();
+  // Z_t is close to the boundary of column dominance (both neighbours' Schur terms are
+  // subtracted), so its elimination checks the partial-pivoting choice exactly instead
+  (void)build(2);
+  if (block_gauss_jordan<T, M, true>(Mx, LD, Pn, &flag)) {
+    if (t == 0) atomicExch(fallback + s, 1);
+    return;
+  }
+  if (rhs) {
+    for (int i = t; i < M; i += NT)
+      vin[i] = P.hy2i * ((tw > 0 ? gs[(size_t)(tw - 1) * M + i] : 0.0) +
+                         (tw + 1 < ty ? gs[(size_t)(tw + 1) * M + i] : 0.0));
+    solve_line(tw);
+  }
+  store(tw);
 }
 
 // Fallback for subdomains with a line block that is not column diagonally dominant
@@ -413,7 +538,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
                                                               double eps_fixed, const double* __restrict__ rhs,
                                                               double rhs_scale, T* __restrict__ facT,
                                                               double* __restrict__ gout,
-                                                              const int* __restrict__ only) {
+                                                              int* __restrict__ only) {
   constexpr int R = M / 16;          // rows (and columns) of the line block per thread
   constexpr int LD = M + 1;
   __shared__ T Mx[M * LD];      // finished in-place Gauss-Jordan result of the line
@@ -441,10 +566,20 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
   const double hy4i = P.hy2i * P.hy2i;
   T A[R][R];
 
+  const int tw = ty / 2;
+  const T* Fm = tw > 0 ? facT + ((size_t)s * P.tym + tw - 1) * M * M : nullptr;
+  const T* Fp = tw + 1 < ty ? facT + ((size_t)s * P.tym + tw + 1) * M * M : nullptr;
   for (int i = t; i < M; i += kFacThreads) gprev[i] = 0.0;
 
-  for (int j = 0; j < ty; ++j) {
-    const int pj = j & 1, pp = pj ^ 1;
+  // the two-ended order of k_factor_mfma: top lines 0 .. t-1, bottom lines ty-1 .. t+1,
+  // then the twist line t, whose neighbours' inverses and vectors are read back from
+  // facT and gout
+  for (int q = 0; q < ty; ++q) {
+    const bool twist = q == ty - 1;
+    const int j = q < tw ? q : (twist ? tw : ty - 1 - (q - tw));
+    const bool has_prev = q < tw ? q > 0 : (!twist && q > tw);
+    if (twist) __threadfence();
+    const int pj = q & 1, pp = pj ^ 1;
     // coefficients of line j at z = R_i x + c
     for (int a = t; a < tx; a += kFacThreads) {
       const double y = tilex[halo_idx(P, s, 0, j + 1, a + 1)] + (c ? c[tile_idx(P, s, 0, j, a)] : 0.0);
@@ -475,7 +610,9 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
           } else if (ar == ac) {
             d = fr == 0 ? lb[ar] : lc[ar];
           }
-          if (j > 0) d -= hy4i * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
+          if (has_prev) d -= hy4i * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
+          if (twist) d -= hy4i * ((Fm ? (double)Fm[(size_t)b * M + a] : 0.0) +
+                                 (Fp ? (double)Fp[(size_t)b * M + a] : 0.0));
         }
         A[rr][cc] = (T)d;
       }
@@ -589,7 +726,13 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
           const int f = i >= tx;
           rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
         }
-        vin[i] = rv + P.hy2i * gprev[i];
+        double nb = has_prev ? gprev[i] : 0.0;
+        if (twist) {
+          const double* gs = gout + (size_t)s * P.tym * M;
+          if (tw > 0) nb += gs[(size_t)(tw - 1) * M + i];
+          if (tw + 1 < ty) nb += gs[(size_t)(tw + 1) * M + i];
+        }
+        vin[i] = rv + P.hy2i * nb;
       }
       __syncthreads();
       if (t < M) {
@@ -614,6 +757,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
     }
     __syncthreads();
   }
+  if (t == 0) only[s] = 0;   // consumed: the flags start at 0 for the next launch
 }
 
 #define RSP_DISPATCH_M(M_, CALL) \
@@ -631,20 +775,21 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
 
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, hipStream_t st) {
+                   int* fallback, int* counter, hipStream_t st) {
   if (I.count <= 0) return;
+  const dim3 grid(I.count, 2);
   if (fp32) {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor_mfma<float, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,        \
-                                                            rhs_scale, (float*)facT, g, fallback);     \
+  k_factor_mfma<float, MM><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale,      \
+                                                    (float*)facT, g, fallback, counter);                \
   k_factor_pivot<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
                                                              rhs_scale, (float*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor_mfma<double, MM><<<I.count, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
-                                                             rhs_scale, (double*)facT, g, fallback);   \
+  k_factor_mfma<double, MM><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale,     \
+                                                     (double*)facT, g, fallback, counter);              \
   k_factor_pivot<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,      \
                                                               rhs_scale, (double*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)

@@ -1,9 +1,18 @@
-// Block-tridiagonal solves with the stored line factors (one workgroup per subdomain).
+// Block-tridiagonal solves with the stored line factors (twisted form).
 //
-// With F_j = S_j^{-1} (stored transposed: facT[s][j][b][a] = F_j[a][b]) and c = 1/hy^2:
-//   forward   g_0 = F_0 r_0,  g_j = F_j (r_j + c g_{j-1})
-//   backward  z_{ty-1} = g_{ty-1},  z_j = g_j + c F_j z_{j+1}
-// (block LU of the local Jacobian, Section 4: x-derivative of F; eq. (DerC)).
+// Lines 0 .. ty-1 of a tile, twist line t = ty / 2, c = 1/hy^2.  The factors are the
+// inverses F_j of the two-ended Schur complements (kernels_factor.hip): S_j from the
+// top (j < t), T_j from the bottom (j > t) and Z_t at the twist, stored transposed
+// (facT[s][j][b][a] = F_j[a][b]).  A solve J z = r is
+//   inward   g_0 = F_0 r_0,  g_j = F_j (r_j + c g_{j-1})            (j < t)
+//            h_{ty-1} = F_{ty-1} r_{ty-1},  h_j = F_j (r_j + c h_{j+1})   (j > t)
+//   twist    z_t = F_t (r_t + c g_{t-1} + c h_{t+1})
+//   outward  z_j = g_j + c F_j z_{j+1} (j < t),  z_j = h_j + c F_j z_{j-1} (j > t)
+// (block LU of the local Jacobian, Section 4: x-derivative of F; eq. (DerC)).  The two
+// halves are independent until the twist, so the Jacobian action runs them in two
+// workgroups per subdomain: one launch for the inward halves, a second one in which
+// each workgroup forms the twist line from the first launch's results and sweeps its
+// half outward.
 //
 // Each line is an M x M matrix-vector product that only depends on the previous
 // line through the (small) vector, so the matrices are streamed from HBM with
@@ -81,62 +90,94 @@ __device__ __forceinline__ double line_product(const typename Sweep<TF, M>::VT (
   return y;
 }
 
-// Forward sweep in place on gl[ty][M] (rhs -> g).
+// Inward sweep over the n lines j0, j0 + dir, ... (dir = +1 or -1), in place on
+// gl[ty][M]: gl_j <- F_j gl_j, then c gl_j is added to the next line j + dir (also
+// after the last one, where that is the twist line), if it lies in [0, ty).
 template <typename TF, int M>
-__device__ void forward_sweep(const TF* __restrict__ Fs, int ty, double c, double* gl, double* red) {
+__device__ void sweep_in(const TF* __restrict__ Fs, int ty, int j0, int n, int dir, double c, double* gl,
+                         double* red) {
   using S = Sweep<TF, M>;
+  if (n <= 0) return;
   const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
   const size_t MM = (size_t)M * M;
+  auto line = [&](int k) { return j0 + dir * min(k, n - 1); };
   typename S::VT b0[S::K], b1[S::K], b2[S::K];
-  load_line<TF, M>(Fs, ac, bg, b0);
-  load_line<TF, M>(Fs + MM * min(1, ty - 1), ac, bg, b1);
-  auto step = [&](const typename S::VT(&buf)[S::K], int j) {
+  load_line<TF, M>(Fs + MM * line(0), ac, bg, b0);
+  load_line<TF, M>(Fs + MM * line(1), ac, bg, b1);
+  auto step = [&](const typename S::VT(&buf)[S::K], int k) {
+    const int j = j0 + dir * k;
     const double y = line_product<TF, M>(buf, gl + (size_t)j * M, ac, bg, red);
     if (t < M) {
       gl[(size_t)j * M + t] = y;
-      if (j + 1 < ty) gl[(size_t)(j + 1) * M + t] += c * y;
+      const int jn = j + dir;
+      if (jn >= 0 && jn < ty) gl[(size_t)jn * M + t] += c * y;
     }
     __syncthreads();
   };
-  for (int j = 0; j < ty; j += 3) {
-    load_line<TF, M>(Fs + MM * min(j + 2, ty - 1), ac, bg, b2);
-    step(b0, j);
-    if (j + 1 >= ty) break;
-    load_line<TF, M>(Fs + MM * min(j + 3, ty - 1), ac, bg, b0);
-    step(b1, j + 1);
-    if (j + 2 >= ty) break;
-    load_line<TF, M>(Fs + MM * min(j + 4, ty - 1), ac, bg, b1);
-    step(b2, j + 2);
+  for (int k = 0; k < n; k += 3) {
+    load_line<TF, M>(Fs + MM * line(k + 2), ac, bg, b2);
+    step(b0, k);
+    if (k + 1 >= n) break;
+    load_line<TF, M>(Fs + MM * line(k + 3), ac, bg, b0);
+    step(b1, k + 1);
+    if (k + 2 >= n) break;
+    load_line<TF, M>(Fs + MM * line(k + 4), ac, bg, b1);
+    step(b2, k + 2);
   }
 }
 
-// Backward sweep in place on gl (g -> z) for lines ty-2 down to jstop.
+// Outward sweep over the n lines j0, j0 + dir, ...: gl_j += c F_j gl_{j - dir}.
 template <typename TF, int M>
-__device__ void backward_sweep(const TF* __restrict__ Fs, int ty, int jstop, double c, double* gl,
-                               double* red) {
+__device__ void sweep_out(const TF* __restrict__ Fs, int j0, int n, int dir, double c, double* gl,
+                          double* red) {
   using S = Sweep<TF, M>;
+  if (n <= 0) return;
   const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
   const size_t MM = (size_t)M * M;
-  const int j0 = ty - 2;
-  if (j0 < jstop) return;
+  auto line = [&](int k) { return j0 + dir * min(k, n - 1); };
   typename S::VT b0[S::K], b1[S::K], b2[S::K];
-  load_line<TF, M>(Fs + MM * j0, ac, bg, b0);
-  load_line<TF, M>(Fs + MM * max(j0 - 1, jstop), ac, bg, b1);
-  auto step = [&](const typename S::VT(&buf)[S::K], int j) {
-    const double y = line_product<TF, M>(buf, gl + (size_t)(j + 1) * M, ac, bg, red);
+  load_line<TF, M>(Fs + MM * line(0), ac, bg, b0);
+  load_line<TF, M>(Fs + MM * line(1), ac, bg, b1);
+  auto step = [&](const typename S::VT(&buf)[S::K], int k) {
+    const int j = j0 + dir * k;
+    const double y = line_product<TF, M>(buf, gl + (size_t)(j - dir) * M, ac, bg, red);
     if (t < M) gl[(size_t)j * M + t] += c * y;
     __syncthreads();
   };
-  for (int j = j0; j >= jstop; j -= 3) {
-    load_line<TF, M>(Fs + MM * max(j - 2, jstop), ac, bg, b2);
-    step(b0, j);
-    if (j - 1 < jstop) break;
-    load_line<TF, M>(Fs + MM * max(j - 3, jstop), ac, bg, b0);
-    step(b1, j - 1);
-    if (j - 2 < jstop) break;
-    load_line<TF, M>(Fs + MM * max(j - 4, jstop), ac, bg, b1);
-    step(b2, j - 2);
+  for (int k = 0; k < n; k += 3) {
+    load_line<TF, M>(Fs + MM * line(k + 2), ac, bg, b2);
+    step(b0, k);
+    if (k + 1 >= n) break;
+    load_line<TF, M>(Fs + MM * line(k + 3), ac, bg, b0);
+    step(b1, k + 1);
+    if (k + 2 >= n) break;
+    load_line<TF, M>(Fs + MM * line(k + 4), ac, bg, b1);
+    step(b2, k + 2);
   }
+}
+
+// gl_tw <- F_tw gl_tw (the twist line, its neighbours' terms already added).
+template <typename TF, int M>
+__device__ void twist_line(const TF* __restrict__ Fs, int tw, double* gl, double* red) {
+  using S = Sweep<TF, M>;
+  const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
+  typename S::VT b0[S::K];
+  load_line<TF, M>(Fs + (size_t)M * M * tw, ac, bg, b0);
+  const double y = line_product<TF, M>(b0, gl + (size_t)tw * M, ac, bg, red);
+  if (t < M) gl[(size_t)tw * M + t] = y;
+  __syncthreads();
+}
+
+// Whole solve in one workgroup; the outward sweeps stop at lines jlo <= t <= jhi.
+template <typename TF, int M>
+__device__ void full_solve(const TF* __restrict__ Fs, int ty, int jlo, int jhi, double c, double* gl,
+                           double* red) {
+  const int tw = ty / 2;
+  sweep_in<TF, M>(Fs, ty, 0, tw, 1, c, gl, red);
+  sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, c, gl, red);
+  twist_line<TF, M>(Fs, tw, gl, red);
+  sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, c, gl, red);
+  sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, c, gl, red);
 }
 
 template <int M>
@@ -195,14 +236,14 @@ __device__ void sub_local_jacobian(const DevProblem& P, int s, int tx, int ty,
   }
 }
 
-// Right-hand side of Algorithm 4 on the tile: hx^-2 / hy^-2 times the values of d
-// just outside the tile (the ring), in line layout.
+// Right-hand side of Algorithm 4 on the tile, lines [j0, j1): hx^-2 / hy^-2 times the
+// values of d just outside the tile (the ring), in line layout.
 template <int M>
-__device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty,
+__device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty, int j0, int j1,
                                          const double* __restrict__ d, double* gl) {
   const size_t n = (size_t)P.nx * P.ny;
   d += 2 * P.noff;
-  for (int e = threadIdx.x; e < ty * M; e += 4 * M) {
+  for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
     if (i < 2 * tx) {
@@ -215,6 +256,28 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
       if (j == ty - 1 && gj + 1 < P.ny) v += P.hy2i * df[(size_t)(gj + 1) * P.nx + gi];
     }
     gl[e] = v;
+  }
+}
+
+// out = -d + z on the core nodes of lines [j0, j1) (every global node is written by one
+// subdomain: the cores tile the grid).
+template <int M>
+__device__ __forceinline__ void core_out(const DevProblem& P, int4 bx, int4 co, int tx, int j0, int j1,
+                                         const double* gl, const double* __restrict__ d,
+                                         double* __restrict__ out) {
+  const size_t n = (size_t)P.nx * P.ny;
+  const int cw = co.y - co.x;
+  const int b0 = max(j0, co.z - bx.z), b1 = min(j1, co.w - bx.z);
+  if (b1 <= b0) return;
+  const int ch = b1 - b0;
+  d += 2 * P.noff;
+  out += 2 * P.noff;
+  for (int e = threadIdx.x; e < 2 * cw * ch; e += 4 * M) {
+    const int f = e / (cw * ch);
+    const int r = e - f * cw * ch;
+    const int b = b0 + r / cw, a = co.x - bx.x + (r % cw);
+    const size_t gidx = f * n + (size_t)(bx.z + b) * P.nx + (bx.x + a);
+    out[gidx] = gl[b * M + f * tx + a] - d[gidx];
   }
 }
 
@@ -232,12 +295,12 @@ __global__ __launch_bounds__(4 * M) void k_block_solve(Items I, const TF* __rest
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   tile_to_lines<M>(P, s, tx, ty, rhs, 1.0, gl);
   __syncthreads();
-  forward_sweep<TF, M>(Fs, ty, P.hy2i, gl, red);
-  backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, gl, red);
+  full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, gl, red);
   lines_to_tile<M>(P, s, tx, ty, gl, out);
 }
 
-// Backward sweep after the factorisation kernel's fused forward sweep (g in gout).
+// Outward half-sweeps after the factorisation kernel's fused inward sweeps and twist
+// (g, h and z_t in gout); blockIdx.y = 0: lines t .. 0, 1: lines t+1 .. ty-1.
 template <typename TF, int M>
 __global__ __launch_bounds__(4 * M) void k_solve_bwd(Items I, const SubState* __restrict__ state,
                                                      const TF* __restrict__ facT,
@@ -250,12 +313,22 @@ __global__ __launch_bounds__(4 * M) void k_solve_bwd(Items I, const SubState* __
   if (!item_of(I, s, P)) return;
   if (state && !state[s].active) return;
   const int4 bx = I.box[s];
-  const int tx = bx.y - bx.x, ty = bx.w - bx.z;
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z, tw = ty / 2;
+  const int half = blockIdx.y;
+  const int j0 = half == 0 ? 0 : tw, j1 = half == 0 ? tw + 1 : ty;   // lines read
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
-  for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] = g[(size_t)s * P.tym * M + e];
+  for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) gl[e] = g[(size_t)s * P.tym * M + e];
   __syncthreads();
-  backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, gl, red);
-  lines_to_tile<M>(P, s, tx, ty, gl, out);
+  if (half == 0) sweep_out<TF, M>(Fs, tw - 1, tw, -1, P.hy2i, gl, red);
+  else sweep_out<TF, M>(Fs, tw + 1, ty - 1 - tw, 1, P.hy2i, gl, red);
+  // tile rows of this half (half 1 also writes the padding rows)
+  const int r0 = half == 0 ? 0 : tw + 1, r1 = half == 0 ? tw + 1 : P.tym;
+  for (int e = threadIdx.x; e < 2 * P.txm * (r1 - r0); e += 4 * M) {
+    const int f = e / (P.txm * (r1 - r0));
+    const int r = e - f * P.txm * (r1 - r0);
+    const int b = r0 + r / P.txm, a = r % P.txm;
+    out[tile_idx(P, s, f, b, a)] = (a < tx && b < ty) ? gl[b * M + f * tx + a] : 0.0;
+  }
 }
 
 // nref refinement steps of the Newton direction of Algorithm 1:
@@ -284,61 +357,107 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(Items I, const double* 
     __syncthreads();
     sub_local_jacobian<M>(P, s, tx, ty, tilex, c, eps, gl, rb);
     __syncthreads();
-    forward_sweep<TF, M>(Fs, ty, P.hy2i, rb, red);
-    backward_sweep<TF, M>(Fs, ty, 0, P.hy2i, rb, red);
+    full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, rb, red);
     for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
     __syncthreads();
   }
   lines_to_tile<M>(P, s, tx, ty, gl, dir);
 }
 
-// Algorithm 4 for one subdomain, fused: right-hand side from the values of d just
-// outside the tile, both sweeps (plus nref FP64 refinement steps with J_i at
-// x^(i) = R_i x + c, eps_min), and out = -d + z on the non-overlapping box (every
-// global node is written by exactly one subdomain).
-template <typename TF, int M, bool REF>
-__global__ __launch_bounds__(4 * M) void k_jac_apply(Items I, const TF* __restrict__ facT,
-                                                     const double* __restrict__ tilex,
-                                                     const double* __restrict__ c,
-                                                     const double* __restrict__ d,
-                                                     double* __restrict__ out, int nref) {
+// Algorithm 4, inward part, two workgroups per subdomain (blockIdx.y: 0 top lines
+// 0 .. t-1, 1 bottom lines ty-1 .. t+1): right-hand side from the values of d just
+// outside the tile, inward sweep, the half's lines g_j / h_j to gbuf.
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restrict__ facT,
+                                                    const double* __restrict__ d, double* __restrict__ gbuf) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
-  __shared__ double rb[REF ? kMaxTile * M : 1];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
-  if (!REF) nref = 0;
+  const int4 bx = I.box[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z, tw = ty / 2;
+  const int half = blockIdx.y;
+  const int j0 = half == 0 ? 0 : tw + 1, j1 = half == 0 ? tw : ty;   // lines of the half
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  double* gs = gbuf + (size_t)s * P.tym * M;
+  ring_rhs<M>(P, bx, tx, ty, j0, j1, d, gl);
+  __syncthreads();
+  if (half == 0) sweep_in<TF, M>(Fs, ty, 0, tw, 1, P.hy2i, gl, red);
+  else sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, P.hy2i, gl, red);
+  for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) gs[e] = gl[e];
+}
+
+// Algorithm 4, outward part (blockIdx.y as above; half 0 also owns the twist line):
+// both workgroups form z_t = F_t (r_t + c g_{t-1} + c h_{t+1}) from the inward results,
+// then sweep outward to the half's last core line; out = -d + z on the core.
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restrict__ facT,
+                                                     const double* __restrict__ gbuf,
+                                                     const double* __restrict__ d, double* __restrict__ out) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 bx = I.box[s], co = I.core[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z, tw = ty / 2;
+  const int half = blockIdx.y;
+  const int clo = co.z - bx.z, chi = co.w - bx.z - 1;   // core lines
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  const double* gs = gbuf + (size_t)s * P.tym * M;
+  const int jlo = half == 0 ? min(clo, tw) : tw + 1;   // lines read back (besides the twist)
+  const int jhi = half == 0 ? tw - 1 : max(chi, tw);
+  for (int e = jlo * M + threadIdx.x; e < (jhi + 1) * M; e += 4 * M) gl[e] = gs[e];
+  ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, gl);
+  __syncthreads();
+  for (int i = threadIdx.x; i < M; i += 4 * M) {
+    double v = gl[(size_t)tw * M + i];
+    if (tw > 0) v += P.hy2i * gs[(size_t)(tw - 1) * M + i];
+    if (tw + 1 < ty) v += P.hy2i * gs[(size_t)(tw + 1) * M + i];
+    gl[(size_t)tw * M + i] = v;
+  }
+  __syncthreads();
+  twist_line<TF, M>(Fs, tw, gl, red);
+  if (half == 0) {
+    sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, P.hy2i, gl, red);
+    core_out<M>(P, bx, co, tx, jlo, tw + 1, gl, d, out);
+  } else {
+    sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, P.hy2i, gl, red);
+    core_out<M>(P, bx, co, tx, tw + 1, jhi + 1, gl, d, out);
+  }
+}
+
+// Algorithm 4 with nref FP64 refinement steps of each local solve (the local Jacobian at
+// x^(i) = R_i x + c, eps_min), one workgroup per subdomain.
+template <typename TF, int M>
+__global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __restrict__ facT,
+                                                         const double* __restrict__ tilex,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ d,
+                                                         double* __restrict__ out, int nref) {
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double rb[kMaxTile * M];
+  __shared__ double red[Sweep<TF, M>::G * M];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
   const int4 bx = I.box[s], co = I.core[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
-  const int jcore = co.z - bx.z;
-  ring_rhs<M>(P, bx, tx, ty, d, gl);
-  __syncthreads();
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
-  forward_sweep<TF, M>(Fs, ty, P.hy2i, gl, red);
-  backward_sweep<TF, M>(Fs, ty, nref > 0 ? 0 : jcore, P.hy2i, gl, red);
+  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, gl);
+  __syncthreads();
+  full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, gl, red);
   for (int it = 0; it < nref; ++it) {
-    ring_rhs<M>(P, bx, tx, ty, d, rb);
+    ring_rhs<M>(P, bx, tx, ty, 0, ty, d, rb);
     __syncthreads();
     sub_local_jacobian<M>(P, s, tx, ty, tilex, c, P.eps_min, gl, rb);
     __syncthreads();
-    forward_sweep<TF, M>(Fs, ty, P.hy2i, rb, red);
-    backward_sweep<TF, M>(Fs, ty, it + 1 == nref ? jcore : 0, P.hy2i, rb, red);
+    full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, rb, red);
     for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
     __syncthreads();
   }
-  const size_t n = (size_t)P.nx * P.ny;
-  const int cw = co.y - co.x, ch = co.w - co.z;
-  d += 2 * P.noff;
-  out += 2 * P.noff;
-  for (int e = threadIdx.x; e < 2 * cw * ch; e += 4 * M) {
-    const int f = e / (cw * ch);
-    const int r = e - f * cw * ch;
-    const int b = r / cw, a = r - b * cw;
-    const int gi = co.x + a, gj = co.z + b;
-    const size_t gidx = f * n + (size_t)gj * P.nx + gi;
-    out[gidx] = gl[(gj - bx.z) * M + f * tx + (gi - bx.x)] - d[gidx];
-  }
+  core_out<M>(P, bx, co, tx, 0, ty, gl, d, out);
 }
 
 #define RSP_DISPATCH_M(M_, CALL) \
@@ -357,12 +476,13 @@ __global__ __launch_bounds__(4 * M) void k_jac_apply(Items I, const TF* __restri
 void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
                       const double* g, double* out, hipStream_t st) {
   if (I.count <= 0) return;
+  const dim3 grid(I.count, 2);
   if (fp32) {
-#define RSP_CALL(MM) k_solve_bwd<float, MM><<<I.count, 4 * MM, 0, st>>>(I, state, (const float*)facT, g, out)
+#define RSP_CALL(MM) k_solve_bwd<float, MM><<<grid, 4 * MM, 0, st>>>(I, state, (const float*)facT, g, out)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
-#define RSP_CALL(MM) k_solve_bwd<double, MM><<<I.count, 4 * MM, 0, st>>>(I, state, (const double*)facT, g, out)
+#define RSP_CALL(MM) k_solve_bwd<double, MM><<<grid, 4 * MM, 0, st>>>(I, state, (const double*)facT, g, out)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
@@ -400,28 +520,37 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 }
 
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
-                      const double* c, const double* d, double* out, int nref, hipStream_t st) {
+                      const double* c, const double* d, double* out, int nref, double* gbuf, hipStream_t st) {
   if (I.count <= 0) return;
-#define RSP_APPLY(TT, REFB, MM) \
-  k_jac_apply<TT, MM, REFB><<<I.count, 4 * MM, 0, st>>>(I, (const TT*)facT, tilex, c, d, out, nref)
-  if (fp32 && nref > 0) {
-#define RSP_CALL(MM) RSP_APPLY(float, true, MM)
-    RSP_DISPATCH_M(M, RSP_CALL)
+  const dim3 grid(I.count, 2);
+  if (nref > 0) {
+#define RSP_REF(TT, MM) \
+  k_apply_refined<TT, MM><<<I.count, 4 * MM, 0, st>>>(I, (const TT*)facT, tilex, c, d, out, nref)
+    if (fp32) {
+#define RSP_CALL(MM) RSP_REF(float, MM)
+      RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
-  } else if (fp32) {
-#define RSP_CALL(MM) RSP_APPLY(float, false, MM)
-    RSP_DISPATCH_M(M, RSP_CALL)
+    } else {
+#define RSP_CALL(MM) RSP_REF(double, MM)
+      RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
-  } else if (nref > 0) {
-#define RSP_CALL(MM) RSP_APPLY(double, true, MM)
+    }
+#undef RSP_REF
+    return;
+  }
+#define RSP_TWO(TT, MM)                                                                        \
+  k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, gbuf);                    \
+  k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, out)
+  if (fp32) {
+#define RSP_CALL(MM) RSP_TWO(float, MM)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
-#define RSP_CALL(MM) RSP_APPLY(double, false, MM)
+#define RSP_CALL(MM) RSP_TWO(double, MM)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }
-#undef RSP_APPLY
+#undef RSP_TWO
 }
 
 }  // namespace rsp

@@ -97,6 +97,24 @@ struct GmBatch {
   int m;
 };
 
+// Two workgroups per subdomain: the second of the two to call this returns true (in
+// all its threads), after which the first one's global writes are visible to it, and
+// the subdomain's counter is back at 0 for the next launch.  Neither workgroup waits
+// for the other.  Every thread of both workgroups calls it.
+__device__ __forceinline__ bool second_to_arrive(int* __restrict__ counter, int s, int* flag_lds) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = atomicAdd(counter + s, 1);
+    *flag_lds = old;
+    if (old == 1) atomicExch(counter + s, 0);
+  }
+  __syncthreads();
+  const bool last = *flag_lds == 1;
+  if (last) __threadfence();
+  return last;
+}
+
 // ---------------------------------------------------------------- pointwise
 // P_eps in the cancellation-free form 2t / (sqrt((t+1)^2+eps) + sqrt((t-1)^2+eps))
 // (Lemma 3.1, proof of point (i)).

@@ -29,12 +29,13 @@ void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t s
 // a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1},
 // stored as double, or as float when fp32 != 0 (facT points to that type).  The
 // smoothing is state[s].eps (state != nullptr; inactive items are skipped), else
-// eps_fixed when > 0, else the instance's eps_min.  fallback: [items] scratch flags
-// (subdomains redone with partial pivoting).
+// eps_fixed when > 0, else the instance's eps_min.  Two-ended (twisted) block LU with
+// the twist at line ty / 2.  fallback, counter: [items] flags and counters, 0 between
+// launches (subdomains redone with partial pivoting; arrival of the two workgroups).
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, hipStream_t st);
-// a5: backward sweep after a fused forward sweep.
+                   int* fallback, int* counter, hipStream_t st);
+// a5: outward sweeps after the fused inward sweeps and twist of launch_factor.
 void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
                       const double* g, double* out, hipStream_t st);
 // Refinement of the Newton direction: nref steps dir += F^{-1}(-res - J dir) (FP64 J).
@@ -44,10 +45,12 @@ void launch_newton_refine(const Items& I, int M, const double* tilex, const doub
 // a5: forward + backward sweeps with stored factors (tile rhs -> tile out).
 void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const double* rhs, double* out,
                         hipStream_t st);
-// a9 (Algorithm 4), fused: ring rhs of d, both sweeps (+ nref FP64 refinement steps with
-// the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.
+// a9 (Algorithm 4): ring rhs of d, the local solves (+ nref FP64 refinement steps with
+// the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  Without refinement two
+// launches of two workgroups per subdomain (inward halves; twist + outward halves);
+// gbuf: [items][tym][M] scratch.
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
-                      const double* c, const double* d, double* out, int nref, hipStream_t st);
+                      const double* c, const double* d, double* out, int nref, double* gbuf, hipStream_t st);
 // Section 4 F(x, eps) on the whole grid of one instance and its control u(p)
 // (pointers at the instance's arrays).
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
