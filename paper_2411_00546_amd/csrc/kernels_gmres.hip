@@ -108,12 +108,13 @@ __global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, const double* __restr
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = 0.0;
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
+    // all NB loads first, so that they are in flight together
+    double v[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
     const double we = w[e];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const double v = V[(size_t)min(i, nv - 1) * B.ldv + e];
-      acc[i] = fma(v, i < nv ? we : 0.0, acc[i]);
-    }
+    for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
   }
   const double r = block_sums<NB>(acc, nv, red);
   if ((int)threadIdx.x < nv) partial[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
@@ -169,37 +170,34 @@ __global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __res
   if ((int)threadIdx.x < nout) pout[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
 }
 
-// |w| from the partials; V_{j+1} = w / |w|; block 0 stores H[j+1][j].
+// |w| from the partials; V_{j+1} = w / |w|.  Block 0 then stores H[j+1][j] and applies
+// the Givens rotations to Hessenberg column j: residual estimate and stopping test.
+// (Once the stop flag is set, blocks that start later skip V_{j+1}, which is then not
+// used: the update of x takes V_0 .. V_j.)  The column and the rotations are staged
+// in LDS so the sequential part runs from LDS.
 __global__ __launch_bounds__(kT) void k_gm_normalize(GmBatch B, double* __restrict__ V,
                                                      const double* __restrict__ w,
                                                      const double* __restrict__ pin, int j) {
   __shared__ double hs[1];
+  __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
   const Seg g = seg_of(B);
-  if (B.st[g.i].done) return;
+  GmState* st = B.st + g.i;
+  if (st->done) return;
   const size_t L = g.L;
   double* Vn = V + (size_t)(j + 1) * B.ldv + g.off;
   w += g.off;
   gather_partials(pin + g.i * kPart, 1, hs);
   const double nrm = sqrt(hs[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) B.hs[g.i].H[(j + 1) * B.m + j] = nrm;
   const double inv = 1.0 / nrm;
   size_t lo, hi;
   chunk_of(L, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) Vn[e] = w[e] * inv;
-}
-
-// Givens rotations on Hessenberg column j, residual estimate and stopping test (one
-// block per instance).  The column and the rotations are staged in LDS so the
-// sequential part runs from LDS.
-__global__ __launch_bounds__(kT) void k_gm_givens(GmBatch B, int j) {
-  __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
-  const Seg g = seg_of(B);
-  GmState* st = B.st + g.i;
+  if (blockIdx.x != 0) return;
   GmHess* hz = B.hs + g.i;
-  if (st->done) return;
   const int m = B.m;
   const int t = threadIdx.x;
-  if (t <= j + 1) col[t] = hz->H[t * m + j];
+  if (t <= j) col[t] = hz->H[t * m + j];
+  if (t == j + 1) col[t] = nrm;
   if (t < j) {
     cs[t] = hz->cs[t];
     sn[t] = hz->sn[t];
@@ -391,7 +389,6 @@ void arnoldi_nb(const GmBatch& B, double* V, int j, double* w, double* p1, doubl
   k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1, 1, 0, p2, j);
   k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p2, 0, 1, p1, j);
   k_gm_normalize<<<gr, kT, 0, s>>>(B, V, w, p1, j);
-  k_gm_givens<<<dim3(1, B.count), kT, 0, s>>>(B, j);
 }
 void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2,
                        hipStream_t s) {
