@@ -130,11 +130,25 @@ def cpu_baseline(prob, opts, hist):
                           sample_s))}
 
 
+def dominant(stats):
+    """The single-pass kernel class with the largest device time (the GMRES
+    orthogonalisation is a chain of kernels, not one)."""
+    single = {k: v for k, v in stats.items() if v["launches"] > 0 and k != "gmres_ortho"}
+    return max(single, key=lambda k: single[k]["ms"])
+
+
+def kernel_table(stats):
+    return {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
+                "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                "GFLOPps": round(v["flops"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
+            for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"] > 0}
+
+
 def kernel_roofline(stats, fp32):
     """Roofline object of the dominant single-pass kernel from rsp_kernel_stats output."""
     kern = {k: v for k, v in stats.items() if v["launches"] > 0}
-    single = {k: v for k, v in kern.items() if k != "gmres_ortho"}
-    dom = max(single, key=lambda k: single[k]["ms"])
+    dom = dominant(kern)
     d = kern[dom]
     bound, peak, unit = BOUND[dom]
     if dom == "factor" and fp32:
@@ -148,12 +162,7 @@ def kernel_roofline(stats, fp32):
             "frac": achieved / peak, "traffic": traffic_for(dom, fp32),
             "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
             "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
-    kernels = {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
-                   "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
-                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
-                   "GFLOPps": round(v["flops"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None}
-               for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
-    return roof, kernels
+    return roof
 
 
 def pct(lat_s):
@@ -233,8 +242,16 @@ def run_batch_workload(args, R):
         def batch(o, steps, warm, profile):
             for _ in range(warm):
                 R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
+            breakdown = None
             if profile:
+                # an untimed batch with every kernel class timed, then events around the
+                # dominant kernel only in the timed batches
+                R.rsp_set_profiling_filter(ctx, None)
                 R.rsp_set_profiling(ctx, True)
+                R.rsp_reset_kernel_stats(ctx)
+                R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
+                breakdown = R.rsp_kernel_stats(ctx)
+                R.rsp_set_profiling_filter(ctx, dominant(breakdown))
                 R.rsp_reset_kernel_stats(ctx)
             torch.cuda.synchronize()
             lat = []
@@ -249,7 +266,8 @@ def run_batch_workload(args, R):
             el = time.perf_counter() - t0
             stats = R.rsp_kernel_stats(ctx) if profile else None
             R.rsp_set_profiling(ctx, False)
-            return el, lat, hists, stats, [inst.x(q) for q in range(len(probs))]
+            R.rsp_set_profiling_filter(ctx, None)
+            return el, lat, hists, (stats, breakdown), [inst.x(q) for q in range(len(probs))]
 
         el, lat, hists, stats, xs = batch(O, args.steps, args.warmup, True)
         el64b, _, hists64, _, x64 = batch(O64, 1, 0, False)
@@ -266,7 +284,9 @@ def run_batch_workload(args, R):
         el1 = time.perf_counter() - t0
     finally:
         R.rsp_context_destroy(ctx)
-    roof, kernels = kernel_roofline(stats, opts.precision == 1)
+    stats, breakdown = stats
+    roof = kernel_roofline(stats, opts.precision == 1)
+    kernels = kernel_table(breakdown)
     flops = sum(h["flops"] for h in hists)
     sizes = sorted({(pr.nx, pr.ny) for pr in probs})
     cpu = None if args.no_cpu_baseline else batch_cpu_baseline(probs, opts, hists)
@@ -437,8 +457,17 @@ def main():
     def solves(opt, steps, warmup, profile):
         for _ in range(warmup):
             R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+        breakdown = None
         if profile:
+            # one untimed solve with every kernel class timed: the per-kernel table and
+            # the choice of the dominant kernel; the timed solves then carry events
+            # around that kernel only
+            R.rsp_set_profiling_filter(ctx, None)
             R.rsp_set_profiling(ctx, True)
+            R.rsp_reset_kernel_stats(ctx)
+            R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+            breakdown = R.rsp_kernel_stats(ctx)
+            R.rsp_set_profiling_filter(ctx, dominant(breakdown))
             R.rsp_reset_kernel_stats(ctx)
         torch.cuda.synchronize()
         lat, hist = [], None
@@ -453,8 +482,9 @@ def main():
         el = time.perf_counter() - t0
         stats = R.rsp_kernel_stats(ctx) if profile else None
         R.rsp_set_profiling(ctx, False)
+        R.rsp_set_profiling_filter(ctx, None)
         x = torch.cat([y.reshape(-1), p.reshape(-1)]).cpu().numpy()
-        return el, lat, hist, stats, x
+        return el, lat, hist, (stats, breakdown), x
 
     try:
         elapsed, lat, hist, stats, x = solves(O, args.steps, args.warmup, True)
@@ -472,7 +502,9 @@ def main():
         R.rsp_context_destroy(ctx)
 
     value = args.steps / elapsed
-    roof, kernels = kernel_roofline(stats, opts.precision == 1)
+    stats, breakdown = stats
+    roof = kernel_roofline(stats, opts.precision == 1)
+    kernels = kernel_table(breakdown)
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob, opts, hist)
     lat_ms = np.array(lat) * 1e3
     out = {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",

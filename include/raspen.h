@@ -291,6 +291,12 @@ typedef struct rsp_kernel_stat {
 /* Turn event timing on (1) or off (0) for the calls that follow on this context. */
 int rsp_set_profiling(rsp_context* ctx, int on);
 
+/* Restrict event timing to one kernel class, named as rsp_kernel_stats names it
+   ("block_solve", "factor", "gmres_ortho", ...); NULL or "" times every class.  Each
+   timed launch adds two event records to the stream, so timing a single class keeps
+   the overhead on the rest of the solve away.  Unknown name: RSP_EINVAL. */
+int rsp_set_profiling_filter(rsp_context* ctx, const char* name);
+
 /* Zero the accumulated kernel statistics. */
 int rsp_reset_kernel_stats(rsp_context* ctx);
 

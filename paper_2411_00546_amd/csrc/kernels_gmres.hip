@@ -20,6 +20,9 @@ namespace {
 constexpr int kT = 256;
 constexpr size_t kPart = (size_t)kGmBlocks * kGmMaxVec;   // partial sums per instance
 
+// Partial sum i of block b, laid out [i][b] so the consumers read runs of blocks.
+__device__ __forceinline__ size_t part_at(int i, int b) { return (size_t)i * kGmBlocks + b; }
+
 struct Seg {
   int i;          // instance
   size_t off, L;  // its vector segment
@@ -74,7 +77,7 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
     const int i = t / Q, q = t - i * Q;
     double acc = 0.0;
 #pragma unroll 8
-    for (int b = q; b < kGmBlocks; b += Q) acc += partial[b * kGmMaxVec + i];
+    for (int b = q; b < kGmBlocks; b += Q) acc += partial[part_at(i, b)];
     seg[t] = acc;
   }
   __syncthreads();
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, const double* __restr
     for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
   }
   const double r = block_sums<NB>(acc, nv, red);
-  if ((int)threadIdx.x < nv) partial[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
+  if ((int)threadIdx.x < nv) partial[part_at(threadIdx.x, blockIdx.x)] = r;
 }
 
 // h = sum of the previous partials; w -= V h; then either the partial dots of the new
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __res
   }
   const int nout = next == 0 ? nv : 1;
   const double r = block_sums<NB>(acc, nout, red);
-  if ((int)threadIdx.x < nout) pout[blockIdx.x * kGmMaxVec + threadIdx.x] = r;
+  if ((int)threadIdx.x < nout) pout[part_at(threadIdx.x, blockIdx.x)] = r;
 }
 
 // |w| from the partials; V_{j+1} = w / |w|.  Block 0 then stores H[j+1][j] and applies
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kT) void k_gm_sumsq(GmBatch B, const double* __rest
   double acc[1] = {0.0};
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) acc[0] = fma(v[e], v[e], acc[0]);
   const double r = block_sums<1>(acc, 1, red);
-  if (threadIdx.x == 0) partial[g.i * kPart + blockIdx.x * kGmMaxVec] = r;
+  if (threadIdx.x == 0) partial[g.i * kPart + part_at(0, blockIdx.x)] = r;
 }
 
 // out[instance] = sqrt(sum of its partials) (one block per instance)
@@ -394,10 +397,19 @@ void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1
                        hipStream_t s) {
   if (B.count <= 0) return;
   const int nv = j + 1;
-  if (nv <= 8) arnoldi_nb<8>(B, V, j, w, p1, p2, s);
-  else if (nv <= 16) arnoldi_nb<16>(B, V, j, w, p1, p2, s);
-  else if (nv <= 32) arnoldi_nb<32>(B, V, j, w, p1, p2, s);
-  else arnoldi_nb<64>(B, V, j, w, p1, p2, s);
+  switch ((nv + 3) / 4) {
+    case 1: arnoldi_nb<4>(B, V, j, w, p1, p2, s); break;
+    case 2: arnoldi_nb<8>(B, V, j, w, p1, p2, s); break;
+    case 3: arnoldi_nb<12>(B, V, j, w, p1, p2, s); break;
+    case 4: arnoldi_nb<16>(B, V, j, w, p1, p2, s); break;
+    case 5: arnoldi_nb<20>(B, V, j, w, p1, p2, s); break;
+    case 6: arnoldi_nb<24>(B, V, j, w, p1, p2, s); break;
+    case 7: arnoldi_nb<28>(B, V, j, w, p1, p2, s); break;
+    case 8: arnoldi_nb<32>(B, V, j, w, p1, p2, s); break;
+    default:
+      if (nv <= 48) arnoldi_nb<48>(B, V, j, w, p1, p2, s);
+      else arnoldi_nb<64>(B, V, j, w, p1, p2, s);
+  }
 }
 void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s) {
   if (B.count > 0) k_gm_update_x<<<grid_of(B), kT, 0, s>>>(B, V, x);

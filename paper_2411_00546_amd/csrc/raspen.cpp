@@ -303,6 +303,7 @@ struct rsp_context {
   bool ready = false;
   // kernel timing
   bool prof = false;
+  int prof_only = -1;   // time only this kernel class (-1: every class)
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   rsp_kernel_stat kstat[KID_N]{};
@@ -348,7 +349,9 @@ struct Timed {
   hipEvent_t a = nullptr;
   Timed(rsp_context* c_, int kid_, hipStream_t st_, double fl_, double by_)
       : c(c_), kid(kid_), st(st_), fl(fl_), by(by_) {
-    if (c->prof && (a = event_get(c)) != nullptr && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+    if (c->prof && (c->prof_only < 0 || c->prof_only == kid) && (a = event_get(c)) != nullptr &&
+        hipEventRecord(a, st) != hipSuccess)
+      a = nullptr;
   }
   ~Timed() {
     if (!a) return;
@@ -1174,6 +1177,20 @@ int rsp_set_profiling(rsp_context* ctx, int on) {
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   ctx->prof = on != 0;
   return 0;
+}
+
+int rsp_set_profiling_filter(rsp_context* ctx, const char* name) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  if (!name || !*name) {
+    ctx->prof_only = -1;
+    return 0;
+  }
+  for (int k = 0; k < KID_N; ++k)
+    if (std::strcmp(name, kKidName[k]) == 0) {
+      ctx->prof_only = k;
+      return 0;
+    }
+  return fail(RSP_EINVAL, "unknown kernel class '%s'", name);
 }
 
 int rsp_reset_kernel_stats(rsp_context* ctx) {

@@ -70,7 +70,7 @@ struct SubState {
 // matrix with the Givens rotations and the rotated right-hand side.
 constexpr int kGmMaxRestart = 64;
 constexpr int kGmMaxVec = kGmMaxRestart + 1;
-constexpr int kGmBlocks = 128;        // fixed reduction blocks per instance of the GMRES vector kernels
+constexpr int kGmBlocks = 256;        // fixed reduction blocks per instance of the GMRES vector kernels
 struct GmState {
   int m, maxit, steps, used, done, pad;
   double rtol, bnorm, beta, rel;

@@ -122,6 +122,7 @@ SIGNATURES = [
     ("rsp_server_stats", _I, [_P, ctypes.POINTER(rsp_server_report)]),
     ("rsp_server_destroy", _I, [_P]),
     ("rsp_set_profiling", _I, [_P, _I]),
+    ("rsp_set_profiling_filter", _I, [_P, ctypes.c_char_p]),
     ("rsp_reset_kernel_stats", _I, [_P]),
     ("rsp_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
 ]
@@ -345,6 +346,10 @@ def rsp_server_destroy(srv):
 
 def rsp_set_profiling(ctx, on=True):
     return _check(load().rsp_set_profiling(ctx, int(on)))
+
+
+def rsp_set_profiling_filter(ctx, name=None):
+    return _check(load().rsp_set_profiling_filter(ctx, name.encode() if name else None))
 
 
 def rsp_reset_kernel_stats(ctx):
