@@ -225,6 +225,19 @@ def batch_cpu_baseline(probs, opts, hists):
                       "counts of all %d instances" % (probs[big].nx, probs[big].ny, one["sample"], len(probs))}
 
 
+def apply_tuning(R, ctx, args, prob, opts, yd, f):
+    """--tune 1: the autotuner picks the execution settings on this workload's problem
+    (graphs, Arnoldi chunk; the partition stays the workload's); else --graphs and
+    --gm-chunk.  Returns the settings as a dict."""
+    if args.tune:
+        t = R.rsp_autotune(ctx, prob, opts, yd, f, flags=0)
+    else:
+        R.rsp_set_tuning(ctx, graphs=args.graphs, gm_chunk=args.gm_chunk)
+        t = R.rsp_get_tuning(ctx)
+    return {"graphs": t.graphs, "gm_chunk": t.gm_chunk, "autotuned": bool(args.tune),
+            "tuner_solves_per_s": t.solves_per_s if args.tune else None}
+
+
 def run_batch_workload(args, R):
     """64 uneven instances per step through rsp_solve_batch (FP32 line factors), checked
     against the FP64 batch, with plain FP64 one-at-a-time solves timed beside it."""
@@ -239,6 +252,9 @@ def run_batch_workload(args, R):
     O, O64 = R.make_options(opts), R.make_options(opts64)
     ctx = R.rsp_context_create(0)
     try:
+        big = max(range(len(probs)), key=lambda q: probs[q].nx * probs[q].ny)
+        tuning = apply_tuning(R, ctx, args, P[big], O, inst.yd[big], inst.f[big])
+
         def batch(o, steps, warm, profile):
             for _ in range(warm):
                 R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
@@ -305,7 +321,8 @@ def run_batch_workload(args, R):
             "rel_err_mixed_vs_fp64": errs, "all_solves_per_s": len(probs) * args.steps / el,
             "fp64_batch": {"value": len(probs) / el64b, "unit": "solves/s"},
             "fp64_one_at_a_time": {"value": len(probs) / el1, "unit": "solves/s", "latency_ms": pct(lat1)},
-            "outer": [h["outer"] for h in hists], "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+            "outer": [h["outer"] for h in hists], "tuning": tuning, "roofline": roof, "kernels": kernels,
+            "cpu_baseline": cpu}
 
 
 def run_serve_workload(args, R):
@@ -323,8 +340,17 @@ def run_serve_workload(args, R):
     P = [R.make_problem(pr) for pr in probs]
     O, O64 = R.make_options(opts), R.make_options(synth.Options(max_gmres=1500))
 
+    # execution settings for the server's context, tuned on a median-size request
+    mid = sorted(range(len(probs)), key=lambda q: probs[q].nx * probs[q].ny)[len(probs) // 2]
+    ctx = R.rsp_context_create(0)
+    try:
+        tuning = apply_tuning(R, ctx, args, P[mid], O, inst.yd[mid], inst.f[mid])
+        tune = R.rsp_get_tuning(ctx)
+    finally:
+        R.rsp_context_destroy(ctx)
+
     def serve(arrivals):
-        srv = R.rsp_server_create(O)
+        srv = R.rsp_server_create(O, tune=tune)
         try:
             t0 = time.perf_counter()
             tickets = []
@@ -381,7 +407,7 @@ def run_serve_workload(args, R):
                             "mean_batch": st_c["mean_batch"]},
             "rel_err_mixed_vs_fp64": errs, "all_solves_per_s": st_o["solves_per_s"],
             "fp64_one_at_a_time": {"value": len(probs) / el1, "unit": "solves/s", "latency_ms": pct(lat1)},
-            "roofline": None, "cpu_baseline": None}
+            "tuning": tuning, "roofline": None, "cpu_baseline": None}
 
 
 def main():
@@ -393,6 +419,12 @@ def main():
                     help="plain: 255x255 (default); small: 63x63; precision: 511x511 exp; batch: 64 uneven "
                          "instances per step; serve: Poisson request stream through the server")
     ap.add_argument("--count", type=int, default=64, help="instances (batch) or requests (serve)")
+    ap.add_argument("--tune", type=int, default=1, choices=[0, 1],
+                    help="1: rsp_autotune picks graphs and the Arnoldi chunk on the workload first")
+    ap.add_argument("--graphs", type=int, default=0, choices=[0, 1],
+                    help="with --tune 0: capture Arnoldi chunks and continuation runs into hipGraphs")
+    ap.add_argument("--gm-chunk", type=int, default=32, help="with --tune 0: Arnoldi steps between GMRES "
+                                                             "header reads")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"],
                     help="mixed: FP32 line factors + FP64 refinement (the FP64 path is timed beside it)")
     ap.add_argument("--max-refine", type=int, default=0,
@@ -427,6 +459,9 @@ def main():
     y, p, u = (torch.empty_like(ydt) for _ in range(3))
     P, O, O64 = R.make_problem(prob), R.make_options(opts), R.make_options(opts64)
     ctx = R.rsp_context_create(0)
+    tuning = None
+    if not args.phases:
+        tuning = apply_tuning(R, ctx, args, P, O, ydt, ft)
     if args.phases:
         try:
             R.rsp_setup(ctx, P, O, ydt, ft)
@@ -517,7 +552,7 @@ def main():
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
                      "residual_final": hist["residual_final"], "norm": hist["norm"][-1]},
-           "fp64": cmp64, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+           "fp64": cmp64, "tuning": tuning, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
     print(json.dumps(out))
 
 

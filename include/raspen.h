@@ -221,6 +221,48 @@ int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const
 /* Device bytes rsp_solve_batch needs for these problems (0 if one is invalid). */
 size_t rsp_batch_workspace_bytes(int count, const rsp_problem* probs, const rsp_options* opts);
 
+/* ---- execution tuning ----
+   How a context issues its launches; none of it changes a result (the same kernels
+   run in the same order either way, so results are bitwise equal). */
+typedef struct rsp_tuning {
+  int32_t graphs;      /* 1: the Arnoldi chunks of GMRES and the continuation runs of the
+                          local Newton solves are captured once into hipGraphs (per
+                          layout, options and launch shape) and replayed; 0: direct
+                          stream launches.  Timing (rsp_set_profiling) launches directly. */
+  int32_t gm_chunk;    /* Arnoldi steps (Jacobian action + orthogonalisation) enqueued
+                          between two host reads of the GMRES stop flags, 1..64 (default 32):
+                          longer chunks read back less often and waste at most
+                          gm_chunk - 1 skipped steps once every instance has stopped */
+  int32_t sx, sy;      /* rsp_autotune: suggested subdomain counts for the sample's grid */
+  int32_t max_batch;   /* rsp_autotune: instances per batch beyond which throughput no
+                          longer grows (copies of the sample) */
+  double solves_per_s; /* rsp_autotune: measured throughput of the chosen settings */
+} rsp_tuning;
+
+/* Current settings of the context (sx, sy, max_batch, solves_per_s are 0). */
+int rsp_get_tuning(rsp_context* ctx, rsp_tuning* out);
+
+/* Apply graphs and gm_chunk (the other fields are ignored).  RSP_EINVAL if out of range. */
+int rsp_set_tuning(rsp_context* ctx, const rsp_tuning* t);
+
+#define RSP_TUNE_PARTITION 1   /* also try other subdomain counts (same overlap)          */
+#define RSP_TUNE_BATCH 2       /* also measure batches of copies of the sample             */
+
+/* Autotuner.  Times whole solves of the sample (device inputs yd, f as for rsp_solve)
+   on this context: graphs {0, 1} x gm_chunk {4, 8, 16, restart}; with
+   RSP_TUNE_PARTITION the subdomain counts whose tiles (with the sample's overlap) fill
+   line blocks of 48, 64 or 80 unknowns, which changes the iteration counts but not the
+   solution the method converges to (its fixed point solves the global system for any
+   partition); with RSP_TUNE_BATCH batches of 1, 2, 4, ... copies up to the first that
+   gains less than 5 % (max_batch: the smallest within 5 % of the best).  Applies the
+   chosen graphs and gm_chunk to the context and writes everything to `out`.  Results
+   are cached per grid, partition, overlap, precision, restart length and flags for
+   the life of the process (a cached call measures nothing).  Allocates device memory
+   for the trial outputs and replaces the problem bound by rsp_setup.  Errors:
+   RSP_EINVAL (bad arguments, or the sample does not converge), RSP_ENOMEM, RSP_EHIP. */
+int rsp_autotune(rsp_context* ctx, const rsp_problem* sample, const rsp_options* opts,
+                 const double* yd, const double* f, int flags, rsp_tuning* out, hipStream_t stream);
+
 /* ---- serving: continuous batching of solves on one device ----
    A server owns a context, a stream and a worker thread.  Requests are admitted
    first come first served between two outer iterations of the running batch
@@ -237,6 +279,8 @@ typedef struct rsp_server_options {
   int32_t max_batch;    /* most instances solved together (0: no limit)               */
   size_t hbm_budget;    /* device bytes for the batch layout (0: no limit)            */
   rsp_options opts;     /* solver options of every request                            */
+  rsp_tuning tune;      /* execution settings of the server's context (gm_chunk 0:
+                           the defaults); e.g. from rsp_autotune on a typical request */
 } rsp_server_options;
 
 #define RSP_TICKET_QUEUED 0

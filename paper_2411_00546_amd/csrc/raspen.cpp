@@ -16,7 +16,9 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 using rsp::DevProblem;
@@ -271,7 +273,19 @@ struct Pending {
   int kid;
   hipEvent_t a, b;
   double flops, bytes;
+  int step;   // Arnoldi step of a GMRES launch whose work is settled afterwards, else -1
 };
+
+// A launch sequence that is captured once and replayed: its kind and the integers
+// that shape its launches (list slot, item and instance counts, first step, length).
+enum SeqKind { SEQ_ARNOLDI, SEQ_NEWTON };
+struct GraphKey {
+  int kind, a, b, c, d;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(kind, a, b, c, d) < std::tie(o.kind, o.a, o.b, o.c, o.d);
+  }
+};
+constexpr size_t kMaxGraphs = 256;
 
 }  // namespace
 
@@ -301,6 +315,12 @@ struct rsp_context {
   // the instance bound by rsp_setup / rsp_solve for the single-problem calls
   Inst single;
   bool ready = false;
+  // captured launch sequences (hipGraphs), valid while the launch signature holds
+  int graphs = 0;               // capture and replay (else plain stream launches)
+  int gm_chunk = 32;            // Arnoldi steps between two reads of the GMRES headers
+  hipStream_t cap = nullptr;    // private stream, only ever in capture mode
+  uint64_t gsig = 0;
+  std::map<GraphKey, hipGraphExec_t> gcache;
   // kernel timing
   bool prof = false;
   int prof_only = -1;   // time only this kernel class (-1: every class)
@@ -311,20 +331,32 @@ struct rsp_context {
 
 namespace {
 
+int account(rsp_context* ctx, const Pending& p) {
+  HIPCHK(hipEventSynchronize(p.b));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+  rsp_kernel_stat& k = ctx->kstat[p.kid];
+  k.launches += 1;
+  k.ms += ms;
+  k.flops += p.flops;
+  k.bytes += p.bytes;
+  return 0;
+}
+
+// Accounts the pending timings (those of GMRES launches whose work is not settled
+// yet stay pending).
 int resolve_events(rsp_context* ctx) {
+  std::vector<Pending> keep;
   for (auto& p : ctx->pending) {
-    HIPCHK(hipEventSynchronize(p.b));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-    rsp_kernel_stat& k = ctx->kstat[p.kid];
-    k.launches += 1;
-    k.ms += ms;
-    k.flops += p.flops;
-    k.bytes += p.bytes;
+    if (p.step >= 0) {
+      keep.push_back(p);
+      continue;
+    }
+    RSPCHK(account(ctx, p));
     ctx->ev_pool.push_back(p.a);
     ctx->ev_pool.push_back(p.b);
   }
-  ctx->pending.clear();
+  ctx->pending.swap(keep);
   return 0;
 }
 
@@ -346,9 +378,10 @@ struct Timed {
   int kid;
   hipStream_t st;
   double fl, by;
+  int step;
   hipEvent_t a = nullptr;
-  Timed(rsp_context* c_, int kid_, hipStream_t st_, double fl_, double by_)
-      : c(c_), kid(kid_), st(st_), fl(fl_), by(by_) {
+  Timed(rsp_context* c_, int kid_, hipStream_t st_, double fl_, double by_, int step_ = -1)
+      : c(c_), kid(kid_), st(st_), fl(fl_), by(by_), step(step_) {
     if (c->prof && (c->prof_only < 0 || c->prof_only == kid) && (a = event_get(c)) != nullptr &&
         hipEventRecord(a, st) != hipSuccess)
       a = nullptr;
@@ -357,10 +390,80 @@ struct Timed {
     if (!a) return;
     hipEvent_t b = event_get(c);
     if (!b || hipEventRecord(b, st) != hipSuccess) return;
-    c->pending.push_back({kid, a, b, fl, by});
+    c->pending.push_back({kid, a, b, fl, by, step});
     if (c->pending.size() > 16384) (void)resolve_events(c);
   }
 };
+
+// Everything the captured launches take as arguments besides the graph key: the
+// layout, the arena pointers and the options the kernels read.  A change drops
+// every captured graph.
+uint64_t launch_signature(const rsp_context* ctx) {
+  uint64_t h = 1469598103934665603ull;   // FNV-1a
+  auto add = [&h](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  auto val = [&add](auto v) { add(&v, sizeof v); };
+  const Geometry& g = ctx->geo;
+  val(g.ninst), val(g.S), val(g.txm), val(g.tym), val(g.M), val(g.ntot);
+  add(&ctx->w, sizeof(Work));   // pointers only
+  val(ctx->yd), val(ctx->f), val(ctx->x);
+  const rsp_options& o = ctx->opts;
+  val(o.tol_inner), val(o.sigma), val(o.alpha_min), val(o.gmres_restart), val(o.max_inner);
+  val(o.precision), val(ctx->fp32), val(ctx->nref);
+  return h;
+}
+
+// Drops the captured graphs (after the stream has drained: none may still run).
+int drop_graphs(rsp_context* ctx, hipStream_t st) {
+  if (ctx->gcache.empty()) return 0;
+  HIPCHK(hipStreamSynchronize(st));
+  for (auto& kv : ctx->gcache) (void)hipGraphExecDestroy(kv.second);
+  ctx->gcache.clear();
+  return 0;
+}
+
+// Runs the launches `enqueue(stream)` issues on `st`: directly, or (graphs on) as a
+// graph captured from them once on the private stream and replayed for every later
+// call with the same key and launch signature.  The sequences captured here are
+// kernel launches only.  With event timing on they are launched directly: event
+// pairs recorded inside a graph do not give usable elapsed times.
+template <class F>
+int launch_seq(rsp_context* ctx, const GraphKey& key, hipStream_t st, F&& enqueue) {
+  if (!ctx->graphs || ctx->prof) {
+    enqueue(st);
+    HIPCHK(hipGetLastError());
+    return 0;
+  }
+  const uint64_t sig = launch_signature(ctx);
+  if (sig != ctx->gsig) {
+    RSPCHK(drop_graphs(ctx, st));
+    ctx->gsig = sig;
+  }
+  auto it = ctx->gcache.find(key);
+  if (it == ctx->gcache.end()) {
+    if (ctx->gcache.size() >= kMaxGraphs) RSPCHK(drop_graphs(ctx, st));
+    if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    enqueue(ctx->cap);
+    const hipError_t le = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(ctx->cap, &g);
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipSuccess;
+    if (le == hipSuccess && ce == hipSuccess && g) ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (le != hipSuccess || ce != hipSuccess || !g || ie != hipSuccess) {
+      const hipError_t e = le != hipSuccess ? le : ce != hipSuccess ? ce : ie;
+      return fail(RSP_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    it = ctx->gcache.emplace(key, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, st));
+  return 0;
+}
 
 // Algorithmic work of the per-subdomain kernels (m = 2 tx line unknowns, ty lines).
 struct SubWork {
@@ -501,27 +604,29 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
     // without looking, then check after every step
     const int batch = std::max(1, std::min(ncont - it, o.max_inner + 1 - it));
     const SubWork sw = sub_work(ctx, set, true);
-    for (int b = 0; b < batch; ++b) {
-      {
-        Timed t(ctx, KID_FACTOR, st, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
-        rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g, w.fallback, w.counter, st);
+    RSPCHK(launch_seq(ctx, GraphKey{SEQ_NEWTON, count, batch, 0, 0}, st, [&](hipStream_t s) {
+      for (int b = 0; b < batch; ++b) {
+        {
+          Timed t(ctx, KID_FACTOR, s, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
+          rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g,
+                             w.fallback, w.counter, s);
+        }
+        {
+          Timed t(ctx, KID_SOLVE_BWD, s, sw.bwd_fl, sw.bwd_by);
+          rsp::launch_solve_bwd(I, M, w.state, w.fac, ctx->fp32, w.g, w.dir, s);
+        }
+        if (ctx->nref > 0) {
+          Timed t(ctx, KID_REFINE, s, ctx->nref * (sw.solve_fl + 20.0 * sw.tile_by / 8),
+                  ctx->nref * (sw.solve_by + 2 * sw.tile_by));
+          rsp::launch_newton_refine(I, M, w.tilex, w.c, w.state, w.fac, ctx->fp32, w.res, w.dir, ctx->nref, s);
+        }
+        {
+          Timed t(ctx, KID_LINESEARCH, s, 40.0 * sw.tile_by / 8, 6 * sw.tile_by);
+          rsp::launch_linesearch(I, w.tilex, ctx->yd, ctx->f, w.c, w.dir, w.res, w.state, o.sigma,
+                                 o.alpha_min, o.max_inner, s);
+        }
       }
-      {
-        Timed t(ctx, KID_SOLVE_BWD, st, sw.bwd_fl, sw.bwd_by);
-        rsp::launch_solve_bwd(I, M, w.state, w.fac, ctx->fp32, w.g, w.dir, st);
-      }
-      if (ctx->nref > 0) {
-        Timed t(ctx, KID_REFINE, st, ctx->nref * (sw.solve_fl + 20.0 * sw.tile_by / 8),
-                ctx->nref * (sw.solve_by + 2 * sw.tile_by));
-        rsp::launch_newton_refine(I, M, w.tilex, w.c, w.state, w.fac, ctx->fp32, w.res, w.dir, ctx->nref, st);
-      }
-      {
-        Timed t(ctx, KID_LINESEARCH, st, 40.0 * sw.tile_by / 8, 6 * sw.tile_by);
-        rsp::launch_linesearch(I, w.tilex, ctx->yd, ctx->f, w.c, w.dir, w.res, w.state, o.sigma,
-                               o.alpha_min, o.max_inner, st);
-      }
-    }
-    HIPCHK(hipGetLastError());
+    }));
     it += batch;
     RSPCHK(read_state());
     active = count_active();
@@ -566,12 +671,60 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
 
 // Algorithm 4 for the items I: out = -d + sum_i P~_i J_i^{-1}(h^-2 weighted outside
 // neighbours of d) on their instances' segments.
+// Algorithmic flops and bytes of one Jacobian action over the subdomains of `sw`, and
+// of Arnoldi step q (classical Gram-Schmidt twice, normalisation) on vectors of total
+// length L.
+double apply_flops(const rsp_context* ctx, const SubWork& sw) { return (1 + ctx->nref) * sw.solve_fl; }
+double apply_bytes(const rsp_context* ctx, const SubWork& sw) {
+  return (1 + ctx->nref) * sw.solve_by + 2 * sw.tile_by;
+}
+double ortho_flops(double L, int q) { return L * (8.0 * (q + 1) + 3); }
+double ortho_bytes(double L, int q) { return 8.0 * L * (4.0 * q + 13); }
+
+// step >= 0: Arnoldi step of a GMRES cycle (its timing is settled by settle_gmres_timing).
 void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
-               hipStream_t st) {
-  Timed t(ctx, KID_BLOCK_SOLVE, st, (1 + ctx->nref) * sw.solve_fl,
-          (1 + ctx->nref) * sw.solve_by + 2 * sw.tile_by);
+               hipStream_t st, int step = -1) {
+  Timed t(ctx, KID_BLOCK_SOLVE, st, apply_flops(ctx, sw), apply_bytes(ctx, sw), step);
   rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, out, ctx->nref,
                         ctx->w.g, st);
+}
+
+// After the headers of a GMRES chunk are read: Arnoldi step q did work for the
+// instances whose step count now exceeds q (a stopped instance's kernels return at
+// once).  The timed launches of the chunk are re-priced by those instances, and
+// launches that did no work for any instance are dropped from the statistics.
+void settle_gmres_timing(rsp_context* ctx, const std::vector<Inst*>& cyc) {
+  std::vector<Pending> keep;
+  keep.reserve(ctx->pending.size());
+  for (Pending p : ctx->pending) {
+    if (p.step < 0) {
+      keep.push_back(p);
+      continue;
+    }
+    std::vector<Inst*> act;
+    double L = 0;
+    for (Inst* in : cyc)
+      if (ctx->hgm[in->slot].steps > p.step) {
+        act.push_back(in);
+        L += 2.0 * in->n;
+      }
+    if (act.empty()) {
+      ctx->ev_pool.push_back(p.a);
+      ctx->ev_pool.push_back(p.b);
+      continue;
+    }
+    if (p.kid == KID_BLOCK_SOLVE) {
+      const SubWork sw = sub_work(ctx, act, false);
+      p.flops = apply_flops(ctx, sw);
+      p.bytes = apply_bytes(ctx, sw);
+    } else {
+      p.flops = ortho_flops(L, p.step);
+      p.bytes = ortho_bytes(L, p.step);
+    }
+    p.step = -1;
+    keep.push_back(p);
+  }
+  ctx->pending.swap(keep);
 }
 
 // |v|_2 of every instance of `set` (list slot l must hold set), read back into hnorm.
@@ -597,7 +750,6 @@ int read_gm_headers(rsp_context* ctx, hipStream_t st) {
 // in lockstep (a finished one is skipped through its stop flag); the host enqueues
 // Arnoldi steps in chunks and reads the headers back once per chunk.
 int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
-  constexpr int kChunk = 8;
   const rsp_options& o = ctx->opts;
   const int m = o.gmres_restart;
   Work& w = ctx->w;
@@ -617,17 +769,21 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     I.skip = &w.gst[0].done;
     I.skip_stride = rsp::kGmDoneStride;
     const SubWork sw = sub_work(ctx, cyc, false);
+    double L = 0;
+    for (const Inst* in : cyc) L += 2.0 * in->n;
     for (int j = 0; j < m;) {
-      const int chunk = std::min(kChunk, m - j);
-      for (int c = 0; c < chunk; ++c, ++j) {
-        jac_apply(ctx, I, sw, w.V + (size_t)j * ldv, w.w, st);
-        double L = 0;
-        for (const Inst* in : cyc) L += 2.0 * in->n;
-        Timed tm(ctx, KID_GMRES_ORTHO, st, L * (8.0 * (j + 1) + 3), 8.0 * L * (4.0 * j + 13));
-        rsp::launch_gm_arnoldi(B, w.V, j, w.w, w.p1, w.p2, st);
-      }
-      HIPCHK(hipGetLastError());
+      const int chunk = std::min(ctx->gm_chunk, m - j), j0 = j;
+      RSPCHK(launch_seq(ctx, GraphKey{SEQ_ARNOLDI, lslot, I.count, B.count, j0 * 1024 + chunk}, st,
+                        [&](hipStream_t s) {
+                          for (int q = j0; q < j0 + chunk; ++q) {
+                            jac_apply(ctx, I, sw, w.V + (size_t)q * ldv, w.w, s, q);
+                            Timed tm(ctx, KID_GMRES_ORTHO, s, ortho_flops(L, q), ortho_bytes(L, q), q);
+                            rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, s);
+                          }
+                        }));
+      j += chunk;
       RSPCHK(read_gm_headers(ctx, st));
+      if (ctx->prof) settle_gmres_timing(ctx, cyc);
       bool all = true;
       for (const Inst* in : cyc) all = all && ctx->hgm[in->slot].done;
       if (all) break;
@@ -1040,6 +1196,13 @@ int rsp_context_destroy(rsp_context* ctx) {
   if (!ctx) return 0;
   (void)hipSetDevice(ctx->device);
   (void)resolve_events(ctx);
+  for (const Pending& p : ctx->pending) {
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  if (!ctx->gcache.empty()) (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->gcache) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (void* m : ctx->gmem)
     if (m) (void)hipFree(m);
@@ -1179,6 +1342,24 @@ int rsp_set_profiling(rsp_context* ctx, int on) {
   return 0;
 }
 
+int rsp_get_tuning(rsp_context* ctx, rsp_tuning* out) {
+  if (!ctx || !out) return fail(RSP_EINVAL, "ctx and out are required");
+  *out = rsp_tuning{};
+  out->graphs = ctx->graphs;
+  out->gm_chunk = ctx->gm_chunk;
+  return 0;
+}
+
+int rsp_set_tuning(rsp_context* ctx, const rsp_tuning* t) {
+  if (!ctx || !t) return fail(RSP_EINVAL, "ctx and tuning are required");
+  if (t->graphs != 0 && t->graphs != 1) return fail(RSP_EINVAL, "graphs must be 0 or 1");
+  if (t->gm_chunk < 1 || t->gm_chunk > kMaxRestart)
+    return fail(RSP_EINVAL, "gm_chunk must be in [1, %d]", kMaxRestart);
+  ctx->graphs = t->graphs;
+  ctx->gm_chunk = t->gm_chunk;
+  return 0;
+}
+
 int rsp_set_profiling_filter(rsp_context* ctx, const char* name) {
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   if (!name || !*name) {
@@ -1196,6 +1377,11 @@ int rsp_set_profiling_filter(rsp_context* ctx, const char* name) {
 int rsp_reset_kernel_stats(rsp_context* ctx) {
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   RSPCHK(resolve_events(ctx));
+  for (const Pending& p : ctx->pending) {   // unsettled timings of an interrupted GMRES chunk
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
   for (auto& k : ctx->kstat) k = rsp_kernel_stat{};
   return 0;
 }

@@ -164,6 +164,10 @@ int rsp_server_create(rsp_server** out, const rsp_server_options* opts) {
   s->opts = *opts;
   r = rsp_context_create(&s->ctx, opts->device, opts->hbm_budget);
   if (r < 0) return r;
+  if (opts->tune.gm_chunk != 0 && (r = rsp_set_tuning(s->ctx, &opts->tune)) < 0) {
+    rsp_context_destroy(s->ctx);
+    return r;
+  }
   hipError_t e = hipSetDevice(opts->device);
   if (e == hipSuccess) e = hipStreamCreate(&s->stream);
   if (e != hipSuccess) {

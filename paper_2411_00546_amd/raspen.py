@@ -17,6 +17,7 @@ RSP_TICKET_QUEUED, RSP_TICKET_RUNNING, RSP_TICKET_DONE = 0, 1, 2
 RSP_FP64, RSP_FP32_REFINED = 0, 1
 RSP_CONT_FIRST, RSP_CONT_NONE, RSP_CONT_EVERY = 0, 1, 2
 RSP_HIST_MAX = 64
+RSP_TUNE_PARTITION, RSP_TUNE_BATCH = 1, 2
 
 
 class RaspenError(RuntimeError):
@@ -74,9 +75,14 @@ class rsp_kernel_stat(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class rsp_tuning(ctypes.Structure):
+    _fields_ = [("graphs", ctypes.c_int32), ("gm_chunk", ctypes.c_int32), ("sx", ctypes.c_int32),
+                ("sy", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("solves_per_s", ctypes.c_double)]
+
+
 class rsp_server_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t), ("opts", rsp_options)]
+                ("hbm_budget", ctypes.c_size_t), ("opts", rsp_options), ("tune", rsp_tuning)]
 
 
 class rsp_server_report(ctypes.Structure):
@@ -115,6 +121,9 @@ SIGNATURES = [
     ("rsp_solve_batch", _I, [_P, _I, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(rsp_history), _P]),
     ("rsp_batch_workspace_bytes", ctypes.c_size_t, [_I, _PROB, _OPTS]),
+    ("rsp_get_tuning", _I, [_P, ctypes.POINTER(rsp_tuning)]),
+    ("rsp_set_tuning", _I, [_P, ctypes.POINTER(rsp_tuning)]),
+    ("rsp_autotune", _I, [_P, _PROB, _OPTS, _P, _P, _I, ctypes.POINTER(rsp_tuning), _P]),
     ("rsp_server_create", _I, [ctypes.POINTER(_P), ctypes.POINTER(rsp_server_options)]),
     ("rsp_server_submit", _I, [_P, _PROB, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]),
     ("rsp_server_poll", _I, [_P, ctypes.c_uint64, _I32P]),
@@ -305,10 +314,10 @@ def rsp_batch_workspace_bytes(probs, opts):
     return load().rsp_batch_workspace_bytes(n, parr, ctypes.byref(opts))
 
 
-def rsp_server_create(opts, device=0, max_batch=0, hbm_budget=0):
-    """Start a server; opts: rsp_options of every request."""
+def rsp_server_create(opts, device=0, max_batch=0, hbm_budget=0, tune=None):
+    """Start a server; opts: rsp_options of every request; tune: rsp_tuning or None."""
     h = ctypes.c_void_p()
-    so = rsp_server_options(device, max_batch, hbm_budget, opts)
+    so = rsp_server_options(device, max_batch, hbm_budget, opts, tune if tune is not None else rsp_tuning())
     _check(load().rsp_server_create(ctypes.byref(h), ctypes.byref(so)))
     return h
 
@@ -346,6 +355,28 @@ def rsp_server_destroy(srv):
 
 def rsp_set_profiling(ctx, on=True):
     return _check(load().rsp_set_profiling(ctx, int(on)))
+
+
+def rsp_get_tuning(ctx):
+    t = rsp_tuning()
+    _check(load().rsp_get_tuning(ctx, ctypes.byref(t)))
+    return t
+
+
+def rsp_set_tuning(ctx, graphs=None, gm_chunk=None):
+    t = rsp_get_tuning(ctx)
+    if graphs is not None:
+        t.graphs = int(graphs)
+    if gm_chunk is not None:
+        t.gm_chunk = int(gm_chunk)
+    return _check(load().rsp_set_tuning(ctx, ctypes.byref(t)))
+
+
+def rsp_autotune(ctx, prob, opts, yd, f, flags=0, stream=None):
+    t = rsp_tuning()
+    _check(load().rsp_autotune(ctx, ctypes.byref(prob), ctypes.byref(opts), _ptr(yd), _ptr(f, True),
+                               int(flags), ctypes.byref(t), _stream(stream)))
+    return t
 
 
 def rsp_set_profiling_filter(ctx, name=None):

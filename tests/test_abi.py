@@ -109,3 +109,39 @@ def test_server_and_batch_entry_points_are_declared():
     for must in ["rsp_solve_batch", "rsp_batch_workspace_bytes", "rsp_server_create", "rsp_server_submit",
                  "rsp_server_poll", "rsp_server_wait", "rsp_server_stats", "rsp_server_destroy"]:
         assert must in names
+
+
+def test_tuning_entry_points_are_declared():
+    names = declared_functions()
+    for must in ["rsp_get_tuning", "rsp_set_tuning", "rsp_autotune", "rsp_set_profiling_filter"]:
+        assert must in names
+
+
+def test_struct_layouts_match_the_header(R, tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets of the C structs,
+    as a plain C compile of the header reports them."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("no C compiler or HIP headers")
+    structs = {"rsp_problem": R.rsp_problem, "rsp_options": R.rsp_options, "rsp_history": R.rsp_history,
+               "rsp_tuning": R.rsp_tuning, "rsp_server_options": R.rsp_server_options,
+               "rsp_server_report": R.rsp_server_report, "rsp_kernel_stat": R.rsp_kernel_stat}
+    lines = []
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    src = tmp_path / "probe.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"raspen.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I",
+                    "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert int(out[name + "." + field]) == getattr(cls, field).offset, (name, field)

@@ -71,11 +71,12 @@ def single(R, p, opts):
     return st, h, b.result()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_served_results_equal_single_solves(R, precision):
+@pytest.mark.parametrize("precision,graphs", [(0, 0), (1, 0), (1, 1)])
+def test_served_results_equal_single_solves(R, precision, graphs):
     import torch
     opts = synth.Options(precision=precision, max_refine=0)
-    srv = R.rsp_server_create(R.make_options(opts))
+    tune = R.rsp_tuning(graphs=1, gm_chunk=5) if graphs else None
+    srv = R.rsp_server_create(R.make_options(opts), tune=tune)
     try:
         bufs = [Buffers(p) for p in REQS]
         torch.cuda.synchronize()

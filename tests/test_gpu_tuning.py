@@ -1,0 +1,213 @@
+"""GPU tests of the execution settings (rsp_tuning) and the autotuner: captured
+launch sequences (graphs) and the Arnoldi chunk length.  Both change only how the same launches are
+issued, never what they compute, so every result must be bit-identical to the one
+obtained with direct stream launches:
+
+  * one solve replayed several times from a context, with direct-launch solves,
+    other layouts (which drop the captured graphs) and eager evaluations between
+    the replays, each replay checked against the direct-launch result;
+  * a batch of mixed tile sizes, partial-pivoting subdomains included;
+  * chunk lengths 1, 5, 8 and 30 against the default of 32, with and without graphs.
+
+The autotuner (rsp_autotune) must return settings in range, apply them, answer a
+repeated call from its cache, and a partition it suggests must converge to the
+same solution as the sample's (the fixed point of the method does not depend on
+the partition).
+"""
+import numpy as np
+import pytest
+
+import synth
+from test_gpu_batch import MIXED, SAME_M, TIGHT, dev, host, prob, run_batch, run_single
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_00546_amd import raspen
+    raspen.load()
+    return raspen
+
+
+def same(a, b):
+    (xa, ua), (xb, ub) = a, b
+    return np.array_equal(xa, xb) and np.array_equal(ua, ub)
+
+
+def test_default_tuning_and_validation(R):
+    ctx = R.rsp_context_create(0)
+    try:
+        t = R.rsp_get_tuning(ctx)
+        assert (t.graphs, t.gm_chunk) == (0, 32)
+        for bad in ({"graphs": 2}, {"gm_chunk": 0}, {"gm_chunk": 65}):
+            with pytest.raises(R.RaspenError) as e:
+                R.rsp_set_tuning(ctx, **bad)
+            assert e.value.code == R.RSP_EINVAL
+        R.rsp_set_tuning(ctx, graphs=1, gm_chunk=30)
+        t = R.rsp_get_tuning(ctx)
+        assert (t.graphs, t.gm_chunk) == (1, 30)
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_equal_direct_launches(R, precision):
+    import torch
+    opts = synth.Options(precision=precision, max_refine=1 if precision else 0)
+    p, other = SAME_M[0], prob(40, 52, 1, 2, 3, phi=synth.PHI_EXP, seed=31)
+    ctx = R.rsp_context_create(0)
+    try:
+        st0, h0, eager = run_single(R, p, opts, ctx)
+        _, _, eager_other = run_single(R, other, opts, ctx)
+        assert st0 == 0
+        R.rsp_set_tuning(ctx, graphs=1)
+        for rep in range(3):
+            st, h, got = run_single(R, p, opts, ctx)     # captures on rep 0, replays after
+            assert st == 0 and same(got, eager), rep
+            assert h["norm"] == h0["norm"] and h["gmres_its"] == h0["gmres_its"], rep
+            # direct launches in between
+            R.rsp_set_tuning(ctx, graphs=0)
+            assert same(run_single(R, other, opts, ctx)[2], eager_other), rep
+            R.rsp_set_tuning(ctx, graphs=1)
+            # another layout with graphs on: drops and re-captures
+            assert same(run_single(R, other, opts, ctx)[2], eager_other), rep
+            # eager evaluation on the bound problem between replays
+            yd, f = p.inputs()
+            R.rsp_setup(ctx, R.make_problem(p), R.make_options(opts), dev(yd), dev(f))
+            out = dev(np.zeros(2 * p.nx * p.ny))
+            R.rsp_eval(ctx, dev(eager[0]), 0, out)
+            torch.cuda.synchronize()
+            assert np.abs(host(out)).max() <= 1e-7 * np.abs(eager[0]).max(), rep
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
+def test_graph_batch_equals_direct_launches(R):
+    ctx = R.rsp_context_create(0)
+    try:
+        st, hists, eager = run_batch(R, MIXED, TIGHT, ctx=ctx)
+        assert st == 0
+        R.rsp_set_tuning(ctx, graphs=1)
+        for rep in range(2):
+            st2, hists2, got = run_batch(R, MIXED, TIGHT, ctx=ctx)
+            assert st2 == 0
+            for q in range(len(MIXED)):
+                assert same(got[q], eager[q]), (rep, q)
+                assert hists2[q]["norm"] == hists[q]["norm"], (rep, q)
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_chunk_length_does_not_change_results(R, graphs):
+    probs = SAME_M[:3]
+    opts = synth.Options(gmres_restart=30)
+    ctx = R.rsp_context_create(0)
+    try:
+        _, h_ref, ref = run_batch(R, probs, opts, ctx=ctx)
+        for chunk in (1, 5, 8, 30):
+            R.rsp_set_tuning(ctx, graphs=graphs, gm_chunk=chunk)
+            st, hists, got = run_batch(R, probs, opts, ctx=ctx)
+            assert st == 0
+            for q in range(len(probs)):
+                assert same(got[q], ref[q]), (chunk, q)
+                assert hists[q]["gmres_its"] == h_ref[q]["gmres_its"], (chunk, q)
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
+def test_autotune(R):
+    import time
+    import torch
+    p = prob(63, 63, 2, 2, 2, seed=41)
+    yd, f = p.inputs()
+    ydt, ft = dev(yd), dev(f)
+    opts = synth.Options(precision=1, max_refine=0)
+    ctx = R.rsp_context_create(0)
+    try:
+        with pytest.raises(R.RaspenError) as e:
+            R.rsp_autotune(ctx, R.make_problem(p), R.make_options(opts), ydt, ft, flags=8)
+        assert e.value.code == R.RSP_EINVAL
+        flags = R.RSP_TUNE_PARTITION | R.RSP_TUNE_BATCH
+        t = R.rsp_autotune(ctx, R.make_problem(p), R.make_options(opts), ydt, ft, flags=flags)
+        assert t.graphs in (0, 1) and 1 <= t.gm_chunk <= opts.gmres_restart
+        assert t.max_batch >= 1 and (t.max_batch & (t.max_batch - 1)) == 0
+        assert t.solves_per_s > 0
+        cur = R.rsp_get_tuning(ctx)
+        assert (cur.graphs, cur.gm_chunk) == (t.graphs, t.gm_chunk)
+        # a cached answer: same settings, no measurement
+        t0 = time.perf_counter()
+        t2 = R.rsp_autotune(ctx, R.make_problem(p), R.make_options(opts), ydt, ft, flags=flags)
+        assert time.perf_counter() - t0 < 0.05
+        assert (t2.graphs, t2.gm_chunk, t2.sx, t2.sy, t2.max_batch) == (t.graphs, t.gm_chunk, t.sx, t.sy, t.max_batch)
+        # the suggested partition converges to the same solution
+        q = synth.Problem(**{**p.__dict__, "sx": t.sx, "sy": t.sy})
+        R.rsp_partition(R.make_problem(q))
+        _, _, (x0, _) = run_single(R, p, TIGHT, ctx)
+        st, _, (x1, _) = run_single(R, q, TIGHT, ctx)
+        assert st == 0
+        assert np.abs(x1 - x0).max() <= 1e-9 * np.abs(x0).max(), (t.sx, t.sy)
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
+def test_kernel_timing_inside_graphs(R):
+    """Event timing with graphs on launches directly (event pairs recorded inside a
+    graph give no usable elapsed times): the counts equal those with graphs off, the
+    times are of the same size, and the results do not change."""
+    p = SAME_M[1]
+    opts = synth.Options(precision=1, max_refine=0)
+    ctx = R.rsp_context_create(0)
+    try:
+        stats, outs = {}, {}
+        for graphs in (0, 1):
+            R.rsp_set_tuning(ctx, graphs=graphs)
+            for flt in (None, "block_solve"):
+                R.rsp_set_profiling_filter(ctx, flt)
+                R.rsp_set_profiling(ctx, True)
+                R.rsp_reset_kernel_stats(ctx)
+                _, _, out = run_single(R, p, opts, ctx)
+                R.rsp_set_profiling(ctx, False)
+                stats[graphs, flt] = R.rsp_kernel_stats(ctx)
+                outs[graphs, flt] = out
+        R.rsp_set_profiling_filter(ctx, None)
+    finally:
+        R.rsp_context_destroy(ctx)
+    for key, out in outs.items():
+        assert same(out, outs[0, None]), key
+    for flt in (None, "block_solve"):
+        a, b = stats[0, flt], stats[1, flt]
+        for name in a:
+            assert a[name]["launches"] == b[name]["launches"], (flt, name)
+            if flt == "block_solve" and name != "block_solve":
+                assert b[name]["launches"] == 0, name
+        for name in ("block_solve", "gmres_ortho", "factor") if flt is None else ("block_solve",):
+            ta = a[name]["ms"] / a[name]["launches"]
+            tb = b[name]["ms"] / b[name]["launches"]
+            assert 0.3 < tb / ta < 3.0, (flt, name, ta, tb)
+
+
+@pytest.mark.parametrize("chunk", [1, 8, 30])
+def test_timed_gmres_launches_count_only_work_done(R, chunk):
+    """Arnoldi steps enqueued past an instance's stop are no-ops: the kernel statistics
+    count only the launches that did work, whatever the chunk length, so they agree
+    with the history's Jacobian-action and GMRES counts."""
+    p = SAME_M[3]
+    opts = synth.Options(precision=1, max_refine=0)
+    ctx = R.rsp_context_create(0)
+    try:
+        R.rsp_set_tuning(ctx, gm_chunk=chunk)
+        R.rsp_set_profiling(ctx, True)
+        R.rsp_reset_kernel_stats(ctx)
+        st, h, _ = run_single(R, p, opts, ctx)
+        R.rsp_set_profiling(ctx, False)
+        ks = R.rsp_kernel_stats(ctx)
+    finally:
+        R.rsp_context_destroy(ctx)
+    assert st == 0
+    assert ks["block_solve"]["launches"] == h["jac_applies"], (ks["block_solve"], h["jac_applies"])
+    assert ks["gmres_ortho"]["launches"] == h["gmres_total"], (ks["gmres_ortho"], h["gmres_total"])
