@@ -1,4 +1,4 @@
-// Local Jacobian factorisation and solves (one workgroup per subdomain).
+// Local Jacobian factorisation for the local Newton solves and Algorithm 4.
 //
 // J_i = R_i F'_eps(x + P_i c) P_i (Section 4: x-derivative of F; eq. (DerC)) is
 // block tridiagonal over the grid lines of the tile: with the unknowns of line j
@@ -6,20 +6,29 @@
 //   D_j = [[T + diag(phi'(y)),        diag(g'(p)/nu)   ],
 //          [diag(phi''(y) p - 1),     T + diag(phi'(y))]]
 // with T = tridiag(-1/hx^2, 2/hx^2 + 2/hy^2, -1/hx^2), and both off-diagonal
-// blocks are -(1/hy^2) I.  Block LU: S_0 = D_0, S_j = D_j - hy^-4 S_{j-1}^{-1};
-// forward g_j = S_j^{-1}(r_j + hy^-2 g_{j-1}); backward z_j = g_j + hy^-2 S_j^{-1} z_{j+1}.
-// Each S_j is assembled in LDS and tested for column diagonal dominance.  A dominant
-// S_j (the usual case) is inverted by Gauss-Jordan with 16 x 16 pivot blocks whose
-// block products run on the matrix cores; partial pivoting would keep its diagonal,
-// so this is the same elimination.  A subdomain with a line that is not dominant is
-// redone by a second kernel with in-place Gauss-Jordan with partial pivoting in
-// registers (rows are not moved: step k pivots on row pr[k]; afterwards
-// S^{-1}[a][b] = A[pr[a]][pinv[b]]): per step the pivot is found inside the wave
-// that holds the column, the column goes through LDS (one barrier per step) and the
-// pivot row is broadcast with in-wave shuffles.
-// The inverses are stored transposed, facT[s][j][b][a] = S_j^{-1}[a][b], so that
-// the solves read them coalesced.  Lines are padded to M (multiple of 16) with
-// an identity block.
+// blocks are -(1/hy^2) I.  It is factored two-ended (twisted block LU) around the
+// twist line t = ty / 2:
+//   from the top     S_0 = D_0,       S_j = D_j - hy^-4 S_{j-1}^{-1}      (j < t)
+//   from the bottom  T_{ty-1} = D_{ty-1}, T_j = D_j - hy^-4 T_{j+1}^{-1}  (j > t)
+//   twist            Z_t = D_t - hy^-4 (S_{t-1}^{-1} + T_{t+1}^{-1})
+// and the explicit inverses F_j of S_j, T_j and Z_t are stored (the solves are
+// described in kernels_solve.hip).  The two chains are independent, so each
+// subdomain takes two workgroups, and the second one to finish factors the twist.
+//
+// Each line block is assembled in LDS and tested for column diagonal dominance.  A
+// dominant block (the usual case) is inverted by Gauss-Jordan with 16 x 16 pivot
+// blocks whose block products run on the matrix cores; partial pivoting would keep
+// its diagonal, so this is the same elimination.  The twist block adds the
+// contributions of both chains and need not be dominant: its block elimination
+// checks the exact partial-pivoting condition (every multiplier at most 1 in
+// magnitude) instead.  A subdomain where a test fails is redone by a second kernel
+// with in-place Gauss-Jordan with partial pivoting in registers (rows are not moved:
+// step k pivots on row pr[k]; afterwards S^{-1}[a][b] = A[pr[a]][pinv[b]]): per step
+// the pivot is found inside the wave that holds the column, the column goes through
+// LDS (one barrier per step) and the pivot row is broadcast with in-wave shuffles.
+// The inverses are stored transposed, facT[s][j][b][a] = F_j[a][b], so that the
+// solves read them coalesced.  Lines are padded to M (multiple of 16) with an
+// identity block.
 #include "rsp_kernels.h"
 
 namespace rsp {
