@@ -2,6 +2,14 @@
 // Algorithm 2, for every instance of a batch at once: Arnoldi with classical
 // Gram-Schmidt applied twice, Givens rotations on the Hessenberg column, the
 // stopping test |g_{j+1}| <= rtol |b| and the triangular solve, all on the device.
+//
+// Normalisation is deferred by one step: the second Gram-Schmidt pass of step j
+// writes the orthogonalised vector unscaled into V_{j+1} together with partial sums
+// of its squared norm, the Jacobian action of step j+1 takes it unscaled (the
+// operator is linear), and the first kernel of step j+1 scales V_{j+1} and the
+// product by 1/|V_{j+1}| while it forms the dot products, and applies the Givens
+// rotations to column j.  An Arnoldi step is three launches; a chunk of steps ends
+// with one small launch that finishes its last column.
 // Launch grid: (kGmBlocks, instances); blockIdx.y selects the instance, whose
 // vectors are its segment of the batch's concatenated vectors (basis vector k of
 // every instance: V + k ldv).  A per-instance stop
@@ -93,110 +101,13 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
 // NB vectors are issued unconditionally (index clamped to nv - 1, the extra ones hit
 // the cache) and the unused products are masked, so the loads are not serialised.
 
-// partial sums of V_i . w for i < nv over this block's chunk
-template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, const double* __restrict__ V, int nv,
-                                                const double* __restrict__ w,
-                                                double* __restrict__ partial) {
-  __shared__ double red[(kT / 64) * kGmMaxVec];
-  const Seg g = seg_of(B);
-  if (B.st[g.i].done) return;
-  const size_t L = g.L;
-  V += g.off;
-  w += g.off;
-  partial += g.i * kPart;
-  size_t lo, hi;
-  chunk_of(L, lo, hi);
-  double acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
-    // all NB loads first, so that they are in flight together
-    double v[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
-    const double we = w[e];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
-  }
-  const double r = block_sums<NB>(acc, nv, red);
-  if ((int)threadIdx.x < nv) partial[part_at(threadIdx.x, blockIdx.x)] = r;
-}
-
-// h = sum of the previous partials; w -= V h; then either the partial dots of the new
-// w with V (next = 0) or its partial squared norm (next = 1).  Block 0 adds h into
-// the Hessenberg column j.
-template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __restrict__ V, int nv,
-                                                  double* __restrict__ w,
-                                                  const double* __restrict__ pin, int first,
-                                                  int next, double* __restrict__ pout, int j) {
-  __shared__ double red[(kT / 64) * kGmMaxVec];
-  __shared__ double hs[kGmMaxVec];
-  const Seg g = seg_of(B);
-  if (B.st[g.i].done) return;
-  const size_t L = g.L;
-  V += g.off;
-  w += g.off;
-  pin += g.i * kPart;
-  pout += g.i * kPart;
-  gather_partials(pin, nv, hs);
-  if (blockIdx.x == 0 && (int)threadIdx.x < nv) {
-    double* Hc = B.hs[g.i].H + threadIdx.x * B.m + j;
-    *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
-  }
-  double h[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) h[i] = i < nv ? hs[i] : 0.0;
-  size_t lo, hi;
-  chunk_of(L, lo, hi);
-  double acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
-    double v[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
-    double we = w[e];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
-    w[e] = we;
-    if (next == 0) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
-    } else {
-      acc[0] = fma(we, we, acc[0]);
-    }
-  }
-  const int nout = next == 0 ? nv : 1;
-  const double r = block_sums<NB>(acc, nout, red);
-  if ((int)threadIdx.x < nout) pout[part_at(threadIdx.x, blockIdx.x)] = r;
-}
-
-// |w| from the partials; V_{j+1} = w / |w|.  Block 0 then stores H[j+1][j] and applies
-// the Givens rotations to Hessenberg column j: residual estimate and stopping test.
-// (Once the stop flag is set, blocks that start later skip V_{j+1}, which is then not
-// used: the update of x takes V_0 .. V_j.)  The column and the rotations are staged
-// in LDS so the sequential part runs from LDS.
-__global__ __launch_bounds__(kT) void k_gm_normalize(GmBatch B, double* __restrict__ V,
-                                                     const double* __restrict__ w,
-                                                     const double* __restrict__ pin, int j) {
-  __shared__ double hs[1];
+// Givens rotations on Hessenberg column j, whose subdiagonal entry is nrm: residual
+// estimate and stopping test.  Called by every thread of one block; the column and
+// the rotations are staged in LDS so the sequential part runs from LDS.
+__device__ void givens_column(const GmBatch& B, int inst, int j, double nrm) {
   __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
-  const Seg g = seg_of(B);
-  GmState* st = B.st + g.i;
-  if (st->done) return;
-  const size_t L = g.L;
-  double* Vn = V + (size_t)(j + 1) * B.ldv + g.off;
-  w += g.off;
-  gather_partials(pin + g.i * kPart, 1, hs);
-  const double nrm = sqrt(hs[0]);
-  const double inv = 1.0 / nrm;
-  size_t lo, hi;
-  chunk_of(L, lo, hi);
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) Vn[e] = w[e] * inv;
-  if (blockIdx.x != 0) return;
-  GmHess* hz = B.hs + g.i;
+  GmState* st = B.st + inst;
+  GmHess* hz = B.hs + inst;
   const int m = B.m;
   const int t = threadIdx.x;
   if (t <= j) col[t] = hz->H[t * m + j];
@@ -228,6 +139,120 @@ __global__ __launch_bounds__(kT) void k_gm_normalize(GmBatch B, double* __restri
   st->steps = j + 1;
   st->used += 1;
   if (!(st->rel > st->rtol) || st->used >= st->maxit || breakdown || j + 1 >= m) st->done = 1;
+}
+
+// First kernel of Arnoldi step j = nv - 1 (w = A V_j as the Jacobian action left it):
+// partial sums of V_i . w for i < nv over this block's chunk.  mode 0 (j = 0): V_j is
+// normalised already.  mode 1: V_j is unscaled; sigma = 1/|V_j| from the squared-norm
+// partials `pnorm`, V_j <- sigma V_j and w <- sigma w in place, and block 0 applies
+// the Givens rotations to column j - 1.  mode 2: as 1, but column j - 1 was finished
+// by k_gm_column at the end of the previous chunk.
+template <int NB>
+__global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, double* __restrict__ V, int nv,
+                                                double* __restrict__ w, const double* __restrict__ pnorm,
+                                                double* __restrict__ partial, int mode) {
+  __shared__ double red[(kT / 64) * kGmMaxVec];
+  __shared__ double hs[1];
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  const int j = nv - 1;
+  double nrm = 1.0, sig = 1.0;
+  if (mode != 0) {
+    gather_partials(pnorm + g.i * kPart, 1, hs);
+    nrm = sqrt(hs[0]);
+    sig = 1.0 / nrm;
+  }
+  const size_t L = g.L;
+  V += g.off;
+  w += g.off;
+  double* Vj = V + (size_t)j * B.ldv;
+  partial += g.i * kPart;
+  size_t lo, hi;
+  chunk_of(L, lo, hi);
+  double acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
+    // all NB loads first, so that they are in flight together
+    double v[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e];
+    const double we = w[e] * sig;
+    if (mode != 0) {
+      Vj[e] = Vj[e] * sig;
+      w[e] = we;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
+  }
+  // V_j entered the sums unscaled
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i == j) acc[i] *= sig;
+  const double r = block_sums<NB>(acc, nv, red);
+  if ((int)threadIdx.x < nv) partial[part_at(threadIdx.x, blockIdx.x)] = r;
+  if (mode == 1 && blockIdx.x == 0) givens_column(B, g.i, j - 1, nrm);
+}
+
+// h = sum of the previous partials; w -= V h; then either the partial dots of the new
+// w with V (next = 0, result back into w) or its partial squared norm (next = 1,
+// result into `out`, the unscaled V_{j+1}).  Block 0 adds h into the Hessenberg
+// column j.
+template <int NB>
+__global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __restrict__ V, int nv,
+                                                  double* w, const double* __restrict__ pin, int first,
+                                                  int next, double* __restrict__ pout, int j, double* out) {
+  __shared__ double red[(kT / 64) * kGmMaxVec];
+  __shared__ double hs[kGmMaxVec];
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  const size_t L = g.L;
+  V += g.off;
+  w += g.off;
+  out += g.off;
+  pin += g.i * kPart;
+  pout += g.i * kPart;
+  gather_partials(pin, nv, hs);
+  if (blockIdx.x == 0 && (int)threadIdx.x < nv) {
+    double* Hc = B.hs[g.i].H + threadIdx.x * B.m + j;
+    *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
+  }
+  double h[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) h[i] = i < nv ? hs[i] : 0.0;
+  size_t lo, hi;
+  chunk_of(L, lo, hi);
+  double acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
+    double v[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
+    double we = w[e];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
+    out[e] = we;
+    if (next == 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
+    } else {
+      acc[0] = fma(we, we, acc[0]);
+    }
+  }
+  const int nout = next == 0 ? nv : 1;
+  const double r = block_sums<NB>(acc, nout, red);
+  if ((int)threadIdx.x < nout) pout[part_at(threadIdx.x, blockIdx.x)] = r;
+}
+
+// End of a chunk of Arnoldi steps whose last step is j: Givens rotations on column j
+// with |V_{j+1}| from the squared-norm partials (V_{j+1} is scaled by the next step).
+__global__ __launch_bounds__(kT) void k_gm_column(GmBatch B, const double* __restrict__ pnorm, int j) {
+  __shared__ double hs[1];
+  const Seg g = seg_of(B);
+  if (B.st[g.i].done) return;
+  gather_partials(pnorm + g.i * kPart, 1, hs);
+  givens_column(B, g.i, j, sqrt(hs[0]));
 }
 
 // Fresh solve: header of every instance of the launch (one block per instance).
@@ -385,31 +410,34 @@ void launch_gm_start(const GmBatch& B, double* V, const double* r, const double*
   if (B.count > 0) k_gm_start<<<grid_of(B), kT, 0, s>>>(B, V, r, partial, first_cycle);
 }
 template <int NB>
-void arnoldi_nb(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, hipStream_t s) {
+void arnoldi_nb(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
+                int mode, hipStream_t s) {
   const int nv = j + 1;
   const dim3 gr = grid_of(B);
-  k_gm_dots<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1);
-  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1, 1, 0, p2, j);
-  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p2, 0, 1, p1, j);
-  k_gm_normalize<<<gr, kT, 0, s>>>(B, V, w, p1, j);
+  k_gm_dots<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p3, p1, mode);
+  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1, 1, 0, p2, j, w);
+  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p2, 0, 1, p3, j, V + (size_t)(j + 1) * B.ldv);
 }
-void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2,
-                       hipStream_t s) {
+void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
+                       int mode, hipStream_t s) {
   if (B.count <= 0) return;
   const int nv = j + 1;
   switch ((nv + 3) / 4) {
-    case 1: arnoldi_nb<4>(B, V, j, w, p1, p2, s); break;
-    case 2: arnoldi_nb<8>(B, V, j, w, p1, p2, s); break;
-    case 3: arnoldi_nb<12>(B, V, j, w, p1, p2, s); break;
-    case 4: arnoldi_nb<16>(B, V, j, w, p1, p2, s); break;
-    case 5: arnoldi_nb<20>(B, V, j, w, p1, p2, s); break;
-    case 6: arnoldi_nb<24>(B, V, j, w, p1, p2, s); break;
-    case 7: arnoldi_nb<28>(B, V, j, w, p1, p2, s); break;
-    case 8: arnoldi_nb<32>(B, V, j, w, p1, p2, s); break;
+    case 1: arnoldi_nb<4>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 2: arnoldi_nb<8>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 3: arnoldi_nb<12>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 4: arnoldi_nb<16>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 5: arnoldi_nb<20>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 6: arnoldi_nb<24>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 7: arnoldi_nb<28>(B, V, j, w, p1, p2, p3, mode, s); break;
+    case 8: arnoldi_nb<32>(B, V, j, w, p1, p2, p3, mode, s); break;
     default:
-      if (nv <= 48) arnoldi_nb<48>(B, V, j, w, p1, p2, s);
-      else arnoldi_nb<64>(B, V, j, w, p1, p2, s);
+      if (nv <= 48) arnoldi_nb<48>(B, V, j, w, p1, p2, p3, mode, s);
+      else arnoldi_nb<64>(B, V, j, w, p1, p2, p3, mode, s);
   }
+}
+void launch_gm_column(const GmBatch& B, const double* p3, int j, hipStream_t s) {
+  if (B.count > 0) k_gm_column<<<dim3(1, B.count), kT, 0, s>>>(B, p3, j);
 }
 void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s) {
   if (B.count > 0) k_gm_update_x<<<grid_of(B), kT, 0, s>>>(B, V, x);

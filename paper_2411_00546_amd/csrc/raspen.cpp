@@ -193,7 +193,7 @@ struct Work {
   double *F = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr, *r = nullptr;   // [2 ntot]
   double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
   void* fac = nullptr;
-  double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr;
+  double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
 };
 
 void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x) {
@@ -236,6 +236,7 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->V = cv.take<double>((size_t)(o.gmres_restart + 1) * L);
   w->p1 = cv.take<double>(part);
   w->p2 = cv.take<double>(part);
+  w->p3 = cv.take<double>(part);
 }
 
 Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns) {
@@ -366,8 +367,10 @@ hipEvent_t event_get(rsp_context* ctx) {
     ctx->ev_pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (cache writeback) at each record, which would
+  // slow the work between the events
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -778,7 +781,9 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
                           for (int q = j0; q < j0 + chunk; ++q) {
                             jac_apply(ctx, I, sw, w.V + (size_t)q * ldv, w.w, s, q);
                             Timed tm(ctx, KID_GMRES_ORTHO, s, ortho_flops(L, q), ortho_bytes(L, q), q);
-                            rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, s);
+                            const int mode = q == 0 ? 0 : q == j0 ? 2 : 1;
+                            rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, w.p3, mode, s);
+                            if (q == j0 + chunk - 1) rsp::launch_gm_column(B, w.p3, q, s);
                           }
                         }));
       j += chunk;

@@ -69,8 +69,13 @@ void launch_gm_axpy(const GmBatch& B, double a, const double* x, double* y, int 
 void launch_gm_zero(const GmBatch& B, double* x, hipStream_t s);
 void launch_gm_start(const GmBatch& B, double* V, const double* r, const double* partial, int first_cycle,
                      hipStream_t s);
-void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2,
-                       hipStream_t s);
+// Arnoldi step j on w = A V_j: orthogonalisation against V_0..V_j into V_{j+1}
+// (unscaled; partial squared norms in p3).  mode 0: j = 0; 1: scale V_j and w and
+// finish column j - 1; 2: scale only (column j - 1 finished by launch_gm_column).
+void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
+                       int mode, hipStream_t s);
+// Givens rotations and stopping test of column j (the last step of a chunk).
+void launch_gm_column(const GmBatch& B, const double* p3, int j, hipStream_t s);
 void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s);
 
 }  // namespace rsp
