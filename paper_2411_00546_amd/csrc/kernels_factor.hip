@@ -151,6 +151,76 @@ __device__ __forceinline__ double recip(double x) {
   return r;
 }
 
+// Lane exchanges inside one wave, as VALU operations (no LDS).  Rows are the four
+// groups of 16 lanes.
+//   row_bcast<n>(v): lane n of each row, to every lane of that row (DPP row_newbcast);
+//   col_bcast<R>(v): lane (i, row R), to lane (i, any row) (two permlane swaps: the
+//     16-lane swap pairs rows 0-1 and 2-3, the 32-lane swap pairs the halves);
+//   read_lane(v, l): lane l, to every lane.
+template <int N>
+__device__ __forceinline__ int row_bcast_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, false);
+}
+template <int R>
+__device__ __forceinline__ int col_bcast_i(int v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);   // rows (0,0,2,2), (1,1,3,3)
+  const int c = (int)((R & 1) ? p[1] : p[0]);
+  const auto q = __builtin_amdgcn_permlane32_swap(c, c, false, false);   // (c0,c1,c0,c1), (c2,c3,c2,c3)
+  return (int)((R & 2) ? q[1] : q[0]);
+}
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(row_bcast_i<N>(__float_as_int(v)));
+}
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __hiloint2double(row_bcast_i<N>(__double2hiint(v)), row_bcast_i<N>(__double2loint(v)));
+}
+template <int R>
+__device__ __forceinline__ float col_bcast(float v) {
+  return __int_as_float(col_bcast_i<R>(__float_as_int(v)));
+}
+template <int R>
+__device__ __forceinline__ double col_bcast(double v) {
+  return __hiloint2double(col_bcast_i<R>(__double2hiint(v)), col_bcast_i<R>(__double2loint(v)));
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// In-place inverse of the 16 x 16 block X (LDS, row stride ld) by Gauss-Jordan with
+// pivots in order, by one wave in registers: lane (i, r) = i + 16 r holds row i,
+// columns 4 r .. 4 r + 3.  Step k takes the pivot row from lane (k, r) (row_bcast),
+// the pivot-column entry of row i from lane (i, k / 4) (col_bcast) and the pivot from
+// lane (k, k / 4).
+template <typename T, int K>
+__device__ __forceinline__ void gj16_step(T (&own)[4], int li, int q4) {
+  constexpr int KQ = K >> 2, KR = K & 3;
+  T prow[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) prow[q] = row_bcast<K>(own[q]);
+  const T pcol = col_bcast<KQ>(own[KR]);
+  const T inv = recip(read_lane(own[KR], K + 16 * KQ));
+  const bool on_row = li == K;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const bool on_col = 4 * q4 + q == K;
+    const T tr = prow[q] * inv;
+    own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
+  }
+}
+template <typename T, int K>
+__device__ __forceinline__ void gj16_steps(T (&own)[4], int li, int q4) {
+  if constexpr (K < 16) {
+    gj16_step<T, K>(own, li, q4);
+    gj16_steps<T, K + 1>(own, li, q4);
+  }
+}
+
 // A operand (row-major 16 x 16 tile X, stride ldx) of instruction q.
 template <typename T>
 __device__ __forceinline__ void a_operand(const T* X, int ldx, int lane, T (&a)[4]) {
@@ -225,26 +295,11 @@ __device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
     if (J == K) {
       const int li = lane & 15, q4 = lane >> 4;
       if (!PANEL) {
-        // lane (li, q4) owns row li, columns 4 q4 .. 4 q4 + 3 of the pivot block and
-        // keeps them in registers; each step reads the pivot row and column written by
-        // the step before (one wave's LDS accesses complete in order)
+        // lane (li, q4) owns row li, columns 4 q4 .. 4 q4 + 3 of the pivot block
         T own[4];
         load4<T>(AKK + li * LD + 4 * q4, own);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          T prow[4];
-          load4<T>(AKK + k * LD + 4 * q4, prow);
-          const T pcol = AKK[li * LD + k];
-          const T inv = recip(AKK[k * LD + k]);
-          const bool on_row = li == k;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool on_col = 4 * q4 + q == k;
-            const T tr = prow[q] * inv;
-            own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
-          }
-          store4<T>(AKK + li * LD + 4 * q4, own);
-        }
+        gj16_steps<T, 0>(own, li, q4);
+        store4<T>(AKK + li * LD + 4 * q4, own);
       } else {
         // lane (li, q4) owns rows li + 16 r (r < NB), columns 4 q4 .. 4 q4 + 3 of the panel
         T own[NB][4];
@@ -406,29 +461,37 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   // active column is not dominant.  Column b = 16 wave + (lane & 15), rows (lane >> 4) + 4 r.
   auto build = [&](int mode) -> bool {
     const int b = 16 * wave + (lane & 15), rg = lane >> 4;
-    const int fc = b >= tx, bc = b - fc * tx;
     T off = 0, dia = 0;
+    if (b < m) {
+      // column b of D_j has entries in four rows only: the diagonal, the x-neighbours in
+      // the same field and the same node in the other field (the y-p coupling)
+      const int fc = b >= tx, bc = b - fc * tx;
+      const int r_l = bc > 0 ? b - 1 : -1, r_r = bc + 1 < tx ? b + 1 : -1;
+      const int r_c = fc ? bc : tx + bc;
+      const T d_d = (T)(P.diag0 + la[bc]), d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
 #pragma unroll 4
-    for (int r = 0; r < M / 4; ++r) {
-      const int a = rg + 4 * r;
-      T v;
-      if (a < m && b < m) {
-        const int fr = a >= tx, ar = a - fr * tx;
-        double d = 0.0;
-        if (fr == fc) {
-          if (ar == bc) d = P.diag0 + la[ar];
-          else if (ar == bc + 1 || bc == ar + 1) d = -P.hx2i;
-        } else if (ar == bc) {
-          d = fr == 0 ? lb[ar] : lc[ar];
+      for (int r = 0; r < M / 4; ++r) {
+        const int a = rg + 4 * r;
+        T v = 0;
+        if (a < m) {
+          T d = 0;
+          d = a == b ? d_d : d;
+          d = (a == r_l || a == r_r) ? d_x : d;
+          d = a == r_c ? d_c : d;
+          const T prev = Mx[a * LD + b];
+          v = (mode == 0 ? (T)0 : (mode == 1 ? nh4 * prev : prev)) + d;
         }
-        const T prev = Mx[a * LD + b];
-        v = (mode == 0 ? (T)0 : (mode == 1 ? nh4 * prev : prev)) + (T)d;
-      } else {
-        v = (T)(a == b ? 1 : 0);
+        Mx[a * LD + b] = v;
+        if (a == b) dia = fabs(v);
+        else off += fabs(v);
       }
-      Mx[a * LD + b] = v;
-      if (a == b) dia = fabs(v);
-      else off += fabs(v);
+    } else {
+      // padding: identity
+#pragma unroll 4
+      for (int r = 0; r < M / 4; ++r) {
+        const int a = rg + 4 * r;
+        Mx[a * LD + b] = (T)(a == b ? 1 : 0);
+      }
     }
     off += __shfl_xor(off, 16, 64);
     off += __shfl_xor(off, 32, 64);
