@@ -398,6 +398,76 @@ __device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
   return false;
 }
 
+// The same inverse as block_gauss_jordan<T, M, false> (the same operations on the same
+// values, so bitwise equal), with every wave's column block J kept in registers for the
+// whole elimination (accumulator layout; a tile in that layout is exactly the B
+// operand of a product).  Step K: wave K publishes its old column and the inverse of
+// A_KK (inverted in place by the same register Gauss-Jordan) into a staging panel, the
+// other waves take the inverse and their A_IK from there as A operands and update
+// their tiles in registers, and wave K forms its new column.  The staging panels
+// alternate between steps, so a step needs one barrier.  St: 2 panels of M x
+// padded(16).
+template <typename T, int M>
+__device__ void block_gauss_jordan_regs(T* A, int LD, T* St) {
+  constexpr int NB = M / 16;
+  constexpr int PLD = padded<T>(16);
+  using V = typename Mfma<T>::V;
+  const int t = threadIdx.x, lane = t & 63, J = t >> 6;
+  const int li = lane & 15, q4 = lane >> 4;
+  V c[NB];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) c[I] = tile_load<T>(A + 16 * I * LD + 16 * J, LD, lane);
+#pragma unroll
+  for (int K = 0; K < NB; ++K) {
+    T* S = St + (K & 1) * M * PLD;
+    if (J == K) {
+#pragma unroll
+      for (int I = 0; I < NB; ++I) tile_store<T>(S + 16 * I * PLD, PLD, c[I], lane);
+      T own[4];
+      load4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
+      gj16_steps<T, 0>(own, li, q4);
+      store4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
+    }
+    __syncthreads();
+    if (J != K) {
+      // row-panel tile R = A_KK^{-1} A_KJ, then A_IJ -= A_IK R, A_KJ = R
+      T a[4], b[4];
+      a_operand<T>(S + 16 * K * PLD, PLD, lane, a);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = c[K][q];
+      V r = {0, 0, 0, 0};
+      r = mma16<T>(a, b, (T)1, r);
+      T rb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rb[q] = r[q];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        if (I == K) continue;
+        T ai[4];
+        a_operand<T>(S + 16 * I * PLD, PLD, lane, ai);
+        c[I] = mma16<T>(ai, rb, (T)-1, c[I]);
+      }
+      c[K] = r;
+    } else {
+      // new column K: A_IK <- -A_IK A_KK^{-1} (I != K), A_KK <- its inverse
+      T b[4];
+      b_operand<T>(S + 16 * K * PLD, PLD, lane, b);
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        if (I == K) continue;
+        T ai[4];
+        a_operand<T>(S + 16 * I * PLD, PLD, lane, ai);
+        V z = {0, 0, 0, 0};
+        c[I] = mma16<T>(ai, b, (T)-1, z);
+      }
+      c[K] = tile_load<T>(S + 16 * K * PLD, PLD, lane);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < NB; ++I) tile_store<T>(A + 16 * I * LD + 16 * J, LD, c[I], lane);
+  __syncthreads();
+}
+
 // The usual path, two-ended (twisted) block LU over the lines of the tile, t = ty / 2:
 // workgroup blockIdx.y = 0 factors lines 0 .. t-1 from the top (S_j = D_j - hy^-4
 // S_{j-1}^{-1}), workgroup 1 lines ty-1 .. t+1 from the bottom (T_j = D_j - hy^-4
@@ -424,7 +494,9 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   __shared__ double vin[M], gprev[M];
   __shared__ double part[4 * M];
   __shared__ int flag;
-  __shared__ __attribute__((aligned(16))) T Pn[M * padded<T>(16)];   // column panel of the twist line
+  // staging panels of the blocked Gauss-Jordan; the first is the column panel of the twist line
+  __shared__ __attribute__((aligned(16))) T St[2 * M * padded<T>(16)];
+  T* const Pn = St;
 
   int s;
   DevProblem P;
@@ -555,7 +627,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       bad = true;
       break;
     }
-    block_gauss_jordan<T, M, false>(Mx, LD, nullptr, nullptr);
+    block_gauss_jordan_regs<T, M>(Mx, LD, St);
     if (rhs) {
       for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
       solve_line(j);
@@ -564,9 +636,10 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   }
   if (bad && t == 0) atomicExch(fallback + s, 1);
   if (!second_to_arrive(counter, s, &flag)) return;
-  if (t == 0) flag = atomicAdd(fallback + s, 0);
+  __shared__ int other_bad;
+  if (t == 0) other_bad = atomicAdd(fallback + s, 0);
   __syncthreads();
-  if (flag) return;
+  if (other_bad) return;
 
   // the twist line: Mx = -hy^-4 (F_{t-1} + F_{t+1}) from the stored inverses, then + D_t
   if (t < tx) {
@@ -574,12 +647,31 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
     state_at(tw, y, p);
     coefficients(y, p);
   }
-  const T* Fm = tw > 0 ? Fs + (size_t)(tw - 1) * M * M : nullptr;
-  const T* Fp = tw + 1 < ty ? Fs + (size_t)(tw + 1) * M * M : nullptr;
-  for (int e = t; e < M * M; e += NT) {
-    const int b = e / M, a = e - b * M;   // stored transposed: F[b][a] = inverse[a][b]
-    const double v = (Fm ? (double)Fm[e] : 0.0) + (Fp ? (double)Fp[e] : 0.0);
-    Mx[a * LD + b] = (T)(-hy4i * v);
+  // This workgroup's last inverse (the line next to the twist on its side) is still
+  // in Mx; the other side's comes from global memory (stored transposed, F[b][a] =
+  // inverse[a][b]), 16-byte loads along a.
+  {
+    const bool mine = nlines > 0;
+    const int jo = half == 0 ? tw + 1 : tw - 1;   // the other side's line
+    const T* Fo = jo >= 0 && jo < ty ? Fs + (size_t)jo * M * M : nullptr;
+    constexpr int PER = M * M / 4 / NT;           // 16-byte groups per thread (M = 16 k)
+    T v[PER][4];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = 4 * (t + i * NT);
+      if (Fo) load4<T>(Fo + e, v[i]);
+      else v[i][0] = v[i][1] = v[i][2] = v[i][3] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = 4 * (t + i * NT), b = e / M, a0 = e - b * M;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T* x = Mx + (a0 + q) * LD + b;
+        const double own = mine ? (double)*x : 0.0;
+        *x = (T)(-hy4i * (own + (double)v[i][q]));
+      }
+    }
   }
   __syncthreads();
   // Z_t is close to the boundary of column dominance (both neighbours' Schur terms are

@@ -111,6 +111,7 @@ __device__ __forceinline__ bool second_to_arrive(int* __restrict__ counter, int 
   }
   __syncthreads();
   const bool last = *flag_lds == 1;
+  __syncthreads();   // every thread has read the flag before anyone reuses it
   if (last) __threadfence();
   return last;
 }

@@ -325,6 +325,35 @@ def test_solve_is_deterministic(R):
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
 
 
+def test_plain_workload_repeatable_in_one_context(R):
+    """The 255x255 workload (64 subdomains, two workgroups each in the factor and the
+    Jacobian action) solved repeatedly in one context, FP64 and mixed, interleaved:
+    every repeat is bit-identical.  The hand-off between a subdomain's two factor
+    workgroups is the part that depends on which one finishes first."""
+    import torch
+    prob = synth.config_plain()
+    yd, f = prob.inputs()
+    ydt, ft = dev(yd), dev(f)
+    ctx = R.rsp_context_create(0)
+    try:
+        first = {}
+        for rep in range(3):
+            for name, o in (("fp64", synth.Options()), ("mixed", synth.Options(precision=1, max_refine=0)),
+                            ("mixed_ref", synth.Options(precision=1, max_refine=1))):
+                y, p, u = (dev(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+                st, h = R.rsp_solve(ctx, R.make_problem(prob), R.make_options(o), ydt, ft, None, None, y, p, u)
+                torch.cuda.synchronize()
+                x = np.concatenate([host(y).reshape(-1), host(p).reshape(-1)])
+                assert st == 0, (rep, name, st)
+                if name in first:
+                    assert np.array_equal(x, first[name][0]), (rep, name)
+                    assert h["backtracks"] == first[name][1], (rep, name)
+                else:
+                    first[name] = (x, h["backtracks"])
+    finally:
+        R.rsp_context_destroy(ctx)
+
+
 def test_warm_start_at_solution(R):
     prob = make_problem("small63")
     yd, f = prob.inputs()
