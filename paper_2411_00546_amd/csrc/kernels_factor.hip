@@ -262,88 +262,68 @@ __device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c,
 // by Gauss-Jordan with 16 x 16 pivot blocks taken in order (no pivot search): for
 // pivot block K,
 //   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
-//   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K).
-// This is the partial-pivoting Gauss-Jordan result whenever partial pivoting would
-// keep the diagonal: for column diagonally dominant A always (the Schur complements
-// inherit the property).  M / 16 waves; wave J owns column block J.
-//
-// PANEL = false: wave K inverts A_KK in place (one wave, LDS), then every other wave
-// forms its row-panel tile A_KK^{-1} A_KJ in registers and updates its column, while
-// wave K forms its new column and writes it once the others have read the old one.
-//
-// PANEL = true: wave K eliminates the whole column panel A[:, K] (a copy in Pn), which
-// gives A_KK^{-1} and the new column K at once and every multiplier a_ik / a_kk of the
+//   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K),
+// checking the partial-pivoting condition on the way (for the twist line, whose block
+// need not be column diagonally dominant).  M / 16 waves; wave J owns column block J.
+// Wave K eliminates the whole column panel A[:, K] (a copy in Pn), which gives
+// A_KK^{-1} and the new column K at once and every multiplier a_ik / a_kk of the
 // elimination in natural order; if one exceeds 1 in magnitude for an unpivoted row,
 // partial pivoting would have swapped rows, and the function returns true (A is then
-// left partly eliminated).  Returns false otherwise.
-template <typename T, int M, bool PANEL>
-__device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
+// left partly eliminated).  The other waves form their row-panel tile A_KK^{-1} A_KJ
+// and update their column.  Returns false otherwise.
+template <typename T, int M>
+__device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
   const int t = threadIdx.x, lane = t & 63, J = t >> 6;
-  if (PANEL && t == 0) *flag = 0;
+  const int li = lane & 15, q4 = lane >> 4;
+  if (t == 0) *flag = 0;
 #pragma unroll 1
   for (int K = 0; K < NB; ++K) {
-    T* AKK = A + 16 * K * LD + 16 * K;
-    const T* Pinv = AKK;          // where the other waves find A_KK^{-1}
-    int ldp = LD;
-    if (PANEL) {
-      Pinv = Pn + 16 * K * PLD;
-      ldp = PLD;
-    }
+    const T* Pinv = Pn + 16 * K * PLD;   // where the other waves find A_KK^{-1}
     if (J == K) {
-      const int li = lane & 15, q4 = lane >> 4;
-      if (!PANEL) {
-        // lane (li, q4) owns row li, columns 4 q4 .. 4 q4 + 3 of the pivot block
-        T own[4];
-        load4<T>(AKK + li * LD + 4 * q4, own);
-        gj16_steps<T, 0>(own, li, q4);
-        store4<T>(AKK + li * LD + 4 * q4, own);
-      } else {
-        // lane (li, q4) owns rows li + 16 r (r < NB), columns 4 q4 .. 4 q4 + 3 of the panel
-        T own[NB][4];
+      // lane (li, q4) owns rows li + 16 r (r < NB), columns 4 q4 .. 4 q4 + 3 of the panel
+      T own[NB][4];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        load4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, own[r]);
+        store4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, own[r]);
+      }
+      bool swap = false;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int kk = 16 * K + k;               // pivot row
+        T prow[4];
+        load4<T>(Pn + kk * PLD + 4 * q4, prow);
+        T pcol[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) pcol[r] = Pn[(li + 16 * r) * PLD + k];
+        const T piv = Pn[kk * PLD + k];
+        const T inv = recip(piv);
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-          load4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, own[r]);
-          store4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, own[r]);
-        }
-        bool swap = false;
+          const int i = li + 16 * r;
+          swap |= i > kk && fabs(pcol[r]) > fabs(piv);
+          const bool on_row = i == kk;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const int kk = 16 * K + k;               // pivot row
-          T prow[4];
-          load4<T>(Pn + kk * PLD + 4 * q4, prow);
-          T pcol[NB];
-#pragma unroll
-          for (int r = 0; r < NB; ++r) pcol[r] = Pn[(li + 16 * r) * PLD + k];
-          const T piv = Pn[kk * PLD + k];
-          const T inv = recip(piv);
-#pragma unroll
-          for (int r = 0; r < NB; ++r) {
-            const int i = li + 16 * r;
-            swap |= i > kk && fabs(pcol[r]) > fabs(piv);
-            const bool on_row = i == kk;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const bool on_col = 4 * q4 + q == k;
-              const T tr = prow[q] * inv;
-              own[r][q] = on_col ? (on_row ? inv : -pcol[r] * inv)
-                                 : (on_row ? tr : fma(-pcol[r], tr, own[r][q]));
-            }
-            store4<T>(Pn + i * PLD + 4 * q4, own[r]);
+          for (int q = 0; q < 4; ++q) {
+            const bool on_col = 4 * q4 + q == k;
+            const T tr = prow[q] * inv;
+            own[r][q] = on_col ? (on_row ? inv : -pcol[r] * inv)
+                               : (on_row ? tr : fma(-pcol[r], tr, own[r][q]));
           }
+          store4<T>(Pn + i * PLD + 4 * q4, own[r]);
         }
-        if (__any(swap) && lane == 0) *flag = 1;
       }
+      if (__any(swap) && lane == 0) *flag = 1;
     }
     __syncthreads();
-    if (PANEL && *flag) return true;
-    V acc[NB];
+    if (*flag) return true;
     if (J != K) {
       // row-panel tile R = A_KK^{-1} A_KJ, then column J: A_IJ -= A_IK R, A_KJ = R
       T a[4], b[4];
-      a_operand<T>(Pinv, ldp, lane, a);
+      a_operand<T>(Pinv, PLD, lane, a);
       b_operand<T>(A + 16 * K * LD + 16 * J, LD, lane, b);
       V r = {0, 0, 0, 0};
       r = mma16<T>(a, b, (T)1, r);
@@ -363,34 +343,15 @@ __device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
           tile_store<T>(AIJ, LD, c, lane);
         }
       }
-    } else if (!PANEL) {
-      // new column K: A_IK <- -A_IK A_KK^{-1} (I != K); A_KK already holds the inverse
-      T b[4];
-      b_operand<T>(AKK, LD, lane, b);
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        if (I == K) continue;
-        T ai[4];
-        a_operand<T>(A + 16 * I * LD + 16 * K, LD, lane, ai);
-        V c = {0, 0, 0, 0};
-        acc[I] = mma16<T>(ai, b, (T)-1, c);
-      }
     }
     __syncthreads();
     if (J == K) {
-      if (!PANEL) {
+      // the eliminated panel is the new column K (A_KK^{-1} in rows K)
 #pragma unroll
-        for (int I = 0; I < NB; ++I)
-          if (I != K) tile_store<T>(A + 16 * I * LD + 16 * K, LD, acc[I], lane);
-      } else {
-        // the eliminated panel is the new column K (A_KK^{-1} in rows K)
-        const int li = lane & 15, q4 = lane >> 4;
-#pragma unroll
-        for (int r = 0; r < NB; ++r) {
-          T v[4];
-          load4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, v);
-          store4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, v);
-        }
+      for (int r = 0; r < NB; ++r) {
+        T v[4];
+        load4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, v);
+        store4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, v);
       }
     }
   }
@@ -398,17 +359,23 @@ __device__ bool block_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
   return false;
 }
 
-// The same inverse as block_gauss_jordan<T, M, false> (the same operations on the same
-// values, so bitwise equal), with every wave's column block J kept in registers for the
-// whole elimination (accumulator layout; a tile in that layout is exactly the B
-// operand of a product).  Step K: wave K publishes its old column and the inverse of
-// A_KK (inverted in place by the same register Gauss-Jordan) into a staging panel, the
-// other waves take the inverse and their A_IK from there as A operands and update
-// their tiles in registers, and wave K forms its new column.  The staging panels
-// alternate between steps, so a step needs one barrier.  St: 2 panels of M x
-// padded(16).
+// In-place inverse of the M x M matrix A (LDS, row stride LD, rows 16-byte aligned)
+// by Gauss-Jordan with 16 x 16 pivot blocks taken in order (no pivot search): for
+// pivot block K,
+//   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
+//   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K).
+// This is the partial-pivoting Gauss-Jordan result whenever partial pivoting would
+// keep the diagonal: for column diagonally dominant A always (the Schur complements
+// inherit the property).  M / 16 waves; wave J owns column block J and keeps it in
+// registers for the whole elimination (accumulator layout; a tile in that layout is
+// exactly the B operand of a product).  Step K: wave K publishes its old column and
+// the inverse of A_KK (inverted by one wave in registers, gj16_steps) into a staging
+// panel, the other waves take the inverse and their A_IK from there as A operands and
+// update their tiles in registers, and wave K forms its new column.  The staging
+// panels alternate between steps, so a step needs one barrier.  St: 2 panels of
+// M x padded(16).
 template <typename T, int M>
-__device__ void block_gauss_jordan_regs(T* A, int LD, T* St) {
+__device__ void block_gauss_jordan(T* A, int LD, T* St) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
@@ -627,7 +594,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       bad = true;
       break;
     }
-    block_gauss_jordan_regs<T, M>(Mx, LD, St);
+    block_gauss_jordan<T, M>(Mx, LD, St);
     if (rhs) {
       for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
       solve_line(j);
@@ -677,7 +644,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   // Z_t is close to the boundary of column dominance (both neighbours' Schur terms are
   // subtracted), so its elimination checks the partial-pivoting choice exactly instead
   (void)build(2);
-  if (block_gauss_jordan<T, M, true>(Mx, LD, Pn, &flag)) {
+  if (panel_gauss_jordan<T, M>(Mx, LD, Pn, &flag)) {
     if (t == 0) atomicExch(fallback + s, 1);
     return;
   }

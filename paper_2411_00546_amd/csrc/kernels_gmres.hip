@@ -52,7 +52,35 @@ __device__ __forceinline__ void chunk_of(size_t L, size_t& lo, size_t& hi) {
   if (lo > L) lo = L;
 }
 
-// Block sums of acc[i] for i < nv (wave shuffles, then the 4 wave results in order);
+// Sum over the 64 lanes of a wave, the same value in every lane, by VALU lane
+// exchanges only: four DPP steps inside each 16-lane row (quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror), then the 16-lane swap adds rows
+// 0+1 and 2+3 and the 32-lane swap adds the two halves.  Fixed order: deterministic.
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_swap<0xB1>(v);
+  v += dpp_swap<0x4E>(v);
+  v += dpp_swap<0x141>(v);
+  v += dpp_swap<0x140>(v);
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+  return v;
+}
+
+// Block sums of acc[i] for i < nv (wave sums, then the 4 wave results in order);
 // thread i < nv of the block returns sum i.  Fixed order: deterministic.
 template <int NB>
 __device__ __forceinline__ double block_sums(const double (&acc)[NB], int nv, double* red) {
@@ -60,9 +88,7 @@ __device__ __forceinline__ double block_sums(const double (&acc)[NB], int nv, do
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if (i < nv) {
-      double v = acc[i];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      const double v = wave_sum(acc[i]);
       if (lane == 0) red[wave * kGmMaxVec + i] = v;
     }
   }
@@ -156,12 +182,6 @@ __global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, double* __restrict__ 
   const Seg g = seg_of(B);
   if (B.st[g.i].done) return;
   const int j = nv - 1;
-  double nrm = 1.0, sig = 1.0;
-  if (mode != 0) {
-    gather_partials(pnorm + g.i * kPart, 1, hs);
-    nrm = sqrt(hs[0]);
-    sig = 1.0 / nrm;
-  }
   const size_t L = g.L;
   V += g.off;
   w += g.off;
@@ -169,15 +189,31 @@ __global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, double* __restrict__ 
   partial += g.i * kPart;
   size_t lo, hi;
   chunk_of(L, lo, hi);
+  // all NB loads of an element are issued together; the first element's go out
+  // before the norm partials are gathered
+  double v[NB], wf = 0.0;
+  const size_t e0 = lo + threadIdx.x;
+  if (e0 < hi) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e0];
+    wf = w[e0];
+  }
+  double nrm = 1.0, sig = 1.0;
+  if (mode != 0) {
+    gather_partials(pnorm + g.i * kPart, 1, hs);
+    nrm = sqrt(hs[0]);
+    sig = 1.0 / nrm;
+  }
   double acc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
-    // all NB loads first, so that they are in flight together
-    double v[NB];
+  for (size_t e = e0; e < hi; e += kT) {
+    if (e != e0) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e];
-    const double we = w[e] * sig;
+      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e];
+      wf = w[e];
+    }
+    const double we = wf * sig;
     if (mode != 0) {
       Vj[e] = Vj[e] * sig;
       w[e] = we;
@@ -212,6 +248,16 @@ __global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __res
   out += g.off;
   pin += g.i * kPart;
   pout += g.i * kPart;
+  size_t lo, hi;
+  chunk_of(L, lo, hi);
+  // the first element's loads go out before the partial sums are gathered
+  double v[NB], wf = 0.0;
+  const size_t e0 = lo + threadIdx.x;
+  if (e0 < hi) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e0];
+    wf = w[e0];
+  }
   gather_partials(pin, nv, hs);
   if (blockIdx.x == 0 && (int)threadIdx.x < nv) {
     double* Hc = B.hs[g.i].H + threadIdx.x * B.m + j;
@@ -220,16 +266,16 @@ __global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __res
   double h[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) h[i] = i < nv ? hs[i] : 0.0;
-  size_t lo, hi;
-  chunk_of(L, lo, hi);
   double acc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
-    double v[NB];
+  for (size_t e = e0; e < hi; e += kT) {
+    if (e != e0) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
-    double we = w[e];
+      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
+      wf = w[e];
+    }
+    double we = wf;
 #pragma unroll
     for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
     out[e] = we;
