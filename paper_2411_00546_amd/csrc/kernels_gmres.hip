@@ -99,14 +99,30 @@ __device__ __forceinline__ double block_sums(const double (&acc)[NB], int nv, do
   return r;
 }
 
-// h[i] = sum_blk partial[blk][i] for i < nv -> LDS hs (every block, same fixed order):
-// thread (i, q) adds blocks q, q + Q, ... with independent loads, then thread i adds
-// the Q segment sums in order.
-__device__ __forceinline__ void gather_partials(const double* __restrict__ partial, int nv,
-                                                double* hs) {
-  __shared__ double seg[kT];
-  const int Q = nv > 0 ? (kT / nv < kGmBlocks ? kT / nv : kGmBlocks) : 1;
+// h[i] = sum over blocks of partial[i][b] for i < nv -> LDS hs (every block, the same
+// fixed order for a given nv).
+//   nv <= 4 (norms, short bases): output i is summed by wave i, whose lane l adds
+//     blocks l, l + 64, l + 128, l + 192 in that order before the wave sum;
+//   nv > 4: thread (i, q) adds blocks q, q + Q, ... with independent loads, then
+//     thread i adds the Q segment sums in order.
+__device__ __forceinline__ void gather_partials(const double* __restrict__ partial, int nv, double* hs) {
+  constexpr int R = kGmBlocks / 64;   // partials per lane and output
+  static_assert(kGmBlocks % 64 == 0 && kT == 256, "four waves, whole waves of partials");
   const int t = threadIdx.x;
+  if (nv <= kT / 64) {
+    const int lane = t & 63, wave = t >> 6;
+    if (wave < nv) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc += partial[part_at(wave, lane + 64 * r)];
+      acc = wave_sum(acc);
+      if (lane == 0) hs[wave] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  __shared__ double seg[kT];
+  const int Q = kT / nv < kGmBlocks ? kT / nv : kGmBlocks;
   if (t < nv * Q) {
     const int i = t / Q, q = t - i * Q;
     double acc = 0.0;
