@@ -3,13 +3,24 @@
 // Gram-Schmidt applied twice, Givens rotations on the Hessenberg column, the
 // stopping test |g_{j+1}| <= rtol |b| and the triangular solve, all on the device.
 //
-// Normalisation is deferred by one step: the second Gram-Schmidt pass of step j
-// writes the orthogonalised vector unscaled into V_{j+1} together with partial sums
-// of its squared norm, the Jacobian action of step j+1 takes it unscaled (the
-// operator is linear), and the first kernel of step j+1 scales V_{j+1} and the
-// product by 1/|V_{j+1}| while it forms the dot products, and applies the Givens
-// rotations to column j.  An Arnoldi step is three launches; a chunk of steps ends
-// with one small launch that finishes its last column.
+// The second Gram-Schmidt pass of a vector is delayed by one step and shares the
+// global reduction of the next, so a step has one reduction.  At step j the basis
+// V_0 .. V_{j-1} is orthonormal and slot j holds u_j, the new vector after its first
+// pass (unscaled); the Jacobian action gives z = A u_j.  One pass over the vectors
+// forms a = V_{j-1}^T u_j, b = u_j . u_j, c = V_{j-1}^T z and d = u_j . z.  Then:
+//   second pass of u_j:  v_j = (u_j - V_{j-1} a) / nu,  nu^2 = b - |a|^2, and column
+//                        j - 1 of the Hessenberg matrix is its first pass plus a, with
+//                        subdiagonal nu (it gets its Givens rotations here);
+//   A v_j from z:        A u_j = nu A v_j + A V_{j-1} a and A V_{j-1} = V_j H (the
+//                        Arnoldi relation, unrotated columns), so with t = H a,
+//                        A v_j = (z - V_j t) / nu;
+//   first pass of A v_j: h = V_j^T A v_j = ((c - t_{<j}) / nu, (v_j . z - t_j) / nu),
+//                        v_j . z = (d - a . c) / nu, and
+//                        u_{j+1} = (z - V_j s) / nu with s = t + nu h.
+// A second pass over the vectors writes v_j and u_{j+1}.  In exact arithmetic this is
+// the classical Gram-Schmidt process applied twice.  An Arnoldi step is two launches
+// after the Jacobian action; a chunk of steps ends with one reduction and one small
+// launch that finish its last column.
 // Launch grid: (kGmBlocks, instances); blockIdx.y selects the instance, whose
 // vectors are its segment of the batch's concatenated vectors (basis vector k of
 // every instance: V + k ldv).  A per-instance stop
@@ -139,10 +150,6 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
   __syncthreads();
 }
 
-// NB: compile-time bound on the number of basis vectors (bucket >= nv).  Loads of all
-// NB vectors are issued unconditionally (index clamped to nv - 1, the extra ones hit
-// the cache) and the unused products are masked, so the loads are not serialised.
-
 // Givens rotations on Hessenberg column j, whose subdiagonal entry is nrm: residual
 // estimate and stopping test.  Called by every thread of one block; the column and
 // the rotations are staged in LDS so the sequential part runs from LDS.
@@ -183,138 +190,217 @@ __device__ void givens_column(const GmBatch& B, int inst, int j, double nrm) {
   if (!(st->rel > st->rtol) || st->used >= st->maxit || breakdown || j + 1 >= m) st->done = 1;
 }
 
-// First kernel of Arnoldi step j = nv - 1 (w = A V_j as the Jacobian action left it):
-// partial sums of V_i . w for i < nv over this block's chunk.  mode 0 (j = 0): V_j is
-// normalised already.  mode 1: V_j is unscaled; sigma = 1/|V_j| from the squared-norm
-// partials `pnorm`, V_j <- sigma V_j and w <- sigma w in place, and block 0 applies
-// the Givens rotations to column j - 1.  mode 2: as 1, but column j - 1 was finished
-// by k_gm_column at the end of the previous chunk.
+// NB: compile-time bound on the number of basis vectors read besides u (bucket >= j).
+// Loads of all NB vectors are issued unconditionally (index clamped to j - 1, the
+// extra ones hit the cache) and the unused products are masked, so the loads of an
+// element are in flight together.
+
+// Reduction of Arnoldi step j (slot j holds u: unscaled after its first pass, or the
+// normalised V_0 for j = 0): partial sums over this block's chunk of
+//   p1: a_i = V_i . u (i < j), and b = u . u in slot j;
+//   p2: c_i = V_i . z (i < j), and d = u . z in slot j (withz = 0: not formed).
 template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_dots(GmBatch B, double* __restrict__ V, int nv,
-                                                double* __restrict__ w, const double* __restrict__ pnorm,
-                                                double* __restrict__ partial, int mode) {
+__global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __restrict__ V, int j,
+                                                  const double* __restrict__ z, double* __restrict__ p1,
+                                                  double* __restrict__ p2, int withz) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
-  __shared__ double hs[1];
   const Seg g = seg_of(B);
   if (B.st[g.i].done) return;
-  const int j = nv - 1;
-  const size_t L = g.L;
   V += g.off;
-  w += g.off;
+  z += g.off;
+  const double* u = V + (size_t)j * B.ldv;
+  p1 += g.i * kPart;
+  p2 += g.i * kPart;
+  size_t lo, hi;
+  chunk_of(g.L, lo, hi);
+  double aa[NB], cc[NB], bb = 0.0, dd = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) aa[i] = cc[i] = 0.0;
+  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
+    double v[NB];
+    if (j > 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+    }
+    const double ue = u[e];
+    const double ze = withz ? z[e] : 0.0;
+    if (j > 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        aa[i] = fma(v[i], i < j ? ue : 0.0, aa[i]);
+        cc[i] = fma(v[i], i < j ? ze : 0.0, cc[i]);
+      }
+    }
+    bb = fma(ue, ue, bb);
+    dd = fma(ue, ze, dd);
+  }
+  // slot j carries b (d)
+  double A[NB + 1], C[NB + 1];
+#pragma unroll
+  for (int i = 0; i <= NB; ++i) {
+    A[i] = i < j ? (i < NB ? aa[i] : 0.0) : (i == j ? bb : 0.0);
+    C[i] = i < j ? (i < NB ? cc[i] : 0.0) : (i == j ? dd : 0.0);
+  }
+  const double r1 = block_sums<NB + 1>(A, j + 1, red);
+  if ((int)threadIdx.x <= j) p1[part_at(threadIdx.x, blockIdx.x)] = r1;
+  if (!withz) return;
+  __syncthreads();   // red is reused
+  const double r2 = block_sums<NB + 1>(C, j + 1, red);
+  if ((int)threadIdx.x <= j) p2[part_at(threadIdx.x, blockIdx.x)] = r2;
+}
+
+// Second pass of u_j against V_0 .. V_{j-1} from the partial sums a, b (p1, j + 1
+// values): nu and the finished column j - 1 (its first pass plus a, subdiagonal nu),
+// into colv[0 .. j] and *nu_out.  `mode` 2: the column is final in Hr already.  Every
+// thread of the block calls it; the result is in LDS for all.
+__device__ __forceinline__ void second_pass_column(const GmHess* hz, int m, int j, const double* ha,
+                                                   int mode, double* colv, double* nu_out) {
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss = fma(ha[i], ha[i], ss);
+    const double nu = sqrt(ha[j] - ss);
+    *nu_out = nu;
+    colv[j] = nu;
+  }
+  if (t < j) colv[t] = mode == 2 ? hz->Hr[t * m + j - 1] : hz->hf[(j - 1) & 1][t] + ha[t];
+  __syncthreads();
+}
+
+// Arnoldi step j after the reduction (p1: a and b, p2: c and d): every block forms nu,
+// t = H a, h and s (small, in LDS), then writes v_j over u_j (j > 0) and u_{j+1} into
+// slot j + 1.  Block 0 stores h as the first pass of column j and, for mode 1, the
+// finished column j - 1 with its Givens rotations (residual estimate, stopping test).
+// mode 0: j = 0 (V_0 is normalised, no column to finish); mode 2: column j - 1 was
+// finished at the end of the previous chunk.
+template <int NB>
+__global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict__ V, int j,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ p1,
+                                                   const double* __restrict__ p2, int mode) {
+  __shared__ double ha[kGmMaxVec], hc[kGmMaxVec], colv[kGmMaxVec], tv[kGmMaxVec], hv[kGmMaxVec],
+      sv[kGmMaxVec];
+  __shared__ double hl[kGmMaxVec * kGmMaxRestart];   // unrotated columns 0 .. j - 2, rows 0 .. j
+  __shared__ double scal[2];
+  const Seg g = seg_of(B);
+  GmState* st = B.st + g.i;
+  if (st->done) return;
+  GmHess* hz = B.hs + g.i;
+  const int m = B.m;
+  const int t = threadIdx.x;
+  // loads that do not depend on the partial sums go out first: the Hessenberg block
+  // for t = H a, and the first element of this block's chunk
+  for (int q = t; q < (j + 1) * j; q += kT) {
+    const int r = q / j, i = q - r * j;
+    hl[q] = (i < j - 1 && r <= i + 1) ? hz->Hr[r * m + i] : 0.0;
+  }
+  V += g.off;
+  z += g.off;
   double* Vj = V + (size_t)j * B.ldv;
-  partial += g.i * kPart;
+  double* Vn = V + (size_t)(j + 1) * B.ldv;
   size_t lo, hi;
-  chunk_of(L, lo, hi);
-  // all NB loads of an element are issued together; the first element's go out
-  // before the norm partials are gathered
-  double v[NB], wf = 0.0;
+  chunk_of(g.L, lo, hi);
   const size_t e0 = lo + threadIdx.x;
+  double v[NB], ue = 0.0, ze = 0.0;
   if (e0 < hi) {
+    if (j > 0) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e0];
-    wf = w[e0];
+      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e0];
+    }
+    ue = Vj[e0];
+    ze = z[e0];
   }
-  double nrm = 1.0, sig = 1.0;
-  if (mode != 0) {
-    gather_partials(pnorm + g.i * kPart, 1, hs);
-    nrm = sqrt(hs[0]);
-    sig = 1.0 / nrm;
+  gather_partials(p2 + g.i * kPart, j + 1, hc);
+  if (j == 0) {
+    if (t == 0) {
+      scal[0] = 1.0;
+      hv[0] = hc[0];
+      sv[0] = hc[0];
+    }
+    __syncthreads();
+  } else {
+    gather_partials(p1 + g.i * kPart, j + 1, ha);
+    second_pass_column(hz, m, j, ha, mode, colv, scal);
+    if (t == 0) {
+      double ac = 0.0;
+      for (int i = 0; i < j; ++i) ac = fma(ha[i], hc[i], ac);
+      scal[1] = (hc[j] - ac) / scal[0];   // v_j . z
+    }
+    // t = H a over the unrotated columns 0 .. j - 1 (column j - 1 as just finished)
+    if (t <= j) {
+      double acc = 0.0;
+      for (int i = 0; i < j; ++i) {
+        const double hki = i == j - 1 ? colv[t] : hl[t * j + i];
+        acc = fma(hki, ha[i], acc);
+      }
+      tv[t] = acc;
+    }
+    __syncthreads();
+    if (t <= j) {
+      const double nu = scal[0];
+      const double hk = (t < j ? hc[t] - tv[t] : scal[1] - tv[j]) / nu;
+      hv[t] = hk;
+      sv[t] = fma(nu, hk, tv[t]);
+    }
+    __syncthreads();
   }
-  double acc[NB];
+  const double inv = 1.0 / scal[0];
+  double a[NB], sc[NB];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NB; ++i) {
+    a[i] = i < j ? ha[i] : 0.0;
+    sc[i] = i < j ? sv[i] : 0.0;
+  }
+  const double sj = sv[j];
   for (size_t e = e0; e < hi; e += kT) {
     if (e != e0) {
+      if (j > 0) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j) * B.ldv + e];
-      wf = w[e];
+        for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+      }
+      ue = Vj[e];
+      ze = z[e];
     }
-    const double we = wf * sig;
-    if (mode != 0) {
-      Vj[e] = Vj[e] * sig;
-      w[e] = we;
-    }
+    double vj = ue, un = ze;
+    if (j > 0) {
 #pragma unroll
-    for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
+      for (int i = 0; i < NB; ++i) {
+        vj = fma(-a[i], v[i], vj);
+        un = fma(-sc[i], v[i], un);
+      }
+      vj *= inv;
+      Vj[e] = vj;
+    }
+    un = fma(-sj, vj, un) * inv;
+    Vn[e] = un;
   }
-  // V_j entered the sums unscaled
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-    if (i == j) acc[i] *= sig;
-  const double r = block_sums<NB>(acc, nv, red);
-  if ((int)threadIdx.x < nv) partial[part_at(threadIdx.x, blockIdx.x)] = r;
-  if (mode == 1 && blockIdx.x == 0) givens_column(B, g.i, j - 1, nrm);
+  if (blockIdx.x != 0) return;
+  if (t <= j) hz->hf[j & 1][t] = hv[t];
+  if (mode == 1) {
+    if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
+    if (t < j) hz->H[t * m + j - 1] = colv[t];
+    __syncthreads();
+    givens_column(B, g.i, j - 1, colv[j]);
+  }
 }
 
-// h = sum of the previous partials; w -= V h; then either the partial dots of the new
-// w with V (next = 0, result back into w) or its partial squared norm (next = 1,
-// result into `out`, the unscaled V_{j+1}).  Block 0 adds h into the Hessenberg
-// column j.
-template <int NB>
-__global__ __launch_bounds__(kT) void k_gm_update(GmBatch B, const double* __restrict__ V, int nv,
-                                                  double* w, const double* __restrict__ pin, int first,
-                                                  int next, double* __restrict__ pout, int j, double* out) {
-  __shared__ double red[(kT / 64) * kGmMaxVec];
-  __shared__ double hs[kGmMaxVec];
+// End of a chunk whose last step was j - 1 (slot j holds u_j): column j - 1 finished
+// from the partial sums a, b (p1) and its Givens rotations applied (one block per
+// instance).
+__global__ __launch_bounds__(kT) void k_gm_finish(GmBatch B, const double* __restrict__ p1, int j) {
+  __shared__ double ha[kGmMaxVec], colv[kGmMaxVec];
+  __shared__ double nu;
   const Seg g = seg_of(B);
   if (B.st[g.i].done) return;
-  const size_t L = g.L;
-  V += g.off;
-  w += g.off;
-  out += g.off;
-  pin += g.i * kPart;
-  pout += g.i * kPart;
-  size_t lo, hi;
-  chunk_of(L, lo, hi);
-  // the first element's loads go out before the partial sums are gathered
-  double v[NB], wf = 0.0;
-  const size_t e0 = lo + threadIdx.x;
-  if (e0 < hi) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e0];
-    wf = w[e0];
-  }
-  gather_partials(pin, nv, hs);
-  if (blockIdx.x == 0 && (int)threadIdx.x < nv) {
-    double* Hc = B.hs[g.i].H + threadIdx.x * B.m + j;
-    *Hc = first ? hs[threadIdx.x] : *Hc + hs[threadIdx.x];
-  }
-  double h[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) h[i] = i < nv ? hs[i] : 0.0;
-  double acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0.0;
-  for (size_t e = e0; e < hi; e += kT) {
-    if (e != e0) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, nv - 1) * B.ldv + e];
-      wf = w[e];
-    }
-    double we = wf;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) we = fma(-h[i], v[i], we);
-    out[e] = we;
-    if (next == 0) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i) acc[i] = fma(v[i], i < nv ? we : 0.0, acc[i]);
-    } else {
-      acc[0] = fma(we, we, acc[0]);
-    }
-  }
-  const int nout = next == 0 ? nv : 1;
-  const double r = block_sums<NB>(acc, nout, red);
-  if ((int)threadIdx.x < nout) pout[part_at(threadIdx.x, blockIdx.x)] = r;
-}
-
-// End of a chunk of Arnoldi steps whose last step is j: Givens rotations on column j
-// with |V_{j+1}| from the squared-norm partials (V_{j+1} is scaled by the next step).
-__global__ __launch_bounds__(kT) void k_gm_column(GmBatch B, const double* __restrict__ pnorm, int j) {
-  __shared__ double hs[1];
-  const Seg g = seg_of(B);
-  if (B.st[g.i].done) return;
-  gather_partials(pnorm + g.i * kPart, 1, hs);
-  givens_column(B, g.i, j, sqrt(hs[0]));
+  GmHess* hz = B.hs + g.i;
+  const int m = B.m;
+  const int t = threadIdx.x;
+  gather_partials(p1 + g.i * kPart, j + 1, ha);
+  second_pass_column(hz, m, j, ha, 1, colv, &nu);
+  if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
+  if (t < j) hz->H[t * m + j - 1] = colv[t];
+  __syncthreads();
+  givens_column(B, g.i, j - 1, colv[j]);
 }
 
 // Fresh solve: header of every instance of the launch (one block per instance).
@@ -472,34 +558,44 @@ void launch_gm_start(const GmBatch& B, double* V, const double* r, const double*
   if (B.count > 0) k_gm_start<<<grid_of(B), kT, 0, s>>>(B, V, r, partial, first_cycle);
 }
 template <int NB>
-void arnoldi_nb(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
-                int mode, hipStream_t s) {
-  const int nv = j + 1;
+void arnoldi_nb(const GmBatch& B, double* V, int j, const double* z, double* p1, double* p2, int mode,
+                hipStream_t s) {
   const dim3 gr = grid_of(B);
-  k_gm_dots<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p3, p1, mode);
-  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p1, 1, 0, p2, j, w);
-  k_gm_update<NB><<<gr, kT, 0, s>>>(B, V, nv, w, p2, 0, 1, p3, j, V + (size_t)(j + 1) * B.ldv);
+  k_gm_reduce<NB><<<gr, kT, 0, s>>>(B, V, j, z, p1, p2, 1);
+  k_gm_vupdate<NB><<<gr, kT, 0, s>>>(B, V, j, z, p1, p2, mode);
 }
-void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
-                       int mode, hipStream_t s) {
-  if (B.count <= 0) return;
-  const int nv = j + 1;
-  switch ((nv + 3) / 4) {
-    case 1: arnoldi_nb<4>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 2: arnoldi_nb<8>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 3: arnoldi_nb<12>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 4: arnoldi_nb<16>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 5: arnoldi_nb<20>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 6: arnoldi_nb<24>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 7: arnoldi_nb<28>(B, V, j, w, p1, p2, p3, mode, s); break;
-    case 8: arnoldi_nb<32>(B, V, j, w, p1, p2, p3, mode, s); break;
-    default:
-      if (nv <= 48) arnoldi_nb<48>(B, V, j, w, p1, p2, p3, mode, s);
-      else arnoldi_nb<64>(B, V, j, w, p1, p2, p3, mode, s);
+template <int NB>
+void finish_nb(const GmBatch& B, const double* V, int j, double* p1, double* p2, hipStream_t s) {
+  k_gm_reduce<NB><<<grid_of(B), kT, 0, s>>>(B, V, j, V, p1, p2, 0);   // z not read (withz = 0)
+  k_gm_finish<<<dim3(1, B.count), kT, 0, s>>>(B, p1, j);
+}
+// NB bucket for j basis vectors before u: multiples of 4 up to 32, then 48, 64
+#define RSP_GM_BUCKET(j_, CALL)                    \
+  switch (((j_) > 0 ? (j_) + 3 : 4) / 4) {         \
+    case 1: CALL(4); break;                        \
+    case 2: CALL(8); break;                        \
+    case 3: CALL(12); break;                       \
+    case 4: CALL(16); break;                       \
+    case 5: CALL(20); break;                       \
+    case 6: CALL(24); break;                       \
+    case 7: CALL(28); break;                       \
+    case 8: CALL(32); break;                       \
+    default:                                       \
+      if ((j_) <= 48) CALL(48);                    \
+      else CALL(64);                               \
   }
+void launch_gm_arnoldi(const GmBatch& B, double* V, int j, const double* z, double* p1, double* p2, int mode,
+                       hipStream_t s) {
+  if (B.count <= 0) return;
+#define RSP_CALL(NB) arnoldi_nb<NB>(B, V, j, z, p1, p2, mode, s)
+  RSP_GM_BUCKET(j, RSP_CALL)
+#undef RSP_CALL
 }
-void launch_gm_column(const GmBatch& B, const double* p3, int j, hipStream_t s) {
-  if (B.count > 0) k_gm_column<<<dim3(1, B.count), kT, 0, s>>>(B, p3, j);
+void launch_gm_finish(const GmBatch& B, const double* V, int j, double* p1, double* p2, hipStream_t s) {
+  if (B.count <= 0) return;
+#define RSP_CALL(NB) finish_nb<NB>(B, V, j, p1, p2, s)
+  RSP_GM_BUCKET(j, RSP_CALL)
+#undef RSP_CALL
 }
 void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s) {
   if (B.count > 0) k_gm_update_x<<<grid_of(B), kT, 0, s>>>(B, V, x);

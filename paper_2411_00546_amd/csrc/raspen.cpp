@@ -193,7 +193,7 @@ struct Work {
   double *F = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr, *r = nullptr;   // [2 ntot]
   double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
   void* fac = nullptr;
-  double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
+  double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr;
 };
 
 void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x) {
@@ -236,7 +236,6 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->V = cv.take<double>((size_t)(o.gmres_restart + 1) * L);
   w->p1 = cv.take<double>(part);
   w->p2 = cv.take<double>(part);
-  w->p3 = cv.take<double>(part);
 }
 
 Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns) {
@@ -681,8 +680,8 @@ double apply_flops(const rsp_context* ctx, const SubWork& sw) { return (1 + ctx-
 double apply_bytes(const rsp_context* ctx, const SubWork& sw) {
   return (1 + ctx->nref) * sw.solve_by + 2 * sw.tile_by;
 }
-double ortho_flops(double L, int q) { return L * (8.0 * (q + 1) + 3); }
-double ortho_bytes(double L, int q) { return 8.0 * L * (4.0 * q + 13); }
+double ortho_flops(double L, int q) { return L * (8.0 * q + 8); }
+double ortho_bytes(double L, int q) { return 8.0 * L * (2.0 * q + 6); }
 
 // step >= 0: Arnoldi step of a GMRES cycle (its timing is settled by settle_gmres_timing).
 void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
@@ -782,8 +781,8 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
                             jac_apply(ctx, I, sw, w.V + (size_t)q * ldv, w.w, s, q);
                             Timed tm(ctx, KID_GMRES_ORTHO, s, ortho_flops(L, q), ortho_bytes(L, q), q);
                             const int mode = q == 0 ? 0 : q == j0 ? 2 : 1;
-                            rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, w.p3, mode, s);
-                            if (q == j0 + chunk - 1) rsp::launch_gm_column(B, w.p3, q, s);
+                            rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, mode, s);
+                            if (q == j0 + chunk - 1) rsp::launch_gm_finish(B, w.V, q + 1, w.p1, w.p2, s);
                           }
                         }));
       j += chunk;

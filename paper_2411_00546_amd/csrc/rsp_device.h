@@ -77,7 +77,9 @@ struct GmState {
 };
 constexpr int kGmDoneStride = sizeof(GmState) / sizeof(int);   // ints between two instances' done flags
 struct GmHess {
-  double H[(kGmMaxRestart + 1) * kGmMaxRestart];   // H[i * m + j]
+  double H[(kGmMaxRestart + 1) * kGmMaxRestart];    // H[i * m + j], Givens-rotated columns
+  double Hr[(kGmMaxRestart + 1) * kGmMaxRestart];   // the same columns unrotated (Arnoldi relation)
+  double hf[2][kGmMaxRestart + 1];                  // first-pass column of the last step (by parity)
   double cs[kGmMaxRestart], sn[kGmMaxRestart], g[kGmMaxRestart + 1];
 };
 // Segment of one instance in the batch's concatenated global vectors (length L =

@@ -69,13 +69,15 @@ void launch_gm_axpy(const GmBatch& B, double a, const double* x, double* y, int 
 void launch_gm_zero(const GmBatch& B, double* x, hipStream_t s);
 void launch_gm_start(const GmBatch& B, double* V, const double* r, const double* partial, int first_cycle,
                      hipStream_t s);
-// Arnoldi step j on w = A V_j: orthogonalisation against V_0..V_j into V_{j+1}
-// (unscaled; partial squared norms in p3).  mode 0: j = 0; 1: scale V_j and w and
-// finish column j - 1; 2: scale only (column j - 1 finished by launch_gm_column).
-void launch_gm_arnoldi(const GmBatch& B, double* V, int j, double* w, double* p1, double* p2, double* p3,
+// Arnoldi step j on z = A u_j (slot j of V holds u_j after its first Gram-Schmidt
+// pass, or V_0): the second pass of u_j gives V_j, the first pass of A V_j gives u_{j+1}
+// in slot j + 1 (partial sums in p1, p2).  mode 0: j = 0; 1: finish column j - 1 and
+// apply its Givens rotations; 2: column j - 1 was finished by launch_gm_finish.
+void launch_gm_arnoldi(const GmBatch& B, double* V, int j, const double* z, double* p1, double* p2,
                        int mode, hipStream_t s);
-// Givens rotations and stopping test of column j (the last step of a chunk).
-void launch_gm_column(const GmBatch& B, const double* p3, int j, hipStream_t s);
+// End of a chunk of steps ending with j - 1: column j - 1 finished (Givens rotations,
+// stopping test).
+void launch_gm_finish(const GmBatch& B, const double* V, int j, double* p1, double* p2, hipStream_t s);
 void launch_gm_update_x(const GmBatch& B, const double* V, double* x, hipStream_t s);
 
 }  // namespace rsp
