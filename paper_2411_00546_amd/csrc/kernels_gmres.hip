@@ -151,9 +151,9 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
 }
 
 // Givens rotations on Hessenberg column j, whose subdiagonal entry is nrm: residual
-// estimate and stopping test.  Called by every thread of one block; the column and
+// estimate and stopping test (`lucky`: the basis cannot be extended, the cycle ends).  Called by every thread of one block; the column and
 // the rotations are staged in LDS so the sequential part runs from LDS.
-__device__ void givens_column(const GmBatch& B, int inst, int j, double nrm) {
+__device__ void givens_column(const GmBatch& B, int inst, int j, double nrm, bool lucky) {
   __shared__ double col[kGmMaxVec], cs[kGmMaxRestart], sn[kGmMaxRestart];
   GmState* st = B.st + inst;
   GmHess* hz = B.hs + inst;
@@ -180,7 +180,7 @@ __device__ void givens_column(const GmBatch& B, int inst, int j, double nrm) {
   col[j] = den;
   col[j + 1] = 0.0;
   for (int i = 0; i <= j + 1; ++i) hz->H[i * m + j] = col[i];
-  const bool breakdown = !(b > 0.0);
+  const bool breakdown = lucky || !(b > 0.0);
   const double gj = hz->g[j];
   hz->g[j + 1] = -s * gj;
   hz->g[j] = c * gj;
@@ -249,21 +249,36 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
   if ((int)threadIdx.x <= j) p2[part_at(threadIdx.x, blockIdx.x)] = r2;
 }
 
+// u_j is taken to lie in span(V_0 .. V_{j-1}) (a lucky breakdown: the Krylov space is
+// invariant up to rounding) when nu^2 = |u|^2 - |a|^2 is at most this fraction of
+// |A v_{j-1}|^2.  Below it the difference of two nearly equal sums is not resolved in
+// FP64: its sign and size are rounding residue (on the order of 1e-16 |A v|^2).
+constexpr double kGmLucky = 1e-12;
+
 // Second pass of u_j against V_0 .. V_{j-1} from the partial sums a, b (p1, j + 1
 // values): nu and the finished column j - 1 (its first pass plus a, subdiagonal nu),
-// into colv[0 .. j] and *nu_out.  `mode` 2: the column is final in Hr already.  Every
-// thread of the block calls it; the result is in LDS for all.
+// into colv[0 .. j], nu and the breakdown flag into out[0], out[1] (1.0: lucky
+// breakdown, nu is then max(nu^2, 0)^(1/2) and v_j is not formed).  `mode` 2: the
+// column is final in Hr already.  Every thread of the block calls it; the result is in
+// LDS for all.
 __device__ __forceinline__ void second_pass_column(const GmHess* hz, int m, int j, const double* ha,
-                                                   int mode, double* colv, double* nu_out) {
+                                                   int mode, double* colv, double* out) {
   const int t = threadIdx.x;
+  if (t < j) colv[t] = mode == 2 ? hz->Hr[t * m + j - 1] : hz->hf[(j - 1) & 1][t] + ha[t];
+  __syncthreads();
   if (t == 0) {
-    double ss = 0.0;
-    for (int i = 0; i < j; ++i) ss = fma(ha[i], ha[i], ss);
-    const double nu = sqrt(ha[j] - ss);
-    *nu_out = nu;
+    // |A v_{j-1}|^2 = |H column|^2 + |u_j|^2 (z = V h + u after the first pass)
+    double ss = 0.0, zz = ha[j];
+    for (int i = 0; i < j; ++i) {
+      ss = fma(ha[i], ha[i], ss);
+      zz = fma(colv[i], colv[i], zz);
+    }
+    const double nu2 = ha[j] - ss;
+    const double nu = sqrt(fmax(nu2, 0.0));
+    out[0] = nu;
+    out[1] = nu2 > kGmLucky * zz ? 0.0 : 1.0;
     colv[j] = nu;
   }
-  if (t < j) colv[t] = mode == 2 ? hz->Hr[t * m + j - 1] : hz->hf[(j - 1) & 1][t] + ha[t];
   __syncthreads();
 }
 
@@ -281,7 +296,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   __shared__ double ha[kGmMaxVec], hc[kGmMaxVec], colv[kGmMaxVec], tv[kGmMaxVec], hv[kGmMaxVec],
       sv[kGmMaxVec];
   __shared__ double hl[kGmMaxVec * kGmMaxRestart];   // unrotated columns 0 .. j - 2, rows 0 .. j
-  __shared__ double scal[2];
+  __shared__ double scal[3];   // nu, lucky flag, v_j . z
   const Seg g = seg_of(B);
   GmState* st = B.st + g.i;
   if (st->done) return;
@@ -314,6 +329,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   if (j == 0) {
     if (t == 0) {
       scal[0] = 1.0;
+      scal[1] = 0.0;
       hv[0] = hc[0];
       sv[0] = hc[0];
     }
@@ -324,7 +340,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     if (t == 0) {
       double ac = 0.0;
       for (int i = 0; i < j; ++i) ac = fma(ha[i], hc[i], ac);
-      scal[1] = (hc[j] - ac) / scal[0];   // v_j . z
+      scal[2] = scal[1] != 0.0 ? 0.0 : (hc[j] - ac) / scal[0];   // v_j . z
     }
     // t = H a over the unrotated columns 0 .. j - 1 (column j - 1 as just finished)
     if (t <= j) {
@@ -337,14 +353,15 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     }
     __syncthreads();
     if (t <= j) {
-      const double nu = scal[0];
-      const double hk = (t < j ? hc[t] - tv[t] : scal[1] - tv[j]) / nu;
+      // (after a lucky breakdown nothing of this step is used; it stays finite)
+      const double nu = scal[1] != 0.0 ? 1.0 : scal[0];
+      const double hk = (t < j ? hc[t] - tv[t] : scal[2] - tv[j]) / nu;
       hv[t] = hk;
       sv[t] = fma(nu, hk, tv[t]);
     }
     __syncthreads();
   }
-  const double inv = 1.0 / scal[0];
+  const double inv = scal[1] != 0.0 ? 0.0 : 1.0 / scal[0];
   double a[NB], sc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -380,7 +397,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
     if (t < j) hz->H[t * m + j - 1] = colv[t];
     __syncthreads();
-    givens_column(B, g.i, j - 1, colv[j]);
+    givens_column(B, g.i, j - 1, colv[j], scal[1] != 0.0);
   }
 }
 
@@ -389,18 +406,18 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
 // instance).
 __global__ __launch_bounds__(kT) void k_gm_finish(GmBatch B, const double* __restrict__ p1, int j) {
   __shared__ double ha[kGmMaxVec], colv[kGmMaxVec];
-  __shared__ double nu;
+  __shared__ double nu[2];
   const Seg g = seg_of(B);
   if (B.st[g.i].done) return;
   GmHess* hz = B.hs + g.i;
   const int m = B.m;
   const int t = threadIdx.x;
   gather_partials(p1 + g.i * kPart, j + 1, ha);
-  second_pass_column(hz, m, j, ha, 1, colv, &nu);
+  second_pass_column(hz, m, j, ha, 1, colv, nu);
   if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
   if (t < j) hz->H[t * m + j - 1] = colv[t];
   __syncthreads();
-  givens_column(B, g.i, j - 1, colv[j]);
+  givens_column(B, g.i, j - 1, colv[j], nu[1] != 0.0);
 }
 
 // Fresh solve: header of every instance of the launch (one block per instance).
@@ -473,7 +490,16 @@ __global__ __launch_bounds__(kT) void k_gm_update_x(GmBatch B, const double* __r
   chunk_of(L, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
     double acc = x[e];
-    for (int i = 0; i < k; ++i) acc += ys[i] * V[(size_t)i * B.ldv + e];
+    // the basis loads are independent: eight in flight at a time, added in order
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = V[(size_t)(i + q) * B.ldv + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += ys[i + q] * v[q];
+    }
+    for (; i < k; ++i) acc += ys[i] * V[(size_t)i * B.ldv + e];
     x[e] = acc;
   }
 }

@@ -354,6 +354,25 @@ def test_plain_workload_repeatable_in_one_context(R):
         R.rsp_context_destroy(ctx)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_single_subdomain_lucky_breakdown(R, precision, seed):
+    """One subdomain: the RASPEN Jacobian is the identity (Section 4.2: the local
+    solution depends only on the fixed outer boundary), so GMRES ends with a lucky
+    breakdown after one product, and the outer step lands on the fixed point."""
+    prob = make_problem("one_sub", phi=synth.PHI_PAPER, mu=1e-2, seed=seed)
+    yd, f = prob.inputs()
+    o = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12, precision=precision)
+    st, hist, x, u = gpu_solve(R, prob, o, yd, f)
+    ref = Raspen(prob, TIGHT, yd, f).solve()
+    assert st == 0 and ref["status"] == 0
+    k = hist["outer"]
+    assert k == 1 and hist["gmres_its"] == [1]   # entries for outer steps 1 .. k
+    assert np.isfinite(hist["gmres_rel"][0]) and hist["gmres_rel"][0] <= 1e-12
+    assert np.isfinite(hist["residual_final"])
+    assert rel(x, ref["x"]) <= 1e-10
+
+
 def test_warm_start_at_solution(R):
     prob = make_problem("small63")
     yd, f = prob.inputs()
