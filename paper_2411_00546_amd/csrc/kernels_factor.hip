@@ -184,6 +184,36 @@ template <int R>
 __device__ __forceinline__ double col_bcast(double v) {
   return __hiloint2double(col_bcast_i<R>(__double2hiint(v)), col_bcast_i<R>(__double2loint(v)));
 }
+// Product and sum rounded separately (never contracted into one fused operation).
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+
+// Sum over the four 16-lane rows of a wave (lanes i, i + 16, i + 32, i + 48), the
+// same value in all four: the 16-lane swap adds rows 0+1 and 2+3, the 32-lane swap
+// adds the halves.
+__device__ __forceinline__ int2 swap_pair16(int v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return make_int2((int)p[0], (int)p[1]);
+}
+__device__ __forceinline__ int2 swap_pair32(int v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return make_int2((int)p[0], (int)p[1]);
+}
+__device__ __forceinline__ float rows_sum(float v) {
+  int2 p = swap_pair16(__float_as_int(v));
+  v = __int_as_float(p.x) + __int_as_float(p.y);
+  p = swap_pair32(__float_as_int(v));
+  return __int_as_float(p.x) + __int_as_float(p.y);
+}
+__device__ __forceinline__ double rows_sum(double v) {
+  int2 lo = swap_pair16(__double2loint(v)), hi = swap_pair16(__double2hiint(v));
+  v = __hiloint2double(hi.x, lo.x) + __hiloint2double(hi.y, lo.y);
+  lo = swap_pair32(__double2loint(v));
+  hi = swap_pair32(__double2hiint(v));
+  return __hiloint2double(hi.x, lo.x) + __hiloint2double(hi.y, lo.y);
+}
 __device__ __forceinline__ float read_lane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -359,31 +389,27 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
   return false;
 }
 
-// In-place inverse of the M x M matrix A (LDS, row stride LD, rows 16-byte aligned)
-// by Gauss-Jordan with 16 x 16 pivot blocks taken in order (no pivot search): for
-// pivot block K,
+// Inverse of the M x M matrix A by Gauss-Jordan with 16 x 16 pivot blocks taken in
+// order (no pivot search): for pivot block K,
 //   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
 //   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K).
 // This is the partial-pivoting Gauss-Jordan result whenever partial pivoting would
 // keep the diagonal: for column diagonally dominant A always (the Schur complements
-// inherit the property).  M / 16 waves; wave J owns column block J and keeps it in
-// registers for the whole elimination (accumulator layout; a tile in that layout is
-// exactly the B operand of a product).  Step K: wave K publishes its old column and
+// inherit the property).  M / 16 waves; wave J owns column block J in registers, c[I]
+// holding tile (I, J) in accumulator layout (a tile in that layout is exactly the B
+// operand of a product), on entry the matrix and on return its inverse.  Step K: wave K publishes its old column and
 // the inverse of A_KK (inverted by one wave in registers, gj16_steps) into a staging
 // panel, the other waves take the inverse and their A_IK from there as A operands and
 // update their tiles in registers, and wave K forms its new column.  The staging
 // panels alternate between steps, so a step needs one barrier.  St: 2 panels of
 // M x padded(16).
 template <typename T, int M>
-__device__ void block_gauss_jordan(T* A, int LD, T* St) {
+__device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
   const int t = threadIdx.x, lane = t & 63, J = t >> 6;
   const int li = lane & 15, q4 = lane >> 4;
-  V c[NB];
-#pragma unroll
-  for (int I = 0; I < NB; ++I) c[I] = tile_load<T>(A + 16 * I * LD + 16 * J, LD, lane);
 #pragma unroll
   for (int K = 0; K < NB; ++K) {
     T* S = St + (K & 1) * M * PLD;
@@ -430,9 +456,6 @@ __device__ void block_gauss_jordan(T* A, int LD, T* St) {
       c[K] = tile_load<T>(S + 16 * K * PLD, PLD, lane);
     }
   }
-#pragma unroll
-  for (int I = 0; I < NB; ++I) tile_store<T>(A + 16 * I * LD + 16 * J, LD, c[I], lane);
-  __syncthreads();
 }
 
 // The usual path, two-ended (twisted) block LU over the lines of the tile, t = ty / 2:
@@ -579,6 +602,54 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
 
   // this workgroup's half; thread a < tx keeps (y, p) of node a of the next line in
   // registers, so that the HBM loads overlap the work of the current line
+  // The line block stays in registers from one line to the next: wave J holds column
+  // block J in accumulator layout (c[I]: rows 16 I .. 16 I + 15).  form_block turns the
+  // previous inverse (mode 1; mode 0: nothing) into the next line block, D_j +
+  // (-hy^-4) S_{j-1}^{-1}: column b of D_j has entries in the diagonal row, the
+  // x-neighbours in the same field and the coupling row in the other field.  Identity
+  // padding; returns true when some active column is not dominant.
+  using VT = typename Mfma<T>::V;
+  constexpr int NB = M / 16;
+  VT blk[NB];
+  auto form_block = [&](int mode) -> bool {
+    const int bl = lane & 15, b = 16 * wave + bl;
+    T off = 0, dia = 0;
+    if (b < m) {
+      const int fc = b >= tx, bc = b - fc * tx;
+      const int r_l = bc > 0 ? b - 1 : -1, r_r = bc + 1 < tx ? b + 1 : -1;
+      const int r_c = fc ? bc : tx + bc;
+      const T d_d = (T)(P.diag0 + la[bc]), d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * I + Mfma<T>::row(lane, r);
+          T v = 0;
+          if (a < m) {
+            T d = 0;
+            d = a == b ? d_d : d;
+            d = (a == r_l || a == r_r) ? d_x : d;
+            d = a == r_c ? d_c : d;
+            // -hy^-4 S^{-1} + D, rounded after the product and after the sum
+            v = mode == 0 ? d : add_rn(mul_rn(nh4, (T)blk[I][r]), d);
+          }
+          blk[I][r] = v;
+          if (a == b) dia = fabs(v);
+          else off += fabs(v);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) blk[I][r] = (T)(16 * I + Mfma<T>::row(lane, r) == b ? 1 : 0);
+      }
+    }
+    off = rows_sum(off);
+    dia = rows_sum(dia);
+    return __syncthreads_or(b < m && !(dia >= off)) != 0;
+  };
+
   bool bad = false;
   double ynext = 0.0, pnext = 0.0;
   if (nlines > 0 && t < tx) state_at(j0, ynext, pnext);
@@ -590,11 +661,15 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       coefficients(y, p);
     }
     __syncthreads();
-    if (build(k == 0 ? 0 : 1)) {
+    if (form_block(k == 0 ? 0 : 1)) {
       bad = true;
       break;
     }
-    block_gauss_jordan<T, M>(Mx, LD, St);
+    block_gauss_jordan<T, M>(blk, St);
+    // the inverse also to LDS, for the fused sweep, the store and (last line) the twist
+#pragma unroll
+    for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
+    __syncthreads();
     if (rhs) {
       for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
       solve_line(j);
