@@ -148,6 +148,9 @@ def kernel_table(stats):
             for k, v in sorted(stats.items(), key=lambda kv: -kv[1]["ms"]) if v["launches"] > 0}
 
 
+TIME_EVERY = [1]   # launch sequences per timed one in the timed solves (--time-every)
+
+
 def kernel_roofline(stats, fp32):
     """Roofline object of the dominant single-pass kernel from rsp_kernel_stats output."""
     kern = {k: v for k, v in stats.items() if v["launches"] > 0}
@@ -163,7 +166,7 @@ def kernel_roofline(stats, fp32):
         achieved = d["flops"] / d["launches"] / avg_s / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": traffic_for(dom, fp32),
-            "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+            "avg_launch_us": avg_s * 1e6, "launches": d["launches"], "timed_every": TIME_EVERY[0],
             "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
     return roof
 
@@ -271,6 +274,7 @@ def run_batch_workload(args, R):
                 R.rsp_solve_batch(ctx, P, o, inst.yd, inst.f, None, None, inst.y, inst.p, inst.u)
                 breakdown = R.rsp_kernel_stats(ctx)
                 R.rsp_set_profiling_filter(ctx, dominant(breakdown))
+                R.rsp_set_profiling_sample(ctx, args.time_every)
                 R.rsp_reset_kernel_stats(ctx)
             torch.cuda.synchronize()
             lat = []
@@ -286,6 +290,7 @@ def run_batch_workload(args, R):
             stats = R.rsp_kernel_stats(ctx) if profile else None
             R.rsp_set_profiling(ctx, False)
             R.rsp_set_profiling_filter(ctx, None)
+            R.rsp_set_profiling_sample(ctx, 1)
             return el, lat, hists, (stats, breakdown), [inst.x(q) for q in range(len(probs))]
 
         el, lat, hists, stats, xs = batch(O, args.steps, args.warmup, True)
@@ -433,6 +438,9 @@ def main():
     ap.add_argument("--max-refine", type=int, default=0,
                     help="FP64 refinement steps per FP32 local solve (the local Newton iteration "
                          "refines against its FP64 residual in any case)")
+    ap.add_argument("--time-every", type=int, default=4,
+                    help="in the timed solves, HIP events around the dominant kernel in one of every "
+                         "N launch sequences (Arnoldi chunks); the others run untimed, as graphs when on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0, "
@@ -444,6 +452,9 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.time_every < 1:
+        ap.error("--time-every must be >= 1")
+    TIME_EVERY[0] = args.time_every
 
     import numpy as np
     import torch
@@ -506,6 +517,7 @@ def main():
             R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
             breakdown = R.rsp_kernel_stats(ctx)
             R.rsp_set_profiling_filter(ctx, dominant(breakdown))
+            R.rsp_set_profiling_sample(ctx, args.time_every)
             R.rsp_reset_kernel_stats(ctx)
         torch.cuda.synchronize()
         lat, hist = [], None
@@ -521,6 +533,7 @@ def main():
         stats = R.rsp_kernel_stats(ctx) if profile else None
         R.rsp_set_profiling(ctx, False)
         R.rsp_set_profiling_filter(ctx, None)
+        R.rsp_set_profiling_sample(ctx, 1)
         x = torch.cat([y.reshape(-1), p.reshape(-1)]).cpu().numpy()
         return el, lat, hist, (stats, breakdown), x
 

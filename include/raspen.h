@@ -228,7 +228,8 @@ typedef struct rsp_tuning {
   int32_t graphs;      /* 1: the Arnoldi chunks of GMRES and the continuation runs of the
                           local Newton solves are captured once into hipGraphs (per
                           layout, options and launch shape) and replayed; 0: direct
-                          stream launches.  Timing (rsp_set_profiling) launches directly. */
+                          stream launches.  Timed sequences (rsp_set_profiling,
+                          rsp_set_profiling_sample) are launched directly. */
   int32_t gm_chunk;    /* Arnoldi steps (Jacobian action + orthogonalisation) enqueued
                           between two host reads of the GMRES stop flags, 1..64 (default 32):
                           longer chunks read back less often and waste at most
@@ -340,6 +341,14 @@ int rsp_set_profiling(rsp_context* ctx, int on);
    timed launch adds two event records to the stream, so timing a single class keeps
    the overhead on the rest of the solve away.  Unknown name: RSP_EINVAL. */
 int rsp_set_profiling_filter(rsp_context* ctx, const char* name);
+
+/* Sample the event timing: with timing on, only one in `every` launch sequences
+   (a chunk of Arnoldi steps, a run of continuation steps) has its launches timed,
+   the first of every `every` from this call on; the other sequences run untimed, and
+   are replayed as captured hipGraphs when graphs are on (rsp_tuning).  Launches
+   outside such sequences are always timed.  every = 1 (the default) times every
+   sequence.  RSP_EINVAL if every < 1. */
+int rsp_set_profiling_sample(rsp_context* ctx, int every);
 
 /* Zero the accumulated kernel statistics. */
 int rsp_reset_kernel_stats(rsp_context* ctx);

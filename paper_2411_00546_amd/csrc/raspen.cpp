@@ -324,6 +324,9 @@ struct rsp_context {
   // kernel timing
   bool prof = false;
   int prof_only = -1;   // time only this kernel class (-1: every class)
+  int prof_every = 1;   // time the launches of one in prof_every launch sequences
+  uint64_t prof_seq = 0;
+  bool prof_mute = false;   // inside a launch sequence that is not timed
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pending> pending;
   rsp_kernel_stat kstat[KID_N]{};
@@ -384,7 +387,7 @@ struct Timed {
   hipEvent_t a = nullptr;
   Timed(rsp_context* c_, int kid_, hipStream_t st_, double fl_, double by_, int step_ = -1)
       : c(c_), kid(kid_), st(st_), fl(fl_), by(by_), step(step_) {
-    if (c->prof && (c->prof_only < 0 || c->prof_only == kid) && (a = event_get(c)) != nullptr &&
+    if (c->prof && !c->prof_mute && (c->prof_only < 0 || c->prof_only == kid) && (a = event_get(c)) != nullptr &&
         hipEventRecord(a, st) != hipSuccess)
       a = nullptr;
   }
@@ -429,11 +432,27 @@ int drop_graphs(rsp_context* ctx, hipStream_t st) {
 // Runs the launches `enqueue(stream)` issues on `st`: directly, or (graphs on) as a
 // graph captured from them once on the private stream and replayed for every later
 // call with the same key and launch signature.  The sequences captured here are
-// kernel launches only.  With event timing on they are launched directly: event
-// pairs recorded inside a graph do not give usable elapsed times.
+// kernel launches only.  A sequence whose launches are timed is launched directly:
+// event pairs recorded inside a graph do not give usable elapsed times.  With event
+// timing on, one in prof_every sequences is timed; the others run untimed (muted),
+// as graphs when graphs are on.
+// Kernel classes each kind of sequence launches.
+constexpr unsigned kSeqKids[2] = {(1u << KID_BLOCK_SOLVE) | (1u << KID_GMRES_ORTHO),
+                                  (1u << KID_FACTOR) | (1u << KID_SOLVE_BWD) | (1u << KID_REFINE) |
+                                      (1u << KID_LINESEARCH)};
+
 template <class F>
 int launch_seq(rsp_context* ctx, const GraphKey& key, hipStream_t st, F&& enqueue) {
-  if (!ctx->graphs || ctx->prof) {
+  // a sequence with no launch of the timed class is never timed
+  const bool timeable = ctx->prof && (ctx->prof_only < 0 || ((kSeqKids[key.kind] >> ctx->prof_only) & 1u));
+  const bool timed = timeable && ctx->prof_seq++ % (uint64_t)ctx->prof_every == 0;
+  struct Mute {
+    rsp_context* c;
+    bool old;
+    ~Mute() { c->prof_mute = old; }
+  } mute{ctx, ctx->prof_mute};
+  ctx->prof_mute = ctx->prof && !timed;
+  if (!ctx->graphs || timed) {
     enqueue(st);
     HIPCHK(hipGetLastError());
     return 0;
@@ -1343,6 +1362,14 @@ int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const
 int rsp_set_profiling(rsp_context* ctx, int on) {
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   ctx->prof = on != 0;
+  return 0;
+}
+
+int rsp_set_profiling_sample(rsp_context* ctx, int every) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  if (every < 1) return fail(RSP_EINVAL, "every must be >= 1 (got %d)", every);
+  ctx->prof_every = every;
+  ctx->prof_seq = 0;
   return 0;
 }
 

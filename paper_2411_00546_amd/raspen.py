@@ -132,6 +132,7 @@ SIGNATURES = [
     ("rsp_server_destroy", _I, [_P]),
     ("rsp_set_profiling", _I, [_P, _I]),
     ("rsp_set_profiling_filter", _I, [_P, ctypes.c_char_p]),
+    ("rsp_set_profiling_sample", _I, [_P, ctypes.c_int]),
     ("rsp_reset_kernel_stats", _I, [_P]),
     ("rsp_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
 ]
@@ -381,6 +382,11 @@ def rsp_autotune(ctx, prob, opts, yd, f, flags=0, stream=None):
 
 def rsp_set_profiling_filter(ctx, name=None):
     return _check(load().rsp_set_profiling_filter(ctx, name.encode() if name else None))
+
+
+def rsp_set_profiling_sample(ctx, every):
+    """Time the launches of one in `every` launch sequences (rsp_set_profiling_sample)."""
+    return _check(load().rsp_set_profiling_sample(ctx, int(every)))
 
 
 def rsp_reset_kernel_stats(ctx):

@@ -113,7 +113,8 @@ def test_server_and_batch_entry_points_are_declared():
 
 def test_tuning_entry_points_are_declared():
     names = declared_functions()
-    for must in ["rsp_get_tuning", "rsp_set_tuning", "rsp_autotune", "rsp_set_profiling_filter"]:
+    for must in ["rsp_get_tuning", "rsp_set_tuning", "rsp_autotune", "rsp_set_profiling_filter",
+                 "rsp_set_profiling_sample"]:
         assert must in names
 
 

@@ -211,3 +211,40 @@ def test_timed_gmres_launches_count_only_work_done(R, chunk):
     assert st == 0
     assert ks["block_solve"]["launches"] == h["jac_applies"], (ks["block_solve"], h["jac_applies"])
     assert ks["gmres_ortho"]["launches"] == h["gmres_total"], (ks["gmres_ortho"], h["gmres_total"])
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_sampled_timing(R, graphs):
+    """rsp_set_profiling_sample(ctx, k): one in k Arnoldi chunks carries events (the
+    others run untimed, as graphs when graphs are on).  The results are those of an
+    untimed solve, fewer launches are timed, and their average duration is that of
+    timing every launch."""
+    p = SAME_M[3]
+    opts = synth.Options(precision=1, max_refine=0)
+    ctx = R.rsp_context_create(0)
+    stats, outs = {}, {}
+    try:
+        R.rsp_set_tuning(ctx, graphs=graphs, gm_chunk=4)
+        _, _, outs["plain"] = run_single(R, p, opts, ctx)
+        R.rsp_set_profiling_filter(ctx, "block_solve")
+        for every in (1, 3):
+            R.rsp_set_profiling_sample(ctx, every)
+            R.rsp_set_profiling(ctx, True)
+            R.rsp_reset_kernel_stats(ctx)
+            st, h, outs[every] = run_single(R, p, opts, ctx)
+            R.rsp_set_profiling(ctx, False)
+            stats[every] = R.rsp_kernel_stats(ctx)["block_solve"]
+            assert st == 0
+        with pytest.raises(RuntimeError):
+            R.rsp_set_profiling_sample(ctx, 0)
+        R.rsp_set_profiling_sample(ctx, 1)
+        R.rsp_set_profiling_filter(ctx, None)
+    finally:
+        R.rsp_context_destroy(ctx)
+    assert same(outs[1], outs["plain"]) and same(outs[3], outs["plain"])
+    full, part = stats[1], stats[3]
+    assert full["launches"] == h["jac_applies"]
+    # about a third of the chunks, plus the restarts' actions, which are always timed
+    assert 0 < part["launches"] < 0.6 * full["launches"], (part, full)
+    ta, tb = full["ms"] / full["launches"], part["ms"] / part["launches"]
+    assert 0.5 < tb / ta < 2.0, (ta, tb)
