@@ -310,6 +310,10 @@ struct rsp_context {
   std::vector<GmSeg> hseg;
   std::vector<SubState> hstate;
   std::vector<GmState> hgm;
+  // pinned staging for the small device-to-host reads (a read from pageable memory is
+  // staged through an extra copy kernel and a host copy)
+  void* pin = nullptr;
+  size_t pin_cap = 0;
   std::vector<double> hnorm;
   std::vector<int> hlist[kLists], hilist[kLists];
   // the instance bound by rsp_setup / rsp_solve for the single-problem calls
@@ -333,6 +337,25 @@ struct rsp_context {
 };
 
 namespace {
+
+// Copies n bytes of device memory to host memory `dst` through the pinned staging
+// buffer and waits for them (every read-back of the solver goes through here).
+int read_back(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_t st) {
+  if (n == 0) return 0;
+  if (ctx->pin_cap < n) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctx->pin) HIPCHK(hipHostFree(ctx->pin));
+    ctx->pin = nullptr;
+    ctx->pin_cap = 0;
+    const size_t cap = std::max(n, (size_t)4096);
+    HIPCHK(hipHostMalloc(&ctx->pin, cap, hipHostMallocDefault));
+    ctx->pin_cap = cap;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->pin, src, n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::memcpy(dst, ctx->pin, n);
+  return 0;
+}
 
 int account(rsp_context* ctx, const Pending& p) {
   HIPCHK(hipEventSynchronize(p.b));
@@ -607,10 +630,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
   }
   HIPCHK(hipGetLastError());
   auto read_state = [&]() -> int {
-    HIPCHK(hipMemcpyAsync(ctx->hstate.data(), w.state, sizeof(SubState) * ctx->hstate.size(),
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return 0;
+    return read_back(ctx, ctx->hstate.data(), w.state, sizeof(SubState) * ctx->hstate.size(), st);
   };
   auto count_active = [&]() {
     int a = 0;
@@ -753,17 +773,11 @@ int read_norms(rsp_context* ctx, int l, int count, const double* v, hipStream_t 
   const GmBatch B = gm_of(ctx, ctx->w.ilist[l], count);
   rsp::launch_gm_norms(B, v, ctx->w.p1, ctx->w.norms, st);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(ctx->hnorm.data(), ctx->w.norms, sizeof(double) * ctx->hnorm.size(),
-                        hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return 0;
+  return read_back(ctx, ctx->hnorm.data(), ctx->w.norms, sizeof(double) * ctx->hnorm.size(), st);
 }
 
 int read_gm_headers(rsp_context* ctx, hipStream_t st) {
-  HIPCHK(hipMemcpyAsync(ctx->hgm.data(), ctx->w.gst, sizeof(GmState) * ctx->hgm.size(),
-                        hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  return 0;
+  return read_back(ctx, ctx->hgm.data(), ctx->w.gst, sizeof(GmState) * ctx->hgm.size(), st);
 }
 
 // Restarted GMRES(m), x_0 = 0, on the device for every instance of `go` (list slot
@@ -1230,6 +1244,7 @@ int rsp_context_destroy(rsp_context* ctx) {
   for (void* m : ctx->gmem)
     if (m) (void)hipFree(m);
   if (ctx->wmem) (void)hipFree(ctx->wmem);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   delete ctx;
   return 0;
 }
