@@ -344,3 +344,70 @@ def test_smoothing_error_decays_at_least_like_sqrt_eps():
             errs.append(np.linalg.norm(x - ref))
     slopes = np.diff(np.log(errs)) / np.diff(np.log(epss))
     assert errs[0] > 0 and np.all(slopes >= 0.45)
+
+
+# ---------------------------------------------------------------- Newton_RAS,eps (Section 4.1)
+@pytest.mark.parametrize("nx,ny,sx,sy,ov,kind,cont", [(15, 15, 2, 2, 1, synth.PHI_CUBIC, 0),
+                                                      (23, 17, 3, 2, 2, synth.PHI_EXP, 0),
+                                                      (15, 15, 2, 2, 1, synth.PHI_CUBIC, 1)])
+def test_newton_ras_equals_global_newton(nx, ny, sx, sy, ov, kind, cont):
+    """RAS only preconditions the Newton systems: at tight GMRES tolerances the iterates
+    are those of Algorithm 1 with a sparse direct solve (same steps, backtracks and
+    answer)."""
+    from oracle.newton_ras import NewtonRas
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=sx, sy=sy, overlap=ov, seed=11)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-12, gmres_rtol=1e-13, continuation=cont)
+    eps0 = prob.eps_min if cont == 1 else prob.eps0
+    xg, info, s = global_newton(prob, synth.Options(tol_outer=1e-12, max_inner=opts.max_outer), yd, f,
+                                eps0=eps0)
+    out = NewtonRas(prob, opts, yd, f).solve()
+    assert info.status == CONVERGED and out["status"] == CONVERGED
+    assert out["iterations"] == info.iterations and out["backtracks"] == info.backtracks
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-11 * np.max(np.abs(xg))
+    assert np.linalg.norm(s.residual(out["x"], prob.eps_min)) <= 1e-10
+    assert all(1 <= g for g in out["gmres_its"])
+
+
+def test_ras_of_one_subdomain_is_the_exact_inverse():
+    """One subdomain covering the grid: M^{-1} = F'(x)^{-1}, so every preconditioned
+    Newton system is solved by GMRES with a single product."""
+    from oracle.newton_ras import NewtonRas
+    prob = synth.Problem(nx=12, ny=9, phi=synth.PHI_PAPER, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=1, sy=1, overlap=2, seed=3)
+    yd, f = prob.inputs()
+    out = NewtonRas(prob, synth.Options(tol_outer=1e-12), yd, f).solve()
+    assert out["status"] == CONVERGED
+    assert out["gmres_its"] == [1] * out["iterations"]
+    xg, info, _ = global_newton(prob, synth.Options(tol_outer=1e-12, max_inner=50), yd, f)
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-12 * np.max(np.abs(xg))
+
+
+def test_ras_preconditioned_operator_halo_form():
+    """M^{-1} F'(x) d = d + sum_i P~_i J_i^{-1} B_i d, J_i = R_i F'(x) P_i and
+    B_i d = R_i diag(A, A)(I - P_i R_i) d: the halo form of Algorithm 4 with local
+    Jacobians at x (the identity sum_i P~_i R_i = I and the locality of the
+    pointwise terms)."""
+    from oracle.newton_ras import RasPreconditioner
+    prob = synth.Problem(nx=17, ny=13, phi=synth.PHI_CUBIC, nu=1e-2, mu=1e-2, eps0=1e-3, eps_min=1e-3,
+                         sx=3, sy=2, overlap=2, seed=5)
+    yd, f = prob.inputs()
+    s = System(prob, yd, f)
+    n = s.n
+    rng = np.random.default_rng(4)
+    x = np.concatenate([0.3 * rng.standard_normal(n), 0.02 * rng.standard_normal(n)])
+    d = rng.standard_normal(2 * n)
+    J = s.jacobian(x, 1e-3).tocsr()
+    subs = partition(prob.nx, prob.ny, prob.sx, prob.sy, prob.overlap)
+    M = RasPreconditioner(J, subs, n)
+    lit = M.apply(J @ d)
+    halo = d.copy()
+    for sub, lu in zip(subs, M.lu):
+        dout = d.copy()
+        dout[sub.rows] = 0.0
+        dout[n + sub.rows] = 0.0
+        Ar = s.A[sub.rows, :]
+        Bd = np.concatenate([Ar @ dout[:n], Ar @ dout[n:]])
+        halo += prolong_core(sub, lu.solve(Bd), n)
+    assert np.max(np.abs(halo - lit)) <= 1e-12 * np.max(np.abs(lit))
