@@ -31,7 +31,8 @@ BOUND = {"factor": ("mfma", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm",
          "solve_bwd": ("hbm", HBM_PEAK_GBS, "GB/s"), "gmres_ortho": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "linesearch": ("hbm", HBM_PEAK_GBS, "GB/s"), "prolong": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "ring_rhs": ("hbm", HBM_PEAK_GBS, "GB/s"), "restrict_halo": ("hbm", HBM_PEAK_GBS, "GB/s"),
-         "newton_init": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_residual": ("hbm", HBM_PEAK_GBS, "GB/s")}
+         "newton_init": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_residual": ("hbm", HBM_PEAK_GBS, "GB/s"),
+         "ras_precond": ("hbm", HBM_PEAK_GBS, "GB/s")}
 
 
 def workload(name, precision="fp64", max_refine=0):

@@ -201,6 +201,21 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
               const double* yd, const double* f, const double* y0, const double* p0,
               double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
 
+/* The linearly preconditioned comparison method of Section 4.1 (Newton_RAS,eps; with
+   opts->continuation == RSP_CONT_NONE, Newton_RAS at eps_min): Algorithm 1 on the
+   whole system F_eps(x) = 0 from eps_0 to eps_min.  Each Newton system
+   F'_eps(x^k) d = -F_eps(x^k) is solved by GMRES preconditioned from the left with
+   one-level restricted additive Schwarz on the partition of Section 4.2,
+   M^{-1} = sum_i P~_i (R_i F'_eps(x^k) P_i)^{-1} R_i (local line factors at x^k, FP32
+   with RSP_FP32_REFINED); GMRES stops at rtol relative to |M^{-1} F|.  Backtracking
+   as in Algorithm 1 (sigma, alpha_min); at most max_outer + 1 Newton steps.
+   Arguments, ownership, stream ordering and status codes as rsp_solve; tol_inner,
+   max_inner and max_refine are not used.  History: norm[k] = |F_eps_k(x^k)|_2,
+   gmres_its[k], gmres_rel[k], backtracks[k]; inner iteration fields are 0. */
+int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
+                         const double* yd, const double* f, const double* y0, const double* p0,
+                         double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
+
 /* Algorithm 2 for `count` independent instances at once (a batch).  Every launch of
    the hot path covers the subdomains of all instances still iterating, and each
    instance runs its own outer iteration: stopping test, GMRES (in lockstep, a

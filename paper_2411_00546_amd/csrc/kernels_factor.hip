@@ -492,7 +492,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   DevProblem P;
   if (!item_of(I, s, P)) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
+  double eps = eps_fixed > 0.0 ? eps_fixed : eps_fixed < 0.0 ? P.eps_start : P.eps_min;
   if (state) {
     if (!state[s].active) return;
     eps = state[s].eps;
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
   if (!only[s]) return;
   const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
   const int lane = t & 63;
-  double eps = eps_fixed > 0.0 ? eps_fixed : P.eps_min;
+  double eps = eps_fixed > 0.0 ? eps_fixed : eps_fixed < 0.0 ? P.eps_start : P.eps_min;
   if (state) {
     if (!state[s].active) return;
     eps = state[s].eps;

@@ -263,11 +263,12 @@ size_t layout_bytes(const Geometry& g, const rsp_options& o) {
 // Kernel timing: HIP events around launches, resolved at synchronisation points.
 enum Kid {
   KID_RESTRICT, KID_INIT, KID_FACTOR, KID_SOLVE_BWD, KID_LINESEARCH, KID_PROLONG, KID_RING,
-  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_N
+  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_PRECOND, KID_N
 };
 const char* const kKidName[KID_N] = {"restrict_halo", "newton_init", "factor", "solve_bwd",
                                      "linesearch", "prolong", "ring_rhs", "block_solve",
-                                     "gmres_ortho", "global_residual", "newton_refine"};
+                                     "gmres_ortho", "global_residual", "newton_refine",
+                                     "ras_precond"};
 
 struct Pending {
   int kid;
@@ -1127,6 +1128,116 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
   return 0;
 }
 
+// Newton_RAS,eps (Section 4.1) for one placed instance: Algorithm 1 on the whole
+// system F_eps(x) = 0, each Newton system F'_eps(x^k) d = -F_eps(x^k) solved by GMRES
+// preconditioned from the left with one-level RAS, M^{-1} = sum_i P~_i J_i^{-1} R_i,
+// J_i = R_i F'_eps(x^k) P_i.  The local Jacobians are factored at R_i x^k with the
+// current smoothing.  Because the spatial coupling of F' is the Laplacian only,
+//   M^{-1} F'(x) d = d + sum_i P~_i J_i^{-1} B_i d,  B_i d = R_i diag(A, A)(I - P_i R_i) d,
+// which is minus the Jacobian action of Algorithm 4 with these factors.  So GMRES runs
+// on that action with right-hand side M^{-1} F, and its solution is the Newton direction.
+// Backtracking on ||F_eps_k||, eps_{k+1} = max(gamma eps_k, eps_min); the loop also
+// runs while eps_k > eps_min, at most max_outer + 1 steps.
+int ras_newton(rsp_context* ctx, Inst* in, hipStream_t st) {
+  const rsp_options& o = ctx->opts;
+  Work& w = ctx->w;
+  const int M = ctx->geo.M;
+  const std::vector<Inst*> one{in};
+  RSPCHK(upload_lists(ctx, kLGo, one, st));
+  const Items I = items_of(ctx, w.list[kLGo], (int)ctx->hlist[kLGo].size());
+  const GmBatch B = gm_of(ctx, w.ilist[kLGo], 1);
+  const SubWork all = sub_work(ctx, one, false);
+  const double L = 2.0 * in->n;
+  DevProblem& P = ctx->hprob[in->slot];
+  const size_t off = 2 * in->noff;
+  // ||F_eps(x)|| of the instance, F_eps(x) into out (x, out: batch vectors)
+  auto residual = [&](const double* x, double eps, double* out, double* norm) -> int {
+    {
+      Timed t(ctx, KID_GLOBAL, st, 20.0 * L, 24.0 * L);   // x, y_d, f read, F written
+      rsp::launch_global_residual(P, ctx->yd + in->noff, ctx->f + in->noff, x + off, eps, out + off, st);
+    }
+    HIPCHK(hipGetLastError());
+    RSPCHK(read_norms(ctx, kLGo, 1, out, st));
+    *norm = ctx->hnorm[in->slot];
+    return 0;
+  };
+  double eps = o.continuation == RSP_CONT_NONE ? in->prob.eps_min : in->prob.eps0;
+  double Fn = 0;
+  RSPCHK(residual(ctx->x, eps, w.F, &Fn));
+  in->started = true;
+  in->thr = std::max(o.tol_outer, o.tol_outer * Fn);
+  in->hist.norm[0] = Fn;
+  int k = 0;
+  while ((!(Fn <= in->thr) || eps > in->prob.eps_min) && k <= o.max_outer) {
+    auto t = Clock::now();
+    // local Jacobians at x^k with smoothing eps_k
+    P.eps_start = eps;
+    HIPCHK(hipMemcpyAsync(w.prob + in->slot, &P, sizeof(DevProblem), hipMemcpyHostToDevice, st));
+    {
+      Timed tm(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
+      rsp::launch_restrict_halo(I, ctx->x, w.tilex, st);
+    }
+    {
+      Timed tm(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
+      rsp::launch_factor(I, M, w.tilex, nullptr, nullptr, -1.0, nullptr, 0.0, w.fac, ctx->fp32, w.g,
+                         w.fallback, w.counter, st);
+    }
+    // w.F <- -M^{-1} F_eps(x^k): GMRES then solves (action) d = M^{-1} F
+    {
+      Timed tm(ctx, KID_PRECOND, st, all.solve_fl, all.solve_by + 2 * all.tile_by + 16.0 * L);
+      rsp::launch_restrict(I, w.F, w.t1, st);
+      rsp::launch_block_solve(I, M, w.fac, ctx->fp32, w.t1, w.t2, st);
+      rsp::launch_prolong(I, w.t2, nullptr, w.w, st);
+      rsp::launch_gm_axpy(B, -1.0, w.w, w.F, 0, st);
+    }
+    HIPCHK(hipGetLastError());
+    in->n_factor += in->part.S;
+    in->flops += all.factor_fl + all.solve_fl;
+    in->ms_eval += ms_since(t);
+    t = Clock::now();
+    RSPCHK(run_gmres(ctx, one, st));
+    in->ms_gmres += ms_since(t);
+    // relaxed backtracking: alpha = 1, 1/2, ... until ||F_eps(x + alpha d)|| <= sigma ||F_eps(x)||
+    double alpha = 1.0, rt = 0;
+    int bt = 0;
+    bool fail_ls = false;
+    for (;;) {
+      rsp::launch_gm_axpy(B, 1.0, ctx->x, w.b, 0, st);
+      rsp::launch_gm_axpy(B, alpha, w.dx, w.b, 1, st);
+      RSPCHK(residual(w.b, eps, w.w, &rt));
+      if (rt <= o.sigma * Fn) break;
+      alpha *= 0.5;
+      bt += 1;
+      if (alpha < o.alpha_min) {
+        fail_ls = true;
+        break;
+      }
+    }
+    in->n_newton += 1;
+    if (fail_ls) {
+      in->status = std::max(in->status, (int)RSP_LINESEARCH_FAIL);
+      if (k + 1 <= RSP_HIST_MAX) in->hist.backtracks[k + 1] = bt;
+      break;
+    }
+    rsp::launch_gm_axpy(B, alpha, w.dx, ctx->x, 1, st);
+    eps = std::max(in->prob.gamma * eps, in->prob.eps_min);
+    k += 1;
+    RSPCHK(residual(ctx->x, eps, w.F, &Fn));
+    if (k <= RSP_HIST_MAX) {
+      rsp_history* h = &in->hist;
+      h->norm[k] = Fn;
+      h->gmres_its[k] = in->gm_used;
+      h->gmres_rel[k] = in->gm_rel;
+      h->backtracks[k] = bt;
+    }
+  }
+  in->k = k;
+  in->Fn = Fn;
+  if (in->status == 0 && (!(Fn <= in->thr) || eps > in->prob.eps_min))
+    in->status = in->gm_stagnated ? RSP_GMRES_STAGNATION : RSP_NOT_CONVERGED;
+  return finish(ctx, one, st);
+}
+
 }  // namespace rsp
 
 namespace {
@@ -1359,6 +1470,24 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
     ctx->ready = true;
   }
   return r;
+}
+
+int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts, const double* yd,
+                         const double* f, const double* y0, const double* p0, double* y, double* p, double* u,
+                         rsp_history* hist, hipStream_t stream) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  RSPCHK(rsp::validate_options(opts));
+  if (!prob) return fail(RSP_EINVAL, "problem is NULL");
+  ctx->ready = false;
+  std::vector<Inst> insts;
+  RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
+  std::vector<Inst*> live{&insts[0]};
+  RSPCHK(engine_place(ctx, *opts, live, stream));
+  insts[0].t0 = rsp::Clock::now();
+  RSPCHK(rsp::ras_newton(ctx, &insts[0], stream));
+  if (hist) *hist = insts[0].hist;
+  RSPCHK(resolve_events(ctx));
+  return insts[0].status;
 }
 
 int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const rsp_options* opts,

@@ -29,7 +29,8 @@ void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t s
 // a4 (+ fused forward sweep when rhs != nullptr): block-tridiagonal factors S_j^{-1},
 // stored as double, or as float when fp32 != 0 (facT points to that type).  The
 // smoothing is state[s].eps (state != nullptr; inactive items are skipped), else
-// eps_fixed when > 0, else the instance's eps_min.  Two-ended (twisted) block LU with
+// eps_fixed when > 0, the instance's eps_start when < 0 (each instance its own
+// smoothing), else the instance's eps_min.  Two-ended (twisted) block LU with
 // the twist at line ty / 2.  fallback, counter: [items] flags and counters, 0 between
 // launches (subdomains redone with partial pivoting; arrival of the two workgroups).
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,

@@ -1,0 +1,129 @@
+"""Newton_RAS,eps on the GPU (rsp_solve_newton_ras) against the oracle.
+
+Section 4.1: Algorithm 1 on F_eps(x) = 0 with each Newton system solved by GMRES
+preconditioned from the left with one-level RAS.  The GPU forms the preconditioned
+operator in the halo form of Algorithm 4 (local line factors at x^k); the oracle
+forms it literally with sparse LU factors.  Both run the same Newton steps, so the
+step counts, backtracks and answers agree.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.newton_ras import NewtonRas
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2411_00546_amd import raspen
+    raspen.load()
+    return raspen
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = {
+    "small63": dict(nx=63, ny=63, sx=2, sy=2, overlap=2),
+    "rect23x17": dict(nx=23, ny=17, sx=3, sy=2, overlap=2),
+    "ragged37x29": dict(nx=37, ny=29, sx=3, sy=3, overlap=3),
+    "one_sub": dict(nx=12, ny=9, sx=1, sy=1, overlap=2),
+}
+
+
+def problem(name, phi=synth.PHI_CUBIC, mu=1e-2, seed=1):
+    return synth.Problem(phi=phi, nu=1e-2, mu=mu, eps0=1.0, eps_min=1e-6, gamma=0.5, seed=seed, **CASES[name])
+
+
+def gpu_newton_ras(R, prob, opts, yd, f):
+    import torch
+    y, p, u = (dev(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+    ctx = R.rsp_context_create(0)
+    try:
+        st, h = R.rsp_solve_newton_ras(ctx, R.make_problem(prob), R.make_options(opts), dev(yd),
+                                       None if f is None else dev(f), None, None, y, p, u)
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+    return st, h, np.concatenate([host(y).reshape(-1), host(p).reshape(-1)]), host(u).reshape(-1)
+
+
+TIGHT = dict(tol_outer=1e-11, gmres_rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,phi,mu,cont", [("small63", synth.PHI_CUBIC, 1e-2, 0),
+                                              ("rect23x17", synth.PHI_EXP, 3e-2, 0),
+                                              ("ragged37x29", synth.PHI_PAPER, 0.0, 0),
+                                              ("small63", synth.PHI_CUBIC, 1e-2, 1)])
+def test_newton_ras_matches_oracle(R, name, phi, mu, cont):
+    prob = problem(name, phi, mu)
+    yd, f = prob.inputs()
+    opts = synth.Options(continuation=cont, **TIGHT)
+    st, h, x, u = gpu_newton_ras(R, prob, opts, yd, f)
+    ref = NewtonRas(prob, opts, yd, f).solve()
+    assert st == 0 and ref["status"] == 0
+    assert h["outer"] == ref["iterations"]
+    assert sum(h["backtracks"]) == ref["backtracks"]
+    scale = np.abs(ref["x"]).max()
+    assert np.abs(x - ref["x"]).max() <= 1e-10 * scale
+    assert np.abs(u - ref["u"]).max() <= 1e-10 * max(np.abs(ref["u"]).max(), 1.0)
+    # |F_eps_k(x^k)| along the iteration, and GMRES products per Newton system
+    # (classical Gram-Schmidt twice on the GPU, modified Gram-Schmidt in the oracle)
+    assert len(h["gmres_its"]) == ref["iterations"]
+    assert all(abs(a - b) <= 1 for a, b in zip(h["gmres_its"], ref["gmres_its"]))
+    assert h["residual_final"] <= 1e-9
+
+
+def test_newton_ras_fp32_preconditioner(R):
+    """FP32 line factors in the preconditioner (RSP_FP32_REFINED): the Newton directions
+    are those of the FP32 halo-form operator, the answer that of FP64 within 1e-8."""
+    prob = problem("small63")
+    yd, f = prob.inputs()
+    st64, h64, x64, _ = gpu_newton_ras(R, prob, synth.Options(**TIGHT), yd, f)
+    st32, h32, x32, _ = gpu_newton_ras(R, prob, synth.Options(precision=1, max_refine=0, **TIGHT), yd, f)
+    assert st64 == 0 and st32 == 0
+    assert np.abs(x32 - x64).max() <= 1e-8 * np.abs(x64).max()
+
+
+def test_newton_ras_one_subdomain_is_one_product_per_system(R):
+    """One subdomain: M^{-1} F' = I, so every GMRES solve ends after one product with a
+    lucky breakdown, and the iterates are the oracle's."""
+    prob = problem("one_sub", synth.PHI_PAPER, 1e-2, seed=3)
+    yd, f = prob.inputs()
+    opts = synth.Options(**TIGHT)
+    st, h, x, u = gpu_newton_ras(R, prob, opts, yd, f)
+    ref = NewtonRas(prob, opts, yd, f).solve()
+    assert st == 0 and ref["status"] == 0
+    assert h["gmres_its"] == [1] * h["outer"] and ref["gmres_its"] == [1] * ref["iterations"]
+    assert h["outer"] == ref["iterations"]
+    assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
+
+
+def test_newton_ras_rejects_bad_input(R):
+    prob = problem("small63")
+    yd, f = prob.inputs()
+    ctx = R.rsp_context_create(0)
+    try:
+        y, p, u = (dev(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+        with pytest.raises(RuntimeError):
+            R.rsp_solve_newton_ras(ctx, R.make_problem(prob), R.make_options(synth.Options(gmres_restart=0)),
+                                   dev(yd), dev(f), None, None, y, p, u)
+        bad = problem("small63")
+        bad.sx = 200
+        with pytest.raises(RuntimeError):
+            R.rsp_solve_newton_ras(ctx, R.make_problem(bad), R.make_options(synth.Options()), dev(yd), dev(f),
+                                   None, None, y, p, u)
+    finally:
+        R.rsp_context_destroy(ctx)
