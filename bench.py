@@ -442,6 +442,9 @@ def main():
     ap.add_argument("--time-every", type=int, default=4,
                     help="in the timed solves, HIP events around the dominant kernel in one of every "
                          "N launch sequences (Arnoldi chunks); the others run untimed, as graphs when on")
+    ap.add_argument("--method", default="raspen", choices=["raspen", "newton_ras"],
+                    help="plain/small/precision workloads: RASPEN (Algorithm 2, the default) or the "
+                         "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0, "
@@ -504,9 +507,13 @@ def main():
             R.rsp_context_destroy(ctx)
         return
 
+    # the method timed: RASPEN (Algorithm 2), or the linearly RAS-preconditioned Newton
+    # of Section 4.1 on the same workload
+    solve_fn = R.rsp_solve if args.method == "raspen" else R.rsp_solve_newton_ras
+
     def solves(opt, steps, warmup, profile):
         for _ in range(warmup):
-            R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+            solve_fn(ctx, P, opt, ydt, ft, None, None, y, p, u)
         breakdown = None
         if profile:
             # one untimed solve with every kernel class timed: the per-kernel table and
@@ -515,7 +522,7 @@ def main():
             R.rsp_set_profiling_filter(ctx, None)
             R.rsp_set_profiling(ctx, True)
             R.rsp_reset_kernel_stats(ctx)
-            R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+            solve_fn(ctx, P, opt, ydt, ft, None, None, y, p, u)
             breakdown = R.rsp_kernel_stats(ctx)
             R.rsp_set_profiling_filter(ctx, dominant(breakdown))
             R.rsp_set_profiling_sample(ctx, args.time_every)
@@ -525,7 +532,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(steps):
             ts = time.perf_counter()
-            st, hist = R.rsp_solve(ctx, P, opt, ydt, ft, None, None, y, p, u)
+            st, hist = solve_fn(ctx, P, opt, ydt, ft, None, None, y, p, u)
             lat.append(time.perf_counter() - ts)
             if st != 0:
                 raise RuntimeError("solve ended with status %d" % st)
@@ -557,14 +564,15 @@ def main():
     stats, breakdown = stats
     roof = kernel_roofline(stats, opts.precision == 1)
     kernels = kernel_table(breakdown)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(prob, opts, hist)
+    # the CPU baseline is the RASPEN oracle's sample; none for the comparison method
+    cpu = None if args.no_cpu_baseline or args.method != "raspen" else cpu_baseline(prob, opts, hist)
     lat_ms = np.array(lat) * 1e3
     out = {"metric": "solves/s at 1e-8 rel err (mixed vs FP64); p50/p99 solve latency",
            "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
            "data": "synthetic (seeded Gaussian-bump y_d)",
-           "config": describe(prob, opts),
+           "config": dict(describe(prob, opts), method=args.method),
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
