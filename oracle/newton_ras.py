@@ -1,5 +1,6 @@
-"""Linearly RAS-preconditioned monolithic Newton with eps-continuation (Newton_RAS,eps;
-oracle; test infrastructure only).
+"""Monolithic Newton with eps-continuation, its Newton systems solved by GMRES with or
+without a linear RAS preconditioner (Newton_RAS,eps and Newton_eps; oracle; test
+infrastructure only).
 
 Section 4.1 of the paper: Algorithm 1 on the whole system F_eps(x) = 0, where each
 Newton system F'_eps(x^k) d = -F_eps(x^k) is solved by GMRES with a one-level
@@ -10,6 +11,9 @@ Section 4.2:
 
 the local matrices being the rows and columns of the global Jacobian at the current
 iterate that belong to the overlapping box Omega_i.
+
+Without the preconditioner (precond=False) this is the monolithic Newton_eps of
+Section 4.1: GMRES on F'_eps(x^k) d = -F_eps(x^k) itself.
 
 Readings taken where the paper leaves room (each listed in the design doc):
   * the preconditioner is applied from the left: GMRES solves
@@ -47,10 +51,11 @@ class RasPreconditioner:
 
 
 class NewtonRas:
-    """Newton_RAS,eps for one problem instance (prob: synth.Problem, opts: synth.Options)."""
+    """Newton_RAS,eps (precond=True) or Newton_eps (precond=False) for one problem
+    instance (prob: synth.Problem, opts: synth.Options)."""
 
-    def __init__(self, prob, opts, yd, f=None):
-        self.prob, self.opts = prob, opts
+    def __init__(self, prob, opts, yd, f=None, precond=True):
+        self.prob, self.opts, self.precond = prob, opts, precond
         self.sys = System(prob, yd, f)
         self.n = self.sys.n
         self.subs = partition(prob.nx, prob.ny, prob.sx, prob.sy, prob.overlap)
@@ -58,12 +63,15 @@ class NewtonRas:
         self.gmres_rel = []
 
     def linsolve(self, J, b):
-        """d with M^{-1} J d = M^{-1} b by GMRES (left RAS preconditioning)."""
+        """d with M^{-1} J d = M^{-1} b by GMRES (left RAS preconditioning), or J d = b."""
         o = self.opts
-        M = RasPreconditioner(J, self.subs, self.n)
         Jc = J.tocsr()
-        d, used, rel = gmres(lambda v: M.apply(Jc @ v), M.apply(b), o.gmres_restart, o.gmres_rtol,
-                             o.max_gmres)
+        if self.precond:
+            M = RasPreconditioner(J, self.subs, self.n)
+            d, used, rel = gmres(lambda v: M.apply(Jc @ v), M.apply(b), o.gmres_restart, o.gmres_rtol,
+                                 o.max_gmres)
+        else:
+            d, used, rel = gmres(lambda v: Jc @ v, b, o.gmres_restart, o.gmres_rtol, o.max_gmres)
         self.gmres_its.append(used)
         self.gmres_rel.append(rel)
         return d

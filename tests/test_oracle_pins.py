@@ -411,3 +411,24 @@ def test_ras_preconditioned_operator_halo_form():
         Bd = np.concatenate([Ar @ dout[:n], Ar @ dout[n:]])
         halo += prolong_core(sub, lu.solve(Bd), n)
     assert np.max(np.abs(halo - lit)) <= 1e-12 * np.max(np.abs(lit))
+
+
+@pytest.mark.parametrize("cont", [0, 1])
+def test_newton_gmres_equals_global_newton(cont):
+    """Newton_eps (Section 4.1, GMRES without preconditioner): with GMRES run to a tight
+    tolerance the iterates are those of the sparse direct Newton solve."""
+    from oracle.newton_ras import NewtonRas
+    prob = synth.Problem(nx=15, ny=11, phi=synth.PHI_CUBIC, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=2, sy=2, overlap=1, seed=12)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-11, gmres_rtol=1e-13, max_gmres=5000, continuation=cont)
+    eps0 = prob.eps_min if cont == 1 else prob.eps0
+    xg, info, s = global_newton(prob, synth.Options(tol_outer=1e-11, max_inner=opts.max_outer), yd, f,
+                                eps0=eps0)
+    out = NewtonRas(prob, opts, yd, f, precond=False).solve()
+    assert info.status == CONVERGED and out["status"] == CONVERGED
+    assert out["iterations"] == info.iterations and out["backtracks"] == info.backtracks
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-10 * np.max(np.abs(xg))
+    # the unpreconditioned systems take far more products than the RAS ones
+    ras = NewtonRas(prob, opts, yd, f).solve()
+    assert np.mean(out["gmres_its"]) > 3 * np.mean(ras["gmres_its"])
