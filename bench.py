@@ -32,7 +32,7 @@ BOUND = {"factor": ("mfma", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm",
          "linesearch": ("hbm", HBM_PEAK_GBS, "GB/s"), "prolong": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "ring_rhs": ("hbm", HBM_PEAK_GBS, "GB/s"), "restrict_halo": ("hbm", HBM_PEAK_GBS, "GB/s"),
          "newton_init": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_residual": ("hbm", HBM_PEAK_GBS, "GB/s"),
-         "ras_precond": ("hbm", HBM_PEAK_GBS, "GB/s")}
+         "ras_precond": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_jacobian": ("hbm", HBM_PEAK_GBS, "GB/s")}
 
 
 def workload(name, precision="fp64", max_refine=0):
@@ -442,9 +442,10 @@ def main():
     ap.add_argument("--time-every", type=int, default=4,
                     help="in the timed solves, HIP events around the dominant kernel in one of every "
                          "N launch sequences (Arnoldi chunks); the others run untimed, as graphs when on")
-    ap.add_argument("--method", default="raspen", choices=["raspen", "newton_ras"],
-                    help="plain/small/precision workloads: RASPEN (Algorithm 2, the default) or the "
-                         "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras)")
+    ap.add_argument("--method", default="raspen", choices=["raspen", "newton_ras", "newton"],
+                    help="plain/small/precision workloads: RASPEN (Algorithm 2, the default), the "
+                         "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras) "
+                         "or the unpreconditioned one (rsp_solve_newton)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0, "
@@ -509,7 +510,8 @@ def main():
 
     # the method timed: RASPEN (Algorithm 2), or the linearly RAS-preconditioned Newton
     # of Section 4.1 on the same workload
-    solve_fn = R.rsp_solve if args.method == "raspen" else R.rsp_solve_newton_ras
+    solve_fn = {"raspen": R.rsp_solve, "newton_ras": R.rsp_solve_newton_ras,
+                "newton": R.rsp_solve_newton}[args.method]
 
     def solves(opt, steps, warmup, profile):
         for _ in range(warmup):

@@ -216,6 +216,16 @@ int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_op
                          const double* yd, const double* f, const double* y0, const double* p0,
                          double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
 
+/* The unpreconditioned monolithic method of Section 4.1 (Newton_eps; with
+   opts->continuation == RSP_CONT_NONE, Newton at eps_min): Algorithm 1 on the whole
+   system F_eps(x) = 0 as in rsp_solve_newton_ras, each Newton system solved by GMRES on
+   F'_eps(x^k) itself (products with the whole-system Jacobian: the 5-point stencil
+   and the pointwise terms).  Arguments, options, history and status codes as
+   rsp_solve_newton_ras; precision does not apply (all FP64). */
+int rsp_solve_newton(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
+                     const double* yd, const double* f, const double* y0, const double* p0,
+                     double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
+
 /* Algorithm 2 for `count` independent instances at once (a batch).  Every launch of
    the hot path covers the subdomains of all instances still iterating, and each
    instance runs its own outer iteration: stopping test, GMRES (in lockstep, a

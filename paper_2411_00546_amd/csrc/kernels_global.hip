@@ -29,6 +29,42 @@ __global__ __launch_bounds__(kVecBlock) void k_global_residual(DevProblem P, con
   }
 }
 
+// out = F'_eps(x) d on the whole grid of instance `inst`: the Jacobian of the system of
+// Section 3.2,
+//   [ A + diag phi'(y)        diag g'(p) / nu   ] [d_y]
+//   [ diag(phi''(y) p - 1)    A + diag phi'(y)  ] [d_p],
+// A the 5-point -Laplacian with homogeneous Dirichlet values.  x, d, out are batch
+// vectors (the instance's segment at 2 noff) and eps is the instance's eps_start, all
+// read through memory, so a captured launch stays valid while the smoothing changes.
+// Returns at once when the instance's GMRES has stopped (done flag).
+__global__ __launch_bounds__(kVecBlock) void k_global_jac_apply(const DevProblem* __restrict__ prob, int inst,
+                                                                const GmState* __restrict__ gst,
+                                                                const double* __restrict__ x,
+                                                                const double* __restrict__ d,
+                                                                double* __restrict__ out) {
+  if (gst && gst[inst].done) return;
+  const DevProblem P = prob[inst];
+  const double eps = P.eps_start;
+  const size_t n = (size_t)P.nx * P.ny;
+  x += 2 * P.noff;
+  d += 2 * P.noff;
+  out += 2 * P.noff;
+  for (size_t g = blockIdx.x * (size_t)kVecBlock + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * kVecBlock) {
+    const int j = (int)(g / P.nx), i = (int)(g - (size_t)j * P.nx);
+    const double yc = x[g], pc = x[n + g];
+    const double* dy = d;
+    const double* dp = d + n;
+    const double lap_y = P.diag0 * dy[g] - P.hx2i * ((i > 0 ? dy[g - 1] : 0.0) + (i + 1 < P.nx ? dy[g + 1] : 0.0)) -
+                         P.hy2i * ((j > 0 ? dy[g - P.nx] : 0.0) + (j + 1 < P.ny ? dy[g + P.nx] : 0.0));
+    const double lap_p = P.diag0 * dp[g] - P.hx2i * ((i > 0 ? dp[g - 1] : 0.0) + (i + 1 < P.nx ? dp[g + 1] : 0.0)) -
+                         P.hy2i * ((j > 0 ? dp[g - P.nx] : 0.0) + (j + 1 < P.ny ? dp[g + P.nx] : 0.0));
+    const double a = dphi_of(P.phi, yc, P.kappa);
+    out[g] = lap_y + a * dy[g] + dg_of(pc, P.mu, eps) * P.inv_nu * dp[g];
+    out[n + g] = (ddphi_of(P.phi, yc, P.kappa) * pc - 1.0) * dy[g] + lap_p + a * dp[g];
+  }
+}
+
 __global__ __launch_bounds__(kVecBlock) void k_control(DevProblem P, const double* __restrict__ p,
                                                        double eps, double* __restrict__ u) {
   const size_t n = (size_t)P.nx * P.ny;
@@ -47,6 +83,10 @@ int grid_for(size_t L) {
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
                             const double* x, double eps, double* out, hipStream_t st) {
   k_global_residual<<<grid_for((size_t)P.nx * P.ny), kVecBlock, 0, st>>>(P, yd, f, x, eps, out);
+}
+void launch_global_jac_apply(const DevProblem* prob, const DevProblem& P, int inst, const GmState* gst,
+                             const double* x, const double* d, double* out, hipStream_t st) {
+  k_global_jac_apply<<<grid_for((size_t)P.nx * P.ny), kVecBlock, 0, st>>>(prob, inst, gst, x, d, out);
 }
 void launch_control(const DevProblem& P, const double* p, double eps, double* u, hipStream_t st) {
   k_control<<<grid_for((size_t)P.nx * P.ny), kVecBlock, 0, st>>>(P, p, eps, u);

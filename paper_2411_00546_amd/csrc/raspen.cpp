@@ -263,12 +263,12 @@ size_t layout_bytes(const Geometry& g, const rsp_options& o) {
 // Kernel timing: HIP events around launches, resolved at synchronisation points.
 enum Kid {
   KID_RESTRICT, KID_INIT, KID_FACTOR, KID_SOLVE_BWD, KID_LINESEARCH, KID_PROLONG, KID_RING,
-  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_PRECOND, KID_N
+  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_PRECOND, KID_GJAC, KID_N
 };
 const char* const kKidName[KID_N] = {"restrict_halo", "newton_init", "factor", "solve_bwd",
                                      "linesearch", "prolong", "ring_rhs", "block_solve",
                                      "gmres_ortho", "global_residual", "newton_refine",
-                                     "ras_precond"};
+                                     "ras_precond", "global_jacobian"};
 
 struct Pending {
   int kid;
@@ -323,6 +323,8 @@ struct rsp_context {
   // captured launch sequences (hipGraphs), valid while the launch signature holds
   int graphs = 0;               // capture and replay (else plain stream launches)
   int gm_chunk = 32;            // Arnoldi steps between two reads of the GMRES headers
+  int gm_op = 0;                // operator of GMRES: 0 the Jacobian action of Algorithm 4,
+                                // 1 F'_eps(x) of the whole system (monolithic Newton)
   hipStream_t cap = nullptr;    // private stream, only ever in capture mode
   uint64_t gsig = 0;
   std::map<GraphKey, hipGraphExec_t> gcache;
@@ -440,7 +442,7 @@ uint64_t launch_signature(const rsp_context* ctx) {
   val(ctx->yd), val(ctx->f), val(ctx->x);
   const rsp_options& o = ctx->opts;
   val(o.tol_inner), val(o.sigma), val(o.alpha_min), val(o.gmres_restart), val(o.max_inner);
-  val(o.precision), val(ctx->fp32), val(ctx->nref);
+  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op);
   return h;
 }
 
@@ -731,6 +733,23 @@ void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double
                         ctx->w.g, st);
 }
 
+// The operator of GMRES on the instances of `set` (items I): the Jacobian action of
+// Algorithm 4, or (gm_op 1) F'_eps(x) of the whole system with each instance's current
+// smoothing.  skip_done: instances whose GMRES has stopped are skipped.
+void gm_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const std::vector<Inst*>& set,
+              const double* d, double* out, hipStream_t st, bool skip_done, int step = -1) {
+  if (ctx->gm_op == 0) {
+    jac_apply(ctx, I, sw, d, out, st, step);
+    return;
+  }
+  double L = 0;
+  for (const Inst* in : set) L += 2.0 * in->n;
+  Timed t(ctx, KID_GJAC, st, 14.0 * L, 24.0 * L, step);
+  for (const Inst* in : set)
+    rsp::launch_global_jac_apply(ctx->w.prob, ctx->hprob[in->slot], in->slot, skip_done ? ctx->w.gst : nullptr,
+                                 ctx->x, d, out, st);
+}
+
 // After the headers of a GMRES chunk are read: Arnoldi step q did work for the
 // instances whose step count now exceeds q (a stopped instance's kernels return at
 // once).  The timed launches of the chunk are re-priced by those instances, and
@@ -759,6 +778,9 @@ void settle_gmres_timing(rsp_context* ctx, const std::vector<Inst*>& cyc) {
       const SubWork sw = sub_work(ctx, act, false);
       p.flops = apply_flops(ctx, sw);
       p.bytes = apply_bytes(ctx, sw);
+    } else if (p.kid == KID_GJAC) {
+      p.flops = 14.0 * L;
+      p.bytes = 24.0 * L;
     } else {
       p.flops = ortho_flops(L, p.step);
       p.bytes = ortho_bytes(L, p.step);
@@ -812,7 +834,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
       RSPCHK(launch_seq(ctx, GraphKey{SEQ_ARNOLDI, lslot, I.count, B.count, j0 * 1024 + chunk}, st,
                         [&](hipStream_t s) {
                           for (int q = j0; q < j0 + chunk; ++q) {
-                            jac_apply(ctx, I, sw, w.V + (size_t)q * ldv, w.w, s, q);
+                            gm_apply(ctx, I, sw, cyc, w.V + (size_t)q * ldv, w.w, s, true, q);
                             Timed tm(ctx, KID_GMRES_ORTHO, s, ortho_flops(L, q), ortho_bytes(L, q), q);
                             const int mode = q == 0 ? 0 : q == j0 ? 2 : 1;
                             rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, mode, s);
@@ -838,7 +860,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     lslot = kLCyc;
     const GmBatch Br = gm_of(ctx, w.ilist[kLCyc], (int)next.size());
     const Items Ir = items_of(ctx, w.list[kLCyc], (int)ctx->hlist[kLCyc].size());
-    jac_apply(ctx, Ir, sub_work(ctx, next, false), w.dx, w.w, st);
+    gm_apply(ctx, Ir, sub_work(ctx, next, false), next, w.dx, w.w, st, false);
     rsp::launch_gm_residual(Br, w.b, w.w, w.r, st);
     rsp::launch_gm_sumsq(Br, w.r, w.p1, st);
     rsp::launch_gm_start(Br, w.V, w.r, w.p1, 0, st);
@@ -1128,9 +1150,11 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
   return 0;
 }
 
-// Newton_RAS,eps (Section 4.1) for one placed instance: Algorithm 1 on the whole
-// system F_eps(x) = 0, each Newton system F'_eps(x^k) d = -F_eps(x^k) solved by GMRES
-// preconditioned from the left with one-level RAS, M^{-1} = sum_i P~_i J_i^{-1} R_i,
+// The monolithic methods of Section 4.1 for one placed instance: Algorithm 1 on the
+// whole system F_eps(x) = 0, each Newton system F'_eps(x^k) d = -F_eps(x^k) solved by
+// GMRES.  precond false (Newton_eps): GMRES on F'_eps(x^k) itself.  precond true
+// (Newton_RAS,eps): GMRES preconditioned from the left with one-level RAS,
+// M^{-1} = sum_i P~_i J_i^{-1} R_i,
 // J_i = R_i F'_eps(x^k) P_i.  The local Jacobians are factored at R_i x^k with the
 // current smoothing.  Because the spatial coupling of F' is the Laplacian only,
 //   M^{-1} F'(x) d = d + sum_i P~_i J_i^{-1} B_i d,  B_i d = R_i diag(A, A)(I - P_i R_i) d,
@@ -1138,7 +1162,7 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
 // on that action with right-hand side M^{-1} F, and its solution is the Newton direction.
 // Backtracking on ||F_eps_k||, eps_{k+1} = max(gamma eps_k, eps_min); the loop also
 // runs while eps_k > eps_min, at most max_outer + 1 steps.
-int ras_newton(rsp_context* ctx, Inst* in, hipStream_t st) {
+int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) {
   const rsp_options& o = ctx->opts;
   Work& w = ctx->w;
   const int M = ctx->geo.M;
@@ -1170,32 +1194,39 @@ int ras_newton(rsp_context* ctx, Inst* in, hipStream_t st) {
   int k = 0;
   while ((!(Fn <= in->thr) || eps > in->prob.eps_min) && k <= o.max_outer) {
     auto t = Clock::now();
-    // local Jacobians at x^k with smoothing eps_k
+    // the smoothing of this step, read by the factor and the whole-system Jacobian
     P.eps_start = eps;
     HIPCHK(hipMemcpyAsync(w.prob + in->slot, &P, sizeof(DevProblem), hipMemcpyHostToDevice, st));
-    {
-      Timed tm(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
-      rsp::launch_restrict_halo(I, ctx->x, w.tilex, st);
+    if (precond) {
+      // local Jacobians at x^k with smoothing eps_k
+      {
+        Timed tm(ctx, KID_RESTRICT, st, 0, all.halo_by * 2);
+        rsp::launch_restrict_halo(I, ctx->x, w.tilex, st);
+      }
+      {
+        Timed tm(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
+        rsp::launch_factor(I, M, w.tilex, nullptr, nullptr, -1.0, nullptr, 0.0, w.fac, ctx->fp32, w.g,
+                           w.fallback, w.counter, st);
+      }
+      // w.F <- -M^{-1} F_eps(x^k): GMRES then solves (action) d = M^{-1} F
+      {
+        Timed tm(ctx, KID_PRECOND, st, all.solve_fl, all.solve_by + 2 * all.tile_by + 16.0 * L);
+        rsp::launch_restrict(I, w.F, w.t1, st);
+        rsp::launch_block_solve(I, M, w.fac, ctx->fp32, w.t1, w.t2, st);
+        rsp::launch_prolong(I, w.t2, nullptr, w.w, st);
+        rsp::launch_gm_axpy(B, -1.0, w.w, w.F, 0, st);
+      }
+      HIPCHK(hipGetLastError());
+      in->n_factor += in->part.S;
+      in->flops += all.factor_fl + all.solve_fl;
     }
-    {
-      Timed tm(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
-      rsp::launch_factor(I, M, w.tilex, nullptr, nullptr, -1.0, nullptr, 0.0, w.fac, ctx->fp32, w.g,
-                         w.fallback, w.counter, st);
-    }
-    // w.F <- -M^{-1} F_eps(x^k): GMRES then solves (action) d = M^{-1} F
-    {
-      Timed tm(ctx, KID_PRECOND, st, all.solve_fl, all.solve_by + 2 * all.tile_by + 16.0 * L);
-      rsp::launch_restrict(I, w.F, w.t1, st);
-      rsp::launch_block_solve(I, M, w.fac, ctx->fp32, w.t1, w.t2, st);
-      rsp::launch_prolong(I, w.t2, nullptr, w.w, st);
-      rsp::launch_gm_axpy(B, -1.0, w.w, w.F, 0, st);
-    }
-    HIPCHK(hipGetLastError());
-    in->n_factor += in->part.S;
-    in->flops += all.factor_fl + all.solve_fl;
+    // (no preconditioner: w.F holds F_eps(x^k) and GMRES solves F'(x^k) d = -F directly)
     in->ms_eval += ms_since(t);
     t = Clock::now();
-    RSPCHK(run_gmres(ctx, one, st));
+    ctx->gm_op = precond ? 0 : 1;
+    const int gr = run_gmres(ctx, one, st);
+    ctx->gm_op = 0;
+    RSPCHK(gr);
     in->ms_gmres += ms_since(t);
     // relaxed backtracking: alpha = 1, 1/2, ... until ||F_eps(x + alpha d)|| <= sigma ||F_eps(x)||
     double alpha = 1.0, rt = 0;
@@ -1484,7 +1515,25 @@ int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_op
   std::vector<Inst*> live{&insts[0]};
   RSPCHK(engine_place(ctx, *opts, live, stream));
   insts[0].t0 = rsp::Clock::now();
-  RSPCHK(rsp::ras_newton(ctx, &insts[0], stream));
+  RSPCHK(rsp::monolithic_newton(ctx, &insts[0], true, stream));
+  if (hist) *hist = insts[0].hist;
+  RSPCHK(resolve_events(ctx));
+  return insts[0].status;
+}
+
+int rsp_solve_newton(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts, const double* yd,
+                     const double* f, const double* y0, const double* p0, double* y, double* p, double* u,
+                     rsp_history* hist, hipStream_t stream) {
+  if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
+  RSPCHK(rsp::validate_options(opts));
+  if (!prob) return fail(RSP_EINVAL, "problem is NULL");
+  ctx->ready = false;
+  std::vector<Inst> insts;
+  RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
+  std::vector<Inst*> live{&insts[0]};
+  RSPCHK(engine_place(ctx, *opts, live, stream));
+  insts[0].t0 = rsp::Clock::now();
+  RSPCHK(rsp::monolithic_newton(ctx, &insts[0], false, stream));
   if (hist) *hist = insts[0].hist;
   RSPCHK(resolve_events(ctx));
   return insts[0].status;

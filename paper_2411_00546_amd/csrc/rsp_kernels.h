@@ -57,6 +57,11 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
                             const double* x, double eps, double* out, hipStream_t st);
 void launch_control(const DevProblem& P, const double* p, double eps, double* u, hipStream_t st);
+// out = F'_eps(x) d on the whole grid of instance `inst` (batch vectors; eps is the
+// instance's eps_start in prob, the device table; P its host copy, for the grid size).
+// Nothing is done when gst != nullptr and the instance's GMRES has stopped.
+void launch_global_jac_apply(const DevProblem* prob, const DevProblem& P, int inst, const GmState* gst,
+                             const double* x, const double* d, double* out, hipStream_t st);
 
 // Device-resident GMRES over the instances of B (kernels_gmres.hip); vectors are the
 // batch's concatenated global vectors, V the concatenated Krylov bases.

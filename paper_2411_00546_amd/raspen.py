@@ -120,6 +120,8 @@ SIGNATURES = [
                        ctypes.POINTER(rsp_history), _P]),
     ("rsp_solve_newton_ras", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                                   ctypes.POINTER(rsp_history), _P]),
+    ("rsp_solve_newton", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
+                              ctypes.POINTER(rsp_history), _P]),
     ("rsp_solve_batch", _I, [_P, _I, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(rsp_history), _P]),
     ("rsp_batch_workspace_bytes", ctypes.c_size_t, [_I, _PROB, _OPTS]),
@@ -288,6 +290,15 @@ def rsp_solve_newton_ras(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):
     st = _check(load().rsp_solve_newton_ras(ctx, ctypes.byref(prob), ctypes.byref(opts), _ptr(yd),
                                             _ptr(f, True), _ptr(y0, True), _ptr(p0, True), _ptr(y),
                                             _ptr(p), _ptr(u), ctypes.byref(h), _stream(stream)))
+    return st, h.as_dict()
+
+
+def rsp_solve_newton(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):
+    """Newton_eps, unpreconditioned GMRES (rsp_solve_newton).  Returns (status, history dict)."""
+    h = rsp_history()
+    st = _check(load().rsp_solve_newton(ctx, ctypes.byref(prob), ctypes.byref(opts), _ptr(yd),
+                                        _ptr(f, True), _ptr(y0, True), _ptr(p0, True), _ptr(y),
+                                        _ptr(p), _ptr(u), ctypes.byref(h), _stream(stream)))
     return st, h.as_dict()
 
 

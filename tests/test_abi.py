@@ -106,7 +106,7 @@ def test_batch_workspace_bytes(R):
 
 def test_server_and_batch_entry_points_are_declared():
     names = declared_functions()
-    for must in ["rsp_solve_batch", "rsp_solve_newton_ras", "rsp_batch_workspace_bytes", "rsp_server_create",
+    for must in ["rsp_solve_batch", "rsp_solve_newton_ras", "rsp_solve_newton", "rsp_batch_workspace_bytes", "rsp_server_create",
                  "rsp_server_submit",
                  "rsp_server_poll", "rsp_server_wait", "rsp_server_stats", "rsp_server_destroy"]:
         assert must in names

@@ -127,3 +127,28 @@ def test_newton_ras_rejects_bad_input(R):
                                    None, None, y, p, u)
     finally:
         R.rsp_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("name,cont", [("rect23x17", 0), ("rect23x17", 1), ("one_sub", 0)])
+def test_newton_unpreconditioned_matches_oracle(R, name, cont):
+    """Newton_eps (rsp_solve_newton): GMRES on the whole-system Jacobian, run to a tight
+    tolerance; the same steps, backtracks and answer as the oracle."""
+    import torch
+    prob = problem(name, synth.PHI_EXP, 3e-2)
+    yd, f = prob.inputs()
+    opts = synth.Options(continuation=cont, max_gmres=3000, **TIGHT)
+    y, p, u = (dev(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+    ctx = R.rsp_context_create(0)
+    try:
+        st, h = R.rsp_solve_newton(ctx, R.make_problem(prob), R.make_options(opts), dev(yd), dev(f), None,
+                                   None, y, p, u)
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+    x = np.concatenate([host(y).reshape(-1), host(p).reshape(-1)])
+    ref = NewtonRas(prob, opts, yd, f, precond=False).solve()
+    assert st == 0 and ref["status"] == 0
+    assert h["outer"] == ref["iterations"] and sum(h["backtracks"]) == ref["backtracks"]
+    assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
+    # GMRES products per Newton system: within a few of the oracle's (CGS2 vs MGS)
+    assert all(abs(a - b) <= max(2, 0.05 * b) for a, b in zip(h["gmres_its"], ref["gmres_its"]))
