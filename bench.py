@@ -445,7 +445,7 @@ def main():
     ap.add_argument("--method", default="raspen", choices=["raspen", "newton_ras", "newton"],
                     help="plain/small/precision workloads: RASPEN (Algorithm 2, the default), the "
                          "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras) "
-                         "or the unpreconditioned one (rsp_solve_newton)
+                         "or the unpreconditioned one (rsp_solve_newton)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0, "

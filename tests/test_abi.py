@@ -147,3 +147,23 @@ def test_struct_layouts_match_the_header(R, tmp_path):
         assert int(out[name]) == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert int(out[name + "." + field]) == getattr(cls, field).offset, (name, field)
+
+
+def test_bench_and_entry_scripts_parse():
+    """bench.py and __graft_entry__.py compile, and bench.py's argument parser runs
+    (no GPU needed: --help exits before anything is loaded)."""
+    import os
+    import py_compile
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for f in ("bench.py", "__graft_entry__.py"):
+        py_compile.compile(os.path.join(root, f), doraise=True, cfile=os.devnull)
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    for flag in ("--method", "--time-every", "--workload", "--gpus", "--steps", "--warmup"):
+        assert flag in r.stdout
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
