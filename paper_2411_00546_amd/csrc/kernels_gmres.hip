@@ -255,6 +255,34 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
 // FP64: its sign and size are rounding residue (on the order of 1e-16 |A v|^2).
 constexpr double kGmLucky = 1e-12;
 
+// The two reductions of an Arnoldi step gathered in one pass: ha[i] = sum over blocks of
+// pa[i][b] and hb[i] of pb[i][b], i < nv.  Thread (v, q), v < 2 nv (v < nv: pa), adds
+// blocks q, q + Q, ... (Q = kT / (2 nv)) with independent loads, then thread v adds
+// its Q segment sums in order: every block, the same fixed order for a given nv.
+// The loads of both arrays are in flight together.
+__device__ __forceinline__ void gather_pair(const double* __restrict__ pa, const double* __restrict__ pb, int nv,
+                                            double* ha, double* hb) {
+  __shared__ double seg[kT];
+  const int t = threadIdx.x;
+  const int Q = kT / (2 * nv);
+  if (t < 2 * nv * Q) {
+    const int v = t / Q, q = t - v * Q;
+    const double* src = v < nv ? pa : pb;
+    const int i = v < nv ? v : v - nv;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int b = q; b < kGmBlocks; b += Q) acc += src[part_at(i, b)];
+    seg[t] = acc;
+  }
+  __syncthreads();
+  if (t < 2 * nv) {
+    double acc = 0.0;
+    for (int q = 0; q < Q; ++q) acc += seg[t * Q + q];
+    (t < nv ? ha : hb)[t < nv ? t : t - nv] = acc;
+  }
+  __syncthreads();
+}
+
 // Second pass of u_j against V_0 .. V_{j-1} from the partial sums a, b (p1, j + 1
 // values): nu and the finished column j - 1 (its first pass plus a, subdiagonal nu),
 // into colv[0 .. j], nu and the breakdown flag into out[0], out[1] (1.0: lucky
@@ -325,7 +353,8 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     ue = Vj[e0];
     ze = z[e0];
   }
-  gather_partials(p2 + g.i * kPart, j + 1, hc);
+  // a, b (p1) and c, d (p2) of this step, in one gather
+  gather_pair(p1 + g.i * kPart, p2 + g.i * kPart, j + 1, ha, hc);
   if (j == 0) {
     if (t == 0) {
       scal[0] = 1.0;
@@ -335,7 +364,6 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     }
     __syncthreads();
   } else {
-    gather_partials(p1 + g.i * kPart, j + 1, ha);
     second_pass_column(hz, m, j, ha, mode, colv, scal);
     if (t == 0) {
       double ac = 0.0;
@@ -412,7 +440,8 @@ __global__ __launch_bounds__(kT) void k_gm_finish(GmBatch B, const double* __res
   GmHess* hz = B.hs + g.i;
   const int m = B.m;
   const int t = threadIdx.x;
-  gather_partials(p1 + g.i * kPart, j + 1, ha);
+  // a, b in the order of the step kernel's gather (its second array is not used here)
+  gather_pair(p1 + g.i * kPart, p1 + g.i * kPart, j + 1, ha, colv);
   second_pass_column(hz, m, j, ha, 1, colv, nu);
   if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
   if (t < j) hz->H[t * m + j - 1] = colv[t];

@@ -75,7 +75,12 @@ def test_newton_ras_matches_oracle(R, name, phi, mu, cont):
     ref = NewtonRas(prob, opts, yd, f).solve()
     assert st == 0 and ref["status"] == 0
     assert h["outer"] == ref["iterations"]
-    assert sum(h["backtracks"]) == ref["backtracks"]
+    # the loop also runs while eps_k > eps_min; steps taken once |F| is at the rounding
+    # floor decide their backtracking by rounding noise, the others exactly
+    floor = sum(1 for v in h["norm"][:-1] if v < 1e-9)
+    assert abs(sum(h["backtracks"]) - ref["backtracks"]) <= floor
+    if floor == 0:
+        assert sum(h["backtracks"]) == ref["backtracks"]
     scale = np.abs(ref["x"]).max()
     assert np.abs(x - ref["x"]).max() <= 1e-10 * scale
     assert np.abs(u - ref["u"]).max() <= 1e-10 * max(np.abs(ref["u"]).max(), 1.0)
@@ -148,7 +153,9 @@ def test_newton_unpreconditioned_matches_oracle(R, name, cont):
     x = np.concatenate([host(y).reshape(-1), host(p).reshape(-1)])
     ref = NewtonRas(prob, opts, yd, f, precond=False).solve()
     assert st == 0 and ref["status"] == 0
-    assert h["outer"] == ref["iterations"] and sum(h["backtracks"]) == ref["backtracks"]
+    assert h["outer"] == ref["iterations"]
+    floor = sum(1 for v in h["norm"][:-1] if v < 1e-9)   # steps at the rounding floor
+    assert abs(sum(h["backtracks"]) - ref["backtracks"]) <= floor
     assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
     # GMRES products per Newton system: within a few of the oracle's (CGS2 vs MGS)
     assert all(abs(a - b) <= max(2, 0.05 * b) for a, b in zip(h["gmres_its"], ref["gmres_its"]))
