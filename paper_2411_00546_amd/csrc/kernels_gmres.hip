@@ -216,11 +216,20 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
   double aa[NB], cc[NB], bb = 0.0, dd = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) aa[i] = cc[i] = 0.0;
-  for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
-    double v[NB];
+  // two elements per pass (up to 32 basis vectors: the registers of both), the loads of
+  // both in flight together; a second element past the chunk reads the first again and
+  // counts 0
+  constexpr int EP = NB <= 32 ? 2 : 1;
+  for (size_t e = lo + threadIdx.x; e < hi; e += EP * kT) {
+    const bool two = EP == 2 && e + kT < hi;
+    const size_t e2 = two ? e + kT : e;
+    double v[NB], v2[EP == 2 ? NB : 1];
     if (j > 0) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+      for (int i = 0; i < NB; ++i) {
+        v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+        if constexpr (EP == 2) v2[i] = V[(size_t)min(i, j - 1) * B.ldv + e2];
+      }
     }
     const double ue = u[e];
     const double ze = withz ? z[e] : 0.0;
@@ -233,6 +242,19 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
     }
     bb = fma(ue, ue, bb);
     dd = fma(ue, ze, dd);
+    if constexpr (EP == 2) {
+      const double ur2 = u[e2], zr2 = withz ? z[e2] : 0.0;
+      const double ue2 = two ? ur2 : 0.0, ze2 = two ? zr2 : 0.0;
+      if (j > 0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          aa[i] = fma(v2[i], i < j ? ue2 : 0.0, aa[i]);
+          cc[i] = fma(v2[i], i < j ? ze2 : 0.0, cc[i]);
+        }
+      }
+      bb = fma(ue2, ue2, bb);
+      dd = fma(ue2, ze2, dd);
+    }
   }
   // slot j carries b (d)
   double A[NB + 1], C[NB + 1];
@@ -332,7 +354,8 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   const int m = B.m;
   const int t = threadIdx.x;
   // loads that do not depend on the partial sums go out first: the Hessenberg block
-  // for t = H a, and the first element of this block's chunk
+  // for t = H a, and the first two elements of this thread (the second one up to 32
+  // basis vectors: the registers of both)
   for (int q = t; q < (j + 1) * j; q += kT) {
     const int r = q / j, i = q - r * j;
     hl[q] = (i < j - 1 && r <= i + 1) ? hz->Hr[r * m + i] : 0.0;
@@ -343,8 +366,10 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   double* Vn = V + (size_t)(j + 1) * B.ldv;
   size_t lo, hi;
   chunk_of(g.L, lo, hi);
-  const size_t e0 = lo + threadIdx.x;
+  constexpr int EP = NB <= 32 ? 2 : 1;
+  const size_t e0 = lo + threadIdx.x, e1 = e0 + kT;
   double v[NB], ue = 0.0, ze = 0.0;
+  double v1[EP == 2 ? NB : 1], ue1 = 0.0, ze1 = 0.0;
   if (e0 < hi) {
     if (j > 0) {
 #pragma unroll
@@ -352,6 +377,16 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     }
     ue = Vj[e0];
     ze = z[e0];
+  }
+  if constexpr (EP == 2) {
+    if (e1 < hi) {
+      if (j > 0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) v1[i] = V[(size_t)min(i, j - 1) * B.ldv + e1];
+      }
+      ue1 = Vj[e1];
+      ze1 = z[e1];
+    }
   }
   // a, b (p1) and c, d (p2) of this step, in one gather
   gather_pair(p1 + g.i * kPart, p2 + g.i * kPart, j + 1, ha, hc);
@@ -397,27 +432,54 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     sc[i] = i < j ? sv[i] : 0.0;
   }
   const double sj = sv[j];
-  for (size_t e = e0; e < hi; e += kT) {
-    if (e != e0) {
-      if (j > 0) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
-      }
-      ue = Vj[e];
-      ze = z[e];
-    }
-    double vj = ue, un = ze;
+  // v_j over u_j and u_{j+1} at element e from the basis values vv, u_j and z there
+  auto update = [&](size_t e, const double (&vv)[NB], double uu, double zz) {
+    double vj = uu, un = zz;
     if (j > 0) {
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        vj = fma(-a[i], v[i], vj);
-        un = fma(-sc[i], v[i], un);
+        vj = fma(-a[i], vv[i], vj);
+        un = fma(-sc[i], vv[i], un);
       }
       vj *= inv;
       Vj[e] = vj;
     }
     un = fma(-sj, vj, un) * inv;
     Vn[e] = un;
+  };
+  if constexpr (EP == 2) {
+    if (e0 < hi) update(e0, v, ue, ze);
+    if (e1 < hi) update(e1, v1, ue1, ze1);
+    for (size_t e = e1 + kT; e < hi; e += kT) {
+      if (j > 0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+      }
+      update(e, v, Vj[e], z[e]);
+    }
+  } else {
+    for (size_t e = e0; e < hi; e += kT) {
+      if (e != e0) {
+        if (j > 0) {
+#pragma unroll
+          for (int i = 0; i < NB; ++i) v[i] = V[(size_t)min(i, j - 1) * B.ldv + e];
+        }
+        ue = Vj[e];
+        ze = z[e];
+      }
+      double vj = ue, un = ze;
+      if (j > 0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          vj = fma(-a[i], v[i], vj);
+          un = fma(-sc[i], v[i], un);
+        }
+        vj *= inv;
+        Vj[e] = vj;
+      }
+      un = fma(-sj, vj, un) * inv;
+      Vn[e] = un;
+    }
   }
   if (blockIdx.x != 0) return;
   if (t <= j) hz->hf[j & 1][t] = hv[t];
