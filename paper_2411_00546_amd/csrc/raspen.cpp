@@ -865,14 +865,10 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     rsp::launch_gm_sumsq(Br, w.r, w.p1, st);
     rsp::launch_gm_start(Br, w.V, w.r, w.p1, 0, st);
     HIPCHK(hipGetLastError());
-    RSPCHK(read_gm_headers(ctx, st));
-    cyc.clear();
-    for (Inst* in : next) {
-      in->restarts += 1;
-      if (!ctx->hgm[in->slot].done) cyc.push_back(in);
-    }
-    if (cyc.empty()) break;
-    if (cyc.size() != next.size()) RSPCHK(upload_lists(ctx, kLCyc, cyc, st));
+    // an instance whose restart residual already meets the tolerance is stopped by
+    // k_gm_start on the device, and the chunk's kernels skip it: no read-back here
+    for (Inst* in : next) in->restarts += 1;
+    cyc = next;
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
