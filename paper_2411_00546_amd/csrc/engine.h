@@ -60,7 +60,8 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
 // of F (Algorithm 3; continuation as the options say), the stopping test, and for
 // those that go on GMRES on the Newton system (Algorithm 4 products) and the
 // update.  Instances that stop get their outputs and history and are marked
-// finished; the stream is synchronised when this returns.
+// finished (their outputs are complete on return); the update of the others may
+// still be running on the stream.
 int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st);
 
 }  // namespace rsp

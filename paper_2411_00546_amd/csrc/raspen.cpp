@@ -315,6 +315,7 @@ struct rsp_context {
   // staged through an extra copy kernel and a host copy)
   void* pin = nullptr;
   size_t pin_cap = 0;
+  hipEvent_t wait_ev = nullptr;   // completion of the work before a read-back
   std::vector<double> hnorm;
   std::vector<int> hlist[kLists], hilist[kLists];
   // the instance bound by rsp_setup / rsp_solve for the single-problem calls
@@ -341,6 +342,19 @@ struct rsp_context {
 
 namespace {
 
+// Waits until the work enqueued on `st` so far has completed, polling an event: a
+// read-back decides the next launches, and a polling thread resumes sooner than one
+// that blocks in hipStreamSynchronize.
+int wait_stream(rsp_context* ctx, hipStream_t st) {
+  if (!ctx->wait_ev) HIPCHK(hipEventCreateWithFlags(&ctx->wait_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ctx->wait_ev, st));
+  for (;;) {
+    const hipError_t e = hipEventQuery(ctx->wait_ev);
+    if (e == hipSuccess) return 0;
+    if (e != hipErrorNotReady) return fail(RSP_EHIP, "waiting for the stream: %s", hipGetErrorString(e));
+  }
+}
+
 // Copies n bytes of device memory to host memory `dst` through the pinned staging
 // buffer and waits for them (every read-back of the solver goes through here).
 int read_back(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_t st) {
@@ -355,7 +369,7 @@ int read_back(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_
     ctx->pin_cap = cap;
   }
   HIPCHK(hipMemcpyAsync(ctx->pin, src, n, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  RSPCHK(wait_stream(ctx, st));
   std::memcpy(dst, ctx->pin, n);
   return 0;
 }
@@ -871,7 +885,6 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     cyc = next;
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
   for (Inst* in : go) {
     const GmState& h = ctx->hgm[in->slot];
     in->gm_used = h.used;
@@ -1136,7 +1149,6 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
     const GmBatch B = gm_of(ctx, ctx->w.ilist[kLGo], (int)go.size());
     rsp::launch_gm_axpy(B, 1.0, ctx->w.dx, ctx->x, 1, st);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
     dt = ms_since(t);
     for (Inst* in : go) {
       in->ms_gmres += dt;
@@ -1383,6 +1395,7 @@ int rsp_context_destroy(rsp_context* ctx) {
     if (m) (void)hipFree(m);
   if (ctx->wmem) (void)hipFree(ctx->wmem);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
   delete ctx;
   return 0;
 }
