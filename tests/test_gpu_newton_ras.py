@@ -159,3 +159,40 @@ def test_newton_unpreconditioned_matches_oracle(R, name, cont):
     assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
     # GMRES products per Newton system: within a few of the oracle's (CGS2 vs MGS)
     assert all(abs(a - b) <= max(2, 0.05 * b) for a, b in zip(h["gmres_its"], ref["gmres_its"]))
+
+
+def test_methods_on_one_context_with_graphs_equal_direct_launches(R):
+    """The GMRES operator is part of the captured graphs' signature: RASPEN, Newton_RAS,eps
+    and Newton_eps, one after the other on one context with graphs on (Arnoldi chunks of
+    8), give bitwise the results of direct launches on fresh contexts."""
+    import torch
+    prob = problem("rect23x17", synth.PHI_EXP, 3e-2)
+    yd, f = prob.inputs()
+    opts = synth.Options(max_gmres=3000, **TIGHT)
+    P, O = R.make_problem(prob), R.make_options(opts)
+    methods = [("raspen", R.rsp_solve), ("newton_ras", R.rsp_solve_newton_ras), ("newton", R.rsp_solve_newton),
+               ("newton_ras", R.rsp_solve_newton_ras)]
+
+    def run(fn, ctx):
+        y, p, u = (dev(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+        st, h = fn(ctx, P, O, dev(yd), dev(f), None, None, y, p, u)
+        torch.cuda.synchronize()
+        return st, np.concatenate([host(y).reshape(-1), host(p).reshape(-1)])
+
+    ref = {}
+    for name, fn in methods[:3]:
+        ctx = R.rsp_context_create(0)
+        try:
+            R.rsp_set_tuning(ctx, graphs=0, gm_chunk=8)
+            ref[name] = run(fn, ctx)
+        finally:
+            R.rsp_context_destroy(ctx)
+    ctx = R.rsp_context_create(0)
+    try:
+        R.rsp_set_tuning(ctx, graphs=1, gm_chunk=8)
+        for name, fn in methods:
+            st, x = run(fn, ctx)
+            assert st == 0 and ref[name][0] == 0, name
+            assert np.array_equal(x, ref[name][1]), (name, np.abs(x - ref[name][1]).max())
+    finally:
+        R.rsp_context_destroy(ctx)
