@@ -562,18 +562,28 @@ __global__ __launch_bounds__(kT) void k_gm_start(GmBatch B, double* __restrict__
 __global__ __launch_bounds__(kT) void k_gm_update_x(GmBatch B, const double* __restrict__ V,
                                                     double* __restrict__ x) {
   __shared__ double ys[kGmMaxVec];
+  __shared__ double rs[kGmMaxRestart * kGmMaxRestart];   // the k x k triangle R
   const Seg g = seg_of(B);
   const size_t L = g.L;
   V += g.off;
   x += g.off;
   const GmHess* hz = B.hs + g.i;
   const int k = B.st[g.i].steps;
-  if (threadIdx.x == 0) {
+  // R and g to LDS by all threads (independent loads), then the substitution from LDS
+  {
     const int m = B.m;
+    for (int q = threadIdx.x; q < k * k; q += kT) {
+      const int i = q / k, l = q - i * k;
+      rs[q] = l >= i ? hz->H[i * m + l] : 0.0;
+    }
+    if ((int)threadIdx.x < k) ys[threadIdx.x] = hz->g[threadIdx.x];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     for (int i = k - 1; i >= 0; --i) {
-      double s = hz->g[i];
-      for (int l = i + 1; l < k; ++l) s -= hz->H[i * m + l] * ys[l];
-      ys[i] = s / hz->H[i * m + i];
+      double s = ys[i];
+      for (int l = i + 1; l < k; ++l) s -= rs[i * k + l] * ys[l];
+      ys[i] = s / rs[i * k + i];
     }
   }
   __syncthreads();
