@@ -210,8 +210,9 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
    with RSP_FP32_REFINED); GMRES stops at rtol relative to |M^{-1} F|.  Backtracking
    as in Algorithm 1 (sigma, alpha_min); at most max_outer + 1 Newton steps.
    Arguments, ownership, stream ordering and status codes as rsp_solve; tol_inner,
-   max_inner and max_refine are not used.  History: norm[k] = |F_eps_k(x^k)|_2,
-   gmres_its[k], gmres_rel[k], backtracks[k]; inner iteration fields are 0. */
+   max_inner and max_refine are not used.  History: outer = Newton steps,
+   norm[k] = |F_eps_k(x^k)|_2, gmres_its[k], gmres_rel[k], backtracks[k]; the inner
+   iteration fields and newton_iterations (local solves) are 0. */
 int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
                          const double* yd, const double* f, const double* y0, const double* p0,
                          double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);

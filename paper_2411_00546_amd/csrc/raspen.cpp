@@ -1252,7 +1252,6 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
         break;
       }
     }
-    in->n_newton += 1;
     if (fail_ls) {
       in->status = std::max(in->status, (int)RSP_LINESEARCH_FAIL);
       if (k + 1 <= RSP_HIST_MAX) in->hist.backtracks[k + 1] = bt;
