@@ -153,6 +153,20 @@ def kernel_table(stats):
 TIME_EVERY = [1]   # launch sequences per timed one in the timed solves (--time-every)
 
 
+def solve_roofline(stats, fp32, ms_per_solve):
+    """Solve-level roofline: sum over the kernel classes of one solve (every class timed)
+    of max(algorithmic bytes / HBM peak, algorithmic flops / peak of the class), over the
+    measured time of a solve.  The FP32 line factorisation takes the FP32 matrix peak,
+    every other class the FP64 one."""
+    bound_s = 0.0
+    for name, v in stats.items():
+        if v["launches"] == 0:
+            continue
+        peak = (FP32_PEAK_TFLOPS if (name == "factor" and fp32) else FP64_PEAK_TFLOPS) * 1e12
+        bound_s += max(v["bytes"] / (HBM_PEAK_GBS * 1e9), v["flops"] / peak)
+    return {"bound_ms": 1e3 * bound_s, "measured_ms": ms_per_solve, "frac": 1e3 * bound_s / ms_per_solve}
+
+
 def kernel_roofline(stats, fp32):
     """Roofline object of the dominant single-pass kernel from rsp_kernel_stats output."""
     kern = {k: v for k, v in stats.items() if v["launches"] > 0}
@@ -580,7 +594,9 @@ def main():
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
                      "residual_final": hist["residual_final"], "norm": hist["norm"][-1]},
-           "fp64": cmp64, "tuning": tuning, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu}
+           "fp64": cmp64, "tuning": tuning, "roofline": roof,
+           "solve_roofline": solve_roofline(breakdown, opts.precision == 1, 1e3 * elapsed / args.steps),
+           "kernels": kernels, "cpu_baseline": cpu}
     print(json.dumps(out))
 
 
