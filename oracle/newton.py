@@ -1,7 +1,7 @@
 """Algorithm 1 of the paper: damped Newton with eps-continuation and relaxed
 backtracking line search (oracle; test infrastructure only).
 
-Readings taken where the paper leaves room (each listed in the design doc):
+Readings taken where the paper leaves room:
   * the loop also continues while eps_k > eps_min, so a continued solve always
     ends at the target smoothing;
   * backtracking halves alpha while NOT (||F(x + alpha d)|| <= sigma ||F(x)||), so

@@ -15,7 +15,7 @@ iterate that belong to the overlapping box Omega_i.
 Without the preconditioner (precond=False) this is the monolithic Newton_eps of
 Section 4.1: GMRES on F'_eps(x^k) d = -F_eps(x^k) itself.
 
-Readings taken where the paper leaves room (each listed in the design doc):
+Readings taken where the paper leaves room:
   * the preconditioner is applied from the left: GMRES solves
     M^{-1} F'(x) d = -M^{-1} F(x), and its stopping test is relative to
     ||M^{-1} F(x)||;
