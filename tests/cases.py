@@ -35,3 +35,40 @@ def mms_problem(kind, nx, ny, sx, sy, ov, eps_min=1e-6):
     f = r[:s0.n].reshape(ny, nx)              # F_1(x*) - f = r_1 with f = 0  =>  f := r_1
     yd = -r[s0.n:].reshape(ny, nx)            # F_2 = ... + y_d              =>  y_d := -r_2
     return prob, yd, f, x
+
+
+def paper_model_problem(n, sx, sy, ov, eps_min, gamma=0.2, k=5, eps_bar=1e-15):
+    """The numerical model problem of Section 5: phi(y) = kappa (y^3 + exp(kappa y)),
+    kappa = 0.1, nu = 1e-6, mu = 1, f = 0 on an n x n grid, with
+      p_bar = 1.3 mu sin(2 pi k x1) sin(2 pi k x2)                            eq. (ppp),
+      y_bar: A y + phi(y) - f + g_eps(p_bar) / nu = 0 at eps = eps_bar        eq. (pppp),
+      y_d = -A p_bar - phi'(y_bar) p_bar + y_bar                              eq. (ydpppp),
+    so (y_bar, p_bar) solves F_eps_bar = 0 (the sign of the g term as in F).  y_bar is
+    found by damped Newton on that monotone equation (A + diag phi' is SPD)."""
+    from oracle import pointwise as pw
+    prob = synth.Problem(nx=n, ny=n, phi=synth.PHI_PAPER, kappa=0.1, nu=1e-6, mu=1.0, eps0=1.0,
+                         eps_min=eps_min, gamma=gamma, sx=sx, sy=sy, overlap=ov)
+    X, Y = synth.node_coords(n, n)
+    pbar = (1.3 * prob.mu * np.sin(2 * math.pi * k * X) * np.sin(2 * math.pi * k * Y)).reshape(-1)
+    zero = np.zeros((n, n))
+    s = System(prob, zero, zero)
+    c = pw.g(pbar, prob.mu, eps_bar) / prob.nu
+    y = np.zeros(n * n)
+    G = s.A @ y + s._phi(y) + c
+    for _ in range(100):
+        r = np.linalg.norm(G)
+        if r <= 1e-9 * max(1.0, np.linalg.norm(c)):
+            break
+        d = spla.spsolve((s.A + sp.diags(s._dphi(y))).tocsc(), -G)
+        a = 1.0
+        while True:
+            yt = y + a * d
+            Gt = s.A @ yt + s._phi(yt) + c
+            if np.linalg.norm(Gt) < r or a < 1e-12:
+                break
+            a *= 0.5
+        y, G = yt, Gt
+    else:
+        raise RuntimeError("the state equation of the model problem did not converge")
+    yd = (-(s.A @ pbar) - s._dphi(y) * pbar + y).reshape(n, n)
+    return prob, yd, zero, np.concatenate([y, pbar])
