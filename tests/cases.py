@@ -72,3 +72,15 @@ def paper_model_problem(n, sx, sy, ov, eps_min, gamma=0.2, k=5, eps_bar=1e-15):
         raise RuntimeError("the state equation of the model problem did not converge")
     yd = (-(s.A @ pbar) - s._dphi(y) * pbar + y).reshape(n, n)
     return prob, yd, zero, np.concatenate([y, pbar])
+
+
+def paper_inner_tol(nx, ny, tol=1e-8):
+    """The inner tolerance of Section 5 (1e-8) in the units of F here.
+
+    F is the 5-point system with A = -Laplacian / h^2, unscaled.  The paper's tolerance
+    is read as one on the residual of the equations multiplied by the cell area hx*hy
+    (the scaling of a finite-element or h^2-scaled difference code), so it becomes
+    tol / (hx hy) here.  Taken unscaled, 1e-8 lies below what FP64 can resolve in a
+    local residual of the model problem: at N = 450 the rounding of one evaluation of
+    F on a 45 x 45 box alone is about 4e-8 (test_model_problem_local_rounding_floor)."""
+    return tol * (nx + 1) * (ny + 1)

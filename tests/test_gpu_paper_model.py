@@ -8,6 +8,10 @@ the step counts are the paper's for every eps_min.  With continuation the paper'
 is reached at eps_min = 1e-15 and at eps_min = 1; for larger eps_min our loop (which
 stops once |F| meets the tolerance and eps_k = eps_min) takes fewer steps than the
 paper reports.
+
+RASPEN and RASPEN_eps (Algorithm 2, rsp_solve) on the same problem take the paper's inner
+tolerance 1e-8 on the cell-area-scaled residual (cases.paper_inner_tol): unscaled, it is
+below the rounding floor of a local residual here.
 """
 import os
 
@@ -15,7 +19,7 @@ import numpy as np
 import pytest
 
 import synth
-from cases import paper_model_problem
+from cases import paper_inner_tol, paper_model_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -81,3 +85,38 @@ def test_newton_steps_with_continuation_at_the_ends(R, model, eps_min):
     st, h, x = solve(R, prob, yd, f, cont=0)
     assert st == 0
     assert h["outer"] == golden()[eps_min][1]
+
+
+def raspen(R, prob, yd, f, cont, precision=0):
+    import torch
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    opts = synth.Options(tol_outer=1e-10, tol_inner=paper_inner_tol(prob.nx, prob.ny), gmres_rtol=1e-10,
+                         max_gmres=1500, max_outer=60, continuation=cont, precision=precision)
+    y, p, u = (t(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+    ctx = R.rsp_context_create(0)
+    try:
+        st, h = R.rsp_solve(ctx, R.make_problem(prob), R.make_options(opts), t(yd), t(f), None, None, y, p, u)
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+    return st, h, np.concatenate([y.cpu().numpy().reshape(-1), p.cpu().numpy().reshape(-1)])
+
+
+def test_raspen_on_the_model_problem(R, model):
+    """RASPEN (continuation 1: none) and RASPEN_eps (continuation 0: in the first
+    evaluation's local solves) at eps_min = 1e-15 with the tolerances of Section 5: both
+    converge in a few outer steps (the paper reports 3 to 6 over its partitions) to the
+    constructed solution, and the continuation lowers the parallel inner iterations (the
+    per-evaluation maximum over subdomains, averaged; the paper sees about half)."""
+    prob, yd, f, xbar = model
+    prob.eps_min = 1e-15
+    runs = {cont: raspen(R, prob, yd, f, cont) for cont in (1, 0)}
+    for cont, (st, h, x) in runs.items():
+        assert st == 0, (cont, st)
+        assert h["outer"] <= 8, (cont, h["outer"])
+        assert np.abs(x - xbar).max() <= 1e-8 * np.abs(xbar).max(), cont
+    parallel = {cont: np.mean(h["inner_max"]) for cont, (_, h, _) in runs.items()}
+    assert parallel[0] < 0.8 * parallel[1], parallel
+    # FP32 line factors: the same answer within 1e-8
+    st, h, x = raspen(R, prob, yd, f, 0, precision=1)
+    assert st == 0 and np.abs(x - runs[0][2]).max() <= 1e-8 * np.abs(xbar).max()

@@ -432,3 +432,39 @@ def test_newton_gmres_equals_global_newton(cont):
     # the unpreconditioned systems take far more products than the RAS ones
     ras = NewtonRas(prob, opts, yd, f).solve()
     assert np.mean(out["gmres_its"]) > 3 * np.mean(ras["gmres_its"])
+
+
+def test_model_problem_local_rounding_floor():
+    """The model problem of Section 5 at N = 450 (|y_bar| ~ 56, nu = 1e-6): the FP64
+    rounding of one evaluation of F on a 45 x 45 box (the size of a subdomain of the
+    11 x 11 partition with overlap 2h) exceeds an unscaled inner tolerance of 1e-8, and
+    lies far below it once the equations are scaled by the cell area.  The reference
+    evaluation is the same 5-point residual in extended precision; the constructed pair
+    solves F = 0 at eps = 1e-15 to well within the unscaled floor on every box row."""
+    from cases import paper_inner_tol, paper_model_problem
+    n = 450
+    prob, yd, f, xbar = paper_model_problem(n, 11, 11, 2, 1e-15)
+    s = System(prob, yd, f)
+    r64 = s.residual(xbar, 1e-15)
+    y = xbar[:s.n].reshape(n, n).astype(np.longdouble)
+    p = xbar[s.n:].reshape(n, n).astype(np.longdouble)
+    h2 = np.longdouble(1.0) / np.longdouble((n + 1) ** 2)
+
+    def lap(v):
+        z = np.zeros((n + 2, n + 2), dtype=np.longdouble)
+        z[1:-1, 1:-1] = v
+        return (4 * z[1:-1, 1:-1] - z[:-2, 1:-1] - z[2:, 1:-1] - z[1:-1, :-2] - z[1:-1, 2:]) / h2
+
+    k = np.longdouble(prob.kappa)
+    g = pw.g(xbar[s.n:], prob.mu, 1e-15).reshape(n, n).astype(np.longdouble)
+    r1 = lap(y) + k * (y ** 3 + np.exp(k * y)) + g / np.longdouble(prob.nu)
+    r2 = lap(p) + k * (3 * y ** 2 + k * np.exp(k * y)) * p - y + yd.astype(np.longdouble)
+    box = (slice(200, 245), slice(200, 245))
+    err = np.hypot(np.linalg.norm((r64[:s.n].reshape(n, n) - r1)[box].astype(np.float64)),
+                   np.linalg.norm((r64[s.n:].reshape(n, n) - r2)[box].astype(np.float64)))
+    exact = np.hypot(np.linalg.norm(r1[box].astype(np.float64)), np.linalg.norm(r2[box].astype(np.float64)))
+    assert err > 1e-8                       # unscaled: the tolerance is below the floor
+    assert exact < 10 * err                 # x_bar is a solution to rounding level
+    tol = paper_inner_tol(n, n)
+    assert tol == pytest.approx(1e-8 * 451 ** 2)
+    assert err < 1e-3 * tol                 # scaled: six orders of magnitude of room
