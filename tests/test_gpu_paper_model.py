@@ -87,11 +87,15 @@ def test_newton_steps_with_continuation_at_the_ends(R, model, eps_min):
     assert h["outer"] == golden()[eps_min][1]
 
 
+def raspen_options(prob, cont, precision=0):
+    return synth.Options(tol_outer=1e-10, tol_inner=paper_inner_tol(prob.nx, prob.ny), gmres_rtol=1e-10,
+                         max_gmres=1500, max_outer=60, continuation=cont, precision=precision)
+
+
 def raspen(R, prob, yd, f, cont, precision=0):
     import torch
     t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
-    opts = synth.Options(tol_outer=1e-10, tol_inner=paper_inner_tol(prob.nx, prob.ny), gmres_rtol=1e-10,
-                         max_gmres=1500, max_outer=60, continuation=cont, precision=precision)
+    opts = raspen_options(prob, cont, precision)
     y, p, u = (t(np.zeros((prob.ny, prob.nx))) for _ in range(3))
     ctx = R.rsp_context_create(0)
     try:
@@ -120,3 +124,28 @@ def test_raspen_on_the_model_problem(R, model):
     # FP32 line factors: the same answer within 1e-8
     st, h, x = raspen(R, prob, yd, f, 0, precision=1)
     assert st == 0 and np.abs(x - runs[0][2]).max() <= 1e-8 * np.abs(xbar).max()
+
+
+@pytest.mark.parametrize("n,sx,sy,eps_min,cont", [(90, 3, 3, 1e-15, 0), (90, 3, 3, 1e-15, 1), (97, 4, 3, 1e-5, 0)])
+def test_raspen_matches_oracle_on_the_model_problem(R, n, sx, sy, eps_min, cont):
+    """The paper's regime (nu = 1e-6, so g(p)/nu reaches 3e5) at sizes the oracle finishes
+    in seconds, one partition ragged (97 nodes as 25 + 25 + 25 + 22 across, 33 + 33 + 31
+    down): the GPU takes the oracle's outer steps, the same local Newton iterations in
+    every evaluation (most and fewest over the subdomains), GMRES products within one,
+    and lands within 1e-10 of the oracle's answer (and of the constructed solution at
+    eps_min = 1e-15)."""
+    from oracle.schwarz import Raspen
+    prob, yd, f, xbar = paper_model_problem(n, sx, sy, 2, 1e-15)
+    prob.eps_min = eps_min
+    st, h, x = raspen(R, prob, yd, f, cont)
+    ref = Raspen(prob, raspen_options(prob, cont), yd, f).solve()
+    assert st == 0 and ref["status"] == 0
+    assert h["outer"] == ref["outer"]
+    got = [(a, b) for a, b in zip(h["inner_min"], h["inner_max"])]
+    want = [(min(r["inner"]), max(r["inner"])) for r in ref["history"]]
+    assert got == want, (got, want)
+    want_gm = [r["gmres"] for r in ref["history"][1:]]
+    assert all(abs(a - b) <= 1 for a, b in zip(h["gmres_its"], want_gm)), (h["gmres_its"], want_gm)
+    assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
+    if eps_min == 1e-15:
+        assert np.abs(x - xbar).max() <= 1e-10 * np.abs(xbar).max()
