@@ -149,3 +149,34 @@ def test_raspen_matches_oracle_on_the_model_problem(R, n, sx, sy, eps_min, cont)
     assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
     if eps_min == 1e-15:
         assert np.abs(x - xbar).max() <= 1e-10 * np.abs(xbar).max()
+
+
+@pytest.mark.parametrize("n,sx,sy,eps_min,method,cont", [(90, 3, 3, 1e-15, "newton_ras", 0),
+                                                         (90, 3, 3, 1e-15, "newton_ras", 1),
+                                                         (97, 4, 3, 1e-5, "newton_ras", 0),
+                                                         (97, 4, 3, 1e-15, "newton", 0)])
+def test_monolithic_methods_match_oracle_on_the_model_problem(R, n, sx, sy, eps_min, method, cont):
+    """Newton_RAS,eps / Newton_RAS (left RAS-preconditioned GMRES) and Newton_eps (GMRES
+    on F' itself) in the paper's regime, against the oracle: the same Newton steps and
+    backtracks, and the answer within 1e-10 (GMRES run tightly, so the steps are
+    Newton's)."""
+    import torch
+    from oracle.newton_ras import NewtonRas
+    prob, yd, f, xbar = paper_model_problem(n, sx, sy, 2, 1e-15)
+    prob.eps_min = eps_min
+    opts = synth.Options(tol_outer=1e-10, gmres_rtol=1e-12, max_gmres=4000, max_outer=60, continuation=cont)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    y, p, u = (t(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+    fn = R.rsp_solve_newton_ras if method == "newton_ras" else R.rsp_solve_newton
+    ctx = R.rsp_context_create(0)
+    try:
+        st, h = fn(ctx, R.make_problem(prob), R.make_options(opts), t(yd), t(f), None, None, y, p, u)
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+    x = np.concatenate([y.cpu().numpy().reshape(-1), p.cpu().numpy().reshape(-1)])
+    ref = NewtonRas(prob, opts, yd, f, precond=(method == "newton_ras")).solve()
+    assert st == 0 and ref["status"] == 0
+    assert h["outer"] == ref["iterations"], (h["outer"], ref["iterations"])
+    assert sum(h["backtracks"]) == ref["backtracks"], (sum(h["backtracks"]), ref["backtracks"])
+    assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
