@@ -666,7 +666,18 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       break;
     }
     block_gauss_jordan<T, M>(blk, St);
-    // the inverse also to LDS, for the fused sweep, the store and (last line) the twist
+    if constexpr (sizeof(T) == 4) {
+      // FP32: a lane holds four consecutive rows of its column, which are consecutive
+      // in the transposed layout facT[j][b][a], so the inverse goes to HBM straight
+      // from the registers (16-byte stores, padding columns included)
+      T* F = Fs + (size_t)j * M * M + (size_t)(16 * wave + (lane & 15)) * M + 4 * (lane >> 4);
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        const T v[4] = {blk[I][0], blk[I][1], blk[I][2], blk[I][3]};
+        store4<T>(F + 16 * I, v);
+      }
+    }
+    // the inverse also to LDS, for the fused sweep, the FP64 store and (last line) the twist
 #pragma unroll
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
     __syncthreads();
@@ -674,7 +685,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
       solve_line(j);
     }
-    store(j);
+    if constexpr (sizeof(T) != 4) store(j);
   }
   if (bad && t == 0) atomicExch(fallback + s, 1);
   if (!second_to_arrive(counter, s, &flag)) return;
