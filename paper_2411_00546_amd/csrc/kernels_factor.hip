@@ -184,6 +184,22 @@ template <int R>
 __device__ __forceinline__ double col_bcast(double v) {
   return __hiloint2double(col_bcast_i<R>(__double2hiint(v)), col_bcast_i<R>(__double2loint(v)));
 }
+// Exchanges between lane groups of two double registers a, b (groups = 16-lane rows):
+//   swap_lanes32: a <- (a rows 0,1; b rows 0,1), b <- (a rows 2,3; b rows 2,3);
+//   swap_lanes16: a <- (a row 0, b row 0, a row 2, b row 2), b <- (a row 1, b row 1,
+//                 a row 3, b row 3).
+__device__ __forceinline__ void swap_lanes32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap_lanes16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
 // Product and sum rounded separately (never contracted into one fused operation).
 __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
 __device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
@@ -666,18 +682,28 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       break;
     }
     block_gauss_jordan<T, M>(blk, St);
-    if constexpr (sizeof(T) == 4) {
-      // FP32: a lane holds four consecutive rows of its column, which are consecutive
-      // in the transposed layout facT[j][b][a], so the inverse goes to HBM straight
-      // from the registers (16-byte stores, padding columns included)
+    {
+      // The inverse goes to HBM straight from the registers (16-byte stores, padding
+      // columns included): lane (column b, group g = lane >> 4) writes rows 4 g .. 4 g + 3
+      // of row block I, which are consecutive in the transposed layout facT[j][b][a].
+      // FP32 lanes hold exactly those rows; FP64 lanes hold rows g + 4 r, so the four
+      // lane groups first transpose their 4 x 4 block (two 32-lane swaps, then two
+      // 16-lane swaps).
       T* F = Fs + (size_t)j * M * M + (size_t)(16 * wave + (lane & 15)) * M + 4 * (lane >> 4);
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
-        const T v[4] = {blk[I][0], blk[I][1], blk[I][2], blk[I][3]};
+        T r0 = blk[I][0], r1 = blk[I][1], r2 = blk[I][2], r3 = blk[I][3];
+        if constexpr (sizeof(T) == 8) {
+          swap_lanes32(r0, r2);
+          swap_lanes32(r1, r3);
+          swap_lanes16(r0, r1);
+          swap_lanes16(r2, r3);
+        }
+        const T v[4] = {r0, r1, r2, r3};
         store4<T>(F + 16 * I, v);
       }
     }
-    // the inverse also to LDS, for the fused sweep, the FP64 store and (last line) the twist
+    // the inverse also to LDS, for the fused sweep and (last line) the twist
 #pragma unroll
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
     __syncthreads();
@@ -685,7 +711,6 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
       solve_line(j);
     }
-    if constexpr (sizeof(T) != 4) store(j);
   }
   if (bad && t == 0) atomicExch(fallback + s, 1);
   if (!second_to_arrive(counter, s, &flag)) return;
