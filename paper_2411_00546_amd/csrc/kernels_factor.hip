@@ -19,9 +19,9 @@
 // dominant block (the usual case) is inverted by Gauss-Jordan with 16 x 16 pivot
 // blocks whose block products run on the matrix cores; partial pivoting would keep
 // its diagonal, so this is the same elimination.  The twist block adds the
-// contributions of both chains and need not be dominant: its block elimination
-// checks the exact partial-pivoting condition (every multiplier at most 1 in
-// magnitude) instead.  A subdomain where a test fails is redone by a second kernel
+// contributions of both chains and need not be dominant: when it is not, its block
+// elimination checks the exact partial-pivoting condition (every multiplier at most 1
+// in magnitude) instead.  A subdomain where a test fails is redone by a second kernel
 // with in-place Gauss-Jordan with partial pivoting in registers (rows are not moved:
 // step k pivots on row pr[k]; afterwards S^{-1}[a][b] = A[pr[a]][pinv[b]]): per step
 // the pivot is found inside the wave that holds the column, the column goes through
@@ -666,6 +666,28 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
     return __syncthreads_or(b < m && !(dia >= off)) != 0;
   };
 
+  // The inverse of line j goes to HBM straight from the registers (16-byte stores,
+  // padding columns included): lane (column b, group g = lane >> 4) writes rows
+  // 4 g .. 4 g + 3 of row block I, which are consecutive in the transposed layout
+  // facT[j][b][a].  FP32 lanes hold exactly those rows; FP64 lanes hold rows g + 4 r,
+  // so the four lane groups first transpose their 4 x 4 block (two 32-lane swaps,
+  // then two 16-lane swaps).
+  auto store_regs = [&](int j) {
+    T* F = Fs + (size_t)j * M * M + (size_t)(16 * wave + (lane & 15)) * M + 4 * (lane >> 4);
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      T r0 = blk[I][0], r1 = blk[I][1], r2 = blk[I][2], r3 = blk[I][3];
+      if constexpr (sizeof(T) == 8) {
+        swap_lanes32(r0, r2);
+        swap_lanes32(r1, r3);
+        swap_lanes16(r0, r1);
+        swap_lanes16(r2, r3);
+      }
+      const T v[4] = {r0, r1, r2, r3};
+      store4<T>(F + 16 * I, v);
+    }
+  };
+
   bool bad = false;
   double ynext = 0.0, pnext = 0.0;
   if (nlines > 0 && t < tx) state_at(j0, ynext, pnext);
@@ -682,27 +704,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
       break;
     }
     block_gauss_jordan<T, M>(blk, St);
-    {
-      // The inverse goes to HBM straight from the registers (16-byte stores, padding
-      // columns included): lane (column b, group g = lane >> 4) writes rows 4 g .. 4 g + 3
-      // of row block I, which are consecutive in the transposed layout facT[j][b][a].
-      // FP32 lanes hold exactly those rows; FP64 lanes hold rows g + 4 r, so the four
-      // lane groups first transpose their 4 x 4 block (two 32-lane swaps, then two
-      // 16-lane swaps).
-      T* F = Fs + (size_t)j * M * M + (size_t)(16 * wave + (lane & 15)) * M + 4 * (lane >> 4);
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        T r0 = blk[I][0], r1 = blk[I][1], r2 = blk[I][2], r3 = blk[I][3];
-        if constexpr (sizeof(T) == 8) {
-          swap_lanes32(r0, r2);
-          swap_lanes32(r1, r3);
-          swap_lanes16(r0, r1);
-          swap_lanes16(r2, r3);
-        }
-        const T v[4] = {r0, r1, r2, r3};
-        store4<T>(F + 16 * I, v);
-      }
-    }
+    store_regs(j);
     // the inverse also to LDS, for the fused sweep and (last line) the twist
 #pragma unroll
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
@@ -752,10 +754,21 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
     }
   }
   __syncthreads();
-  // Z_t is close to the boundary of column dominance (both neighbours' Schur terms are
-  // subtracted), so its elimination checks the partial-pivoting choice exactly instead
-  (void)build(2);
-  if (panel_gauss_jordan<T, M>(Mx, LD, Pn, &flag)) {
+  // Z_t subtracts both neighbours' Schur terms and is often close to the boundary of
+  // column dominance.  A dominant Z_t takes the register elimination of the chain
+  // lines (partial pivoting would keep its diagonal); otherwise its elimination checks
+  // the partial-pivoting choice exactly.  Each wave reads and writes only its own
+  // column block of Mx here.
+  const bool dominant = !build(2);
+  if (dominant) {
+#pragma unroll
+    for (int I = 0; I < NB; ++I) blk[I] = tile_load<T>(Mx + 16 * I * LD + 16 * wave, LD, lane);
+    block_gauss_jordan<T, M>(blk, St);
+    store_regs(tw);
+#pragma unroll
+    for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
+    __syncthreads();
+  } else if (panel_gauss_jordan<T, M>(Mx, LD, Pn, &flag)) {
     if (t == 0) atomicExch(fallback + s, 1);
     return;
   }
@@ -765,7 +778,7 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
                          (tw + 1 < ty ? gs[(size_t)(tw + 1) * M + i] : 0.0));
     solve_line(tw);
   }
-  store(tw);
+  if (!dominant) store(tw);
 }
 
 // Fallback for subdomains with a line block that is not column diagonally dominant
