@@ -84,7 +84,14 @@ typedef struct rsp_problem {
   int32_t overlap;        /* >= 0, nodes added on each side                        */
 } rsp_problem;
 
-/* Solver options (paper Section 5 gives tol 1e-10, inner tol 1e-8, sigma 1.1). */
+/* Solver options (paper Section 5 gives tol 1e-10, inner tol 1e-8, sigma 1.1).
+   Norms are Euclidean norms of the discrete vectors.  The outer test of Algorithm 2
+   measures the RASPEN residual, a sum of corrections in the units of x.  The inner
+   test measures the local residual K_i of the unscaled 5-point equations, whose
+   stencil entries are O(h^-2).  A tolerance stated for equations scaled by the cell
+   area hx hy (the inner 1e-8 of Section 5 read that way) is therefore passed as
+   tol_inner = tol / (hx hy); taken unscaled, 1e-8 can lie below the FP64 rounding
+   floor of a local residual, and the local solves then stop at max_inner. */
 typedef struct rsp_options {
   double tol_outer;       /* Algorithm 2: stop when |F(x^k)| <= max(tol, tol |F(x^0)|)  */
   double tol_inner;       /* Algorithm 1 tolerance of the local solves                 */
