@@ -46,11 +46,13 @@ extern "C" {
 #define RSP_NOT_CONVERGED 1     /* iteration limit reached (Algorithms 1 and 2 k_max) */
 #define RSP_LINESEARCH_FAIL 2   /* backtracking went below alpha_min (Algorithm 1) */
 #define RSP_GMRES_STAGNATION 3  /* not converged, and a GMRES solve hit max_gmres above its tolerance */
-#define RSP_REFINE_FALLBACK 4   /* FP32 factors + refinement did not converge */
+#define RSP_REFINE_FALLBACK 4   /* converged, but only after the instance left the FP32 line
+                                   factors for FP64 ones (rsp_options.fallback_rho) */
 #define RSP_EINVAL (-1)
 #define RSP_ENOMEM (-2)
 #define RSP_EHIP (-3)
-#define RSP_ENUMERIC (-4)
+#define RSP_ENUMERIC (-4)       /* a residual or a Newton direction is not finite: NaN or Inf
+                                   in the data, or a singular local Jacobian (zero pivot) */
 #define RSP_EAGAIN (-5)         /* rsp_server_wait: not done within the timeout */
 
 /* phi(y), Assumption 1 (phi in C^2, monotone increasing) */
@@ -59,8 +61,8 @@ extern "C" {
 #define RSP_PHI_EXP 2           /* phi = exp(y) - 1                            */
 #define RSP_PHI_PAPER 3         /* phi = kappa (y^3 + exp(kappa y)), Section 4 */
 
-/* where eps-continuation is applied (Algorithm 2 and Section 5: "only in the
-   first inner Newton iterations") */
+/* where eps-continuation is applied (Algorithm 2 with the solver settings of
+   Section 5: continuation in the local solves of the first evaluation only) */
 #define RSP_CONT_FIRST 0        /* local solves of the first evaluation only */
 #define RSP_CONT_NONE 1         /* never: every local solve at eps_min        */
 #define RSP_CONT_EVERY 2        /* every evaluation                           */
@@ -87,14 +89,17 @@ typedef struct rsp_problem {
 /* Solver options (paper Section 5 gives tol 1e-10, inner tol 1e-8, sigma 1.1).
    Norms are Euclidean norms of the discrete vectors.  The outer test of Algorithm 2
    measures the RASPEN residual, a sum of corrections in the units of x.  The inner
-   test measures the local residual K_i of the unscaled 5-point equations, whose
-   stencil entries are O(h^-2).  A tolerance stated for equations scaled by the cell
-   area hx hy (the inner 1e-8 of Section 5 read that way) is therefore passed as
-   tol_inner = tol / (hx hy); taken unscaled, 1e-8 can lie below the FP64 rounding
-   floor of a local residual, and the local solves then stop at max_inner. */
+   test of Algorithm 1, max(tol, tol |K_i(0)|), measures the local residual K_i of the
+   unscaled 5-point equations, whose stencil entries are O(h^-2).  Its two branches
+   have their own tolerances: the absolute one (tol_inner) has the units of K_i, the
+   relative one (tol_inner_rel) none.  A tolerance stated for equations scaled by the
+   cell area hx hy (the inner 1e-8 of Section 5 read that way) therefore becomes
+   tol_inner = tol / (hx hy) with tol_inner_rel = tol; taken unscaled, 1e-8 can lie
+   below the FP64 rounding floor of a local residual, and the local solves then stop
+   at max_inner. */
 typedef struct rsp_options {
   double tol_outer;       /* Algorithm 2: stop when |F(x^k)| <= max(tol, tol |F(x^0)|)  */
-  double tol_inner;       /* Algorithm 1 tolerance of the local solves                 */
+  double tol_inner;       /* Algorithm 1, absolute branch of the local stopping test    */
   double gmres_rtol;      /* GMRES: stop when |r| <= rtol |b|                          */
   double sigma;           /* >= 1, relaxed backtracking, eq. (line_search)             */
   double alpha_min;       /* > 0, backtracking floor (then RSP_LINESEARCH_FAIL)        */
@@ -105,6 +110,20 @@ typedef struct rsp_options {
   int32_t precision;      /* RSP_FP64 or RSP_FP32_REFINED                               */
   int32_t max_refine;     /* refinement steps per FP32 local solve                      */
   int32_t continuation;   /* RSP_CONT_*                                                 */
+  int32_t record_eps_snapshots;  /* rsp_solve only (0 elsewhere): record at most this many
+                          (<= RSP_HIST_MAX + 1) states x^0 + sum_i P~_i c_i^(k) of the
+                          first evaluation into eps_snapshots, k = 0, 1, ... counting the
+                          local Newton (eps) steps of Algorithm 1; c_i^(k) is subdomain i's
+                          correction after its k-th step, or its last one once it stopped */
+  double tol_inner_rel;   /* Algorithm 1, relative branch; < 0: equal to tol_inner       */
+  double fallback_rho;    /* FP32 factors only: after outer step k an instance leaves them
+                          for FP64 factors when |F(x^k)| > fallback_rho |F(x^(k-1))| (k >= 2),
+                          when the GMRES solve of step k stopped at max_gmres above its
+                          tolerance, or when a local solve of the evaluation at x^k failed
+                          (status 1 or 2).  It continues from x^k with FP64 factors (a new
+                          budget of max_outer steps) and, if it then converges, ends with
+                          RSP_REFINE_FALLBACK.  < 0: never; 0 forces the switch at k = 2. */
+  double* eps_snapshots;  /* device, [record_eps_snapshots][2][ny][nx], caller-owned      */
 } rsp_options;
 
 #define RSP_HIST_MAX 64
@@ -129,6 +148,10 @@ typedef struct rsp_history {
   double residual_final;                /* |F_{eps_min}(y, p)|_2 on the global grid      */
   double flops;                         /* algorithmic flops of the solve               */
   double ms_eval, ms_gmres, ms_total;   /* wall time of Algorithm 3 calls, GMRES, total  */
+  int32_t fallback_outer;               /* outer step after which the instance switched to
+                                           FP64 factors (-1: it did not)                 */
+  int32_t snapshots;                    /* states recorded into eps_snapshots           */
+  double snapshot_eps[RSP_HIST_MAX + 1];/* eps_k of the local solves at snapshot k      */
 } rsp_history;
 
 typedef struct rsp_context rsp_context;
@@ -203,7 +226,9 @@ int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t st
 
 /* Algorithm 2 (RASPEN with eps-continuation in the local solves): from x^0 =
    (y0, p0) (both NULL for x^0 = 0) to y, p and u = D_eps_min(p), all [ny][nx].
-   yd, f as in rsp_setup; `hist` (host, nullable) receives the history. */
+   yd, f as in rsp_setup; `hist` (host, nullable) receives the history.  With
+   opts->record_eps_snapshots > 0 the states of the first evaluation's local Newton
+   steps are written to opts->eps_snapshots (their eps_k to hist->snapshot_eps). */
 int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts,
               const double* yd, const double* f, const double* y0, const double* p0,
               double* y, double* p, double* u, rsp_history* hist, hipStream_t stream);
@@ -244,8 +269,11 @@ int rsp_solve_newton(rsp_context* ctx, const rsp_problem* prob, const rsp_option
    have a fixed order that depends only on the instance, so an instance's result
    does not depend on the other members of the batch when the batch's padded
    line-block size (16-multiple above twice the widest tile) equals its own.
-   Returns the largest per-instance status (hist[q].status holds each), or a hard
-   error (< 0).  The single-problem calls above need rsp_setup again afterwards. */
+   Instances that stall with FP32 factors (fallback_rho) finish together, after the
+   others, in a layout with FP64 factors.  Returns the largest per-instance status
+   (hist[q].status holds each); RSP_ENUMERIC when an instance ended with it (only that
+   instance's outputs are undefined); another hard error (< 0) for the whole call.
+   The single-problem calls above need rsp_setup again afterwards. */
 int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const rsp_options* opts,
                     const double* const* yd, const double* const* f, const double* const* y0,
                     const double* const* p0, double* const* y, double* const* p, double* const* u,

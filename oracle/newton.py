@@ -29,12 +29,14 @@ class NewtonInfo:
 
 
 def newton_continuation(residual, jacobian, x0, eps0, eps_min, gamma, sigma,
-                        tol, kmax, alpha_min, linsolve=None, on_step=None):
+                        tol, kmax, alpha_min, linsolve=None, on_step=None, tol_rel=None):
     """Algorithm 1.
 
     residual(x, eps) -> F_eps(x);  jacobian(x, eps) -> sparse F'_eps(x).
-    The loop runs while (||F_{eps_k}(x^k)|| > max(tol, tol ||F_{eps_0}(x^0)||) or
-    eps_k > eps_min) and k <= kmax: solve F'_{eps_k}(x^k) d = -F_{eps_k}(x^k),
+    The loop runs while (||F_{eps_k}(x^k)|| > max(tol, tol_rel ||F_{eps_0}(x^0)||) or
+    eps_k > eps_min) and k <= kmax (tol_rel = tol unless given: the algorithm uses one
+    tolerance for both branches; a tolerance in the units of F and a relative one may
+    differ when F is scaled): solve F'_{eps_k}(x^k) d = -F_{eps_k}(x^k),
     backtrack alpha = 1, 1/2, ... until ||F_{eps_k}(x^k + alpha d)|| <= sigma ||F_{eps_k}(x^k)||,
     then x^{k+1} = x^k + alpha d, eps_{k+1} = max(gamma eps_k, eps_min).
     on_step(k, x, eps) is called after every accepted update.
@@ -45,7 +47,7 @@ def newton_continuation(residual, jacobian, x0, eps0, eps_min, gamma, sigma,
     Fx = residual(x, eps)
     r = float(np.linalg.norm(Fx))
     r0 = r
-    thresh = max(tol, tol * r0)
+    thresh = max(tol, (tol if tol_rel is None else tol_rel) * r0)
     k = 0
     backtracks = 0
     status = CONVERGED

@@ -34,6 +34,12 @@ from .system import System
 CONT_FIRST, CONT_NONE, CONT_EVERY = 0, 1, 2
 
 
+def inner_rel_tol(opts):
+    """Relative branch of the local stopping test (tol_inner_rel < 0: tol_inner)."""
+    r = getattr(opts, "tol_inner_rel", -1.0)
+    return opts.tol_inner if r < 0 else r
+
+
 def split_1d(n, s):
     """Non-overlapping intervals [jB, min((j+1)B, n)), B = ceil(n/s)."""
     if s < 1 or s > n:
@@ -137,7 +143,7 @@ class Raspen:
             lambda c, eps: self.local_residual(i, x, c, eps),
             lambda c, eps: self.local_jacobian(i, x, c, eps),
             np.zeros(2 * m), eps0, p.eps_min, p.gamma, o.sigma, o.tol_inner,
-            o.max_inner, o.alpha_min, on_step=cb)
+            o.max_inner, o.alpha_min, on_step=cb, tol_rel=inner_rel_tol(o))
         return c, info
 
     # -- Algorithm 3 ----------------------------------------------------------

@@ -46,6 +46,15 @@ struct Inst {
   int64_t n_factor = 0, n_solve = 0, n_gmres = 0, n_newton = 0, n_apply = 0;
   double flops = 0, ms_eval = 0, ms_gmres = 0;
   Clock::time_point t0;
+  // FP32 -> FP64 fallback (rsp_options.fallback_rho)
+  bool gm_cap_last = false;  // the last GMRES solve stopped at max_gmres above its tolerance
+  double Fn_prev = 0;        // |F(x^(k-1))|
+  bool parked = false;       // left its FP32 layout; x^k saved in y, p (y0, p0 point there)
+  int fallback_outer = -1;   // outer step k at the switch
+  int k_base = 0;            // outer steps done before the current max_outer budget
+  // snapshots x^0 + sum_i P~_i c_i^(k) of the first evaluation (rsp_solve)
+  double* snap = nullptr;    // device [snap_max][2][ny][nx]
+  int snap_max = 0;
 };
 
 // Validates the problem, partitions it and resets the solve state.
@@ -63,5 +72,11 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
 // finished (their outputs are complete on return); the update of the others may
 // still be running on the stream.
 int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st);
+// With FP32 line factors, an instance whose evaluation shows that they are not good
+// enough (rsp_options.fallback_rho) is parked instead of going on: its iterate is
+// copied into its outputs y, p (stream-ordered) and it becomes an unplaced instance
+// that starts from there.  The caller lays parked instances out again with FP64
+// factors (fallback_options) and steps them to the end.
+rsp_options fallback_options(const rsp_options& o);
 
 }  // namespace rsp

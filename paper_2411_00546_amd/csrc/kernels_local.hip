@@ -18,10 +18,12 @@ __device__ __forceinline__ int4 tile_box(const int4* box, int s, int& tx, int& t
 }
 
 // Stage z = R_i x (+ c + alpha dir on the tile interior) into LDS, halo included.
-__device__ void stage(const DevProblem& P, int s, int tx, int ty, const double* __restrict__ tilex,
+// Returns true in a thread that staged a correction c + alpha dir that is not finite.
+__device__ bool stage(const DevProblem& P, int s, int tx, int ty, const double* __restrict__ tilex,
                       const double* __restrict__ c, const double* __restrict__ dir, double alpha,
                       double* z) {
   const int W = tx + 2, H = ty + 2;
+  bool nonfinite = false;
   for (int e = threadIdx.x; e < 2 * W * H; e += kBlock) {
     const int f = e / (W * H);
     const int r = e - f * W * H;
@@ -30,10 +32,12 @@ __device__ void stage(const DevProblem& P, int s, int tx, int ty, const double* 
     if (c && a >= 1 && a <= tx && b >= 1 && b <= ty) {
       double cv = c[tile_idx(P, s, f, b - 1, a - 1)];
       if (dir) cv = cv + alpha * dir[tile_idx(P, s, f, b - 1, a - 1)];
+      nonfinite = nonfinite || !isfinite(cv);
       v = v + cv;
     }
     z[(f * kHalo + b) * kHalo + a] = v;
   }
+  return nonfinite;
 }
 
 // K_i at local node (a, b) from the staged tile: the two rows of F_eps (Section 4).
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Items I, const double* __re
 }
 
 __global__ __launch_bounds__(kBlock) void k_prolong(Items I, const double* __restrict__ tiles,
-                                                    const double* __restrict__ d,
+                                                    const double* __restrict__ base,
                                                     double* __restrict__ out) {
   int s;
   DevProblem P;
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Items I, const double* __res
   const int cw = co.y - co.x, ch = co.w - co.z;
   const size_t n = (size_t)P.nx * P.ny;
   out += 2 * P.noff;
-  if (d) d += 2 * P.noff;
+  if (base) base += 2 * P.noff;
   for (int e = threadIdx.x; e < 2 * cw * ch; e += kBlock) {
     const int f = e / (cw * ch);
     const int r = e - f * cw * ch;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Items I, const double* __res
     const int gi = co.x + a, gj = co.z + b;
     const size_t g = f * n + (size_t)gj * P.nx + gi;
     const double v = tiles[tile_idx(P, s, f, gj - bx.z, gi - bx.x)];
-    out[g] = d ? v - d[g] : v;
+    out[g] = base ? base[g] + v : v;
   }
 }
 
@@ -162,13 +166,14 @@ __global__ __launch_bounds__(kBlock) void k_local_residual(Items I, const double
   if (threadIdx.x == 0) norms[s] = sqrt(ss);
 }
 
-// Algorithm 1 start at eps_0 = the instance's eps_start: c = 0, residual, threshold.
+// Algorithm 1 start at eps_0 = the instance's eps_start: c = 0, residual, threshold
+// max(tol, tol_rel |K(0)|).  A residual that is not finite ends the solve (kSubNumeric).
 __global__ __launch_bounds__(kBlock) void k_newton_init(Items I, const double* __restrict__ tilex,
                                                         const double* __restrict__ yd,
                                                         const double* __restrict__ f,
                                                         double* __restrict__ c, double* __restrict__ res,
                                                         SubState* __restrict__ state, double tol,
-                                                        int kmax) {
+                                                        double tol_rel, int kmax) {
   __shared__ double z[2 * kHalo * kHalo];
   __shared__ double red[kBlock];
   int s;
@@ -188,13 +193,17 @@ __global__ __launch_bounds__(kBlock) void k_newton_init(Items I, const double* _
     SubState S;
     S.eps = eps0;
     S.rnorm = r;
-    S.thresh = fmax(tol, tol * r);
+    S.thresh = fmax(tol, tol_rel * r);
     S.alpha = 0.0;
     S.k = 0;
     S.backtracks = 0;
     const bool done = (r <= S.thresh) && !(eps0 > P.eps_min);
     S.active = (!done && kmax >= 0) ? 1 : 0;
-    S.status = (!done && !S.active) ? 1 : 0;
+    S.status = (!done && !S.active) ? kSubNotConverged : kSubOk;
+    if (!isfinite(r)) {
+      S.active = 0;
+      S.status = kSubNumeric;
+    }
     state[s] = S;
   }
 }
@@ -202,7 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_newton_init(Items I, const double* _
 // One Algorithm 1 step after the Newton direction `dir` is known: alpha = 1, 1/2, ...
 // until |K_{eps_k}(c + alpha dir)| <= sigma |K_{eps_k}(c)| (a NaN trial is rejected),
 // then c += alpha dir, eps_{k+1} = max(gamma eps_k, eps_min), k += 1, new residual,
-// and the loop test of Algorithm 1 (with the eps_k = eps_min requirement).
+// and the loop test of Algorithm 1 (with the eps_k = eps_min requirement).  A
+// direction that is not finite (a singular local Jacobian: a zero pivot gives an
+// infinite inverse) ends the solve with kSubNumeric instead of backtracking.
 __global__ __launch_bounds__(kBlock) void k_linesearch(Items I, const double* __restrict__ tilex,
                                                        const double* __restrict__ yd,
                                                        const double* __restrict__ f,
@@ -224,15 +235,22 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(Items I, const double* __
   f += P.noff;
   double alpha = 1.0;
   for (;;) {
-    stage(P, s, tx, ty, tilex, c, dir, alpha, z);
-    __syncthreads();
+    const bool nonfinite = stage(P, s, tx, ty, tilex, c, dir, alpha, z);
+    if (__syncthreads_or(nonfinite) && alpha == 1.0) {
+      if (threadIdx.x == 0) {
+        S.status = kSubNumeric;
+        S.active = 0;
+        state[s] = S;
+      }
+      return;
+    }
     const double rt = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, S.eps, nullptr, red));
     if (rt <= sigma * S.rnorm) break;
     alpha *= 0.5;
     S.backtracks += 1;
     if (alpha < alpha_min) {
       if (threadIdx.x == 0) {
-        S.status = 2;
+        S.status = kSubLineSearch;
         S.active = 0;
         state[s] = S;
       }
@@ -253,7 +271,11 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(Items I, const double* __
   S.rnorm = sqrt(tile_residual(P, s, bx, tx, ty, z, yd, f, S.eps, res, red));
   const bool done = (S.rnorm <= S.thresh) && !(S.eps > P.eps_min);
   S.active = (!done && S.k <= kmax) ? 1 : 0;
-  S.status = (!done && !S.active) ? 1 : 0;
+  S.status = (!done && !S.active) ? kSubNotConverged : kSubOk;
+  if (!isfinite(S.rnorm)) {
+    S.active = 0;
+    S.status = kSubNumeric;
+  }
   if (threadIdx.x == 0) state[s] = S;
 }
 
@@ -291,16 +313,18 @@ void launch_restrict_halo(const Items& I, const double* x, double* tilex, hipStr
 void launch_restrict(const Items& I, const double* x, double* tiles, hipStream_t st) {
   if (I.count > 0) k_restrict<<<I.count, kBlock, 0, st>>>(I, x, tiles);
 }
-void launch_prolong(const Items& I, const double* tiles, const double* d, double* out, hipStream_t st) {
-  if (I.count > 0) k_prolong<<<I.count, kBlock, 0, st>>>(I, tiles, d, out);
+void launch_prolong(const Items& I, const double* tiles, const double* base, double* out, hipStream_t st) {
+  if (I.count > 0) k_prolong<<<I.count, kBlock, 0, st>>>(I, tiles, base, out);
 }
 void launch_local_residual(const Items& I, const double* tilex, const double* yd, const double* f,
                            const double* c, double eps, double* out, double* norms, hipStream_t st) {
   if (I.count > 0) k_local_residual<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, eps, out, norms);
 }
 void launch_newton_init(const Items& I, const double* tilex, const double* yd, const double* f,
-                        double* c, double* res, SubState* state, double tol, int kmax, hipStream_t st) {
-  if (I.count > 0) k_newton_init<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, res, state, tol, kmax);
+                        double* c, double* res, SubState* state, double tol, double tol_rel, int kmax,
+                        hipStream_t st) {
+  if (I.count > 0)
+    k_newton_init<<<I.count, kBlock, 0, st>>>(I, tilex, yd, f, c, res, state, tol, tol_rel, kmax);
 }
 void launch_linesearch(const Items& I, const double* tilex, const double* yd, const double* f,
                        double* c, const double* dir, double* res, SubState* state, double sigma,

@@ -111,7 +111,23 @@ int validate_options(const rsp_options* o) {
   if (o->max_refine < 0 || o->max_refine > 8) return fail(RSP_EINVAL, "max_refine must be in 0..8");
   if (o->continuation < RSP_CONT_FIRST || o->continuation > RSP_CONT_EVERY) return fail(RSP_EINVAL, "unknown continuation mode");
   if (!(o->tol_outer >= 0) || !(o->tol_inner >= 0) || !(o->gmres_rtol >= 0)) return fail(RSP_EINVAL, "negative tolerance");
+  if (std::isnan(o->tol_inner_rel)) return fail(RSP_EINVAL, "tol_inner_rel is NaN");
+  if (std::isnan(o->fallback_rho)) return fail(RSP_EINVAL, "fallback_rho is NaN");
+  if (o->record_eps_snapshots < 0 || o->record_eps_snapshots > RSP_HIST_MAX + 1)
+    return fail(RSP_EINVAL, "record_eps_snapshots must be in 0..%d", RSP_HIST_MAX + 1);
+  if (o->record_eps_snapshots > 0 && !o->eps_snapshots)
+    return fail(RSP_EINVAL, "record_eps_snapshots needs the eps_snapshots array");
   return 0;
+}
+
+rsp_options fallback_options(const rsp_options& o) {
+  rsp_options r = o;
+  r.precision = RSP_FP64;
+  r.max_refine = 0;
+  r.fallback_rho = -1.0;
+  r.record_eps_snapshots = 0;
+  r.eps_snapshots = nullptr;
+  return r;
 }
 
 int make_partition(const rsp_problem* p, Partition* out) {
@@ -148,6 +164,7 @@ int inst_init(Inst* in, const rsp_problem* prob) {
   in->part = std::move(part);
   in->n = (size_t)prob->nx * prob->ny;
   in->t0 = Clock::now();
+  in->hist.fallback_outer = -1;
   return 0;
 }
 
@@ -643,9 +660,25 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
   }
   {
     Timed t(ctx, KID_INIT, st, 40.0 * all.tile_by / 8, all.halo_by + 3 * all.tile_by);
-    rsp::launch_newton_init(I, w.tilex, ctx->yd, ctx->f, w.c, w.res, w.state, o.tol_inner, o.max_inner, st);
+    rsp::launch_newton_init(I, w.tilex, ctx->yd, ctx->f, w.c, w.res, w.state, o.tol_inner,
+                            o.tol_inner_rel < 0 ? o.tol_inner : o.tol_inner_rel, o.max_inner, st);
   }
   HIPCHK(hipGetLastError());
+  // snapshots of the first evaluation of a single instance: x + sum_i P~_i c_i^(k) after
+  // local Newton step k (k = 0: c = 0), with the eps_k of the steps
+  Inst* rec = (set.size() == 1 && set[0]->snap && cont[0] && !set[0]->started) ? set[0] : nullptr;
+  double rec_eps = rec ? ctx->hprob[rec->slot].eps_start : 0.0;
+  auto record = [&](int k, hipStream_t s) {
+    if (!rec || k >= rec->snap_max) return;
+    // the prolongation writes at the instance's offset in the batch arrays: its own
+    // array is addressed relative to that (the single instance sits at offset 0)
+    double* dst = rec->snap + (size_t)k * 2 * rec->n - 2 * rec->noff;
+    rsp::launch_prolong(I, w.c, x, dst, s);
+    rec->hist.snapshot_eps[k] = rec_eps;
+    rec->hist.snapshots = k + 1;
+    rec_eps = std::max(rec->prob.gamma * rec_eps, rec->prob.eps_min);
+  };
+  record(0, st);
   auto read_state = [&]() -> int {
     return read_back(ctx, ctx->hstate.data(), w.state, sizeof(SubState) * ctx->hstate.size(), st);
   };
@@ -662,7 +695,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
     // without looking, then check after every step
     const int batch = std::max(1, std::min(ncont - it, o.max_inner + 1 - it));
     const SubWork sw = sub_work(ctx, set, true);
-    RSPCHK(launch_seq(ctx, GraphKey{SEQ_NEWTON, count, batch, 0, 0}, st, [&](hipStream_t s) {
+    auto steps = [&](hipStream_t s) {
       for (int b = 0; b < batch; ++b) {
         {
           Timed t(ctx, KID_FACTOR, s, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
@@ -683,8 +716,11 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
           rsp::launch_linesearch(I, w.tilex, ctx->yd, ctx->f, w.c, w.dir, w.res, w.state, o.sigma,
                                  o.alpha_min, o.max_inner, s);
         }
+        record(it + b + 1, s);
       }
-    }));
+    };
+    if (rec) steps(st);   // recorded steps write to step-dependent addresses: no graph
+    else RSPCHK(launch_seq(ctx, GraphKey{SEQ_NEWTON, count, batch, 0, 0}, st, steps));
     it += batch;
     RSPCHK(read_state());
     active = count_active();
@@ -899,7 +935,8 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     }
     in->n_solve += (int64_t)in->part.S * (h.used + in->restarts);
     in->flops += sfl * (h.used + in->restarts);
-    if (!(h.rel <= h.rtol)) in->gm_stagnated = true;
+    in->gm_cap_last = !(h.rel <= h.rtol);
+    if (in->gm_cap_last) in->gm_stagnated = true;
   }
   return 0;
 }
@@ -927,7 +964,10 @@ int finish(rsp_context* ctx, const std::vector<Inst*>& fin, hipStream_t st) {
     // an inexact GMRES solve only matters if the outer iteration then fails to converge
     if (!(in->Fn <= in->thr) && in->status == 0)
       in->status = in->gm_stagnated ? RSP_GMRES_STAGNATION : RSP_NOT_CONVERGED;
+    // converged only after leaving the FP32 factors
+    if (in->status == 0 && in->fallback_outer >= 0) in->status = RSP_REFINE_FALLBACK;
     h->status = in->status;
+    h->fallback_outer = in->fallback_outer;
     h->outer = in->k;
     h->subdomains = in->part.S;
     h->factorizations = in->n_factor;
@@ -1104,7 +1144,7 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
   std::vector<Inst*> ev;
   std::vector<char> cont;
   for (Inst* in : live) {
-    if (in->finished) continue;
+    if (in->finished || in->parked) continue;
     ev.push_back(in);
     cont.push_back(!in->started ? o.continuation != RSP_CONT_NONE : o.continuation == RSP_CONT_EVERY);
   }
@@ -1114,7 +1154,7 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
   RSPCHK(run_eval(ctx, ev, cont, ctx->x, ctx->w.F, &es, st));
   RSPCHK(read_norms(ctx, kLEval, (int)ev.size(), ctx->w.F, st));
   double dt = ms_since(t);
-  std::vector<Inst*> go, fin;
+  std::vector<Inst*> go, fin, park;
   for (size_t q = 0; q < ev.size(); ++q) {
     Inst* in = ev[q];
     in->ms_eval += dt;
@@ -1123,8 +1163,26 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
       in->thr = std::max(o.tol_outer, o.tol_outer * in->Fn);
       in->started = true;
     }
-    in->status = std::max(in->status, es[q].status);
     const int k = in->k;
+    if (es[q].status == kSubNumeric || !std::isfinite(in->Fn)) {
+      // NaN or Inf in a local residual or direction, or in the assembled residual
+      in->status = RSP_ENUMERIC;
+      if (k <= RSP_HIST_MAX) in->hist.norm[k] = in->Fn;
+      fin.push_back(in);
+      continue;
+    }
+    if (ctx->fp32 && o.fallback_rho >= 0) {
+      const bool local_fail = es[q].status == kSubNotConverged || es[q].status == kSubLineSearch;
+      const bool open = !(in->Fn <= in->thr);
+      const bool stalled = open && ((k >= 1 && in->gm_cap_last) ||
+                                    (k >= 2 && !(in->Fn <= o.fallback_rho * in->Fn_prev)));
+      if (local_fail || stalled) {
+        park.push_back(in);
+        continue;
+      }
+    }
+    in->Fn_prev = in->Fn;
+    in->status = std::max(in->status, es[q].status);
     if (k <= RSP_HIST_MAX) {
       rsp_history* h = &in->hist;
       h->norm[k] = in->Fn;
@@ -1137,8 +1195,28 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
         h->gmres_rel[k] = in->gm_rel;
       }
     }
-    if (!(in->Fn <= in->thr) && in->k < o.max_outer) go.push_back(in);
+    if (!(in->Fn <= in->thr) && in->k - in->k_base < o.max_outer) go.push_back(in);
     else fin.push_back(in);
+  }
+  for (Inst* in : park) {
+    // the FP32 factors were not good enough: save x^k in the outputs, to be laid out
+    // again from there with FP64 factors (an evaluation at x^k is redone there)
+    const double* xi = ctx->x + 2 * in->noff;
+    HIPCHK(hipMemcpyAsync(in->y, xi, 8 * in->n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(in->p, xi + in->n, 8 * in->n, hipMemcpyDeviceToDevice, st));
+    in->y0 = in->y;
+    in->p0 = in->p;
+    in->placed = false;
+    in->parked = true;
+    in->fallback_outer = in->k;
+    in->k_base = in->k;
+    in->status = 0;
+    in->gm_stagnated = false;
+    in->gm_cap_last = false;
+    if (in->k == 0) {   // x^0 itself: the first evaluation (and its snapshots) is redone
+      in->started = false;
+      in->hist.snapshots = 0;
+    }
   }
   if (!fin.empty()) RSPCHK(finish(ctx, fin, st));
   if (!go.empty()) {
@@ -1199,6 +1277,11 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
   in->started = true;
   in->thr = std::max(o.tol_outer, o.tol_outer * Fn);
   in->hist.norm[0] = Fn;
+  if (!std::isfinite(Fn)) {   // NaN or Inf in the data or the start
+    in->status = RSP_ENUMERIC;
+    in->Fn = Fn;
+    return finish(ctx, one, st);
+  }
   int k = 0;
   while ((!(Fn <= in->thr) || eps > in->prob.eps_min) && k <= o.max_outer) {
     auto t = Clock::now();
@@ -1314,19 +1397,34 @@ int solve_instances(rsp_context* ctx, const rsp_options* opts, std::vector<Inst>
   for (auto& in : insts) live.push_back(&in);
   RSPCHK(engine_place(ctx, *opts, live, stream));
   for (auto& in : insts) in.t0 = rsp::Clock::now();
-  bool more = true;
-  while (more) {
-    RSPCHK(engine_step(ctx, live, stream));
-    more = false;
-    for (const Inst* in : live) more = more || !in->finished;
+  auto run = [&](const std::vector<Inst*>& set) -> int {
+    bool more = true;
+    while (more) {
+      RSPCHK(engine_step(ctx, set, stream));
+      more = false;
+      for (const Inst* in : set) more = more || (!in->finished && !in->parked);
+    }
+    return 0;
+  };
+  RSPCHK(run(live));
+  // instances that left the FP32 factors continue together with FP64 factors
+  std::vector<Inst*> parked;
+  for (Inst* in : live)
+    if (in->parked) parked.push_back(in);
+  if (!parked.empty()) {
+    const rsp_options o64 = rsp::fallback_options(*opts);
+    RSPCHK(engine_place(ctx, o64, parked, stream));
+    for (Inst* in : parked) in->parked = false;
+    RSPCHK(run(parked));
   }
-  int worst = 0;
+  int worst = 0, hard = 0;
   for (size_t q = 0; q < insts.size(); ++q) {
     if (hist) hist[q] = insts[q].hist;
     worst = std::max(worst, insts[q].status);
+    if (insts[q].status < 0 && hard == 0) hard = insts[q].status;
   }
   RSPCHK(resolve_events(ctx));
-  return worst;
+  return hard ? hard : worst;
 }
 
 }  // namespace
@@ -1482,7 +1580,7 @@ int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out, d
     RSPCHK(read_norms(ctx, kLEval, 1, out, stream));
     *norm = ctx->hnorm[0];
   }
-  return es[0].status;
+  return es[0].status == rsp::kSubNumeric ? RSP_ENUMERIC : es[0].status;
 }
 
 int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream) {
@@ -1502,6 +1600,8 @@ int rsp_solve(rsp_context* ctx, const rsp_problem* prob, const rsp_options* opts
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
+  insts[0].snap = opts->record_eps_snapshots > 0 ? opts->eps_snapshots : nullptr;
+  insts[0].snap_max = opts->record_eps_snapshots;
   const int r = solve_instances(ctx, opts, insts, hist, stream);
   if (r >= 0) {
     // keep the problem bound for the single-problem calls, as after rsp_setup
@@ -1517,6 +1617,7 @@ int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_op
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   RSPCHK(rsp::validate_options(opts));
   if (!prob) return fail(RSP_EINVAL, "problem is NULL");
+  if (opts->record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
@@ -1535,6 +1636,7 @@ int rsp_solve_newton(rsp_context* ctx, const rsp_problem* prob, const rsp_option
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   RSPCHK(rsp::validate_options(opts));
   if (!prob) return fail(RSP_EINVAL, "problem is NULL");
+  if (opts->record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
@@ -1554,6 +1656,7 @@ int rsp_solve_batch(rsp_context* ctx, int count, const rsp_problem* probs, const
   if (!ctx) return fail(RSP_EINVAL, "ctx is NULL");
   if (count < 1 || !probs) return fail(RSP_EINVAL, "need count >= 1 problems");
   RSPCHK(rsp::validate_options(opts));
+  if (opts->record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(count, probs, yd, f, y0, p0, y, p, u, &insts));

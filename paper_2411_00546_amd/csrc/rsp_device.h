@@ -53,14 +53,20 @@ __device__ __forceinline__ bool item_of(const Items& I, int& s, DevProblem& P) {
   return true;
 }
 
+// Outcome of a local Newton solve (SubState::status).
+constexpr int kSubOk = 0;
+constexpr int kSubNotConverged = 1;   // k_max reached
+constexpr int kSubLineSearch = 2;     // backtracking below alpha_min
+constexpr int kSubNumeric = 3;        // residual or direction not finite
+
 // Per-subdomain state of the local Newton solve (Algorithm 1).
 struct SubState {
   double eps;        // eps_k
   double rnorm;      // |K_{eps_k}(c^k)|_2
-  double thresh;     // max(tol, tol |K_{eps_0}(0)|)
+  double thresh;     // max(tol, tol_rel |K_{eps_0}(0)|)
   double alpha;      // last accepted step length
   int k;             // iterations done
-  int status;        // 0 ok / 1 not converged / 2 line-search failure
+  int status;        // kSub*
   int active;        // another Newton step is needed
   int backtracks;    // step halvings so far
 };

@@ -12,14 +12,16 @@ void launch_restrict_halo(const Items& I, const double* x, double* tilex, hipStr
 // R_i x without halo ([S][2][tym][txm]).
 void launch_restrict(const Items& I, const double* x, double* tiles, hipStream_t st);
 // a7: out[core of s] = tiles[s] (every node written once: the cores tile the grid).
-// If d != nullptr: out = -d + (that), the assembly of Algorithm 4.
-void launch_prolong(const Items& I, const double* tiles, const double* d, double* out, hipStream_t st);
+// If base != nullptr: out = base + (that) on the same nodes.
+void launch_prolong(const Items& I, const double* tiles, const double* base, double* out, hipStream_t st);
 // a3: K_i(c) at `eps`, tiles -> out, norms[s].
 void launch_local_residual(const Items& I, const double* tilex, const double* yd, const double* f,
                            const double* c, double eps, double* out, double* norms, hipStream_t st);
-// Algorithm 1 start at each instance's eps_start: c = 0, residual, threshold, active flags.
+// Algorithm 1 start at each instance's eps_start: c = 0, residual, threshold
+// max(tol, tol_rel |K(0)|), active flags.
 void launch_newton_init(const Items& I, const double* tilex, const double* yd, const double* f,
-                        double* c, double* res, SubState* state, double tol, int kmax, hipStream_t st);
+                        double* c, double* res, SubState* state, double tol, double tol_rel, int kmax,
+                        hipStream_t st);
 // a6: backtracking on |K|, update c and eps, new residual, stopping test.
 void launch_linesearch(const Items& I, const double* tilex, const double* yd, const double* f,
                        double* c, const double* dir, double* res, SubState* state, double sigma,

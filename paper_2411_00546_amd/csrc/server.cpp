@@ -45,6 +45,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 struct rsp_server {
   rsp_server_options opts{};
   rsp_context* ctx = nullptr;
+  rsp_context* ctx64 = nullptr;   // requests that left the FP32 factors (made on first use)
   hipStream_t stream = nullptr;
   std::thread worker;
   std::mutex mu;
@@ -86,17 +87,40 @@ void complete(rsp_server* s, Request* r, int result) {
   s->t_last = r->t_done;
 }
 
+// Requests whose FP32 factors were not good enough (rsp_options.fallback_rho) leave
+// the main batch parked and run to the end as a second batch with FP64 factors, in
+// a context of their own (with the same budget), one outer iteration per round.
+int step_fallback(rsp_server* s, std::vector<Request*>& fb, const std::vector<Request*>& fresh) {
+  const rsp_options o64 = rsp::fallback_options(s->opts.opts);
+  if (!s->ctx64) {
+    int r = rsp_context_create(&s->ctx64, s->opts.device, s->opts.hbm_budget);
+    if (r < 0) return r;
+    if (s->opts.tune.gm_chunk != 0 && (r = rsp_set_tuning(s->ctx64, &s->opts.tune)) < 0) return r;
+  }
+  std::vector<Inst*> li;
+  if (!fresh.empty()) {
+    fb.insert(fb.end(), fresh.begin(), fresh.end());
+    for (Request* r : fb) li.push_back(&r->inst);
+    int e = rsp::engine_place(s->ctx64, o64, li, s->stream);
+    if (e < 0) return e;
+    for (Request* r : fresh) r->inst.parked = false;
+    li.clear();
+  }
+  for (Request* r : fb) li.push_back(&r->inst);
+  return li.empty() ? 0 : rsp::engine_step(s->ctx64, li, s->stream);
+}
+
 void worker_main(rsp_server* s) {
   (void)hipSetDevice(s->opts.device);
-  std::vector<Request*> live;
+  std::vector<Request*> live, fb;
   const rsp_options& o = s->opts.opts;
   const size_t budget = s->opts.hbm_budget;
   for (;;) {
     std::vector<Request*> adm;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !live.empty(); });
-      if (live.empty() && s->queue.empty() && s->stop) break;
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !live.empty() || !fb.empty(); });
+      if (live.empty() && fb.empty() && s->queue.empty() && s->stop) break;
       while (!s->queue.empty()) {
         if (s->opts.max_batch > 0 && (int)(live.size() + adm.size()) >= s->opts.max_batch) break;
         Request* r = s->queue.front();
@@ -130,23 +154,38 @@ void worker_main(rsp_server* s) {
       for (Request* r : live) li.push_back(&r->inst);
       err = rsp::engine_step(s->ctx, li, s->stream);
     }
-    std::vector<Request*> still;
+    std::vector<Request*> still, parked;
+    for (Request* r : live) {
+      if (err >= 0 && r->inst.parked) parked.push_back(r);
+      else still.push_back(r);
+    }
+    live.swap(still);
+    still.clear();
+    int err64 = 0;
+    if (err >= 0 && (!fb.empty() || !parked.empty())) err64 = step_fallback(s, fb, parked);
+    std::vector<Request*> fb_still;
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      if (!live.empty()) {
+      if (!live.empty() || !fb.empty()) {
         s->steps += 1;
-        s->step_members += (int64_t)live.size();
+        s->step_members += (int64_t)(live.size() + fb.size());
       }
       for (Request* r : live) {
         if (err < 0) complete(s, r, err);
         else if (r->inst.finished) complete(s, r, r->inst.status);
         else still.push_back(r);
       }
-      s->running = (int64_t)still.size();
+      for (Request* r : fb) {
+        if (err64 < 0) complete(s, r, err64);
+        else if (r->inst.finished) complete(s, r, r->inst.status);
+        else fb_still.push_back(r);
+      }
+      s->running = (int64_t)(still.size() + fb_still.size());
     }
     s->cv_done.notify_all();
-    if (err < 0) (void)hipStreamSynchronize(s->stream);
+    if (err < 0 || err64 < 0) (void)hipStreamSynchronize(s->stream);
     live.swap(still);
+    fb.swap(fb_still);
   }
 }
 
@@ -159,6 +198,7 @@ int rsp_server_create(rsp_server** out, const rsp_server_options* opts) {
   if (opts->max_batch < 0) return fail(RSP_EINVAL, "max_batch must be >= 0");
   int r = rsp::validate_options(&opts->opts);
   if (r < 0) return r;
+  if (opts->opts.record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
   std::unique_ptr<rsp_server> s(new (std::nothrow) rsp_server());
   if (!s) return fail(RSP_ENOMEM, "out of host memory");
   s->opts = *opts;
@@ -288,6 +328,7 @@ int rsp_server_destroy(rsp_server* s) {
   (void)hipSetDevice(s->opts.device);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   rsp_context_destroy(s->ctx);
+  if (s->ctx64) rsp_context_destroy(s->ctx64);
   delete s;
   return 0;
 }

@@ -39,7 +39,9 @@ class rsp_options(ctypes.Structure):
                 ("alpha_min", ctypes.c_double), ("gmres_restart", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("max_inner", ctypes.c_int32),
                 ("max_gmres", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_refine", ctypes.c_int32), ("continuation", ctypes.c_int32)]
+                ("max_refine", ctypes.c_int32), ("continuation", ctypes.c_int32),
+                ("record_eps_snapshots", ctypes.c_int32), ("tol_inner_rel", ctypes.c_double),
+                ("fallback_rho", ctypes.c_double), ("eps_snapshots", ctypes.c_void_p)]
 
 
 _H = RSP_HIST_MAX + 1
@@ -55,7 +57,9 @@ class rsp_history(ctypes.Structure):
                 ("gmres_total", ctypes.c_int64), ("newton_iterations", ctypes.c_int64),
                 ("jac_applies", ctypes.c_int64), ("residual_final", ctypes.c_double),
                 ("flops", ctypes.c_double), ("ms_eval", ctypes.c_double),
-                ("ms_gmres", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_gmres", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("fallback_outer", ctypes.c_int32), ("snapshots", ctypes.c_int32),
+                ("snapshot_eps", ctypes.c_double * _H)]
 
     def as_dict(self):
         k = min(self.outer, RSP_HIST_MAX)
@@ -67,7 +71,8 @@ class rsp_history(ctypes.Structure):
                     local_solves=self.local_solves, gmres_total=self.gmres_total,
                     newton_iterations=self.newton_iterations, jac_applies=self.jac_applies,
                     residual_final=self.residual_final, flops=self.flops, ms_eval=self.ms_eval,
-                    ms_gmres=self.ms_gmres, ms_total=self.ms_total)
+                    ms_gmres=self.ms_gmres, ms_total=self.ms_total, fallback_outer=self.fallback_outer,
+                    snapshots=self.snapshots, snapshot_eps=list(self.snapshot_eps[:self.snapshots]))
 
 
 class rsp_kernel_stat(ctypes.Structure):
@@ -190,11 +195,19 @@ def make_problem(p):
                        p.sx, p.sy, p.overlap)
 
 
-def make_options(o):
-    """rsp_options from a synth.Options-like object."""
+def make_options(o, eps_snapshots=None):
+    """rsp_options from a synth.Options-like object; eps_snapshots: device tensor
+    [K][2][ny][nx] that receives up to K = o.record_eps_snapshots snapshots (rsp_solve)."""
+    k = int(getattr(o, "record_eps_snapshots", 0))
+    if k and eps_snapshots is None:
+        raise ValueError("record_eps_snapshots needs an eps_snapshots tensor")
+    if k and (eps_snapshots.dim() != 4 or eps_snapshots.shape[0] < k or eps_snapshots.shape[1] != 2):
+        raise ValueError("eps_snapshots must be [K >= record_eps_snapshots][2][ny][nx]")
     return rsp_options(o.tol_outer, o.tol_inner, o.gmres_rtol, o.sigma, o.alpha_min,
                        o.gmres_restart, o.max_outer, o.max_inner, o.max_gmres, o.precision,
-                       o.max_refine, o.continuation)
+                       o.max_refine, o.continuation, k, getattr(o, "tol_inner_rel", -1.0),
+                       getattr(o, "fallback_rho", 1.0),
+                       None if eps_snapshots is None else _ptr(eps_snapshots))
 
 
 # ---------------------------------------------------------------- entry points
@@ -317,17 +330,20 @@ def _ptr_array(ts, allow_none=False):
 
 def rsp_solve_batch(ctx, probs, opts, yd, f, y0, p0, y, p, u, stream=None):
     """Algorithm 2 for a batch.  probs: list of rsp_problem; yd .. u: lists of tensors
-    (f, y0, p0 may be None or hold None).  Returns (worst status, [history dicts])."""
+    (f, y0, p0 may be None or hold None).  Returns (status, [history dicts]); the
+    status is RSP_ENUMERIC when an instance ended with it (the others' results and
+    histories are complete), other hard errors raise."""
     n = len(probs)
     parr = (rsp_problem * n)(*probs)
     hist = (rsp_history * n)()
     none = [None] * n
-    st = _check(load().rsp_solve_batch(ctx, n, parr, ctypes.byref(opts), _ptr_array(yd),
-                                       _ptr_array(f if f is not None else none, True),
-                                       _ptr_array(y0 if y0 is not None else none, True),
-                                       _ptr_array(p0 if p0 is not None else none, True),
-                                       _ptr_array(y), _ptr_array(p), _ptr_array(u), hist,
-                                       _stream(stream)))
+    st = load().rsp_solve_batch(ctx, n, parr, ctypes.byref(opts), _ptr_array(yd),
+                                _ptr_array(f if f is not None else none, True),
+                                _ptr_array(y0 if y0 is not None else none, True),
+                                _ptr_array(p0 if p0 is not None else none, True),
+                                _ptr_array(y), _ptr_array(p), _ptr_array(u), hist, _stream(stream))
+    if st != RSP_ENUMERIC:
+        _check(st)
     return st, [h.as_dict() for h in hist]
 
 

@@ -100,6 +100,9 @@ class Options:
     precision: int = 0          # 0 FP64, 1 FP32 factors + FP64 refinement
     max_refine: int = 1
     continuation: int = 0       # 0 first evaluation, 1 none, 2 every evaluation
+    record_eps_snapshots: int = 0   # snapshots of the first evaluation (GPU path only)
+    tol_inner_rel: float = -1.0     # relative branch of the inner test (< 0: tol_inner)
+    fallback_rho: float = 1.0       # FP32 -> FP64 switch (GPU path only; < 0: never)
 
 
 def subdomains_for(n: int, size: int = 32) -> int:

@@ -38,7 +38,7 @@ def mms_problem(kind, nx, ny, sx, sy, ov, eps_min=1e-6):
 
 
 def paper_model_problem(n, sx, sy, ov, eps_min, gamma=0.2, k=5, eps_bar=1e-15):
-    """The numerical model problem of Section 5: phi(y) = kappa (y^3 + exp(kappa y)),
+    """The numerical model problem of Section 4 (eqs. (ppp), (pppp), (ydpppp)): phi(y) = kappa (y^3 + exp(kappa y)),
     kappa = 0.1, nu = 1e-6, mu = 1, f = 0 on an n x n grid, with
       p_bar = 1.3 mu sin(2 pi k x1) sin(2 pi k x2)                            eq. (ppp),
       y_bar: A y + phi(y) - f + g_eps(p_bar) / nu = 0 at eps = eps_bar        eq. (pppp),
@@ -75,7 +75,8 @@ def paper_model_problem(n, sx, sy, ov, eps_min, gamma=0.2, k=5, eps_bar=1e-15):
 
 
 def paper_inner_tol(nx, ny, tol=1e-8):
-    """The inner tolerance of Section 5 (1e-8) in the units of F here.
+    """The absolute branch of the inner tolerance of Section 5 (1e-8) in the units of F
+    here (the relative branch, tol |K(0)|, has no units and keeps 1e-8).
 
     F is the 5-point system with A = -Laplacian / h^2, unscaled.  The paper's tolerance
     is read as one on the residual of the equations multiplied by the cell area hx*hy

@@ -435,7 +435,7 @@ def test_newton_gmres_equals_global_newton(cont):
 
 
 def test_model_problem_local_rounding_floor():
-    """The model problem of Section 5 at N = 450 (|y_bar| ~ 56, nu = 1e-6): the FP64
+    """The model problem of Section 4 at N = 450 (|y_bar| ~ 56, nu = 1e-6): the FP64
     rounding of one evaluation of F on a 45 x 45 box (the size of a subdomain of the
     11 x 11 partition with overlap 2h) exceeds an unscaled inner tolerance of 1e-8, and
     lies far below it once the equations are scaled by the cell area.  The reference
