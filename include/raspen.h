@@ -116,13 +116,15 @@ typedef struct rsp_options {
                           local Newton (eps) steps of Algorithm 1; c_i^(k) is subdomain i's
                           correction after its k-th step, or its last one once it stopped */
   double tol_inner_rel;   /* Algorithm 1, relative branch; < 0: equal to tol_inner       */
-  double fallback_rho;    /* FP32 factors only: after outer step k an instance leaves them
-                          for FP64 factors when |F(x^k)| > fallback_rho |F(x^(k-1))| (k >= 2),
-                          when the GMRES solve of step k stopped at max_gmres above its
-                          tolerance, or when a local solve of the evaluation at x^k failed
-                          (status 1 or 2).  It continues from x^k with FP64 factors (a new
-                          budget of max_outer steps) and, if it then converges, ends with
-                          RSP_REFINE_FALLBACK.  < 0: never; 0 forces the switch at k = 2. */
+  double fallback_rho;    /* FP32 factors only: an instance leaves them for FP64 factors
+                          when a local solve of its evaluation at x^k fails (status 1 or 2),
+                          or, x^k not meeting the outer test, when the GMRES solve of step k
+                          ended above fallback_rho (relative residual) or, from k = 2 on,
+                          |F(x^k)| > fallback_rho |F(x^(k-1))|: the FP32 Jacobian action no
+                          longer gives a contraction by fallback_rho per outer step.  It
+                          continues from x^k with FP64 factors (a new budget of max_outer
+                          steps) and, if it then converges, ends with RSP_REFINE_FALLBACK.
+                          < 0: never; 0 forces the switch at the first open x^k, k >= 1.  */
   double* eps_snapshots;  /* device, [record_eps_snapshots][2][ny][nx], caller-owned      */
 } rsp_options;
 

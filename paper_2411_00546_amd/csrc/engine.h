@@ -47,7 +47,6 @@ struct Inst {
   double flops = 0, ms_eval = 0, ms_gmres = 0;
   Clock::time_point t0;
   // FP32 -> FP64 fallback (rsp_options.fallback_rho)
-  bool gm_cap_last = false;  // the last GMRES solve stopped at max_gmres above its tolerance
   double Fn_prev = 0;        // |F(x^(k-1))|
   bool parked = false;       // left its FP32 layout; x^k saved in y, p (y0, p0 point there)
   int fallback_outer = -1;   // outer step k at the switch

@@ -935,8 +935,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     }
     in->n_solve += (int64_t)in->part.S * (h.used + in->restarts);
     in->flops += sfl * (h.used + in->restarts);
-    in->gm_cap_last = !(h.rel <= h.rtol);
-    if (in->gm_cap_last) in->gm_stagnated = true;
+    if (!(h.rel <= h.rtol)) in->gm_stagnated = true;
   }
   return 0;
 }
@@ -1174,7 +1173,9 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
     if (ctx->fp32 && o.fallback_rho >= 0) {
       const bool local_fail = es[q].status == kSubNotConverged || es[q].status == kSubLineSearch;
       const bool open = !(in->Fn <= in->thr);
-      const bool stalled = open && ((k >= 1 && in->gm_cap_last) ||
+      // an outer step contracts by about the relative residual of its GMRES solve, so
+      // both say whether the FP32 Jacobian action still gives a contraction by rho
+      const bool stalled = open && ((k >= 1 && !(in->gm_rel <= o.fallback_rho)) ||
                                     (k >= 2 && !(in->Fn <= o.fallback_rho * in->Fn_prev)));
       if (local_fail || stalled) {
         park.push_back(in);
@@ -1212,7 +1213,6 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
     in->k_base = in->k;
     in->status = 0;
     in->gm_stagnated = false;
-    in->gm_cap_last = false;
     if (in->k == 0) {   // x^0 itself: the first evaluation (and its snapshots) is redone
       in->started = false;
       in->hist.snapshots = 0;

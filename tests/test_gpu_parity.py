@@ -487,14 +487,16 @@ def test_eval_and_jacobian_action_fp32_refined(R, nref, tol):
         c.close()
 
 
+@pytest.mark.parametrize("nref", [0, 1])
 @pytest.mark.parametrize("name,phi,mu", [("small63", synth.PHI_CUBIC, 1e-2), ("rect23x17", synth.PHI_EXP, 1e-2),
                                          ("ragged37x29", synth.PHI_CUBIC, 0.0)])
-def test_solve_mixed_precision(R, name, phi, mu):
-    """FP32 factors + FP64 refinement: within 1e-8 of the FP64 oracle and of the
-    GPU FP64 path."""
+def test_solve_mixed_precision(R, name, phi, mu, nref):
+    """FP32 factors with nref FP64 refinement steps per local solve (0: the benchmarked
+    form): within 1e-8 of the FP64 oracle and of the GPU FP64 path."""
     prob = make_problem(name, phi=phi, mu=mu)
     yd, f = prob.inputs()
-    st, hist, x, u = gpu_solve(R, prob, MIXED, yd, f)
+    o = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12, precision=1, max_refine=nref)
+    st, hist, x, u = gpu_solve(R, prob, o, yd, f)
     st64, hist64, x64, u64 = gpu_solve(R, prob, TIGHT, yd, f)
     ref = Raspen(prob, TIGHT, yd, f).solve()
     assert st == 0 and st64 == 0

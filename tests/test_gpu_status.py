@@ -5,7 +5,7 @@
   and in a batch only for the instance concerned.
 * RSP_REFINE_FALLBACK (4): with FP32 line factors an instance that stalls leaves them
   for FP64 factors and continues from its iterate; fallback_rho = 0 forces the switch
-  after outer step 2, and the answer is then the FP64 one (within 1e-10 of the oracle).
+  after outer step 1, and the answer is then the FP64 one (within 1e-10 of the oracle).
 * Snapshots of the first evaluation (record_eps_snapshots): x^0 + sum_i P~_i c_i^(k)
   after each local Newton (eps) step k of Algorithm 1, against the oracle's iterates.
 """
@@ -93,9 +93,9 @@ def test_forced_fallback_ends_with_the_fp64_answer(R, phi, nu, mu):
     yd, f = prob.inputs()
     st, h, x, u = solve(R, prob, FORCED, yd, f)
     ref = Raspen(prob, TIGHT, yd, f).solve()
-    assert ref["outer"] >= 3          # not converged at step 2, so the switch happens there
+    assert ref["outer"] >= 2          # not converged at step 1, so the switch happens there
     assert st == R.RSP_REFINE_FALLBACK and h["status"] == st
-    assert h["fallback_outer"] == 2
+    assert h["fallback_outer"] == 1
     assert rel(x, ref["x"]) <= 1e-10
 
 
@@ -115,9 +115,9 @@ def test_fp64_solves_never_fall_back(R):
 
 
 def test_forced_fallback_in_a_batch(R):
-    """Every member is switched after its step 2 (one FP64 layout for all of them) and
-    ends with the oracle's answer; an instance that converges within two steps keeps
-    its FP32 result."""
+    """Every member is switched after its step 1 (one FP64 layout for all of them) and
+    ends with the oracle's answer; an instance that converges in one step keeps its
+    FP32 result."""
     import torch
     probs = [ragged(phi=synth.PHI_EXP, nu=1e-3, mu=5e-3, seed=s) for s in (1, 2)]
     probs.append(ragged(nx=12, ny=9, sx=1, sy=1, overlap=2, seed=4))   # one subdomain: 1 step
@@ -131,7 +131,7 @@ def test_forced_fallback_in_a_batch(R):
     finally:
         R.rsp_context_destroy(ctx)
     assert [h["status"] for h in hs] == [R.RSP_REFINE_FALLBACK, R.RSP_REFINE_FALLBACK, 0]
-    assert [h["fallback_outer"] for h in hs] == [2, 2, -1]
+    assert [h["fallback_outer"] for h in hs] == [1, 1, -1]
     for q, p in enumerate(probs):
         ref = Raspen(p, TIGHT, *ins[q]).solve()
         x = np.concatenate([host(ys[q]).reshape(-1), host(ps[q]).reshape(-1)])
@@ -142,16 +142,17 @@ def test_forced_fallback_in_the_server(R):
     """Served requests that leave the FP32 factors finish in the server's FP64 batch."""
     probs = [ragged(phi=synth.PHI_EXP, nu=1e-3, mu=5e-3, seed=s) for s in (1, 2, 3)]
     ins = [p.inputs() for p in probs]
+    inp = [(dev(a), dev(b)) for a, b in ins]      # inputs stay alive until the tickets are done
     outs = [[dev(np.zeros((p.ny, p.nx))) for _ in range(3)] for p in probs]
     srv = R.rsp_server_create(R.make_options(FORCED))
     try:
-        tickets = [R.rsp_server_submit(srv, R.make_problem(p), dev(ins[q][0]), dev(ins[q][1]), *outs[q])
+        tickets = [R.rsp_server_submit(srv, R.make_problem(p), inp[q][0], inp[q][1], *outs[q])
                    for q, p in enumerate(probs)]
         res = [R.rsp_server_wait(srv, t, 60000.0) for t in tickets]
     finally:
         R.rsp_server_destroy(srv)
     for q, (st, h) in enumerate(res):
-        assert st == R.RSP_REFINE_FALLBACK and h["fallback_outer"] == 2
+        assert st == R.RSP_REFINE_FALLBACK and h["fallback_outer"] == 1
         ref = Raspen(probs[q], TIGHT, *ins[q]).solve()
         x = np.concatenate([host(outs[q][0]).reshape(-1), host(outs[q][1]).reshape(-1)])
         assert rel(x, ref["x"]) <= 1e-10
@@ -184,15 +185,26 @@ def test_snapshots_match_the_oracle(R, name, phi, nu, mu):
 
 
 def test_snapshots_fp32_factors_and_truncation(R):
-    """FP32 line factors: every snapshot within 1e-8 of the oracle's; with fewer slots
-    than steps only the first ones are written."""
+    """FP32 line factors: the local Newton directions carry the FP32 inverses' error, so
+    the intermediate iterates differ from the oracle's by up to that error times the
+    step (bounded by 1e-4 relative, the accuracy of an FP32 block LU here); the residual
+    is FP64, so the last snapshot, at the converged local solutions, is within 1e-8.
+    With fewer slots than steps only the first ones are written."""
     prob = ragged(phi=synth.PHI_EXP, nu=1e-3, mu=5e-3)
     yd, f = prob.inputs()
     ref = Raspen(prob, TIGHT, yd, f).solve(snapshots=True)["snapshots"]
-    st, h, x, u, snaps = solve(R, prob, opts_with(TIGHT, precision=1, max_refine=0), yd, f, snapshots=8)
+    o = opts_with(TIGHT, precision=1, max_refine=0)
+    st, h, x, u, snaps = solve(R, prob, o, yd, f, snapshots=8)
     assert st == 0 and h["snapshots"] == 8
     for k in range(8):
-        assert np.abs(snaps[k] - ref[k]).max() <= 1e-8 * max(np.abs(ref[k]).max(), 1e-300), k
+        assert np.abs(snaps[k] - ref[k]).max() <= 1e-4 * max(np.abs(ref[k]).max(), 1e-300), k
+    st, h, x, u, snaps = solve(R, prob, o, yd, f, snapshots=40)
+    K = h["snapshots"]
+    assert st == 0 and K == len(ref)
+    worst = max(np.abs(snaps[k] - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-300) for k in range(1, K))
+    print("FP32 snapshots: worst intermediate error %.3e, last %.3e" %
+          (worst, np.abs(snaps[K - 1] - ref[-1]).max() / np.abs(ref[-1]).max()))
+    assert np.abs(snaps[K - 1] - ref[-1]).max() <= 1e-8 * np.abs(ref[-1]).max()
 
 
 def test_snapshots_only_in_single_solves(R):
