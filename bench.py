@@ -2,15 +2,19 @@
 """RASPEN solve throughput on one MI355X.
 
 A step is one whole solve (Algorithm 2: local Newton solves with eps-continuation,
-RAS restriction/prolongation, outer Newton-GMRES) of the 255x255 workload:
-phi = y^3, f = 0, y_d = 8 seeded Gaussian bumps, nu = 1e-3, mu = 5e-3, eps 1 -> 1e-8
-halving, 8x8 subdomains (32x32 each) with overlap 4, GMRES(30) rtol 1e-10, outer
-tolerance 1e-10, inner tolerance 1e-8.  Inputs are resident in HBM before timing.
+RAS restriction/prolongation, outer Newton-GMRES) of the 511x511 precision workload
+(the default): phi = exp(y) - 1, f = 0, y_d = 8 seeded Gaussian bumps, nu = 1e-3,
+mu = 5e-3, eps 1 -> 1e-8 halving, 16x16 subdomains (32x32 each) with overlap 4,
+GMRES(30) rtol 1e-10 with at most 300 products per outer step, outer tolerance 1e-10,
+inner tolerance 1e-8; FP32 line factors on the matrix cores, FP64 everything else.
+Inputs are resident in HBM before timing.
 
-Prints one JSON line: solves/s, per-solve latency percentiles, the roofline of the
-dominant kernel (HIP-event durations measured during the timed solves, algorithmic
-bytes or flops per launch), and the CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line: solves/s, per-solve latency percentiles, the FP64 solve timed
+beside it, each result's error against the oracle's stored solution of the same
+workload and tolerances, the error of every eps step of the first evaluation against
+the oracle on sampled subdomains, the roofline of the dominant kernel (HIP-event
+durations measured during the timed solves, algorithmic bytes or flops per launch),
+and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -54,14 +58,16 @@ def describe(prob, opts):
             "seed": prob.seed, "unknowns": 2 * prob.nx * prob.ny}
 
 
-def traffic_for(kernel, fp32):
+def traffic_for(kernel, fp32, workload):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size)
-    from the committed rocprofv3 counters, when they were taken on the current source
-    of the kernel and for the same factor precision (else None)."""
+    from the committed rocprofv3 counters, when they were taken on this workload, on the
+    current source of the kernel and for the same factor precision (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     data = json.load(open(path))
+    if data.get("workload") != workload:
+        return None
     ent = data.get(kernel + ("/fp32" if fp32 else "/fp64")) or data.get(kernel)
     if not ent:
         return None
@@ -71,12 +77,14 @@ def traffic_for(kernel, fp32):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(prob, opts, hist):
-    """Oracle cost per solve from a bounded sample of the same workload (about 10 s of one
-    core on the 255^2 workload): the local Newton iterations of the first evaluation on
-    every subdomain, sparse LU factorisations and solves of local Jacobians, and
-    Gram-Schmidt steps on full-size vectors; each unit cost times the counts of the same
-    solve (the oracle runs the same algorithm)."""
+def cpu_baseline(prob, opts, hist, max_sub=64):
+    """Oracle cost per solve from a bounded sample of the same workload (10-30 s of one
+    core): the local Newton iterations of the first evaluation on up to max_sub
+    subdomains (every subdomain up to 64, else an even spread), sparse LU factorisations
+    and solves of their local Jacobians, and Gram-Schmidt steps on full-size vectors;
+    each unit cost times the counts of the same solve (the oracle runs the same
+    algorithm).  A whole oracle solve of the 511^2 workload takes about 12 minutes of
+    one core, beyond the time of a bench run."""
     import numpy as np
     import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
@@ -86,7 +94,9 @@ def cpu_baseline(prob, opts, hist):
         ora = Raspen(prob, opts, yd, f)
         n = ora.n
         x0 = np.zeros(2 * n)
-        sample = list(range(len(ora.subs)))           # corner, edge and interior tiles
+        S_all = len(ora.subs)
+        step = max(1, -(-S_all // max_sub))
+        sample = list(range(0, S_all, step))           # corner, edge and interior tiles
         t0 = time.perf_counter()
         iters = 0
         for i in sample:
@@ -122,8 +132,9 @@ def cpu_baseline(prob, opts, hist):
     fac_extra = hist["factorizations"] - inner                    # factorisations at x^(i)
     per_solve = (inner * t_iter + fac_extra * t_factor + hist["jac_applies"] * S * t_apply_sub
                  + hist["gmres_total"] * t_mgs)
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "seconds_per_solve": per_solve,
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1,
+            "cores_available": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "seconds_per_solve": per_solve, "extrapolated_from_sample": True,
             "units": {"t_iter": t_iter, "t_factor": t_factor, "t_apply_sub": t_apply_sub, "t_mgs": t_mgs},
             "sample": ("NumPy/SciPy oracle, 1 thread: first-evaluation local Newton solves of %d of the %d "
                        "subdomains (%d iterations, %.2f ms each), %d sparse LU factorisations (%.1f ms), "
@@ -133,6 +144,52 @@ def cpu_baseline(prob, opts, hist):
                        % (len(sample), S, iters, 1e3 * t_iter, len(sample), 1e3 * t_factor, reps * len(sample),
                           1e3 * t_apply_sub, reps, 1e3 * t_mgs, inner, fac_extra, hist["jac_applies"],
                           sample_s))}
+
+
+ORACLE_REFS = {"plain": "plain_cfg", "precision": "precision_cfg"}
+
+
+def oracle_reference(work):
+    """The oracle's solution of this workload at its own tolerances, stored by
+    tests/golden/make_oracle_refs.py (which runs the oracle alone), or None."""
+    import numpy as np
+    if work not in ORACLE_REFS:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", "oracle_%s.npz" % ORACLE_REFS[work])
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {"x": z["x"], "outer": int(z["outer"]), "seconds": float(z["seconds"]),
+                "name": os.path.relpath(path, ROOT)}
+
+
+def sample_subdomains(prob, count=6):
+    """Corner, edge and interior subdomains of the partition (row-major numbering)."""
+    S = prob.sx * prob.sy
+    return sorted({0, prob.sx - 1, S - prob.sx, S - 1, (prob.sy // 2) * prob.sx + prob.sx // 2,
+                   min(S - 1, prob.sx + 1)})[:count]
+
+
+def eps_step_errors(ora, prob, snaps, count):
+    """Error of each eps step of the first evaluation against the oracle: snapshot k
+    (x^0 + sum_i P~_i c_i^(k), x^0 = 0) on the cores of sampled subdomains against the
+    oracle's local Newton iterates c_i^(k) there (the oracle solves one subdomain at a
+    time), relative to the largest |c_i| of the converged local solutions.  snaps:
+    {subdomain: [count][2 core] host array}."""
+    import numpy as np
+    n = prob.nx * prob.ny
+    per_k = np.zeros(count)
+    for i, got in snaps.items():
+        sub = ora.subs[i]
+        rec = []
+        ora.local_solve(i, np.zeros(2 * n), prob.eps0, record=rec)
+        m = sub.rows.size
+        scale = max(np.abs(rec[-1]).max(), 1e-300)
+        for k in range(count):
+            c = rec[min(k, len(rec) - 1)]
+            want = np.concatenate([c[:m][sub.core_local], c[m:][sub.core_local]])
+            per_k[k] = max(per_k[k], float(np.abs(got[k] - want).max() / scale))
+    return [float(e) for e in per_k]
 
 
 def dominant(stats):
@@ -167,7 +224,7 @@ def solve_roofline(stats, fp32, ms_per_solve):
     return {"bound_ms": 1e3 * bound_s, "measured_ms": ms_per_solve, "frac": 1e3 * bound_s / ms_per_solve}
 
 
-def kernel_roofline(stats, fp32):
+def kernel_roofline(stats, fp32, workload):
     """Roofline object of the dominant single-pass kernel from rsp_kernel_stats output."""
     kern = {k: v for k, v in stats.items() if v["launches"] > 0}
     dom = dominant(kern)
@@ -181,7 +238,7 @@ def kernel_roofline(stats, fp32):
     else:
         achieved = d["flops"] / d["launches"] / avg_s / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic_for(dom, fp32),
+            "frac": achieved / peak, "traffic": traffic_for(dom, fp32, workload),
             "avg_launch_us": avg_s * 1e6, "launches": d["launches"], "timed_every": TIME_EVERY[0],
             "algorithmic_per_launch": (d["bytes"] if bound == "hbm" else d["flops"]) / d["launches"]}
     return roof
@@ -241,8 +298,9 @@ def batch_cpu_baseline(probs, opts, hists):
         total += (inner * u["t_iter"] + (h["factorizations"] - inner) * u["t_factor"]
                   + h["jac_applies"] * S * u["t_apply_sub"]
                   + h["gmres_total"] * u["t_mgs"] * (pr.nx * pr.ny) / n_big)
-    return {"value": len(probs) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "seconds_per_batch": total,
+    return {"value": len(probs) / total, "unit": "solves/s", "cores": 1,
+            "cores_available": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "seconds_per_batch": total, "extrapolated_from_sample": True,
             "sample": "unit costs from the bounded oracle sample of the %dx%d instance (%s), scaled by the "
                       "counts of all %d instances" % (probs[big].nx, probs[big].ny, one["sample"], len(probs))}
 
@@ -325,7 +383,7 @@ def run_batch_workload(args, R):
     finally:
         R.rsp_context_destroy(ctx)
     stats, breakdown = stats
-    roof = kernel_roofline(stats, opts.precision == 1)
+    roof = kernel_roofline(stats, opts.precision == 1, None)
     kernels = kernel_table(breakdown)
     flops = sum(h["flops"] for h in hists)
     sizes = sorted({(pr.nx, pr.ny) for pr in probs})
@@ -439,8 +497,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision", "batch", "serve"],
-                    help="plain: 255x255 (default); small: 63x63; precision: 511x511 exp; batch: 64 uneven "
+    ap.add_argument("--workload", default="precision", choices=["plain", "small", "precision", "batch", "serve"],
+                    help="precision: 511x511 exp (default); plain: 255x255; small: 63x63; batch: 64 uneven "
                          "instances per step; serve: Poisson request stream through the server")
     ap.add_argument("--count", type=int, default=64, help="instances (batch) or requests (serve)")
     ap.add_argument("--tune", type=int, default=1, choices=[0, 1],
@@ -462,6 +520,8 @@ def main():
                          "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras) "
                          "or the unpreconditioned one (rsp_solve_newton)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eps-errors", action="store_true",
+                    help="skip the per-eps-step comparison with the oracle on sampled subdomains")
     ap.add_argument("--phases", type=int, default=0,
                     help="profiling mode: run N residual evaluations with continuation at x = 0, "
                          "20 Jacobian actions of the workload and 3 plain 64 MiB device copies "
@@ -561,6 +621,27 @@ def main():
         x = torch.cat([y.reshape(-1), p.reshape(-1)]).cpu().numpy()
         return el, lat, hist, (stats, breakdown), x
 
+    def snapshot_cores(opt, sample, K=48):
+        """One untimed solve recording the first evaluation's eps steps; the cores of
+        the sampled subdomains of each snapshot, as host arrays."""
+        o = type(opt).from_buffer_copy(opt)
+        o.record_eps_snapshots = K
+        buf = torch.empty((K, 2, prob.ny, prob.nx), dtype=torch.float64, device=dev)
+        o.eps_snapshots = buf.data_ptr()
+        st, h = solve_fn(ctx, P, o, ydt, ft, None, None, y, p, u)
+        if st != 0:
+            raise RuntimeError("snapshot solve ended with status %d" % st)
+        k = h["snapshots"]
+        out = {}
+        for i in sample:
+            x0, x1, y0, y1 = part[i][4:]
+            out[i] = torch.cat([buf[:k, 0, y0:y1, x0:x1].reshape(k, -1),
+                                buf[:k, 1, y0:y1, x0:x1].reshape(k, -1)], 1).cpu().numpy()
+        return out, k, h["snapshot_eps"]
+
+    ref = oracle_reference(args.workload) if args.method == "raspen" else None
+    sample = sample_subdomains(prob)
+    part = R.rsp_partition(P)[3]
     try:
         elapsed, lat, hist, stats, x = solves(O, args.steps, args.warmup, True)
         cmp64 = None
@@ -570,15 +651,40 @@ def main():
             cmp64 = {"value": args.steps / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / args.steps,
                      "latency_ms": {"p50": float(np.percentile(np.array(lat64) * 1e3, 50)),
                                     "p99": float(np.percentile(np.array(lat64) * 1e3, 99))},
-                     "rel_err_mixed_vs_fp64": err, "outer": hist64["outer"]}
+                     "rel_err_mixed_vs_fp64": err, "outer": hist64["outer"],
+                     "rel_err_vs_oracle": (float(np.abs(x64 - ref["x"]).max() / np.abs(ref["x"]).max())
+                                           if ref is not None else None)}
             if not err <= 1e-8:
                 raise RuntimeError("mixed-precision solution differs from FP64 by %.3e > 1e-8" % err)
+        snaps = None
+        if args.method == "raspen" and not args.no_eps_errors:
+            snaps = {"mixed" if opts.precision == 1 else "fp64": snapshot_cores(O, sample)}
+            if opts.precision == 1:
+                snaps["fp64"] = snapshot_cores(O64, sample)
     finally:
         R.rsp_context_destroy(ctx)
 
+    vs_oracle = None
+    if ref is not None:
+        vs_oracle = {"reference": ref["name"], "oracle_outer": ref["outer"],
+                     "rel_err": float(np.abs(x - ref["x"]).max() / np.abs(ref["x"]).max()),
+                     "oracle_full_solve_s_on_build_host": ref["seconds"]}
+    ora = None
+    eps_err = None
+    if snaps is not None:
+        from threadpoolctl import threadpool_limits
+        from oracle.schwarz import Raspen
+        with threadpool_limits(limits=1):
+            ora = Raspen(prob, opts64, yd, f)
+            eps_err = {"sampled_subdomains": sample, "unit": "max-norm error on the sampled cores / max |c_i|"}
+            for key, (cores, k, eps_k) in snaps.items():
+                e = eps_step_errors(ora, prob, cores, k)
+                eps_err[key] = {"per_step": e, "max": max(e), "last": e[-1], "eps": eps_k}
+
     value = args.steps / elapsed
     stats, breakdown = stats
-    roof = kernel_roofline(stats, opts.precision == 1)
+    desc = describe(prob, opts)
+    roof = kernel_roofline(stats, opts.precision == 1, desc["workload"])
     kernels = kernel_table(breakdown)
     # the CPU baseline is the RASPEN oracle's sample; none for the comparison method
     cpu = None if args.no_cpu_baseline or args.method != "raspen" else cpu_baseline(prob, opts, hist)
@@ -588,12 +694,13 @@ def main():
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
            "data": "synthetic (seeded Gaussian-bump y_d)",
-           "config": dict(describe(prob, opts), method=args.method),
+           "config": dict(desc, method=args.method),
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
                      "residual_final": hist["residual_final"], "norm": hist["norm"][-1]},
-           "fp64": cmp64, "tuning": tuning, "roofline": roof,
+           "fp64": cmp64, "vs_oracle": vs_oracle, "eps_step_errors": eps_err, "tuning": tuning,
+           "roofline": roof,
            "solve_roofline": solve_roofline(breakdown, opts.precision == 1, 1e3 * elapsed / args.steps),
            "kernels": kernels, "cpu_baseline": cpu}
     print(json.dumps(out))

@@ -7,8 +7,9 @@ GPU tests and ``bench.py`` compare against them.
 
     python tests/golden/make_oracle_refs.py [name ...]
 
-Each file holds x = (y, p) (float64, [2 nx ny]), u, the status, the outer iteration
-count and the history of |F(x^k)|_2 and GMRES products; names are listed in REFS.
+Each file holds x = (y, p) (float64, [2 nx ny]; u follows from p), the status, the
+outer iteration count, the history of |F(x^k)|_2 and GMRES products and the oracle's
+time; names are listed in REFS.
 """
 import os
 import sys
@@ -57,7 +58,7 @@ def make(name):
     r = Raspen(prob, opts, yd, f).solve()
     dt = time.perf_counter() - t0
     h = r["history"]
-    np.savez_compressed(path_of(name), x=r["x"], u=r["u"], status=r["status"], outer=r["outer"],
+    np.savez_compressed(path_of(name), x=r["x"], status=r["status"], outer=r["outer"],
                         norms=np.array([e["norm"] for e in h]),
                         gmres=np.array([e["gmres"] for e in h]),
                         inner_max=np.array([max(e["inner"]) for e in h]), seconds=dt)
