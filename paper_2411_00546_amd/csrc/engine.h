@@ -24,7 +24,13 @@ struct Partition {
 };
 
 int validate_options(const rsp_options* o);
+int validate_problem(const rsp_problem* p);
 int make_partition(const rsp_problem* p, Partition* out);
+// Padded line-block size of tiles up to txm wide: a multiple of 16 above 2 txm.
+int line_block(int txm);
+// Constants of an instance in the form the kernels read them (its arrays at offset
+// noff; the batch's S, txm, tym and line-block size M).
+DevProblem dev_problem(const rsp_problem& p, long long noff, int S, int txm, int tym, int M);
 
 // One problem instance of a batch and its Algorithm 2 state.
 struct Inst {

@@ -82,6 +82,10 @@ int split_1d(int n, int s, std::vector<std::pair<int, int>>* out) {
   return 0;
 }
 
+}  // namespace
+
+namespace rsp {
+
 int validate_problem(const rsp_problem* p) {
   if (!p) return fail(RSP_EINVAL, "problem is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(RSP_EINVAL, "grid must have nx, ny >= 1");
@@ -96,7 +100,34 @@ int validate_problem(const rsp_problem* p) {
 
 int line_block(int txm) { return ((2 * txm + 15) / 16) * 16; }
 
-}  // namespace
+DevProblem dev_problem(const rsp_problem& p, long long noff, int S, int txm, int tym, int M) {
+  DevProblem P{};
+  P.nx = p.nx;
+  P.ny = p.ny;
+  P.phi = p.phi_kind;
+  P.kappa = p.kappa;
+  P.nu = p.nu;
+  P.inv_nu = 1.0 / p.nu;
+  P.mu = p.mu;
+  const double hx = 1.0 / (p.nx + 1), hy = 1.0 / (p.ny + 1);
+  P.hx2i = 1.0 / (hx * hx);
+  P.hy2i = 1.0 / (hy * hy);
+  P.diag0 = 2.0 * P.hx2i + 2.0 * P.hy2i;
+  P.eps_min = p.eps_min;
+  P.gamma = p.gamma;
+  P.eps_start = p.eps_min;
+  P.noff = noff;
+  P.S = S;
+  P.txm = txm;
+  P.tym = tym;
+  P.M = M;
+  return P;
+}
+
+}  // namespace rsp
+
+using rsp::validate_problem;
+using rsp::line_block;
 
 namespace rsp {
 
@@ -1094,27 +1125,7 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   std::vector<int4> hbox, hcore;
   std::vector<int> hinst;
   for (const Inst* in : live) {
-    const rsp_problem* p = &in->prob;
-    DevProblem& P = ctx->hprob[in->slot];
-    P.nx = p->nx;
-    P.ny = p->ny;
-    P.phi = p->phi_kind;
-    P.kappa = p->kappa;
-    P.nu = p->nu;
-    P.inv_nu = 1.0 / p->nu;
-    P.mu = p->mu;
-    const double hx = 1.0 / (p->nx + 1), hy = 1.0 / (p->ny + 1);
-    P.hx2i = 1.0 / (hx * hx);
-    P.hy2i = 1.0 / (hy * hy);
-    P.diag0 = 2.0 * P.hx2i + 2.0 * P.hy2i;
-    P.eps_min = p->eps_min;
-    P.gamma = p->gamma;
-    P.eps_start = p->eps_min;
-    P.noff = in->noff;
-    P.S = g.S;
-    P.txm = g.txm;
-    P.tym = g.tym;
-    P.M = g.M;
+    ctx->hprob[in->slot] = rsp::dev_problem(in->prob, in->noff, g.S, g.txm, g.tym, g.M);
     ctx->hseg[in->slot].off = 2 * in->noff;
     ctx->hseg[in->slot].L = 2 * (long long)in->n;
     for (int q = 0; q < in->part.S; ++q) {
@@ -1165,7 +1176,8 @@ int engine_step(rsp_context* ctx, const std::vector<Inst*>& live, hipStream_t st
     const int k = in->k;
     if (es[q].status == kSubNumeric || !std::isfinite(in->Fn)) {
       // NaN or Inf in a local residual or direction, or in the assembled residual
-      in->status = RSP_ENUMERIC;
+      in->status = fail(RSP_ENUMERIC, "a local residual, Newton direction or the RASPEN residual is not "
+                                      "finite (NaN or Inf in the data, or a singular local Jacobian)");
       if (k <= RSP_HIST_MAX) in->hist.norm[k] = in->Fn;
       fin.push_back(in);
       continue;
@@ -1278,7 +1290,7 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
   in->thr = std::max(o.tol_outer, o.tol_outer * Fn);
   in->hist.norm[0] = Fn;
   if (!std::isfinite(Fn)) {   // NaN or Inf in the data or the start
-    in->status = RSP_ENUMERIC;
+    in->status = fail(RSP_ENUMERIC, "the residual of the start is not finite (NaN or Inf in the data)");
     in->Fn = Fn;
     return finish(ctx, one, st);
   }
@@ -1580,7 +1592,9 @@ int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out, d
     RSPCHK(read_norms(ctx, kLEval, 1, out, stream));
     *norm = ctx->hnorm[0];
   }
-  return es[0].status == rsp::kSubNumeric ? RSP_ENUMERIC : es[0].status;
+  if (es[0].status == rsp::kSubNumeric)
+    return fail(RSP_ENUMERIC, "a local residual or Newton direction is not finite");
+  return es[0].status;
 }
 
 int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream) {

@@ -394,8 +394,9 @@ def test_nan_input_is_not_reported_converged(R):
     prob = make_problem("rect23x17")
     yd, f = prob.inputs()
     yd[3, 4] = np.nan
-    st, hist, x, u = gpu_solve(R, prob, synth.Options(max_outer=3, max_inner=30), yd, f)
-    assert st != 0
+    with pytest.raises(R.RaspenError) as e:
+        gpu_solve(R, prob, synth.Options(max_outer=3, max_inner=30), yd, f)
+    assert e.value.code == R.RSP_ENUMERIC and "finite" in str(e.value)
 
 
 # ------------------------------------------------------------------ full-size workload (sampled)

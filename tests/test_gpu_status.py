@@ -57,7 +57,7 @@ def test_nonfinite_data_is_a_numeric_error(R, method, precision, bad):
         yd = yd * 1e200          # |K|^2 overflows: the residual norm is not finite
     with pytest.raises(R.RaspenError) as e:
         solve(R, prob, opts_with(TIGHT, precision=precision, max_outer=5), yd, f, method=method)
-    assert e.value.code == R.RSP_ENUMERIC
+    assert e.value.code == R.RSP_ENUMERIC and "finite" in str(e.value)
 
 
 def test_numeric_error_in_a_batch_is_per_instance(R):
