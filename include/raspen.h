@@ -210,6 +210,22 @@ int rsp_prolong(rsp_context* ctx, const double* tiles, double* out, hipStream_t 
 int rsp_local_residual(rsp_context* ctx, const double* x, const double* c, double eps,
                        double* out, double* norms, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid hipMalloc): rsp_local_residual without a
+   context and without any allocation.  The problem `prob` is partitioned as in
+   rsp_partition; yd (required), f (NULL: 0) are [ny][nx], x is [2][ny][nx], c, out
+   are tiles [S][2][tym][txm] (tym, txm from rsp_partition) and norms gets S doubles;
+   all device pointers on the current device, caller-owned.  The results are those of
+   rsp_local_residual on a context set up with the same problem and data.  The staging
+   (the instance's constants, the boxes and the halo tiles of R_i x) lives in a
+   library-owned device array of 32 MiB on each device, held until the process ends:
+   RSP_EINVAL when a problem needs more (S (txm + 2)(tym + 2) * 16 bytes plus the
+   tables), or for a tile wider than the supported one.  Stream-ordered; calls that
+   overlap on one device (another stream, another host thread) share the array and
+   race.  Calls no hipMalloc or hipFree. */
+int rsp_local_residual_noalloc(const rsp_problem* prob, const double* yd, const double* f, const double* x,
+                               const double* c, double eps, double* out, double* norms, hipStream_t stream);
+
 /* Local linear solves z_i = J_i^{-1} r_i with J_i = R_i F'_eps(x + P_i c_i) P_i
    (eq. (DerC) and the local Newton systems of Algorithm 1), by block-tridiagonal
    LU over grid lines.  c, rhs, z: tiles. */

@@ -118,6 +118,7 @@ SIGNATURES = [
     ("rsp_restrict", _I, [_P, _P, _P, _P]),
     ("rsp_prolong", _I, [_P, _P, _P, _P]),
     ("rsp_local_residual", _I, [_P, _P, _P, _D, _P, _P, _P]),
+    ("rsp_local_residual_noalloc", _I, [_PROB, _P, _P, _P, _P, _D, _P, _P, _P]),
     ("rsp_local_solve", _I, [_P, _P, _P, _D, _P, _P, _P]),
     ("rsp_eval", _I, [_P, _P, _I, _P, ctypes.POINTER(_D), _P]),
     ("rsp_jac_apply", _I, [_P, _P, _P, _P]),
@@ -269,6 +270,12 @@ def rsp_prolong(ctx, tiles, out, stream=None):
 def rsp_local_residual(ctx, x, c, eps, out, norms, stream=None):
     return _check(load().rsp_local_residual(ctx, _ptr(x), _ptr(c), eps, _ptr(out), _ptr(norms),
                                             _stream(stream)))
+
+
+def rsp_local_residual_noalloc(prob, yd, f, x, c, eps, out, norms, stream=None):
+    """rsp_local_residual without a context and without device allocation."""
+    return _check(load().rsp_local_residual_noalloc(ctypes.byref(prob), _ptr(yd), _ptr(f, True), _ptr(x),
+                                                    _ptr(c), eps, _ptr(out), _ptr(norms), _stream(stream)))
 
 
 def rsp_local_solve(ctx, x, c, eps, rhs, z, stream=None):
