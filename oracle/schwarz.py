@@ -25,6 +25,7 @@ import math
 from typing import List
 
 import numpy as np
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .krylov import gmres
@@ -179,9 +180,55 @@ class Raspen:
             out += prolong_core(sub, -self.lu[i].solve(rhs), self.n)
         return out
 
+    # -- second level: coarse correction ---------------------------------------
+    # The paper leaves a second level to future work (end of Section 5.3 and
+    # Section 6).  Reading taken here: the hybrid two-level Schwarz preconditioner
+    # P2 = Q + M^{-1}(I - F' Q) with the one-level RAS part M^{-1} = sum_i P~_i J_i^{-1} R_i
+    # and the coarse correction Q = Z (Z^T F'(x) Z)^{-1} Z^T, where column (i, field)
+    # of Z is the indicator of the non-overlapping box Omega~_i in that field.  With
+    # F_RAS ~ -M^{-1} F and F_RAS' ~ -M^{-1} F' (exact for affine F), the Newton system
+    # P2 F'(x) d = -P2 F(x) becomes
+    #     F_RAS'(x)(d - Q F'(x) d) - Q F'(x) d = -F_RAS(x) + (F_RAS'(x) + I) Q F(x),
+    # whose operator and right-hand side use only the Jacobian action of Algorithm 4,
+    # F'(x) of the whole system and the coarse solve.  The outer iteration and its
+    # stopping test are those of Algorithm 2.
+    def coarse_basis(self):
+        """Z: [2n][2S] sparse, column 2 i + f = indicator of Omega~_i in field f."""
+        n, S = self.n, len(self.subs)
+        rows, cols = [], []
+        for i, sub in enumerate(self.subs):
+            for fld in range(2):
+                rows.append(fld * n + sub.core_rows)
+                cols.append(np.full(sub.core_rows.size, 2 * i + fld))
+        r = np.concatenate(rows)
+        return sp.csr_matrix((np.ones(r.size), (r, np.concatenate(cols))), shape=(2 * n, 2 * S))
+
+    def coarse_operator(self, x, Z=None):
+        """A_0 = Z^T F'_eps_min(x) Z (dense [2S][2S])."""
+        Z = self.coarse_basis() if Z is None else Z
+        return (Z.T @ self.sys.jacobian(x, self.prob.eps_min) @ Z).toarray()
+
+    def two_level_newton_step(self, x, Fx, Z):
+        """The direction d of the two-level Newton system above (GMRES on its operator)."""
+        o = self.opts
+        eps = self.prob.eps_min
+        J = self.sys.jacobian(x, eps)
+        A0 = (Z.T @ J @ Z).toarray()
+
+        def Q(v):
+            return Z @ np.linalg.solve(A0, Z.T @ v)
+        QF = Q(self.sys.residual(x, eps))
+        rhs = -Fx + self.jac_apply(QF) + QF
+
+        def op(v):
+            qv = Q(J @ v)
+            return self.jac_apply(v - qv) - qv
+        return gmres(op, rhs, o.gmres_restart, o.gmres_rtol, o.max_gmres)
+
     # -- Algorithm 2 ----------------------------------------------------------
-    def solve(self, x0=None, snapshots=False):
-        """Returns dict(x, y, p, u, status, history[, snapshots])."""
+    def solve(self, x0=None, snapshots=False, coarse=False):
+        """Returns dict(x, y, p, u, status, history[, snapshots]).  coarse: the outer
+        Newton systems with the second level above (same iteration otherwise)."""
         p, o = self.prob, self.opts
         n = self.n
         x = np.zeros(2 * n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -201,8 +248,12 @@ class Raspen:
         status = info.status
         F0 = hist[0]["norm"]
         k = 0
+        Z = self.coarse_basis() if coarse else None
         while not (hist[-1]["norm"] <= max(o.tol_outer, o.tol_outer * F0)) and k < o.max_outer:
-            d, used, rel = gmres(self.jac_apply, -Fx, o.gmres_restart, o.gmres_rtol, o.max_gmres)
+            if coarse:
+                d, used, rel = self.two_level_newton_step(x, Fx, Z)
+            else:
+                d, used, rel = gmres(self.jac_apply, -Fx, o.gmres_restart, o.gmres_rtol, o.max_gmres)
             x = x + d
             k += 1
             Fx, info = self.eval_F(x, continuation=(o.continuation == CONT_EVERY))

@@ -468,3 +468,129 @@ def test_model_problem_local_rounding_floor():
     tol = paper_inner_tol(n, n)
     assert tol == pytest.approx(1e-8 * 451 ** 2)
     assert err < 1e-3 * tol                 # scaled: six orders of magnitude of room
+
+
+# ---------------------------------------------------------------- second level (coarse correction)
+def coarse_closed_form(prob, subs, dphi_sum, dg_sum, cpl_sum):
+    """A_0 = Z^T F' Z written out: for the indicator of a core of cw x ch nodes, the
+    5-point -Laplacian sums to h^-2 times the grid edges leaving the core (2 ch hx^-2 +
+    2 cw hy^-2 on the core itself, -(shared edges) h^-2 with the four neighbouring
+    cores, 0 otherwise); the pointwise blocks of F' sum over the core."""
+    hx2, hy2 = (prob.nx + 1) ** 2, (prob.ny + 1) ** 2
+    S = len(subs)
+    A0 = np.zeros((2 * S, 2 * S))
+    for i, a in enumerate(subs):
+        ax0, ax1, ay0, ay1 = a.core
+        for j, b in enumerate(subs):
+            bx0, bx1, by0, by1 = b.core
+            if i == j:
+                lap = 2 * (ay1 - ay0) * hx2 + 2 * (ax1 - ax0) * hy2
+            elif ay0 == by0 and (ax1 == bx0 or bx1 == ax0):
+                lap = -(ay1 - ay0) * hx2
+            elif ax0 == bx0 and (ay1 == by0 or by1 == ay0):
+                lap = -(ax1 - ax0) * hy2
+            else:
+                continue
+            for fld in range(2):
+                A0[2 * i + fld, 2 * j + fld] = lap
+        A0[2 * i, 2 * i] += dphi_sum[i]
+        A0[2 * i + 1, 2 * i + 1] += dphi_sum[i]
+        A0[2 * i, 2 * i + 1] = dg_sum[i]
+        A0[2 * i + 1, 2 * i] = cpl_sum[i]
+    return A0
+
+
+@pytest.mark.parametrize("nx,ny,sx,sy,ov,kind", [(23, 17, 3, 2, 2, synth.PHI_EXP), (31, 29, 4, 3, 1, synth.PHI_CUBIC)])
+def test_coarse_operator_closed_form(nx, ny, sx, sy, ov, kind):
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-3, mu=5e-3, eps_min=1e-4, sx=sx, sy=sy, overlap=ov, seed=3)
+    yd, f = prob.inputs()
+    ora = Raspen(prob, synth.Options(), yd, f)
+    rng = np.random.default_rng(4)
+    n = ora.n
+    x = np.concatenate([0.4 * rng.standard_normal(n), 0.01 * rng.standard_normal(n)])
+    y, p = x[:n], x[n:]
+    sums = [[], [], []]
+    for s in ora.subs:
+        r = s.core_rows
+        sums[0].append(pw.dphi(y[r], kind, prob.kappa).sum())
+        sums[1].append((pw.dg(p[r], prob.mu, prob.eps_min) / prob.nu).sum())
+        sums[2].append((pw.ddphi(y[r], kind, prob.kappa) * p[r] - 1.0).sum())
+    want = coarse_closed_form(prob, ora.subs, *sums)
+    got = ora.coarse_operator(x)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_coarse_correction_galerkin_property():
+    """Q = Z (Z^T F' Z)^{-1} Z^T makes the coarse residual of every correction vanish:
+    Z^T F'(x)(v - Q F'(x) v) = 0."""
+    prob = synth.Problem(nx=31, ny=29, phi=synth.PHI_EXP, nu=1e-3, mu=5e-3, eps_min=1e-6, sx=4, sy=3, overlap=2)
+    yd, f = prob.inputs()
+    ora = Raspen(prob, synth.Options(), yd, f)
+    rng = np.random.default_rng(5)
+    x = np.concatenate([0.3 * rng.standard_normal(ora.n), 0.01 * rng.standard_normal(ora.n)])
+    Z = ora.coarse_basis()
+    J = ora.sys.jacobian(x, prob.eps_min)
+    A0 = ora.coarse_operator(x, Z)
+    v = rng.standard_normal(2 * ora.n)
+    w = v - Z @ np.linalg.solve(A0, Z.T @ (J @ v))
+    r = Z.T @ (J @ w)
+    assert np.abs(r).max() <= 1e-10 * np.abs(Z.T @ (J @ v)).max()
+
+
+def test_two_level_operator_is_minus_identity_on_the_coarse_space():
+    """Affine F (phi = 0, mu = 0): the RASPEN Jacobian is -M^{-1} F' exactly, so the
+    two-level operator d -> F_RAS'(d - Q F' d) - Q F' d is minus the hybrid preconditioned
+    operator P2 F', which maps every coarse vector Z c to itself."""
+    prob = synth.Problem(nx=25, ny=21, phi=synth.PHI_ZERO, nu=1e-2, mu=0.0, eps0=1e-6, eps_min=1e-6,
+                         sx=3, sy=2, overlap=2, seed=8)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-13)
+    ora = Raspen(prob, opts, yd, f)
+    x = np.zeros(2 * ora.n)
+    ora.eval_F(x, continuation=False)
+    Z = ora.coarse_basis()
+    J = ora.sys.jacobian(x, prob.eps_min)
+    A0 = ora.coarse_operator(x, Z)
+    zc = Z @ np.random.default_rng(6).standard_normal(Z.shape[1])
+    qv = Z @ np.linalg.solve(A0, Z.T @ (J @ zc))
+    out = ora.jac_apply(zc - qv) - qv
+    assert np.abs(out + zc).max() <= 1e-10 * np.abs(zc).max()
+
+
+def test_two_level_raspen_linear_quadratic_case():
+    prob = synth.Problem(nx=21, ny=17, phi=synth.PHI_ZERO, nu=1e-3, mu=0.0, eps0=1e-6,
+                         eps_min=1e-6, sx=3, sy=2, overlap=2, seed=7)
+    yd, f = prob.inputs()
+    f = f + 0.3
+    xs = lq_direct(prob.nx, prob.ny, prob.nu, yd, f)
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-14, max_gmres=500)
+    out = Raspen(prob, opts, yd, f).solve(coarse=True)
+    assert out["outer"] == 1
+    assert np.max(np.abs(out["x"] - xs)) <= 1e-11 * np.max(np.abs(xs))
+
+
+@pytest.mark.parametrize("nx,ny,sx,sy,ov,kind", [(31, 31, 3, 3, 2, synth.PHI_CUBIC),
+                                                 (23, 17, 3, 2, 2, synth.PHI_EXP)])
+def test_two_level_raspen_equals_global_newton(nx, ny, sx, sy, ov, kind):
+    prob = synth.Problem(nx=nx, ny=ny, phi=kind, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=sx, sy=sy, overlap=ov, seed=11)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-13)
+    xg, info, s = global_newton(prob, opts, yd, f)
+    out = Raspen(prob, opts, yd, f).solve(coarse=True)
+    assert out["status"] == CONVERGED
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-11 * np.max(np.abs(xg))
+
+
+def test_two_level_takes_fewer_gmres_products():
+    """The purpose of the second level (end of Section 5.3): GMRES products per outer
+    step no longer grow as much with the number of subdomains."""
+    prob = synth.Problem(nx=63, ny=63, phi=synth.PHI_EXP, nu=1e-3, mu=5e-3, eps_min=1e-6, sx=4, sy=4,
+                         overlap=3, seed=2)
+    opts = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12)
+    yd, f = prob.inputs()
+    one = Raspen(prob, opts, yd, f).solve()
+    two = Raspen(prob, opts, yd, f).solve(coarse=True)
+    assert two["outer"] == one["outer"]
+    assert sum(h["gmres"] for h in two["history"]) < 0.8 * sum(h["gmres"] for h in one["history"])
+    assert np.max(np.abs(two["x"] - one["x"])) <= 1e-11 * np.max(np.abs(one["x"]))
