@@ -126,6 +126,13 @@ typedef struct rsp_options {
                           steps) and, if it then converges, ends with RSP_REFINE_FALLBACK.
                           < 0: never; 0 forces the switch at the first open x^k, k >= 1.  */
   double* eps_snapshots;  /* device, [record_eps_snapshots][2][ny][nx], caller-owned      */
+  int32_t coarse;         /* RASPEN only: 0 one level (the paper's method); 1 a second level
+                          for the outer Newton systems, which the paper leaves to future
+                          work (Sections 5.3, 6): the hybrid two-level Schwarz preconditioner
+                          with one coarse unknown per subdomain core and field and the
+                          coarse operator Z^T F'(x) Z.  Same outer iteration and fixed point,
+                          fewer GMRES products as subdomains are added; at most 32
+                          subdomains per row. */
 } rsp_options;
 
 #define RSP_HIST_MAX 64
@@ -241,6 +248,12 @@ int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out,
 
 /* Algorithm 4: out = F'_eps(x) d for the x of the last rsp_eval ([2][ny][nx]). */
 int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream);
+
+/* The operator of the two-level outer Newton systems (rsp_options.coarse = 1, which the
+   context must have been set up with): out = F'_RAS(x)(d - Q F'(x) d) - Q F'(x) d,
+   Q = Z (Z^T F'_eps_min(x) Z)^{-1} Z^T, with x the point of the last rsp_eval (passed
+   again here, [2][ny][nx]) and F'_RAS(x) its Jacobian action (Algorithm 4). */
+int rsp_coarse_jac_apply(rsp_context* ctx, const double* x, const double* d, double* out, hipStream_t stream);
 
 /* Algorithm 2 (RASPEN with eps-continuation in the local solves): from x^0 =
    (y0, p0) (both NULL for x^0 = 0) to y, p and u = D_eps_min(p), all [ny][nx].

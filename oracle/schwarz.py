@@ -226,9 +226,12 @@ class Raspen:
         return gmres(op, rhs, o.gmres_restart, o.gmres_rtol, o.max_gmres)
 
     # -- Algorithm 2 ----------------------------------------------------------
-    def solve(self, x0=None, snapshots=False, coarse=False):
-        """Returns dict(x, y, p, u, status, history[, snapshots]).  coarse: the outer
-        Newton systems with the second level above (same iteration otherwise)."""
+    def solve(self, x0=None, snapshots=False, coarse=None):
+        """Returns dict(x, y, p, u, status, history[, snapshots]).  coarse (default: the
+        options' `coarse`): the outer Newton systems with the second level above (same
+        iteration otherwise)."""
+        if coarse is None:
+            coarse = bool(getattr(self.opts, "coarse", 0))
         p, o = self.prob, self.opts
         n = self.n
         x = np.zeros(2 * n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)

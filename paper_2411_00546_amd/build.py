@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RSP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["kernels_local.hip", "kernels_global.hip", "kernels_factor.hip", "kernels_solve.hip",
-           "kernels_gmres.hip", "noalloc.hip", "raspen.cpp", "server.cpp", "tune.cpp"]
+           "kernels_gmres.hip", "kernels_coarse.hip", "noalloc.hip", "raspen.cpp", "server.cpp", "tune.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", "--offload-arch=" + ARCH,

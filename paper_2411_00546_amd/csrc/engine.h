@@ -19,7 +19,7 @@ using Clock = std::chrono::steady_clock;
 int fail(int code, const char* fmt, ...);
 
 struct Partition {
-  int S = 0, txm = 0, tym = 0;
+  int S = 0, txm = 0, tym = 0, sx = 0, sy = 0;
   std::vector<int4> box, core;   // (x0, x1, y0, y1) half-open
 };
 

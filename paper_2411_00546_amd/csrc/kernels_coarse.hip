@@ -1,0 +1,333 @@
+// Second level of RASPEN: a coarse correction for the outer Newton systems.
+//
+// The paper leaves a second level to future work (end of Section 5.3, Section 6).  The
+// one taken here is the hybrid two-level Schwarz preconditioner
+//   P2 = Q + M^{-1} (I - F' Q),  Q = Z A0^{-1} Z^T,  A0 = Z^T F'(x) Z,
+// with M^{-1} the one-level RAS part of the RASPEN Jacobian and Z the indicators of the
+// non-overlapping boxes (cores) per field: the coarse unknown (i, f) is subdomain i's
+// core in field f, numbered 2 i + f over the items of the batch.  On the RASPEN Newton
+// system it gives the operator
+//   d -> F_RAS'(x)(d - Z e) - Z e,  e = A0^{-1} Z^T F'(x) d,
+// and, because F_RAS'(x) w = -w - sum_i P~_i J_i^{-1} B_i w with B_i the one-node ring
+// outside Omega_i, this is -d - sum_i P~_i J_i^{-1} B_i (d - Z e): the Jacobian action of
+// Algorithm 4 whose ring values have the coarse values of their cores subtracted.
+//
+// A0 is block tridiagonal over the rows of cores: with the 2 sx coarse unknowns of core
+// row r (core column c, field f at 2 c + f), the diagonal block T_r holds the sums over
+// each core of the pointwise blocks of F' (phi'(y), g'(p) / nu, phi''(y) p - 1) plus the
+// 5-point Laplacian summed over cores: 2 (ch hx^-2 + cw hy^-2) on a cw x ch core itself,
+// -ch hx^-2 with its left and right neighbours; the coupling between rows r - 1 and r
+// is diagonal, -cw hy^-2 for core column c in both fields.  It is factored by block
+// elimination with explicit inverses of the Schur complements S_r = T_r - C S_{r-1}^{-1} C
+// (Gauss-Jordan with partial pivoting, one workgroup per instance), and A0^{-1} is
+// formed densely from them (2 S columns in blocks, many workgroups), so that each coarse
+// solve in GMRES is one dense product.
+#include "rsp_kernels.h"
+
+namespace rsp {
+
+namespace {
+
+constexpr int kCoarseThreads = 256;
+constexpr int kColBlock = 32;           // columns of A0^{-1} per workgroup
+
+// Width of core column c / height of core row r of an instance.
+__device__ __forceinline__ int core_w(const DevProblem& P, int c) { return min((c + 1) * P.cbx, P.nx) - c * P.cbx; }
+__device__ __forceinline__ int core_h(const DevProblem& P, int r) { return min((r + 1) * P.cby, P.ny) - r * P.cby; }
+
+// Sums over each core of phi'(y), g'(p) / nu and phi''(y) p - 1 at x (eps_min).
+__global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* __restrict__ x,
+                                                        double* __restrict__ sums) {
+  __shared__ double red[kBlock];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 co = I.core[s];
+  const int cw = co.y - co.x, ch = co.w - co.z;
+  const size_t n = (size_t)P.nx * P.ny;
+  const double* y = x + 2 * P.noff;
+  const double* p = y + n;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int e = threadIdx.x; e < cw * ch; e += kBlock) {
+    const int r = e / cw, q = e - r * cw;
+    const size_t g = (size_t)(co.z + r) * P.nx + (co.x + q);
+    const double yv = y[g], pv = p[g];
+    a += dphi_of(P.phi, yv, P.kappa);
+    b += dg_of(pv, P.mu, P.eps_min) * P.inv_nu;
+    c += ddphi_of(P.phi, yv, P.kappa) * pv - 1.0;
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) {
+    sums[3 * (size_t)s] = a;
+    sums[3 * (size_t)s + 1] = b;
+    sums[3 * (size_t)s + 2] = c;
+  }
+}
+
+// c[2 s + f] = sum over the core of item s of v (mode 0) or of (F'_eps_min(x) v) (mode 1),
+// field f.
+__global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, const double* __restrict__ x,
+                                                           const double* __restrict__ v,
+                                                           double* __restrict__ cv) {
+  __shared__ double red[kBlock];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 co = I.core[s];
+  const int cw = co.y - co.x, ch = co.w - co.z;
+  const size_t n = (size_t)P.nx * P.ny;
+  const double* vy = v + 2 * P.noff;
+  const double* vp = vy + n;
+  const double* y = x + 2 * P.noff;
+  const double* p = y + n;
+  double ay = 0.0, ap = 0.0;
+  for (int e = threadIdx.x; e < cw * ch; e += kBlock) {
+    const int r = e / cw, q = e - r * cw;
+    const int i = co.x + q, j = co.z + r;
+    const size_t g = (size_t)j * P.nx + i;
+    if (mode == 0) {
+      ay += vy[g];
+      ap += vp[g];
+      continue;
+    }
+    const double dy = vy[g], dp = vp[g];
+    const double ly = P.diag0 * dy - P.hx2i * ((i > 0 ? vy[g - 1] : 0.0) + (i + 1 < P.nx ? vy[g + 1] : 0.0))
+                      - P.hy2i * ((j > 0 ? vy[g - P.nx] : 0.0) + (j + 1 < P.ny ? vy[g + P.nx] : 0.0));
+    const double lp = P.diag0 * dp - P.hx2i * ((i > 0 ? vp[g - 1] : 0.0) + (i + 1 < P.nx ? vp[g + 1] : 0.0))
+                      - P.hy2i * ((j > 0 ? vp[g - P.nx] : 0.0) + (j + 1 < P.ny ? vp[g + P.nx] : 0.0));
+    const double yv = y[g], pv = p[g];
+    const double d1 = dphi_of(P.phi, yv, P.kappa);
+    ay += ly + d1 * dy + dg_of(pv, P.mu, P.eps_min) * P.inv_nu * dp;
+    ap += (ddphi_of(P.phi, yv, P.kappa) * pv - 1.0) * dy + lp + d1 * dp;
+  }
+  ay = block_sum(ay, red);
+  ap = block_sum(ap, red);
+  if (threadIdx.x == 0) {
+    cv[2 * (size_t)s] = ay;
+    cv[2 * (size_t)s + 1] = ap;
+  }
+}
+
+// Block elimination of A0 over the core rows: S_r^{-1} for r = 0 .. sy-1, one workgroup
+// per instance (blockIdx.x -> instance list[blockIdx.x]).  W = [S_r | I] is reduced to
+// [I | S_r^{-1}] by Gauss-Jordan with partial pivoting (rows are swapped).
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProblem* __restrict__ prob,
+                                                                  const int* __restrict__ list,
+                                                                  const GmState* __restrict__ gst,
+                                                                  const double* __restrict__ sums,
+                                                                  double* __restrict__ sinv) {
+  constexpr int LDW = 2 * kCoarseMaxNc + 1;
+  __shared__ double W[kCoarseMaxNc * LDW];
+  __shared__ double colk[kCoarseMaxNc];
+  __shared__ int piv;
+  const int q = list ? list[blockIdx.x] : (int)blockIdx.x;
+  if (gst && gst[q].done) return;
+  const DevProblem P = prob[q];
+  const int sx = P.csx, nc = 2 * sx, t = threadIdx.x;
+  double* Sq = sinv + P.sinv_off;
+  for (int r = 0; r < P.csy; ++r) {
+    const int ch = core_h(P, r);
+    for (int e = t; e < nc * 2 * nc; e += kCoarseThreads) {
+      const int a = e / (2 * nc), b = e - a * 2 * nc;
+      double v;
+      if (b < nc) {
+        const int ca = a >> 1, fa = a & 1, cb = b >> 1, fb = b & 1;
+        v = 0.0;
+        if (ca == cb) {
+          const double* sm = sums + 3 * (size_t)(P.sub0 + r * sx + ca);
+          const double lap = 2.0 * ch * P.hx2i + 2.0 * core_w(P, ca) * P.hy2i;
+          v = fa == fb ? lap + sm[0] : (fa == 0 ? sm[1] : sm[2]);
+        } else if (fa == fb && (ca == cb + 1 || cb == ca + 1)) {
+          v = -ch * P.hx2i;
+        }
+        if (r > 0) {
+          const double wa = core_w(P, ca) * P.hy2i, wb = core_w(P, cb) * P.hy2i;
+          v -= wa * wb * Sq[((size_t)(r - 1) * nc + a) * nc + b];
+        }
+      } else {
+        v = (b - nc == a) ? 1.0 : 0.0;
+      }
+      W[a * LDW + b] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < nc; ++k) {
+      if (t < 64) {   // pivot: largest |W[i][k]|, i >= k (ties to the smaller row)
+        double best = -1.0;
+        int bi = nc;
+        for (int i = k + t; i < nc; i += 64) {
+          const double m = fabs(W[i * LDW + k]);
+          if (m > best) {
+            best = m;
+            bi = i;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (t == 0) piv = bi < nc ? bi : k;
+      }
+      __syncthreads();
+      const int pr = piv;
+      if (pr != k) {
+        for (int b = t; b < 2 * nc; b += kCoarseThreads) {
+          const double u = W[k * LDW + b];
+          W[k * LDW + b] = W[pr * LDW + b];
+          W[pr * LDW + b] = u;
+        }
+        __syncthreads();
+      }
+      const double inv = 1.0 / W[k * LDW + k];
+      for (int i = t; i < nc; i += kCoarseThreads) colk[i] = W[i * LDW + k];
+      __syncthreads();
+      for (int b = t; b < 2 * nc; b += kCoarseThreads) W[k * LDW + b] *= inv;
+      __syncthreads();
+      for (int e = t; e < nc * 2 * nc; e += kCoarseThreads) {
+        const int a = e / (2 * nc), b = e - a * 2 * nc;
+        if (a != k) W[a * LDW + b] -= colk[a] * W[k * LDW + b];
+      }
+      __syncthreads();
+    }
+    for (int e = t; e < nc * nc; e += kCoarseThreads) {
+      const int a = e / nc, b = e - a * nc;
+      Sq[((size_t)r * nc + a) * nc + b] = W[a * LDW + nc + b];
+    }
+    __syncthreads();   // S_r^{-1} is read back by every thread for the next row
+  }
+}
+
+// A0^{-1} densely, kColBlock columns per workgroup (blockIdx.y -> instance, blockIdx.x ->
+// column block).  Column k (core row rk = k / nc, position lk) is the solution of
+// A0 z = e_k by the block sweeps g_r = S_r^{-1}(e_k[r] - C g_{r-1}),
+// z_r = g_r - S_r^{-1} C z_{r+1}; C = -diag(cw hy^-2), so -C multiplies by cw hy^-2.
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProblem* __restrict__ prob,
+                                                                   const int* __restrict__ list,
+                                                                   const GmState* __restrict__ gst,
+                                                                   const double* __restrict__ sinv,
+                                                                   double* __restrict__ ainv) {
+  __shared__ double Gl[kCoarseMaxNc * kColBlock];
+  const int q = list ? list[blockIdx.y] : (int)blockIdx.y;
+  if (gst && gst[q].done) return;
+  const DevProblem P = prob[q];
+  const int nc = 2 * P.csx, sy = P.csy, N = nc * sy, t = threadIdx.x;
+  const int k0 = blockIdx.x * kColBlock;
+  if (k0 >= N) return;
+  const double* Sq = sinv + P.sinv_off;
+  double* Aq = ainv + P.ainv_off;
+  constexpr int PER = kCoarseMaxNc * kColBlock / kCoarseThreads;   // (a, column) pairs per thread
+  double own[PER];
+  // forward sweep
+  for (int r = 0; r < sy; ++r) {
+    const double* Sr = Sq + (size_t)r * nc * nc;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kCoarseThreads;
+      const int a = e / kColBlock, kk = e - a * kColBlock, k = k0 + kk;
+      double v = 0.0;
+      if (a < nc && k < N) {
+        const int rk = k / nc, lk = k - rk * nc;
+        if (r == rk) {
+          v = Sr[(size_t)a * nc + lk];
+        } else if (r > rk) {
+          for (int b = 0; b < nc; ++b) v += Sr[(size_t)a * nc + b] * (core_w(P, b >> 1) * P.hy2i) * Gl[b * kColBlock + kk];
+        }
+      }
+      own[u] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kCoarseThreads;
+      const int a = e / kColBlock, kk = e - a * kColBlock, k = k0 + kk;
+      if (a < nc) {
+        Gl[a * kColBlock + kk] = own[u];
+        if (k < N) Aq[(size_t)(r * nc + a) * N + k] = own[u];
+      }
+    }
+    __syncthreads();
+  }
+  // backward sweep (the last block row is final); each thread reads back its own g_r
+  for (int r = sy - 2; r >= 0; --r) {
+    const double* Sr = Sq + (size_t)r * nc * nc;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kCoarseThreads;
+      const int a = e / kColBlock, kk = e - a * kColBlock, k = k0 + kk;
+      double v = 0.0;
+      if (a < nc && k < N) {
+        double acc = 0.0;
+        for (int b = 0; b < nc; ++b) acc += Sr[(size_t)a * nc + b] * (core_w(P, b >> 1) * P.hy2i) * Gl[b * kColBlock + kk];
+        v = Aq[(size_t)(r * nc + a) * N + k] + acc;
+      }
+      own[u] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + u * kCoarseThreads;
+      const int a = e / kColBlock, kk = e - a * kColBlock, k = k0 + kk;
+      if (a < nc) {
+        Gl[a * kColBlock + kk] = own[u];
+        if (k < N) Aq[(size_t)(r * nc + a) * N + k] = own[u];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// e[2 sub0 + r] = scale * sum_k A0^{-1}[r][k] c[2 sub0 + k] for the rows of the instance,
+// one wave per row (blockIdx.y -> instance, blockIdx.x -> rows 4 bx .. 4 bx + 3).
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(const DevProblem* __restrict__ prob,
+                                                                 const int* __restrict__ list,
+                                                                 const GmState* __restrict__ gst,
+                                                                 const double* __restrict__ ainv,
+                                                                 const double* __restrict__ cv, double scale,
+                                                                 double* __restrict__ ev) {
+  const int q = list ? list[blockIdx.y] : (int)blockIdx.y;
+  if (gst && gst[q].done) return;
+  const DevProblem P = prob[q];
+  const int N = 2 * P.csx * P.csy;
+  const int row = blockIdx.x * (kCoarseThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const double* Ar = ainv + P.ainv_off + (size_t)row * N;
+  const double* c = cv + 2 * (size_t)P.sub0;
+  double acc = 0.0;
+  for (int k = lane; k < N; k += 64) acc += Ar[k] * c[k];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) ev[2 * (size_t)P.sub0 + row] = scale * acc;
+}
+
+}  // namespace
+
+void launch_coarse_sums(const Items& I, const double* x, double* sums, hipStream_t st) {
+  if (I.count > 0) k_coarse_sums<<<I.count, kBlock, 0, st>>>(I, x, sums);
+}
+void launch_coarse_project(const Items& I, int mode, const double* x, const double* v, double* cv,
+                           hipStream_t st) {
+  if (I.count > 0) k_coarse_project<<<I.count, kBlock, 0, st>>>(I, mode, x, v, cv);
+}
+void launch_coarse_factor(const DevProblem* prob, const int* list, int count, const GmState* gst,
+                          const double* sums, double* sinv, hipStream_t st) {
+  if (count > 0) k_coarse_factor<<<count, kCoarseThreads, 0, st>>>(prob, list, gst, sums, sinv);
+}
+void launch_coarse_inverse(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
+                           const double* sinv, double* ainv, hipStream_t st) {
+  if (count > 0 && max_n > 0)
+    k_coarse_inverse<<<dim3((max_n + kColBlock - 1) / kColBlock, count), kCoarseThreads, 0, st>>>(prob, list, gst,
+                                                                                                  sinv, ainv);
+}
+void launch_coarse_solve(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
+                         const double* ainv, const double* cv, double scale, double* ev, hipStream_t st) {
+  constexpr int rows = kCoarseThreads / 64;
+  if (count > 0 && max_n > 0)
+    k_coarse_solve<<<dim3((max_n + rows - 1) / rows, count), kCoarseThreads, 0, st>>>(prob, list, gst, ainv, cv,
+                                                                                     scale, ev);
+}
+
+}  // namespace rsp

@@ -237,12 +237,21 @@ __device__ void sub_local_jacobian(const DevProblem& P, int s, int tx, int ty,
 }
 
 // Right-hand side of Algorithm 4 on the tile, lines [j0, j1): hx^-2 / hy^-2 times the
-// values of d just outside the tile (the ring), in line layout.
+// values of d just outside the tile (the ring), in line layout.  With the coarse
+// correction (ce != nullptr) the ring values are those of d - Z e: each has the coarse
+// value e of its node's core and field subtracted (core (gi / cbx, gj / cby) of the
+// instance, coarse unknown 2 (sub0 + core) + f).
 template <int M>
 __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty, int j0, int j1,
-                                         const double* __restrict__ d, double* gl) {
+                                         const double* __restrict__ d, const double* __restrict__ ce,
+                                         double* gl) {
   const size_t n = (size_t)P.nx * P.ny;
   d += 2 * P.noff;
+  auto val = [&](const double* df, int f, int gi, int gj) {
+    double v = df[(size_t)gj * P.nx + gi];
+    if (ce) v -= ce[2 * (size_t)(P.sub0 + (gj / P.cby) * P.csx + gi / P.cbx) + f];
+    return v;
+  };
   for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
@@ -250,10 +259,10 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
       const int f = i >= tx, a = i - f * tx;
       const int gi = bx.x + a, gj = bx.z + j;
       const double* df = d + f * n;
-      if (a == 0 && gi > 0) v += P.hx2i * df[(size_t)gj * P.nx + gi - 1];
-      if (a == tx - 1 && gi + 1 < P.nx) v += P.hx2i * df[(size_t)gj * P.nx + gi + 1];
-      if (j == 0 && gj > 0) v += P.hy2i * df[(size_t)(gj - 1) * P.nx + gi];
-      if (j == ty - 1 && gj + 1 < P.ny) v += P.hy2i * df[(size_t)(gj + 1) * P.nx + gi];
+      if (a == 0 && gi > 0) v += P.hx2i * val(df, f, gi - 1, gj);
+      if (a == tx - 1 && gi + 1 < P.nx) v += P.hx2i * val(df, f, gi + 1, gj);
+      if (j == 0 && gj > 0) v += P.hy2i * val(df, f, gi, gj - 1);
+      if (j == ty - 1 && gj + 1 < P.ny) v += P.hy2i * val(df, f, gi, gj + 1);
     }
     gl[e] = v;
   }
@@ -369,7 +378,8 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(Items I, const double* 
 // outside the tile, inward sweep, the half's lines g_j / h_j to gbuf.
 template <typename TF, int M>
 __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restrict__ facT,
-                                                    const double* __restrict__ d, double* __restrict__ gbuf) {
+                                                    const double* __restrict__ d, const double* __restrict__ ce,
+                                                    double* __restrict__ gbuf) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
   int s;
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restric
   const int j0 = half == 0 ? 0 : tw + 1, j1 = half == 0 ? tw : ty;   // lines of the half
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   double* gs = gbuf + (size_t)s * P.tym * M;
-  ring_rhs<M>(P, bx, tx, ty, j0, j1, d, gl);
+  ring_rhs<M>(P, bx, tx, ty, j0, j1, d, ce, gl);
   __syncthreads();
   if (half == 0) sweep_in<TF, M>(Fs, ty, 0, tw, 1, P.hy2i, gl, red);
   else sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, P.hy2i, gl, red);
@@ -394,7 +404,8 @@ __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restric
 template <typename TF, int M>
 __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restrict__ facT,
                                                      const double* __restrict__ gbuf,
-                                                     const double* __restrict__ d, double* __restrict__ out) {
+                                                     const double* __restrict__ d, const double* __restrict__ ce,
+                                                     double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
   int s;
@@ -409,7 +420,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restri
   const int jlo = half == 0 ? min(clo, tw) : tw + 1;   // lines read back (besides the twist)
   const int jhi = half == 0 ? tw - 1 : max(chi, tw);
   for (int e = jlo * M + threadIdx.x; e < (jhi + 1) * M; e += 4 * M) gl[e] = gs[e];
-  ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, gl);
+  ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, ce, gl);
   __syncthreads();
   for (int i = threadIdx.x; i < M; i += 4 * M) {
     double v = gl[(size_t)tw * M + i];
@@ -435,6 +446,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
                                                          const double* __restrict__ tilex,
                                                          const double* __restrict__ c,
                                                          const double* __restrict__ d,
+                                                         const double* __restrict__ ce,
                                                          double* __restrict__ out, int nref) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double rb[kMaxTile * M];
@@ -445,11 +457,11 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
   const int4 bx = I.box[s], co = I.core[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
-  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, gl);
+  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl);
   __syncthreads();
   full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, gl, red);
   for (int it = 0; it < nref; ++it) {
-    ring_rhs<M>(P, bx, tx, ty, 0, ty, d, rb);
+    ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, rb);
     __syncthreads();
     sub_local_jacobian<M>(P, s, tx, ty, tilex, c, P.eps_min, gl, rb);
     __syncthreads();
@@ -520,12 +532,13 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 }
 
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
-                      const double* c, const double* d, double* out, int nref, double* gbuf, hipStream_t st) {
+                      const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
+                      hipStream_t st) {
   if (I.count <= 0) return;
   const dim3 grid(I.count, 2);
   if (nref > 0) {
 #define RSP_REF(TT, MM) \
-  k_apply_refined<TT, MM><<<I.count, 4 * MM, 0, st>>>(I, (const TT*)facT, tilex, c, d, out, nref)
+  k_apply_refined<TT, MM><<<I.count, 4 * MM, 0, st>>>(I, (const TT*)facT, tilex, c, d, ce, out, nref)
     if (fp32) {
 #define RSP_CALL(MM) RSP_REF(float, MM)
       RSP_DISPATCH_M(M, RSP_CALL)
@@ -539,8 +552,8 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
     return;
   }
 #define RSP_TWO(TT, MM)                                                                        \
-  k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, gbuf);                    \
-  k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, out)
+  k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);                \
+  k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, ce, out)
   if (fp32) {
 #define RSP_CALL(MM) RSP_TWO(float, MM)
     RSP_DISPATCH_M(M, RSP_CALL)

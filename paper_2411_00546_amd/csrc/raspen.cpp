@@ -148,6 +148,7 @@ int validate_options(const rsp_options* o) {
     return fail(RSP_EINVAL, "record_eps_snapshots must be in 0..%d", RSP_HIST_MAX + 1);
   if (o->record_eps_snapshots > 0 && !o->eps_snapshots)
     return fail(RSP_EINVAL, "record_eps_snapshots needs the eps_snapshots array");
+  if (o->coarse != 0 && o->coarse != 1) return fail(RSP_EINVAL, "coarse must be 0 or 1");
   return 0;
 }
 
@@ -180,6 +181,8 @@ int make_partition(const rsp_problem* p, Partition* out) {
       out->tym = std::max(out->tym, b.w - b.z);
     }
   out->S = (int)out->box.size();
+  out->sx = p->sx;
+  out->sy = p->sy;
   if (out->txm > kMaxTile)
     return fail(RSP_EINVAL, "tile width %d exceeds the supported %d nodes", out->txm, kMaxTile);
   if (out->tym > kMaxTile)
@@ -207,6 +210,10 @@ namespace {
 struct Geometry {
   int ninst = 0, S = 0, txm = 0, tym = 0, M = 0;
   long long ntot = 0;   // nodes of the concatenated [ny][nx] arrays (instances 32-aligned)
+  // second level: entries of the coarse factors S_r^{-1} and of the dense A0^{-1} of all
+  // instances, the widest row of cores
+  long long sinv = 0, ainv = 0;
+  int csx_max = 0;
 };
 
 // Carves 256-byte aligned buffers; with base == nullptr it only counts the bytes,
@@ -242,6 +249,8 @@ struct Work {
   double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
   void* fac = nullptr;
   double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr;
+  // second level (rsp_options.coarse): core sums [3 S], coarse vectors [2 S], factors
+  double *csum = nullptr, *cvec = nullptr, *evec = nullptr, *sinv = nullptr, *ainv = nullptr;
 };
 
 void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x) {
@@ -284,6 +293,13 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->V = cv.take<double>((size_t)(o.gmres_restart + 1) * L);
   w->p1 = cv.take<double>(part);
   w->p2 = cv.take<double>(part);
+  if (o.coarse) {
+    w->csum = cv.take<double>(3 * S);
+    w->cvec = cv.take<double>(2 * S);
+    w->evec = cv.take<double>(2 * S);
+    w->sinv = cv.take<double>(g.sinv);
+    w->ainv = cv.take<double>(g.ainv);
+  }
 }
 
 Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns) {
@@ -294,6 +310,10 @@ Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vect
     g.txm = std::max(g.txm, parts[q]->txm);
     g.tym = std::max(g.tym, parts[q]->tym);
     g.ntot += ((long long)ns[q] + kAlignN - 1) / kAlignN * kAlignN;
+    const long long nc = 2LL * parts[q]->sx, N = nc * parts[q]->sy;
+    g.sinv += parts[q]->sy * nc * nc;
+    g.ainv += N * N;
+    g.csx_max = std::max(g.csx_max, parts[q]->sx);
   }
   g.M = line_block(g.txm);
   return g;
@@ -311,12 +331,14 @@ size_t layout_bytes(const Geometry& g, const rsp_options& o) {
 // Kernel timing: HIP events around launches, resolved at synchronisation points.
 enum Kid {
   KID_RESTRICT, KID_INIT, KID_FACTOR, KID_SOLVE_BWD, KID_LINESEARCH, KID_PROLONG, KID_RING,
-  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_PRECOND, KID_GJAC, KID_N
+  KID_BLOCK_SOLVE, KID_GMRES_ORTHO, KID_GLOBAL, KID_REFINE, KID_PRECOND, KID_GJAC, KID_COARSE,
+  KID_COARSE_SETUP, KID_N
 };
 const char* const kKidName[KID_N] = {"restrict_halo", "newton_init", "factor", "solve_bwd",
                                      "linesearch", "prolong", "ring_rhs", "block_solve",
                                      "gmres_ortho", "global_residual", "newton_refine",
-                                     "ras_precond", "global_jacobian"};
+                                     "ras_precond", "global_jacobian", "coarse_correction",
+                                     "coarse_setup"};
 
 struct Pending {
   int kid;
@@ -808,19 +830,52 @@ double ortho_bytes(double L, int q) { return 8.0 * L * (2.0 * q + 6); }
 
 // step >= 0: Arnoldi step of a GMRES cycle (its timing is settled by settle_gmres_timing).
 void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
-               hipStream_t st, int step = -1) {
+               hipStream_t st, int step = -1, const double* ce = nullptr) {
   Timed t(ctx, KID_BLOCK_SOLVE, st, apply_flops(ctx, sw), apply_bytes(ctx, sw), step);
-  rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, out, ctx->nref,
+  rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, ce, out, ctx->nref,
                         ctx->w.g, st);
+}
+
+// Largest number of coarse unknowns (2 S) over the instances of `set`.
+int coarse_max_n(const std::vector<Inst*>& set) {
+  int m = 0;
+  for (const Inst* in : set) m = std::max(m, 2 * in->part.S);
+  return m;
+}
+
+// Algorithmic work of the coarse correction in one GMRES product over the instances of
+// `set`: the core sums of F'(x) v (two vectors read, 28 flops per node) and the dense
+// coarse solve (2 S)^2.
+void coarse_work(const std::vector<Inst*>& set, double* fl, double* by) {
+  *fl = *by = 0;
+  for (const Inst* in : set) {
+    const double N = 2.0 * in->part.S;
+    *fl += 28.0 * in->n + 2 * N * N;
+    *by += 32.0 * in->n + 8 * N * N;
+  }
 }
 
 // The operator of GMRES on the instances of `set` (items I): the Jacobian action of
 // Algorithm 4, or (gm_op 1) F'_eps(x) of the whole system with each instance's current
 // smoothing.  skip_done: instances whose GMRES has stopped are skipped.
 void gm_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const std::vector<Inst*>& set,
-              const double* d, double* out, hipStream_t st, bool skip_done, int step = -1) {
+              const GmBatch& B, const double* d, double* out, hipStream_t st, bool skip_done, int step = -1) {
   if (ctx->gm_op == 0) {
     jac_apply(ctx, I, sw, d, out, st, step);
+    return;
+  }
+  if (ctx->gm_op == 2) {
+    // the two-level operator d -> -d - sum_i P~_i J_i^{-1} B_i (d - Z e), e = A0^{-1} Z^T F'(x) d
+    Work& w = ctx->w;
+    {
+      double fl, by;
+      coarse_work(set, &fl, &by);
+      Timed t(ctx, KID_COARSE, st, fl, by, step);
+      rsp::launch_coarse_project(I, 1, ctx->x, d, w.cvec, st);
+      rsp::launch_coarse_solve(w.prob, B.list, B.count, coarse_max_n(set), skip_done ? w.gst : nullptr, w.ainv,
+                               w.cvec, 1.0, w.evec, st);
+    }
+    jac_apply(ctx, I, sw, d, out, st, step, w.evec);
     return;
   }
   double L = 0;
@@ -884,6 +939,59 @@ int read_gm_headers(rsp_context* ctx, hipStream_t st) {
   return read_back(ctx, ctx->hgm.data(), ctx->w.gst, sizeof(GmState) * ctx->hgm.size(), st);
 }
 
+// Second level at the outer iterate x of the instances of `go` (list slot kLGo): the
+// coarse operator A0 = Z^T F'(x) Z is assembled, factored by core rows and inverted
+// densely, and the right-hand side of the two-level Newton system gets its coarse part:
+// b = -F_RAS(x) + (F_RAS'(x) + I) Q F(x) = -F_RAS(x) - sum_i P~_i J_i^{-1} B_i (Z e_F), with
+// e_F = A0^{-1} Z^T F(x) (Jacobian action on d = 0 with ring values -(-Z e_F)).
+// A0 = Z^T F'(x) Z of the instances of `set` (items I, device instance list ilist),
+// factored by rows of cores and inverted densely into the work arena.
+void coarse_factorize(rsp_context* ctx, const Items& I, const int* ilist, const std::vector<Inst*>& set,
+                      const double* x, hipStream_t st) {
+  Work& w = ctx->w;
+  double fl = 0, by = 0;
+  for (const Inst* in : set) {
+    const double N = 2.0 * in->part.S, nc = 2.0 * in->part.sx;
+    fl += 12.0 * in->n + in->part.sy * (2 * nc * nc * nc + 4 * nc * nc * N);
+    by += 16.0 * in->n + 8.0 * (N * N + in->part.sy * nc * nc);
+  }
+  Timed t(ctx, KID_COARSE_SETUP, st, fl, by);
+  rsp::launch_coarse_sums(I, x, w.csum, st);
+  rsp::launch_coarse_factor(w.prob, ilist, (int)set.size(), nullptr, w.csum, w.sinv, st);
+  rsp::launch_coarse_inverse(w.prob, ilist, (int)set.size(), coarse_max_n(set), nullptr, w.sinv, w.ainv, st);
+}
+
+int coarse_setup(rsp_context* ctx, const std::vector<Inst*>& go, const GmBatch& B, hipStream_t st) {
+  Work& w = ctx->w;
+  const Items I = items_of(ctx, w.list[kLGo], (int)ctx->hlist[kLGo].size());
+  const int max_n = coarse_max_n(go);
+  coarse_factorize(ctx, I, w.ilist[kLGo], go, ctx->x, st);
+  {
+    double fl = 0, by = 0;
+    for (const Inst* in : go) {
+      const double N = 2.0 * in->part.S;
+      fl += 28.0 * in->n + 2 * N * N;
+      by += 40.0 * in->n + 8.0 * N * N;
+    }
+    Timed t(ctx, KID_COARSE, st, fl, by);
+    for (const Inst* in : go)
+      rsp::launch_global_residual(ctx->hprob[in->slot], ctx->yd + in->noff, ctx->f + in->noff, ctx->x + 2 * in->noff,
+                                  in->prob.eps_min, w.r + 2 * in->noff, st);
+    rsp::launch_coarse_project(I, 0, nullptr, w.r, w.cvec, st);
+    rsp::launch_coarse_solve(w.prob, w.ilist[kLGo], (int)go.size(), max_n, nullptr, w.ainv, w.cvec, -1.0, w.evec,
+                             st);
+    rsp::launch_gm_zero(B, w.dx, st);
+  }
+  jac_apply(ctx, I, sub_work(ctx, go, false), w.dx, w.w, st, -1, w.evec);
+  rsp::launch_gm_axpy(B, 1.0, w.w, w.b, 1, st);
+  HIPCHK(hipGetLastError());
+  for (Inst* in : go) {
+    const double N = 2.0 * in->part.S;
+    in->flops += 40.0 * in->n + 2 * N * N;
+  }
+  return 0;
+}
+
 // Restarted GMRES(m), x_0 = 0, on the device for every instance of `go` (list slot
 // kLGo must hold go): dx = F'(x)^{-1} b with b = -F.  All instances run their cycles
 // in lockstep (a finished one is skipped through its stop flag); the host enqueues
@@ -895,6 +1003,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
   const size_t ldv = 2 * (size_t)ctx->geo.ntot;
   const GmBatch Bgo = gm_of(ctx, w.ilist[kLGo], (int)go.size());
   rsp::launch_gm_axpy(Bgo, -1.0, w.F, w.b, 0, st);
+  if (ctx->gm_op == 2) RSPCHK(coarse_setup(ctx, go, Bgo, st));
   rsp::launch_gm_init(Bgo, o.max_gmres, o.gmres_rtol, st);
   rsp::launch_gm_zero(Bgo, w.dx, st);
   rsp::launch_gm_sumsq(Bgo, w.b, w.p1, st);
@@ -915,7 +1024,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
       RSPCHK(launch_seq(ctx, GraphKey{SEQ_ARNOLDI, lslot, I.count, B.count, j0 * 1024 + chunk}, st,
                         [&](hipStream_t s) {
                           for (int q = j0; q < j0 + chunk; ++q) {
-                            gm_apply(ctx, I, sw, cyc, w.V + (size_t)q * ldv, w.w, s, true, q);
+                            gm_apply(ctx, I, sw, cyc, B, w.V + (size_t)q * ldv, w.w, s, true, q);
                             Timed tm(ctx, KID_GMRES_ORTHO, s, ortho_flops(L, q), ortho_bytes(L, q), q);
                             const int mode = q == 0 ? 0 : q == j0 ? 2 : 1;
                             rsp::launch_gm_arnoldi(B, w.V, q, w.w, w.p1, w.p2, mode, s);
@@ -941,7 +1050,7 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     lslot = kLCyc;
     const GmBatch Br = gm_of(ctx, w.ilist[kLCyc], (int)next.size());
     const Items Ir = items_of(ctx, w.list[kLCyc], (int)ctx->hlist[kLCyc].size());
-    gm_apply(ctx, Ir, sub_work(ctx, next, false), next, w.dx, w.w, st, false);
+    gm_apply(ctx, Ir, sub_work(ctx, next, false), next, Br, w.dx, w.w, st, false);
     rsp::launch_gm_residual(Br, w.b, w.w, w.r, st);
     rsp::launch_gm_sumsq(Br, w.r, w.p1, st);
     rsp::launch_gm_start(Br, w.V, w.r, w.p1, 0, st);
@@ -966,6 +1075,10 @@ int run_gmres(rsp_context* ctx, const std::vector<Inst*>& go, hipStream_t st) {
     }
     in->n_solve += (int64_t)in->part.S * (h.used + in->restarts);
     in->flops += sfl * (h.used + in->restarts);
+    if (ctx->gm_op == 2) {
+      const double N = 2.0 * in->part.S;
+      in->flops += (28.0 * in->n + 2 * N * N) * (h.used + in->restarts);
+    }
     if (!(h.rel <= h.rtol)) in->gm_stagnated = true;
   }
   return 0;
@@ -1046,6 +1159,9 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
     ns.push_back(in->n);
   }
   const Geometry g = geometry_of(pp, ns);
+  if (o.coarse && 2 * g.csx_max > rsp::kCoarseMaxNc)
+    return fail(RSP_EINVAL, "the second level supports at most %d subdomains per row (got %d)",
+                rsp::kCoarseMaxNc / 2, g.csx_max);
   Carve cg, cw;
   double *yd, *f, *x;
   Work w;
@@ -1119,13 +1235,26 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   ctx->opts = o;
   ctx->fp32 = o.precision == RSP_FP32_REFINED;
   ctx->nref = ctx->fp32 ? o.max_refine : 0;
+  ctx->gm_op = o.coarse ? 2 : 0;
   // tables
   ctx->hprob.assign(g.ninst, DevProblem{});
   ctx->hseg.assign(g.ninst, GmSeg{});
   std::vector<int4> hbox, hcore;
   std::vector<int> hinst;
+  long long sinv_off = 0, ainv_off = 0;
   for (const Inst* in : live) {
-    ctx->hprob[in->slot] = rsp::dev_problem(in->prob, in->noff, g.S, g.txm, g.tym, g.M);
+    DevProblem& P = ctx->hprob[in->slot];
+    P = rsp::dev_problem(in->prob, in->noff, g.S, g.txm, g.tym, g.M);
+    P.csx = in->part.sx;
+    P.csy = in->part.sy;
+    P.cbx = (in->prob.nx + in->part.sx - 1) / in->part.sx;
+    P.cby = (in->prob.ny + in->part.sy - 1) / in->part.sy;
+    P.sub0 = in->sub0;
+    P.sinv_off = sinv_off;
+    P.ainv_off = ainv_off;
+    const long long nc = 2LL * in->part.sx, N = nc * in->part.sy;
+    sinv_off += in->part.sy * nc * nc;
+    ainv_off += N * N;
     ctx->hseg[in->slot].off = 2 * in->noff;
     ctx->hseg[in->slot].L = 2 * (long long)in->n;
     for (int q = 0; q < in->part.S; ++q) {
@@ -1326,9 +1455,10 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
     // (no preconditioner: w.F holds F_eps(x^k) and GMRES solves F'(x^k) d = -F directly)
     in->ms_eval += ms_since(t);
     t = Clock::now();
+    const int gm_op = ctx->gm_op;
     ctx->gm_op = precond ? 0 : 1;
     const int gr = run_gmres(ctx, one, st);
-    ctx->gm_op = 0;
+    ctx->gm_op = gm_op;
     RSPCHK(gr);
     in->ms_gmres += ms_since(t);
     // relaxed backtracking: alpha = 1, 1/2, ... until ||F_eps(x + alpha d)|| <= sigma ||F_eps(x)||
@@ -1597,6 +1727,22 @@ int rsp_eval(rsp_context* ctx, const double* x, int continuation, double* out, d
   return es[0].status;
 }
 
+int rsp_coarse_jac_apply(rsp_context* ctx, const double* x, const double* d, double* out, hipStream_t stream) {
+  NEED_READY(ctx);
+  if (!ctx->opts.coarse) return fail(RSP_EINVAL, "the context was set up without the second level");
+  if (!x || !d || !out) return fail(RSP_EINVAL, "x, d and out are required");
+  std::vector<Inst*> set{&ctx->single};
+  RSPCHK(upload_lists(ctx, kLGo, set, stream));
+  const Items I = all_items(ctx);
+  Work& w = ctx->w;
+  coarse_factorize(ctx, I, w.ilist[kLGo], set, x, stream);
+  rsp::launch_coarse_project(I, 1, x, d, w.cvec, stream);
+  rsp::launch_coarse_solve(w.prob, w.ilist[kLGo], 1, coarse_max_n(set), nullptr, w.ainv, w.cvec, 1.0, w.evec, stream);
+  jac_apply(ctx, I, sub_work(ctx, set, false), d, out, stream, -1, w.evec);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 int rsp_jac_apply(rsp_context* ctx, const double* d, double* out, hipStream_t stream) {
   NEED_READY(ctx);
   std::vector<Inst*> set{&ctx->single};
@@ -1632,6 +1778,7 @@ int rsp_solve_newton_ras(rsp_context* ctx, const rsp_problem* prob, const rsp_op
   RSPCHK(rsp::validate_options(opts));
   if (!prob) return fail(RSP_EINVAL, "problem is NULL");
   if (opts->record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
+  if (opts->coarse) return fail(RSP_EINVAL, "the second level applies to RASPEN (rsp_solve, batch, server)");
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));
@@ -1651,6 +1798,7 @@ int rsp_solve_newton(rsp_context* ctx, const rsp_problem* prob, const rsp_option
   RSPCHK(rsp::validate_options(opts));
   if (!prob) return fail(RSP_EINVAL, "problem is NULL");
   if (opts->record_eps_snapshots) return fail(RSP_EINVAL, "eps snapshots are recorded by rsp_solve only");
+  if (opts->coarse) return fail(RSP_EINVAL, "the second level applies to RASPEN (rsp_solve, batch, server)");
   ctx->ready = false;
   std::vector<Inst> insts;
   RSPCHK(make_instances(1, prob, &yd, &f, &y0, &p0, &y, &p, &u, &insts));

@@ -27,7 +27,14 @@ struct DevProblem {
   int S;              // subdomains of the batch
   int txm, tym;       // largest tile width / height of the batch
   int M;              // padded line-block size (multiple of 16, >= 2*txm)
+  // partition and second level: csx x csy cores of width cbx / height cby (the last
+  // ones may be narrower); the instance's items are sub0 .. sub0 + csx csy - 1, row-major;
+  // offsets of its coarse factors S_r^{-1} and of the dense A0^{-1} in their arrays
+  int csx, csy, cbx, cby, sub0;
+  long long sinv_off, ainv_off;
 };
+
+constexpr int kCoarseMaxNc = 64;   // 2 csx: coarse unknowns of a row of cores (csx <= 32)
 
 // Work list of a per-subdomain launch.  Items are the (instance, subdomain) pairs
 // of the batch, numbered consecutively; workgroup b handles item list[b] (or b).

@@ -51,9 +51,26 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 // a9 (Algorithm 4): ring rhs of d, the local solves (+ nref FP64 refinement steps with
 // the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  Without refinement two
 // launches of two workgroups per subdomain (inward halves; twist + outward halves);
-// gbuf: [items][tym][M] scratch.
+// gbuf: [items][tym][M] scratch.  ce != nullptr: the ring values are those of d - Z ce
+// (the coarse correction, kernels_coarse.hip).
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
-                      const double* c, const double* d, double* out, int nref, double* gbuf, hipStream_t st);
+                      const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
+                      hipStream_t st);
+// Second level (kernels_coarse.hip).  Coarse vectors have 2 entries (fields) per item.
+// Sums over each core of phi'(y), g'(p) / nu, phi''(y) p - 1 at x (eps_min): sums[3 items].
+void launch_coarse_sums(const Items& I, const double* x, double* sums, hipStream_t st);
+// cv[2 s + f] = sum over the core of item s of v (mode 0) or F'_eps_min(x) v (mode 1).
+void launch_coarse_project(const Items& I, int mode, const double* x, const double* v, double* cv,
+                           hipStream_t st);
+// Block elimination of A0 = Z^T F' Z per instance of the list: S_r^{-1} into sinv.
+void launch_coarse_factor(const DevProblem* prob, const int* list, int count, const GmState* gst,
+                          const double* sums, double* sinv, hipStream_t st);
+// A0^{-1} densely into ainv (max_n: the largest 2 S of the listed instances).
+void launch_coarse_inverse(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
+                           const double* sinv, double* ainv, hipStream_t st);
+// ev = scale A0^{-1} cv on each listed instance's coarse unknowns.
+void launch_coarse_solve(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
+                         const double* ainv, const double* cv, double scale, double* ev, hipStream_t st);
 // Section 4 F(x, eps) on the whole grid of one instance and its control u(p)
 // (pointers at the instance's arrays).
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,

@@ -41,7 +41,8 @@ class rsp_options(ctypes.Structure):
                 ("max_gmres", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("continuation", ctypes.c_int32),
                 ("record_eps_snapshots", ctypes.c_int32), ("tol_inner_rel", ctypes.c_double),
-                ("fallback_rho", ctypes.c_double), ("eps_snapshots", ctypes.c_void_p)]
+                ("fallback_rho", ctypes.c_double), ("eps_snapshots", ctypes.c_void_p),
+                ("coarse", ctypes.c_int32)]
 
 
 _H = RSP_HIST_MAX + 1
@@ -122,6 +123,7 @@ SIGNATURES = [
     ("rsp_local_solve", _I, [_P, _P, _P, _D, _P, _P, _P]),
     ("rsp_eval", _I, [_P, _P, _I, _P, ctypes.POINTER(_D), _P]),
     ("rsp_jac_apply", _I, [_P, _P, _P, _P]),
+    ("rsp_coarse_jac_apply", _I, [_P, _P, _P, _P, _P]),
     ("rsp_solve", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
                        ctypes.POINTER(rsp_history), _P]),
     ("rsp_solve_newton_ras", _I, [_P, _PROB, _OPTS, _P, _P, _P, _P, _P, _P, _P,
@@ -208,7 +210,7 @@ def make_options(o, eps_snapshots=None):
                        o.gmres_restart, o.max_outer, o.max_inner, o.max_gmres, o.precision,
                        o.max_refine, o.continuation, k, getattr(o, "tol_inner_rel", -1.0),
                        getattr(o, "fallback_rho", 1.0),
-                       None if eps_snapshots is None else _ptr(eps_snapshots))
+                       None if eps_snapshots is None else _ptr(eps_snapshots), int(getattr(o, "coarse", 0)))
 
 
 # ---------------------------------------------------------------- entry points
@@ -293,6 +295,11 @@ def rsp_eval(ctx, x, continuation, out, stream=None):
 
 def rsp_jac_apply(ctx, d, out, stream=None):
     return _check(load().rsp_jac_apply(ctx, _ptr(d), _ptr(out), _stream(stream)))
+
+
+def rsp_coarse_jac_apply(ctx, x, d, out, stream=None):
+    """The two-level outer Newton operator at x (rsp_coarse_jac_apply)."""
+    return _check(load().rsp_coarse_jac_apply(ctx, _ptr(x), _ptr(d), _ptr(out), _stream(stream)))
 
 
 def rsp_solve(ctx, prob, opts, yd, f, y0, p0, y, p, u, stream=None):

@@ -103,6 +103,7 @@ class Options:
     record_eps_snapshots: int = 0   # snapshots of the first evaluation (GPU path only)
     tol_inner_rel: float = -1.0     # relative branch of the inner test (< 0: tol_inner)
     fallback_rho: float = 1.0       # FP32 -> FP64 switch (GPU path only; < 0: never)
+    coarse: int = 0                 # 1: second level for the outer Newton systems
 
 
 def subdomains_for(n: int, size: int = 32) -> int:
