@@ -7,7 +7,8 @@ RAS restriction/prolongation, outer Newton-GMRES) of the 511x511 precision workl
 mu = 5e-3, eps 1 -> 1e-8 halving, 16x16 subdomains (32x32 each) with overlap 4,
 GMRES(30) rtol 1e-10 with at most 300 products per outer step, outer tolerance 1e-10,
 inner tolerance 1e-8; FP32 line factors on the matrix cores, FP64 everything else.
-Inputs are resident in HBM before timing.
+By default the outer Newton systems take the second level (coarse correction), with
+the paper's one-level method timed beside it.  Inputs are resident in HBM before timing.
 
 Prints one JSON line: solves/s, per-solve latency percentiles, the FP64 solve timed
 beside it, each result's error against the oracle's stored solution of the same
@@ -39,10 +40,10 @@ BOUND = {"factor": ("mfma", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm",
          "ras_precond": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_jacobian": ("hbm", HBM_PEAK_GBS, "GB/s")}
 
 
-def workload(name, precision="fp64", max_refine=0):
+def workload(name, precision="fp64", max_refine=0, coarse=0):
     import synth
     prob = synth.config_by_name(name)
-    opts = synth.Options(precision=1 if precision == "mixed" else 0, max_refine=max_refine)
+    opts = synth.Options(precision=1 if precision == "mixed" else 0, max_refine=max_refine, coarse=coarse)
     return prob, opts
 
 
@@ -51,7 +52,8 @@ def describe(prob, opts):
                                                           prob.overlap),
             "grid": [prob.nx, prob.ny], "phi": ["0", "y^3", "exp(y)-1", "kappa(y^3+exp(kappa y))"][prob.phi],
             "nu": prob.nu, "mu": prob.mu, "eps": [prob.eps0, prob.eps_min], "gamma": prob.gamma,
-            "subdomains": [prob.sx, prob.sy], "overlap": prob.overlap, "gmres": [opts.gmres_restart, opts.gmres_rtol],
+            "subdomains": [prob.sx, prob.sy], "overlap": prob.overlap,
+            "gmres": [opts.gmres_restart, opts.gmres_rtol, opts.max_gmres],
             "tol_outer": opts.tol_outer, "tol_inner": opts.tol_inner,
             "precision": ("fp32 line factors, fp64 residuals / Newton / GMRES, %d extra refinement step(s) "
                           "per local solve" % opts.max_refine) if opts.precision == 1 else "fp64",
@@ -127,22 +129,36 @@ def cpu_baseline(prob, opts, hist, max_sub=64):
                 w = w - h * V[i]
         t_mgs = (time.perf_counter() - t0) / reps
         sample_s = t_iter * iters + t_factor * len(sample) + (t_apply_sub * len(sample) + t_mgs) * reps
+        # second level: the oracle's coarse correction per product (F'(x) v, the coarse solve)
+        t_coarse = 0.0
+        if getattr(opts, "coarse", 0):
+            Z = ora.coarse_basis()
+            J = ora.sys.jacobian(x0, prob.eps_min)
+            A0 = ora.coarse_operator(x0, Z)
+            t0 = time.perf_counter()
+            creps = 5
+            for _ in range(creps):
+                Z @ np.linalg.solve(A0, Z.T @ (J @ d))
+            t_coarse = (time.perf_counter() - t0) / creps
+            sample_s += t_coarse * creps
     S = hist["subdomains"]
     inner = hist["newton_iterations"]                              # local Newton iterations
     fac_extra = hist["factorizations"] - inner                    # factorisations at x^(i)
     per_solve = (inner * t_iter + fac_extra * t_factor + hist["jac_applies"] * S * t_apply_sub
-                 + hist["gmres_total"] * t_mgs)
+                 + hist["gmres_total"] * t_mgs + hist["jac_applies"] * t_coarse)
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1,
             "cores_available": len(os.sched_getaffinity(0)), "kind": "oracle",
             "seconds_per_solve": per_solve, "extrapolated_from_sample": True,
-            "units": {"t_iter": t_iter, "t_factor": t_factor, "t_apply_sub": t_apply_sub, "t_mgs": t_mgs},
+            "units": {"t_iter": t_iter, "t_factor": t_factor, "t_apply_sub": t_apply_sub, "t_mgs": t_mgs,
+                      "t_coarse": t_coarse},
             "sample": ("NumPy/SciPy oracle, 1 thread: first-evaluation local Newton solves of %d of the %d "
                        "subdomains (%d iterations, %.2f ms each), %d sparse LU factorisations (%.1f ms), "
                        "%d local Jacobian solves (%.2f ms), %d Gram-Schmidt sweeps of 16 vectors (%.1f ms); "
                        "scaled by this solve's counts (%d local Newton iterations, %d extra factorisations, "
-                       "%d RASPEN Jacobian products); %.1f s of CPU work"
+                       "%d RASPEN Jacobian products%s); %.1f s of CPU work"
                        % (len(sample), S, iters, 1e3 * t_iter, len(sample), 1e3 * t_factor, reps * len(sample),
                           1e3 * t_apply_sub, reps, 1e3 * t_mgs, inner, fac_extra, hist["jac_applies"],
+                          ", each with a coarse correction of %.1f ms" % (1e3 * t_coarse) if t_coarse else "",
                           sample_s))}
 
 
@@ -519,6 +535,9 @@ def main():
                     help="plain/small/precision workloads: RASPEN (Algorithm 2, the default), the "
                          "linearly RAS-preconditioned Newton with eps-continuation (rsp_solve_newton_ras) "
                          "or the unpreconditioned one (rsp_solve_newton)")
+    ap.add_argument("--coarse", type=int, default=1, choices=[0, 1],
+                    help="RASPEN: 1 (default) the two-level method (coarse correction of the outer "
+                         "Newton systems), with the paper's one-level method timed beside it; 0 one level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eps-errors", action="store_true",
                     help="skip the per-eps-step comparison with the oracle on sampled subdomains")
@@ -543,14 +562,17 @@ def main():
         run = run_batch_workload if args.workload == "batch" else run_serve_workload
         print(json.dumps(run(args, R)))
         return
-    prob, opts = workload(args.workload, args.precision, args.max_refine)
-    _, opts64 = workload(args.workload, "fp64")
+    coarse = args.coarse if args.method == "raspen" else 0
+    prob, opts = workload(args.workload, args.precision, args.max_refine, coarse)
+    _, opts64 = workload(args.workload, "fp64", 0, coarse)
+    _, opts_one = workload(args.workload, args.precision, args.max_refine, 0)
     yd, f = prob.inputs()
     dev = torch.device("cuda:0")
     ydt = torch.as_tensor(yd, dtype=torch.float64, device=dev).contiguous()
     ft = torch.as_tensor(f, dtype=torch.float64, device=dev).contiguous()
     y, p, u = (torch.empty_like(ydt) for _ in range(3))
     P, O, O64 = R.make_problem(prob), R.make_options(opts), R.make_options(opts64)
+    O1 = R.make_options(opts_one)
     ctx = R.rsp_context_create(0)
     tuning = None
     if not args.phases:
@@ -656,6 +678,16 @@ def main():
                                            if ref is not None else None)}
             if not err <= 1e-8:
                 raise RuntimeError("mixed-precision solution differs from FP64 by %.3e > 1e-8" % err)
+        one_level = None
+        if coarse:
+            # the paper's one-level method on the same workload, timed beside it
+            el1, lat1, hist1, _, x1 = solves(O1, args.steps, 1, False)
+            one_level = {"value": args.steps / el1, "unit": "solves/s", "ms_per_step": 1e3 * el1 / args.steps,
+                         "latency_ms": {"p50": float(np.percentile(np.array(lat1) * 1e3, 50)),
+                                        "p99": float(np.percentile(np.array(lat1) * 1e3, 99))},
+                         "outer": hist1["outer"], "gmres_its": hist1["gmres_its"],
+                         "rel_err_vs_oracle": (float(np.abs(x1 - ref["x"]).max() / np.abs(ref["x"]).max())
+                                               if ref is not None else None)}
         snaps = None
         if args.method == "raspen" and not args.no_eps_errors:
             snaps = {"mixed" if opts.precision == 1 else "fp64": snapshot_cores(O, sample)}
@@ -694,12 +726,15 @@ def main():
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64+f32" if opts.precision == 1 else "f64",
            "data": "synthetic (seeded Gaussian-bump y_d)",
-           "config": dict(desc, method=args.method),
+           "config": dict(desc, method=args.method + (" two-level (coarse correction of the outer Newton "
+                                                       "systems; the one-level method under one_level)"
+                                                       if coarse else "")),
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
            "gflops": hist["flops"] / (elapsed / args.steps) / 1e9,
            "solve": {"outer": hist["outer"], "gmres_its": hist["gmres_its"], "inner_max": hist["inner_max"],
                      "residual_final": hist["residual_final"], "norm": hist["norm"][-1]},
-           "fp64": cmp64, "vs_oracle": vs_oracle, "eps_step_errors": eps_err, "tuning": tuning,
+           "fp64": cmp64, "one_level": one_level, "vs_oracle": vs_oracle, "eps_step_errors": eps_err,
+           "tuning": tuning,
            "roofline": roof,
            "solve_roofline": solve_roofline(breakdown, opts.precision == 1, 1e3 * elapsed / args.steps),
            "kernels": kernels, "cpu_baseline": cpu}
