@@ -236,3 +236,42 @@ def test_batch_budget(R):
         assert e.value.code == R.RSP_ENOMEM
     finally:
         R.rsp_context_destroy(ctx)
+
+
+# draws of the uneven batch workload (synth.batch_instances: nu = 10^U(-4,-1), mu ~ U(0, 0.05),
+# phi in {y^3, exp(y) - 1}, 32 x 32-node subdomains, overlap 4, eps 1 -> 1e-8); the draws
+# with grids up to 127 x 127, whose oracle solves take seconds
+PARITY = synth.Options(tol_outer=1e-12, tol_inner=1e-9, gmres_rtol=1e-12)
+
+
+def batch_draws():
+    """The two draws with the smallest nu and the first two others (the smaller grids)."""
+    out = [p for p in synth.batch_instances(24) if max(p.nx, p.ny) <= 127]
+    low = sorted(out, key=lambda p: p.nu)[:2]
+    return low + [p for p in out if p not in low][:2]
+
+
+@pytest.fixture(scope="module")
+def draws():
+    probs = batch_draws()
+    refs = []
+    for p in probs:
+        yd, f = p.inputs()
+        refs.append(Raspen(p, PARITY, yd, f).solve()["x"])
+    return probs, refs
+
+
+@pytest.mark.parametrize("precision,coarse", [(0, 0), (1, 0), (1, 1)])
+def test_batch_workload_draws_match_oracle(R, draws, precision, coarse):
+    """FP64 within 1e-10 of the oracle, the mixed form (FP32 line factors, no refinement
+    step) within 1e-8, one level and two."""
+    probs, refs = draws
+    assert min(p.nu for p in probs) < 1e-3 and len({(p.nx, p.ny) for p in probs}) > 1
+    o = synth.Options(tol_outer=PARITY.tol_outer, tol_inner=PARITY.tol_inner, gmres_rtol=PARITY.gmres_rtol,
+                      precision=precision, max_refine=0, coarse=coarse)
+    st, hists, out = run_batch(R, probs, o)
+    assert st == 0
+    for q, p in enumerate(probs):
+        err = rel(out[q][0], refs[q])
+        print("draw %d (%dx%d, nu %.1e, mu %.3f, phi %d): error %.3e" % (q, p.nx, p.ny, p.nu, p.mu, p.phi, err))
+        assert err <= (1e-10 if precision == 0 else 1e-8), (q, err)

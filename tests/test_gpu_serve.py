@@ -169,3 +169,32 @@ def test_invalid_requests(R):
     with pytest.raises(R.RaspenError) as e:
         R.rsp_server_create(R.make_options(synth.Options(gmres_restart=0)))
     assert e.value.code == R.RSP_EINVAL
+
+
+def test_served_full_size_request_matches_oracle(R):
+    """A 255 x 255 request (8 x 8 subdomains) served among smaller ones, at the
+    workload's own tolerances: within 1e-8 of the oracle's stored solution of the same
+    problem and tolerances with FP32 line factors, one level and two."""
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("refs", os.path.join(here, "golden", "make_oracle_refs.py"))
+    refs = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(refs)
+    ref = refs.load("plain_cfg")["x"]
+    big = synth.config_plain()
+    for coarse in (0, 1):
+        o = synth.Options(precision=1, max_refine=0, coarse=coarse)
+        srv = R.rsp_server_create(R.make_options(o))
+        try:
+            bufs = [Buffers(p) for p in (REQS[0], big, REQS[5])]
+            tickets = [R.rsp_server_submit(srv, R.make_problem(p), b.yd, b.f, b.y, b.p, b.u)
+                       for p, b in zip((REQS[0], big, REQS[5]), bufs)]
+            res = [R.rsp_server_wait(srv, t, 120000.0) for t in tickets]
+        finally:
+            R.rsp_server_destroy(srv)
+        assert all(st == 0 for st, _ in res)
+        x, _ = bufs[1].result()
+        err = np.abs(x - ref).max() / np.abs(ref).max()
+        print("served 255^2 request, coarse %d: error vs oracle %.3e" % (coarse, err))
+        assert err <= 1e-8
