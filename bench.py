@@ -321,6 +321,15 @@ def batch_cpu_baseline(probs, opts, hists):
                       "counts of all %d instances" % (probs[big].nx, probs[big].ny, one["sample"], len(probs))}
 
 
+def serve_cpu_baseline(probs, opts, hists, count=32):
+    """Oracle cost of the request stream: unit costs measured (bounded sample) on the
+    largest of the first `count` requests, scaled by the counts of every request."""
+    out = batch_cpu_baseline(probs[:count], opts, hists[:count])
+    out["sample"] = "the first %d requests: %s" % (count, out["sample"])
+    out["seconds_per_request"] = 1.0 / out["value"]
+    return out
+
+
 def apply_tuning(R, ctx, args, prob, opts, yd, f):
     """--tune 1: the autotuner picks the execution settings on this workload's problem
     (graphs, Arnoldi chunk; the partition stays the workload's); else --graphs and
@@ -341,8 +350,9 @@ def run_batch_workload(args, R):
     import synth
     import torch
     probs = synth.batch_instances(args.count)
-    opts = synth.Options(precision=1 if args.precision == "mixed" else 0, max_refine=args.max_refine)
-    opts64 = synth.Options()
+    opts = synth.Options(precision=1 if args.precision == "mixed" else 0, max_refine=args.max_refine,
+                         coarse=args.coarse)
+    opts64 = synth.Options(coarse=args.coarse)
     inst = Instances(probs)
     P = [R.make_problem(pr) for pr in probs]
     O, O64 = R.make_options(opts), R.make_options(opts64)
@@ -411,7 +421,8 @@ def run_batch_workload(args, R):
             "data": "synthetic (seeded Gaussian-bump y_d)",
             "config": {"workload": "raspen_batch%d_grids63-255_32x32subdomains_ov4" % len(probs),
                        "instances": len(probs), "grids": sizes, "step": "one rsp_solve_batch of every instance",
-                       "precision": "fp32 line factors" if opts.precision == 1 else "fp64"},
+                       "precision": "fp32 line factors" if opts.precision == 1 else "fp64",
+                       "levels": 2 if args.coarse else 1},
             "latency_ms": pct([l / 1.0 for l in lat]),
             "per_instance_latency_ms": {"p50": float(np.percentile([h["ms_total"] for h in hists], 50)),
                                         "p99": float(np.percentile([h["ms_total"] for h in hists], 99))},
@@ -432,11 +443,11 @@ def run_serve_workload(args, R):
     # grids up to 511x511 (256 subdomains): the GMRES iterations of an outer step grow with the
     # subdomain count, so the cap on products per outer step is raised for this stream
     opts = synth.Options(precision=1 if args.precision == "mixed" else 0, max_refine=args.max_refine,
-                         max_gmres=1500)
+                         max_gmres=1500, coarse=args.coarse)
     _, probs = synth.request_stream(args.count, 1.0)
     inst = Instances(probs)
     P = [R.make_problem(pr) for pr in probs]
-    O, O64 = R.make_options(opts), R.make_options(synth.Options(max_gmres=1500))
+    O, O64 = R.make_options(opts), R.make_options(synth.Options(max_gmres=1500, coarse=args.coarse))
 
     # execution settings for the server's context, tuned on a median-size request
     mid = sorted(range(len(probs)), key=lambda q: probs[q].nx * probs[q].ny)[len(probs) // 2]
@@ -447,8 +458,8 @@ def run_serve_workload(args, R):
     finally:
         R.rsp_context_destroy(ctx)
 
-    def serve(arrivals):
-        srv = R.rsp_server_create(O, tune=tune)
+    def serve(arrivals, profile=False):
+        srv = R.rsp_server_create(O, tune=tune, profile_every=args.time_every if profile else 0)
         try:
             t0 = time.perf_counter()
             tickets = []
@@ -467,16 +478,17 @@ def run_serve_workload(args, R):
                 hists.append(h)
             el = time.perf_counter() - t0
             stats = R.rsp_server_stats(srv)
+            kstats = R.rsp_server_kernel_stats(srv) if profile else None
         finally:
             R.rsp_server_destroy(srv)
-        return el, hists, stats
+        return el, hists, (stats, kstats)
 
     serve(None)                                     # warm-up (code objects, allocations)
-    el_c, _, st_c = serve(None)
+    el_c, _, (st_c, _) = serve(None)
     capacity = len(probs) / el_c
     rate = 0.8 * capacity
     arrivals, _ = synth.request_stream(args.count, rate)
-    el_o, hists, st_o = serve(arrivals)
+    el_o, hists, (st_o, kst) = serve(arrivals, profile=True)
     xs = [inst.x(q) for q in range(len(probs))]
     ctx = R.rsp_context_create(0)
     try:
@@ -505,7 +517,9 @@ def run_serve_workload(args, R):
                             "mean_batch": st_c["mean_batch"]},
             "rel_err_mixed_vs_fp64": errs, "all_solves_per_s": st_o["solves_per_s"],
             "fp64_one_at_a_time": {"value": len(probs) / el1, "unit": "solves/s", "latency_ms": pct(lat1)},
-            "tuning": tuning, "roofline": None, "cpu_baseline": None}
+            "tuning": tuning, "roofline": kernel_roofline(kst, opts.precision == 1, None) if kst else None,
+            "levels": 2 if args.coarse else 1,
+            "cpu_baseline": None if args.no_cpu_baseline else serve_cpu_baseline(probs, opts, hists)}
 
 
 def main():

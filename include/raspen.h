@@ -374,6 +374,9 @@ typedef struct rsp_server_options {
   rsp_options opts;     /* solver options of every request                            */
   rsp_tuning tune;      /* execution settings of the server's context (gm_chunk 0:
                            the defaults); e.g. from rsp_autotune on a typical request */
+  int32_t profile_every;  /* 0: no kernel timing; N >= 1: HIP events around the Jacobian
+                           action (class "block_solve") in one of every N launch
+                           sequences of the main batch, read by rsp_server_kernel_stats */
 } rsp_server_options;
 
 #define RSP_TICKET_QUEUED 0
@@ -411,6 +414,12 @@ int rsp_server_wait(rsp_server* srv, uint64_t ticket, double timeout_ms, rsp_his
 
 /* Counters and latency percentiles (nearest rank) since the server started. */
 int rsp_server_stats(rsp_server* srv, rsp_server_report* out);
+
+/* Kernel timing of the main batch since the server started (profile_every > 0; as
+   rsp_kernel_stats: up to `max` entries into `out`, their number into `count`),
+   settled after each outer iteration of the worker. */
+struct rsp_kernel_stat;
+int rsp_server_kernel_stats(rsp_server* srv, struct rsp_kernel_stat* out, int max, int32_t* count);
 
 /* Finish every submitted request, then stop the worker and free the server. */
 int rsp_server_destroy(rsp_server* srv);

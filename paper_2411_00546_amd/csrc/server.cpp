@@ -59,6 +59,8 @@ struct rsp_server {
   std::vector<double> latencies;
   bool any_submit = false;
   Clock::time_point t_first, t_last;
+  // kernel timing of the main batch (profile_every > 0), settled after each step
+  std::vector<rsp_kernel_stat> kstat;
 };
 
 namespace {
@@ -163,6 +165,15 @@ void worker_main(rsp_server* s) {
     still.clear();
     int err64 = 0;
     if (err >= 0 && (!fb.empty() || !parked.empty())) err64 = step_fallback(s, fb, parked);
+    if (s->opts.profile_every > 0 && err >= 0) {
+      int32_t nk = 0;
+      std::vector<rsp_kernel_stat> ks(32);
+      if (rsp_kernel_stats(s->ctx, ks.data(), (int)ks.size(), &nk) >= 0) {
+        ks.resize(nk);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->kstat.swap(ks);
+      }
+    }
     std::vector<Request*> fb_still;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -207,6 +218,15 @@ int rsp_server_create(rsp_server** out, const rsp_server_options* opts) {
   if (opts->tune.gm_chunk != 0 && (r = rsp_set_tuning(s->ctx, &opts->tune)) < 0) {
     rsp_context_destroy(s->ctx);
     return r;
+  }
+  if (opts->profile_every < 0) {
+    rsp_context_destroy(s->ctx);
+    return fail(RSP_EINVAL, "profile_every must be >= 0");
+  }
+  if (opts->profile_every > 0) {
+    rsp_set_profiling(s->ctx, 1);
+    rsp_set_profiling_filter(s->ctx, "block_solve");
+    rsp_set_profiling_sample(s->ctx, opts->profile_every);
   }
   hipError_t e = hipSetDevice(opts->device);
   if (e == hipSuccess) e = hipStreamCreate(&s->stream);
@@ -314,6 +334,15 @@ int rsp_server_stats(rsp_server* s, rsp_server_report* out) {
     const double span = ms_between(s->t_first, s->t_last);
     out->solves_per_s = span > 0 ? 1000.0 * s->completed / span : 0.0;
   }
+  return 0;
+}
+
+int rsp_server_kernel_stats(rsp_server* s, rsp_kernel_stat* out, int max, int32_t* count) {
+  if (!s) return fail(RSP_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int n = 0;
+  for (; out && n < max && n < (int)s->kstat.size(); ++n) out[n] = s->kstat[n];
+  if (count) *count = out ? n : (int32_t)s->kstat.size();
   return 0;
 }
 

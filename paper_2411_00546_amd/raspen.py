@@ -88,7 +88,8 @@ class rsp_tuning(ctypes.Structure):
 
 class rsp_server_options(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t), ("opts", rsp_options), ("tune", rsp_tuning)]
+                ("hbm_budget", ctypes.c_size_t), ("opts", rsp_options), ("tune", rsp_tuning),
+                ("profile_every", ctypes.c_int32)]
 
 
 class rsp_server_report(ctypes.Structure):
@@ -141,6 +142,7 @@ SIGNATURES = [
     ("rsp_server_poll", _I, [_P, ctypes.c_uint64, _I32P]),
     ("rsp_server_wait", _I, [_P, ctypes.c_uint64, _D, ctypes.POINTER(rsp_history)]),
     ("rsp_server_stats", _I, [_P, ctypes.POINTER(rsp_server_report)]),
+    ("rsp_server_kernel_stats", _I, [_P, ctypes.POINTER(rsp_kernel_stat), _I, _I32P]),
     ("rsp_server_destroy", _I, [_P]),
     ("rsp_set_profiling", _I, [_P, _I]),
     ("rsp_set_profiling_filter", _I, [_P, ctypes.c_char_p]),
@@ -367,10 +369,11 @@ def rsp_batch_workspace_bytes(probs, opts):
     return load().rsp_batch_workspace_bytes(n, parr, ctypes.byref(opts))
 
 
-def rsp_server_create(opts, device=0, max_batch=0, hbm_budget=0, tune=None):
+def rsp_server_create(opts, device=0, max_batch=0, hbm_budget=0, tune=None, profile_every=0):
     """Start a server; opts: rsp_options of every request; tune: rsp_tuning or None."""
     h = ctypes.c_void_p()
-    so = rsp_server_options(device, max_batch, hbm_budget, opts, tune if tune is not None else rsp_tuning())
+    so = rsp_server_options(device, max_batch, hbm_budget, opts, tune if tune is not None else rsp_tuning(),
+                            profile_every)
     _check(load().rsp_server_create(ctypes.byref(h), ctypes.byref(so)))
     return h
 
@@ -400,6 +403,17 @@ def rsp_server_stats(srv):
     r = rsp_server_report()
     _check(load().rsp_server_stats(srv, ctypes.byref(r)))
     return {k: getattr(r, k) for k, _ in rsp_server_report._fields_}
+
+
+def rsp_server_kernel_stats(srv):
+    """Returns {name: dict(launches, ms, flops, bytes)} of the server's main batch."""
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.rsp_server_kernel_stats(srv, None, 0, ctypes.byref(n)))
+    arr = (rsp_kernel_stat * max(1, n.value))()
+    _check(lib.rsp_server_kernel_stats(srv, arr, n.value, ctypes.byref(n)))
+    return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
+            for a in arr[:n.value]}
 
 
 def rsp_server_destroy(srv):
