@@ -19,7 +19,7 @@
 // -ch hx^-2 with its left and right neighbours; the coupling between rows r - 1 and r
 // is diagonal, -cw hy^-2 for core column c in both fields.  It is factored by block
 // elimination with explicit inverses of the Schur complements S_r = T_r - C S_{r-1}^{-1} C
-// (Gauss-Jordan with partial pivoting, one workgroup per instance), and A0^{-1} is
+// (Gauss-Jordan, one workgroup per instance), and A0^{-1} is
 // formed densely from them (2 S columns in blocks, many workgroups), so that each coarse
 // solve in GMRES is one dense product.
 #include "rsp_kernels.h"
@@ -111,15 +111,22 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
 }
 
 // Block elimination of A0 over the core rows: S_r^{-1} for r = 0 .. sy-1, one workgroup
-// per instance (blockIdx.x -> instance list[blockIdx.x]).  W = [S_r | I] is reduced to
-// [I | S_r^{-1}] by Gauss-Jordan with partial pivoting (rows are swapped).
+// per instance (blockIdx.x -> instance list[blockIdx.x]).  A column diagonally dominant
+// S_r (the usual case: the Laplacian part dominates the pointwise sums) keeps its
+// diagonal pivots under partial pivoting and is inverted in place by Gauss-Jordan with
+// its pivots in order, one barrier per step (two buffers alternate); otherwise
+// W = [S_r | I] is reduced to [I | S_r^{-1}] with partial pivoting (rows swapped).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProblem* __restrict__ prob,
                                                                   const int* __restrict__ list,
                                                                   const GmState* __restrict__ gst,
                                                                   const double* __restrict__ sums,
                                                                   double* __restrict__ sinv) {
-  constexpr int LDW = 2 * kCoarseMaxNc + 1;
-  __shared__ double W[kCoarseMaxNc * LDW];
+  constexpr int LDW = 2 * kCoarseMaxNc + 1;                // W = [S_r | I], pivoting path
+  constexpr int LDB = kCoarseMaxNc + 1;                    // the two buffers of the in-place path
+  constexpr int kWords = 2 * kCoarseMaxNc * LDB;           // >= kCoarseMaxNc * LDW: both fit
+  static_assert(kWords >= kCoarseMaxNc * LDW, "LDS buffers");
+  constexpr int kPer = kCoarseMaxNc * kCoarseMaxNc / kCoarseThreads;
+  __shared__ double W[kWords];
   __shared__ double colk[kCoarseMaxNc];
   __shared__ int piv;
   const int q = list ? list[blockIdx.x] : (int)blockIdx.x;
@@ -127,6 +134,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
   const DevProblem P = prob[q];
   const int sx = P.csx, nc = 2 * sx, t = threadIdx.x;
   double* Sq = sinv + P.sinv_off;
+  double* const B0 = W;
+  double* const B1 = W + kCoarseMaxNc * LDB;
   for (int r = 0; r < P.csy; ++r) {
     const int ch = core_h(P, r);
     for (int e = t; e < nc * 2 * nc; e += kCoarseThreads) {
@@ -152,6 +161,72 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
       W[a * LDW + b] = v;
     }
     __syncthreads();
+    // column diagonal dominance of S_r (the left half of W)
+    if (t < 64) {
+      bool bad = false;
+      for (int b = t; b < nc; b += 64) {
+        double off = 0.0;
+        for (int a = 0; a < nc; ++a)
+          if (a != b) off += fabs(W[a * LDW + b]);
+        bad = bad || !(fabs(W[b * LDW + b]) > off);
+      }
+      const bool any_bad = __any(bad);
+      if (t == 0) piv = any_bad ? 1 : 0;
+    }
+    __syncthreads();
+    if (piv == 0) {
+      // in place, pivots in order: W -> S_r^{-1}.  Step k reads buffer `cur` and writes
+      // the other: a_kk <- 1 / a_kk, row k <- row k / a_kk, column k <- -column k / a_kk,
+      // a_ij <- a_ij - a_ik a_kj / a_kk.
+      {
+        // the buffers overlap W: every thread holds its entries before any is rewritten
+        double own[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = t + u * kCoarseThreads, a = e / nc, b = e - a * nc;
+          own[u] = e < nc * nc ? W[a * LDW + b] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = t + u * kCoarseThreads, a = e / nc, b = e - a * nc;
+          if (e < nc * nc) B0[a * LDB + b] = own[u];
+        }
+        __syncthreads();
+      }
+      double* cur = B0;
+      double* nxt = B1;
+      int ra[kPer], rb[kPer];   // this thread's entries (row, column), -1: none
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = t + u * kCoarseThreads;
+        ra[u] = e < nc * nc ? e / nc : -1;
+        rb[u] = e < nc * nc ? e - ra[u] * nc : -1;
+      }
+      for (int k = 0; k < nc; ++k) {
+        const double inv = 1.0 / cur[k * LDB + k];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int a = ra[u], b = rb[u];
+          if (a < 0) continue;
+          double v;
+          if (a == k) v = b == k ? inv : cur[k * LDB + b] * inv;
+          else if (b == k) v = -cur[a * LDB + k] * inv;
+          else v = cur[a * LDB + b] - cur[a * LDB + k] * inv * cur[k * LDB + b];
+          nxt[a * LDB + b] = v;
+        }
+        __syncthreads();
+        double* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+      }
+      for (int e = t; e < nc * nc; e += kCoarseThreads) {
+        const int a = e / nc, b = e - a * nc;
+        Sq[((size_t)r * nc + a) * nc + b] = cur[a * LDB + b];
+      }
+      __syncthreads();   // S_r^{-1} is read back by every thread for the next row
+      continue;
+    }
     for (int k = 0; k < nc; ++k) {
       if (t < 64) {   // pivot: largest |W[i][k]|, i >= k (ties to the smaller row)
         double best = -1.0;
