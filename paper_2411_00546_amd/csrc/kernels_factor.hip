@@ -29,6 +29,8 @@
 // The inverses are stored transposed, facT[s][j][b][a] = F_j[a][b], so that the
 // solves read them coalesced.  Lines are padded to M (multiple of 16) with an
 // identity block.
+#include <type_traits>
+
 #include "rsp_kernels.h"
 
 namespace rsp {
@@ -485,7 +487,7 @@ __device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
 // subdomain with a line that is not dominant is marked in fallback[s] and redone by
 // k_factor_pivot.  M / 16 waves per workgroup.
 template <typename T, int M>
-__global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __restrict__ tilex,
+__global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_factor_mfma(Items I, const double* __restrict__ tilex,
                                                        const double* __restrict__ c,
                                                        const SubState* __restrict__ state,
                                                        double eps_fixed, const double* __restrict__ rhs,
@@ -528,6 +530,15 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   auto state_at = [&](int jj, double& y, double& p) {
     y = tilex[halo_idx(P, s, 0, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 0, jj, t)] : 0.0);
     p = tilex[halo_idx(P, s, 1, jj + 1, t + 1)] + (c ? c[tile_idx(P, s, 1, jj, t)] : 0.0);
+  };
+  // The loads of state_at without the sums, so that the loads of the next line stay in
+  // flight while the current line is factored.
+  struct Raw { double xy, cy, xp, cp; };
+  auto fetch = [&](int jj, Raw& r) {
+    r.xy = tilex[halo_idx(P, s, 0, jj + 1, t + 1)];
+    r.xp = tilex[halo_idx(P, s, 1, jj + 1, t + 1)];
+    r.cy = c ? c[tile_idx(P, s, 0, jj, t)] : 0.0;
+    r.cp = c ? c[tile_idx(P, s, 1, jj, t)] : 0.0;
   };
   auto coefficients = [&](double y, double p) {
     la[t] = dphi_of(P.phi, y, P.kappa);
@@ -627,43 +638,40 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   using VT = typename Mfma<T>::V;
   constexpr int NB = M / 16;
   VT blk[NB];
-  auto form_block = [&](int mode) -> bool {
+  auto form_block = [&](auto mode_c) -> bool {
+    constexpr int mode = decltype(mode_c)::value;
     const int bl = lane & 15, b = 16 * wave + bl;
+    const bool act = b < m;
+    const int fc = b >= tx, bc = act ? b - fc * tx : 0;
+    const int r_l = act && bc > 0 ? b - 1 : -1, r_r = act && bc + 1 < tx ? b + 1 : -1;
+    const int r_c = act ? (fc ? bc : tx + bc) : -1;
+    // a padding column is the identity column: its previous inverse column is the
+    // identity column too (finite), which the zero scale removes
+    const T d_d = act ? (T)(P.diag0 + la[bc]) : (T)1, d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
+    const T sc = act ? nh4 : (T)0;
     T off = 0, dia = 0;
-    if (b < m) {
-      const int fc = b >= tx, bc = b - fc * tx;
-      const int r_l = bc > 0 ? b - 1 : -1, r_r = bc + 1 < tx ? b + 1 : -1;
-      const int r_c = fc ? bc : tx + bc;
-      const T d_d = (T)(P.diag0 + la[bc]), d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
+    for (int I = 0; I < NB; ++I) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = 16 * I + Mfma<T>::row(lane, r);
-          T v = 0;
-          if (a < m) {
-            T d = 0;
-            d = a == b ? d_d : d;
-            d = (a == r_l || a == r_r) ? d_x : d;
-            d = a == r_c ? d_c : d;
-            // -hy^-4 S^{-1} + D, rounded after the product and after the sum
-            v = mode == 0 ? d : add_rn(mul_rn(nh4, (T)blk[I][r]), d);
-          }
-          blk[I][r] = v;
-          if (a == b) dia = fabs(v);
-          else off += fabs(v);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) blk[I][r] = (T)(16 * I + Mfma<T>::row(lane, r) == b ? 1 : 0);
+      for (int r = 0; r < 4; ++r) {
+        int a = 16 * I + Mfma<T>::row(lane, r);
+        // the row tests are the same for every line; recomputing them here keeps the
+        // compiler from holding 3 NB * 4 lane masks in scalar registers across the line loop
+        asm volatile("" : "+v"(a));
+        T d = a == b ? d_d : (T)0;
+        d = (a == r_l || a == r_r) ? d_x : d;
+        d = a == r_c ? d_c : d;
+        // -hy^-4 S^{-1} + D, rounded after the product and after the sum (padding rows
+        // of an active column: 0)
+        const T v = mode == 0 ? d : add_rn(mul_rn(sc, (T)blk[I][r]), d);
+        blk[I][r] = v;
+        dia = a == b ? fabs(v) : dia;
+        off += a == b ? (T)0 : fabs(v);
       }
     }
     off = rows_sum(off);
     dia = rows_sum(dia);
-    return __syncthreads_or(b < m && !(dia >= off)) != 0;
+    return __syncthreads_or(act && !(dia >= off)) != 0;
   };
 
   // The inverse of line j goes to HBM straight from the registers (16-byte stores,
@@ -689,17 +697,17 @@ __global__ __launch_bounds__(4 * M) void k_factor_mfma(Items I, const double* __
   };
 
   bool bad = false;
-  double ynext = 0.0, pnext = 0.0;
-  if (nlines > 0 && t < tx) state_at(j0, ynext, pnext);
+  Raw next{0.0, 0.0, 0.0, 0.0};
+  if (nlines > 0 && t < tx) fetch(j0, next);
   for (int k = 0; k < nlines; ++k) {
     const int j = j0 + dir * k;
     if (t < tx) {
-      const double y = ynext, p = pnext;
-      if (k + 1 < nlines) state_at(j + dir, ynext, pnext);
+      const double y = next.xy + next.cy, p = next.xp + next.cp;
+      if (k + 1 < nlines) fetch(j + dir, next);
       coefficients(y, p);
     }
     __syncthreads();
-    if (form_block(k == 0 ? 0 : 1)) {
+    if (k == 0 ? form_block(std::integral_constant<int, 0>{}) : form_block(std::integral_constant<int, 1>{})) {
       bad = true;
       break;
     }
