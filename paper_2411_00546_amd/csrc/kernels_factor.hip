@@ -161,7 +161,9 @@ __device__ __forceinline__ double recip(double x) {
 //   read_lane(v, l): lane l, to every lane.
 template <int N>
 __device__ __forceinline__ int row_bcast_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x150 + N, 0xF, 0xF, false);
+  // every lane reads a lane of its own row, so no lane keeps its old value: the move
+  // needs no copy of the source
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
 }
 template <int R>
 __device__ __forceinline__ int col_bcast_i(int v) {
@@ -244,7 +246,10 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 // pivots in order, by one wave in registers: lane (i, r) = i + 16 r holds row i,
 // columns 4 r .. 4 r + 3.  Step k takes the pivot row from lane (k, r) (row_bcast),
 // the pivot-column entry of row i from lane (i, k / 4) (col_bcast) and the pivot from
-// lane (k, k / 4).
+// lane (k, k / 4).  Row i != k becomes a_i - m_i a_k with m_i = a_ik / a_kk, the pivot
+// row a_k / a_kk, and column k holds -m_i (row i != k) and 1 / a_kk (row k): one fused
+// multiply-add per entry with the row factor f_i = -m_i (f_k = 1 / a_kk, applied to a
+// zeroed pivot row), which is also the new column-k entry.
 template <typename T, int K>
 __device__ __forceinline__ void gj16_step(T (&own)[4], int li, int q4) {
   constexpr int KQ = K >> 2, KR = K & 3;
@@ -254,12 +259,10 @@ __device__ __forceinline__ void gj16_step(T (&own)[4], int li, int q4) {
   const T pcol = col_bcast<KQ>(own[KR]);
   const T inv = recip(read_lane(own[KR], K + 16 * KQ));
   const bool on_row = li == K;
+  const T f = on_row ? inv : -(pcol * inv);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const bool on_col = 4 * q4 + q == K;
-    const T tr = prow[q] * inv;
-    own[q] = on_col ? (on_row ? inv : -pcol * inv) : (on_row ? tr : fma(-pcol, tr, own[q]));
-  }
+  for (int q = 0; q < 4; ++q) own[q] = fma(f, prow[q], on_row ? (T)0 : own[q]);
+  own[KR] = q4 == KQ ? f : own[KR];
 }
 template <typename T, int K>
 __device__ __forceinline__ void gj16_steps(T (&own)[4], int li, int q4) {
@@ -432,12 +435,28 @@ __device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
   for (int K = 0; K < NB; ++K) {
     T* S = St + (K & 1) * M * PLD;
     if (J == K) {
+      if constexpr (sizeof(T) == 4) {
+        // FP32: lane (j, g) holds rows 4 g .. 4 g + 3 of column j, which is the row
+        // layout of gj16_steps for the transpose; inverting the transpose in place
+        // leaves A_KK^{-1} in accumulator layout, without a trip through LDS
 #pragma unroll
-      for (int I = 0; I < NB; ++I) tile_store<T>(S + 16 * I * PLD, PLD, c[I], lane);
-      T own[4];
-      load4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
-      gj16_steps<T, 0>(own, li, q4);
-      store4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
+        for (int I = 0; I < NB; ++I)
+          if (I != K) tile_store<T>(S + 16 * I * PLD, PLD, c[I], lane);
+        T own[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) own[q] = c[K][q];
+        gj16_steps<T, 0>(own, li, q4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[K][q] = own[q];
+        tile_store<T>(S + 16 * K * PLD, PLD, c[K], lane);
+      } else {
+#pragma unroll
+        for (int I = 0; I < NB; ++I) tile_store<T>(S + 16 * I * PLD, PLD, c[I], lane);
+        T own[4];
+        load4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
+        gj16_steps<T, 0>(own, li, q4);
+        store4<T>(S + (16 * K + li) * PLD + 4 * q4, own);
+      }
     }
     __syncthreads();
     if (J != K) {
@@ -460,9 +479,15 @@ __device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
       }
       c[K] = r;
     } else {
-      // new column K: A_IK <- -A_IK A_KK^{-1} (I != K), A_KK <- its inverse
+      // new column K: A_IK <- -A_IK A_KK^{-1} (I != K), A_KK <- its inverse (FP32: c[K]
+      // already holds it, in the B-operand layout)
       T b[4];
-      b_operand<T>(S + 16 * K * PLD, PLD, lane, b);
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = c[K][q];
+      } else {
+        b_operand<T>(S + 16 * K * PLD, PLD, lane, b);
+      }
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
         if (I == K) continue;
@@ -471,7 +496,7 @@ __device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
         V z = {0, 0, 0, 0};
         c[I] = mma16<T>(ai, b, (T)-1, z);
       }
-      c[K] = tile_load<T>(S + 16 * K * PLD, PLD, lane);
+      if constexpr (sizeof(T) != 4) c[K] = tile_load<T>(S + 16 * K * PLD, PLD, lane);
     }
   }
 }
