@@ -15,13 +15,17 @@
 // described in kernels_solve.hip).  The two chains are independent, so each
 // subdomain takes two workgroups, and the second one to finish factors the twist.
 //
-// Each line block is assembled in LDS and tested for column diagonal dominance.  A
-// dominant block (the usual case) is inverted by Gauss-Jordan with 16 x 16 pivot
-// blocks whose block products run on the matrix cores; partial pivoting would keep
-// its diagonal, so this is the same elimination.  The twist block adds the
+// Each line block is assembled and tested for column diagonal dominance with the rows
+// of y weighted by dom_w, a power of two near sqrt(nu) that balances the couplings
+// g'(p)/nu and phi''(y) p - 1 between the fields: the dominance of W S W^{-1},
+// W = diag(dom_w I, I), on which partial pivoting would keep the diagonal.  Without
+// pivoting, the elimination of S performs the operations of that of W S W^{-1} scaled
+// exactly by powers of two, so it is that elimination.  A dominant block (the usual
+// case) is inverted by Gauss-Jordan with 16 x 16 pivot blocks whose block products run
+// on the matrix cores.  The twist block adds the
 // contributions of both chains and need not be dominant: when it is not, its block
-// elimination checks the exact partial-pivoting condition (every multiplier at most 1
-// in magnitude) instead.  A subdomain where a test fails is redone by a second kernel
+// elimination checks the partial-pivoting condition of W Z W^{-1} exactly (every
+// weighted multiplier at most 1 in magnitude) instead.  A subdomain where a test fails is redone by a second kernel
 // with in-place Gauss-Jordan with partial pivoting in registers (rows are not moved:
 // step k pivots on row pr[k]; afterwards S^{-1}[a][b] = A[pr[a]][pinv[b]]): per step
 // the pivot is found inside the wave that holds the column, the column goes through
@@ -315,7 +319,8 @@ __device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c,
 //   A_KK <- A_KK^{-1},  A_KJ <- A_KK^{-1} A_KJ,  A_IK <- -A_IK A_KK^{-1},
 //   A_IJ <- A_IJ - A_IK A_KK^{-1} A_KJ                      (I, J != K),
 // checking the partial-pivoting condition on the way (for the twist line, whose block
-// need not be column diagonally dominant).  M / 16 waves; wave J owns column block J.
+// need not be column diagonally dominant), on the block with its rows of the first
+// field (rows below tx) weighted by wy, as the dominance test (see k_factor_mfma).  M / 16 waves; wave J owns column block J.
 // Wave K eliminates the whole column panel A[:, K] (a copy in Pn), which gives
 // A_KK^{-1} and the new column K at once and every multiplier a_ik / a_kk of the
 // elimination in natural order; if one exceeds 1 in magnitude for an unpivoted row,
@@ -323,7 +328,7 @@ __device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c,
 // left partly eliminated).  The other waves form their row-panel tile A_KK^{-1} A_KJ
 // and update their column.  Returns false otherwise.
 template <typename T, int M>
-__device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
+__device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
@@ -352,10 +357,11 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag) {
         for (int r = 0; r < NB; ++r) pcol[r] = Pn[(li + 16 * r) * PLD + k];
         const T piv = Pn[kk * PLD + k];
         const T inv = recip(piv);
+        const T wpiv = (kk < tx ? wy : (T)1) * fabs(piv);
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
           const int i = li + 16 * r;
-          swap |= i > kk && fabs(pcol[r]) > fabs(piv);
+          swap |= i > kk && (i < tx ? wy : (T)1) * fabs(pcol[r]) > wpiv;
           const bool on_row = i == kk;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -545,6 +551,9 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
   const int m = 2 * tx;
   const double hy4i = P.hy2i * P.hy2i;
   const T nh4 = (T)(-hy4i);
+  // row weight of the first field in the dominance tests (a power of two, so the
+  // weighted and the plain block take the same elimination arithmetic)
+  const T wy = (T)P.dom_w;
   const int half = blockIdx.y;
   const int j0 = half == 0 ? 0 : ty - 1, dir = half == 0 ? 1 : -1;
   const int nlines = half == 0 ? tw : ty - 1 - tw;
@@ -596,8 +605,9 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
           v = (mode == 0 ? (T)0 : (mode == 1 ? nh4 * prev : prev)) + d;
         }
         Mx[a * LD + b] = v;
-        if (a == b) dia = fabs(v);
-        else off += fabs(v);
+        const T wv = (a < tx ? wy : (T)1) * fabs(v);
+        if (a == b) dia = wv;
+        else off += wv;
       }
     } else {
       // padding: identity
@@ -690,8 +700,9 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
         // of an active column: 0)
         const T v = mode == 0 ? d : add_rn(mul_rn(sc, (T)blk[I][r]), d);
         blk[I][r] = v;
-        dia = a == b ? fabs(v) : dia;
-        off += a == b ? (T)0 : fabs(v);
+        const T wv = (a < tx ? wy : (T)1) * fabs(v);
+        dia = a == b ? wv : dia;
+        off += a == b ? (T)0 : wv;
       }
     }
     off = rows_sum(off);
@@ -801,7 +812,7 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
 #pragma unroll
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
     __syncthreads();
-  } else if (panel_gauss_jordan<T, M>(Mx, LD, Pn, &flag)) {
+  } else if (panel_gauss_jordan<T, M>(Mx, LD, Pn, &flag, tx, wy)) {
     if (t == 0) atomicExch(fallback + s, 1);
     return;
   }

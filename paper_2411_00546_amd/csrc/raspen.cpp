@@ -113,6 +113,10 @@ DevProblem dev_problem(const rsp_problem& p, long long noff, int S, int txm, int
   P.hx2i = 1.0 / (hx * hx);
   P.hy2i = 1.0 / (hy * hy);
   P.diag0 = 2.0 * P.hx2i + 2.0 * P.hy2i;
+  // Line blocks couple the fields through g'(p)/nu (rows of y, columns of p) and
+  // phi''(y) p - 1 (rows of p): weighting the rows of y by about sqrt(nu), rounded to a
+  // power of two, balances the two in the column dominance test of the line factors.
+  P.dom_w = std::ldexp(1.0, std::max(-60, std::min(0, (int)std::lround(0.5 * std::log2(p.nu)))));
   P.eps_min = p.eps_min;
   P.gamma = p.gamma;
   P.eps_start = p.eps_min;

@@ -21,6 +21,7 @@ struct DevProblem {
   double nu, inv_nu, mu;
   double hx2i, hy2i;  // 1/hx^2, 1/hy^2
   double diag0;       // 2/hx^2 + 2/hy^2
+  double dom_w;       // weight of the rows of y in the line factors' dominance test
   double eps_min, gamma;
   double eps_start;   // eps_0 of the local solves of the next evaluation
   long long noff;     // offset of this instance's [ny][nx] arrays

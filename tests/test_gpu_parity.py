@@ -89,6 +89,7 @@ class Case:
 PROBLEMS = {
     "small63": dict(nx=63, ny=63, sx=2, sy=2, overlap=2),
     "rect23x17": dict(nx=23, ny=17, sx=3, sy=2, overlap=2),
+    "rect23x17_pivot": dict(nx=23, ny=17, sx=3, sy=2, overlap=2),
     "tile40": dict(nx=80, ny=40, sx=2, sy=1, overlap=0),
     "ragged37x29": dict(nx=37, ny=29, sx=3, sy=4, overlap=3),
     "one_sub": dict(nx=12, ny=9, sx=1, sy=1, overlap=2),
@@ -189,7 +190,11 @@ def test_local_residual(R, name, phi):
 
 
 # ------------------------------------------------------------------ J_i^{-1}
+# rect23x17 with nu = 1e-6: every subdomain has a line block that is not column
+# dominant even with the rows of y weighted (checked with the oracle's Jacobians), so the
+# partial-pivoting factorisation runs; with nu = 1e-4 only the weighted test passes.
 @pytest.mark.parametrize("name,phi,nu", [("small63", synth.PHI_CUBIC, 1e-2), ("rect23x17", synth.PHI_EXP, 1e-4),
+                                         ("rect23x17_pivot", synth.PHI_EXP, 1e-6),
                                          ("tile40", synth.PHI_CUBIC, 1e-3), ("ragged37x29", synth.PHI_PAPER, 1e-3),
                                          ("thin", synth.PHI_CUBIC, 1e-2), ("one_sub", synth.PHI_ZERO, 1e-2)])
 def test_local_solve(R, name, phi, nu):
@@ -442,6 +447,7 @@ MIXED = synth.Options(tol_outer=1e-12, tol_inner=1e-11, gmres_rtol=1e-12, precis
 
 
 @pytest.mark.parametrize("name,phi,nu", [("small63", synth.PHI_CUBIC, 1e-2), ("rect23x17", synth.PHI_EXP, 1e-4),
+                                         ("rect23x17_pivot", synth.PHI_EXP, 1e-6),
                                          ("tile40", synth.PHI_CUBIC, 1e-3)])
 def test_local_solve_fp32_factors(R, name, phi, nu):
     """FP32 line inverses (no refinement in this entry point): the error is that of
