@@ -3,6 +3,11 @@
 Discretisation (Section 4, model problem; Section 5): Omega = (0,1)^2, A = -Laplacian
 by the 5-point finite-difference stencil with homogeneous Dirichlet data, nodal
 unknowns at the interior nodes, vectors ordered row-major [ny][nx] (x fastest).
+Assumption 1 (3) allows any symmetric uniformly elliptic A = -div(a grad) + a0; for a
+diagonal coefficient tensor (a1, a2) and a0 >= 0 the same stencil in flux form gives
+  (A y)_ij = sum over the four faces f of node ij of a_f (y_ij - y_nb(f)) / h_f^2 + a0_ij y_ij
+with a1 at the x-faces, a2 at the y-faces and y = 0 on the boundary
+(``variable_operator``; face layout as ``synth.coefficient_fields``).
 
 Unknown x = (y, p) in R^{2n}, n = nx*ny.  With g(p) = p + mu P_eps(-p/mu):
 
@@ -32,17 +37,48 @@ def laplacian(nx, ny):
             + sp.kron(laplacian_1d(ny, hy), sp.identity(nx))).tocsr()
 
 
+def variable_operator(nx, ny, ax, ay, a0):
+    """A = Dx^T diag(ax / hx^2) Dx + Dy^T diag(ay / hy^2) Dy + diag(a0): Dx takes the
+    difference y_i - y_{i-1} across each x-face (i = 0..nx, with the boundary values
+    zero), Dy across each y-face.  ax: [ny][nx+1], ay: [ny+1][nx], a0: [ny][nx]."""
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    n = nx * ny
+    rows, cols, vals = [], [], []
+    for j in range(ny):
+        for i in range(nx + 1):
+            r = j * (nx + 1) + i
+            if i < nx:
+                rows.append(r); cols.append(j * nx + i); vals.append(1.0)
+            if i > 0:
+                rows.append(r); cols.append(j * nx + i - 1); vals.append(-1.0)
+    Dx = sp.csr_matrix((vals, (rows, cols)), shape=(ny * (nx + 1), n))
+    rows, cols, vals = [], [], []
+    for j in range(ny + 1):
+        for i in range(nx):
+            r = j * nx + i
+            if j < ny:
+                rows.append(r); cols.append(j * nx + i); vals.append(1.0)
+            if j > 0:
+                rows.append(r); cols.append((j - 1) * nx + i); vals.append(-1.0)
+    Dy = sp.csr_matrix((vals, (rows, cols)), shape=((ny + 1) * nx, n))
+    A = (Dx.T @ sp.diags(np.ravel(ax) / (hx * hx)) @ Dx + Dy.T @ sp.diags(np.ravel(ay) / (hy * hy)) @ Dy
+         + sp.diags(np.ravel(a0)))
+    return A.tocsr()
+
+
 class System:
     """F_eps and F'_eps for one problem instance.
 
-    prob: a synth.Problem (nx, ny, phi, kappa, nu, mu); yd, f: [ny][nx] arrays.
+    prob: a synth.Problem (nx, ny, phi, kappa, nu, mu; with coef set, A takes the
+    problem's coefficient fields); yd, f: [ny][nx] arrays.
     """
 
     def __init__(self, prob, yd, f=None):
         self.prob = prob
         self.nx, self.ny = prob.nx, prob.ny
         self.n = prob.nx * prob.ny
-        self.A = laplacian(prob.nx, prob.ny)
+        cf = prob.coefficients() if getattr(prob, "coef", 0) else None
+        self.A = laplacian(prob.nx, prob.ny) if cf is None else variable_operator(prob.nx, prob.ny, *cf)
         self.yd = np.asarray(yd, dtype=np.float64).reshape(-1).copy()
         self.f = (np.zeros(self.n) if f is None
                   else np.asarray(f, dtype=np.float64).reshape(-1).copy())

@@ -60,10 +60,52 @@ def random_state(nx: int, ny: int, seed: int, scale_y: float = 0.5,
     return y, p
 
 
+def smooth_field(xs, ys, seed: int, nbumps: int = 4) -> np.ndarray:
+    """A smooth field at the points (xs, ys) (equal-shape arrays): the sum of
+    ``nbumps`` Gaussian bumps.  Draw order (one ``numpy.random.default_rng(seed)``), per
+    bump: centre x ~ U[0, 1], centre y ~ U[0, 1], width ~ U[0.1, 0.3], amplitude ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(np.shape(xs), dtype=np.float64)
+    for _ in range(nbumps):
+        cx = rng.uniform(0.0, 1.0)
+        cy = rng.uniform(0.0, 1.0)
+        w = rng.uniform(0.1, 0.3)
+        a = rng.uniform(-1.0, 1.0)
+        out += a * np.exp(-((xs - cx) ** 2 + (ys - cy) ** 2) / (2.0 * w * w))
+    return out
+
+
+def coefficient_fields(nx: int, ny: int, seed: int):
+    """Coefficients of A y = -d/dx(a1 dy/dx) - d/dy(a2 dy/dy) + a0 y (a diagonal
+    coefficient tensor): a1 at the x-faces, a2 at the y-faces, a0 at the nodes.
+
+    a1 = exp(B1), a2 = exp(B2), a0 = 5 B3^2 with B1, B2, B3 smooth_field draws with
+    seeds 3 seed + 1, 3 seed + 2, 3 seed + 3.  Face (i, j) of ``ax`` ([ny][nx+1]) lies
+    between nodes i-1 and i of row j, at ((i + 1/2) hx, (j + 1) hy); face (i, j) of
+    ``ay`` ([ny+1][nx]) between rows j-1 and j of column i, at ((i + 1) hx, (j + 1/2) hy);
+    index -1 and nx (ny) are the Dirichlet boundary."""
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    xf, yf = np.meshgrid((np.arange(nx + 1) + 0.5) * hx, (np.arange(ny) + 1.0) * hy, indexing="xy")
+    ax = np.exp(smooth_field(xf, yf, 3 * seed + 1))
+    xg, yg = np.meshgrid((np.arange(nx) + 1.0) * hx, (np.arange(ny + 1) + 0.5) * hy, indexing="xy")
+    ay = np.exp(smooth_field(xg, yg, 3 * seed + 2))
+    X, Y = node_coords(nx, ny)
+    a0 = 5.0 * smooth_field(X, Y, 3 * seed + 3) ** 2
+    return ax, ay, a0
+
+
+def pack_coefficients(ax, ay, a0) -> np.ndarray:
+    """The coefficient layout of the C ABI: ax, ay, a0 back to back, float64."""
+    return np.concatenate([np.ravel(ax), np.ravel(ay), np.ravel(a0)]).astype(np.float64)
+
+
 @dataclasses.dataclass
 class Problem:
     """Problem data of the smoothed optimality system (paper, eq. (P) and the
-    reduced smoothed system of Section 3.2) plus the Schwarz partition."""
+    reduced smoothed system of Section 3.2) plus the Schwarz partition.
+
+    ``coef`` = 0: A = -Laplacian (the model problem); 1: A with the seeded variable
+    coefficients of ``coefficient_fields(nx, ny, seed)``."""
     nx: int
     ny: int
     phi: int = PHI_CUBIC
@@ -77,12 +119,19 @@ class Problem:
     sy: int = 2
     overlap: int = 2
     seed: int = 1
+    coef: int = 0
 
     def inputs(self):
         """(y_d, f) for this problem: bumps for y_d, f = 0."""
         yd = gaussian_bumps(self.nx, self.ny, self.seed)
         f = np.zeros((self.ny, self.nx), dtype=np.float64)
         return yd, f
+
+    def coefficients(self):
+        """(ax, ay, a0) of the operator, or None for the Laplacian (coef = 0)."""
+        if not self.coef:
+            return None
+        return coefficient_fields(self.nx, self.ny, self.seed)
 
 
 @dataclasses.dataclass

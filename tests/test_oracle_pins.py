@@ -594,3 +594,184 @@ def test_two_level_takes_fewer_gmres_products():
     assert two["outer"] == one["outer"]
     assert sum(h["gmres"] for h in two["history"]) < 0.8 * sum(h["gmres"] for h in one["history"])
     assert np.max(np.abs(two["x"] - one["x"])) <= 1e-11 * np.max(np.abs(one["x"]))
+
+
+# ---------------------------------------------------------------- variable coefficients of A
+# Assumption 1 (3): A = -div(a grad) + a0 with a diagonal coefficient tensor (a1, a2) and
+# a0 >= 0, in the 5-point flux form with face coefficients (oracle/system.py).
+from oracle.system import variable_operator  # noqa: E402
+
+
+def test_variable_operator_with_unit_coefficients_is_the_laplacian():
+    for nx, ny in [(7, 5), (1, 4), (12, 9)]:
+        A = variable_operator(nx, ny, np.ones((ny, nx + 1)), np.ones((ny + 1, nx)), np.zeros((ny, nx)))
+        assert abs(A - laplacian(nx, ny)).max() == 0
+
+
+@pytest.mark.parametrize("a1,a2,a0", [(2.5, 0.3, 0.0), (0.7, 4.0, 3.0)])
+def test_variable_operator_constant_coefficients_eigenpairs(a1, a2, a0):
+    """Constant coefficients: the sine vectors are eigenvectors with eigenvalue
+    a1 (4/hx^2) sin^2(k pi hx/2) + a2 (4/hy^2) sin^2(l pi hy/2) + a0."""
+    nx, ny = 9, 6
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    A = variable_operator(nx, ny, np.full((ny, nx + 1), a1), np.full((ny + 1, nx), a2), np.full((ny, nx), a0))
+    X, Y = synth.node_coords(nx, ny)
+    for k, l in [(1, 1), (3, 2), (9, 6), (5, 1)]:
+        v = (np.sin(k * math.pi * X) * np.sin(l * math.pi * Y)).reshape(-1)
+        lam = (a1 * 4 / hx ** 2 * math.sin(k * math.pi * hx / 2) ** 2
+               + a2 * 4 / hy ** 2 * math.sin(l * math.pi * hy / 2) ** 2 + a0)
+        assert np.max(np.abs(A @ v - lam * v)) < 1e-9 * lam
+
+
+def test_variable_operator_energy_identity_and_symmetry():
+    """y^T A y is the sum over all faces (boundary faces included, y = 0 outside) of
+    a_f (jump of y)^2 / h^2 plus the sum of a0 y^2; A is symmetric."""
+    nx, ny = 8, 6
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    ax, ay, a0 = synth.coefficient_fields(nx, ny, 4)
+    A = variable_operator(nx, ny, ax, ay, a0)
+    assert abs(A - A.T).max() == 0
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        y = rng.standard_normal((ny, nx))
+        yb = np.zeros((ny + 2, nx + 2))
+        yb[1:-1, 1:-1] = y
+        e = 0.0
+        for j in range(ny):
+            for i in range(nx + 1):            # x-face between nodes i-1 and i
+                e += ax[j, i] * (yb[j + 1, i + 1] - yb[j + 1, i]) ** 2 / hx ** 2
+        for j in range(ny + 1):
+            for i in range(nx):                # y-face between rows j-1 and j
+                e += ay[j, i] * (yb[j + 1, i + 1] - yb[j, i + 1]) ** 2 / hy ** 2
+        e += float(np.sum(a0 * y * y))
+        v = y.reshape(-1)
+        assert abs(v @ (A @ v) - e) <= 1e-12 * e
+
+
+def test_variable_operator_is_second_order_consistent():
+    """With the face coefficients taken at the face midpoints, A applied to the nodal
+    values of a smooth u converges to -d/dx(a1 u_x) - d/dy(a2 u_y) + a0 u (written out
+    by hand below) at second order."""
+    a1 = lambda x, y: 1.0 + x * x * y
+    a1x = lambda x, y: 2.0 * x * y
+    a2 = lambda x, y: 2.0 + np.sin(x)
+    a2y = lambda x, y: 0.0 * x
+    a0 = lambda x, y: 1.0 + x * y
+    u = lambda x, y: np.sin(np.pi * x) * np.sin(2 * np.pi * y)
+    ux = lambda x, y: np.pi * np.cos(np.pi * x) * np.sin(2 * np.pi * y)
+    uy = lambda x, y: 2 * np.pi * np.sin(np.pi * x) * np.cos(2 * np.pi * y)
+    uxx = lambda x, y: -np.pi ** 2 * u(x, y)
+    uyy = lambda x, y: -4 * np.pi ** 2 * u(x, y)
+    Lu = lambda x, y: -(a1x(x, y) * ux(x, y) + a1(x, y) * uxx(x, y)) - (a2y(x, y) * uy(x, y) + a2(x, y) * uyy(x, y)) \
+        + a0(x, y) * u(x, y)
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / (n + 1)
+        xf, yf = np.meshgrid((np.arange(n + 1) + 0.5) * h, (np.arange(n) + 1.0) * h, indexing="xy")
+        xg, yg = np.meshgrid((np.arange(n) + 1.0) * h, (np.arange(n + 1) + 0.5) * h, indexing="xy")
+        X, Y = synth.node_coords(n, n)
+        A = variable_operator(n, n, a1(xf, yf), a2(xg, yg), a0(X, Y))
+        errs.append(np.max(np.abs(A @ u(X, Y).reshape(-1) - Lu(X, Y).reshape(-1))))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def test_variable_coefficient_jacobian_central_difference():
+    prob = synth.Problem(nx=9, ny=7, phi=synth.PHI_EXP, nu=1e-2, mu=0.02, coef=1, seed=3)
+    rng = np.random.default_rng(1)
+    s = System(prob, rng.standard_normal((7, 9)), rng.standard_normal((7, 9)))
+    x = np.concatenate([0.5 * rng.standard_normal(s.n), 0.05 * rng.standard_normal(s.n)])
+    d = rng.standard_normal(2 * s.n)
+    t = 1e-6
+    fd = (s.residual(x + t * d, 1e-3) - s.residual(x - t * d, 1e-3)) / (2 * t)
+    Jd = s.jacobian(x, 1e-3) @ d
+    assert np.linalg.norm(fd - Jd) < 1e-6 * np.linalg.norm(Jd)
+
+
+@pytest.mark.parametrize("coarse", [False, True])
+def test_variable_coefficient_raspen_equals_global_newton(coarse):
+    prob = synth.Problem(nx=23, ny=17, phi=synth.PHI_EXP, nu=1e-2, mu=1e-2, eps0=1.0, eps_min=1e-6,
+                         gamma=0.5, sx=3, sy=2, overlap=2, seed=11, coef=1)
+    yd, f = prob.inputs()
+    opts = synth.Options(tol_outer=1e-13, tol_inner=1e-13, gmres_rtol=1e-13)
+    xg, info, s = global_newton(prob, opts, yd, f)
+    assert info.status == CONVERGED
+    out = Raspen(prob, opts, yd, f).solve(coarse=coarse)
+    assert out["status"] == CONVERGED
+    assert np.max(np.abs(out["x"] - xg)) <= 1e-11 * np.max(np.abs(xg))
+    # a different operator: the solution moves away from the Laplacian one
+    base = synth.Problem(**{**prob.__dict__, "coef": 0})
+    xl, _, _ = global_newton(base, opts, yd, f)
+    assert np.max(np.abs(xl - xg)) > 1e-3 * np.max(np.abs(xg))
+
+
+def coarse_closed_form_variable(prob, subs, dphi_sum, dg_sum, cpl_sum):
+    """Z^T F' Z for the variable-coefficient operator written out over faces: core I and
+    a different core J are coupled by minus the sum of a_f / h^2 over the faces between
+    them; the diagonal holds the sum of a_f / h^2 over every face with exactly one node
+    in the core (domain boundary faces included) plus the sum of a0 over the core."""
+    nx, ny = prob.nx, prob.ny
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    ax, ay, a0 = prob.coefficients()
+    owner = -np.ones((ny, nx), dtype=int)
+    for i, s in enumerate(subs):
+        c = s.core_rows
+        owner.reshape(-1)[c] = i
+    S = len(subs)
+    L = np.zeros((S, S))
+    for j in range(ny):
+        for i in range(nx + 1):
+            l = owner[j, i - 1] if i > 0 else -1
+            r = owner[j, i] if i < nx else -1
+            w = ax[j, i] / hx ** 2
+            if l != r:
+                if l >= 0:
+                    L[l, l] += w
+                if r >= 0:
+                    L[r, r] += w
+                if l >= 0 and r >= 0:
+                    L[l, r] -= w
+                    L[r, l] -= w
+    for j in range(ny + 1):
+        for i in range(nx):
+            d = owner[j - 1, i] if j > 0 else -1
+            u = owner[j, i] if j < ny else -1
+            w = ay[j, i] / hy ** 2
+            if d != u:
+                if d >= 0:
+                    L[d, d] += w
+                if u >= 0:
+                    L[u, u] += w
+                if d >= 0 and u >= 0:
+                    L[d, u] -= w
+                    L[u, d] -= w
+    for i, s in enumerate(subs):
+        L[i, i] += a0.reshape(-1)[s.core_rows].sum()
+    A0 = np.zeros((2 * S, 2 * S))
+    for fld in range(2):
+        A0[fld::2, fld::2] = L
+    for i in range(S):
+        A0[2 * i, 2 * i] += dphi_sum[i]
+        A0[2 * i + 1, 2 * i + 1] += dphi_sum[i]
+        A0[2 * i, 2 * i + 1] = dg_sum[i]
+        A0[2 * i + 1, 2 * i] = cpl_sum[i]
+    return A0
+
+
+def test_coarse_operator_closed_form_variable_coefficients():
+    prob = synth.Problem(nx=23, ny=17, phi=synth.PHI_EXP, nu=1e-3, mu=5e-3, eps_min=1e-4, sx=3, sy=2, overlap=2,
+                         seed=3, coef=1)
+    yd, f = prob.inputs()
+    ora = Raspen(prob, synth.Options(), yd, f)
+    rng = np.random.default_rng(4)
+    n = ora.n
+    x = np.concatenate([0.4 * rng.standard_normal(n), 0.01 * rng.standard_normal(n)])
+    y, p = x[:n], x[n:]
+    sums = [[], [], []]
+    for s in ora.subs:
+        r = s.core_rows
+        sums[0].append(pw.dphi(y[r], prob.phi, prob.kappa).sum())
+        sums[1].append((pw.dg(p[r], prob.mu, prob.eps_min) / prob.nu).sum())
+        sums[2].append((pw.ddphi(y[r], prob.phi, prob.kappa) * p[r] - 1.0).sum())
+    want = coarse_closed_form_variable(prob, ora.subs, *sums)
+    got = ora.coarse_operator(x)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
