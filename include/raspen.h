@@ -84,6 +84,18 @@ typedef struct rsp_problem {
   double gamma;           /* eps_{k+1} = max(gamma eps_k, eps_min), 0 < gamma < 1   */
   int32_t sx, sy;         /* boxes per direction, 1 <= s <= n, no box may be empty */
   int32_t overlap;        /* >= 0, nodes added on each side                        */
+  const double* coef;     /* NULL: A = -Laplacian (5-point).  Else device memory, caller-
+                             owned, valid until the call that reads it returns: the
+                             coefficients of A y = -d/dx(a1 dy/dx) - d/dy(a2 dy/dy) + a0 y,
+                             Assumption 1 (3) with a diagonal tensor, discretised in flux
+                             form, (A y)_ij = sum over the four faces f of node ij of
+                             a_f (y_ij - y_nb) / h_f^2 + a0_ij y_ij (y = 0 on the boundary).
+                             Three float64 arrays back to back: a1 at the x-faces,
+                             [ny][nx+1] (face i of row j between nodes i-1 and i), a2 at the
+                             y-faces, [ny+1][nx] (face j of column i between rows j-1 and
+                             j), a0 at the nodes, [ny][nx]; a1, a2 > 0 and a0 >= 0 are the
+                             caller's to ensure.  rsp_solve, rsp_setup, the batch and the
+                             server copy them into their workspace. */
 } rsp_problem;
 
 /* Solver options (paper Section 5 gives tol 1e-10, inner tol 1e-8, sigma 1.1).

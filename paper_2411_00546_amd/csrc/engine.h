@@ -41,6 +41,7 @@ struct Inst {
   double *y = nullptr, *p = nullptr, *u = nullptr;                        // caller's outputs
   int slot = -1;          // instance index in the current layout
   long long noff = 0;     // offset of its [ny][nx] arrays in the batch arrays
+  long long coff = -1;    // offset of its coefficient arrays of A (-1: A = -Laplacian)
   int sub0 = 0;           // its first item
   bool placed = false;    // x, y_d and f are in the current layout
   bool started = false;   // first evaluation done

@@ -17,7 +17,10 @@
 // each core of the pointwise blocks of F' (phi'(y), g'(p) / nu, phi''(y) p - 1) plus the
 // 5-point Laplacian summed over cores: 2 (ch hx^-2 + cw hy^-2) on a cw x ch core itself,
 // -ch hx^-2 with its left and right neighbours; the coupling between rows r - 1 and r
-// is diagonal, -cw hy^-2 for core column c in both fields.  It is factored by block
+// is diagonal, -cw hy^-2 for core column c in both fields.  With variable coefficients of
+// A the same structure holds with sums over faces: each coupling is minus the sum of
+// a_f / h^2 over the faces between the two cores, and the diagonal holds the sum over
+// the faces on the core's boundary plus the sum of a0 over the core.  It is factored by block
 // elimination with explicit inverses of the Schur complements S_r = T_r - C S_{r-1}^{-1} C
 // (Gauss-Jordan, one workgroup per instance), and A0^{-1} is
 // formed densely from them (2 S columns in blocks, many workgroups), so that each coarse
@@ -29,13 +32,17 @@ namespace rsp {
 namespace {
 
 constexpr int kCoarseThreads = 256;
+// per item of the core sums: phi'(y), g'(p)/nu, phi''(y) p - 1, and (variable
+// coefficients) the face couplings west, east, south, north and the sum of a0
+constexpr int kCSum = 8;
 constexpr int kColBlock = 32;           // columns of A0^{-1} per workgroup
 
 // Width of core column c / height of core row r of an instance.
 __device__ __forceinline__ int core_w(const DevProblem& P, int c) { return min((c + 1) * P.cbx, P.nx) - c * P.cbx; }
 __device__ __forceinline__ int core_h(const DevProblem& P, int r) { return min((r + 1) * P.cby, P.ny) - r * P.cby; }
 
-// Sums over each core of phi'(y), g'(p) / nu and phi''(y) p - 1 at x (eps_min).
+// Sums over each core of phi'(y), g'(p) / nu and phi''(y) p - 1 at x (eps_min), and
+// with variable coefficients the couplings over the core's four sides and its sum of a0.
 __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* __restrict__ x,
                                                         double* __restrict__ sums) {
   __shared__ double red[kBlock];
@@ -59,10 +66,38 @@ __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* _
   a = block_sum(a, red);
   b = block_sum(b, red);
   c = block_sum(c, red);
+  double* o = sums + kCSum * (size_t)s;
   if (threadIdx.x == 0) {
-    sums[3 * (size_t)s] = a;
-    sums[3 * (size_t)s + 1] = b;
-    sums[3 * (size_t)s + 2] = c;
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+  }
+  if (P.cx) {
+    double w = 0.0, e = 0.0, so = 0.0, no = 0.0, z = 0.0;
+    for (int r = threadIdx.x; r < ch; r += kBlock) {
+      w += c_w(P, co.x, co.z + r);
+      e += c_e(P, co.y - 1, co.z + r);
+    }
+    for (int q = threadIdx.x; q < cw; q += kBlock) {
+      so += c_s(P, co.x + q, co.z);
+      no += c_n(P, co.x + q, co.w - 1);
+    }
+    for (int el = threadIdx.x; el < cw * ch; el += kBlock) {
+      const int r = el / cw, q = el - r * cw;
+      z += P.c0[(size_t)(co.z + r) * P.nx + co.x + q];
+    }
+    w = block_sum(w, red);
+    e = block_sum(e, red);
+    so = block_sum(so, red);
+    no = block_sum(no, red);
+    z = block_sum(z, red);
+    if (threadIdx.x == 0) {
+      o[3] = w;
+      o[4] = e;
+      o[5] = so;
+      o[6] = no;
+      o[7] = z;
+    }
   }
 }
 
@@ -93,10 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
       continue;
     }
     const double dy = vy[g], dp = vp[g];
-    const double ly = P.diag0 * dy - P.hx2i * ((i > 0 ? vy[g - 1] : 0.0) + (i + 1 < P.nx ? vy[g + 1] : 0.0))
-                      - P.hy2i * ((j > 0 ? vy[g - P.nx] : 0.0) + (j + 1 < P.ny ? vy[g + P.nx] : 0.0));
-    const double lp = P.diag0 * dp - P.hx2i * ((i > 0 ? vp[g - 1] : 0.0) + (i + 1 < P.nx ? vp[g + 1] : 0.0))
-                      - P.hy2i * ((j > 0 ? vp[g - P.nx] : 0.0) + (j + 1 < P.ny ? vp[g + P.nx] : 0.0));
+    const double ly = apply_a(P, i, j, dy, i > 0 ? vy[g - 1] : 0.0, i + 1 < P.nx ? vy[g + 1] : 0.0,
+                              j > 0 ? vy[g - P.nx] : 0.0, j + 1 < P.ny ? vy[g + P.nx] : 0.0);
+    const double lp = apply_a(P, i, j, dp, i > 0 ? vp[g - 1] : 0.0, i + 1 < P.nx ? vp[g + 1] : 0.0,
+                              j > 0 ? vp[g - P.nx] : 0.0, j + 1 < P.ny ? vp[g + P.nx] : 0.0);
     const double yv = y[g], pv = p[g];
     const double d1 = dphi_of(P.phi, yv, P.kappa);
     ay += ly + d1 * dy + dg_of(pv, P.mu, P.eps_min) * P.inv_nu * dp;
@@ -144,15 +179,18 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
       if (b < nc) {
         const int ca = a >> 1, fa = a & 1, cb = b >> 1, fb = b & 1;
         v = 0.0;
+        const double* sa = sums + kCSum * (size_t)(P.sub0 + r * sx + ca);
+        const double* sb = sums + kCSum * (size_t)(P.sub0 + r * sx + cb);
         if (ca == cb) {
-          const double* sm = sums + 3 * (size_t)(P.sub0 + r * sx + ca);
-          const double lap = 2.0 * ch * P.hx2i + 2.0 * core_w(P, ca) * P.hy2i;
-          v = fa == fb ? lap + sm[0] : (fa == 0 ? sm[1] : sm[2]);
+          const double lap = P.cx ? sa[3] + sa[4] + sa[5] + sa[6] + sa[7]
+                                  : 2.0 * ch * P.hx2i + 2.0 * core_w(P, ca) * P.hy2i;
+          v = fa == fb ? lap + sa[0] : (fa == 0 ? sa[1] : sa[2]);
         } else if (fa == fb && (ca == cb + 1 || cb == ca + 1)) {
-          v = -ch * P.hx2i;
+          v = P.cx ? -(cb == ca + 1 ? sa[4] : sa[3]) : -ch * P.hx2i;
         }
         if (r > 0) {
-          const double wa = core_w(P, ca) * P.hy2i, wb = core_w(P, cb) * P.hy2i;
+          // couplings to the row of cores below: the south sides of this row's cores
+          const double wa = P.cx ? sa[5] : core_w(P, ca) * P.hy2i, wb = P.cx ? sb[5] : core_w(P, cb) * P.hy2i;
           v -= wa * wb * Sq[((size_t)(r - 1) * nc + a) * nc + b];
         }
       } else {
@@ -284,6 +322,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProblem* __restrict__ prob,
                                                                    const int* __restrict__ list,
                                                                    const GmState* __restrict__ gst,
+                                                                   const double* __restrict__ sums,
                                                                    const double* __restrict__ sinv,
                                                                    double* __restrict__ ainv) {
   __shared__ double Gl[kCoarseMaxNc * kColBlock];
@@ -310,7 +349,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
         if (r == rk) {
           v = Sr[(size_t)a * nc + lk];
         } else if (r > rk) {
-          for (int b = 0; b < nc; ++b) v += Sr[(size_t)a * nc + b] * (core_w(P, b >> 1) * P.hy2i) * Gl[b * kColBlock + kk];
+          for (int b = 0; b < nc; ++b) {
+            // coupling of core (r, b / 2) to the row below: its south side
+            const double cb = P.cx ? sums[kCSum * (size_t)(P.sub0 + r * P.csx + (b >> 1)) + 5]
+                                   : core_w(P, b >> 1) * P.hy2i;
+            v += Sr[(size_t)a * nc + b] * cb * Gl[b * kColBlock + kk];
+          }
         }
       }
       own[u] = v;
@@ -337,7 +381,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
       double v = 0.0;
       if (a < nc && k < N) {
         double acc = 0.0;
-        for (int b = 0; b < nc; ++b) acc += Sr[(size_t)a * nc + b] * (core_w(P, b >> 1) * P.hy2i) * Gl[b * kColBlock + kk];
+        for (int b = 0; b < nc; ++b) {
+          // coupling of core (r, b / 2) to the row above: its north side
+          const double cb = P.cx ? sums[kCSum * (size_t)(P.sub0 + r * P.csx + (b >> 1)) + 6]
+                                 : core_w(P, b >> 1) * P.hy2i;
+          acc += Sr[(size_t)a * nc + b] * cb * Gl[b * kColBlock + kk];
+        }
         v = Aq[(size_t)(r * nc + a) * N + k] + acc;
       }
       own[u] = v;
@@ -392,10 +441,10 @@ void launch_coarse_factor(const DevProblem* prob, const int* list, int count, co
   if (count > 0) k_coarse_factor<<<count, kCoarseThreads, 0, st>>>(prob, list, gst, sums, sinv);
 }
 void launch_coarse_inverse(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
-                           const double* sinv, double* ainv, hipStream_t st) {
+                           const double* sums, const double* sinv, double* ainv, hipStream_t st) {
   if (count > 0 && max_n > 0)
     k_coarse_inverse<<<dim3((max_n + kColBlock - 1) / kColBlock, count), kCoarseThreads, 0, st>>>(prob, list, gst,
-                                                                                                  sinv, ainv);
+                                                                                                  sums, sinv, ainv);
 }
 void launch_coarse_solve(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
                          const double* ainv, const double* cv, double scale, double* ev, hipStream_t st) {

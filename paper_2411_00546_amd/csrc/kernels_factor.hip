@@ -517,7 +517,7 @@ __device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
 // z_t = Z_t^{-1}(r_t + hy^-2 (g_{t-1} + h_{t+1})) for the Newton right-hand side.  A
 // subdomain with a line that is not dominant is marked in fallback[s] and redone by
 // k_factor_pivot.  M / 16 waves per workgroup.
-template <typename T, int M>
+template <typename T, int M, bool VAR>
 __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_factor_mfma(Items I, const double* __restrict__ tilex,
                                                        const double* __restrict__ c,
                                                        const SubState* __restrict__ state,
@@ -530,6 +530,10 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
   constexpr int KC = M / 4;             // the forward sweep adds each row in 4 parts
   __shared__ __attribute__((aligned(16))) T Mx[M * LD];   // S_j, then S_j^{-1}
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
+  // variable coefficients of A (VAR): diagonal of A, west and east couplings of each node
+  // of the line, and its couplings to the previous line (lp) and, at the twist, to the
+  // line below the twist (lq; lp then couples to the line above)
+  __shared__ double ldg[M / 2], lw[M / 2], le[M / 2], lp[M / 2], lq[M / 2];
   __shared__ double vin[M], gprev[M];
   __shared__ double part[4 * M];
   __shared__ int flag;
@@ -574,11 +578,24 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     r.cy = c ? c[tile_idx(P, s, 0, jj, t)] : 0.0;
     r.cp = c ? c[tile_idx(P, s, 1, jj, t)] : 0.0;
   };
-  auto coefficients = [&](double y, double p) {
+  // the pointwise coefficients of node t of line jj; with VAR also the operator's (the
+  // previous line of the chain is jj - dir; at the twist lp and lq couple to tw - 1 and
+  // tw + 1)
+  auto coefficients = [&](double y, double p, int jj, bool twist) {
     la[t] = dphi_of(P.phi, y, P.kappa);
     lb[t] = dg_of(p, P.mu, eps) * P.inv_nu;
     lc[t] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
+    if constexpr (VAR) {
+      const int gi = bx.x + t, gj = bx.z + jj;
+      ldg[t] = a_diag(P, gi, gj);
+      lw[t] = c_w(P, gi, gj);
+      le[t] = c_e(P, gi, gj);
+      lp[t] = (twist || dir == 1) ? c_s(P, gi, gj) : c_n(P, gi, gj);
+      lq[t] = c_n(P, gi, gj);
+    }
   };
+  // node of line-vector entry i < m
+  auto node = [&](int i) { return i < tx ? i : i - tx; };
   // Line block of line j: D_j + (mode 0: nothing; 1: hy^-4 times -(the previous inverse
   // in Mx); 2: Mx as it stands), identity padding, column sums; returns true when some
   // active column is not dominant.  Column b = 16 wave + (lane & 15), rows (lane >> 4) + 4 r.
@@ -591,7 +608,8 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
       const int fc = b >= tx, bc = b - fc * tx;
       const int r_l = bc > 0 ? b - 1 : -1, r_r = bc + 1 < tx ? b + 1 : -1;
       const int r_c = fc ? bc : tx + bc;
-      const T d_d = (T)(P.diag0 + la[bc]), d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
+      const T d_d = (T)((VAR ? ldg[bc] : P.diag0) + la[bc]), d_c = (T)(fc ? lb[bc] : lc[bc]);
+      const T d_xl = (T)(VAR ? -lw[bc] : -P.hx2i), d_xr = (T)(VAR ? -le[bc] : -P.hx2i);
 #pragma unroll 4
       for (int r = 0; r < M / 4; ++r) {
         const int a = rg + 4 * r;
@@ -599,7 +617,8 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
         if (a < m) {
           T d = 0;
           d = a == b ? d_d : d;
-          d = (a == r_l || a == r_r) ? d_x : d;
+          d = a == r_l ? d_xl : d;
+          d = a == r_r ? d_xr : d;
           d = a == r_c ? d_c : d;
           const T prev = Mx[a * LD + b];
           v = (mode == 0 ? (T)0 : (mode == 1 ? nh4 * prev : prev)) + d;
@@ -682,8 +701,10 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     const int r_c = act ? (fc ? bc : tx + bc) : -1;
     // a padding column is the identity column: its previous inverse column is the
     // identity column too (finite), which the zero scale removes
-    const T d_d = act ? (T)(P.diag0 + la[bc]) : (T)1, d_x = (T)(-P.hx2i), d_c = (T)(fc ? lb[bc] : lc[bc]);
+    const T d_d = act ? (T)((VAR ? ldg[bc] : P.diag0) + la[bc]) : (T)1, d_c = (T)(fc ? lb[bc] : lc[bc]);
+    const T d_xl = (T)(VAR ? -lw[bc] : -P.hx2i), d_xr = (T)(VAR ? -le[bc] : -P.hx2i);
     const T sc = act ? nh4 : (T)0;
+    const double cpb = VAR && act ? lp[bc] : 0.0;
     T off = 0, dia = 0;
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
@@ -694,11 +715,14 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
         // compiler from holding 3 NB * 4 lane masks in scalar registers across the line loop
         asm volatile("" : "+v"(a));
         T d = a == b ? d_d : (T)0;
-        d = (a == r_l || a == r_r) ? d_x : d;
+        d = a == r_l ? d_xl : d;
+        d = a == r_r ? d_xr : d;
         d = a == r_c ? d_c : d;
-        // -hy^-4 S^{-1} + D, rounded after the product and after the sum (padding rows
-        // of an active column: 0)
-        const T v = mode == 0 ? d : add_rn(mul_rn(sc, (T)blk[I][r]), d);
+        // -hy^-4 S^{-1} + D (VAR: -C S^{-1} C + D, C the couplings to the previous line),
+        // rounded after the product and after the sum (padding rows of an active column: 0)
+        T scv = sc;
+        if constexpr (VAR) scv = (T)(-(cpb * (a < m ? lp[node(a)] : 0.0)));
+        const T v = mode == 0 ? d : add_rn(mul_rn(scv, (T)blk[I][r]), d);
         blk[I][r] = v;
         const T wv = (a < tx ? wy : (T)1) * fabs(v);
         dia = a == b ? wv : dia;
@@ -740,7 +764,7 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     if (t < tx) {
       const double y = next.xy + next.cy, p = next.xp + next.cp;
       if (k + 1 < nlines) fetch(j + dir, next);
-      coefficients(y, p);
+      coefficients(y, p, j, false);
     }
     __syncthreads();
     if (k == 0 ? form_block(std::integral_constant<int, 0>{}) : form_block(std::integral_constant<int, 1>{})) {
@@ -754,7 +778,10 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
     __syncthreads();
     if (rhs) {
-      for (int i = t; i < M; i += NT) vin[i] = P.hy2i * gprev[i];
+      for (int i = t; i < M; i += NT) {
+        if constexpr (VAR) vin[i] = (i < m ? lp[node(i)] : 0.0) * gprev[i];
+        else vin[i] = P.hy2i * gprev[i];
+      }
       solve_line(j);
     }
   }
@@ -769,8 +796,9 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
   if (t < tx) {
     double y, p;
     state_at(tw, y, p);
-    coefficients(y, p);
+    coefficients(y, p, tw, true);
   }
+  if constexpr (VAR) __syncthreads();   // the twist couplings are read below
   // This workgroup's last inverse (the line next to the twist on its side) is still
   // in Mx; the other side's comes from global memory (stored transposed, F[b][a] =
   // inverse[a][b]), 16-byte loads along a.
@@ -793,7 +821,17 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
       for (int q = 0; q < 4; ++q) {
         T* x = Mx + (a0 + q) * LD + b;
         const double own = mine ? (double)*x : 0.0;
-        *x = (T)(-hy4i * (own + (double)v[i][q]));
+        if (VAR && P.cx) {
+          // couplings of the row's and the column's nodes to this side's line and the other's
+          const double* cm = half == 0 ? lp : lq;
+          const double* co = half == 0 ? lq : lp;
+          const int na = a0 + q < m ? node(a0 + q) : -1, nb = b < m ? node(b) : -1;
+          const double km = na >= 0 && nb >= 0 ? cm[na] * cm[nb] : 0.0;
+          const double ko = na >= 0 && nb >= 0 ? co[na] * co[nb] : 0.0;
+          *x = (T)(-(km * own + ko * (double)v[i][q]));
+        } else {
+          *x = (T)(-hy4i * (own + (double)v[i][q]));
+        }
       }
     }
   }
@@ -817,9 +855,16 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     return;
   }
   if (rhs) {
-    for (int i = t; i < M; i += NT)
-      vin[i] = P.hy2i * ((tw > 0 ? gs[(size_t)(tw - 1) * M + i] : 0.0) +
-                         (tw + 1 < ty ? gs[(size_t)(tw + 1) * M + i] : 0.0));
+    for (int i = t; i < M; i += NT) {
+      if (VAR && P.cx) {
+        vin[i] = i < m ? (tw > 0 ? lp[node(i)] * gs[(size_t)(tw - 1) * M + i] : 0.0) +
+                             (tw + 1 < ty ? lq[node(i)] * gs[(size_t)(tw + 1) * M + i] : 0.0)
+                       : 0.0;
+      } else {
+        vin[i] = P.hy2i * ((tw > 0 ? gs[(size_t)(tw - 1) * M + i] : 0.0) +
+                           (tw + 1 < ty ? gs[(size_t)(tw + 1) * M + i] : 0.0));
+      }
+    }
     solve_line(tw);
   }
   if (!dominant) store(tw);
@@ -846,12 +891,16 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
   __shared__ T pivv[2][2];      // pivot value and its reciprocal
   __shared__ int pr[2][M], pinv[2][M];
   __shared__ double la[M / 2], lb[M / 2], lc[M / 2];
+  // variable coefficients of A (as in k_factor_mfma): diagonal, west / east couplings,
+  // couplings to the previous line (twist: to line tw - 1) and, at the twist, to tw + 1
+  __shared__ double ldg[M / 2], lw[M / 2], le[M / 2], lp[M / 2], lq[M / 2];
   __shared__ double vin[M], gprev[M];
 
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
   if (!only[s]) return;
+  const bool var = P.cx != nullptr;
   const int t = threadIdx.x, ti = t & 15, tj = t >> 4;
   const int lane = t & 63;
   double eps = eps_fixed > 0.0 ? eps_fixed : eps_fixed < 0.0 ? P.eps_start : P.eps_min;
@@ -886,6 +935,14 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
       la[a] = dphi_of(P.phi, y, P.kappa);
       lb[a] = dg_of(p, P.mu, eps) * P.inv_nu;
       lc[a] = ddphi_of(P.phi, y, P.kappa) * p - 1.0;
+      if (var) {
+        const int gi = bx.x + a, gj = bx.z + j;
+        ldg[a] = a_diag(P, gi, gj);
+        lw[a] = c_w(P, gi, gj);
+        le[a] = c_e(P, gi, gj);
+        lp[a] = (q < tw || twist) ? c_s(P, gi, gj) : c_n(P, gi, gj);
+        lq[a] = c_n(P, gi, gj);
+      }
     }
     __syncthreads();
     // S_j = D_j - hy^-4 S_{j-1}^{-1} on the active m x m block, identity padding;
@@ -904,14 +961,23 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
           const int ar = a - fr * tx, ac = b - fc * tx;
           d = 0.0;
           if (fr == fc) {
-            if (ar == ac) d = P.diag0 + la[ar];
-            else if (ar == ac + 1 || ac == ar + 1) d = -P.hx2i;
+            if (ar == ac) d = (var ? ldg[ar] : P.diag0) + la[ar];
+            else if (ar == ac + 1) d = var ? -lw[ar] : -P.hx2i;
+            else if (ac == ar + 1) d = var ? -le[ar] : -P.hx2i;
           } else if (ar == ac) {
             d = fr == 0 ? lb[ar] : lc[ar];
           }
-          if (has_prev) d -= hy4i * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
-          if (twist) d -= hy4i * ((Fm ? (double)Fm[(size_t)b * M + a] : 0.0) +
-                                 (Fp ? (double)Fp[(size_t)b * M + a] : 0.0));
+          if (var) {
+            // -C S^{-1} C with the diagonal couplings C of the faces to the neighbour lines
+            if (has_prev) d -= lp[ar] * lp[ac] * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
+            if (twist)
+              d -= lp[ar] * lp[ac] * (Fm ? (double)Fm[(size_t)b * M + a] : 0.0) +
+                   lq[ar] * lq[ac] * (Fp ? (double)Fp[(size_t)b * M + a] : 0.0);
+          } else {
+            if (has_prev) d -= hy4i * (double)Mx[pr[pp][a] * LD + pinv[pp][b]];
+            if (twist) d -= hy4i * ((Fm ? (double)Fm[(size_t)b * M + a] : 0.0) +
+                                   (Fp ? (double)Fp[(size_t)b * M + a] : 0.0));
+          }
         }
         A[rr][cc] = (T)d;
       }
@@ -1025,13 +1091,27 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
           const int f = i >= tx;
           rv = rhs_scale * rhs[tile_idx(P, s, f, j, i - f * tx)];
         }
-        double nb = has_prev ? gprev[i] : 0.0;
-        if (twist) {
-          const double* gs = gout + (size_t)s * P.tym * M;
-          if (tw > 0) nb += gs[(size_t)(tw - 1) * M + i];
-          if (tw + 1 < ty) nb += gs[(size_t)(tw + 1) * M + i];
+        if (var) {
+          const int nd = i < tx ? i : i - tx;
+          double nb = 0.0;
+          if (i < m) {
+            if (has_prev) nb += lp[nd] * gprev[i];
+            if (twist) {
+              const double* gs = gout + (size_t)s * P.tym * M;
+              if (tw > 0) nb += lp[nd] * gs[(size_t)(tw - 1) * M + i];
+              if (tw + 1 < ty) nb += lq[nd] * gs[(size_t)(tw + 1) * M + i];
+            }
+          }
+          vin[i] = rv + nb;
+        } else {
+          double nb = has_prev ? gprev[i] : 0.0;
+          if (twist) {
+            const double* gs = gout + (size_t)s * P.tym * M;
+            if (tw > 0) nb += gs[(size_t)(tw - 1) * M + i];
+            if (tw + 1 < ty) nb += gs[(size_t)(tw + 1) * M + i];
+          }
+          vin[i] = rv + P.hy2i * nb;
         }
-        vin[i] = rv + P.hy2i * nb;
       }
       __syncthreads();
       if (t < M) {
@@ -1074,21 +1154,29 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
 
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, int* counter, hipStream_t st) {
+                   int* fallback, int* counter, bool var, hipStream_t st) {
   if (I.count <= 0) return;
   const dim3 grid(I.count, 2);
   if (fp32) {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor_mfma<float, MM><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale,      \
-                                                    (float*)facT, g, fallback, counter);                \
+  if (var)                                                                                             \
+    k_factor_mfma<float, MM, true><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                           (float*)facT, g, fallback, counter);         \
+  else                                                                                                 \
+    k_factor_mfma<float, MM, false><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
+                                                            (float*)facT, g, fallback, counter);        \
   k_factor_pivot<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
                                                              rhs_scale, (float*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
 #define RSP_CALL(MM)                                                                                   \
-  k_factor_mfma<double, MM><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale,     \
-                                                     (double*)facT, g, fallback, counter);              \
+  if (var)                                                                                             \
+    k_factor_mfma<double, MM, true><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,        \
+                                                            rhs_scale, (double*)facT, g, fallback, counter); \
+  else                                                                                                 \
+    k_factor_mfma<double, MM, false><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
+                                                             rhs_scale, (double*)facT, g, fallback, counter); \
   k_factor_pivot<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,      \
                                                               rhs_scale, (double*)facT, g, fallback)
     RSP_DISPATCH_M(M, RSP_CALL)

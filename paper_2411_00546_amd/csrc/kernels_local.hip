@@ -41,17 +41,16 @@ __device__ bool stage(const DevProblem& P, int s, int tx, int ty, const double* 
 }
 
 // K_i at local node (a, b) from the staged tile: the two rows of F_eps (Section 4).
-__device__ __forceinline__ void node_residual(const DevProblem& P, const double* z, int a, int b,
-                                              double ydv, double fv, double eps, double& ky,
+// (gi, gj): the node on the grid.
+__device__ __forceinline__ void node_residual(const DevProblem& P, const double* z, int a, int b, int gi,
+                                              int gj, double ydv, double fv, double eps, double& ky,
                                               double& kp) {
   const double* zy = z;
   const double* zp = z + kHalo * kHalo;
   const int c0 = (b + 1) * kHalo + (a + 1);
   const double y = zy[c0], p = zp[c0];
-  const double lap_y = P.diag0 * y - P.hx2i * (zy[c0 - 1] + zy[c0 + 1])
-                       - P.hy2i * (zy[c0 - kHalo] + zy[c0 + kHalo]);
-  const double lap_p = P.diag0 * p - P.hx2i * (zp[c0 - 1] + zp[c0 + 1])
-                       - P.hy2i * (zp[c0 - kHalo] + zp[c0 + kHalo]);
+  const double lap_y = apply_a(P, gi, gj, y, zy[c0 - 1], zy[c0 + 1], zy[c0 - kHalo], zy[c0 + kHalo]);
+  const double lap_p = apply_a(P, gi, gj, p, zp[c0 - 1], zp[c0 + 1], zp[c0 - kHalo], zp[c0 + kHalo]);
   ky = lap_y + phi_of(P.phi, y, P.kappa) - fv + g_of(p, P.mu, eps) * P.inv_nu;
   kp = lap_p + dphi_of(P.phi, y, P.kappa) * p - y + ydv;
 }
@@ -66,7 +65,7 @@ __device__ double tile_residual(const DevProblem& P, int s, int4 bx, int tx, int
     const int b = e / tx, a = e - b * tx;
     const size_t gi = (size_t)(bx.z + b) * P.nx + (bx.x + a);
     double ky, kp;
-    node_residual(P, z, a, b, yd[gi], f ? f[gi] : 0.0, eps, ky, kp);
+    node_residual(P, z, a, b, bx.x + a, bx.z + b, yd[gi], f ? f[gi] : 0.0, eps, ky, kp);
     if (out) {
       out[tile_idx(P, s, 0, b, a)] = ky;
       out[tile_idx(P, s, 1, b, a)] = kp;
@@ -296,10 +295,10 @@ __global__ __launch_bounds__(kBlock) void k_ring_rhs(Items I, const double* __re
     if (a < tx && b < ty) {
       const int gi = bx.x + a, gj = bx.z + b;
       const double* df = d + f * n;
-      if (a == 0 && gi > 0) v += P.hx2i * df[(size_t)gj * P.nx + gi - 1];
-      if (a == tx - 1 && gi + 1 < P.nx) v += P.hx2i * df[(size_t)gj * P.nx + gi + 1];
-      if (b == 0 && gj > 0) v += P.hy2i * df[(size_t)(gj - 1) * P.nx + gi];
-      if (b == ty - 1 && gj + 1 < P.ny) v += P.hy2i * df[(size_t)(gj + 1) * P.nx + gi];
+      if (a == 0 && gi > 0) v += c_w(P, gi, gj) * df[(size_t)gj * P.nx + gi - 1];
+      if (a == tx - 1 && gi + 1 < P.nx) v += c_e(P, gi, gj) * df[(size_t)gj * P.nx + gi + 1];
+      if (b == 0 && gj > 0) v += c_s(P, gi, gj) * df[(size_t)(gj - 1) * P.nx + gi];
+      if (b == ty - 1 && gj + 1 < P.ny) v += c_n(P, gi, gj) * df[(size_t)(gj + 1) * P.nx + gi];
     }
     rhs[tile_idx(P, s, f, b, a)] = v;
   }

@@ -1,6 +1,7 @@
 // Block-tridiagonal solves with the stored line factors (twisted form).
 //
-// Lines 0 .. ty-1 of a tile, twist line t = ty / 2, c = 1/hy^2.  The factors are the
+// Lines 0 .. ty-1 of a tile, twist line t = ty / 2, c = 1/hy^2 (with variable
+// coefficients of A, c is the diagonal of a2 / hy^2 on the faces between the two lines).  The factors are the
 // inverses F_j of the two-ended Schur complements (kernels_factor.hip): S_j from the
 // top (j < t), T_j from the bottom (j > t) and Z_t at the twist, stored transposed
 // (facT[s][j][b][a] = F_j[a][b]).  A solve J z = r is
@@ -90,11 +91,29 @@ __device__ __forceinline__ double line_product(const typename Sweep<TF, M>::VT (
   return y;
 }
 
+// Coupling between consecutive lines of a tile: c times the identity for the Laplacian
+// (cy == nullptr), else the diagonal of a2 / hy^2 on the faces between the lines (face k
+// lies between local lines k - 1 and k; both fields of a node share its face).
+struct Cpl {
+  double c;
+  const double* cy;
+  int nx, gx0, gy0, tx;
+  __device__ __forceinline__ double at(int k, int i) const {
+    if (!cy) return c;
+    if (i >= 2 * tx) return 0.0;   // padding
+    const int a = i < tx ? i : i - tx;
+    return cy[(size_t)(gy0 + k) * nx + gx0 + a];
+  }
+};
+__device__ __forceinline__ Cpl cpl_of(const DevProblem& P, int4 bx) {
+  return Cpl{P.hy2i, P.cx ? P.cy : nullptr, P.nx, bx.x, bx.z, bx.y - bx.x};
+}
+
 // Inward sweep over the n lines j0, j0 + dir, ... (dir = +1 or -1), in place on
 // gl[ty][M]: gl_j <- F_j gl_j, then c gl_j is added to the next line j + dir (also
 // after the last one, where that is the twist line), if it lies in [0, ty).
 template <typename TF, int M>
-__device__ void sweep_in(const TF* __restrict__ Fs, int ty, int j0, int n, int dir, double c, double* gl,
+__device__ void sweep_in(const TF* __restrict__ Fs, int ty, int j0, int n, int dir, const Cpl& cp, double* gl,
                          double* red) {
   using S = Sweep<TF, M>;
   if (n <= 0) return;
@@ -110,7 +129,7 @@ __device__ void sweep_in(const TF* __restrict__ Fs, int ty, int j0, int n, int d
     if (t < M) {
       gl[(size_t)j * M + t] = y;
       const int jn = j + dir;
-      if (jn >= 0 && jn < ty) gl[(size_t)jn * M + t] += c * y;
+      if (jn >= 0 && jn < ty) gl[(size_t)jn * M + t] += cp.at(max(j, jn), t) * y;
     }
     __syncthreads();
   };
@@ -126,10 +145,11 @@ __device__ void sweep_in(const TF* __restrict__ Fs, int ty, int j0, int n, int d
   }
 }
 
-// Outward sweep over the n lines j0, j0 + dir, ...: gl_j += c F_j gl_{j - dir}.
+// Outward sweep over the n lines j0, j0 + dir, ...: gl_j += F_j (c gl_{j - dir}); vs: M
+// doubles of LDS for the scaled vector when the coupling varies along the line.
 template <typename TF, int M>
-__device__ void sweep_out(const TF* __restrict__ Fs, int j0, int n, int dir, double c, double* gl,
-                          double* red) {
+__device__ void sweep_out(const TF* __restrict__ Fs, int j0, int n, int dir, const Cpl& cp, double* gl,
+                          double* red, double* vs) {
   using S = Sweep<TF, M>;
   if (n <= 0) return;
   const int t = threadIdx.x, ac = t % S::NC, bg = t / S::NC;
@@ -139,9 +159,16 @@ __device__ void sweep_out(const TF* __restrict__ Fs, int j0, int n, int dir, dou
   load_line<TF, M>(Fs + MM * line(0), ac, bg, b0);
   load_line<TF, M>(Fs + MM * line(1), ac, bg, b1);
   auto step = [&](const typename S::VT(&buf)[S::K], int k) {
-    const int j = j0 + dir * k;
-    const double y = line_product<TF, M>(buf, gl + (size_t)(j - dir) * M, ac, bg, red);
-    if (t < M) gl[(size_t)j * M + t] += c * y;
+    const int j = j0 + dir * k, jp = j - dir;
+    if (cp.cy) {
+      if (t < M) vs[t] = cp.at(max(j, jp), t) * gl[(size_t)jp * M + t];
+      __syncthreads();
+      const double y = line_product<TF, M>(buf, vs, ac, bg, red);
+      if (t < M) gl[(size_t)j * M + t] += y;
+    } else {
+      const double y = line_product<TF, M>(buf, gl + (size_t)jp * M, ac, bg, red);
+      if (t < M) gl[(size_t)j * M + t] += cp.c * y;
+    }
     __syncthreads();
   };
   for (int k = 0; k < n; k += 3) {
@@ -170,14 +197,14 @@ __device__ void twist_line(const TF* __restrict__ Fs, int tw, double* gl, double
 
 // Whole solve in one workgroup; the outward sweeps stop at lines jlo <= t <= jhi.
 template <typename TF, int M>
-__device__ void full_solve(const TF* __restrict__ Fs, int ty, int jlo, int jhi, double c, double* gl,
-                           double* red) {
+__device__ void full_solve(const TF* __restrict__ Fs, int ty, int jlo, int jhi, const Cpl& cp, double* gl,
+                           double* red, double* vs) {
   const int tw = ty / 2;
-  sweep_in<TF, M>(Fs, ty, 0, tw, 1, c, gl, red);
-  sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, c, gl, red);
+  sweep_in<TF, M>(Fs, ty, 0, tw, 1, cp, gl, red);
+  sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, cp, gl, red);
   twist_line<TF, M>(Fs, tw, gl, red);
-  sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, c, gl, red);
-  sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, c, gl, red);
+  sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, cp, gl, red, vs);
+  sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, cp, gl, red, vs);
 }
 
 template <int M>
@@ -209,7 +236,7 @@ __device__ __forceinline__ void lines_to_tile(const DevProblem& P, int s, int tx
 // rb -= J_i z on the tile (z in line layout, zero outside the tile), J_i the local
 // Jacobian at R_i x + c with smoothing eps (FP64, matrix-free 5-point stencil).
 template <int M>
-__device__ void sub_local_jacobian(const DevProblem& P, int s, int tx, int ty,
+__device__ void sub_local_jacobian(const DevProblem& P, int s, int4 bx, int tx, int ty,
                                    const double* __restrict__ tilex, const double* __restrict__ c,
                                    double eps, const double* gl, double* rb) {
   for (int e = threadIdx.x; e < ty * tx; e += 4 * M) {
@@ -225,9 +252,17 @@ __device__ void sub_local_jacobian(const DevProblem& P, int s, int tx, int ty,
     const double* zd = gl + (size_t)jd * M;
     const double* zu = gl + (size_t)ju * M;
     const double zy = zl[a], zp = zl[tx + a];
-    const double lap_y = P.diag0 * zy - P.hx2i * (wl * zl[al] + wr * zl[ar]) - P.hy2i * (wd * zd[a] + wu * zu[a]);
-    const double lap_p = P.diag0 * zp - P.hx2i * (wl * zl[tx + al] + wr * zl[tx + ar])
-                         - P.hy2i * (wd * zd[tx + a] + wu * zu[tx + a]);
+    double lap_y, lap_p;
+    if (!P.cx) {
+      lap_y = P.diag0 * zy - P.hx2i * (wl * zl[al] + wr * zl[ar]) - P.hy2i * (wd * zd[a] + wu * zu[a]);
+      lap_p = P.diag0 * zp - P.hx2i * (wl * zl[tx + al] + wr * zl[tx + ar]) - P.hy2i * (wd * zd[tx + a] + wu * zu[tx + a]);
+    } else {
+      const int gi = bx.x + a, gj = bx.z + j;
+      const double cw = wl * c_w(P, gi, gj), ce = wr * c_e(P, gi, gj);
+      const double cs = wd * c_s(P, gi, gj), cn = wu * c_n(P, gi, gj), dg = a_diag(P, gi, gj);
+      lap_y = dg * zy - (cw * zl[al] + ce * zl[ar]) - (cs * zd[a] + cn * zu[a]);
+      lap_p = dg * zp - (cw * zl[tx + al] + ce * zl[tx + ar]) - (cs * zd[tx + a] + cn * zu[tx + a]);
+    }
     const double dphi = dphi_of(P.phi, y, P.kappa);
     const double jy = lap_y + dphi * zy + dg_of(p, P.mu, eps) * P.inv_nu * zp;
     const double jp = (ddphi_of(P.phi, y, P.kappa) * p - 1.0) * zy + lap_p + dphi * zp;
@@ -259,10 +294,10 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
       const int f = i >= tx, a = i - f * tx;
       const int gi = bx.x + a, gj = bx.z + j;
       const double* df = d + f * n;
-      if (a == 0 && gi > 0) v += P.hx2i * val(df, f, gi - 1, gj);
-      if (a == tx - 1 && gi + 1 < P.nx) v += P.hx2i * val(df, f, gi + 1, gj);
-      if (j == 0 && gj > 0) v += P.hy2i * val(df, f, gi, gj - 1);
-      if (j == ty - 1 && gj + 1 < P.ny) v += P.hy2i * val(df, f, gi, gj + 1);
+      if (a == 0 && gi > 0) v += c_w(P, gi, gj) * val(df, f, gi - 1, gj);
+      if (a == tx - 1 && gi + 1 < P.nx) v += c_e(P, gi, gj) * val(df, f, gi + 1, gj);
+      if (j == 0 && gj > 0) v += c_s(P, gi, gj) * val(df, f, gi, gj - 1);
+      if (j == ty - 1 && gj + 1 < P.ny) v += c_n(P, gi, gj) * val(df, f, gi, gj + 1);
     }
     gl[e] = v;
   }
@@ -296,6 +331,7 @@ __global__ __launch_bounds__(4 * M) void k_block_solve(Items I, const TF* __rest
                                                        double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -304,7 +340,7 @@ __global__ __launch_bounds__(4 * M) void k_block_solve(Items I, const TF* __rest
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   tile_to_lines<M>(P, s, tx, ty, rhs, 1.0, gl);
   __syncthreads();
-  full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, gl, red);
+  full_solve<TF, M>(Fs, ty, 0, ty - 1, cpl_of(P, bx), gl, red, vsc);
   lines_to_tile<M>(P, s, tx, ty, gl, out);
 }
 
@@ -317,6 +353,7 @@ __global__ __launch_bounds__(4 * M) void k_solve_bwd(Items I, const SubState* __
                                                      double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -328,8 +365,9 @@ __global__ __launch_bounds__(4 * M) void k_solve_bwd(Items I, const SubState* __
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) gl[e] = g[(size_t)s * P.tym * M + e];
   __syncthreads();
-  if (half == 0) sweep_out<TF, M>(Fs, tw - 1, tw, -1, P.hy2i, gl, red);
-  else sweep_out<TF, M>(Fs, tw + 1, ty - 1 - tw, 1, P.hy2i, gl, red);
+  const Cpl cp = cpl_of(P, bx);
+  if (half == 0) sweep_out<TF, M>(Fs, tw - 1, tw, -1, cp, gl, red, vsc);
+  else sweep_out<TF, M>(Fs, tw + 1, ty - 1 - tw, 1, cp, gl, red, vsc);
   // tile rows of this half (half 1 also writes the padding rows)
   const int r0 = half == 0 ? 0 : tw + 1, r1 = half == 0 ? tw + 1 : P.tym;
   for (int e = threadIdx.x; e < 2 * P.txm * (r1 - r0); e += 4 * M) {
@@ -352,6 +390,7 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(Items I, const double* 
   __shared__ double gl[kMaxTile * M];
   __shared__ double rb[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -364,9 +403,9 @@ __global__ __launch_bounds__(4 * M) void k_newton_refine(Items I, const double* 
   for (int it = 0; it < nref; ++it) {
     tile_to_lines<M>(P, s, tx, ty, res, -1.0, rb);
     __syncthreads();
-    sub_local_jacobian<M>(P, s, tx, ty, tilex, c, eps, gl, rb);
+    sub_local_jacobian<M>(P, s, bx, tx, ty, tilex, c, eps, gl, rb);
     __syncthreads();
-    full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, rb, red);
+    full_solve<TF, M>(Fs, ty, 0, ty - 1, cpl_of(P, bx), rb, red, vsc);
     for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
     __syncthreads();
   }
@@ -382,6 +421,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restric
                                                     double* __restrict__ gbuf) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -393,8 +433,9 @@ __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restric
   double* gs = gbuf + (size_t)s * P.tym * M;
   ring_rhs<M>(P, bx, tx, ty, j0, j1, d, ce, gl);
   __syncthreads();
-  if (half == 0) sweep_in<TF, M>(Fs, ty, 0, tw, 1, P.hy2i, gl, red);
-  else sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, P.hy2i, gl, red);
+  const Cpl cp = cpl_of(P, bx);
+  if (half == 0) sweep_in<TF, M>(Fs, ty, 0, tw, 1, cp, gl, red);
+  else sweep_in<TF, M>(Fs, ty, ty - 1, ty - 1 - tw, -1, cp, gl, red);
   for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) gs[e] = gl[e];
 }
 
@@ -408,6 +449,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restri
                                                      double* __restrict__ out) {
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -422,19 +464,20 @@ __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restri
   for (int e = jlo * M + threadIdx.x; e < (jhi + 1) * M; e += 4 * M) gl[e] = gs[e];
   ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, ce, gl);
   __syncthreads();
+  const Cpl cp = cpl_of(P, bx);
   for (int i = threadIdx.x; i < M; i += 4 * M) {
     double v = gl[(size_t)tw * M + i];
-    if (tw > 0) v += P.hy2i * gs[(size_t)(tw - 1) * M + i];
-    if (tw + 1 < ty) v += P.hy2i * gs[(size_t)(tw + 1) * M + i];
+    if (tw > 0) v += cp.at(tw, i) * gs[(size_t)(tw - 1) * M + i];
+    if (tw + 1 < ty) v += cp.at(tw + 1, i) * gs[(size_t)(tw + 1) * M + i];
     gl[(size_t)tw * M + i] = v;
   }
   __syncthreads();
   twist_line<TF, M>(Fs, tw, gl, red);
   if (half == 0) {
-    sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, P.hy2i, gl, red);
+    sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, cp, gl, red, vsc);
     core_out<M>(P, bx, co, tx, jlo, tw + 1, gl, d, out);
   } else {
-    sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, P.hy2i, gl, red);
+    sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, cp, gl, red, vsc);
     core_out<M>(P, bx, co, tx, tw + 1, jhi + 1, gl, d, out);
   }
 }
@@ -451,6 +494,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
   __shared__ double gl[kMaxTile * M];
   __shared__ double rb[kMaxTile * M];
   __shared__ double red[Sweep<TF, M>::G * M];
+  __shared__ double vsc[M];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -459,13 +503,14 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl);
   __syncthreads();
-  full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, gl, red);
+  const Cpl cp = cpl_of(P, bx);
+  full_solve<TF, M>(Fs, ty, 0, ty - 1, cp, gl, red, vsc);
   for (int it = 0; it < nref; ++it) {
     ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, rb);
     __syncthreads();
-    sub_local_jacobian<M>(P, s, tx, ty, tilex, c, P.eps_min, gl, rb);
+    sub_local_jacobian<M>(P, s, bx, tx, ty, tilex, c, P.eps_min, gl, rb);
     __syncthreads();
-    full_solve<TF, M>(Fs, ty, 0, ty - 1, P.hy2i, rb, red);
+    full_solve<TF, M>(Fs, ty, 0, ty - 1, cp, rb, red, vsc);
     for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
     __syncthreads();
   }

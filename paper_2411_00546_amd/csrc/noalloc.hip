@@ -2,7 +2,8 @@
 // problem (the same kernels and results as rsp_local_residual) without a context and
 // without any device allocation.  Its staging buffers (the instance's constants, the
 // subdomain boxes and the halo tiles of R_i x) live in a file-scope device array of
-// kScratchBytes.  The array's device address is resolved once per device
+// kScratchBytes (with variable coefficients of A also their scaled copies).  The array's
+// device address is resolved once per device
 // (hipGetSymbolAddress) and only that address is passed to kernels and copies.
 #include <algorithm>
 #include <mutex>
@@ -71,7 +72,10 @@ extern "C" int rsp_local_residual_noalloc(const rsp_problem* prob, const double*
   const size_t o_core = o_box + align256(sizeof(int4) * S);
   const size_t o_inst = o_core + align256(sizeof(int4) * S);
   const size_t o_tile = o_inst + align256(sizeof(int) * S);
-  const size_t need = o_tile + sizeof(double) * S * 2 * (size_t)(txm + 2) * (tym + 2);
+  const size_t o_coef = o_tile + align256(sizeof(double) * S * 2 * (size_t)(txm + 2) * (tym + 2));
+  const size_t nxf = (size_t)(prob->nx + 1) * prob->ny, nyf = (size_t)prob->nx * (prob->ny + 1);
+  const size_t nn = (size_t)prob->nx * prob->ny;
+  const size_t need = prob->coef ? o_coef + align256(8 * nxf) + align256(8 * nyf) + 8 * nn : o_coef;
   if (need > kScratchBytes)
     return fail(RSP_EINVAL, "needs %zu bytes of staging, the limit is %zu", need, kScratchBytes);
   int dev = 0;
@@ -94,7 +98,16 @@ extern "C" int rsp_local_residual_noalloc(const rsp_problem* prob, const double*
   int4* core = reinterpret_cast<int4*>(base + o_core);
   int* inst = reinterpret_cast<int*>(base + o_inst);
   double* tilex = reinterpret_cast<double*>(base + o_tile);
-  const rsp::DevProblem P = rsp::dev_problem(*prob, 0, S, txm, tym, rsp::line_block(txm));
+  rsp::DevProblem P = rsp::dev_problem(*prob, 0, S, txm, tym, rsp::line_block(txm));
+  if (prob->coef) {
+    double* cx = reinterpret_cast<double*>(base + o_coef);
+    double* cy = reinterpret_cast<double*>(base + o_coef + align256(8 * nxf));
+    double* c0 = reinterpret_cast<double*>(base + o_coef + align256(8 * nxf) + align256(8 * nyf));
+    rsp::launch_coef_load(P, prob->coef, cx, cy, c0, stream);
+    P.cx = cx;
+    P.cy = cy;
+    P.c0 = c0;
+  }
   k_noalloc_tables<<<(S + 255) / 256, 256, 0, stream>>>(P, prob->sx, prob->sy, prob->overlap, P_d, box, core,
                                                          inst);
   rsp::Items I{};

@@ -214,6 +214,7 @@ namespace {
 struct Geometry {
   int ninst = 0, S = 0, txm = 0, tym = 0, M = 0;
   long long ntot = 0;   // nodes of the concatenated [ny][nx] arrays (instances 32-aligned)
+  long long ncoef = 0;  // doubles of the coefficient arrays of A (instances that have them)
   // second level: entries of the coarse factors S_r^{-1} and of the dense A0^{-1} of all
   // instances, the widest row of cores
   long long sinv = 0, ainv = 0;
@@ -257,10 +258,17 @@ struct Work {
   double *csum = nullptr, *cvec = nullptr, *evec = nullptr, *sinv = nullptr, *ainv = nullptr;
 };
 
-void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x) {
+void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x, double** coef) {
   *yd = cv.take<double>(g.ntot);
   *f = cv.take<double>(g.ntot);
   *x = cv.take<double>(2 * g.ntot);
+  *coef = g.ncoef ? cv.take<double>(g.ncoef) : nullptr;
+}
+
+// Doubles of the scaled coefficient arrays of one instance (cx, cy, c0), 32-aligned each.
+long long coef_doubles(int nx, int ny) {
+  auto al = [](long long v) { return (v + kAlignN - 1) / kAlignN * kAlignN; };
+  return al((long long)(nx + 1) * ny) + al((long long)nx * (ny + 1)) + al((long long)nx * ny);
 }
 
 void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
@@ -298,7 +306,7 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->p1 = cv.take<double>(part);
   w->p2 = cv.take<double>(part);
   if (o.coarse) {
-    w->csum = cv.take<double>(3 * S);
+    w->csum = cv.take<double>(8 * S);
     w->cvec = cv.take<double>(2 * S);
     w->evec = cv.take<double>(2 * S);
     w->sinv = cv.take<double>(g.sinv);
@@ -306,10 +314,12 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   }
 }
 
-Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns) {
+Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vector<size_t>& ns,
+                     const std::vector<long long>& ncoef) {
   Geometry g;
   g.ninst = (int)parts.size();
   for (size_t q = 0; q < parts.size(); ++q) {
+    g.ncoef += ncoef[q];
     g.S += parts[q]->S;
     g.txm = std::max(g.txm, parts[q]->txm);
     g.tym = std::max(g.tym, parts[q]->tym);
@@ -325,9 +335,9 @@ Geometry geometry_of(const std::vector<const Partition*>& parts, const std::vect
 
 size_t layout_bytes(const Geometry& g, const rsp_options& o) {
   Carve a, b;
-  double *yd, *f, *x;
+  double *yd, *f, *x, *coef;
   Work w;
-  carve_global(a, g, &yd, &f, &x);
+  carve_global(a, g, &yd, &f, &x, &coef);
   carve_work(b, g, o, &w);
   return a.off + b.off;
 }
@@ -374,6 +384,8 @@ struct rsp_context {
   size_t gcap[2] = {0, 0};
   int gcur = 0;
   double *yd = nullptr, *f = nullptr, *x = nullptr;
+  double* coef = nullptr;   // scaled coefficient arrays of A of the instances that have them
+  bool var = false;         // some instance of the layout has variable coefficients
   // work arena (capacity grows)
   void* wmem = nullptr;
   size_t wcap = 0;
@@ -390,6 +402,13 @@ struct rsp_context {
   void* pin = nullptr;
   size_t pin_cap = 0;
   hipEvent_t wait_ev = nullptr;   // completion of the work before a read-back
+  // pinned ring for the host-to-device uploads of the solve loop (item lists, instance
+  // constants): a copy from pageable memory holds the host until the stream has reached
+  // it, and the GPU then idles while the next launches are enqueued.  Regions are
+  // reused once a wait on upin_st has passed them.
+  char* upin = nullptr;
+  size_t upin_cap = 0, upin_off = 0;
+  hipStream_t upin_st = nullptr;
   std::vector<double> hnorm;
   std::vector<int> hlist[kLists], hilist[kLists];
   // the instance bound by rsp_setup / rsp_solve for the single-problem calls
@@ -424,9 +443,37 @@ int wait_stream(rsp_context* ctx, hipStream_t st) {
   HIPCHK(hipEventRecord(ctx->wait_ev, st));
   for (;;) {
     const hipError_t e = hipEventQuery(ctx->wait_ev);
-    if (e == hipSuccess) return 0;
+    if (e == hipSuccess) break;
     if (e != hipErrorNotReady) return fail(RSP_EHIP, "waiting for the stream: %s", hipGetErrorString(e));
   }
+  if (ctx->upin_st == st) ctx->upin_off = 0;   // every upload enqueued on st has been done
+  return 0;
+}
+
+// Enqueues the copy of n host bytes to device memory `dst` on `st` through the pinned
+// upload ring; `src` may be reused as soon as this returns.
+int upload(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_t st) {
+  if (n == 0) return 0;
+  const size_t need = (n + 255) / 256 * 256;
+  if (ctx->upin_off > 0 && (ctx->upin_st != st || ctx->upin_off + need > ctx->upin_cap)) {
+    RSPCHK(wait_stream(ctx, ctx->upin_st));   // the ring's earlier copies may be pending
+    ctx->upin_off = 0;
+  }
+  if (need > ctx->upin_cap) {
+    if (ctx->upin) HIPCHK(hipHostFree(ctx->upin));   // nothing pending: upin_off == 0
+    ctx->upin = nullptr;
+    ctx->upin_cap = 0;
+    const size_t cap = std::max(need, (size_t)1 << 20);
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, cap, hipHostMallocDefault));
+    ctx->upin = static_cast<char*>(p);
+    ctx->upin_cap = cap;
+  }
+  std::memcpy(ctx->upin + ctx->upin_off, src, n);
+  HIPCHK(hipMemcpyAsync(dst, ctx->upin + ctx->upin_off, n, hipMemcpyHostToDevice, st));
+  ctx->upin_off += need;
+  ctx->upin_st = st;
+  return 0;
 }
 
 // Copies n bytes of device memory to host memory `dst` through the pinned staging
@@ -677,10 +724,8 @@ int upload_lists(rsp_context* ctx, int l, const std::vector<Inst*>& set, hipStre
     il.push_back(in->slot);
     for (int q = 0; q < in->part.S; ++q) it.push_back(in->sub0 + q);
   }
-  if (!it.empty())
-    HIPCHK(hipMemcpyAsync(ctx->w.list[l], it.data(), sizeof(int) * it.size(), hipMemcpyHostToDevice, st));
-  if (!il.empty())
-    HIPCHK(hipMemcpyAsync(ctx->w.ilist[l], il.data(), sizeof(int) * il.size(), hipMemcpyHostToDevice, st));
+  RSPCHK(upload(ctx, ctx->w.list[l], it.data(), sizeof(int) * it.size(), st));
+  RSPCHK(upload(ctx, ctx->w.ilist[l], il.data(), sizeof(int) * il.size(), st));
   return 0;
 }
 
@@ -704,8 +749,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
     P.eps_start = cont[q] ? in->prob.eps0 : in->prob.eps_min;
     ncont = std::max(ncont, continuation_steps(P.eps_start, in->prob.eps_min, in->prob.gamma));
   }
-  HIPCHK(hipMemcpyAsync(ctx->w.prob, ctx->hprob.data(), sizeof(DevProblem) * ctx->hprob.size(),
-                        hipMemcpyHostToDevice, st));
+  RSPCHK(upload(ctx, ctx->w.prob, ctx->hprob.data(), sizeof(DevProblem) * ctx->hprob.size(), st));
   RSPCHK(upload_lists(ctx, kLEval, set, st));
   const int count = (int)ctx->hlist[kLEval].size();
   const Items I = items_of(ctx, ctx->w.list[kLEval], count);
@@ -757,7 +801,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
         {
           Timed t(ctx, KID_FACTOR, s, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
           rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g,
-                             w.fallback, w.counter, s);
+                             w.fallback, w.counter, ctx->var, s);
         }
         {
           Timed t(ctx, KID_SOLVE_BWD, s, sw.bwd_fl, sw.bwd_by);
@@ -810,7 +854,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
   // factor at x^(i) = x + P_i C_i(x) for Algorithm 4
   {
     Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
-    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, w.fallback, w.counter, st);
+    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, w.fallback, w.counter, ctx->var, st);
   }
   {
     Timed t(ctx, KID_PROLONG, st, 0, all.tile_by * 2);
@@ -962,7 +1006,8 @@ void coarse_factorize(rsp_context* ctx, const Items& I, const int* ilist, const 
   Timed t(ctx, KID_COARSE_SETUP, st, fl, by);
   rsp::launch_coarse_sums(I, x, w.csum, st);
   rsp::launch_coarse_factor(w.prob, ilist, (int)set.size(), nullptr, w.csum, w.sinv, st);
-  rsp::launch_coarse_inverse(w.prob, ilist, (int)set.size(), coarse_max_n(set), nullptr, w.sinv, w.ainv, st);
+  rsp::launch_coarse_inverse(w.prob, ilist, (int)set.size(), coarse_max_n(set), nullptr, w.csum, w.sinv, w.ainv,
+                             st);
 }
 
 int coarse_setup(rsp_context* ctx, const std::vector<Inst*>& go, const GmBatch& B, hipStream_t st) {
@@ -1145,12 +1190,14 @@ size_t batch_bytes(const rsp_problem* const* probs, int count, const rsp_options
   std::vector<Partition> parts(count);
   std::vector<const Partition*> pp;
   std::vector<size_t> ns;
+  std::vector<long long> nc;
   for (int q = 0; q < count; ++q) {
     if (make_partition(probs[q], &parts[q]) < 0) return 0;
     pp.push_back(&parts[q]);
     ns.push_back((size_t)probs[q]->nx * probs[q]->ny);
+    nc.push_back(probs[q]->coef ? coef_doubles(probs[q]->nx, probs[q]->ny) : 0);
   }
-  return layout_bytes(geometry_of(pp, ns), o);
+  return layout_bytes(geometry_of(pp, ns, nc), o);
 }
 
 int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*>& live, hipStream_t st) {
@@ -1158,18 +1205,20 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   if (live.empty()) return fail(RSP_EINVAL, "no instance to place");
   std::vector<const Partition*> pp;
   std::vector<size_t> ns;
+  std::vector<long long> ncv;
   for (const Inst* in : live) {
     pp.push_back(&in->part);
     ns.push_back(in->n);
+    ncv.push_back(in->prob.coef ? coef_doubles(in->prob.nx, in->prob.ny) : 0);
   }
-  const Geometry g = geometry_of(pp, ns);
+  const Geometry g = geometry_of(pp, ns, ncv);
   if (o.coarse && 2 * g.csx_max > rsp::kCoarseMaxNc)
     return fail(RSP_EINVAL, "the second level supports at most %d subdomains per row (got %d)",
                 rsp::kCoarseMaxNc / 2, g.csx_max);
   Carve cg, cw;
-  double *yd, *f, *x;
+  double *yd, *f, *x, *coef;
   Work w;
-  carve_global(cg, g, &yd, &f, &x);
+  carve_global(cg, g, &yd, &f, &x, &coef);
   carve_work(cw, g, o, &w);
   if (ctx->budget && cg.off + cw.off > ctx->budget)
     return fail(RSP_ENOMEM, "workspace needs %zu bytes, budget is %zu", cg.off + cw.off, ctx->budget);
@@ -1190,18 +1239,29 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   }
   Carve cg2;
   cg2.base = (char*)ctx->gmem[tgt];
-  carve_global(cg2, g, &yd, &f, &x);
+  carve_global(cg2, g, &yd, &f, &x, &coef);
   // place the instances: move the state of those already placed, load new ones
-  long long noff = 0;
+  long long noff = 0, coff = 0;
   int sub0 = 0;
   for (size_t q = 0; q < live.size(); ++q) {
     Inst* in = live[q];
     const size_t n = in->n;
+    const long long nc = ncv[q];
     if (in->placed) {
       HIPCHK(hipMemcpyAsync(yd + noff, ctx->yd + in->noff, 8 * n, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(f + noff, ctx->f + in->noff, 8 * n, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(x + 2 * noff, ctx->x + 2 * in->noff, 16 * n, hipMemcpyDeviceToDevice, st));
+      if (nc) HIPCHK(hipMemcpyAsync(coef + coff, ctx->coef + in->coff, 8 * nc, hipMemcpyDeviceToDevice, st));
     } else {
+      if (nc) {
+        // the caller's coefficients, scaled by 1/h^2, into the layout
+        DevProblem P = rsp::dev_problem(in->prob, 0, 0, 0, 0, 0);
+        const long long nxf = (long long)(in->prob.nx + 1) * in->prob.ny;
+        const long long nyf = (long long)in->prob.nx * (in->prob.ny + 1);
+        auto al = [](long long v) { return (v + kAlignN - 1) / kAlignN * kAlignN; };
+        rsp::launch_coef_load(P, in->prob.coef, coef + coff, coef + coff + al(nxf), coef + coff + al(nxf) + al(nyf),
+                              st);
+      }
       HIPCHK(hipMemcpyAsync(yd + noff, in->yd, 8 * n, hipMemcpyDeviceToDevice, st));
       if (in->f) HIPCHK(hipMemcpyAsync(f + noff, in->f, 8 * n, hipMemcpyDeviceToDevice, st));
       else HIPCHK(hipMemsetAsync(f + noff, 0, 8 * n, st));
@@ -1214,14 +1274,18 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
     }
     in->slot = (int)q;
     in->noff = noff;
+    in->coff = nc ? coff : -1;
     in->sub0 = sub0;
     noff += ((long long)n + kAlignN - 1) / kAlignN * kAlignN;
+    coff += nc;
     sub0 += in->part.S;
   }
   ctx->gcur = tgt;
   ctx->yd = yd;
   ctx->f = f;
   ctx->x = x;
+  ctx->coef = coef;
+  ctx->var = g.ncoef > 0;
   // work arena (contents are rebuilt by every outer iteration)
   if (ctx->wcap < cw.off) {
     HIPCHK(hipStreamSynchronize(st));
@@ -1249,6 +1313,14 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   for (const Inst* in : live) {
     DevProblem& P = ctx->hprob[in->slot];
     P = rsp::dev_problem(in->prob, in->noff, g.S, g.txm, g.tym, g.M);
+    if (in->coff >= 0) {
+      const long long nxf = (long long)(in->prob.nx + 1) * in->prob.ny;
+      const long long nyf = (long long)in->prob.nx * (in->prob.ny + 1);
+      auto al = [](long long v) { return (v + kAlignN - 1) / kAlignN * kAlignN; };
+      P.cx = ctx->coef + in->coff;
+      P.cy = P.cx + al(nxf);
+      P.c0 = P.cy + al(nyf);
+    }
     P.csx = in->part.sx;
     P.csy = in->part.sy;
     P.cbx = (in->prob.nx + in->part.sx - 1) / in->part.sx;
@@ -1432,7 +1504,7 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
     auto t = Clock::now();
     // the smoothing of this step, read by the factor and the whole-system Jacobian
     P.eps_start = eps;
-    HIPCHK(hipMemcpyAsync(w.prob + in->slot, &P, sizeof(DevProblem), hipMemcpyHostToDevice, st));
+    RSPCHK(upload(ctx, w.prob + in->slot, &P, sizeof(DevProblem), st));
     if (precond) {
       // local Jacobians at x^k with smoothing eps_k
       {
@@ -1442,7 +1514,7 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
       {
         Timed tm(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
         rsp::launch_factor(I, M, w.tilex, nullptr, nullptr, -1.0, nullptr, 0.0, w.fac, ctx->fp32, w.g,
-                           w.fallback, w.counter, st);
+                           w.fallback, w.counter, ctx->var, st);
       }
       // w.F <- -M^{-1} F_eps(x^k): GMRES then solves (action) d = M^{-1} F
       {
@@ -1638,6 +1710,10 @@ int rsp_context_destroy(rsp_context* ctx) {
     if (m) (void)hipFree(m);
   if (ctx->wmem) (void)hipFree(ctx->wmem);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->upin) {
+    if (ctx->upin_off > 0) (void)hipDeviceSynchronize();   // uploads from the ring may be pending
+    (void)hipHostFree(ctx->upin);
+  }
   if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
   delete ctx;
   return 0;
@@ -1709,7 +1785,7 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
   const Items I = all_items(ctx);
   rsp::launch_restrict_halo(I, x, ctx->w.tilex, stream);
   rsp::launch_factor(I, ctx->geo.M, ctx->w.tilex, c, nullptr, eps, nullptr, 0.0, ctx->w.fac, ctx->fp32,
-                     ctx->w.g, ctx->w.fallback, ctx->w.counter, stream);
+                     ctx->w.g, ctx->w.fallback, ctx->w.counter, ctx->var, stream);
   rsp::launch_block_solve(I, ctx->geo.M, ctx->w.fac, ctx->fp32, rhs, z, stream);
   HIPCHK(hipGetLastError());
   return 0;

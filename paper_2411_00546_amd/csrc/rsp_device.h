@@ -22,6 +22,11 @@ struct DevProblem {
   double hx2i, hy2i;  // 1/hx^2, 1/hy^2
   double diag0;       // 2/hx^2 + 2/hy^2
   double dom_w;       // weight of the rows of y in the line factors' dominance test
+  // coefficients of A (diagonal tensor): cx = a1 / hx^2 at the x-faces [ny][nx+1], cy =
+  // a2 / hy^2 at the y-faces [ny+1][nx], c0 = a0 [ny][nx]; nullptr: A = -Laplacian
+  const double* cx;
+  const double* cy;
+  const double* c0;
   double eps_min, gamma;
   double eps_start;   // eps_0 of the local solves of the next evaluation
   long long noff;     // offset of this instance's [ny][nx] arrays
@@ -130,6 +135,34 @@ __device__ __forceinline__ bool second_to_arrive(int* __restrict__ counter, int 
   __syncthreads();   // every thread has read the flag before anyone reuses it
   if (last) __threadfence();
   return last;
+}
+
+// ---------------------------------------------------------------- the operator A
+// Coupling of node (i, j) to its west / east / south / north neighbour across the face
+// between them (a1 / hx^2 or a2 / hy^2), and the diagonal of A at the node.
+__device__ __forceinline__ double c_w(const DevProblem& P, int i, int j) {
+  return P.cx ? P.cx[(size_t)j * (P.nx + 1) + i] : P.hx2i;
+}
+__device__ __forceinline__ double c_e(const DevProblem& P, int i, int j) {
+  return P.cx ? P.cx[(size_t)j * (P.nx + 1) + i + 1] : P.hx2i;
+}
+__device__ __forceinline__ double c_s(const DevProblem& P, int i, int j) {
+  return P.cx ? P.cy[(size_t)j * P.nx + i] : P.hy2i;
+}
+__device__ __forceinline__ double c_n(const DevProblem& P, int i, int j) {
+  return P.cx ? P.cy[(size_t)(j + 1) * P.nx + i] : P.hy2i;
+}
+__device__ __forceinline__ double a_diag(const DevProblem& P, int i, int j) {
+  if (!P.cx) return P.diag0;
+  return c_w(P, i, j) + c_e(P, i, j) + c_s(P, i, j) + c_n(P, i, j) + P.c0[(size_t)j * P.nx + i];
+}
+// (A v)_ij from the value at the node and its four neighbours (0 beyond the boundary);
+// the Laplacian keeps its own expression.
+__device__ __forceinline__ double apply_a(const DevProblem& P, int i, int j, double vc, double vw, double ve,
+                                          double vs, double vn) {
+  if (!P.cx) return P.diag0 * vc - P.hx2i * (vw + ve) - P.hy2i * (vs + vn);
+  const double w = c_w(P, i, j), e = c_e(P, i, j), s = c_s(P, i, j), n = c_n(P, i, j);
+  return (w + e + s + n + P.c0[(size_t)j * P.nx + i]) * vc - (w * vw + e * ve) - (s * vs + n * vn);
 }
 
 // ---------------------------------------------------------------- pointwise

@@ -37,7 +37,7 @@ void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t s
 // launches (subdomains redone with partial pivoting; arrival of the two workgroups).
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, int* counter, hipStream_t st);
+                   int* fallback, int* counter, bool var, hipStream_t st);
 // a5: outward sweeps after the fused inward sweeps and twist of launch_factor.
 void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
                       const double* g, double* out, hipStream_t st);
@@ -57,7 +57,8 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
                       hipStream_t st);
 // Second level (kernels_coarse.hip).  Coarse vectors have 2 entries (fields) per item.
-// Sums over each core of phi'(y), g'(p) / nu, phi''(y) p - 1 at x (eps_min): sums[3 items].
+// Sums over each core of phi'(y), g'(p) / nu, phi''(y) p - 1 at x (eps_min) and, with
+// variable coefficients of A, its face couplings and sum of a0: sums[8 items].
 void launch_coarse_sums(const Items& I, const double* x, double* sums, hipStream_t st);
 // cv[2 s + f] = sum over the core of item s of v (mode 0) or F'_eps_min(x) v (mode 1).
 void launch_coarse_project(const Items& I, int mode, const double* x, const double* v, double* cv,
@@ -67,7 +68,7 @@ void launch_coarse_factor(const DevProblem* prob, const int* list, int count, co
                           const double* sums, double* sinv, hipStream_t st);
 // A0^{-1} densely into ainv (max_n: the largest 2 S of the listed instances).
 void launch_coarse_inverse(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
-                           const double* sinv, double* ainv, hipStream_t st);
+                           const double* sums, const double* sinv, double* ainv, hipStream_t st);
 // ev = scale A0^{-1} cv on each listed instance's coarse unknowns.
 void launch_coarse_solve(const DevProblem* prob, const int* list, int count, int max_n, const GmState* gst,
                          const double* ainv, const double* cv, double scale, double* ev, hipStream_t st);
@@ -75,6 +76,7 @@ void launch_coarse_solve(const DevProblem* prob, const int* list, int count, int
 // (pointers at the instance's arrays).
 void launch_global_residual(const DevProblem& P, const double* yd, const double* f,
                             const double* x, double eps, double* out, hipStream_t st);
+void launch_coef_load(const DevProblem& P, const double* src, double* cx, double* cy, double* c0, hipStream_t st);
 void launch_control(const DevProblem& P, const double* p, double eps, double* u, hipStream_t st);
 // out = F'_eps(x) d on the whole grid of instance `inst` (batch vectors; eps is the
 // instance's eps_start in prob, the device table; P its host copy, for the grid size).

@@ -30,7 +30,8 @@ class rsp_problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("phi_kind", ctypes.c_int32),
                 ("kappa", ctypes.c_double), ("nu", ctypes.c_double), ("mu", ctypes.c_double),
                 ("eps0", ctypes.c_double), ("eps_min", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("sx", ctypes.c_int32), ("sy", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("coef", ctypes.c_void_p)]
 
 
 class rsp_options(ctypes.Structure):
@@ -194,10 +195,20 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_problem(p):
-    """rsp_problem from a synth.Problem-like object."""
+def make_problem(p, coef=None):
+    """rsp_problem from a synth.Problem-like object.  coef: device tensor (float64) with
+    the coefficients of A in the layout of rsp_problem.coef (a1 [ny][nx+1], a2 [ny+1][nx],
+    a0 [ny][nx]); required when p.coef is set, and kept alive by the caller."""
+    ptr = None
+    if coef is not None:
+        want = (p.nx + 1) * p.ny + p.nx * (p.ny + 1) + p.nx * p.ny
+        if coef.numel() != want or not coef.is_contiguous():
+            raise ValueError("coef must be a contiguous tensor of %d doubles" % want)
+        ptr = _ptr(coef)
+    elif getattr(p, "coef", 0):
+        raise ValueError("the problem has variable coefficients: pass them as coef")
     return rsp_problem(p.nx, p.ny, p.phi, p.kappa, p.nu, p.mu, p.eps0, p.eps_min, p.gamma,
-                       p.sx, p.sy, p.overlap)
+                       p.sx, p.sy, p.overlap, ptr)
 
 
 def make_options(o, eps_snapshots=None):

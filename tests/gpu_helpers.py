@@ -26,6 +26,17 @@ def rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
+def problem_of(R, prob):
+    """(rsp_problem, coefficient tensor or None): the tensor must stay alive while the
+    problem is in use."""
+    cf = prob.coefficients() if getattr(prob, "coef", 0) else None
+    if cf is None:
+        return R.make_problem(prob), None
+    import synth
+    t = dev(synth.pack_coefficients(*cf))
+    return R.make_problem(prob, t), t
+
+
 def solve(R, prob, opts, yd, f=None, snapshots=0, method="raspen"):
     """One solve on a fresh context.  Returns (status, history, x = (y, p), u[, snaps]),
     snaps: [snapshots][2 n] host array when snapshots > 0.  A hard error raises
@@ -42,8 +53,9 @@ def solve(R, prob, opts, yd, f=None, snapshots=0, method="raspen"):
         snap = dev(np.full((snapshots, 2, prob.ny, prob.nx), np.nan))
     fn = {"raspen": R.rsp_solve, "newton_ras": R.rsp_solve_newton_ras, "newton": R.rsp_solve_newton}[method]
     ctx = R.rsp_context_create(0)
+    rp, coef = problem_of(R, prob)
     try:
-        st, h = fn(ctx, R.make_problem(prob), R.make_options(o, snap), dev(yd),
+        st, h = fn(ctx, rp, R.make_options(o, snap), dev(yd),
                    None if f is None else dev(f), None, None, y, p, u)
         torch.cuda.synchronize()
     finally:
