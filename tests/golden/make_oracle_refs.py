@@ -11,6 +11,7 @@ Each file holds x = (y, p) (float64, [2 nx ny]; u follows from p), the status, t
 outer iteration count, the history of |F(x^k)|_2 and GMRES products and the oracle's
 time; names are listed in REFS.
 """
+import dataclasses
 import os
 import sys
 import time
@@ -39,6 +40,8 @@ REFS = {
     # at the 300-product cap in most outer steps; the parity run lets it converge)
     "precision_cfg": (synth.config_precision, {}),
     "precision_parity": (synth.config_precision, dict(PARITY, max_gmres=1000)),
+    # the 255 x 255 workload with the seeded variable coefficients of A
+    "plain_coef_cfg": (lambda: dataclasses.replace(synth.config_plain(), coef=1), {}),
 }
 
 
