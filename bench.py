@@ -40,16 +40,20 @@ BOUND = {"factor": ("mfma", FP64_PEAK_TFLOPS, "TFLOP/s"), "block_solve": ("hbm",
          "ras_precond": ("hbm", HBM_PEAK_GBS, "GB/s"), "global_jacobian": ("hbm", HBM_PEAK_GBS, "GB/s")}
 
 
-def workload(name, precision="fp64", max_refine=0, coarse=0):
+def workload(name, precision="fp64", max_refine=0, coarse=0, coef=0):
     import synth
     prob = synth.config_by_name(name)
+    prob.coef = coef
     opts = synth.Options(precision=1 if precision == "mixed" else 0, max_refine=max_refine, coarse=coarse)
     return prob, opts
 
 
 def describe(prob, opts):
-    return {"workload": "raspen_%dx%d_phi%d_%dx%d_ov%d" % (prob.nx, prob.ny, prob.phi, prob.sx, prob.sy,
-                                                          prob.overlap),
+    coef = getattr(prob, "coef", 0)
+    return {"workload": "raspen_%dx%d_phi%d_%dx%d_ov%d%s" % (prob.nx, prob.ny, prob.phi, prob.sx, prob.sy,
+                                                            prob.overlap, "_coef" if coef else ""),
+            "operator": ("-d/dx(a1 d/dx) - d/dy(a2 d/dy) + a0, seeded smooth coefficients "
+                         "(synth.coefficient_fields)") if coef else "-Laplacian (5-point)",
             "grid": [prob.nx, prob.ny], "phi": ["0", "y^3", "exp(y)-1", "kappa(y^3+exp(kappa y))"][prob.phi],
             "nu": prob.nu, "mu": prob.mu, "eps": [prob.eps0, prob.eps_min], "gamma": prob.gamma,
             "subdomains": [prob.sx, prob.sy], "overlap": prob.overlap,
@@ -162,7 +166,7 @@ def cpu_baseline(prob, opts, hist, max_sub=64):
                           sample_s))}
 
 
-ORACLE_REFS = {"plain": "plain_cfg", "precision": "precision_cfg"}
+ORACLE_REFS = {"plain": "plain_cfg", "precision": "precision_cfg", "plain_coef": "plain_coef_cfg"}
 
 
 def oracle_reference(work):
@@ -552,6 +556,8 @@ def main():
     ap.add_argument("--coarse", type=int, default=1, choices=[0, 1],
                     help="RASPEN: 1 (default) the two-level method (coarse correction of the outer "
                          "Newton systems), with the paper's one-level method timed beside it; 0 one level")
+    ap.add_argument("--coef", type=int, default=0, choices=[0, 1],
+                    help="1: the workload with the seeded variable coefficients of A")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-eps-errors", action="store_true",
                     help="skip the per-eps-step comparison with the oracle on sampled subdomains")
@@ -577,7 +583,7 @@ def main():
         print(json.dumps(run(args, R)))
         return
     coarse = args.coarse if args.method == "raspen" else 0
-    prob, opts = workload(args.workload, args.precision, args.max_refine, coarse)
+    prob, opts = workload(args.workload, args.precision, args.max_refine, coarse, args.coef)
     _, opts64 = workload(args.workload, "fp64", 0, coarse)
     _, opts_one = workload(args.workload, args.precision, args.max_refine, 0)
     yd, f = prob.inputs()
@@ -585,7 +591,11 @@ def main():
     ydt = torch.as_tensor(yd, dtype=torch.float64, device=dev).contiguous()
     ft = torch.as_tensor(f, dtype=torch.float64, device=dev).contiguous()
     y, p, u = (torch.empty_like(ydt) for _ in range(3))
-    P, O, O64 = R.make_problem(prob), R.make_options(opts), R.make_options(opts64)
+    coef_t = None
+    if args.coef:
+        import synth
+        coef_t = torch.as_tensor(synth.pack_coefficients(*prob.coefficients()), dtype=torch.float64, device=dev)
+    P, O, O64 = R.make_problem(prob, coef_t), R.make_options(opts), R.make_options(opts64)
     O1 = R.make_options(opts_one)
     ctx = R.rsp_context_create(0)
     tuning = None
@@ -675,7 +685,7 @@ def main():
                                 buf[:k, 1, y0:y1, x0:x1].reshape(k, -1)], 1).cpu().numpy()
         return out, k, h["snapshot_eps"]
 
-    ref = oracle_reference(args.workload) if args.method == "raspen" else None
+    ref = oracle_reference(args.workload + ("_coef" if args.coef else "")) if args.method == "raspen" else None
     sample = sample_subdomains(prob)
     part = R.rsp_partition(P)[3]
     try:

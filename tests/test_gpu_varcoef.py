@@ -234,3 +234,31 @@ def test_monolithic_newton_with_coefficients(R):
     st, h, x, u = solve(R, prob, TIGHT, yd, f, method="newton")
     ref = Raspen(prob, TIGHT, yd, f).solve()
     assert st == 0 and rel(x, ref["x"]) <= 1e-10
+
+
+def test_full_size_workload_against_the_stored_oracle_answer(R):
+    """255 x 255, 8 x 8 subdomains with the seeded coefficients, at the workload's own
+    tolerances: the oracle's solution is stored (tests/golden/oracle_plain_coef_cfg.npz,
+    written from the oracle alone).  FP64 within 1e-9 with the oracle's outer step count,
+    FP32 factors within 1e-8, one and two levels."""
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("refs", os.path.join(here, "golden", "make_oracle_refs.py"))
+    refs = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(refs)
+    ref = refs.load("plain_coef_cfg")
+    prob = refs.REFS["plain_coef_cfg"][0]()
+    assert prob.coef == 1
+    yd, f = prob.inputs()
+    o = refs.options_of("plain_coef_cfg")
+    for coarse in (0, 1):
+        st, h, x, u = solve(R, prob, with_(o, coarse=coarse), yd, f)
+        st_m, h_m, x_m, _ = solve(R, prob, with_(o, coarse=coarse, precision=1, max_refine=0), yd, f)
+        e64, em = rel(x, ref["x"]), rel(x_m, ref["x"])
+        print("255^2 with coefficients, coarse %d: FP64 outer %d (oracle %d) error %.3e; FP32 factors %.3e" % (
+            coarse, h["outer"], int(ref["outer"]), e64, em))
+        assert st == 0 and st_m == 0
+        if coarse == 0:
+            assert h["outer"] == int(ref["outer"])
+        assert e64 <= 1e-9 and em <= 1e-8
