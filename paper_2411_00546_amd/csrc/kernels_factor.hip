@@ -321,14 +321,16 @@ __device__ __forceinline__ void tile_store(T* X, int ldx, typename Mfma<T>::V c,
 // checking the partial-pivoting condition on the way (for the twist line, whose block
 // need not be column diagonally dominant), on the block with its rows of the first
 // field (rows below tx) weighted by wy, as the dominance test (see k_factor_mfma).  M / 16 waves; wave J owns column block J.
-// Wave K eliminates the whole column panel A[:, K] (a copy in Pn), which gives
+// Wave K eliminates the whole column panel A[:, K] (a copy in one of the two staging
+// panels of Pn, M x padded(16) each, taken in turn: wave K copies its panel back to A
+// after the step's last barrier while wave K + 1 already fills the other), which gives
 // A_KK^{-1} and the new column K at once and every multiplier a_ik / a_kk of the
 // elimination in natural order; if one exceeds 1 in magnitude for an unpivoted row,
 // partial pivoting would have swapped rows, and the function returns true (A is then
 // left partly eliminated).  The other waves form their row-panel tile A_KK^{-1} A_KJ
 // and update their column.  Returns false otherwise.
 template <typename T, int M>
-__device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy) {
+__device__ __forceinline__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
@@ -337,25 +339,26 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy)
   if (t == 0) *flag = 0;
 #pragma unroll 1
   for (int K = 0; K < NB; ++K) {
-    const T* Pinv = Pn + 16 * K * PLD;   // where the other waves find A_KK^{-1}
+    T* const Pk = Pn + (K & 1) * M * PLD;   // this step's staging panel
+    const T* Pinv = Pk + 16 * K * PLD;      // where the other waves find A_KK^{-1}
     if (J == K) {
       // lane (li, q4) owns rows li + 16 r (r < NB), columns 4 q4 .. 4 q4 + 3 of the panel
       T own[NB][4];
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
         load4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, own[r]);
-        store4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, own[r]);
+        store4<T>(Pk + (li + 16 * r) * PLD + 4 * q4, own[r]);
       }
       bool swap = false;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int kk = 16 * K + k;               // pivot row
         T prow[4];
-        load4<T>(Pn + kk * PLD + 4 * q4, prow);
+        load4<T>(Pk + kk * PLD + 4 * q4, prow);
         T pcol[NB];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) pcol[r] = Pn[(li + 16 * r) * PLD + k];
-        const T piv = Pn[kk * PLD + k];
+        for (int r = 0; r < NB; ++r) pcol[r] = Pk[(li + 16 * r) * PLD + k];
+        const T piv = Pk[kk * PLD + k];
         const T inv = recip(piv);
         const T wpiv = (kk < tx ? wy : (T)1) * fabs(piv);
 #pragma unroll
@@ -370,7 +373,7 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy)
             own[r][q] = on_col ? (on_row ? inv : -pcol[r] * inv)
                                : (on_row ? tr : fma(-pcol[r], tr, own[r][q]));
           }
-          store4<T>(Pn + i * PLD + 4 * q4, own[r]);
+          store4<T>(Pk + i * PLD + 4 * q4, own[r]);
         }
       }
       if (__any(swap) && lane == 0) *flag = 1;
@@ -407,7 +410,7 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy)
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
         T v[4];
-        load4<T>(Pn + (li + 16 * r) * PLD + 4 * q4, v);
+        load4<T>(Pk + (li + 16 * r) * PLD + 4 * q4, v);
         store4<T>(A + (li + 16 * r) * LD + 16 * K + 4 * q4, v);
       }
     }
@@ -431,7 +434,7 @@ __device__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* flag, int tx, T wy)
 // panels alternate between steps, so a step needs one barrier.  St: 2 panels of
 // M x padded(16).
 template <typename T, int M>
-__device__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
+__device__ __forceinline__ void block_gauss_jordan(typename Mfma<T>::V (&c)[M / 16], T* St) {
   constexpr int NB = M / 16;
   constexpr int PLD = padded<T>(16);
   using V = typename Mfma<T>::V;
@@ -537,7 +540,7 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
   __shared__ double vin[M], gprev[M];
   __shared__ double part[4 * M];
   __shared__ int flag;
-  // staging panels of the blocked Gauss-Jordan; the first is the column panel of the twist line
+  // the two staging panels of the blocked and of the panel Gauss-Jordan
   __shared__ __attribute__((aligned(16))) T St[2 * M * padded<T>(16)];
   T* const Pn = St;
 

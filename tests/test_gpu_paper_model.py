@@ -181,3 +181,41 @@ def test_monolithic_methods_match_oracle_on_the_model_problem(R, n, sx, sy, eps_
     assert h["outer"] == ref["iterations"], (h["outer"], ref["iterations"])
     assert sum(h["backtracks"]) == ref["backtracks"], (sum(h["backtracks"]), ref["backtracks"])
     assert np.abs(x - ref["x"]).max() <= 1e-10 * np.abs(ref["x"]).max()
+
+
+def test_local_solves_repeat_bitwise(R, model):
+    """Repeated local solves (line factors at an iterate of the eps_min = 1e-10 run, where
+    twist lines of the boundary rows of subdomains are not column dominant and take the
+    panel Gauss-Jordan with the partial-pivoting check) give bitwise the same result: the
+    staging panel of one elimination step is not overwritten by the next step's wave
+    while it is still copied back."""
+    import torch
+    prob, yd, f, xbar = model
+    prob.eps_min = 1e-10
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+    opts = synth.Options(tol_outer=1e-10, gmres_rtol=1e-12, max_gmres=4000, max_outer=30, continuation=1)
+    y, p, u = (t(np.zeros((prob.ny, prob.nx))) for _ in range(3))
+    ctx = R.rsp_context_create(0)
+    try:
+        R.rsp_solve_newton_ras(ctx, R.make_problem(prob), R.make_options(opts), t(yd), t(f), None, None, y, p, u)
+        x = torch.cat([y.reshape(-1), p.reshape(-1)])
+        R.rsp_setup(ctx, R.make_problem(prob), R.make_options(opts), t(yd), t(f))
+        S, txm, tym, _ = R.rsp_partition(R.make_problem(prob))
+        Fx = torch.empty_like(x)
+        R.rsp_residual(ctx, x, prob.eps_min, Fx)
+        rhs = torch.zeros(S, 2, tym, txm, dtype=torch.float64, device="cuda:0")
+        R.rsp_restrict(ctx, Fx, rhs)
+        c = torch.zeros_like(rhs)
+        z0 = torch.full_like(rhs, float("nan"))
+        R.rsp_local_solve(ctx, x, c, prob.eps_min, rhs, z0)
+        z = torch.empty_like(rhs)
+        bad = 0
+        for _ in range(200):
+            z.fill_(float("nan"))
+            R.rsp_local_solve(ctx, x, c, prob.eps_min, rhs, z)
+            bad += int(not torch.equal(z, z0))
+        torch.cuda.synchronize()
+    finally:
+        R.rsp_context_destroy(ctx)
+    assert torch.isfinite(z0).all()
+    assert bad == 0, bad
