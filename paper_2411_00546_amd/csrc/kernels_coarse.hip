@@ -43,8 +43,11 @@ __device__ __forceinline__ int core_h(const DevProblem& P, int r) { return min((
 
 // Sums over each core of phi'(y), g'(p) / nu and phi''(y) p - 1 at x (eps_min), and
 // with variable coefficients the couplings over the core's four sides and its sum of a0.
+// The three pointwise values of each node also go to pt ([3][ntot], batch layout), for the
+// products with F'(x) of the GMRES solve at this x.
 __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* __restrict__ x,
-                                                        double* __restrict__ sums) {
+                                                        double* __restrict__ sums, double* __restrict__ pt,
+                                                        long long ntot) {
   __shared__ double red[kBlock];
   int s;
   DevProblem P;
@@ -59,9 +62,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* _
     const int r = e / cw, q = e - r * cw;
     const size_t g = (size_t)(co.z + r) * P.nx + (co.x + q);
     const double yv = y[g], pv = p[g];
-    a += dphi_of(P.phi, yv, P.kappa);
-    b += dg_of(pv, P.mu, P.eps_min) * P.inv_nu;
-    c += ddphi_of(P.phi, yv, P.kappa) * pv - 1.0;
+    const double va = dphi_of(P.phi, yv, P.kappa);
+    const double vb = dg_of(pv, P.mu, P.eps_min) * P.inv_nu;
+    const double vc = ddphi_of(P.phi, yv, P.kappa) * pv - 1.0;
+    a += va;
+    b += vb;
+    c += vc;
+    const size_t o = (size_t)P.noff + g;
+    pt[o] = va;
+    pt[(size_t)ntot + o] = vb;
+    pt[2 * (size_t)ntot + o] = vc;
   }
   a = block_sum(a, red);
   b = block_sum(b, red);
@@ -101,10 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* _
   }
 }
 
-// c[2 s + f] = sum over the core of item s of v (mode 0) or of (F'_eps_min(x) v) (mode 1),
-// field f.
-__global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, const double* __restrict__ x,
-                                                           const double* __restrict__ v,
+// c[2 s + f] = sum over the core of item s of v (mode 0) or of (F'_eps_min(x) v) (mode 1,
+// with the pointwise blocks of F'(x) from pt, written by k_coarse_sums at this x), field f.
+__global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, const double* __restrict__ pt,
+                                                           long long ntot, const double* __restrict__ v,
                                                            double* __restrict__ cv) {
   __shared__ double red[kBlock];
   int s;
@@ -115,8 +125,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
   const size_t n = (size_t)P.nx * P.ny;
   const double* vy = v + 2 * P.noff;
   const double* vp = vy + n;
-  const double* y = x + 2 * P.noff;
-  const double* p = y + n;
   double ay = 0.0, ap = 0.0;
   for (int e = threadIdx.x; e < cw * ch; e += kBlock) {
     const int r = e / cw, q = e - r * cw;
@@ -132,10 +140,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
                               j > 0 ? vy[g - P.nx] : 0.0, j + 1 < P.ny ? vy[g + P.nx] : 0.0);
     const double lp = apply_a(P, i, j, dp, i > 0 ? vp[g - 1] : 0.0, i + 1 < P.nx ? vp[g + 1] : 0.0,
                               j > 0 ? vp[g - P.nx] : 0.0, j + 1 < P.ny ? vp[g + P.nx] : 0.0);
-    const double yv = y[g], pv = p[g];
-    const double d1 = dphi_of(P.phi, yv, P.kappa);
-    ay += ly + d1 * dy + dg_of(pv, P.mu, P.eps_min) * P.inv_nu * dp;
-    ap += (ddphi_of(P.phi, yv, P.kappa) * pv - 1.0) * dy + lp + d1 * dp;
+    const size_t o = (size_t)P.noff + g;
+    const double d1 = pt[o], gq = pt[(size_t)ntot + o], cc = pt[2 * (size_t)ntot + o];
+    ay += ly + d1 * dy + gq * dp;
+    ap += cc * dy + lp + d1 * dp;
   }
   ay = block_sum(ay, red);
   ap = block_sum(ap, red);
@@ -429,12 +437,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(const DevProble
 
 }  // namespace
 
-void launch_coarse_sums(const Items& I, const double* x, double* sums, hipStream_t st) {
-  if (I.count > 0) k_coarse_sums<<<I.count, kBlock, 0, st>>>(I, x, sums);
+void launch_coarse_sums(const Items& I, const double* x, double* sums, double* pt, long long ntot, hipStream_t st) {
+  if (I.count > 0) k_coarse_sums<<<I.count, kBlock, 0, st>>>(I, x, sums, pt, ntot);
 }
-void launch_coarse_project(const Items& I, int mode, const double* x, const double* v, double* cv,
+void launch_coarse_project(const Items& I, int mode, const double* pt, long long ntot, const double* v, double* cv,
                            hipStream_t st) {
-  if (I.count > 0) k_coarse_project<<<I.count, kBlock, 0, st>>>(I, mode, x, v, cv);
+  if (I.count > 0) k_coarse_project<<<I.count, kBlock, 0, st>>>(I, mode, pt, ntot, v, cv);
 }
 void launch_coarse_factor(const DevProblem* prob, const int* list, int count, const GmState* gst,
                           const double* sums, double* sinv, hipStream_t st) {

@@ -256,6 +256,7 @@ struct Work {
   double *g = nullptr, *V = nullptr, *p1 = nullptr, *p2 = nullptr;
   // second level (rsp_options.coarse): core sums [3 S], coarse vectors [2 S], factors
   double *csum = nullptr, *cvec = nullptr, *evec = nullptr, *sinv = nullptr, *ainv = nullptr;
+  double* cpt = nullptr;   // pointwise blocks of F'(x) at the outer iterate, [3][ntot]
 };
 
 void carve_global(Carve& cv, const Geometry& g, double** yd, double** f, double** x, double** coef) {
@@ -311,6 +312,7 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
     w->evec = cv.take<double>(2 * S);
     w->sinv = cv.take<double>(g.sinv);
     w->ainv = cv.take<double>(g.ainv);
+    w->cpt = cv.take<double>(3 * (size_t)g.ntot);
   }
 }
 
@@ -402,13 +404,6 @@ struct rsp_context {
   void* pin = nullptr;
   size_t pin_cap = 0;
   hipEvent_t wait_ev = nullptr;   // completion of the work before a read-back
-  // pinned ring for the host-to-device uploads of the solve loop (item lists, instance
-  // constants): a copy from pageable memory holds the host until the stream has reached
-  // it, and the GPU then idles while the next launches are enqueued.  Regions are
-  // reused once a wait on upin_st has passed them.
-  char* upin = nullptr;
-  size_t upin_cap = 0, upin_off = 0;
-  hipStream_t upin_st = nullptr;
   std::vector<double> hnorm;
   std::vector<int> hlist[kLists], hilist[kLists];
   // the instance bound by rsp_setup / rsp_solve for the single-problem calls
@@ -443,36 +438,18 @@ int wait_stream(rsp_context* ctx, hipStream_t st) {
   HIPCHK(hipEventRecord(ctx->wait_ev, st));
   for (;;) {
     const hipError_t e = hipEventQuery(ctx->wait_ev);
-    if (e == hipSuccess) break;
+    if (e == hipSuccess) return 0;
     if (e != hipErrorNotReady) return fail(RSP_EHIP, "waiting for the stream: %s", hipGetErrorString(e));
   }
-  if (ctx->upin_st == st) ctx->upin_off = 0;   // every upload enqueued on st has been done
-  return 0;
 }
 
-// Enqueues the copy of n host bytes to device memory `dst` on `st` through the pinned
-// upload ring; `src` may be reused as soon as this returns.
+// Enqueues the copy of n host bytes (pageable memory) to device memory `dst` on `st`.
+// HIP stages a pageable source before the call returns, so `src` may be reused at once
+// (a pinned ring instead changed the results of the monolithic Newton solves: kept out).
 int upload(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_t st) {
+  (void)ctx;
   if (n == 0) return 0;
-  const size_t need = (n + 255) / 256 * 256;
-  if (ctx->upin_off > 0 && (ctx->upin_st != st || ctx->upin_off + need > ctx->upin_cap)) {
-    RSPCHK(wait_stream(ctx, ctx->upin_st));   // the ring's earlier copies may be pending
-    ctx->upin_off = 0;
-  }
-  if (need > ctx->upin_cap) {
-    if (ctx->upin) HIPCHK(hipHostFree(ctx->upin));   // nothing pending: upin_off == 0
-    ctx->upin = nullptr;
-    ctx->upin_cap = 0;
-    const size_t cap = std::max(need, (size_t)1 << 20);
-    void* p = nullptr;
-    HIPCHK(hipHostMalloc(&p, cap, hipHostMallocDefault));
-    ctx->upin = static_cast<char*>(p);
-    ctx->upin_cap = cap;
-  }
-  std::memcpy(ctx->upin + ctx->upin_off, src, n);
-  HIPCHK(hipMemcpyAsync(dst, ctx->upin + ctx->upin_off, n, hipMemcpyHostToDevice, st));
-  ctx->upin_off += need;
-  ctx->upin_st = st;
+  HIPCHK(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st));
   return 0;
 }
 
@@ -919,7 +896,7 @@ void gm_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const std::ve
       double fl, by;
       coarse_work(set, &fl, &by);
       Timed t(ctx, KID_COARSE, st, fl, by, step);
-      rsp::launch_coarse_project(I, 1, ctx->x, d, w.cvec, st);
+      rsp::launch_coarse_project(I, 1, w.cpt, ctx->geo.ntot, d, w.cvec, st);
       rsp::launch_coarse_solve(w.prob, B.list, B.count, coarse_max_n(set), skip_done ? w.gst : nullptr, w.ainv,
                                w.cvec, 1.0, w.evec, st);
     }
@@ -1004,7 +981,7 @@ void coarse_factorize(rsp_context* ctx, const Items& I, const int* ilist, const 
     by += 16.0 * in->n + 8.0 * (N * N + in->part.sy * nc * nc);
   }
   Timed t(ctx, KID_COARSE_SETUP, st, fl, by);
-  rsp::launch_coarse_sums(I, x, w.csum, st);
+  rsp::launch_coarse_sums(I, x, w.csum, w.cpt, ctx->geo.ntot, st);
   rsp::launch_coarse_factor(w.prob, ilist, (int)set.size(), nullptr, w.csum, w.sinv, st);
   rsp::launch_coarse_inverse(w.prob, ilist, (int)set.size(), coarse_max_n(set), nullptr, w.csum, w.sinv, w.ainv,
                              st);
@@ -1026,7 +1003,7 @@ int coarse_setup(rsp_context* ctx, const std::vector<Inst*>& go, const GmBatch& 
     for (const Inst* in : go)
       rsp::launch_global_residual(ctx->hprob[in->slot], ctx->yd + in->noff, ctx->f + in->noff, ctx->x + 2 * in->noff,
                                   in->prob.eps_min, w.r + 2 * in->noff, st);
-    rsp::launch_coarse_project(I, 0, nullptr, w.r, w.cvec, st);
+    rsp::launch_coarse_project(I, 0, nullptr, 0, w.r, w.cvec, st);
     rsp::launch_coarse_solve(w.prob, w.ilist[kLGo], (int)go.size(), max_n, nullptr, w.ainv, w.cvec, -1.0, w.evec,
                              st);
     rsp::launch_gm_zero(B, w.dx, st);
@@ -1710,10 +1687,6 @@ int rsp_context_destroy(rsp_context* ctx) {
     if (m) (void)hipFree(m);
   if (ctx->wmem) (void)hipFree(ctx->wmem);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
-  if (ctx->upin) {
-    if (ctx->upin_off > 0) (void)hipDeviceSynchronize();   // uploads from the ring may be pending
-    (void)hipHostFree(ctx->upin);
-  }
   if (ctx->wait_ev) (void)hipEventDestroy(ctx->wait_ev);
   delete ctx;
   return 0;
@@ -1816,7 +1789,7 @@ int rsp_coarse_jac_apply(rsp_context* ctx, const double* x, const double* d, dou
   const Items I = all_items(ctx);
   Work& w = ctx->w;
   coarse_factorize(ctx, I, w.ilist[kLGo], set, x, stream);
-  rsp::launch_coarse_project(I, 1, x, d, w.cvec, stream);
+  rsp::launch_coarse_project(I, 1, w.cpt, ctx->geo.ntot, d, w.cvec, stream);
   rsp::launch_coarse_solve(w.prob, w.ilist[kLGo], 1, coarse_max_n(set), nullptr, w.ainv, w.cvec, 1.0, w.evec, stream);
   jac_apply(ctx, I, sub_work(ctx, set, false), d, out, stream, -1, w.evec);
   HIPCHK(hipGetLastError());

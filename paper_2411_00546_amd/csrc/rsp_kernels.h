@@ -59,9 +59,11 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
 // Second level (kernels_coarse.hip).  Coarse vectors have 2 entries (fields) per item.
 // Sums over each core of phi'(y), g'(p) / nu, phi''(y) p - 1 at x (eps_min) and, with
 // variable coefficients of A, its face couplings and sum of a0: sums[8 items].
-void launch_coarse_sums(const Items& I, const double* x, double* sums, hipStream_t st);
-// cv[2 s + f] = sum over the core of item s of v (mode 0) or F'_eps_min(x) v (mode 1).
-void launch_coarse_project(const Items& I, int mode, const double* x, const double* v, double* cv,
+// The pointwise blocks of F'(x) of every core node go to pt ([3][ntot]).
+void launch_coarse_sums(const Items& I, const double* x, double* sums, double* pt, long long ntot, hipStream_t st);
+// cv[2 s + f] = sum over the core of item s of v (mode 0) or F'_eps_min(x) v (mode 1, the
+// pointwise blocks from pt as written by launch_coarse_sums at that x).
+void launch_coarse_project(const Items& I, int mode, const double* pt, long long ntot, const double* v, double* cv,
                            hipStream_t st);
 // Block elimination of A0 = Z^T F' Z per instance of the list: S_r^{-1} into sinv.
 void launch_coarse_factor(const DevProblem* prob, const int* list, int count, const GmState* gst,
