@@ -444,8 +444,8 @@ int wait_stream(rsp_context* ctx, hipStream_t st) {
 }
 
 // Enqueues the copy of n host bytes (pageable memory) to device memory `dst` on `st`.
-// HIP stages a pageable source before the call returns, so `src` may be reused at once
-// (a pinned ring instead changed the results of the monolithic Newton solves: kept out).
+// HIP stages a pageable source before the call returns, so `src` may be reused at once.
+// (A pinned staging ring measured no faster on the solves: these copies are small.)
 int upload(rsp_context* ctx, void* dst, const void* src, size_t n, hipStream_t st) {
   (void)ctx;
   if (n == 0) return 0;
