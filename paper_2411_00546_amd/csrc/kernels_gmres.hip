@@ -21,14 +21,14 @@
 // the classical Gram-Schmidt process applied twice.  An Arnoldi step is two launches
 // after the Jacobian action; a chunk of steps ends with one reduction and one small
 // launch that finish its last column.
-// Launch grid: (kGmBlocks, instances); blockIdx.y selects the instance, whose
+// Launch grid: (blocks, instances); blockIdx.y selects the instance, whose
 // vectors are its segment of the batch's concatenated vectors (basis vector k of
-// every instance: V + k ldv).  A per-instance stop
+// every instance: V + k ldv), and the instance uses gm_blocks(L) blocks of the row.  A per-instance stop
 // flag written by the Givens kernel lets the host enqueue a whole restart cycle
 // without reading anything back: the kernels of a stopped instance return at once.
 //
 // Reductions are deterministic and depend only on the instance's own length:
-// kGmBlocks fixed blocks each own a contiguous chunk, write their partial sums, and
+// gm_blocks(L) blocks each own a contiguous chunk, write their partial sums, and
 // every consumer adds the partials in block order.
 #include "rsp_kernels.h"
 
@@ -45,6 +45,7 @@ __device__ __forceinline__ size_t part_at(int i, int b) { return (size_t)i * kGm
 struct Seg {
   int i;          // instance
   size_t off, L;  // its vector segment
+  int nb;         // its reduction blocks, gm_blocks(L)
 };
 
 __device__ __forceinline__ Seg seg_of(const GmBatch& B) {
@@ -53,11 +54,13 @@ __device__ __forceinline__ Seg seg_of(const GmBatch& B) {
   const GmSeg sg = B.seg[g.i];
   g.off = (size_t)sg.off;
   g.L = (size_t)sg.L;
+  g.nb = gm_blocks(sg.L);
   return g;
 }
 
-__device__ __forceinline__ void chunk_of(size_t L, size_t& lo, size_t& hi) {
-  const size_t ch = (L + kGmBlocks - 1) / kGmBlocks;
+// Chunk of block blockIdx.x < nb of a vector of length L.
+__device__ __forceinline__ void chunk_of(size_t L, int nb, size_t& lo, size_t& hi) {
+  const size_t ch = (L + nb - 1) / nb;
   lo = blockIdx.x * ch;
   hi = lo + ch < L ? lo + ch : L;
   if (lo > L) lo = L;
@@ -110,14 +113,14 @@ __device__ __forceinline__ double block_sums(const double (&acc)[NB], int nv, do
   return r;
 }
 
-// h[i] = sum over blocks of partial[i][b] for i < nv -> LDS hs (every block, the same
-// fixed order for a given nv).
+// h[i] = sum over the nb blocks of partial[i][b] for i < nv -> LDS hs (every block, the
+// same fixed order for given nv and nb).
 //   nv <= 4 (norms, short bases): output i is summed by wave i, whose lane l adds
-//     blocks l, l + 64, l + 128, l + 192 in that order before the wave sum;
+//     blocks l, l + 64, l + 128, ... in that order before the wave sum;
 //   nv > 4: thread (i, q) adds blocks q, q + Q, ... with independent loads, then
 //     thread i adds the Q segment sums in order.
-__device__ __forceinline__ void gather_partials(const double* __restrict__ partial, int nv, double* hs) {
-  constexpr int R = kGmBlocks / 64;   // partials per lane and output
+__device__ __forceinline__ void gather_partials(const double* __restrict__ partial, int nv, int nb, double* hs) {
+  constexpr int R = kGmBlocks / 64;   // partials per lane and output, at most
   static_assert(kGmBlocks % 64 == 0 && kT == 256, "four waves, whole waves of partials");
   const int t = threadIdx.x;
   if (nv <= kT / 64) {
@@ -125,7 +128,8 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
     if (wave < nv) {
       double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc += partial[part_at(wave, lane + 64 * r)];
+      for (int r = 0; r < R; ++r)
+        if (lane + 64 * r < nb) acc += partial[part_at(wave, lane + 64 * r)];
       acc = wave_sum(acc);
       if (lane == 0) hs[wave] = acc;
     }
@@ -133,12 +137,12 @@ __device__ __forceinline__ void gather_partials(const double* __restrict__ parti
     return;
   }
   __shared__ double seg[kT];
-  const int Q = kT / nv < kGmBlocks ? kT / nv : kGmBlocks;
+  const int Q = kT / nv < nb ? kT / nv : nb;
   if (t < nv * Q) {
     const int i = t / Q, q = t - i * Q;
     double acc = 0.0;
 #pragma unroll 8
-    for (int b = q; b < kGmBlocks; b += Q) acc += partial[part_at(i, b)];
+    for (int b = q; b < nb; b += Q) acc += partial[part_at(i, b)];
     seg[t] = acc;
   }
   __syncthreads();
@@ -205,14 +209,14 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
                                                   double* __restrict__ p2, int withz) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
   const Seg g = seg_of(B);
-  if (B.st[g.i].done) return;
+  if (blockIdx.x >= g.nb || B.st[g.i].done) return;
   V += g.off;
   z += g.off;
   const double* u = V + (size_t)j * B.ldv;
   p1 += g.i * kPart;
   p2 += g.i * kPart;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   double aa[NB], cc[NB], bb = 0.0, dd = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) aa[i] = cc[i] = 0.0;
@@ -277,13 +281,13 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
 // FP64: its sign and size are rounding residue (on the order of 1e-16 |A v|^2).
 constexpr double kGmLucky = 1e-12;
 
-// The two reductions of an Arnoldi step gathered in one pass: ha[i] = sum over blocks of
-// pa[i][b] and hb[i] of pb[i][b], i < nv.  Thread (v, q), v < 2 nv (v < nv: pa), adds
-// blocks q, q + Q, ... (Q = kT / (2 nv)) with independent loads, then thread v adds
-// its Q segment sums in order: every block, the same fixed order for a given nv.
+// The two reductions of an Arnoldi step gathered in one pass: ha[i] = sum over the nb
+// blocks of pa[i][b] and hb[i] of pb[i][b], i < nv.  Thread (v, q), v < 2 nv (v < nv:
+// pa), adds blocks q, q + Q, ... (Q = kT / (2 nv)) with independent loads, then thread v
+// adds its Q segment sums in order: every block, the same fixed order for given nv, nb.
 // The loads of both arrays are in flight together.
 __device__ __forceinline__ void gather_pair(const double* __restrict__ pa, const double* __restrict__ pb, int nv,
-                                            double* ha, double* hb) {
+                                            int nb, double* ha, double* hb) {
   __shared__ double seg[kT];
   const int t = threadIdx.x;
   const int Q = kT / (2 * nv);
@@ -293,7 +297,7 @@ __device__ __forceinline__ void gather_pair(const double* __restrict__ pa, const
     const int i = v < nv ? v : v - nv;
     double acc = 0.0;
 #pragma unroll 8
-    for (int b = q; b < kGmBlocks; b += Q) acc += src[part_at(i, b)];
+    for (int b = q; b < nb; b += Q) acc += src[part_at(i, b)];
     seg[t] = acc;
   }
   __syncthreads();
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   __shared__ double scal[3];   // nu, lucky flag, v_j . z
   const Seg g = seg_of(B);
   GmState* st = B.st + g.i;
-  if (st->done) return;
+  if (blockIdx.x >= g.nb || st->done) return;
   GmHess* hz = B.hs + g.i;
   const int m = B.m;
   const int t = threadIdx.x;
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   double* Vj = V + (size_t)j * B.ldv;
   double* Vn = V + (size_t)(j + 1) * B.ldv;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   constexpr int EP = NB <= 32 ? 2 : 1;
   const size_t e0 = lo + threadIdx.x, e1 = e0 + kT;
   double v[NB], ue = 0.0, ze = 0.0;
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
     }
   }
   // a, b (p1) and c, d (p2) of this step, in one gather
-  gather_pair(p1 + g.i * kPart, p2 + g.i * kPart, j + 1, ha, hc);
+  gather_pair(p1 + g.i * kPart, p2 + g.i * kPart, j + 1, g.nb, ha, hc);
   if (j == 0) {
     if (t == 0) {
       scal[0] = 1.0;
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(kT) void k_gm_finish(GmBatch B, const double* __res
   const int m = B.m;
   const int t = threadIdx.x;
   // a, b in the order of the step kernel's gather (its second array is not used here)
-  gather_pair(p1 + g.i * kPart, p1 + g.i * kPart, j + 1, ha, colv);
+  gather_pair(p1 + g.i * kPart, p1 + g.i * kPart, j + 1, g.nb, ha, colv);
   second_pass_column(hz, m, j, ha, 1, colv, nu);
   if (t <= j) hz->Hr[t * m + j - 1] = colv[t];
   if (t < j) hz->H[t * m + j - 1] = colv[t];
@@ -535,10 +539,11 @@ __global__ __launch_bounds__(kT) void k_gm_start(GmBatch B, double* __restrict__
                                                  const double* __restrict__ pin, int first_cycle) {
   __shared__ double hs[1];
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   const size_t L = g.L;
   double* V0 = V + g.off;
   r += g.off;
-  gather_partials(pin + g.i * kPart, 1, hs);
+  gather_partials(pin + g.i * kPart, 1, g.nb, hs);
   const double beta = sqrt(hs[0]);
   GmState* st = B.st + g.i;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(kT) void k_gm_start(GmBatch B, double* __restrict__
   if (!(beta > 0.0)) return;
   const double inv = 1.0 / beta;
   size_t lo, hi;
-  chunk_of(L, lo, hi);
+  chunk_of(L, g.nb, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) V0[e] = r[e] * inv;
 }
 
@@ -564,6 +569,7 @@ __global__ __launch_bounds__(kT) void k_gm_update_x(GmBatch B, const double* __r
   __shared__ double ys[kGmMaxVec];
   __shared__ double rs[kGmMaxRestart * kGmMaxRestart];   // the k x k triangle R
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   const size_t L = g.L;
   V += g.off;
   x += g.off;
@@ -588,7 +594,7 @@ __global__ __launch_bounds__(kT) void k_gm_update_x(GmBatch B, const double* __r
   }
   __syncthreads();
   size_t lo, hi;
-  chunk_of(L, lo, hi);
+  chunk_of(L, g.nb, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) {
     double acc = x[e];
     // the basis loads are independent: eight in flight at a time, added in order
@@ -610,9 +616,10 @@ __global__ __launch_bounds__(kT) void k_gm_sumsq(GmBatch B, const double* __rest
                                                  double* __restrict__ partial) {
   __shared__ double red[(kT / 64) * kGmMaxVec];
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   v += g.off;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   double acc[1] = {0.0};
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) acc[0] = fma(v[e], v[e], acc[0]);
   const double r = block_sums<1>(acc, 1, red);
@@ -624,7 +631,7 @@ __global__ __launch_bounds__(kT) void k_gm_norms(GmBatch B, const double* __rest
                                                  double* __restrict__ out) {
   __shared__ double hs[1];
   const Seg g = seg_of(B);
-  gather_partials(partial + g.i * kPart, 1, hs);
+  gather_partials(partial + g.i * kPart, 1, g.nb, hs);
   if (threadIdx.x == 0) out[g.i] = sqrt(hs[0]);
 }
 
@@ -633,8 +640,9 @@ __global__ __launch_bounds__(kT) void k_gm_residual(GmBatch B, const double* __r
                                                     const double* __restrict__ w,
                                                     double* __restrict__ r) {
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) r[g.off + e] = b[g.off + e] - w[g.off + e];
 }
 
@@ -642,8 +650,9 @@ __global__ __launch_bounds__(kT) void k_gm_residual(GmBatch B, const double* __r
 __global__ __launch_bounds__(kT) void k_gm_axpy(GmBatch B, double a, const double* __restrict__ x,
                                                 double* __restrict__ y, int accumulate) {
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT)
     y[g.off + e] = accumulate ? fma(a, x[g.off + e], y[g.off + e]) : a * x[g.off + e];
 }
@@ -651,12 +660,13 @@ __global__ __launch_bounds__(kT) void k_gm_axpy(GmBatch B, double a, const doubl
 // x = 0
 __global__ __launch_bounds__(kT) void k_gm_zero(GmBatch B, double* __restrict__ x) {
   const Seg g = seg_of(B);
+  if (blockIdx.x >= g.nb) return;
   size_t lo, hi;
-  chunk_of(g.L, lo, hi);
+  chunk_of(g.L, g.nb, lo, hi);
   for (size_t e = lo + threadIdx.x; e < hi; e += kT) x[g.off + e] = 0.0;
 }
 
-dim3 grid_of(const GmBatch& B) { return dim3(kGmBlocks, B.count); }
+dim3 grid_of(const GmBatch& B) { return dim3(B.nbx, B.count); }
 
 }  // namespace
 

@@ -412,6 +412,7 @@ struct rsp_context {
   // captured launch sequences (hipGraphs), valid while the launch signature holds
   int graphs = 0;               // capture and replay (else plain stream launches)
   int gm_chunk = 32;            // Arnoldi steps between two reads of the GMRES headers
+  int gm_nbx = 1;               // grid width of the GMRES vector kernels (longest instance)
   int gm_op = 0;                // operator of GMRES: 0 the Jacobian action of Algorithm 4,
                                 // 1 F'_eps(x) of the whole system (monolithic Newton)
   hipStream_t cap = nullptr;    // private stream, only ever in capture mode
@@ -554,7 +555,7 @@ uint64_t launch_signature(const rsp_context* ctx) {
   val(ctx->yd), val(ctx->f), val(ctx->x);
   const rsp_options& o = ctx->opts;
   val(o.tol_inner), val(o.sigma), val(o.alpha_min), val(o.gmres_restart), val(o.max_inner);
-  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op);
+  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op), val(ctx->gm_nbx);
   return h;
 }
 
@@ -688,6 +689,7 @@ GmBatch gm_of(const rsp_context* ctx, const int* list, int count) {
   B.ldv = 2 * ctx->geo.ntot;
   B.count = count;
   B.m = ctx->opts.gmres_restart;
+  B.nbx = ctx->gm_nbx;
   return B;
 }
 
@@ -1284,6 +1286,7 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   // tables
   ctx->hprob.assign(g.ninst, DevProblem{});
   ctx->hseg.assign(g.ninst, GmSeg{});
+  ctx->gm_nbx = 1;
   std::vector<int4> hbox, hcore;
   std::vector<int> hinst;
   long long sinv_off = 0, ainv_off = 0;
@@ -1310,6 +1313,7 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
     ainv_off += N * N;
     ctx->hseg[in->slot].off = 2 * in->noff;
     ctx->hseg[in->slot].L = 2 * (long long)in->n;
+    ctx->gm_nbx = std::max(ctx->gm_nbx, rsp::gm_blocks(2 * (long long)in->n));
     for (int q = 0; q < in->part.S; ++q) {
       hbox.push_back(in->part.box[q]);
       hcore.push_back(in->part.core[q]);

@@ -89,7 +89,16 @@ struct SubState {
 // matrix with the Givens rotations and the rotated right-hand side.
 constexpr int kGmMaxRestart = 64;
 constexpr int kGmMaxVec = kGmMaxRestart + 1;
-constexpr int kGmBlocks = 256;        // fixed reduction blocks per instance of the GMRES vector kernels
+// Reduction blocks of the GMRES vector kernels for an instance of length L: about
+// kGmBlockElems elements each, at least kGmMinBlocks and at most kGmBlocks.  A function
+// of L alone, so an instance's sums are formed in the same order in any batch.
+constexpr int kGmBlocks = 512;
+constexpr int kGmMinBlocks = 16;
+constexpr long long kGmBlockElems = 1024;
+__host__ __device__ inline int gm_blocks(long long L) {
+  const long long b = (L + kGmBlockElems - 1) / kGmBlockElems;
+  return (int)(b < kGmMinBlocks ? kGmMinBlocks : (b > kGmBlocks ? kGmBlocks : b));
+}
 struct GmState {
   int m, maxit, steps, used, done, pad;
   double rtol, bnorm, beta, rel;
@@ -116,6 +125,7 @@ struct GmBatch {
   long long ldv;            // length of the concatenated vectors
   int count;
   int m;
+  int nbx;                  // grid width: gm_blocks of the longest instance of the context
 };
 
 // Two workgroups per subdomain: the second of the two to call this returns true (in
