@@ -26,6 +26,7 @@
 // formed densely from them (2 S columns in blocks, many workgroups), so that each coarse
 // solve in GMRES is one dense product.
 #include "rsp_kernels.h"
+#include "rsp_mfma.h"
 
 namespace rsp {
 
@@ -35,7 +36,7 @@ constexpr int kCoarseThreads = 256;
 // per item of the core sums: phi'(y), g'(p)/nu, phi''(y) p - 1, and (variable
 // coefficients) the face couplings west, east, south, north and the sum of a0
 constexpr int kCSum = 8;
-constexpr int kColBlock = 32;           // columns of A0^{-1} per workgroup
+constexpr int kColBlock = 8;            // columns of A0^{-1} per workgroup
 
 // Width of core column c / height of core row r of an instance.
 __device__ __forceinline__ int core_w(const DevProblem& P, int c) { return min((c + 1) * P.cbx, P.nx) - c * P.cbx; }
@@ -145,20 +146,38 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
     ay += ly + d1 * dy + gq * dp;
     ap += cc * dy + lp + d1 * dp;
   }
-  ay = block_sum(ay, red);
-  ap = block_sum(ap, red);
+  // both sums in one pass: butterfly inside each wave, then the waves in order (fixed
+  // order for thread 0, which writes them)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ay += __shfl_xor(ay, off, 64);
+    ap += __shfl_xor(ap, off, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[w] = ay;
+    red[kBlock / 64 + w] = ap;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    cv[2 * (size_t)s] = ay;
-    cv[2 * (size_t)s + 1] = ap;
+    double sy = 0.0, sp = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+      sy += red[q];
+      sp += red[kBlock / 64 + q];
+    }
+    cv[2 * (size_t)s] = sy;
+    cv[2 * (size_t)s + 1] = sp;
   }
 }
 
 // Block elimination of A0 over the core rows: S_r^{-1} for r = 0 .. sy-1, one workgroup
 // per instance (blockIdx.x -> instance list[blockIdx.x]).  A column diagonally dominant
 // S_r (the usual case: the Laplacian part dominates the pointwise sums) keeps its
-// diagonal pivots under partial pivoting and is inverted in place by Gauss-Jordan with
-// its pivots in order, one barrier per step (two buffers alternate); otherwise
-// W = [S_r | I] is reduced to [I | S_r^{-1}] with partial pivoting (rows swapped).
+// diagonal pivots under partial pivoting and is inverted with its pivots in order: for
+// nc <= 32 by the blocked Gauss-Jordan with 16 x 16 pivot blocks on the matrix cores
+// (two block steps instead of nc scalar ones), wider rows in place in LDS, one barrier
+// per step (two buffers alternate).  Otherwise W = [S_r | I] is reduced to
+// [I | S_r^{-1}] with partial pivoting (rows swapped).
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProblem* __restrict__ prob,
                                                                   const int* __restrict__ list,
                                                                   const GmState* __restrict__ gst,
@@ -172,6 +191,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
   __shared__ double W[kWords];
   __shared__ double colk[kCoarseMaxNc];
   __shared__ int piv;
+  // staging panels of the blocked Gauss-Jordan of rows of at most 32 coarse unknowns
+  __shared__ __attribute__((aligned(16))) double Stc[2 * 32 * padded<double>(16)];
   const int q = list ? list[blockIdx.x] : (int)blockIdx.x;
   if (gst && gst[q].done) return;
   const DevProblem P = prob[q];
@@ -220,6 +241,33 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
       if (t == 0) piv = any_bad ? 1 : 0;
     }
     __syncthreads();
+    if (piv == 0 && nc <= 32) {
+      // S_r padded to 32 x 32 with the identity, inverted by the blocked Gauss-Jordan on
+      // the matrix cores (pivot blocks in order, as partial pivoting would take them):
+      // waves 0 and 1 own the two column blocks, waves 2 and 3 only meet the barriers
+      using Vd = Mfma<double>::V;
+      const int lane = t & 63, J = t >> 6;
+      Vd c[2];
+#pragma unroll
+      for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int a = 16 * I + Mfma<double>::row(lane, q), b = 16 * J + (lane & 15);
+          c[I][q] = J >= 2 ? 0.0 : (a < nc && b < nc) ? W[a * LDW + b] : (a == b ? 1.0 : 0.0);
+        }
+      block_gauss_jordan<double, 32>(c, Stc);
+      if (J < 2) {
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int a = 16 * I + Mfma<double>::row(lane, q), b = 16 * J + (lane & 15);
+            if (a < nc && b < nc) Sq[((size_t)r * nc + a) * nc + b] = c[I][q];
+          }
+      }
+      __syncthreads();   // S_r^{-1} is read back by every thread for the next row
+      continue;
+    }
     if (piv == 0) {
       // in place, pivots in order: W -> S_r^{-1}.  Step k reads buffer `cur` and writes
       // the other: a_kk <- 1 / a_kk, row k <- row k / a_kk, column k <- -column k / a_kk,
@@ -327,13 +375,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_factor(const DevProbl
 // column block).  Column k (core row rk = k / nc, position lk) is the solution of
 // A0 z = e_k by the block sweeps g_r = S_r^{-1}(e_k[r] - C g_{r-1}),
 // z_r = g_r - S_r^{-1} C z_{r+1}; C = -diag(cw hy^-2), so -C multiplies by cw hy^-2.
+// Each row's S_r^{-1} and couplings are staged in LDS once for the workgroup's columns.
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProblem* __restrict__ prob,
                                                                    const int* __restrict__ list,
                                                                    const GmState* __restrict__ gst,
                                                                    const double* __restrict__ sums,
                                                                    const double* __restrict__ sinv,
                                                                    double* __restrict__ ainv) {
+  constexpr int LDS_ = kCoarseMaxNc + 1;
   __shared__ double Gl[kCoarseMaxNc * kColBlock];
+  __shared__ double Sl[kCoarseMaxNc * LDS_];
+  __shared__ double cb[kCoarseMaxNc];
   const int q = list ? list[blockIdx.y] : (int)blockIdx.y;
   if (gst && gst[q].done) return;
   const DevProblem P = prob[q];
@@ -342,11 +394,23 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
   if (k0 >= N) return;
   const double* Sq = sinv + P.sinv_off;
   double* Aq = ainv + P.ainv_off;
-  constexpr int PER = kCoarseMaxNc * kColBlock / kCoarseThreads;   // (a, column) pairs per thread
+  constexpr int PER = (kCoarseMaxNc * kColBlock + kCoarseThreads - 1) / kCoarseThreads;   // (a, column) pairs per thread
   double own[PER];
+  // S_r^{-1} and the couplings of core row r to the row below (side 5: south) or above
+  // (side 6: north) into LDS
+  auto stage = [&](int r, int side) {
+    const double* Sr = Sq + (size_t)r * nc * nc;
+    for (int e = t; e < nc * nc; e += kCoarseThreads) {
+      const int a = e / nc, b = e - a * nc;
+      Sl[a * LDS_ + b] = Sr[e];
+    }
+    for (int b = t; b < nc; b += kCoarseThreads)
+      cb[b] = P.cx ? sums[kCSum * (size_t)(P.sub0 + r * P.csx + (b >> 1)) + side] : core_w(P, b >> 1) * P.hy2i;
+    __syncthreads();
+  };
   // forward sweep
   for (int r = 0; r < sy; ++r) {
-    const double* Sr = Sq + (size_t)r * nc * nc;
+    stage(r, 5);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = t + u * kCoarseThreads;
@@ -355,14 +419,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
       if (a < nc && k < N) {
         const int rk = k / nc, lk = k - rk * nc;
         if (r == rk) {
-          v = Sr[(size_t)a * nc + lk];
+          v = Sl[a * LDS_ + lk];
         } else if (r > rk) {
-          for (int b = 0; b < nc; ++b) {
-            // coupling of core (r, b / 2) to the row below: its south side
-            const double cb = P.cx ? sums[kCSum * (size_t)(P.sub0 + r * P.csx + (b >> 1)) + 5]
-                                   : core_w(P, b >> 1) * P.hy2i;
-            v += Sr[(size_t)a * nc + b] * cb * Gl[b * kColBlock + kk];
-          }
+          for (int b = 0; b < nc; ++b) v += Sl[a * LDS_ + b] * cb[b] * Gl[b * kColBlock + kk];
         }
       }
       own[u] = v;
@@ -381,7 +440,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
   }
   // backward sweep (the last block row is final); each thread reads back its own g_r
   for (int r = sy - 2; r >= 0; --r) {
-    const double* Sr = Sq + (size_t)r * nc * nc;
+    stage(r, 6);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = t + u * kCoarseThreads;
@@ -389,12 +448,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(const DevProb
       double v = 0.0;
       if (a < nc && k < N) {
         double acc = 0.0;
-        for (int b = 0; b < nc; ++b) {
-          // coupling of core (r, b / 2) to the row above: its north side
-          const double cb = P.cx ? sums[kCSum * (size_t)(P.sub0 + r * P.csx + (b >> 1)) + 6]
-                                 : core_w(P, b >> 1) * P.hy2i;
-          acc += Sr[(size_t)a * nc + b] * cb * Gl[b * kColBlock + kk];
-        }
+        for (int b = 0; b < nc; ++b) acc += Sl[a * LDS_ + b] * cb[b] * Gl[b * kColBlock + kk];
         v = Aq[(size_t)(r * nc + a) * N + k] + acc;
       }
       own[u] = v;

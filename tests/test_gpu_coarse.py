@@ -191,3 +191,24 @@ def test_second_level_is_rejected_by_the_monolithic_methods(R):
     with pytest.raises(R.RaspenError) as e:
         solve(R, prob, TIGHT, yd, f, method="newton_ras")
     assert e.value.code == R.RSP_EINVAL
+
+
+@pytest.mark.parametrize("nx,sx", [(80, 20), (64, 16), (50, 13)])
+def test_operator_matches_the_oracle_on_wide_rows_of_cores(R, nx, sx):
+    """Rows of 2 sx coarse unknowns: 40 take the LDS form of the coarse block
+    Gauss-Jordan, 32 and 26 the one-wave register form (26 with identity padding)."""
+    prob = problem(nx=nx, ny=17, sx=sx, sy=2, overlap=2, phi=synth.PHI_EXP, nu=1e-3, mu=5e-3)
+    yd, f = prob.inputs()
+    rng = np.random.default_rng(21)
+    n = prob.nx * prob.ny
+    x = np.concatenate([0.05 * rng.standard_normal(n), 0.005 * rng.standard_normal(n)])
+    d = rng.standard_normal(2 * n)
+    ora = Raspen(prob, TIGHT, yd, f)
+    ora.eval_F(x, continuation=True)
+    Z = ora.coarse_basis()
+    J = ora.sys.jacobian(x, prob.eps_min)
+    A0 = ora.coarse_operator(x, Z)
+    qv = Z @ np.linalg.solve(A0, Z.T @ (J @ d))
+    want = ora.jac_apply(d - qv) - qv
+    got = gpu_operator(R, prob, TIGHT, yd, f, x, d)
+    assert rel(got, want) <= 1e-10
