@@ -191,11 +191,14 @@ __device__ __forceinline__ bool panel_gauss_jordan(T* A, int LD, T* Pn, int* fla
   return false;
 }
 
-// The usual path, two-ended (twisted) block LU over the lines of the tile, t = ty / 2:
-// workgroup blockIdx.y = 0 factors lines 0 .. t-1 from the top (S_j = D_j - hy^-4
-// S_{j-1}^{-1}), workgroup 1 lines ty-1 .. t+1 from the bottom (T_j = D_j - hy^-4
-// T_{j+1}^{-1}); the second of them to finish factors the twist line Z_t = D_t -
-// hy^-4 (S_{t-1}^{-1} + T_{t+1}^{-1}).  Each line block is assembled in LDS with its
+// The usual path, two-ended (twisted) block LU over the lines of the tile, t = ty / 2,
+// in two launches.  phase 0, two workgroups per subdomain: blockIdx.y = 0 factors lines
+// 0 .. t-1 from the top (S_j = D_j - hy^-4 S_{j-1}^{-1}), blockIdx.y = 1 lines ty-1 ..
+// t+1 from the bottom (T_j = D_j - hy^-4 T_{j+1}^{-1}).  phase 1, one workgroup per
+// subdomain: the twist line Z_t = D_t - hy^-4 (S_{t-1}^{-1} + T_{t+1}^{-1}) from the
+// stored inverses (the launch boundary makes both chains' stores visible; a hand-over
+// between the two workgroups inside one launch needs device-scope fences, which write
+// back the L2 and cost more than the second launch).  Each line block is assembled in LDS with its
 // column sums, checked for column diagonal dominance and inverted by the blocked
 // Gauss-Jordan on the matrix cores.  The fused sweep gives g_j (top), h_j (bottom) and
 // z_t = Z_t^{-1}(r_t + hy^-2 (g_{t-1} + h_{t+1})) for the Newton right-hand side.  A
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
                                                        double eps_fixed, const double* __restrict__ rhs,
                                                        double rhs_scale, T* __restrict__ facT,
                                                        double* __restrict__ gout, int* __restrict__ fallback,
-                                                       int* __restrict__ counter) {
+                                                       int phase) {
   constexpr int NT = 4 * M;             // 64 threads per column block
   constexpr int LD = padded<T>(M);
   constexpr int KC = M / 4;             // the forward sweep adds each row in 4 parts
@@ -242,9 +245,9 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
   // row weight of the first field in the dominance tests (a power of two, so the
   // weighted and the plain block take the same elimination arithmetic)
   const T wy = (T)P.dom_w;
-  const int half = blockIdx.y;
+  const int half = phase == 0 ? (int)blockIdx.y : 0;   // phase 1 combines as half 0 would
   const int j0 = half == 0 ? 0 : ty - 1, dir = half == 0 ? 1 : -1;
-  const int nlines = half == 0 ? tw : ty - 1 - tw;
+  const int nlines = phase != 0 ? 0 : half == 0 ? tw : ty - 1 - tw;
   T* Fs = facT + (size_t)s * P.tym * M * M;
   double* gs = gout + (size_t)s * P.tym * M;
   for (int i = t; i < M; i += NT) gprev[i] = 0.0;
@@ -469,12 +472,25 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
       solve_line(j);
     }
   }
-  if (bad && t == 0) atomicExch(fallback + s, 1);
-  if (!second_to_arrive(counter, s, &flag)) return;
-  __shared__ int other_bad;
-  if (t == 0) other_bad = atomicAdd(fallback + s, 0);
+  if (phase == 0) {
+    if (bad && t == 0) atomicExch(fallback + s, 1);
+    return;
+  }
+  // phase 1: a subdomain one of whose chains failed is redone by k_factor_pivot
+  if (fallback[s]) return;
+  // the inverse of line t - 1 into Mx, where the top chain leaves it (F[b][a] =
+  // inverse[a][b]: 16-byte loads along a)
+  if (tw > 0) {
+    const T* Fm = Fs + (size_t)(tw - 1) * M * M;
+    for (int e4 = t; e4 < M * M / 4; e4 += NT) {
+      const int e = 4 * e4, b = e / M, a0 = e - b * M;
+      T v[4];
+      load4<T>(Fm + e, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Mx[(a0 + q) * LD + b] = v[q];
+    }
+  }
   __syncthreads();
-  if (other_bad) return;
 
   // the twist line: Mx = -hy^-4 (F_{t-1} + F_{t+1}) from the stored inverses, then + D_t
   if (t < tx) {
@@ -483,11 +499,10 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     coefficients(y, p, tw, true);
   }
   if constexpr (VAR) __syncthreads();   // the twist couplings are read below
-  // This workgroup's last inverse (the line next to the twist on its side) is still
-  // in Mx; the other side's comes from global memory (stored transposed, F[b][a] =
-  // inverse[a][b]), 16-byte loads along a.
+  // The inverse of line t - 1 is in Mx; that of line t + 1 comes from global memory
+  // (stored transposed, F[b][a] = inverse[a][b]), 16-byte loads along a.
   {
-    const bool mine = nlines > 0;
+    const bool mine = tw > 0;
     const int jo = half == 0 ? tw + 1 : tw - 1;   // the other side's line
     const T* Fo = jo >= 0 && jo < ty ? Fs + (size_t)jo * M * M : nullptr;
     constexpr int PER = M * M / 4 / NT;           // 16-byte groups per thread (M = 16 k)
@@ -836,33 +851,40 @@ __global__ __launch_bounds__(kFacThreads) void k_factor_pivot(Items I, const dou
 
 }  // namespace
 
+// The chains (phase 0), the twist lines (phase 1), then the pivoting redo of the flagged
+// subdomains.
+template <typename T, int MM>
+void factor_launches(const Items& I, const double* tilex, const double* c, const SubState* state,
+                     double eps_fixed, const double* rhs, double rhs_scale, T* facT, double* g, int* fallback,
+                     bool var, hipStream_t st) {
+  const dim3 chains(I.count, 2), twist(I.count, 1);
+  if (var) {
+    k_factor_mfma<T, MM, true><<<chains, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g,
+                                                          fallback, 0);
+    k_factor_mfma<T, MM, true><<<twist, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g,
+                                                         fallback, 1);
+  } else {
+    k_factor_mfma<T, MM, false><<<chains, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g,
+                                                           fallback, 0);
+    k_factor_mfma<T, MM, false><<<twist, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g,
+                                                          fallback, 1);
+  }
+  k_factor_pivot<T, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, facT, g,
+                                                         fallback);
+}
+
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, int* counter, bool var, hipStream_t st) {
+                   int* fallback, bool var, hipStream_t st) {
   if (I.count <= 0) return;
-  const dim3 grid(I.count, 2);
   if (fp32) {
-#define RSP_CALL(MM)                                                                                   \
-  if (var)                                                                                             \
-    k_factor_mfma<float, MM, true><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                           (float*)facT, g, fallback, counter);         \
-  else                                                                                                 \
-    k_factor_mfma<float, MM, false><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, \
-                                                            (float*)facT, g, fallback, counter);        \
-  k_factor_pivot<float, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
-                                                             rhs_scale, (float*)facT, g, fallback)
+#define RSP_CALL(MM) \
+  factor_launches<float, MM>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, (float*)facT, g, fallback, var, st)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   } else {
-#define RSP_CALL(MM)                                                                                   \
-  if (var)                                                                                             \
-    k_factor_mfma<double, MM, true><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,        \
-                                                            rhs_scale, (double*)facT, g, fallback, counter); \
-  else                                                                                                 \
-    k_factor_mfma<double, MM, false><<<grid, 4 * MM, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,       \
-                                                             rhs_scale, (double*)facT, g, fallback, counter); \
-  k_factor_pivot<double, MM><<<I.count, kFacThreads, 0, st>>>(I, tilex, c, state, eps_fixed, rhs,      \
-                                                              rhs_scale, (double*)facT, g, fallback)
+#define RSP_CALL(MM) \
+  factor_launches<double, MM>(I, tilex, c, state, eps_fixed, rhs, rhs_scale, (double*)facT, g, fallback, var, st)
     RSP_DISPATCH_M(M, RSP_CALL)
 #undef RSP_CALL
   }

@@ -248,7 +248,6 @@ struct Work {
   int* inst = nullptr;                    // [S]
   SubState* state = nullptr;              // [S]
   int* fallback = nullptr;                // [S] factor fallback flags (0 between launches)
-  int* counter = nullptr;                 // [S] arrival counters of two-workgroup launches
   int* list[kLists] = {};                 // [S] item lists
   double *F = nullptr, *w = nullptr, *b = nullptr, *dx = nullptr, *r = nullptr;   // [2 ntot]
   double *tilex = nullptr, *c = nullptr, *dir = nullptr, *res = nullptr, *t1 = nullptr, *t2 = nullptr;
@@ -288,7 +287,6 @@ void carve_work(Carve& cv, const Geometry& g, const rsp_options& o, Work* w) {
   w->inst = cv.take<int>(S);
   w->state = cv.take<SubState>(S);
   w->fallback = cv.take<int>(S);
-  w->counter = cv.take<int>(S);
   for (auto& l : w->list) l = cv.take<int>(S);
   w->F = cv.take<double>(L);
   w->w = cv.take<double>(L);
@@ -780,7 +778,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
         {
           Timed t(ctx, KID_FACTOR, s, sw.factor_fl + sw.bwd_fl / 2, sw.factor_by);
           rsp::launch_factor(I, M, w.tilex, w.c, w.state, 0.0, w.res, -1.0, w.fac, ctx->fp32, w.g,
-                             w.fallback, w.counter, ctx->var, s);
+                             w.fallback, ctx->var, s);
         }
         {
           Timed t(ctx, KID_SOLVE_BWD, s, sw.bwd_fl, sw.bwd_by);
@@ -833,7 +831,7 @@ int run_eval(rsp_context* ctx, const std::vector<Inst*>& set, const std::vector<
   // factor at x^(i) = x + P_i C_i(x) for Algorithm 4
   {
     Timed t(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
-    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, w.fallback, w.counter, ctx->var, st);
+    rsp::launch_factor(I, M, w.tilex, w.c, nullptr, 0.0, nullptr, 0.0, w.fac, ctx->fp32, w.g, w.fallback, ctx->var, st);
   }
   {
     Timed t(ctx, KID_PROLONG, st, 0, all.tile_by * 2);
@@ -1326,7 +1324,6 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   HIPCHK(hipMemcpyAsync(ctx->w.core, hcore.data(), sizeof(int4) * g.S, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->w.inst, hinst.data(), sizeof(int) * g.S, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(ctx->w.fallback, 0, sizeof(int) * g.S, st));
-  HIPCHK(hipMemsetAsync(ctx->w.counter, 0, sizeof(int) * g.S, st));
   HIPCHK(hipStreamSynchronize(st));   // host tables are temporaries; old arena no longer read
   for (Inst* in : live) in->placed = true;
   ctx->hstate.assign(g.S, SubState{});
@@ -1495,7 +1492,7 @@ int monolithic_newton(rsp_context* ctx, Inst* in, bool precond, hipStream_t st) 
       {
         Timed tm(ctx, KID_FACTOR, st, all.factor_fl, all.factor_by);
         rsp::launch_factor(I, M, w.tilex, nullptr, nullptr, -1.0, nullptr, 0.0, w.fac, ctx->fp32, w.g,
-                           w.fallback, w.counter, ctx->var, st);
+                           w.fallback, ctx->var, st);
       }
       // w.F <- -M^{-1} F_eps(x^k): GMRES then solves (action) d = M^{-1} F
       {
@@ -1762,7 +1759,7 @@ int rsp_local_solve(rsp_context* ctx, const double* x, const double* c, double e
   const Items I = all_items(ctx);
   rsp::launch_restrict_halo(I, x, ctx->w.tilex, stream);
   rsp::launch_factor(I, ctx->geo.M, ctx->w.tilex, c, nullptr, eps, nullptr, 0.0, ctx->w.fac, ctx->fp32,
-                     ctx->w.g, ctx->w.fallback, ctx->w.counter, ctx->var, stream);
+                     ctx->w.g, ctx->w.fallback, ctx->var, stream);
   rsp::launch_block_solve(I, ctx->geo.M, ctx->w.fac, ctx->fp32, rhs, z, stream);
   HIPCHK(hipGetLastError());
   return 0;

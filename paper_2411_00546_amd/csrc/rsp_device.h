@@ -128,25 +128,6 @@ struct GmBatch {
   int nbx;                  // grid width: gm_blocks of the longest instance of the context
 };
 
-// Two workgroups per subdomain: the second of the two to call this returns true (in
-// all its threads), after which the first one's global writes are visible to it, and
-// the subdomain's counter is back at 0 for the next launch.  Neither workgroup waits
-// for the other.  Every thread of both workgroups calls it.
-__device__ __forceinline__ bool second_to_arrive(int* __restrict__ counter, int s, int* flag_lds) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int old = atomicAdd(counter + s, 1);
-    *flag_lds = old;
-    if (old == 1) atomicExch(counter + s, 0);
-  }
-  __syncthreads();
-  const bool last = *flag_lds == 1;
-  __syncthreads();   // every thread has read the flag before anyone reuses it
-  if (last) __threadfence();
-  return last;
-}
-
 // ---------------------------------------------------------------- the operator A
 // Coupling of node (i, j) to its west / east / south / north neighbour across the face
 // between them (a1 / hx^2 or a2 / hy^2), and the diagonal of A at the node.

@@ -33,11 +33,11 @@ void launch_ring_rhs(const Items& I, const double* d, double* rhs, hipStream_t s
 // smoothing is state[s].eps (state != nullptr; inactive items are skipped), else
 // eps_fixed when > 0, the instance's eps_start when < 0 (each instance its own
 // smoothing), else the instance's eps_min.  Two-ended (twisted) block LU with
-// the twist at line ty / 2.  fallback, counter: [items] flags and counters, 0 between
-// launches (subdomains redone with partial pivoting; arrival of the two workgroups).
+// the twist at line ty / 2 (a second launch).  fallback: [items] flags, 0 between
+// launches (subdomains redone with partial pivoting).
 void launch_factor(const Items& I, int M, const double* tilex, const double* c, const SubState* state,
                    double eps_fixed, const double* rhs, double rhs_scale, void* facT, int fp32, double* g,
-                   int* fallback, int* counter, bool var, hipStream_t st);
+                   int* fallback, bool var, hipStream_t st);
 // a5: outward sweeps after the fused inward sweeps and twist of launch_factor.
 void launch_solve_bwd(const Items& I, int M, const SubState* state, const void* facT, int fp32,
                       const double* g, double* out, hipStream_t st);
