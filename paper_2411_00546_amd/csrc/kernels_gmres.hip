@@ -220,10 +220,11 @@ __global__ __launch_bounds__(kT) void k_gm_reduce(GmBatch B, const double* __res
   double aa[NB], cc[NB], bb = 0.0, dd = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i) aa[i] = cc[i] = 0.0;
-  // two elements per pass (up to 32 basis vectors: the registers of both), the loads of
+  // two elements per pass (up to 12 basis vectors; beyond, the registers of both cost
+  // more occupancy than the second element's loads gain), the loads of
   // both in flight together; a second element past the chunk reads the first again and
   // counts 0
-  constexpr int EP = NB <= 32 ? 2 : 1;
+  constexpr int EP = NB <= 12 ? 2 : 1;
   for (size_t e = lo + threadIdx.x; e < hi; e += EP * kT) {
     const bool two = EP == 2 && e + kT < hi;
     const size_t e2 = two ? e + kT : e;
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   const int m = B.m;
   const int t = threadIdx.x;
   // loads that do not depend on the partial sums go out first: the Hessenberg block
-  // for t = H a, and the first two elements of this thread (the second one up to 32
+  // for t = H a, and the first two elements of this thread (the second one up to 12
   // basis vectors: the registers of both)
   for (int q = t; q < (j + 1) * j; q += kT) {
     const int r = q / j, i = q - r * j;
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(kT) void k_gm_vupdate(GmBatch B, double* __restrict
   double* Vn = V + (size_t)(j + 1) * B.ldv;
   size_t lo, hi;
   chunk_of(g.L, g.nb, lo, hi);
-  constexpr int EP = NB <= 32 ? 2 : 1;
+  constexpr int EP = NB <= 12 ? 2 : 1;
   const size_t e0 = lo + threadIdx.x, e1 = e0 + kT;
   double v[NB], ue = 0.0, ze = 0.0;
   double v1[EP == 2 ? NB : 1], ue1 = 0.0, ze1 = 0.0;
