@@ -13,7 +13,7 @@
 //   twist            Z_t = D_t - hy^-4 (S_{t-1}^{-1} + T_{t+1}^{-1})
 // and the explicit inverses F_j of S_j, T_j and Z_t are stored (the solves are
 // described in kernels_solve.hip).  The two chains are independent, so each
-// subdomain takes two workgroups, and the second one to finish factors the twist.
+// subdomain takes two workgroups for them; the twist lines follow in a second launch.
 //
 // Each line block is assembled and tested for column diagonal dominance with the rows
 // of y weighted by dom_w, a power of two near sqrt(nu) that balances the couplings
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(4 * M, (sizeof(T) == 4 && M <= 80) ? 4 : 1) void k_
     }
     block_gauss_jordan<T, M>(blk, St);
     store_regs(j);
-    // the inverse also to LDS, for the fused sweep and (last line) the twist
+    // the inverse also to LDS, for the fused sweep of the next line
 #pragma unroll
     for (int I = 0; I < NB; ++I) tile_store<T>(Mx + 16 * I * LD + 16 * wave, LD, blk[I], lane);
     __syncthreads();
