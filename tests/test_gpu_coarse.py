@@ -212,3 +212,29 @@ def test_operator_matches_the_oracle_on_wide_rows_of_cores(R, nx, sx):
     want = ora.jac_apply(d - qv) - qv
     got = gpu_operator(R, prob, TIGHT, yd, f, x, d)
     assert rel(got, want) <= 1e-10
+
+
+@pytest.mark.parametrize("nx,sx", [(50, 5), (80, 20)])
+def test_operator_matches_the_oracle_when_rows_of_cores_need_pivoting(R, nx, sx):
+    """nu = 1e-4: the sums of g'(p) / nu make the Schur complements of the rows of cores
+    lose column dominance in the control field (checked with the oracle's A0), so the
+    coarse factor takes its partial-pivoting form (rows of 10 and 40 unknowns)."""
+    prob = problem(nx=nx, ny=34, sx=sx, sy=4, overlap=2, phi=synth.PHI_EXP, nu=1e-4, mu=5e-3, seed=3)
+    yd, f = prob.inputs()
+    rng = np.random.default_rng(1)
+    n = prob.nx * prob.ny
+    x = np.concatenate([0.1 * rng.standard_normal(n), rng.standard_normal(n)])
+    d = rng.standard_normal(2 * n)
+    ora = Raspen(prob, TIGHT, yd, f)
+    ora.eval_F(x, continuation=True)
+    Z = ora.coarse_basis()
+    J = ora.sys.jacobian(x, prob.eps_min)
+    A0 = ora.coarse_operator(x, Z)
+    # the first row of cores is not column diagonally dominant
+    nc = 2 * sx
+    T0 = A0[:nc, :nc]
+    assert (np.abs(np.diag(T0)) <= np.abs(T0).sum(0) - np.abs(np.diag(T0))).any()
+    qv = Z @ np.linalg.solve(A0, Z.T @ (J @ d))
+    want = ora.jac_apply(d - qv) - qv
+    got = gpu_operator(R, prob, TIGHT, yd, f, x, d)
+    assert rel(got, want) <= 1e-10
