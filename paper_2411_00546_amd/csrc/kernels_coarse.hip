@@ -45,7 +45,7 @@ __device__ __forceinline__ int core_h(const DevProblem& P, int r) { return min((
 // Sums over each core of phi'(y), g'(p) / nu and phi''(y) p - 1 at x (eps_min), and
 // with variable coefficients the couplings over the core's four sides and its sum of a0.
 // The three pointwise values of each node also go to pt ([3][ntot], batch layout), for the
-// products with F'(x) of the GMRES solve at this x.
+// products with F'(x) of the GMRES solve at this x (the first with a0 added).
 __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* __restrict__ x,
                                                         double* __restrict__ sums, double* __restrict__ pt,
                                                         long long ntot) {
@@ -70,7 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* _
     b += vb;
     c += vc;
     const size_t o = (size_t)P.noff + g;
-    pt[o] = va;
+    // the diagonal of the pointwise blocks for the products: phi'(y), plus a0 of A
+    pt[o] = P.cx ? va + P.c0[g] : va;
     pt[(size_t)ntot + o] = vb;
     pt[2 * (size_t)ntot + o] = vc;
   }
@@ -114,6 +115,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_sums(Items I, const double* _
 
 // c[2 s + f] = sum over the core of item s of v (mode 0) or of (F'_eps_min(x) v) (mode 1,
 // with the pointwise blocks of F'(x) from pt, written by k_coarse_sums at this x), field f.
+// Summed over a core, the 5-point operator telescopes: each face between two nodes of
+// the core adds c (v_a - v_b) + c (v_b - v_a) = 0, so only the faces on the core's
+// boundary remain, c (v_inside - v_outside) with v = 0 beyond the grid; the a0 part of
+// A is in the first pointwise value.
 __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, const double* __restrict__ pt,
                                                            long long ntot, const double* __restrict__ v,
                                                            double* __restrict__ cv) {
@@ -137,14 +142,37 @@ __global__ __launch_bounds__(kBlock) void k_coarse_project(Items I, int mode, co
       continue;
     }
     const double dy = vy[g], dp = vp[g];
-    const double ly = apply_a(P, i, j, dy, i > 0 ? vy[g - 1] : 0.0, i + 1 < P.nx ? vy[g + 1] : 0.0,
-                              j > 0 ? vy[g - P.nx] : 0.0, j + 1 < P.ny ? vy[g + P.nx] : 0.0);
-    const double lp = apply_a(P, i, j, dp, i > 0 ? vp[g - 1] : 0.0, i + 1 < P.nx ? vp[g + 1] : 0.0,
-                              j > 0 ? vp[g - P.nx] : 0.0, j + 1 < P.ny ? vp[g + P.nx] : 0.0);
     const size_t o = (size_t)P.noff + g;
     const double d1 = pt[o], gq = pt[(size_t)ntot + o], cc = pt[2 * (size_t)ntot + o];
-    ay += ly + d1 * dy + gq * dp;
-    ap += cc * dy + lp + d1 * dp;
+    ay += d1 * dy + gq * dp;
+    ap += cc * dy + d1 * dp;
+  }
+  if (mode != 0) {
+    // the faces on the core's boundary: west, east, south and north sides in turn
+    const int nside = 2 * ch + 2 * cw;
+    for (int e = threadIdx.x; e < nside; e += kBlock) {
+      int i, j, di, dj;
+      double c;
+      if (e < ch) {
+        i = co.x, j = co.z + e, di = -1, dj = 0;
+        c = c_w(P, i, j);
+      } else if (e < 2 * ch) {
+        i = co.y - 1, j = co.z + e - ch, di = 1, dj = 0;
+        c = c_e(P, i, j);
+      } else if (e < 2 * ch + cw) {
+        i = co.x + e - 2 * ch, j = co.z, di = 0, dj = -1;
+        c = c_s(P, i, j);
+      } else {
+        i = co.x + e - 2 * ch - cw, j = co.w - 1, di = 0, dj = 1;
+        c = c_n(P, i, j);
+      }
+      const size_t g = (size_t)j * P.nx + i;
+      const int io = i + di, jo = j + dj;
+      const bool in = io >= 0 && io < P.nx && jo >= 0 && jo < P.ny;
+      const size_t go = in ? (size_t)jo * P.nx + io : g;
+      ay += c * (vy[g] - (in ? vy[go] : 0.0));
+      ap += c * (vp[g] - (in ? vp[go] : 0.0));
+    }
   }
   // both sums in one pass: butterfly inside each wave, then the waves in order (fixed
   // order for thread 0, which writes them)
