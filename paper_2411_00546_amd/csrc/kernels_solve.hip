@@ -10,10 +10,12 @@
 //   twist    z_t = F_t (r_t + c g_{t-1} + c h_{t+1})
 //   outward  z_j = g_j + c F_j z_{j+1} (j < t),  z_j = h_j + c F_j z_{j-1} (j > t)
 // (block LU of the local Jacobian, Section 4: x-derivative of F; eq. (DerC)).  The two
-// halves are independent until the twist, so the Jacobian action runs them in two
-// workgroups per subdomain: one launch for the inward halves, a second one in which
-// each workgroup forms the twist line from the first launch's results and sweeps its
-// half outward.
+// halves are independent until the twist, so the Jacobian action runs them side by side
+// in the two halves of one workgroup per subdomain (k_apply_one), which meet at the
+// twist line in LDS.  With FP64 factors from M = 80 on (whose registers that workgroup
+// would spill) they run in two workgroups per subdomain instead: one launch for the
+// inward halves, a second one in which each workgroup forms the twist line from the
+// first launch's results and sweeps its half outward (k_apply_in, k_apply_out).
 //
 // Each line is an M x M matrix-vector product that only depends on the previous
 // line through the (small) vector, so the matrices are streamed from HBM with
@@ -279,7 +281,7 @@ __device__ void sub_local_jacobian(const DevProblem& P, int s, int4 bx, int tx, 
 template <int M>
 __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty, int j0, int j1,
                                          const double* __restrict__ d, const double* __restrict__ ce,
-                                         double* gl) {
+                                         double* gl, int tid, int nthr) {
   const size_t n = (size_t)P.nx * P.ny;
   d += 2 * P.noff;
   auto val = [&](const double* df, int f, int gi, int gj) {
@@ -287,7 +289,7 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
     if (ce) v -= ce[2 * (size_t)(P.sub0 + (gj / P.cby) * P.csx + gi / P.cbx) + f];
     return v;
   };
-  for (int e = j0 * M + threadIdx.x; e < j1 * M; e += 4 * M) {
+  for (int e = j0 * M + tid; e < j1 * M; e += nthr) {
     const int j = e / M, i = e - j * M;
     double v = 0.0;
     if (i < 2 * tx) {
@@ -308,7 +310,7 @@ __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, i
 template <int M>
 __device__ __forceinline__ void core_out(const DevProblem& P, int4 bx, int4 co, int tx, int j0, int j1,
                                          const double* gl, const double* __restrict__ d,
-                                         double* __restrict__ out) {
+                                         double* __restrict__ out, int tid, int nthr) {
   const size_t n = (size_t)P.nx * P.ny;
   const int cw = co.y - co.x;
   const int b0 = max(j0, co.z - bx.z), b1 = min(j1, co.w - bx.z);
@@ -316,7 +318,7 @@ __device__ __forceinline__ void core_out(const DevProblem& P, int4 bx, int4 co, 
   const int ch = b1 - b0;
   d += 2 * P.noff;
   out += 2 * P.noff;
-  for (int e = threadIdx.x; e < 2 * cw * ch; e += 4 * M) {
+  for (int e = tid; e < 2 * cw * ch; e += nthr) {
     const int f = e / (cw * ch);
     const int r = e - f * cw * ch;
     const int b = b0 + r / cw, a = co.x - bx.x + (r % cw);
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_in(Items I, const TF* __restric
   const int j0 = half == 0 ? 0 : tw + 1, j1 = half == 0 ? tw : ty;   // lines of the half
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   double* gs = gbuf + (size_t)s * P.tym * M;
-  ring_rhs<M>(P, bx, tx, ty, j0, j1, d, ce, gl);
+  ring_rhs<M>(P, bx, tx, ty, j0, j1, d, ce, gl, threadIdx.x, 4 * M);
   __syncthreads();
   const Cpl cp = cpl_of(P, bx);
   if (half == 0) sweep_in<TF, M>(Fs, ty, 0, tw, 1, cp, gl, red);
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restri
   const int jlo = half == 0 ? min(clo, tw) : tw + 1;   // lines read back (besides the twist)
   const int jhi = half == 0 ? tw - 1 : max(chi, tw);
   for (int e = jlo * M + threadIdx.x; e < (jhi + 1) * M; e += 4 * M) gl[e] = gs[e];
-  ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, ce, gl);
+  ring_rhs<M>(P, bx, tx, ty, tw, tw + 1, d, ce, gl, threadIdx.x, 4 * M);
   __syncthreads();
   const Cpl cp = cpl_of(P, bx);
   for (int i = threadIdx.x; i < M; i += 4 * M) {
@@ -475,11 +477,154 @@ __global__ __launch_bounds__(4 * M) void k_apply_out(Items I, const TF* __restri
   twist_line<TF, M>(Fs, tw, gl, red);
   if (half == 0) {
     sweep_out<TF, M>(Fs, tw - 1, tw - jlo, -1, cp, gl, red, vsc);
-    core_out<M>(P, bx, co, tx, jlo, tw + 1, gl, d, out);
+    core_out<M>(P, bx, co, tx, jlo, tw + 1, gl, d, out, threadIdx.x, 4 * M);
   } else {
     sweep_out<TF, M>(Fs, tw + 1, jhi - tw, 1, cp, gl, red, vsc);
-    core_out<M>(P, bx, co, tx, tw + 1, jhi + 1, gl, d, out);
+    core_out<M>(P, bx, co, tx, tw + 1, jhi + 1, gl, d, out, threadIdx.x, 4 * M);
   }
+}
+
+// ---------------------------------------------------------------- one-workgroup action
+// Algorithm 4 in one workgroup per subdomain of 8M threads: two halves of 4M threads
+// (half 0: lines 0 .. t-1 inward and t-1 .. outward, half 1: lines ty-1 .. t+1 inward and
+// t+1 .. outward) run their sweeps side by side.  The halves meet at block barriers, so
+// each runs as many steps as the longer one (idle steps load and compute nothing but
+// pass the same barriers), and the twist line is formed between the inward and the
+// outward sweeps in LDS instead of across two launches.  Every value is formed by the
+// same operations in the same order as in k_apply_in / k_apply_out.
+
+// One line product of a half (act: this half has a line at this step): the half's
+// threads form their partial sums into their own red, every thread of the block passes
+// the barrier, then the half's threads tl < M add the row groups in order.
+template <typename TF, int M>
+__device__ __forceinline__ double line_product_half(const typename Sweep<TF, M>::VT (&buf)[Sweep<TF, M>::K],
+                                                    const double* v, int ac, int bg, int tl, bool act,
+                                                    double* red) {
+  using S = Sweep<TF, M>;
+  if (act) {
+    double sum[S::W];
+#pragma unroll
+    for (int w = 0; w < S::W; ++w) sum[w] = 0.0;
+#pragma unroll
+    for (int i = 0; i < S::K; ++i) {
+      const double vb = v[bg * S::K + i];
+      const TF* e = reinterpret_cast<const TF*>(&buf[i]);
+#pragma unroll
+      for (int w = 0; w < S::W; ++w) sum[w] = fma((double)e[w], vb, sum[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < S::W; ++w) red[bg * M + S::W * ac + w] = sum[w];
+  }
+  __syncthreads();
+  double y = 0.0;
+  if (act && tl < M) {
+#pragma unroll
+    for (int g = 0; g < S::G; ++g) y += red[g * M + tl];
+  }
+  return y;
+}
+
+// The inward (out == false) or outward sweep of both halves: this half's n lines from
+// j0 in direction dir, nmax (>= n, the same in both halves) steps.  Inward: gl_j <- F_j
+// gl_j and c gl_j added to line j + dir unless that is the twist line tw; outward:
+// gl_j += F_j (c gl_{j - dir}).
+template <typename TF, int M, bool OUT>
+__device__ void sweep_half(const TF* __restrict__ Fs, int ty, int tw, int j0, int n, int dir, int nmax,
+                           const Cpl& cp, double* gl, double* red, double* vs, int tl) {
+  using S = Sweep<TF, M>;
+  const int ac = tl % S::NC, bg = tl / S::NC;
+  const size_t MM = (size_t)M * M;
+  auto line = [&](int k) { return j0 + dir * min(k, n - 1); };
+  auto load = [&](int k, typename S::VT(&buf)[S::K]) {
+    if (n > 0) load_line<TF, M>(Fs + MM * line(k), ac, bg, buf);
+  };
+  typename S::VT b0[S::K], b1[S::K], b2[S::K];
+  load(0, b0);
+  load(1, b1);
+  auto step = [&](const typename S::VT(&buf)[S::K], int k) {
+    const bool act = k < n;
+    const int j = j0 + dir * k;
+    if constexpr (!OUT) {
+      const double y = line_product_half<TF, M>(buf, gl + (size_t)j * M, ac, bg, tl, act, red);
+      if (act && tl < M) {
+        gl[(size_t)j * M + tl] = y;
+        const int jn = j + dir;
+        if (jn >= 0 && jn < ty && jn != tw) gl[(size_t)jn * M + tl] += cp.at(max(j, jn), tl) * y;
+      }
+    } else {
+      const int jp = j - dir;
+      if (cp.cy) {
+        if (act && tl < M) vs[tl] = cp.at(max(j, jp), tl) * gl[(size_t)jp * M + tl];
+        __syncthreads();
+        const double y = line_product_half<TF, M>(buf, vs, ac, bg, tl, act, red);
+        if (act && tl < M) gl[(size_t)j * M + tl] += y;
+      } else {
+        const double y = line_product_half<TF, M>(buf, gl + (size_t)jp * M, ac, bg, tl, act, red);
+        if (act && tl < M) gl[(size_t)j * M + tl] += cp.c * y;
+      }
+    }
+    __syncthreads();
+  };
+  for (int k = 0; k < nmax; k += 3) {
+    load(k + 2, b2);
+    step(b0, k);
+    if (k + 1 >= nmax) break;
+    load(k + 3, b0);
+    step(b1, k + 1);
+    if (k + 2 >= nmax) break;
+    load(k + 4, b1);
+    step(b2, k + 2);
+  }
+}
+
+template <typename TF, int M>
+__global__ __launch_bounds__(8 * M) void k_apply_one(Items I, const TF* __restrict__ facT,
+                                                     const double* __restrict__ d, const double* __restrict__ ce,
+                                                     double* __restrict__ out) {
+  using S = Sweep<TF, M>;
+  __shared__ double gl[kMaxTile * M];
+  __shared__ double red[2 * S::G * M];
+  __shared__ double vsc[2 * M];
+  int s;
+  DevProblem P;
+  if (!item_of(I, s, P)) return;
+  const int4 bx = I.box[s], co = I.core[s];
+  const int tx = bx.y - bx.x, ty = bx.w - bx.z, tw = ty / 2;
+  const int half = threadIdx.x >= 4 * M, tl = threadIdx.x - half * 4 * M;
+  const int clo = co.z - bx.z, chi = co.w - bx.z - 1;   // core lines
+  const TF* Fs = facT + (size_t)s * P.tym * M * M;
+  double* rh = red + half * S::G * M;
+  double* vh = vsc + half * M;
+  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl, threadIdx.x, 8 * M);
+  __syncthreads();
+  const Cpl cp = cpl_of(P, bx);
+  // inward: half 0 lines 0 .. tw-1, half 1 lines ty-1 .. tw+1
+  const int n0 = tw, n1 = ty - 1 - tw;
+  sweep_half<TF, M, false>(Fs, ty, tw, half == 0 ? 0 : ty - 1, half == 0 ? n0 : n1, half == 0 ? 1 : -1,
+                           max(n0, n1), cp, gl, rh, vh, tl);
+  // twist line: z_t = F_t (r_t + c g_{t-1} + c h_{t+1}), by half 0
+  if (half == 0 && tl < M) {
+    double v = gl[(size_t)tw * M + tl];
+    if (tw > 0) v += cp.at(tw, tl) * gl[(size_t)(tw - 1) * M + tl];
+    if (tw + 1 < ty) v += cp.at(tw + 1, tl) * gl[(size_t)(tw + 1) * M + tl];
+    gl[(size_t)tw * M + tl] = v;
+  }
+  __syncthreads();
+  {
+    typename S::VT b0[S::K];
+    const int ac = tl % S::NC, bg = tl / S::NC;
+    if (half == 0) load_line<TF, M>(Fs + (size_t)M * M * tw, ac, bg, b0);
+    const double y = line_product_half<TF, M>(b0, gl + (size_t)tw * M, ac, bg, tl, half == 0, rh);
+    if (half == 0 && tl < M) gl[(size_t)tw * M + tl] = y;
+    __syncthreads();
+  }
+  // outward to the core lines: half 0 lines tw-1 .. jlo, half 1 lines tw+1 .. jhi
+  const int jlo = min(clo, tw), jhi = max(chi, tw);
+  const int m0 = tw - jlo, m1 = jhi - tw;
+  sweep_half<TF, M, true>(Fs, ty, tw, half == 0 ? tw - 1 : tw + 1, half == 0 ? m0 : m1, half == 0 ? -1 : 1,
+                          max(m0, m1), cp, gl, rh, vh, tl);
+  if (half == 0) core_out<M>(P, bx, co, tx, jlo, tw + 1, gl, d, out, tl, 4 * M);
+  else core_out<M>(P, bx, co, tx, tw + 1, jhi + 1, gl, d, out, tl, 4 * M);
 }
 
 // Algorithm 4 with nref FP64 refinement steps of each local solve (the local Jacobian at
@@ -501,12 +646,12 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
   const int4 bx = I.box[s], co = I.core[s];
   const int tx = bx.y - bx.x, ty = bx.w - bx.z;
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
-  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl);
+  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl, threadIdx.x, 4 * M);
   __syncthreads();
   const Cpl cp = cpl_of(P, bx);
   full_solve<TF, M>(Fs, ty, 0, ty - 1, cp, gl, red, vsc);
   for (int it = 0; it < nref; ++it) {
-    ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, rb);
+    ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, rb, threadIdx.x, 4 * M);
     __syncthreads();
     sub_local_jacobian<M>(P, s, bx, tx, ty, tilex, c, P.eps_min, gl, rb);
     __syncthreads();
@@ -514,7 +659,7 @@ __global__ __launch_bounds__(4 * M) void k_apply_refined(Items I, const TF* __re
     for (int e = threadIdx.x; e < ty * M; e += 4 * M) gl[e] += rb[e];
     __syncthreads();
   }
-  core_out<M>(P, bx, co, tx, 0, ty, gl, d, out);
+  core_out<M>(P, bx, co, tx, 0, ty, gl, d, out, threadIdx.x, 4 * M);
 }
 
 #define RSP_DISPATCH_M(M_, CALL) \
@@ -596,9 +741,15 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
 #undef RSP_REF
     return;
   }
+// one workgroup of 8M threads per subdomain; FP64 factors from M = 80 on take the two
+// launches of 4M threads, whose registers the wider workgroup would spill
 #define RSP_TWO(TT, MM)                                                                        \
-  k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);                \
-  k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, ce, out)
+  if (sizeof(TT) == 8 && MM >= 80) {                                                           \
+    k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);              \
+    k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, ce, out);        \
+  } else {                                                                                     \
+    k_apply_one<TT, MM><<<I.count, 8 * MM, 0, st>>>(I, (const TT*)facT, d, ce, out);           \
+  }
   if (fp32) {
 #define RSP_CALL(MM) RSP_TWO(float, MM)
     RSP_DISPATCH_M(M, RSP_CALL)
