@@ -512,6 +512,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(const DevProble
   const double* Ar = ainv + P.ainv_off + (size_t)row * N;
   const double* c = cv + 2 * (size_t)P.sub0;
   double acc = 0.0;
+#pragma unroll 8
   for (int k = lane; k < N; k += 64) acc += Ar[k] * c[k];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) ev[2 * (size_t)P.sub0 + row] = scale * acc;

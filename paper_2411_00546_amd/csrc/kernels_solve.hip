@@ -277,16 +277,20 @@ __device__ void sub_local_jacobian(const DevProblem& P, int s, int4 bx, int tx, 
 // values of d just outside the tile (the ring), in line layout.  With the coarse
 // correction (ce != nullptr) the ring values are those of d - Z e: each has the coarse
 // value e of its node's core and field subtracted (core (gi / cbx, gj / cby) of the
-// instance, coarse unknown 2 (sub0 + core) + f).
+// instance, coarse unknown 2 (sub0 + core) + f).  etab != nullptr: the same values from
+// the workgroup's table of the cores its ring touches (apply_coarse_rect: from core
+// (ex0, ey0), ew cores wide).
 template <int M>
 __device__ __forceinline__ void ring_rhs(const DevProblem& P, int4 bx, int tx, int ty, int j0, int j1,
                                          const double* __restrict__ d, const double* __restrict__ ce,
-                                         double* gl, int tid, int nthr) {
+                                         double* gl, int tid, int nthr, const double* etab = nullptr,
+                                         int ex0 = 0, int ey0 = 0, int ew = 0) {
   const size_t n = (size_t)P.nx * P.ny;
   d += 2 * P.noff;
   auto val = [&](const double* df, int f, int gi, int gj) {
     double v = df[(size_t)gj * P.nx + gi];
-    if (ce) v -= ce[2 * (size_t)(P.sub0 + (gj / P.cby) * P.csx + gi / P.cbx) + f];
+    if (etab) v -= etab[2 * ((gj / P.cby - ey0) * ew + gi / P.cbx - ex0) + f];
+    else if (ce) v -= ce[2 * (size_t)(P.sub0 + (gj / P.cby) * P.csx + gi / P.cbx) + f];
     return v;
   };
   for (int e = j0 * M + tid; e < j1 * M; e += nthr) {
@@ -577,14 +581,18 @@ __device__ void sweep_half(const TF* __restrict__ Fs, int ty, int tw, int j0, in
   }
 }
 
+// ainv != nullptr: the coarse values of the cores the ring touches are formed here, each
+// by one wave in the order of k_coarse_solve, from A0^{-1} and the projection cv.
 template <typename TF, int M>
 __global__ __launch_bounds__(8 * M) void k_apply_one(Items I, const TF* __restrict__ facT,
                                                      const double* __restrict__ d, const double* __restrict__ ce,
-                                                     double* __restrict__ out) {
+                                                     const double* __restrict__ ainv,
+                                                     const double* __restrict__ cv, double* __restrict__ out) {
   using S = Sweep<TF, M>;
   __shared__ double gl[kMaxTile * M];
   __shared__ double red[2 * S::G * M];
   __shared__ double vsc[2 * M];
+  __shared__ double etab[kApplyCoarseMax];
   int s;
   DevProblem P;
   if (!item_of(I, s, P)) return;
@@ -595,7 +603,25 @@ __global__ __launch_bounds__(8 * M) void k_apply_one(Items I, const TF* __restri
   const TF* Fs = facT + (size_t)s * P.tym * M * M;
   double* rh = red + half * S::G * M;
   double* vh = vsc + half * M;
-  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl, threadIdx.x, 8 * M);
+  int ex0 = 0, ey0 = 0, ew = 0;
+  if (ainv) {
+    const int ne = min(apply_coarse_rect(bx, P.nx, P.ny, P.cbx, P.cby, &ex0, &ey0, &ew), kApplyCoarseMax);
+    const int N = 2 * P.csx * P.csy;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double* c = cv + 2 * (size_t)P.sub0;
+    for (int r = wave; r < ne; r += 8 * M / 64) {
+      const int q = r >> 1, f = r & 1;
+      const int row = 2 * ((ey0 + q / ew) * P.csx + ex0 + q % ew) + f;
+      const double* Ar = ainv + P.ainv_off + (size_t)row * N;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = lane; k < N; k += 64) acc += Ar[k] * c[k];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) etab[r] = acc;
+    }
+    __syncthreads();
+  }
+  ring_rhs<M>(P, bx, tx, ty, 0, ty, d, ce, gl, threadIdx.x, 8 * M, ainv ? etab : nullptr, ex0, ey0, ew);
   __syncthreads();
   const Cpl cp = cpl_of(P, bx);
   // inward: half 0 lines 0 .. tw-1, half 1 lines ty-1 .. tw+1
@@ -723,7 +749,7 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
-                      hipStream_t st) {
+                      const double* ainv, const double* cv, hipStream_t st) {
   if (I.count <= 0) return;
   const dim3 grid(I.count, 2);
   if (nref > 0) {
@@ -744,11 +770,11 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
 // one workgroup of 8M threads per subdomain; FP64 factors from M = 80 on take the two
 // launches of 4M threads, whose registers the wider workgroup would spill
 #define RSP_TWO(TT, MM)                                                                        \
-  if (sizeof(TT) == 8 && MM >= 80) {                                                           \
+  if (!apply_one_launch(MM, sizeof(TT) == 4)) {                                                \
     k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);              \
     k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, ce, out);        \
   } else {                                                                                     \
-    k_apply_one<TT, MM><<<I.count, 8 * MM, 0, st>>>(I, (const TT*)facT, d, ce, out);           \
+    k_apply_one<TT, MM><<<I.count, 8 * MM, 0, st>>>(I, (const TT*)facT, d, ce, ainv, cv, out); \
   }
   if (fp32) {
 #define RSP_CALL(MM) RSP_TWO(float, MM)

@@ -413,6 +413,8 @@ struct rsp_context {
   int gm_nbx = 1;               // grid width of the GMRES vector kernels (longest instance)
   int gm_op = 0;                // operator of GMRES: 0 the Jacobian action of Algorithm 4,
                                 // 1 F'_eps(x) of the whole system (monolithic Newton)
+  bool coarse_in_apply = false; // the two-level action forms the coarse values of each ring
+                                // in its own workgroups (no separate coarse solve launch)
   hipStream_t cap = nullptr;    // private stream, only ever in capture mode
   uint64_t gsig = 0;
   std::map<GraphKey, hipGraphExec_t> gcache;
@@ -553,7 +555,7 @@ uint64_t launch_signature(const rsp_context* ctx) {
   val(ctx->yd), val(ctx->f), val(ctx->x);
   const rsp_options& o = ctx->opts;
   val(o.tol_inner), val(o.sigma), val(o.alpha_min), val(o.gmres_restart), val(o.max_inner);
-  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op), val(ctx->gm_nbx);
+  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op), val(ctx->gm_nbx), val(ctx->coarse_in_apply);
   return h;
 }
 
@@ -854,11 +856,14 @@ double ortho_flops(double L, int q) { return L * (8.0 * q + 8); }
 double ortho_bytes(double L, int q) { return 8.0 * L * (2.0 * q + 6); }
 
 // step >= 0: Arnoldi step of a GMRES cycle (its timing is settled by settle_gmres_timing).
+// ce: the coarse values (d - Z ce on the rings); ainv, cv: the action forms them itself
+// from A0^{-1} and the projection cv (coarse_in_apply).
 void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
-               hipStream_t st, int step = -1, const double* ce = nullptr) {
+               hipStream_t st, int step = -1, const double* ce = nullptr, const double* ainv = nullptr,
+               const double* cv = nullptr) {
   Timed t(ctx, KID_BLOCK_SOLVE, st, apply_flops(ctx, sw), apply_bytes(ctx, sw), step);
   rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, ce, out, ctx->nref,
-                        ctx->w.g, st);
+                        ctx->w.g, ainv, cv, st);
 }
 
 // Largest number of coarse unknowns (2 S) over the instances of `set`.
@@ -869,12 +874,12 @@ int coarse_max_n(const std::vector<Inst*>& set) {
 }
 
 // Algorithmic work of the coarse correction in one GMRES product over the instances of
-// `set`: the core sums of F'(x) v (two vectors read, 28 flops per node) and the dense
-// coarse solve (2 S)^2.
-void coarse_work(const std::vector<Inst*>& set, double* fl, double* by) {
+// `set`: the core sums of F'(x) v (two vectors read, 28 flops per node) and, unless the
+// action forms the coarse values itself, the dense coarse solve (2 S)^2.
+void coarse_work(const std::vector<Inst*>& set, bool with_solve, double* fl, double* by) {
   *fl = *by = 0;
   for (const Inst* in : set) {
-    const double N = 2.0 * in->part.S;
+    const double N = with_solve ? 2.0 * in->part.S : 0.0;
     *fl += 28.0 * in->n + 2 * N * N;
     *by += 32.0 * in->n + 8 * N * N;
   }
@@ -892,15 +897,18 @@ void gm_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const std::ve
   if (ctx->gm_op == 2) {
     // the two-level operator d -> -d - sum_i P~_i J_i^{-1} B_i (d - Z e), e = A0^{-1} Z^T F'(x) d
     Work& w = ctx->w;
+    const bool fused = ctx->coarse_in_apply;
     {
       double fl, by;
-      coarse_work(set, &fl, &by);
+      coarse_work(set, !fused, &fl, &by);
       Timed t(ctx, KID_COARSE, st, fl, by, step);
       rsp::launch_coarse_project(I, 1, w.cpt, ctx->geo.ntot, d, w.cvec, st);
-      rsp::launch_coarse_solve(w.prob, B.list, B.count, coarse_max_n(set), skip_done ? w.gst : nullptr, w.ainv,
-                               w.cvec, 1.0, w.evec, st);
+      if (!fused)
+        rsp::launch_coarse_solve(w.prob, B.list, B.count, coarse_max_n(set), skip_done ? w.gst : nullptr, w.ainv,
+                                 w.cvec, 1.0, w.evec, st);
     }
-    jac_apply(ctx, I, sw, d, out, st, step, w.evec);
+    if (fused) jac_apply(ctx, I, sw, d, out, st, step, nullptr, w.ainv, w.cvec);
+    else jac_apply(ctx, I, sw, d, out, st, step, w.evec);
     return;
   }
   double L = 0;
@@ -1285,6 +1293,7 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
   ctx->hprob.assign(g.ninst, DevProblem{});
   ctx->hseg.assign(g.ninst, GmSeg{});
   ctx->gm_nbx = 1;
+  int coarse_rect = 0;   // most coarse values the ring of one subdomain touches
   std::vector<int4> hbox, hcore;
   std::vector<int> hinst;
   long long sinv_off = 0, ainv_off = 0;
@@ -1313,11 +1322,16 @@ int engine_place(rsp_context* ctx, const rsp_options& o, const std::vector<Inst*
     ctx->hseg[in->slot].L = 2 * (long long)in->n;
     ctx->gm_nbx = std::max(ctx->gm_nbx, rsp::gm_blocks(2 * (long long)in->n));
     for (int q = 0; q < in->part.S; ++q) {
+      int ex0, ey0, ew;
+      coarse_rect = std::max(coarse_rect, rsp::apply_coarse_rect(in->part.box[q], in->prob.nx, in->prob.ny, P.cbx,
+                                                                 P.cby, &ex0, &ey0, &ew));
       hbox.push_back(in->part.box[q]);
       hcore.push_back(in->part.core[q]);
       hinst.push_back(in->slot);
     }
   }
+  ctx->coarse_in_apply = ctx->gm_op == 2 && ctx->nref == 0 && rsp::apply_one_launch(g.M, ctx->fp32) &&
+                         coarse_rect <= rsp::kApplyCoarseMax;
   HIPCHK(hipMemcpyAsync(ctx->w.prob, ctx->hprob.data(), sizeof(DevProblem) * g.ninst, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->w.seg, ctx->hseg.data(), sizeof(GmSeg) * g.ninst, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->w.box, hbox.data(), sizeof(int4) * g.S, hipMemcpyHostToDevice, st));

@@ -49,13 +49,34 @@ void launch_newton_refine(const Items& I, int M, const double* tilex, const doub
 void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const double* rhs, double* out,
                         hipStream_t st);
 // a9 (Algorithm 4): ring rhs of d, the local solves (+ nref FP64 refinement steps with
-// the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  Without refinement two
-// launches of two workgroups per subdomain (inward halves; twist + outward halves);
-// gbuf: [items][tym][M] scratch.  ce != nullptr: the ring values are those of d - Z ce
-// (the coarse correction, kernels_coarse.hip).
+// the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  Without refinement one
+// launch of one workgroup per subdomain, or (FP64 factors from M = 80 on, see
+// apply_one_launch) two launches of two workgroups per subdomain (inward halves; twist
+// + outward halves); gbuf: [items][tym][M] scratch for the latter.  ce != nullptr: the
+// ring values are those of d - Z ce (the coarse correction, kernels_coarse.hip).
+// ainv != nullptr (one-launch form only, with ce == nullptr): each workgroup forms the
+// coarse values e = A0^{-1} cv of the cores its ring touches itself, in the order of
+// launch_coarse_solve (scale 1), from A0^{-1} and the projection cv; the cores of a
+// ring span at most kApplyCoarseMax / 2 cores (apply_coarse_rect).
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
-                      hipStream_t st);
+                      const double* ainv, const double* cv, hipStream_t st);
+// Whether the Jacobian action without refinement runs as one launch (else two).
+inline bool apply_one_launch(int M, int fp32) { return fp32 || M < 80; }
+// Coarse values held by one workgroup of the one-launch action.
+constexpr int kApplyCoarseMax = 32;
+// Coarse unknowns (2 per core) of the cores that the one-node ring of box bx touches, on
+// an nx x ny grid with cores of cbx x cby nodes: the rectangle of cores from
+// (ex0, ey0), ew cores wide.
+__host__ __device__ inline int apply_coarse_rect(int4 bx, int nx, int ny, int cbx, int cby, int* ex0, int* ey0,
+                                                 int* ew) {
+  const int x0 = (bx.x > 0 ? bx.x - 1 : 0) / cbx, x1 = (bx.y < nx ? bx.y : nx - 1) / cbx;
+  const int y0 = (bx.z > 0 ? bx.z - 1 : 0) / cby, y1 = (bx.w < ny ? bx.w : ny - 1) / cby;
+  *ex0 = x0;
+  *ey0 = y0;
+  *ew = x1 - x0 + 1;
+  return 2 * (x1 - x0 + 1) * (y1 - y0 + 1);
+}
 // Second level (kernels_coarse.hip).  Coarse vectors have 2 entries (fields) per item.
 // Sums over each core of phi'(y), g'(p) / nu, phi''(y) p - 1 at x (eps_min) and, with
 // variable coefficients of A, its face couplings and sum of a0: sums[8 items].
