@@ -12,10 +12,11 @@
 // (block LU of the local Jacobian, Section 4: x-derivative of F; eq. (DerC)).  The two
 // halves are independent until the twist, so the Jacobian action runs them side by side
 // in the two halves of one workgroup per subdomain (k_apply_one), which meet at the
-// twist line in LDS.  With FP64 factors from M = 80 on (whose registers that workgroup
-// would spill) they run in two workgroups per subdomain instead: one launch for the
-// inward halves, a second one in which each workgroup forms the twist line from the
-// first launch's results and sweeps its half outward (k_apply_in, k_apply_out).
+// twist line in LDS.  With fewer subdomains than compute units, and with FP64 factors
+// from M = 80 on (whose registers that workgroup would spill), they run in two
+// workgroups per subdomain instead: one launch for the inward halves, a second one in
+// which each workgroup forms the twist line from the first launch's results and sweeps
+// its half outward (k_apply_in, k_apply_out).
 //
 // Each line is an M x M matrix-vector product that only depends on the previous
 // line through the (small) vector, so the matrices are streamed from HBM with
@@ -749,7 +750,7 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
-                      const double* ainv, const double* cv, hipStream_t st) {
+                      bool one_launch, const double* ainv, const double* cv, hipStream_t st) {
   if (I.count <= 0) return;
   const dim3 grid(I.count, 2);
   if (nref > 0) {
@@ -767,10 +768,11 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
 #undef RSP_REF
     return;
   }
-// one workgroup of 8M threads per subdomain; FP64 factors from M = 80 on take the two
-// launches of 4M threads, whose registers the wider workgroup would spill
+// one workgroup of 8M threads per subdomain when one_launch; else, and for FP64 factors
+// from M = 80 on (whose registers the wider workgroup would spill), two launches of 4M
+// threads
 #define RSP_TWO(TT, MM)                                                                        \
-  if (!apply_one_launch(MM, sizeof(TT) == 4)) {                                                \
+  if (!one_launch || !apply_one_launch(MM, sizeof(TT) == 4)) {                                 \
     k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);              \
     k_apply_out<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, gbuf, d, ce, out);        \
   } else {                                                                                     \

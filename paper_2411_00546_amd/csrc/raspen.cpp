@@ -376,6 +376,7 @@ constexpr size_t kMaxGraphs = 256;
 
 struct rsp_context {
   int device = 0;
+  int n_cu = 1;                 // compute units of the device
   size_t budget = 0;
   rsp_options opts{};
   Geometry geo;
@@ -856,14 +857,22 @@ double ortho_flops(double L, int q) { return L * (8.0 * q + 8); }
 double ortho_bytes(double L, int q) { return 8.0 * L * (2.0 * q + 6); }
 
 // step >= 0: Arnoldi step of a GMRES cycle (its timing is settled by settle_gmres_timing).
+// Whether the Jacobian action over the items I runs as one launch of one workgroup per
+// subdomain: with at least as many subdomains as compute units.  Below that, the two
+// launches of two workgroups per subdomain keep twice as many compute units streaming
+// the factors (at 64 subdomains of 255^2 the one-launch form was 1.5x slower).
+bool apply_one(const rsp_context* ctx, const Items& I) {
+  return rsp::apply_one_launch(ctx->geo.M, ctx->fp32) && I.count >= ctx->n_cu;
+}
+
 // ce: the coarse values (d - Z ce on the rings); ainv, cv: the action forms them itself
-// from A0^{-1} and the projection cv (coarse_in_apply).
+// from A0^{-1} and the projection cv (coarse_in_apply, one-launch form only).
 void jac_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const double* d, double* out,
                hipStream_t st, int step = -1, const double* ce = nullptr, const double* ainv = nullptr,
                const double* cv = nullptr) {
   Timed t(ctx, KID_BLOCK_SOLVE, st, apply_flops(ctx, sw), apply_bytes(ctx, sw), step);
   rsp::launch_jac_apply(I, ctx->geo.M, ctx->w.fac, ctx->fp32, ctx->w.tilex, ctx->w.c, d, ce, out, ctx->nref,
-                        ctx->w.g, ainv, cv, st);
+                        ctx->w.g, apply_one(ctx, I), ainv, cv, st);
 }
 
 // Largest number of coarse unknowns (2 S) over the instances of `set`.
@@ -897,7 +906,7 @@ void gm_apply(rsp_context* ctx, const Items& I, const SubWork& sw, const std::ve
   if (ctx->gm_op == 2) {
     // the two-level operator d -> -d - sum_i P~_i J_i^{-1} B_i (d - Z e), e = A0^{-1} Z^T F'(x) d
     Work& w = ctx->w;
-    const bool fused = ctx->coarse_in_apply;
+    const bool fused = ctx->coarse_in_apply && apply_one(ctx, I);
     {
       double fl, by;
       coarse_work(set, !fused, &fl, &by);
@@ -1682,6 +1691,10 @@ int rsp_context_create(rsp_context** ctx, int device, size_t hbm_budget) {
   if (!c) return fail(RSP_ENOMEM, "out of host memory");
   c->device = device;
   c->budget = hbm_budget;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1) {
+    delete c;
+    return fail(RSP_EHIP, "cannot read the compute-unit count of device %d", device);
+  }
   *ctx = c;
   return 0;
 }

@@ -50,18 +50,18 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
                         hipStream_t st);
 // a9 (Algorithm 4): ring rhs of d, the local solves (+ nref FP64 refinement steps with
 // the local Jacobian at R_i x + c), out = -d + sum_i P~_i z_i.  Without refinement one
-// launch of one workgroup per subdomain, or (FP64 factors from M = 80 on, see
-// apply_one_launch) two launches of two workgroups per subdomain (inward halves; twist
-// + outward halves); gbuf: [items][tym][M] scratch for the latter.  ce != nullptr: the
-// ring values are those of d - Z ce (the coarse correction, kernels_coarse.hip).
+// launch of one workgroup per subdomain (one_launch, where apply_one_launch allows it),
+// else two launches of two workgroups per subdomain (inward halves; twist + outward
+// halves); gbuf: [items][tym][M] scratch for the latter.  ce != nullptr: the ring values
+// are those of d - Z ce (the coarse correction, kernels_coarse.hip).
 // ainv != nullptr (one-launch form only, with ce == nullptr): each workgroup forms the
 // coarse values e = A0^{-1} cv of the cores its ring touches itself, in the order of
 // launch_coarse_solve (scale 1), from A0^{-1} and the projection cv; the cores of a
 // ring span at most kApplyCoarseMax / 2 cores (apply_coarse_rect).
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
-                      const double* ainv, const double* cv, hipStream_t st);
-// Whether the Jacobian action without refinement runs as one launch (else two).
+                      bool one_launch, const double* ainv, const double* cv, hipStream_t st);
+// Whether the Jacobian action without refinement may run as one launch (else two).
 inline bool apply_one_launch(int M, int fp32) { return fp32 || M < 80; }
 // Coarse values held by one workgroup of the one-launch action.
 constexpr int kApplyCoarseMax = 32;
