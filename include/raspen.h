@@ -342,12 +342,19 @@ typedef struct rsp_tuning {
   int32_t max_batch;   /* rsp_autotune: instances per batch beyond which throughput no
                           longer grows (copies of the sample) */
   double solves_per_s; /* rsp_autotune: measured throughput of the chosen settings */
+  int32_t jac_form;    /* Jacobian action without refinement (Algorithm 4): 0 automatic
+                          (one launch of one workgroup per subdomain when the launch's
+                          subdomains fill the device's compute units, else two launches
+                          of two workgroups per subdomain), 1 always the two launches,
+                          2 one launch wherever the factor type allows it (FP64 factors
+                          from 80 line unknowns on always take two).  Same results. */
 } rsp_tuning;
 
 /* Current settings of the context (sx, sy, max_batch, solves_per_s are 0). */
 int rsp_get_tuning(rsp_context* ctx, rsp_tuning* out);
 
-/* Apply graphs and gm_chunk (the other fields are ignored).  RSP_EINVAL if out of range. */
+/* Apply graphs, gm_chunk and jac_form (the other fields are ignored).  RSP_EINVAL if out
+   of range. */
 int rsp_set_tuning(rsp_context* ctx, const rsp_tuning* t);
 
 #define RSP_TUNE_PARTITION 1   /* also try other subdomain counts (same overlap)          */

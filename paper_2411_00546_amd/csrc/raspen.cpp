@@ -411,6 +411,7 @@ struct rsp_context {
   // captured launch sequences (hipGraphs), valid while the launch signature holds
   int graphs = 0;               // capture and replay (else plain stream launches)
   int gm_chunk = 32;            // Arnoldi steps between two reads of the GMRES headers
+  int jac_form = 0;             // rsp_tuning.jac_form
   int gm_nbx = 1;               // grid width of the GMRES vector kernels (longest instance)
   int gm_op = 0;                // operator of GMRES: 0 the Jacobian action of Algorithm 4,
                                 // 1 F'_eps(x) of the whole system (monolithic Newton)
@@ -556,7 +557,7 @@ uint64_t launch_signature(const rsp_context* ctx) {
   val(ctx->yd), val(ctx->f), val(ctx->x);
   const rsp_options& o = ctx->opts;
   val(o.tol_inner), val(o.sigma), val(o.alpha_min), val(o.gmres_restart), val(o.max_inner);
-  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op), val(ctx->gm_nbx), val(ctx->coarse_in_apply);
+  val(o.precision), val(ctx->fp32), val(ctx->nref), val(ctx->gm_op), val(ctx->gm_nbx), val(ctx->coarse_in_apply), val(ctx->jac_form);
   return h;
 }
 
@@ -862,7 +863,8 @@ double ortho_bytes(double L, int q) { return 8.0 * L * (2.0 * q + 6); }
 // launches of two workgroups per subdomain keep twice as many compute units streaming
 // the factors (at 64 subdomains of 255^2 the one-launch form was 1.5x slower).
 bool apply_one(const rsp_context* ctx, const Items& I) {
-  return rsp::apply_one_launch(ctx->geo.M, ctx->fp32) && I.count >= ctx->n_cu;
+  if (!rsp::apply_one_launch(ctx->geo.M, ctx->fp32) || ctx->jac_form == 1) return false;
+  return ctx->jac_form == 2 || I.count >= ctx->n_cu;
 }
 
 // ce: the coarse values (d - Z ce on the rings); ainv, cv: the action forms them itself
@@ -1925,6 +1927,7 @@ int rsp_get_tuning(rsp_context* ctx, rsp_tuning* out) {
   *out = rsp_tuning{};
   out->graphs = ctx->graphs;
   out->gm_chunk = ctx->gm_chunk;
+  out->jac_form = ctx->jac_form;
   return 0;
 }
 
@@ -1933,8 +1936,10 @@ int rsp_set_tuning(rsp_context* ctx, const rsp_tuning* t) {
   if (t->graphs != 0 && t->graphs != 1) return fail(RSP_EINVAL, "graphs must be 0 or 1");
   if (t->gm_chunk < 1 || t->gm_chunk > kMaxRestart)
     return fail(RSP_EINVAL, "gm_chunk must be in [1, %d]", kMaxRestart);
+  if (t->jac_form < 0 || t->jac_form > 2) return fail(RSP_EINVAL, "jac_form must be 0, 1 or 2");
   ctx->graphs = t->graphs;
   ctx->gm_chunk = t->gm_chunk;
+  ctx->jac_form = t->jac_form;
   return 0;
 }
 

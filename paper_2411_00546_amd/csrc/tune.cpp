@@ -109,7 +109,10 @@ int rsp_autotune(rsp_context* ctx, const rsp_problem* sample, const rsp_options*
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
+      rsp_tuning cur;
+      if (int e = rsp_get_tuning(ctx, &cur)) return e;
       *out = it->second;
+      out->jac_form = cur.jac_form;   // not tuned: the context's own
       return rsp_set_tuning(ctx, out);
     }
   }
@@ -120,6 +123,7 @@ int rsp_autotune(rsp_context* ctx, const rsp_problem* sample, const rsp_options*
   if (int e = bufs.alloc(maxb, n)) return e;
   // about 0.3 s of timed solves per candidate, at least 2
   rsp_tuning best{};
+  if (int e = rsp_get_tuning(ctx, &best)) return e;   // keeps the context's jac_form
   best.graphs = 0;
   best.gm_chunk = 8;
   if (int e = rsp_set_tuning(ctx, &best)) return e;

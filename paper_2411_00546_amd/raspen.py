@@ -84,7 +84,8 @@ class rsp_kernel_stat(ctypes.Structure):
 
 class rsp_tuning(ctypes.Structure):
     _fields_ = [("graphs", ctypes.c_int32), ("gm_chunk", ctypes.c_int32), ("sx", ctypes.c_int32),
-                ("sy", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("solves_per_s", ctypes.c_double)]
+                ("sy", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("solves_per_s", ctypes.c_double),
+                ("jac_form", ctypes.c_int32)]
 
 
 class rsp_server_options(ctypes.Structure):
@@ -441,12 +442,14 @@ def rsp_get_tuning(ctx):
     return t
 
 
-def rsp_set_tuning(ctx, graphs=None, gm_chunk=None):
+def rsp_set_tuning(ctx, graphs=None, gm_chunk=None, jac_form=None):
     t = rsp_get_tuning(ctx)
     if graphs is not None:
         t.graphs = int(graphs)
     if gm_chunk is not None:
         t.gm_chunk = int(gm_chunk)
+    if jac_form is not None:
+        t.jac_form = int(jac_form)
     return _check(load().rsp_set_tuning(ctx, ctypes.byref(t)))
 
 

@@ -248,3 +248,34 @@ def test_sampled_timing(R, graphs):
     assert 0 < part["launches"] < 0.6 * full["launches"], (part, full)
     ta, tb = full["ms"] / full["launches"], part["ms"] / part["launches"]
     assert 0.5 < tb / ta < 2.0, (ta, tb)
+
+
+@pytest.mark.parametrize("precision,coarse", [(1, 1), (1, 0), (0, 1)])
+def test_jacobian_action_forms_are_bitwise_equal(R, precision, coarse):
+    """rsp_tuning.jac_form: the one-launch Jacobian action (both half-sweeps of a
+    subdomain in one workgroup; with the second level, the coarse values of each ring
+    formed inside it) and the two launches of two workgroups per subdomain (with the
+    separate coarse solve) give bit-identical solves, single and batched."""
+    opts = synth.Options(precision=precision, max_refine=0, coarse=coarse)
+    p = prob(127, 95, 4, 3, 4, phi=synth.PHI_EXP, nu=3e-3, mu=2e-2, seed=12)
+    ctx = R.rsp_context_create(0)
+    try:
+        res = {}
+        for form in (1, 2, 0):
+            R.rsp_set_tuning(ctx, jac_form=form)
+            assert R.rsp_get_tuning(ctx).jac_form == form
+            st, h, got = run_single(R, p, opts, ctx)
+            assert st == 0, form
+            res[form] = (h["gmres_its"], got, run_batch(R, MIXED, opts, ctx=ctx))
+        for form in (2, 0):
+            assert res[form][0] == res[1][0], form
+            assert same(res[form][1], res[1][1]), form
+            (st_b, _, out_b), (st_1, _, out_1) = res[form][2], res[1][2]
+            assert st_b == st_1, form
+            for a, b in zip(out_b, out_1):
+                assert same(a, b), form
+        with pytest.raises(R.RaspenError) as e:
+            R.rsp_set_tuning(ctx, jac_form=3)
+        assert e.value.code == R.RSP_EINVAL
+    finally:
+        R.rsp_context_destroy(ctx)
