@@ -250,12 +250,18 @@ def test_sampled_timing(R, graphs):
     assert 0.5 < tb / ta < 2.0, (ta, tb)
 
 
+# tiles of one to four lines: one half of the one-launch action idles through every step
+THIN = [prob(40, 6, 2, 3, 0, seed=41), prob(24, 3, 2, 3, 0, seed=42), prob(31, 5, 3, 2, 1, seed=43),
+        prob(33, 4, 2, 2, 1, seed=44)]
+
+
 @pytest.mark.parametrize("precision,coarse", [(1, 1), (1, 0), (0, 1)])
 def test_jacobian_action_forms_are_bitwise_equal(R, precision, coarse):
     """rsp_tuning.jac_form: the one-launch Jacobian action (both half-sweeps of a
     subdomain in one workgroup; with the second level, the coarse values of each ring
     formed inside it) and the two launches of two workgroups per subdomain (with the
-    separate coarse solve) give bit-identical solves, single and batched."""
+    separate coarse solve) give bit-identical solves, single and batched (tiles of one
+    and two lines included)."""
     opts = synth.Options(precision=precision, max_refine=0, coarse=coarse)
     p = prob(127, 95, 4, 3, 4, phi=synth.PHI_EXP, nu=3e-3, mu=2e-2, seed=12)
     ctx = R.rsp_context_create(0)
@@ -266,7 +272,7 @@ def test_jacobian_action_forms_are_bitwise_equal(R, precision, coarse):
             assert R.rsp_get_tuning(ctx).jac_form == form
             st, h, got = run_single(R, p, opts, ctx)
             assert st == 0, form
-            res[form] = (h["gmres_its"], got, run_batch(R, MIXED, opts, ctx=ctx))
+            res[form] = (h["gmres_its"], got, run_batch(R, MIXED + THIN, opts, ctx=ctx))
         for form in (2, 0):
             assert res[form][0] == res[1][0], form
             assert same(res[form][1], res[1][1]), form
