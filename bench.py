@@ -343,7 +343,7 @@ def apply_tuning(R, ctx, args, prob, opts, yd, f):
     else:
         R.rsp_set_tuning(ctx, graphs=args.graphs, gm_chunk=args.gm_chunk)
         t = R.rsp_get_tuning(ctx)
-    return {"graphs": t.graphs, "gm_chunk": t.gm_chunk, "autotuned": bool(args.tune),
+    return {"graphs": t.graphs, "gm_chunk": t.gm_chunk, "jac_form": t.jac_form, "autotuned": bool(args.tune),
             "tuner_solves_per_s": t.solves_per_s if args.tune else None}
 
 
