@@ -347,7 +347,7 @@ typedef struct rsp_tuning {
                           subdomains fill the device's compute units, else two launches
                           of two workgroups per subdomain), 1 always the two launches,
                           2 one launch wherever the factor type allows it (FP64 factors
-                          from 80 line unknowns on always take two).  Same results. */
+                          above 80 line unknowns always take two).  Same results. */
 } rsp_tuning;
 
 /* Current settings of the context (sx, sy, max_batch, solves_per_s are 0). */

@@ -13,7 +13,7 @@
 // halves are independent until the twist, so the Jacobian action runs them side by side
 // in the two halves of one workgroup per subdomain (k_apply_one), which meet at the
 // twist line in LDS.  With fewer subdomains than compute units, and with FP64 factors
-// from M = 80 on (whose registers that workgroup would spill), they run in two
+// above M = 80 (whose registers that workgroup would spill heavily), they run in two
 // workgroups per subdomain instead: one launch for the inward halves, a second one in
 // which each workgroup forms the twist line from the first launch's results and sweeps
 // its half outward (k_apply_in, k_apply_out).
@@ -769,8 +769,8 @@ void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const d
     return;
   }
 // one workgroup of 8M threads per subdomain when one_launch; else, and for FP64 factors
-// from M = 80 on (whose registers the wider workgroup would spill), two launches of 4M
-// threads
+// above M = 80 (whose registers the wider workgroup would spill heavily), two launches
+// of 4M threads
 #define RSP_TWO(TT, MM)                                                                        \
   if (!one_launch || !apply_one_launch(MM, sizeof(TT) == 4)) {                                 \
     k_apply_in<TT, MM><<<grid, 4 * MM, 0, st>>>(I, (const TT*)facT, d, ce, gbuf);              \

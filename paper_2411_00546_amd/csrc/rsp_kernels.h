@@ -61,8 +61,10 @@ void launch_block_solve(const Items& I, int M, const void* facT, int fp32, const
 void launch_jac_apply(const Items& I, int M, const void* facT, int fp32, const double* tilex,
                       const double* c, const double* d, const double* ce, double* out, int nref, double* gbuf,
                       bool one_launch, const double* ainv, const double* cv, hipStream_t st);
-// Whether the Jacobian action without refinement may run as one launch (else two).
-inline bool apply_one_launch(int M, int fp32) { return fp32 || M < 80; }
+// Whether the Jacobian action without refinement may run as one launch (else two): at
+// 8M threads a workgroup has at most 168 VGPRs; the FP64 sweeps spill 12 bytes per lane
+// at M = 80 (still faster than two launches) and 124 at M = 96.
+inline bool apply_one_launch(int M, int fp32) { return fp32 || M <= 80; }
 // Coarse values held by one workgroup of the one-launch action.
 constexpr int kApplyCoarseMax = 32;
 // Coarse unknowns (2 per core) of the cores that the one-node ring of box bx touches, on
